@@ -1,0 +1,703 @@
+/*
+ * FP64 brute-force CPU oracle of the clumped-sphere DEM timestep.
+ * TEST INFRASTRUCTURE ONLY -- see oracle.h.  Built with -ffp-contract=off and
+ * without -ffast-math so that every +, -, *, / and sqrt is a single IEEE-754
+ * double operation evaluated in the order written.
+ *
+ * One step, state S_n -> S_{n+1} (paper Sec. 2.1, with the readings listed
+ * where the paper leaves a choice open):
+ *   1. per clump, the rotation matrix A(q) and the world angular velocity
+ *      A w_body;
+ *   2. sphere centres x_s = x_c + A o_s (multi-sphere clump, Sec. 2.1);
+ *   3. the contact set by brute force: every pair a < b of spheres of
+ *      different clumps in the same scene with d^2 < (Ra+Rb)^2 (strict), and
+ *      every sphere / boundary pair with signed distance phi < R;
+ *   4. per contact: normal n from a to b, penetration delta, contact point at
+ *      the middle of the overlap, lever arms from each clump's CoM, relative
+ *      velocity split into normal and tangential parts (Eq. kinematicsContactInfo);
+ *   5. the Hertz-Mindlin law (Eq. normal_tangential_force_model1/2) with
+ *      stiffness and damping derived from E, nu and CoR: E* and G* from the two
+ *      materials, damping ratio beta(CoR), f = sqrt(Rbar delta);
+ *      tangential history update and projection (Eq. updateUt), Coulomb cap on
+ *      the trial tangential force with the history clamped so the spring part
+ *      equals the cap (Eq. cappingOfut, with k_t taken as the contact's
+ *      tangential stiffness f*k_t);
+ *   6. per sphere: the sum of its contact forces and torques r x F (r from the
+ *      clump CoM to the contact point, normal and tangential parts both), in
+ *      ascending partner id (spheres, then boundaries); per clump: the sum over
+ *      its spheres in ascending id, then + M g (Eq. newton_law_1/2);
+ *   7. symplectic Euler: v += h F/M, x += h v; body-frame Euler equations with
+ *      the gyroscopic term; q += (h/2) q (x) (0, w_body), renormalised.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <omp.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NPARAM_BND 12
+#define NPARAM_PRESC 12
+
+static char g_err[256];
+static void set_err(const char *m) { snprintf(g_err, sizeof g_err, "%s", m); }
+const char *dem_oracle_last_error(void) { return g_err; }
+void dem_oracle_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
+
+struct dem_oracle {
+    double h;
+    int64_t step;
+    int64_t nc, ns;
+    int32_t nsc, nb;
+    /* clump state and static data */
+    double *x, *q, *v, *w;
+    double *mass, *inertia; /* per clump */
+    uint32_t *scene;        /* per clump */
+    int64_t *sbeg;          /* [nc+1] sphere range per clump */
+    int32_t *presc;         /* per clump: -1 or index into presc_param */
+    double *presc_param;
+    /* sphere static data */
+    uint32_t *owner;
+    double *ofs;            /* [ns][3] body offsets */
+    double *rad;
+    double *me, *mg, *mmu, *mbeta; /* (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, beta(CoR) */
+    /* boundaries */
+    int32_t *btype, *bscene;
+    double *bparam, *bvel, *bomega;
+    double *be, *bg, *bmu, *bbeta;
+    double *grav;
+    /* history: contacts of the previous step, ascending key, with their u */
+    int64_t nh;
+    uint64_t *hkey;
+    double *hu;
+    /* per-step work */
+    double *A;              /* [nc][9] */
+    double *ww;             /* [nc][3] world angular velocity */
+    double *xs;             /* [ns][3] */
+    int64_t ncont, capcont;
+    uint64_t *ckey;
+    double *cdelta, *cF, *cu, *cra, *crb; /* per contact: delta, F on b, new u, lever arms */
+    double *sF, *sT;        /* per sphere */
+    double *cFc, *cTc;      /* per clump */
+    /* transposed contact index: for sphere s, contacts in which s is the
+     * higher id (partner < s), ascending partner */
+    int64_t *lo_beg, *lo_idx;
+};
+
+static void *xmalloc(size_t n) {
+    void *p = malloc(n ? n : 1);
+    if (!p) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    return p;
+}
+static double *dup_d(const double *src, size_t n) {
+    double *p = (double *)xmalloc(n * sizeof(double));
+    if (n) memcpy(p, src, n * sizeof(double));
+    return p;
+}
+
+/* Damping ratio of a coefficient of restitution e in (0, 1]: ln e / sqrt(ln^2 e + pi^2).
+ * It is <= 0, zero for e = 1, and increasing in e, so the pair value min(beta_a, beta_b)
+ * is the damping of min(e_a, e_b). */
+static double beta_of_cor(double e) {
+    double l = log(e);
+    return l / sqrt(l * l + M_PI * M_PI);
+}
+
+dem_oracle *dem_oracle_create(const dem_oracle_desc *d) {
+    if (!d || d->n_clumps < 0 || d->n_templates < 1 || !(d->h > 0)) { set_err("invalid descriptor"); return NULL; }
+    dem_oracle *o = (dem_oracle *)calloc(1, sizeof *o);
+    o->h = d->h;
+    o->nc = d->n_clumps;
+    o->nsc = d->n_scenes;
+    o->nb = d->n_bnd;
+    int64_t nc = o->nc;
+    o->sbeg = (int64_t *)xmalloc((nc + 1) * sizeof(int64_t));
+    o->sbeg[0] = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        if ((int32_t)t >= d->n_templates || d->clump_scene[c] >= (uint32_t)d->n_scenes) {
+            set_err("clump template or scene out of range");
+            dem_oracle_destroy(o);
+            return NULL;
+        }
+        o->sbeg[c + 1] = o->sbeg[c] + (d->tmpl_sphere_begin[t + 1] - d->tmpl_sphere_begin[t]);
+    }
+    int64_t ns = o->ns = o->sbeg[nc];
+    o->x = dup_d(d->x, 3 * nc);
+    o->q = dup_d(d->q, 4 * nc);
+    o->v = dup_d(d->v, 3 * nc);
+    o->w = dup_d(d->w, 3 * nc);
+    o->mass = (double *)xmalloc(nc * sizeof(double));
+    o->inertia = (double *)xmalloc(3 * nc * sizeof(double));
+    o->scene = (uint32_t *)xmalloc(nc * sizeof(uint32_t));
+    o->presc = (int32_t *)xmalloc(nc * sizeof(int32_t));
+    o->owner = (uint32_t *)xmalloc(ns * sizeof(uint32_t));
+    o->ofs = (double *)xmalloc(3 * ns * sizeof(double));
+    o->rad = (double *)xmalloc(ns * sizeof(double));
+    o->me = (double *)xmalloc(ns * sizeof(double));
+    o->mg = (double *)xmalloc(ns * sizeof(double));
+    o->mmu = (double *)xmalloc(ns * sizeof(double));
+    o->mbeta = (double *)xmalloc(ns * sizeof(double));
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        o->mass[c] = d->tmpl_mass[t];
+        for (int k = 0; k < 3; k++) o->inertia[3 * c + k] = d->tmpl_inertia[3 * t + k];
+        o->scene[c] = d->clump_scene[c];
+        o->presc[c] = -1;
+        uint32_t tb = d->tmpl_sphere_begin[t];
+        for (int64_t s = o->sbeg[c]; s < o->sbeg[c + 1]; s++) {
+            uint32_t ts = tb + (uint32_t)(s - o->sbeg[c]);
+            o->owner[s] = (uint32_t)c;
+            for (int k = 0; k < 3; k++) o->ofs[3 * s + k] = d->tmpl_offset[3 * ts + k];
+            o->rad[s] = d->tmpl_radius[ts];
+        }
+    }
+    for (int64_t s = 0; s < ns; s++) {
+        const double *m = d->sphere_mat + 4 * s;
+        double E = m[0], nu = m[1];
+        o->me[s] = (1.0 - nu * nu) / E;
+        o->mg[s] = 2.0 * (2.0 - nu) * (1.0 + nu) / E;
+        o->mmu[s] = m[2];
+        o->mbeta[s] = beta_of_cor(m[3]);
+    }
+    o->presc_param = dup_d(d->presc_param, (size_t)NPARAM_PRESC * d->n_presc);
+    for (int32_t i = 0; i < d->n_presc; i++) {
+        int32_t c = d->presc_clump[i];
+        if (c < 0 || c >= nc) { set_err("prescribed clump out of range"); dem_oracle_destroy(o); return NULL; }
+        o->presc[c] = i;
+    }
+    int32_t nb = o->nb;
+    o->btype = (int32_t *)xmalloc(nb * sizeof(int32_t));
+    o->bscene = (int32_t *)xmalloc(nb * sizeof(int32_t));
+    if (nb) {
+        memcpy(o->btype, d->bnd_type, nb * sizeof(int32_t));
+        memcpy(o->bscene, d->bnd_scene, nb * sizeof(int32_t));
+    }
+    o->bparam = dup_d(d->bnd_param, (size_t)NPARAM_BND * nb);
+    o->bvel = dup_d(d->bnd_vel, 3 * (size_t)nb);
+    o->bomega = dup_d(d->bnd_omega, 3 * (size_t)nb);
+    o->be = (double *)xmalloc(nb * sizeof(double));
+    o->bg = (double *)xmalloc(nb * sizeof(double));
+    o->bmu = (double *)xmalloc(nb * sizeof(double));
+    o->bbeta = (double *)xmalloc(nb * sizeof(double));
+    for (int32_t i = 0; i < nb; i++) {
+        const double *m = d->bnd_mat + 4 * i;
+        double E = m[0], nu = m[1];
+        o->be[i] = (1.0 - nu * nu) / E;
+        o->bg[i] = 2.0 * (2.0 - nu) * (1.0 + nu) / E;
+        o->bmu[i] = m[2];
+        o->bbeta[i] = beta_of_cor(m[3]);
+        if (o->btype[i] < 0 || o->btype[i] > 3) { set_err("unknown boundary type"); dem_oracle_destroy(o); return NULL; }
+    }
+    o->grav = dup_d(d->gravity, 3 * (size_t)o->nsc);
+    o->A = (double *)xmalloc(9 * nc * sizeof(double));
+    o->ww = (double *)xmalloc(3 * nc * sizeof(double));
+    o->xs = (double *)xmalloc(3 * ns * sizeof(double));
+    o->sF = (double *)xmalloc(3 * ns * sizeof(double));
+    o->sT = (double *)xmalloc(3 * ns * sizeof(double));
+    o->cFc = (double *)xmalloc(3 * nc * sizeof(double));
+    o->cTc = (double *)xmalloc(3 * nc * sizeof(double));
+    o->lo_beg = (int64_t *)xmalloc((ns + 1) * sizeof(int64_t));
+    return o;
+}
+
+void dem_oracle_destroy(dem_oracle *o) {
+    if (!o) return;
+    void *ptrs[] = {o->x, o->q, o->v, o->w, o->mass, o->inertia, o->scene, o->sbeg, o->presc,
+                    o->presc_param, o->owner, o->ofs, o->rad, o->me, o->mg, o->mmu, o->mbeta,
+                    o->btype, o->bscene, o->bparam, o->bvel, o->bomega, o->be, o->bg, o->bmu,
+                    o->bbeta, o->grav, o->hkey, o->hu, o->A, o->ww, o->xs, o->ckey, o->cdelta,
+                    o->cF, o->cu, o->cra, o->crb, o->sF, o->sT, o->cFc, o->cTc, o->lo_beg, o->lo_idx};
+    for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; i++) free(ptrs[i]);
+    free(o);
+}
+
+int64_t dem_oracle_step_count(const dem_oracle *o) { return o->step; }
+int64_t dem_oracle_n_spheres(const dem_oracle *o) { return o->ns; }
+
+/* ---------------- kinematics of the current state ---------------- */
+
+/* Rotation matrix of a unit quaternion (w, x, y, z), row-major. */
+static void quat_to_matrix(const double *q, double *A) {
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y - w * z);
+    A[2] = 2.0 * (x * z + w * y);
+    A[3] = 2.0 * (x * y + w * z);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z - w * x);
+    A[6] = 2.0 * (x * z - w * y);
+    A[7] = 2.0 * (y * z + w * x);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void compute_poses(dem_oracle *o) {
+    int64_t nc = o->nc;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; c++) {
+        double *A = o->A + 9 * c;
+        quat_to_matrix(o->q + 4 * c, A);
+        const double *wb = o->w + 3 * c;
+        for (int i = 0; i < 3; i++) o->ww[3 * c + i] = A[3 * i] * wb[0] + A[3 * i + 1] * wb[1] + A[3 * i + 2] * wb[2];
+        for (int64_t s = o->sbeg[c]; s < o->sbeg[c + 1]; s++) {
+            const double *of = o->ofs + 3 * s;
+            for (int i = 0; i < 3; i++)
+                o->xs[3 * s + i] = o->x[3 * c + i] + (A[3 * i] * of[0] + A[3 * i + 1] * of[1] + A[3 * i + 2] * of[2]);
+        }
+    }
+}
+
+/* ---------------- analytic boundaries ---------------- */
+
+/* Signed distance phi of point p from boundary b at time t (positive on the
+ * domain side) and the unit normal n pointing from the wall into the domain.
+ * Returns 0 when the boundary cannot touch p (outside its active range or on
+ * a degenerate axis point). */
+static int boundary_distance(const dem_oracle *o, int32_t b, double t, const double *p, double *phi, double *n) {
+    const double *P = o->bparam + NPARAM_BND * b;
+    const double *vel = o->bvel + 3 * b;
+    double r0[3], d[3];
+    for (int i = 0; i < 3; i++) r0[i] = P[i] + t * vel[i];
+    for (int i = 0; i < 3; i++) d[i] = p[i] - r0[i];
+    int type = o->btype[b];
+    if (type == 0) { /* plane through r0 with unit normal P[3..5] into the domain */
+        *phi = d[0] * P[3] + d[1] * P[4] + d[2] * P[5];
+        n[0] = P[3]; n[1] = P[4]; n[2] = P[5];
+        return 1;
+    }
+    /* axisymmetric primitives: axial coordinate ta and radial vector rho */
+    const double *a = P + 3;
+    double ta = d[0] * a[0] + d[1] * a[1] + d[2] * a[2];
+    double rho[3];
+    for (int i = 0; i < 3; i++) rho[i] = d[i] - ta * a[i];
+    double r = sqrt(rho[0] * rho[0] + rho[1] * rho[1] + rho[2] * rho[2]);
+    if (type == 1) { /* inside a cylinder of radius P[6] */
+        if (!(r > 0.0)) return 0;
+        *phi = P[6] - r;
+        for (int i = 0; i < 3; i++) n[i] = -(rho[i] / r);
+        return 1;
+    }
+    double sn = P[6], cs = P[7];
+    if (type == 2) { /* outside a solid cone (apex r0, axis a into the solid) topped by a shaft */
+        double H = P[8];
+        double rb = H * (sn / cs);
+        double lam = ta * cs + r * sn;
+        if (ta >= H) { /* beside the shaft */
+            if (!(r > 0.0)) return 0;
+            *phi = r - rb;
+            for (int i = 0; i < 3; i++) n[i] = rho[i] / r;
+            return 1;
+        }
+        if (lam <= 0.0) { /* nearest point is the apex */
+            double dd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(dd > 0.0)) return 0;
+            *phi = dd;
+            for (int i = 0; i < 3; i++) n[i] = d[i] / dd;
+            return 1;
+        }
+        if (!(r > 0.0)) return 0;
+        if (lam <= H / cs) { /* lateral surface */
+            *phi = r * cs - ta * sn;
+            for (int i = 0; i < 3; i++) n[i] = (rho[i] / r) * cs - a[i] * sn;
+            return 1;
+        }
+        /* nearest point is the base rim */
+        double dt = ta - H, dr = r - rb;
+        double dd = sqrt(dt * dt + dr * dr);
+        if (!(dd > 0.0)) return 0;
+        *phi = dd;
+        for (int i = 0; i < 3; i++) n[i] = (dt * a[i] + dr * (rho[i] / r)) / dd;
+        return 1;
+    }
+    /* type 3: inside an upward-opening cone (funnel wall) for t0 <= ta <= t1 */
+    if (ta < P[8] || ta > P[9] || !(r > 0.0)) return 0;
+    *phi = ta * sn - r * cs;
+    for (int i = 0; i < 3; i++) n[i] = a[i] * sn - (rho[i] / r) * cs;
+    return 1;
+}
+
+/* ---------------- contact law ---------------- */
+
+/* Hertz-Mindlin force on body b of a contact with normal n (a -> b),
+ * penetration delta > 0, relative velocity vrel = v_b - v_a at the contact
+ * point, effective radius and mass, combined material, and the tangential
+ * history u_old.  Writes the force F and the updated history u_new. */
+static void contact_law(const double *n, double delta, const double *vrel, double Rbar, double mbar,
+                        double estar, double gstar, double mu, double beta, double h,
+                        const double *u_old, double *F, double *u_new) {
+    const double kdamp = -2.0 * sqrt(5.0 / 6.0);
+    double vn_s = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    double vn[3], vt[3];
+    for (int i = 0; i < 3; i++) vn[i] = vn_s * n[i];
+    for (int i = 0; i < 3; i++) vt[i] = vrel[i] - vn[i];
+    double sq = sqrt(Rbar * delta);
+    /* normal: Hertz spring (4/3) E* sqrt(Rbar delta) delta and CoR-calibrated dashpot */
+    double Sn = 2.0 * estar * sq;
+    double gn = kdamp * beta * sqrt(Sn * mbar);
+    double kn = (4.0 / 3.0) * estar * sq * delta;
+    double Fn[3];
+    for (int i = 0; i < 3; i++) Fn[i] = kn * n[i] - gn * vn[i];
+    /* tangential: history update and projection onto the tangent plane */
+    double up[3];
+    for (int i = 0; i < 3; i++) up[i] = u_old[i] + h * vt[i];
+    double upn = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
+    double ut[3];
+    for (int i = 0; i < 3; i++) ut[i] = up[i] - upn * n[i];
+    double St = 8.0 * gstar * sq;
+    double gt = kdamp * beta * sqrt(St * mbar);
+    double Ft[3];
+    for (int i = 0; i < 3; i++) Ft[i] = -(St * ut[i]) - gt * vt[i];
+    double fn_norm = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
+    double ft_norm = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+    double cap = mu * fn_norm;
+    if (ft_norm > cap) {
+        double scale = cap / ft_norm;
+        for (int i = 0; i < 3; i++) Ft[i] = Ft[i] * scale;
+        double ut_norm = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        if (ut_norm > 0.0) {
+            double fac = (cap / St) / ut_norm;
+            for (int i = 0; i < 3; i++) u_new[i] = fac * ut[i];
+        } else {
+            for (int i = 0; i < 3; i++) u_new[i] = 0.0;
+        }
+    } else {
+        for (int i = 0; i < 3; i++) u_new[i] = ut[i];
+    }
+    for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
+}
+
+static void cross(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static int64_t find_history(const dem_oracle *o, uint64_t key) {
+    int64_t lo = 0, hi = o->nh;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (o->hkey[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return (lo < o->nh && o->hkey[lo] == key) ? lo : -1;
+}
+
+/* ---------------- contact set (brute force) ---------------- */
+
+/* Count (pass 0) or write (pass 1) the enlarged-geometry pairs of row a. */
+static int64_t row_pairs(const dem_oracle *o, int64_t a, double t, const double *margin, uint64_t *out) {
+    int64_t cnt = 0;
+    const double *xa = o->xs + 3 * a;
+    double Ra = o->rad[a];
+    double ma = margin ? margin[a] : 0.0;
+    uint32_t ca = o->owner[a];
+    uint32_t sa = o->scene[ca];
+    for (int64_t b = a + 1; b < o->ns; b++) {
+        uint32_t cb = o->owner[b];
+        if (cb == ca || o->scene[cb] != sa) continue;
+        const double *xb = o->xs + 3 * b;
+        double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double S = o->rad[a] + o->rad[b];
+        if (margin) S = S + (ma + margin[b]);
+        if (d2 < S * S) {
+            if (out) out[cnt] = ((uint64_t)a << 32) | (uint64_t)b;
+            cnt++;
+        }
+    }
+    for (int32_t w = 0; w < o->nb; w++) {
+        if ((uint32_t)o->bscene[w] != sa) continue;
+        double phi, n[3];
+        if (!boundary_distance(o, w, t, xa, &phi, n)) continue;
+        double lim = margin ? Ra + ma : Ra;
+        if (phi < lim) {
+            if (out) out[cnt] = ((uint64_t)a << 32) | (uint64_t)(o->ns + w);
+            cnt++;
+        }
+    }
+    return cnt;
+}
+
+static int64_t collect_pairs(const dem_oracle *o, const double *margin, uint64_t **keys_out) {
+    int64_t ns = o->ns;
+    double t = (double)o->step * o->h;
+    int64_t *cnt = (int64_t *)xmalloc((ns + 1) * sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < ns; a++) cnt[a] = row_pairs(o, a, t, margin, NULL);
+    int64_t total = 0;
+    for (int64_t a = 0; a < ns; a++) { int64_t c = cnt[a]; cnt[a] = total; total += c; }
+    uint64_t *keys = (uint64_t *)xmalloc(total * sizeof(uint64_t));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < ns; a++) row_pairs(o, a, t, margin, keys + cnt[a]);
+    free(cnt);
+    *keys_out = keys;
+    return total;
+}
+
+/* ---------------- one evaluation ---------------- */
+
+int64_t dem_oracle_eval(dem_oracle *o) {
+    int64_t ns = o->ns, nc = o->nc;
+    double h = o->h;
+    double t = (double)o->step * h;
+    compute_poses(o);
+    free(o->ckey);
+    o->ckey = NULL;
+    int64_t nk = collect_pairs(o, NULL, &o->ckey);
+    o->ncont = nk;
+    free(o->cdelta); free(o->cF); free(o->cu); free(o->cra); free(o->crb);
+    o->cdelta = (double *)xmalloc(nk * sizeof(double));
+    o->cF = (double *)xmalloc(3 * nk * sizeof(double));
+    o->cu = (double *)xmalloc(3 * nk * sizeof(double));
+    o->cra = (double *)xmalloc(3 * nk * sizeof(double));
+    o->crb = (double *)xmalloc(3 * nk * sizeof(double));
+
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < nk; k++) {
+        uint64_t key = o->ckey[k];
+        int64_t a = (int64_t)(key >> 32), b = (int64_t)(key & 0xffffffffu);
+        int64_t hi = find_history(o, key);
+        double u_old[3] = {0.0, 0.0, 0.0};
+        if (hi >= 0) for (int i = 0; i < 3; i++) u_old[i] = o->hu[3 * hi + i];
+        double n[3], delta, p[3], ra[3], rb[3], vrel[3];
+        double Rbar, mbar, estar, gstar, mu, beta;
+        double *F = o->cF + 3 * k, *un = o->cu + 3 * k;
+        if (b < ns) {
+            const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
+            double Ra = o->rad[a], Rb = o->rad[b];
+            uint32_t ca = o->owner[a], cb = o->owner[b];
+            double dx[3];
+            for (int i = 0; i < 3; i++) dx[i] = xb[i] - xa[i];
+            double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+            delta = (Ra + Rb) - d;
+            for (int i = 0; i < 3; i++) n[i] = dx[i] / d;
+            double lever = Ra - 0.5 * delta;
+            for (int i = 0; i < 3; i++) p[i] = xa[i] + lever * n[i];
+            for (int i = 0; i < 3; i++) { ra[i] = p[i] - o->x[3 * ca + i]; rb[i] = p[i] - o->x[3 * cb + i]; }
+            double wa[3], wb[3];
+            cross(o->ww + 3 * ca, ra, wa);
+            cross(o->ww + 3 * cb, rb, wb);
+            for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cb + i] + wb[i]) - (o->v[3 * ca + i] + wa[i]);
+            Rbar = (Ra * Rb) / (Ra + Rb);
+            double Ma = o->mass[ca], Mb = o->mass[cb];
+            mbar = (Ma * Mb) / (Ma + Mb);
+            estar = 1.0 / (o->me[a] + o->me[b]);
+            gstar = 1.0 / (o->mg[a] + o->mg[b]);
+            mu = fmin(o->mmu[a], o->mmu[b]);
+            beta = fmin(o->mbeta[a], o->mbeta[b]);
+        } else {
+            /* boundary contact: the boundary is body a, the sphere is body b */
+            int32_t wi = (int32_t)(b - ns);
+            int64_t s = a;
+            const double *xsph = o->xs + 3 * s;
+            double R = o->rad[s], phi;
+            uint32_t cs = o->owner[s];
+            boundary_distance(o, wi, t, xsph, &phi, n);
+            delta = R - phi;
+            double lever = R - 0.5 * delta;
+            for (int i = 0; i < 3; i++) p[i] = xsph[i] - lever * n[i];
+            const double *P = o->bparam + NPARAM_BND * wi;
+            double cwall[3], wv[3], pw[3];
+            for (int i = 0; i < 3; i++) cwall[i] = P[i] + t * o->bvel[3 * wi + i];
+            for (int i = 0; i < 3; i++) { ra[i] = p[i] - cwall[i]; rb[i] = p[i] - o->x[3 * cs + i]; }
+            cross(o->bomega + 3 * wi, ra, pw);
+            double wb[3];
+            cross(o->ww + 3 * cs, rb, wb);
+            for (int i = 0; i < 3; i++) wv[i] = o->bvel[3 * wi + i] + pw[i];
+            for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cs + i] + wb[i]) - wv[i];
+            Rbar = R;
+            mbar = o->mass[cs];
+            estar = 1.0 / (o->be[wi] + o->me[s]);
+            gstar = 1.0 / (o->bg[wi] + o->mg[s]);
+            mu = fmin(o->bmu[wi], o->mmu[s]);
+            beta = fmin(o->bbeta[wi], o->mbeta[s]);
+        }
+        o->cdelta[k] = delta;
+        for (int i = 0; i < 3; i++) { o->cra[3 * k + i] = ra[i]; o->crb[3 * k + i] = rb[i]; }
+        if (delta > 0.0) {
+            contact_law(n, delta, vrel, Rbar, mbar, estar, gstar, mu, beta, h, u_old, F, un);
+        } else {
+            for (int i = 0; i < 3; i++) { F[i] = 0.0; un[i] = 0.0; }
+        }
+    }
+
+    /* transposed index: contacts in which sphere s is the higher sphere id */
+    for (int64_t s = 0; s <= ns; s++) o->lo_beg[s] = 0;
+    for (int64_t k = 0; k < nk; k++) {
+        int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu);
+        if (b < ns) o->lo_beg[b + 1]++;
+    }
+    for (int64_t s = 0; s < ns; s++) o->lo_beg[s + 1] += o->lo_beg[s];
+    free(o->lo_idx);
+    o->lo_idx = (int64_t *)xmalloc((o->lo_beg[ns] + 1) * sizeof(int64_t));
+    {
+        int64_t *fill = (int64_t *)xmalloc((ns + 1) * sizeof(int64_t));
+        memcpy(fill, o->lo_beg, (ns + 1) * sizeof(int64_t));
+        for (int64_t k = 0; k < nk; k++) {
+            int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu);
+            if (b < ns) o->lo_idx[fill[b]++] = k;
+        }
+        free(fill);
+    }
+    /* row start of each sphere's own (higher-partner) contacts */
+    int64_t *hi_beg = (int64_t *)xmalloc((ns + 1) * sizeof(int64_t));
+    {
+        int64_t k = 0;
+        for (int64_t s = 0; s < ns; s++) {
+            hi_beg[s] = k;
+            while (k < nk && (int64_t)(o->ckey[k] >> 32) == s) k++;
+        }
+        hi_beg[ns] = nk;
+    }
+
+    /* per-sphere sums in ascending partner id */
+#pragma omp parallel for schedule(static)
+    for (int64_t s = 0; s < ns; s++) {
+        double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
+        for (int64_t j = o->lo_beg[s]; j < o->lo_beg[s + 1]; j++) { /* s is body b */
+            int64_t k = o->lo_idx[j];
+            if (!(o->cdelta[k] > 0.0)) continue;
+            const double *F = o->cF + 3 * k;
+            double tq[3];
+            cross(o->crb + 3 * k, F, tq);
+            for (int i = 0; i < 3; i++) { Fs[i] = Fs[i] + F[i]; Ts[i] = Ts[i] + tq[i]; }
+        }
+        for (int64_t k = hi_beg[s]; k < hi_beg[s + 1]; k++) {
+            if (!(o->cdelta[k] > 0.0)) continue;
+            int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu);
+            const double *F = o->cF + 3 * k;
+            double tq[3], f[3];
+            if (b < ns) { /* s is body a: receives -F */
+                for (int i = 0; i < 3; i++) f[i] = -F[i];
+                cross(o->cra + 3 * k, f, tq);
+            } else {      /* boundary contact: s is body b */
+                for (int i = 0; i < 3; i++) f[i] = F[i];
+                cross(o->crb + 3 * k, f, tq);
+            }
+            for (int i = 0; i < 3; i++) { Fs[i] = Fs[i] + f[i]; Ts[i] = Ts[i] + tq[i]; }
+        }
+        for (int i = 0; i < 3; i++) { o->sF[3 * s + i] = Fs[i]; o->sT[3 * s + i] = Ts[i]; }
+    }
+    free(hi_beg);
+
+    /* per-clump sums in ascending sphere id, then gravity */
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; c++) {
+        double Fc[3] = {0.0, 0.0, 0.0}, Tc[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = o->sbeg[c]; s < o->sbeg[c + 1]; s++)
+            for (int i = 0; i < 3; i++) { Fc[i] = Fc[i] + o->sF[3 * s + i]; Tc[i] = Tc[i] + o->sT[3 * s + i]; }
+        const double *g = o->grav + 3 * o->scene[c];
+        for (int i = 0; i < 3; i++) Fc[i] = Fc[i] + o->mass[c] * g[i];
+        for (int i = 0; i < 3; i++) { o->cFc[3 * c + i] = Fc[i]; o->cTc[3 * c + i] = Tc[i]; }
+    }
+    return nk;
+}
+
+/* ---------------- integration ---------------- */
+
+static void integrate(dem_oracle *o) {
+    int64_t nc = o->nc;
+    double h = o->h;
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < nc; c++) {
+        const double *F = o->cFc + 3 * c, *T = o->cTc + 3 * c, *A = o->A + 9 * c;
+        double *x = o->x + 3 * c, *v = o->v + 3 * c, *w = o->w + 3 * c, *q = o->q + 4 * c;
+        double M = o->mass[c];
+        const double *I = o->inertia + 3 * c;
+        int32_t pi = o->presc[c];
+        if (pi < 0) {
+            for (int i = 0; i < 3; i++) v[i] = v[i] + h * (F[i] / M);
+            for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+            /* body-frame torque and Euler's equations with the gyroscopic term */
+            double tb[3];
+            for (int i = 0; i < 3; i++) tb[i] = A[i] * T[0] + A[3 + i] * T[1] + A[6 + i] * T[2];
+            double L[3] = {I[0] * w[0], I[1] * w[1], I[2] * w[2]};
+            double gy[3];
+            cross(w, L, gy);
+            for (int i = 0; i < 3; i++) w[i] = w[i] + h * ((tb[i] - gy[i]) / I[i]);
+        } else {
+            const double *P = o->presc_param + NPARAM_PRESC * pi;
+            for (int i = 0; i < 3; i++) {
+                if (P[3 + i] != 0.0) v[i] = v[i] + h * ((F[i] + P[9 + i]) / M);
+                else v[i] = P[i];
+            }
+            for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+            for (int i = 0; i < 3; i++) w[i] = P[6 + i];
+        }
+        /* q <- q + (h/2) q (x) (0, w), then renormalise */
+        double dq[4];
+        dq[0] = -(q[1] * w[0] + q[2] * w[1] + q[3] * w[2]);
+        dq[1] = q[0] * w[0] + q[2] * w[2] - q[3] * w[1];
+        dq[2] = q[0] * w[1] + q[3] * w[0] - q[1] * w[2];
+        dq[3] = q[0] * w[2] + q[1] * w[1] - q[2] * w[0];
+        double hh = 0.5 * h;
+        for (int i = 0; i < 4; i++) q[i] = q[i] + hh * dq[i];
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        for (int i = 0; i < 4; i++) q[i] = q[i] / qn;
+    }
+}
+
+void dem_oracle_step(dem_oracle *o, int64_t n) {
+    for (int64_t it = 0; it < n; it++) {
+        dem_oracle_eval(o);
+        /* commit history: every contact of this step with its updated u */
+        free(o->hkey);
+        free(o->hu);
+        o->nh = o->ncont;
+        o->hkey = (uint64_t *)xmalloc(o->nh * sizeof(uint64_t));
+        o->hu = (double *)xmalloc(3 * o->nh * sizeof(double));
+        if (o->nh) {
+            memcpy(o->hkey, o->ckey, o->nh * sizeof(uint64_t));
+            memcpy(o->hu, o->cu, 3 * o->nh * sizeof(double));
+        }
+        integrate(o);
+        o->step++;
+    }
+}
+
+/* ---------------- readers ---------------- */
+
+void dem_oracle_read_contacts(const dem_oracle *o, uint32_t *a, uint32_t *b, double *delta, double *F, double *u) {
+    for (int64_t k = 0; k < o->ncont; k++) {
+        if (a) a[k] = (uint32_t)(o->ckey[k] >> 32);
+        if (b) b[k] = (uint32_t)(o->ckey[k] & 0xffffffffu);
+        if (delta) delta[k] = o->cdelta[k];
+    }
+    if (F && o->ncont) memcpy(F, o->cF, 3 * o->ncont * sizeof(double));
+    if (u && o->ncont) memcpy(u, o->cu, 3 * o->ncont * sizeof(double));
+}
+
+void dem_oracle_read_clump_forces(const dem_oracle *o, double *F, double *T) {
+    if (F) memcpy(F, o->cFc, 3 * o->nc * sizeof(double));
+    if (T) memcpy(T, o->cTc, 3 * o->nc * sizeof(double));
+}
+
+void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T) {
+    if (F) memcpy(F, o->sF, 3 * o->ns * sizeof(double));
+    if (T) memcpy(T, o->sT, 3 * o->ns * sizeof(double));
+}
+
+void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w) {
+    if (x) memcpy(x, o->x, 3 * o->nc * sizeof(double));
+    if (q) memcpy(q, o->q, 4 * o->nc * sizeof(double));
+    if (v) memcpy(v, o->v, 3 * o->nc * sizeof(double));
+    if (w) memcpy(w, o->w, 3 * o->nc * sizeof(double));
+}
+
+void dem_oracle_read_sphere_pos(const dem_oracle *o, double *xs) {
+    /* positions of the current state */
+    compute_poses((dem_oracle *)o);
+    memcpy(xs, o->xs, 3 * o->ns * sizeof(double));
+}
+
+int64_t dem_oracle_candidates(dem_oracle *o, const double *margin, uint32_t *a, uint32_t *b, int64_t cap) {
+    compute_poses(o);
+    uint64_t *keys = NULL;
+    int64_t n = collect_pairs(o, margin, &keys);
+    for (int64_t k = 0; k < n && k < cap; k++) {
+        if (a) a[k] = (uint32_t)(keys[k] >> 32);
+        if (b) b[k] = (uint32_t)(keys[k] & 0xffffffffu);
+    }
+    free(keys);
+    return n;
+}

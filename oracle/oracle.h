@@ -1,0 +1,103 @@
+/*
+ * FP64 brute-force CPU oracle of the clumped-sphere DEM timestep.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the HIP implementation.
+ *
+ * What it computes (paper: Sec. 2.1 and Sec. 2.2):
+ *   sphere world positions from clump poses (multi-sphere clumps, Sec. 2.1);
+ *   the contact set by O(N^2) brute force (every candidate pair tested,
+ *   no binning, no margin);
+ *   sphere-boundary contacts against analytic primitives;
+ *   the Hertz-Mindlin law of Eq. "normal_tangential_force_model1/2" with the
+ *   kinematics of Eq. "kinematicsContactInfo", the tangential history update
+ *   of Eq. "updateUt" and its Coulomb clamp of Eq. "cappingOfut";
+ *   accumulation onto clumps and the Newton-Euler equations of
+ *   Eq. "newton_law_1/2", advanced by symplectic Euler.
+ *
+ * Everything is IEEE FP64, evaluated in a fixed order (see oracle.c).
+ * All arrays are SI, structure-of-arrays, 0-based; the descriptor is borrowed
+ * for the duration of dem_oracle_create only.
+ */
+#ifndef DEM_ORACLE_H
+#define DEM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dem_oracle dem_oracle;
+
+typedef struct dem_oracle_desc {
+    double h;                          /* time step [s] */
+    int32_t n_templates;
+    const uint32_t *tmpl_sphere_begin; /* [n_templates+1] CSR into template spheres */
+    const double *tmpl_offset;         /* [n_tmpl_spheres][3] body frame, about the CoM */
+    const double *tmpl_radius;         /* [n_tmpl_spheres] */
+    const double *tmpl_mass;           /* [n_templates] */
+    const double *tmpl_inertia;        /* [n_templates][3] principal moments */
+    int64_t n_clumps;
+    const uint32_t *clump_template;    /* [n_clumps] */
+    const uint32_t *clump_scene;       /* [n_clumps] */
+    const double *x;                   /* [n_clumps][3] CoM position (world) */
+    const double *q;                   /* [n_clumps][4] unit quaternion w,x,y,z (body->world) */
+    const double *v;                   /* [n_clumps][3] CoM velocity (world) */
+    const double *w;                   /* [n_clumps][3] angular velocity (body frame) */
+    const double *sphere_mat;          /* [n_spheres][4] E, nu, mu, CoR per sphere instance */
+    int32_t n_scenes;
+    const double *gravity;             /* [n_scenes][3] */
+    int32_t n_bnd;
+    const int32_t *bnd_type;           /* [n_bnd] 0 plane, 1 cyl_in, 2 cone_out, 3 frustum_in */
+    const double *bnd_param;           /* [n_bnd][12] geometry at t = 0 */
+    const double *bnd_mat;             /* [n_bnd][4] E, nu, mu, CoR */
+    const double *bnd_vel;             /* [n_bnd][3] prescribed translation velocity */
+    const double *bnd_omega;           /* [n_bnd][3] prescribed spin about the reference point */
+    const int32_t *bnd_scene;          /* [n_bnd] */
+    int32_t n_presc;
+    const int32_t *presc_clump;        /* [n_presc] */
+    const double *presc_param;         /* [n_presc][12] v_fixed, free mask, w_body, f_extra */
+} dem_oracle_desc;
+
+/* Returns NULL on invalid input (message via dem_oracle_last_error). */
+dem_oracle *dem_oracle_create(const dem_oracle_desc *d);
+void dem_oracle_destroy(dem_oracle *o);
+const char *dem_oracle_last_error(void);
+void dem_oracle_set_threads(int n);
+
+/* Advance n steps; each step evaluates contacts and forces, commits the
+ * tangential history and integrates. */
+void dem_oracle_step(dem_oracle *o, int64_t n);
+int64_t dem_oracle_step_count(const dem_oracle *o);
+
+/* Evaluate contacts and forces at the current state without advancing and
+ * without committing history.  Returns the number of contacts (sphere-sphere
+ * and sphere-boundary).  The results stay readable until the next call. */
+int64_t dem_oracle_eval(dem_oracle *o);
+
+/* Contacts of the last evaluation, ascending by (a, b).  Sphere-sphere pairs
+ * have a < b < n_spheres; a boundary contact has a = sphere and
+ * b = n_spheres + boundary index.  F is the force on b (the negative acts on
+ * a), u the tangential history after this step's update and clamp.
+ * Any output pointer may be NULL. */
+void dem_oracle_read_contacts(const dem_oracle *o, uint32_t *a, uint32_t *b, double *delta,
+                              double *F, double *u);
+void dem_oracle_read_clump_forces(const dem_oracle *o, double *F, double *T);
+void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T);
+void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w);
+void dem_oracle_read_sphere_pos(const dem_oracle *o, double *xs);
+int64_t dem_oracle_n_spheres(const dem_oracle *o);
+
+/* Brute-force enlarged-geometry candidates at the current state:
+ * sphere pairs with d^2 < ((Ra+Rb)+(ma+mb))^2 and boundary pairs with
+ * phi < R + m.  margin may be NULL (all zero).  Writes at most cap pairs,
+ * returns the total count. */
+int64_t dem_oracle_candidates(dem_oracle *o, const double *margin, uint32_t *a, uint32_t *b,
+                              int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

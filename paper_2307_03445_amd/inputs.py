@@ -1,0 +1,538 @@
+"""Seeded synthetic scene generators for the clumped-sphere DEM timestep.
+
+This module produces *inputs only*: clump templates (sphere offsets, radii,
+mass and principal inertia), clump states, per-sphere materials, analytic
+boundaries and prescribed-motion bodies.  It holds none of the timestep's
+arithmetic (no contact detection, no force law, no integration), so that both
+the FP64 CPU oracle and the HIP path can be driven from the same seeded inputs
+without sharing any of the method's code.
+
+The element model follows the paper's multi-sphere clump representation
+(Sec. 2.1, "clump" paragraph and Fig. "force"): a clump is a rigid union of
+possibly overlapping spheres; mass and moment of inertia belong to the clump,
+while E, nu, mu and CoR belong to each sphere instance.
+
+Conventions (shared by every consumer of a :class:`SceneDesc`):
+
+* SI units, 0-based indices, structure-of-arrays.
+* Template sphere offsets are expressed in the clump's principal body frame,
+  relative to the clump centre of mass; ``tmpl_inertia`` holds the principal
+  moments about the centre of mass.
+* ``q`` is a unit quaternion (w, x, y, z) rotating body to world.
+* ``w`` is the angular velocity in the *body* (principal) frame.
+* Spheres are numbered clump by clump: clump ``c`` owns the consecutive sphere
+  ids ``sphere_begin[c] .. sphere_begin[c+1]-1`` in template order.
+* ``sphere_mat[s] = (E, nu, mu, CoR)`` for every sphere instance ``s``.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_ROOT = 230703445
+
+# Boundary primitive types.  Parameters (12 doubles per boundary), at t = 0:
+#   PLANE      : p0[3], n[3]                      (n: unit normal into the domain)
+#   CYL_IN     : p0[3], a[3], R                   (domain inside the cylinder)
+#   CONE_OUT   : apex[3], a[3], sin, cos, H       (solid cone + shaft, domain outside;
+#                                                  a points from the apex into the solid)
+#   FRUSTUM_IN : apex[3], a[3], sin, cos, t0, t1  (funnel wall, domain inside,
+#                                                  active for axial distance t0..t1)
+BND_PLANE, BND_CYL_IN, BND_CONE_OUT, BND_FRUSTUM_IN = 0, 1, 2, 3
+BND_NPARAM = 12
+
+# Prescribed-motion parameters (12 doubles per prescribed clump):
+#   v_fixed[3], free[3] (1.0 = component integrated, 0.0 = held at v_fixed),
+#   w_body[3] (angular velocity held fixed, body frame), f_extra[3] (world force
+#   added to free components).
+PRESC_NPARAM = 12
+
+DENSITY = 2600.0
+
+
+def rng(config_index: int, replica: int = 0) -> np.random.Generator:
+    """Generator for configuration ``config_index`` (1-based) and replica."""
+    return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(config_index, replica)))
+
+
+@dataclass
+class SceneDesc:
+    """Complete input of one (possibly batched) DEM simulation."""
+
+    h: float
+    tmpl_sphere_begin: np.ndarray
+    tmpl_offset: np.ndarray
+    tmpl_radius: np.ndarray
+    tmpl_mass: np.ndarray
+    tmpl_inertia: np.ndarray
+    clump_template: np.ndarray
+    clump_scene: np.ndarray
+    x: np.ndarray
+    q: np.ndarray
+    v: np.ndarray
+    w: np.ndarray
+    sphere_mat: np.ndarray
+    gravity: np.ndarray
+    domain: np.ndarray
+    bnd_type: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    bnd_param: np.ndarray = field(default_factory=lambda: np.zeros((0, BND_NPARAM)))
+    bnd_mat: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
+    bnd_vel: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    bnd_omega: np.ndarray = field(default_factory=lambda: np.zeros((0, 3)))
+    bnd_scene: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    presc_clump: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    presc_param: np.ndarray = field(default_factory=lambda: np.zeros((0, PRESC_NPARAM)))
+    name: str = "scene"
+
+    # ---- derived sizes -------------------------------------------------
+    @property
+    def n_templates(self) -> int:
+        return int(self.tmpl_mass.shape[0])
+
+    @property
+    def n_clumps(self) -> int:
+        return int(self.clump_template.shape[0])
+
+    @property
+    def n_scenes(self) -> int:
+        return int(self.gravity.shape[0])
+
+    @property
+    def n_bnd(self) -> int:
+        return int(self.bnd_type.shape[0])
+
+    def clump_sphere_counts(self) -> np.ndarray:
+        tsz = np.diff(self.tmpl_sphere_begin.astype(np.int64))
+        return tsz[self.clump_template.astype(np.int64)]
+
+    def sphere_begin(self) -> np.ndarray:
+        cnt = self.clump_sphere_counts()
+        out = np.zeros(self.n_clumps + 1, np.int64)
+        np.cumsum(cnt, out=out[1:])
+        return out
+
+    @property
+    def n_spheres(self) -> int:
+        return int(self.clump_sphere_counts().sum())
+
+    def canonical(self) -> "SceneDesc":
+        """Return a copy with every array in the dtype/layout the bindings expect."""
+        f = lambda a, s=None: np.ascontiguousarray(np.asarray(a, np.float64).reshape(s) if s else np.asarray(a, np.float64))
+        nt, nc, nb, npr, ns = self.n_templates, self.n_clumps, len(self.bnd_type), len(self.presc_clump), self.gravity.size // 3
+        return dataclasses.replace(
+            self,
+            h=float(self.h),
+            tmpl_sphere_begin=np.ascontiguousarray(self.tmpl_sphere_begin, np.uint32),
+            tmpl_offset=f(self.tmpl_offset, (-1, 3)),
+            tmpl_radius=f(self.tmpl_radius),
+            tmpl_mass=f(self.tmpl_mass),
+            tmpl_inertia=f(self.tmpl_inertia, (nt, 3)),
+            clump_template=np.ascontiguousarray(self.clump_template, np.uint32),
+            clump_scene=np.ascontiguousarray(self.clump_scene, np.uint32),
+            x=f(self.x, (nc, 3)), q=f(self.q, (nc, 4)), v=f(self.v, (nc, 3)), w=f(self.w, (nc, 3)),
+            sphere_mat=f(self.sphere_mat, (-1, 4)),
+            gravity=f(self.gravity, (ns, 3)), domain=f(self.domain, (ns, 6)),
+            bnd_type=np.ascontiguousarray(self.bnd_type, np.int32),
+            bnd_param=f(self.bnd_param, (nb, BND_NPARAM)), bnd_mat=f(self.bnd_mat, (nb, 4)),
+            bnd_vel=f(self.bnd_vel, (nb, 3)), bnd_omega=f(self.bnd_omega, (nb, 3)),
+            bnd_scene=np.ascontiguousarray(self.bnd_scene, np.int32),
+            presc_clump=np.ascontiguousarray(self.presc_clump, np.int32),
+            presc_param=f(self.presc_param, (npr, PRESC_NPARAM)),
+        )
+
+    def validate(self) -> None:
+        """Raise ValueError for inputs no consumer may accept."""
+        d = self
+        nt = d.n_templates
+        if d.tmpl_sphere_begin.shape != (nt + 1,) or d.tmpl_sphere_begin[0] != 0:
+            raise ValueError("tmpl_sphere_begin must be a CSR offset array starting at 0")
+        if np.any(np.diff(d.tmpl_sphere_begin.astype(np.int64)) < 1):
+            raise ValueError("every template needs at least one sphere")
+        nts = int(d.tmpl_sphere_begin[-1])
+        if d.tmpl_offset.shape != (nts, 3) or d.tmpl_radius.shape != (nts,):
+            raise ValueError("template sphere arrays have the wrong shape")
+        if np.any(d.tmpl_radius <= 0) or np.any(d.tmpl_mass <= 0) or np.any(d.tmpl_inertia <= 0):
+            raise ValueError("radii, masses and inertias must be positive")
+        if d.n_clumps and int(d.clump_template.max()) >= nt:
+            raise ValueError("clump_template out of range")
+        if d.n_clumps and int(d.clump_scene.max()) >= d.n_scenes:
+            raise ValueError("clump_scene out of range")
+        qn = np.linalg.norm(d.q, axis=1)
+        if np.any(np.abs(qn - 1.0) > 1e-12):
+            raise ValueError("quaternions must be unit")
+        m = d.sphere_mat
+        if m.shape != (d.n_spheres, 4):
+            raise ValueError("sphere_mat must have one (E, nu, mu, CoR) row per sphere")
+        for mm in (m, d.bnd_mat):
+            if mm.size and (np.any(mm[:, 0] <= 0) or np.any(mm[:, 1] <= -1) or np.any(mm[:, 1] >= 0.5)
+                            or np.any(mm[:, 2] < 0) or np.any(mm[:, 3] <= 0) or np.any(mm[:, 3] > 1)):
+                raise ValueError("material out of range (E>0, -1<nu<0.5, mu>=0, 0<CoR<=1)")
+        if not (d.h > 0):
+            raise ValueError("time step must be positive")
+
+
+# ---------------------------------------------------------------------------
+# Rotations (input construction only)
+# ---------------------------------------------------------------------------
+
+def random_unit_quaternions(g: np.random.Generator, n: int) -> np.ndarray:
+    """Uniformly distributed unit quaternions (Shoemake's subgroup method)."""
+    u1, u2, u3 = g.random(n), g.random(n), g.random(n)
+    a, b = np.sqrt(1.0 - u1), np.sqrt(u1)
+    q = np.stack([b * np.cos(2 * np.pi * u3), a * np.sin(2 * np.pi * u2),
+                  a * np.cos(2 * np.pi * u2), b * np.sin(2 * np.pi * u3)], axis=1)
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    q[q[:, 0] < 0] *= -1.0
+    return q
+
+
+def random_unit_vectors(g: np.random.Generator, n: int) -> np.ndarray:
+    z = g.normal(size=(n, 3))
+    return z / np.linalg.norm(z, axis=1, keepdims=True)
+
+
+# ---------------------------------------------------------------------------
+# Template mass properties (voxel integration of the sphere union)
+# ---------------------------------------------------------------------------
+
+def union_mass_properties(offsets: np.ndarray, radii: np.ndarray, density: float = DENSITY, res: int = 48):
+    """Mass, centre of mass and inertia tensor of a union of spheres.
+
+    Midpoint-rule integration on a ``res``^3 grid over the union's bounding
+    box.  Accuracy is that of the grid; both consumers receive the same numbers,
+    so nothing downstream depends on it beyond physical plausibility.
+    Returns (mass, com[3], inertia_about_com[3,3]).
+    """
+    offsets = np.asarray(offsets, np.float64).reshape(-1, 3)
+    radii = np.asarray(radii, np.float64).reshape(-1)
+    if offsets.shape[0] == 1:
+        m = density * 4.0 / 3.0 * np.pi * radii[0] ** 3
+        return m, offsets[0].copy(), np.eye(3) * (0.4 * m * radii[0] ** 2)
+    lo = (offsets - radii[:, None]).min(0)
+    hi = (offsets + radii[:, None]).max(0)
+    step = (hi - lo) / res
+    axes = [lo[k] + (np.arange(res) + 0.5) * step[k] for k in range(3)]
+    X, Y, Z = np.meshgrid(*axes, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    inside = np.zeros(P.shape[0], bool)
+    for o, r in zip(offsets, radii):
+        inside |= ((P - o) ** 2).sum(1) <= r * r
+    P = P[inside]
+    dV = float(np.prod(step))
+    mass = density * dV * P.shape[0]
+    com = P.mean(0)
+    d = P - com
+    dm = density * dV
+    r2 = (d * d).sum(1)
+    I = dm * (np.eye(3) * r2.sum() - d.T @ d)
+    return mass, com, I
+
+
+def principal_template(offsets: np.ndarray, radii: np.ndarray, density: float = DENSITY, res: int = 48):
+    """Recentre a sphere set on its CoM and rotate it to principal axes.
+
+    Returns (body_offsets[n,3], radii[n], mass, principal_moments[3]).
+    """
+    mass, com, I = union_mass_properties(offsets, radii, density, res)
+    evals, evecs = np.linalg.eigh(I)
+    if np.linalg.det(evecs) < 0:
+        evecs[:, 2] *= -1.0
+    body = (np.asarray(offsets, np.float64) - com) @ evecs
+    return body, np.asarray(radii, np.float64).copy(), float(mass), evals.astype(np.float64)
+
+
+def sphere_template(r: float, density: float = DENSITY):
+    """A single-sphere clump: exact mass and moment of inertia."""
+    m = density * 4.0 / 3.0 * math.pi * r ** 3
+    return np.zeros((1, 3)), np.array([r]), m, np.full(3, 0.4 * m * r * r)
+
+
+def bounding_radius(body_offsets: np.ndarray, radii: np.ndarray) -> float:
+    return float((np.linalg.norm(body_offsets, axis=1) + radii).max())
+
+
+# ---------------------------------------------------------------------------
+# Assembly helpers
+# ---------------------------------------------------------------------------
+
+def assemble(templates, clump_template, x, q, v, w, sphere_mat, gravity, domain, h,
+             clump_scene=None, bnd=None, presc=None, name="scene") -> SceneDesc:
+    """Build a SceneDesc from a list of (offsets, radii, mass, moments) templates."""
+    sizes = [t[0].shape[0] for t in templates]
+    begin = np.zeros(len(templates) + 1, np.uint32)
+    begin[1:] = np.cumsum(sizes)
+    nc = len(clump_template)
+    ng = np.asarray(gravity, np.float64).reshape(-1, 3).shape[0]
+    d = SceneDesc(
+        h=h,
+        tmpl_sphere_begin=begin,
+        tmpl_offset=np.concatenate([t[0] for t in templates]).reshape(-1, 3),
+        tmpl_radius=np.concatenate([t[1] for t in templates]),
+        tmpl_mass=np.array([t[2] for t in templates], np.float64),
+        tmpl_inertia=np.array([t[3] for t in templates], np.float64).reshape(-1, 3),
+        clump_template=np.asarray(clump_template, np.uint32),
+        clump_scene=np.zeros(nc, np.uint32) if clump_scene is None else np.asarray(clump_scene, np.uint32),
+        x=np.asarray(x, np.float64).reshape(nc, 3), q=np.asarray(q, np.float64).reshape(nc, 4),
+        v=np.asarray(v, np.float64).reshape(nc, 3), w=np.asarray(w, np.float64).reshape(nc, 3),
+        sphere_mat=np.asarray(sphere_mat, np.float64).reshape(-1, 4),
+        gravity=np.asarray(gravity, np.float64).reshape(ng, 3),
+        domain=np.asarray(domain, np.float64).reshape(ng, 6),
+        name=name,
+    )
+    if bnd:
+        d.bnd_type = np.array([b["type"] for b in bnd], np.int32)
+        P = np.zeros((len(bnd), BND_NPARAM))
+        for i, b in enumerate(bnd):
+            P[i, :len(b["param"])] = b["param"]
+        d.bnd_param = P
+        d.bnd_mat = np.array([b["mat"] for b in bnd], np.float64).reshape(-1, 4)
+        d.bnd_vel = np.array([b.get("vel", (0, 0, 0)) for b in bnd], np.float64).reshape(-1, 3)
+        d.bnd_omega = np.array([b.get("omega", (0, 0, 0)) for b in bnd], np.float64).reshape(-1, 3)
+        d.bnd_scene = np.array([b.get("scene", 0) for b in bnd], np.int32)
+    if presc:
+        d.presc_clump = np.array([p["clump"] for p in presc], np.int32)
+        P = np.zeros((len(presc), PRESC_NPARAM))
+        for i, p in enumerate(presc):
+            P[i, 0:3] = p.get("v_fixed", (0, 0, 0))
+            P[i, 3:6] = p.get("free", (0, 0, 0))
+            P[i, 6:9] = p.get("w_body", (0, 0, 0))
+            P[i, 9:12] = p.get("f_extra", (0, 0, 0))
+        d.presc_param = P
+    return d.canonical()
+
+
+def box_walls(lo, hi, mat, floor=True, ceiling=False, scene=0):
+    """Axis-aligned planes: floor (z=lo), the four sides, optionally a ceiling."""
+    (x0, y0, z0), (x1, y1, z1) = lo, hi
+    walls = []
+    if floor:
+        walls.append(dict(type=BND_PLANE, param=(0, 0, z0, 0, 0, 1), mat=mat, scene=scene))
+    walls += [dict(type=BND_PLANE, param=(x0, 0, 0, 1, 0, 0), mat=mat, scene=scene),
+              dict(type=BND_PLANE, param=(x1, 0, 0, -1, 0, 0), mat=mat, scene=scene),
+              dict(type=BND_PLANE, param=(0, y0, 0, 0, 1, 0), mat=mat, scene=scene),
+              dict(type=BND_PLANE, param=(0, y1, 0, 0, -1, 0), mat=mat, scene=scene)]
+    if ceiling:
+        walls.append(dict(type=BND_PLANE, param=(0, 0, z1, 0, 0, -1), mat=mat, scene=scene))
+    return walls
+
+
+def lattice_sites(nx, ny, nz, spacing, origin):
+    """Simple-cubic lattice sites, x fastest, then y, then z."""
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    pts = np.stack([i.ravel(), j.ravel(), k.ravel()], 1).astype(np.float64) * spacing
+    return pts + np.asarray(origin, np.float64)
+
+
+# ---------------------------------------------------------------------------
+# Sequential deposition (contact-rich initial states)
+# ---------------------------------------------------------------------------
+
+def quat_matrix(q: np.ndarray) -> np.ndarray:
+    """Rotation matrices of unit quaternions (input construction only)."""
+    w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
+    return np.stack([
+        np.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)], -1),
+        np.stack([2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)], -1),
+        np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
+
+
+def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_max, floor_z=0.0):
+    """Drop clumps one by one onto a growing pile.
+
+    Each clump gets a uniformly random orientation and a uniformly random
+    (x, y) that keeps it inside ``footprint = (x0, y0, x1, y1)``; it falls
+    vertically to the highest position at which one of its spheres first
+    touches an already placed sphere or the floor, and is then lowered by a
+    random sink ~ U[0, sink_max] so that it rests with a small overlap.
+    This is a geometric construction of a contact-rich initial state; no
+    dynamics is simulated.  Returns (x[n,3], q[n,4]).
+    """
+    x0, y0, x1, y1 = footprint
+    n = len(clump_template)
+    q = random_unit_quaternions(g, n)
+    R = quat_matrix(q)
+    rmax = max(float(t[1].max()) for t in templates)
+    cell = 2.0 * rmax
+    nx = max(1, int(math.ceil((x1 - x0) / cell)))
+    ny = max(1, int(math.ceil((y1 - y0) / cell)))
+    cols = [[] for _ in range(nx * ny)]
+    P = []   # placed sphere centres
+    Rr = []  # placed sphere radii
+    xs = np.empty((n, 3))
+    for i in range(n):
+        off, rad = templates[clump_template[i]][0], templates[clump_template[i]][1]
+        wo = off @ R[i].T
+        lo_x = float((wo[:, 0] - rad).min()); hi_x = float((wo[:, 0] + rad).max())
+        lo_y = float((wo[:, 1] - rad).min()); hi_y = float((wo[:, 1] + rad).max())
+        cx = g.uniform(x0 - lo_x, x1 - hi_x)
+        cy = g.uniform(y0 - lo_y, y1 - hi_y)
+        zc = float((floor_z + rad - wo[:, 2]).max())  # resting on the floor
+        ix0 = max(0, int((cx + lo_x - rmax - x0) // cell)); ix1 = min(nx - 1, int((cx + hi_x + rmax - x0) // cell))
+        iy0 = max(0, int((cy + lo_y - rmax - y0) // cell)); iy1 = min(ny - 1, int((cy + hi_y + rmax - y0) // cell))
+        cand = [k for jy in range(iy0, iy1 + 1) for jx in range(ix0, ix1 + 1) for k in cols[jy * nx + jx]]
+        if cand:
+            cand = np.asarray(cand)
+            Pc = np.asarray(P)[cand] if isinstance(P, np.ndarray) else np.array([P[k] for k in cand])
+            Rc = np.array([Rr[k] for k in cand])
+            sx = cx + wo[:, 0]; sy = cy + wo[:, 1]
+            dh2 = (sx[:, None] - Pc[None, :, 0]) ** 2 + (sy[:, None] - Pc[None, :, 1]) ** 2
+            S2 = (rad[:, None] + Rc[None, :]) ** 2
+            ok = dh2 < S2
+            if ok.any():
+                zt = np.where(ok, Pc[None, :, 2] + np.sqrt(np.where(ok, S2 - dh2, 0.0)) - wo[:, 2:3], -np.inf)
+                zc = max(zc, float(zt.max()))
+        zc -= g.uniform(0.0, sink_max)
+        zc = max(zc, float((floor_z + rad - wo[:, 2]).max()) - sink_max)
+        xs[i] = (cx, cy, zc)
+        for j in range(wo.shape[0]):
+            p = (cx + wo[j, 0], cy + wo[j, 1], zc + wo[j, 2])
+            k = len(P)
+            P.append(p); Rr.append(float(rad[j]))
+            jx = min(nx - 1, max(0, int((p[0] - x0) // cell))); jy = min(ny - 1, max(0, int((p[1] - y0) // cell)))
+            cols[jy * nx + jx].append(k)
+    return xs, q
+
+
+# ---------------------------------------------------------------------------
+# Configuration 1: 2,000 three-sphere clumps in a 5 cm box (CPU-checkable)
+# ---------------------------------------------------------------------------
+
+CFG1_MAT = (1e7, 0.3, 0.5, 0.5)
+
+
+def _unit_three_sphere_props(dirs: np.ndarray, res: int = 32):
+    """Mass properties of unit-radius three-sphere unions (centres 0.6 along
+    ``dirs[i, j]``), batched; returns (volume[n], com[n,3], inertia/density[n,3,3])."""
+    n = dirs.shape[0]
+    ext = 1.6
+    step = 2 * ext / res
+    ax = -ext + (np.arange(res) + 0.5) * step
+    X, Y, Z = np.meshgrid(ax, ax, ax, indexing="ij")
+    P = np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)
+    dV = step ** 3
+    PP = (P[:, :, None] * P[:, None, :]).reshape(-1, 9)
+    vol = np.empty(n); com = np.empty((n, 3)); I = np.empty((n, 3, 3))
+    for lo in range(0, n, 64):
+        cen = 0.6 * dirs[lo:lo + 64]                              # [b,3,3]
+        inside = np.zeros((cen.shape[0], P.shape[0]), bool)
+        for j in range(3):
+            c3 = cen[:, j, :]
+            d2 = (P * P).sum(1)[None, :] - 2.0 * (c3 @ P.T) + (c3 * c3).sum(1)[:, None]
+            inside |= d2 <= 1.0
+        inside = inside.astype(np.float64)                        # [b,p]
+        cnt = inside.sum(1)
+        c = inside @ P / cnt[:, None]
+        vol[lo:lo + 64] = cnt * dV
+        com[lo:lo + 64] = c
+        s1 = inside @ P                                           # [b,3]
+        s2 = (inside @ PP).reshape(-1, 3, 3)                       # [b,3,3]
+        cov = s2 - s1[:, :, None] * c[:, None, :] - c[:, :, None] * s1[:, None, :] \
+            + cnt[:, None, None] * c[:, :, None] * c[:, None, :]
+        tr = np.trace(cov, axis1=1, axis2=2)
+        I[lo:lo + 64] = (tr[:, None, None] * np.eye(3) - cov) * dV
+    return vol, com, I
+
+
+def _cfg1_templates(g: np.random.Generator, n: int, res: int = 32):
+    """n three-sphere templates, radius r ~ U[1,2] mm shared by the three spheres,
+    centres offset 0.6 r along independent random unit axes; recentred on the
+    CoM and rotated to principal axes (mass properties by voxel integration)."""
+    r = g.uniform(1e-3, 2e-3, n)
+    dirs = random_unit_vectors(g, 3 * n).reshape(n, 3, 3)
+    vol, com, I = _unit_three_sphere_props(dirs, res)
+    out = []
+    for i in range(n):
+        evals, evecs = np.linalg.eigh(I[i])
+        if np.linalg.det(evecs) < 0:
+            evecs[:, 2] *= -1.0
+        body = (0.6 * dirs[i] - com[i]) @ evecs * r[i]
+        mass = DENSITY * vol[i] * r[i] ** 3
+        out.append((body, np.full(3, r[i]), float(mass), DENSITY * evals * r[i] ** 5))
+    return out
+
+
+def config1(replica: int = 0, n_clumps: int = 2000, dense: bool = False, res: int = 32,
+            vel_noise: float = 0.05) -> SceneDesc:
+    """Configuration 1 (plain method, CPU-checkable).
+
+    2,000 clumps of three spheres each, one template per clump, random
+    orientation, simple-cubic lattice of spacing 2*max(bounding radius)+0.1 mm,
+    7 x 7 sites per layer inside a 5 cm x 5 cm footprint with a floor and four
+    side walls; the box height is raised to hold the lattice (the 5 cm cube of
+    the configuration cannot hold 2,000 non-overlapping clumps).  Velocity per
+    component ~ U[-0.05, 0.05] m/s, gravity -9.81 z, E=1e7 Pa, nu=0.3,
+    mu=0.5, CoR=0.5 for spheres and walls, h = 1e-6 s.
+
+    ``dense=True`` builds a contact-rich variant from the same clumps and
+    materials: the clumps are deposited one by one (:func:`deposit`) into the
+    5 cm x 5 cm footprint, each sinking up to 2 % of the smallest radius into
+    the pile, with the same velocity noise.
+    """
+    g = rng(1, replica)
+    tmpls = _cfg1_templates(g, n_clumps, res)
+    L = 0.05
+    mat = np.tile(np.array(CFG1_MAT), (3 * n_clumps, 1))
+    if dense:
+        x, q = deposit(g, tmpls, np.arange(n_clumps), (0.0, 0.0, L, L), 0.02 * 1e-3)
+        top = float(x[:, 2].max()) + 0.02
+    else:
+        rb = max(bounding_radius(t[0], t[1]) for t in tmpls)
+        spacing, nxy = 2.0 * rb + 1e-4, 7
+        nz = -(-n_clumps // (nxy * nxy))
+        origin = (L / 2 - spacing * (nxy - 1) / 2, L / 2 - spacing * (nxy - 1) / 2, spacing / 2 + 5e-5)
+        sites = lattice_sites(nxy, nxy, nz, spacing, origin)
+        perm = g.permutation(sites.shape[0])[:n_clumps]
+        x = sites[perm]
+        q = random_unit_quaternions(g, n_clumps)
+        top = nz * spacing + 0.01
+    v = g.uniform(-vel_noise, vel_noise, (n_clumps, 3))
+    w = np.zeros((n_clumps, 3))
+    walls = box_walls((0, 0, 0), (L, L, top), CFG1_MAT)
+    return assemble(tmpls, np.arange(n_clumps), x, q, v, w, mat, (0, 0, -9.81),
+                    (0, 0, 0, L, L, top), 1e-6, bnd=walls,
+                    name=f"cfg1{'-dense' if dense else ''}-r{replica}")
+
+
+# ---------------------------------------------------------------------------
+# Shared templates of configurations 2-5
+# ---------------------------------------------------------------------------
+
+CFG2_COUNTS = (1, 2, 3, 3, 3, 3, 4, 6)
+
+
+def lognormal_radii(g: np.random.Generator, n: int, median=2e-3, sigma=0.3):
+    """Lognormal radii (median 2 mm, sigma 0.3) clipped to +-3 sigma."""
+    z = np.clip(g.normal(size=n), -3.0, 3.0)
+    return median * np.exp(sigma * z)
+
+
+def multisphere_template(g: np.random.Generator, count: int, radii=None, res: int = 64):
+    """A template of ``count`` spheres, each offset 0.6 r along a random axis."""
+    r = lognormal_radii(g, count) if radii is None else np.asarray(radii, np.float64)
+    if count == 1:
+        return sphere_template(float(r[0]))
+    dirs = random_unit_vectors(g, count)
+    return principal_template(0.6 * r[:, None] * dirs, r, DENSITY, res)
+
+
+def cfg2_templates(replica: int = 0, res: int = 64):
+    g = rng(2, replica)
+    return [multisphere_template(g, c, res=res) for c in CFG2_COUNTS]
+
+
+# ---------------------------------------------------------------------------
+# Small hand-built scenes used to pin the oracle against closed forms
+# ---------------------------------------------------------------------------
+
+def two_sphere_headon(r=1e-3, v0=0.05, mat=CFG1_MAT, gap=1e-7, h=1e-6, r2=None):
+    """Two single-sphere clumps approaching head-on along x, no gravity."""
+    r2 = r if r2 is None else r2
+    t1, t2 = sphere_template(r), sphere_template(r2)
+    x = [(-(r + gap / 2), 0, 0), (r2 + gap / 2, 0, 0)]
+    v = [(v0 / 2, 0, 0), (-v0 / 2, 0, 0)]
+    q = [(1, 0, 0, 0)] * 2
+    return assemble([t1, t2], [0, 1], x, q, v, np.zeros((2, 3)), [mat, mat], (0, 0, 0),
+                    (-0.01, -0.01, -0.01, 0.01, 0.01, 0.01), h, name="headon")
