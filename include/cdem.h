@@ -1,0 +1,222 @@
+/*
+ * cdem -- clumped-sphere discrete-element timestep on MI355X (gfx950).
+ *
+ * C ABI of the HIP library libcdem.so.  Plain pointers and sizes only; no C++
+ * exception crosses this boundary.  Every function returns CDEM_OK (0) or a
+ * negative CDEM_E_* code; cdem_last_error() gives a message for the scene.
+ *
+ * The method (paper Sec. 2.1 and 2.2):
+ *   - elements are clumps: rigid unions of spheres; mass and inertia belong to
+ *     the clump, E, nu, mu and CoR to each sphere instance (Sec. 2.1, clump
+ *     paragraph and Fig. "force");
+ *   - each step detects contacts (spatial binning, Sec. 1 citing the binning
+ *     approach; enlarged contact geometry when detection is deferred, Sec. 2.2),
+ *     evaluates the Hertz-Mindlin force of Eq. normal_tangential_force_model1/2
+ *     with the kinematics of Eq. kinematicsContactInfo and a persistent
+ *     tangential history (Eqs. updateUt and cappingOfut), reduces forces and
+ *     torques onto the clumps and integrates Eq. newton_law_1/2;
+ *   - detection may run every step (the traditional scheme, Sec. 2.2) or every
+ *     k steps with a safety margin (the deferred active-set update of Sec. 2.2).
+ *
+ * Conventions: SI units; 0-based indices; arrays are row-major
+ * ([n][3] means n consecutive xyz triples).  Quaternions are (w, x, y, z),
+ * body to world.  Angular velocity is in the clump's principal body frame.
+ * Clump c owns consecutive sphere ids in template order.
+ */
+#ifndef CDEM_H
+#define CDEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDEM_ABI_VERSION 1
+
+/* ---- error codes ---- */
+#define CDEM_OK 0
+#define CDEM_E_INVALID (-1)        /* bad argument or descriptor (nothing changed) */
+#define CDEM_E_OOM (-2)            /* device allocation failed */
+#define CDEM_E_HIP (-3)            /* a HIP runtime call failed */
+#define CDEM_E_CAPACITY (-4)       /* contact storage overflowed and could not be regrown */
+#define CDEM_E_MISSED_CONTACT (-5) /* an audit found a contact missing from the active set */
+#define CDEM_E_NAN (-6)            /* non-finite state detected */
+#define CDEM_E_STATE (-7)          /* call not valid in the scene's current state */
+
+/* ---- enums ---- */
+#define CDEM_PREC_FP64 0       /* all force arithmetic in FP64 */
+#define CDEM_PREC_FP32_FORCE 1 /* force arithmetic in FP32; penetration, normal,
+                                  history, state and integration in FP64 */
+
+#define CDEM_DETECT_PLAIN 0   /* detect every step, no margin (Sec. 2.2, traditional scheme) */
+#define CDEM_DETECT_FIXED 1   /* detect every k steps, margin from the global maximum speed */
+#define CDEM_DETECT_LEARNED 2 /* detect every k steps, per-bin margins from the MLP envelope */
+
+#define CDEM_BND_PLANE 0      /* p0[3], n[3]: plane, unit normal into the domain */
+#define CDEM_BND_CYL_IN 1     /* p0[3], a[3], R: domain inside a cylinder */
+#define CDEM_BND_CONE_OUT 2   /* apex[3], a[3], sin, cos, H: solid cone + shaft, domain outside */
+#define CDEM_BND_FRUSTUM_IN 3 /* apex[3], a[3], sin, cos, t0, t1: funnel wall, domain inside */
+#define CDEM_BND_NPARAM 12
+#define CDEM_PRESC_NPARAM 12  /* v_fixed[3], free[3] (0/1), w_body[3], f_extra[3] */
+
+#define CDEM_HOST 0
+#define CDEM_DEVICE 1
+
+typedef struct cdem_scene cdem_scene;
+
+/* Scene description.  Borrowed for the duration of cdem_create only; every
+ * array is copied.  Pointers are host memory. */
+typedef struct cdem_scene_desc {
+    double h;                          /* time step [s], > 0 */
+    int32_t precision;                 /* CDEM_PREC_* */
+    int32_t n_templates;               /* >= 1 */
+    const uint32_t *tmpl_sphere_begin; /* [n_templates+1] CSR into template spheres */
+    const double *tmpl_offset;         /* [n_tmpl_spheres][3] body frame, about the CoM */
+    const double *tmpl_radius;         /* [n_tmpl_spheres] > 0 */
+    const double *tmpl_mass;           /* [n_templates] > 0 */
+    const double *tmpl_inertia;        /* [n_templates][3] principal moments > 0 */
+    int64_t n_clumps;
+    const uint32_t *clump_template;    /* [n_clumps] */
+    const uint32_t *clump_scene;       /* [n_clumps] < n_scenes */
+    const double *x;                   /* [n_clumps][3] CoM position */
+    const double *q;                   /* [n_clumps][4] unit quaternion */
+    const double *v;                   /* [n_clumps][3] CoM velocity */
+    const double *w;                   /* [n_clumps][3] angular velocity, body frame */
+    const double *sphere_mat;          /* [n_spheres][4] E > 0, -1 < nu < 0.5, mu >= 0, 0 < CoR <= 1 */
+    int32_t n_scenes;                  /* independent scenes sharing one launch (>= 1) */
+    const double *gravity;             /* [n_scenes][3] */
+    const double *domain;              /* [n_scenes][6] lo[3], hi[3]: binning box (spheres outside are
+                                          still handled, in the edge bins) */
+    int32_t n_bnd;                     /* <= 64 */
+    const int32_t *bnd_type;           /* [n_bnd] CDEM_BND_* */
+    const double *bnd_param;           /* [n_bnd][12] geometry at t = 0 */
+    const double *bnd_mat;             /* [n_bnd][4] E, nu, mu, CoR */
+    const double *bnd_vel;             /* [n_bnd][3] translation velocity (geometry moves) */
+    const double *bnd_omega;           /* [n_bnd][3] surface spin about the reference point
+                                          (geometry is taken as invariant under it) */
+    const int32_t *bnd_scene;          /* [n_bnd] */
+    int32_t n_presc;
+    const int32_t *presc_clump;        /* [n_presc] prescribed-motion clumps */
+    const double *presc_param;         /* [n_presc][12] */
+} cdem_scene_desc;
+
+/* Optional device allocator (e.g. a framework's caching allocator).  NULL
+ * means hipMalloc/hipFree.  alloc returns NULL on failure. */
+typedef struct cdem_allocator {
+    void *ctx;
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*free)(void *ctx, void *ptr, void *stream);
+} cdem_allocator;
+
+typedef struct cdem_detect_params {
+    int32_t mode;          /* CDEM_DETECT_* */
+    int32_t k_max;         /* upper bound of the detection interval, 1..20 */
+    double safety;         /* multiplier (>= 1) on velocity envelopes; default 1.5 */
+    double v_max_user;     /* a-priori bound on sphere speed [m/s], 0 = use measured speeds */
+    double margin_cap;     /* largest margin any sphere may get [m]; sets the bin size */
+    int32_t audit_period;  /* steps between brute-force audits, 0 = never */
+    int32_t reserved;
+} cdem_detect_params;
+
+typedef struct cdem_counts {
+    int64_t clumps, spheres, bins;
+    int64_t candidates;   /* entries in the active set (both directions of a pair count once each) */
+    int64_t steps;        /* completed steps */
+    int64_t detections;   /* active-set rebuilds */
+    int64_t guard_trips;  /* rebuilds forced by a sphere outrunning its margin */
+    int64_t fallbacks;    /* learned envelopes rejected for the fixed rule */
+    int64_t audits;
+    int64_t missed;       /* contacts found by audits but absent from the active set */
+    int64_t capacity;     /* active-set entries that fit in the current storage */
+    int64_t regrows;
+    int32_t k_current;    /* current detection interval */
+    int32_t reserved;
+} cdem_counts;
+
+/* Clump state view: each pointer may be NULL (skipped).  where = CDEM_HOST or
+ * CDEM_DEVICE.  Row-major [n_clumps][3] / [n_clumps][4]. */
+typedef struct cdem_state_view {
+    double *x, *q, *v, *w;
+} cdem_state_view;
+
+/* Contacts of the last recorded step (see cdem_record_next_step), canonical:
+ * sphere pairs a < b < n_spheres, boundary contacts b = n_spheres + index.
+ * Only pairs whose exact predicate held that step (true contacts) are listed,
+ * ascending by (a, b).  Host buffers of capacity 'cap'; *n receives the count
+ * (call with cap = 0 to size).  F is the force on b; u the updated history. */
+typedef struct cdem_contacts_view {
+    int64_t cap;
+    int64_t n;
+    uint32_t *a, *b;
+    double *delta;   /* [cap] */
+    double *F;       /* [cap][3] */
+    double *u;       /* [cap][3] */
+} cdem_contacts_view;
+
+typedef struct cdem_audit_result {
+    int64_t true_contacts;  /* exact contacts found by the independent brute-force sweep */
+    int64_t missed;         /* of those, absent from the active set */
+    uint32_t first_a, first_b;
+} cdem_audit_result;
+
+/* ---- lifecycle ---- */
+int cdem_abi_version(void);
+const char *cdem_strerror(int code);
+const char *cdem_last_error(const cdem_scene *s);   /* never NULL */
+
+/* Validate and copy the description to the device.  stream may be NULL.
+ * On error *out is NULL and nothing is leaked. */
+int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc, void *stream, cdem_scene **out);
+int cdem_destroy(cdem_scene *s);
+
+/* ---- stepping ---- */
+/* Advance n >= 0 steps, enqueued on stream (NULL = the scene's stream).
+ * Returns after enqueueing; synchronises only when the active set must grow. */
+int cdem_step(cdem_scene *s, int64_t n, void *stream);
+int cdem_sync(cdem_scene *s);
+int cdem_set_detection(cdem_scene *s, const cdem_detect_params *p);
+/* When on != 0, the next step stores per-contact penetration and force for
+ * cdem_read_contacts. */
+int cdem_record_next_step(cdem_scene *s, int on);
+
+/* ---- reads and writes (synchronous) ---- */
+int cdem_get_counts(cdem_scene *s, cdem_counts *c);
+int cdem_read_state(cdem_scene *s, const cdem_state_view *v, int where);
+/* Overwrite the clump state; the active set is rebuilt before the next step
+ * (tangential history of pairs that survive is kept). */
+int cdem_write_state(cdem_scene *s, const cdem_state_view *v, int where);
+int cdem_read_contacts(cdem_scene *s, cdem_contacts_view *v);
+/* Per-clump force (contacts + gravity) and torque of the last recorded step,
+ * host buffers [n_clumps][3]. */
+int cdem_read_clump_forces(cdem_scene *s, double *F, double *T);
+/* Sphere centres of the current state, host buffer [n_spheres][3]. */
+int cdem_read_sphere_pos(cdem_scene *s, double *xs);
+
+/* Independent exact contact sweep (no binning, no margin) over the current
+ * state, compared with the active set.  O(N^2): for small scenes and tests. */
+int cdem_audit(cdem_scene *s, cdem_audit_result *r);
+
+/* ---- measurement (not part of the method) ---- */
+/* Per-kernel device time, measured with HIP events recorded on the launch
+ * stream around every kernel while profiling is on. */
+typedef struct cdem_kernel_time {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} cdem_kernel_time;
+
+/* on != 0 starts (and clears) per-kernel timing; on == 0 stops it. */
+int cdem_profile(cdem_scene *s, int on);
+/* Copies up to cap records into out (host), *n receives the number of kernels. */
+int cdem_profile_read(cdem_scene *s, cdem_kernel_time *out, int cap, int *n);
+/* True contacts (exact predicate, positive overlap) of the last completed
+ * step, counted once per pair side (twice per sphere pair, once per boundary
+ * contact). */
+int cdem_last_step_contacts(cdem_scene *s, int64_t *n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,822 @@
+// Host runtime and C ABI of libcdem (see include/cdem.h).
+//
+// A scene owns device copies of the clump templates, clump state, per-sphere
+// materials and analytic boundaries, plus the working buffers of the step:
+// per-scene uniform bins, the double-buffered active set with its tangential
+// history, and a device-resident control block that schedules detections.
+// cdem_step enqueues pose -> (detection when due) -> force/reduce/integrate ->
+// step bookkeeping per step and synchronises once at the end to check for
+// active-set overflow, which it repairs by growing the storage and resuming
+// from the first step that did not complete.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cdem.h"
+#include "cdem_internal.h"
+
+using namespace cdem;
+
+namespace cdem {
+hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack,
+                             hipStream_t st);
+}
+
+// Event pool for per-kernel timing (read after the stream is synchronised).
+struct EventTimer : KernelTimer {
+    std::vector<hipEvent_t> pool;
+    std::vector<int> ids;       // kernel id of each before/after pair
+    size_t used = 0;            // events in use (two per kernel launch)
+    double total_ms[K_COUNT] = {};
+    int64_t launches[K_COUNT] = {};
+    hipEvent_t next() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+    void before(int id, hipStream_t st) override {
+        hipEvent_t e = next();
+        if (e) { (void)hipEventRecord(e, st); ids.push_back(id); } else ids.push_back(-1);
+    }
+    void after(int, hipStream_t st) override {
+        hipEvent_t e = next();
+        if (e) (void)hipEventRecord(e, st);
+    }
+    // accumulate every recorded pair (the stream must be idle)
+    void harvest() {
+        for (size_t k = 0; k < ids.size() && 2 * k + 1 < used; k++) {
+            float ms = 0.f;
+            if (ids[k] >= 0 && hipEventElapsedTime(&ms, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
+                total_ms[ids[k]] += ms;
+                launches[ids[k]]++;
+            }
+        }
+        ids.clear();
+        used = 0;
+    }
+    ~EventTimer() override { for (auto e : pool) (void)hipEventDestroy(e); }
+};
+
+struct cdem_scene {
+    EventTimer *timer = nullptr;
+    bool test_no_guard = false;   // testing aid: deferred detection without the displacement guard
+    std::string err;
+    cdem_allocator alloc{};
+    bool custom_alloc = false;
+    hipStream_t stream = nullptr;
+    DevScene S{};
+    cdem_detect_params det{};
+    // host copies needed for regridding and reads
+    std::vector<Grid> grids;
+    std::vector<double> dom;           // [n_scenes][6]
+    std::vector<int32_t> bnd_user;     // device boundary order -> user index
+    std::vector<Bnd> bnd;
+    double rmax = 0.0;
+    int64_t n_cells_alloc = 0;
+    int64_t rec_cap = 0;
+    std::vector<void *> owned;         // every device allocation, freed on destroy
+    int64_t regrows = 0;
+};
+
+static const char *kErrNames[] = {"ok", "invalid argument", "out of device memory", "HIP runtime error",
+                                  "active-set capacity exceeded", "missed contact", "non-finite state",
+                                  "invalid state"};
+
+extern "C" int cdem_abi_version(void) { return CDEM_ABI_VERSION; }
+
+extern "C" const char *cdem_strerror(int code) {
+    int i = -code;
+    if (i < 0 || i > 7) return "unknown error";
+    return kErrNames[i];
+}
+
+// Message of the last failed cdem_create (which returns no scene to ask).
+static std::string g_create_err = "no error";
+
+extern "C" const char *cdem_last_error(const cdem_scene *s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+static int fail(cdem_scene *s, int code, const std::string &msg) {
+    if (s) s->err = msg;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess)                                                              \
+            return fail(sc, CDEM_E_HIP, std::string(#expr ": ") + hipGetErrorString(_e)); \
+    } while (0)
+
+static void *dev_alloc(cdem_scene *sc, size_t bytes) {
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (sc->custom_alloc) {
+        p = sc->alloc.alloc(sc->alloc.ctx, bytes, (void *)sc->stream);
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+    }
+    if (p) sc->owned.push_back(p);
+    return p;
+}
+
+static void dev_free(cdem_scene *sc, void *p) {
+    if (!p) return;
+    auto it = std::find(sc->owned.begin(), sc->owned.end(), p);
+    if (it != sc->owned.end()) sc->owned.erase(it);
+    if (sc->custom_alloc) sc->alloc.free(sc->alloc.ctx, p, (void *)sc->stream);
+    else (void)hipFree(p);
+}
+
+template <typename T>
+static T *upload(cdem_scene *sc, const T *src, size_t n, int &rc) {
+    T *d = (T *)dev_alloc(sc, n * sizeof(T));
+    if (!d) { rc = fail(sc, CDEM_E_OOM, "device allocation failed"); return nullptr; }
+    if (n && src) {
+        hipError_t e = hipMemcpyAsync(d, src, n * sizeof(T), hipMemcpyHostToDevice, sc->stream);
+        if (e != hipSuccess) { rc = fail(sc, CDEM_E_HIP, hipGetErrorString(e)); return nullptr; }
+    }
+    return d;
+}
+
+static double beta_of_cor(double e) {
+    double l = std::log(e);
+    return l / std::sqrt(l * l + M_PI * M_PI);
+}
+
+static bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; i++) if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+// (Re)build the per-scene grids for bin size b = 2 (R_max + margin cap) and
+// allocate the bin arrays when they grow.
+static int build_grids(cdem_scene *sc) {
+    DevScene &S = sc->S;
+    double b = 2.0 * (sc->rmax + std::max(0.0, sc->det.margin_cap));
+    if (!(b > 0.0)) b = 1.0;  // no spheres: any positive bin size will do
+    int64_t cell0 = 0;
+    for (int k = 0; k < S.n_scenes; k++) {
+        Grid &g = sc->grids[k];
+        const double *d = &sc->dom[6 * k];
+        double bb = b;
+        int64_t nx, ny, nz;
+        for (;;) {
+            nx = std::max<int64_t>(1, (int64_t)std::ceil((d[3] - d[0]) / bb));
+            ny = std::max<int64_t>(1, (int64_t)std::ceil((d[4] - d[1]) / bb));
+            nz = std::max<int64_t>(1, (int64_t)std::ceil((d[5] - d[2]) / bb));
+            if (nx * ny * nz <= (int64_t)1 << 27) break;
+            bb *= 1.25;  // keep the bin count bounded for huge, sparse domains
+        }
+        g.ox = d[0]; g.oy = d[1]; g.oz = d[2];
+        g.inv = 1.0 / bb;
+        g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
+        g.cell0 = cell0;
+        cell0 += nx * ny * nz;
+    }
+    if (cell0 >= ((int64_t)1 << 32)) return fail(sc, CDEM_E_INVALID, "too many bins");
+    S.n_cells = cell0;
+    int rc = CDEM_OK;
+    Grid *dg = (Grid *)S.grids;
+    if (!dg) {
+        dg = upload(sc, sc->grids.data(), sc->grids.size(), rc);
+        if (!dg) return rc;
+        S.grids = dg;
+    } else {
+        hipError_t e = hipMemcpyAsync(dg, sc->grids.data(), sc->grids.size() * sizeof(Grid), hipMemcpyHostToDevice, sc->stream);
+        if (e != hipSuccess) return fail(sc, CDEM_E_HIP, hipGetErrorString(e));
+    }
+    if (cell0 > sc->n_cells_alloc) {
+        dev_free(sc, S.cell_count);
+        dev_free(sc, S.cell_start);
+        dev_free(sc, S.cell_fill);
+        int64_t nblk = (cell0 + 1023) / 1024 + 1;
+        S.cell_count = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.cell_start = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.cell_fill = (uint32_t *)dev_alloc(sc, (cell0 + nblk) * 4);  // + scan block sums
+        if (!S.cell_count || !S.cell_start || !S.cell_fill) return fail(sc, CDEM_E_OOM, "bin arrays");
+        sc->n_cells_alloc = cell0;
+    }
+    return CDEM_OK;
+}
+
+static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
+    DevScene &S = sc->S;
+    uint32_t *nb[2];
+    double *hs[2];
+    for (int k = 0; k < 2; k++) {
+        nb[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        hs[k] = (double *)dev_alloc(sc, cap * 24);
+        if (!nb[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
+    }
+    if (keep) {
+        // preserve the current buffer (rows point into it)
+        Ctl c;
+        if (hipMemcpy(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return fail(sc, CDEM_E_HIP, "ctl read");
+        int cur = c.buf;
+        size_t n = (size_t)std::min<int64_t>(c.n_entries_cur, S.cap);
+        if (n) {
+            if (hipMemcpyAsync(nb[cur], S.nbr[cur], n * 4, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess ||
+                hipMemcpyAsync(hs[cur], S.hist[cur], n * 24, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess)
+                return fail(sc, CDEM_E_HIP, "active-set copy");
+        }
+        if (hipStreamSynchronize(sc->stream) != hipSuccess) return fail(sc, CDEM_E_HIP, "sync");
+        for (int k = 0; k < 2; k++) { dev_free(sc, S.nbr[k]); dev_free(sc, S.hist[k]); }
+    }
+    for (int k = 0; k < 2; k++) { S.nbr[k] = nb[k]; S.hist[k] = hs[k]; }
+    S.cap = cap;
+    if (sc->rec_cap) {  // recording arrays follow the capacity
+        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F);
+        S.rec_state = nullptr; S.rec_delta = nullptr; S.rec_F = nullptr;
+        sc->rec_cap = 0;
+    }
+    return CDEM_OK;
+}
+
+static void set_bnd_margins(cdem_scene *sc) {
+    int kmax = sc->det.mode == CDEM_DETECT_PLAIN ? 0 : std::max(1, sc->det.k_max);
+    for (auto &b : sc->bnd) {
+        double sp = std::sqrt(b.vel[0] * b.vel[0] + b.vel[1] * b.vel[1] + b.vel[2] * b.vel[2]);
+        b.margin = sp * (double)kmax * sc->S.h * 1.01;
+    }
+}
+
+extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc, void *stream, cdem_scene **out) {
+    if (!out) return CDEM_E_INVALID;
+    *out = nullptr;
+    if (!d) return CDEM_E_INVALID;
+    cdem_scene *sc = new (std::nothrow) cdem_scene();
+    if (!sc) return CDEM_E_OOM;
+    auto bail = [&](int rc) { g_create_err = sc->err; cdem_destroy(sc); return rc; };
+    auto invalid = [&](const char *m) { g_create_err = m; cdem_destroy(sc); return CDEM_E_INVALID; };
+    // ---- validation
+    if (!(d->h > 0) || !std::isfinite(d->h)) return invalid("time step must be positive");
+    if (d->precision != CDEM_PREC_FP64 && d->precision != CDEM_PREC_FP32_FORCE) return invalid("unknown precision");
+    if (d->n_templates < 1 || !d->tmpl_sphere_begin || d->tmpl_sphere_begin[0] != 0) return invalid("templates");
+    if (d->n_clumps < 0 || d->n_clumps >= ((int64_t)1 << 31)) return invalid("clump count");
+    if (d->n_scenes < 1 || !d->gravity || !d->domain) return invalid("scenes");
+    if (d->n_bnd < 0 || d->n_bnd > kMaxBnd) return invalid("at most 64 boundaries");
+    int nt = d->n_templates;
+    for (int t = 0; t < nt; t++)
+        if (d->tmpl_sphere_begin[t + 1] <= d->tmpl_sphere_begin[t]) return invalid("empty template");
+    uint32_t nts = d->tmpl_sphere_begin[nt];
+    for (uint32_t i = 0; i < nts; i++)
+        if (!(d->tmpl_radius[i] > 0) || !std::isfinite(d->tmpl_radius[i])) return invalid("template radius");
+    if (!finite_all(d->tmpl_offset, 3 * (size_t)nts)) return invalid("template offsets");
+    for (int t = 0; t < nt; t++) {
+        if (!(d->tmpl_mass[t] > 0)) return invalid("template mass");
+        for (int k = 0; k < 3; k++) if (!(d->tmpl_inertia[3 * t + k] > 0)) return invalid("template inertia");
+    }
+    int64_t nc = d->n_clumps;
+    std::vector<int64_t> sbeg(nc + 1, 0);
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        if ((int)t >= nt || d->clump_scene[c] >= (uint32_t)d->n_scenes) return invalid("clump template/scene");
+        sbeg[c + 1] = sbeg[c] + (d->tmpl_sphere_begin[t + 1] - d->tmpl_sphere_begin[t]);
+        double qn = 0;
+        for (int k = 0; k < 4; k++) qn += d->q[4 * c + k] * d->q[4 * c + k];
+        if (!(std::fabs(qn - 1.0) < 1e-10)) return invalid("quaternions must be unit");
+    }
+    int64_t ns = sbeg[nc];
+    if (ns >= ((int64_t)1 << 31) - kMaxBnd) return invalid("too many spheres");
+    if (!finite_all(d->x, 3 * nc) || !finite_all(d->v, 3 * nc) || !finite_all(d->w, 3 * nc)) return invalid("state");
+    for (int64_t s = 0; s < ns; s++) {
+        const double *m = d->sphere_mat + 4 * s;
+        if (!(m[0] > 0) || !(m[1] > -1 && m[1] < 0.5) || !(m[2] >= 0) || !(m[3] > 0 && m[3] <= 1))
+            return invalid("sphere material out of range");
+    }
+    for (int k = 0; k < d->n_bnd; k++) {
+        const double *m = d->bnd_mat + 4 * k;
+        if (d->bnd_type[k] < 0 || d->bnd_type[k] > 3) return invalid("boundary type");
+        if (d->bnd_scene[k] < 0 || d->bnd_scene[k] >= d->n_scenes) return invalid("boundary scene");
+        if (!(m[0] > 0) || !(m[1] > -1 && m[1] < 0.5) || !(m[2] >= 0) || !(m[3] > 0 && m[3] <= 1))
+            return invalid("boundary material out of range");
+    }
+    for (int k = 0; k < d->n_scenes; k++) {
+        const double *dm = d->domain + 6 * k;
+        for (int j = 0; j < 3; j++) if (!(dm[j + 3] > dm[j])) return invalid("empty domain");
+    }
+    std::vector<int32_t> presc(nc, -1);
+    for (int k = 0; k < d->n_presc; k++) {
+        int32_t c = d->presc_clump[k];
+        if (c < 0 || c >= nc) return invalid("prescribed clump out of range");
+        presc[c] = k;
+    }
+    // ---- host-side derived arrays
+    sc->custom_alloc = alloc && alloc->alloc && alloc->free;
+    if (sc->custom_alloc) sc->alloc = *alloc;
+    sc->stream = (hipStream_t)stream;
+    DevScene &S = sc->S;
+    S.nc = nc; S.ns = ns; S.n_scenes = d->n_scenes; S.n_bnd = d->n_bnd;
+    S.precision = d->precision; S.detect_mode = CDEM_DETECT_PLAIN; S.h = d->h;
+    sc->det.mode = CDEM_DETECT_PLAIN; sc->det.k_max = 1; sc->det.safety = 1.5; sc->det.margin_cap = 0.0;
+    sc->det.audit_period = 0;
+    std::vector<uint32_t> owner(ns), sscene(ns);
+    std::vector<double4> mat64(ns);
+    std::vector<float4> mat32(ns);
+    double rmax = 0;
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        for (int64_t s = sbeg[c]; s < sbeg[c + 1]; s++) {
+            owner[s] = (uint32_t)c;
+            sscene[s] = d->clump_scene[c];
+            rmax = std::max(rmax, d->tmpl_radius[d->tmpl_sphere_begin[t] + (s - sbeg[c])]);
+        }
+    }
+    for (int64_t s = 0; s < ns; s++) {
+        const double *m = d->sphere_mat + 4 * s;
+        double E = m[0], nu = m[1];
+        double e = (1.0 - nu * nu) / E, g = 2.0 * (2.0 - nu) * (1.0 + nu) / E, b = beta_of_cor(m[3]);
+        mat64[s] = make_double4(e, g, m[2], b);
+        mat32[s] = make_float4((float)e, (float)g, (float)m[2], (float)b);
+    }
+    sc->rmax = rmax;
+    // boundaries sorted by scene
+    std::vector<int32_t> order(d->n_bnd);
+    for (int k = 0; k < d->n_bnd; k++) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return d->bnd_scene[a] < d->bnd_scene[b]; });
+    sc->bnd_user = order;
+    sc->bnd.resize(d->n_bnd);
+    for (int i = 0; i < d->n_bnd; i++) {
+        int k = order[i];
+        Bnd &B = sc->bnd[i];
+        memset(&B, 0, sizeof B);
+        B.type = d->bnd_type[k]; B.scene = d->bnd_scene[k];
+        for (int j = 0; j < 12; j++) B.p[j] = d->bnd_param[12 * k + j];
+        for (int j = 0; j < 3; j++) { B.vel[j] = d->bnd_vel[3 * k + j]; B.omg[j] = d->bnd_omega[3 * k + j]; }
+        const double *m = d->bnd_mat + 4 * k;
+        B.e = (1.0 - m[1] * m[1]) / m[0];
+        B.g = 2.0 * (2.0 - m[1]) * (1.0 + m[1]) / m[0];
+        B.mu = m[2]; B.beta = beta_of_cor(m[3]);
+        B.ef = (float)B.e; B.gf = (float)B.g; B.muf = (float)B.mu; B.betaf = (float)B.beta;
+    }
+    set_bnd_margins(sc);
+    sc->grids.resize(d->n_scenes);
+    sc->dom.assign(d->domain, d->domain + 6 * d->n_scenes);
+    for (int k = 0; k < d->n_scenes; k++) {
+        Grid &g = sc->grids[k];
+        memset(&g, 0, sizeof g);
+        g.gx = d->gravity[3 * k]; g.gy = d->gravity[3 * k + 1]; g.gz = d->gravity[3 * k + 2];
+        g.bnd_beg = g.bnd_end = 0;
+    }
+    {
+        int i = 0;
+        for (int k = 0; k < d->n_scenes; k++) {
+            sc->grids[k].bnd_beg = i;
+            while (i < d->n_bnd && sc->bnd[i].scene == k) i++;
+            sc->grids[k].bnd_end = i;
+        }
+    }
+    std::vector<int32_t> big;
+    for (int64_t c = 0; c < nc; c++) if (sbeg[c + 1] - sbeg[c] > kBigClump) big.push_back((int32_t)c);
+    std::vector<float> crad(nc);
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        double rb = 0;
+        for (uint32_t i = d->tmpl_sphere_begin[t]; i < d->tmpl_sphere_begin[t + 1]; i++) {
+            const double *o = d->tmpl_offset + 3 * i;
+            rb = std::max(rb, std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) + d->tmpl_radius[i]);
+        }
+        crad[c] = (float)rb;
+    }
+    S.plan.k_max = 1; S.plan.audit_period = 0; S.plan.safety = 1.5f;
+    S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
+    // ---- device arrays
+    int rc = CDEM_OK;
+    std::vector<double> tmp(nc);
+    double **soa[13] = {&S.px, &S.py, &S.pz, &S.qw, &S.qx, &S.qy, &S.qz, &S.vx, &S.vy, &S.vz, &S.wx, &S.wy, &S.wz};
+    const double *srcs[13] = {d->x, d->x, d->x, d->q, d->q, d->q, d->q, d->v, d->v, d->v, d->w, d->w, d->w};
+    int comp[13] = {0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 0, 1, 2}, stride[13] = {3, 3, 3, 4, 4, 4, 4, 3, 3, 3, 3, 3, 3};
+    for (int a = 0; a < 13; a++) {
+        for (int64_t c = 0; c < nc; c++) tmp[c] = srcs[a][stride[a] * c + comp[a]];
+        *soa[a] = upload(sc, tmp.data(), nc, rc);
+        if (!*soa[a]) return bail(rc);
+        if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
+    }
+    std::vector<double> mass(nc), ix(nc), iy(nc), iz(nc);
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t t = d->clump_template[c];
+        mass[c] = d->tmpl_mass[t];
+        ix[c] = d->tmpl_inertia[3 * t]; iy[c] = d->tmpl_inertia[3 * t + 1]; iz[c] = d->tmpl_inertia[3 * t + 2];
+    }
+#define UP(field, src, n)                                   \
+    do {                                                    \
+        auto *p_ = upload(sc, (src), (n), rc);              \
+        if (!p_) return bail(rc);                           \
+        S.field = p_;                                       \
+    } while (0)
+    UP(mass, mass.data(), nc); UP(ix, ix.data(), nc); UP(iy, iy.data(), nc); UP(iz, iz.data(), nc);
+    UP(sbeg, sbeg.data(), nc + 1);
+    UP(presc, presc.data(), nc);
+    UP(presc_param, d->presc_param, 12 * (size_t)d->n_presc);
+    UP(clump_tmpl, d->clump_template, nc);
+    UP(clump_scene, d->clump_scene, nc);
+    UP(tmpl_sbeg, d->tmpl_sphere_begin, nt + 1);
+    UP(tmpl_ofs, d->tmpl_offset, 3 * (size_t)nts);
+    UP(tmpl_rad, d->tmpl_radius, nts);
+    UP(owner, owner.data(), ns);
+    UP(sscene, sscene.data(), ns);
+    UP(mat64, mat64.data(), ns);
+    UP(mat32, mat32.data(), ns);
+    UP(bnd, sc->bnd.data(), sc->bnd.size());
+    UP(big_list, big.data(), big.size());
+    UP(crad, crad.data(), crad.size());
+#undef UP
+    S.n_big = (int32_t)big.size();
+    S.kin = (double4 *)dev_alloc(sc, 3 * sizeof(double4) * std::max<int64_t>(nc, 1));
+    S.spos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
+    S.sdet = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
+    S.smargin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.cell_of = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.sorted_id = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
+    S.sorted_margin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.rec_cF = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
+    S.rec_cT = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
+    S.ctl = (Ctl *)dev_alloc(sc, sizeof(Ctl));
+    for (int k = 0; k < 2; k++) {
+        S.row_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.row_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    }
+    if (!S.kin || !S.spos || !S.sdet || !S.smargin || !S.cell_of || !S.sorted_id || !S.sorted_owner ||
+        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.row_beg[0] || !S.row_beg[1] ||
+        !S.row_cnt[0] || !S.row_cnt[1])
+        return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    if (!big.empty()) {
+        S.sF = (double *)dev_alloc(sc, 24 * ns);
+        S.sT = (double *)dev_alloc(sc, 24 * ns);
+        if (!S.sF || !S.sT) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    }
+    if ((rc = build_grids(sc)) != CDEM_OK) return bail(rc);
+    // testing aid: deferred detection with zero margin and no guard, which
+    // misses contacts on purpose so the audit's failure path can be tested
+    sc->test_no_guard = getenv("CDEM_TEST_NO_GUARD") != nullptr;
+    int64_t cap0 = std::max<int64_t>(16 * ns, 1024);
+    if (const char *ev = getenv("CDEM_INITIAL_CAPACITY")) cap0 = std::max<int64_t>(atoll(ev), 64);  // testing aid
+    if ((rc = alloc_active_set(sc, cap0, false)) != CDEM_OK) return bail(rc);
+    Ctl c;
+    memset(&c, 0, sizeof c);
+    c.det_due = 1;
+    c.k_cur = 1;
+    if (hipMemcpyAsync(S.ctl, &c, sizeof c, hipMemcpyHostToDevice, sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "ctl"));
+    for (int k = 0; k < 2; k++) {
+        if (launch_zero(S.row_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
+            launch_zero(S.row_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
+            return bail(fail(sc, CDEM_E_HIP, "zero"));
+    }
+    if (launch_zero(S.sdet, sizeof(double4) * ns, sc->stream) != hipSuccess ||
+        launch_zero(S.smargin, 4 * (size_t)ns, sc->stream) != hipSuccess)
+        return bail(fail(sc, CDEM_E_HIP, "zero"));
+    if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
+    *out = sc;
+    return CDEM_OK;
+}
+
+extern "C" int cdem_destroy(cdem_scene *sc) {
+    if (!sc) return CDEM_E_INVALID;
+    (void)hipStreamSynchronize(sc->stream);
+    delete sc->timer;
+    sc->timer = nullptr;
+    auto owned = sc->owned;
+    for (void *p : owned) dev_free(sc, p);
+    delete sc;
+    return CDEM_OK;
+}
+
+static int read_ctl(cdem_scene *sc, Ctl &c) {
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    HIPCHK(hipMemcpy(&c, sc->S.ctl, sizeof c, hipMemcpyDeviceToHost));
+    return CDEM_OK;
+}
+
+static int write_ctl(cdem_scene *sc, const Ctl &c) {
+    HIPCHK(hipMemcpyAsync(sc->S.ctl, &c, sizeof c, hipMemcpyHostToDevice, sc->stream));
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    return CDEM_OK;
+}
+
+static int enqueue_steps(cdem_scene *sc, int64_t n) {
+    const DevScene &S = sc->S;
+    int guard = S.detect_mode != CDEM_DETECT_PLAIN && !sc->test_no_guard;
+    g_timer = sc->timer;
+    for (int64_t i = 0; i < n; i++) {
+        hipError_t e = launch_pose(S, guard, sc->stream);
+        if (e == hipSuccess) e = launch_detect(S, sc->stream);
+        if (e == hipSuccess) e = launch_audit_binned(S, sc->stream);
+        if (e == hipSuccess) e = launch_force_integrate(S, sc->stream);
+        if (e == hipSuccess) e = launch_step_end(S, sc->stream);
+        if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
+        if (sc->timer && sc->timer->used > 4096) {  // bound the event pool
+            HIPCHK(hipStreamSynchronize(sc->stream));
+            sc->timer->harvest();
+        }
+    }
+    g_timer = nullptr;
+    return CDEM_OK;
+}
+
+extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
+    if (!sc || n < 0) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    if (stream) sc->stream = (hipStream_t)stream;
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    int64_t target = c.step + n;
+    int64_t missed0 = c.missed;
+    for (int attempt = 0; attempt < 8; attempt++) {
+        int64_t left = target - c.step;
+        if (left <= 0) break;
+        if ((rc = enqueue_steps(sc, left)) != CDEM_OK) return rc;
+        if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
+        if (sc->timer) sc->timer->harvest();
+        if (c.nonfinite) return fail(sc, CDEM_E_NAN, "non-finite clump state");
+        if (!c.overflow) break;
+        if (c.row_overflow)
+            return fail(sc, CDEM_E_CAPACITY, "a sphere has more than 64 candidate partners (margin or bin too large)");
+        // grow the active set and resume from the step that did not complete
+        int64_t need = (int64_t)(1.3 * (double)c.n_entries) + 1024;
+        int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
+        if ((rc = alloc_active_set(sc, cap, true)) != CDEM_OK) return rc;
+        sc->regrows++;
+        c.overflow = 0;
+        c.row_overflow = 0;
+        c.det_due = 1;
+        c.record = 0;
+        if ((rc = write_ctl(sc, c)) != CDEM_OK) return rc;
+    }
+    if (c.step != target) return fail(sc, CDEM_E_CAPACITY, "active set could not be grown");
+    if (c.missed > missed0)
+        return fail(sc, CDEM_E_MISSED_CONTACT, "an audit found contacts missing from the active set");
+    return CDEM_OK;
+}
+
+extern "C" int cdem_sync(cdem_scene *sc) {
+    if (!sc) return CDEM_E_INVALID;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    return CDEM_OK;
+}
+
+extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
+    if (!sc || !p) return fail(sc, CDEM_E_INVALID, "null argument");
+    if (p->mode < 0 || p->mode > 2 || p->k_max < 1 || p->k_max > 20 || !(p->safety >= 1.0) ||
+        !(p->margin_cap >= 0.0) || p->audit_period < 0 || !(p->v_max_user >= 0.0))
+        return fail(sc, CDEM_E_INVALID, "detection parameters out of range");
+    if (p->mode != CDEM_DETECT_PLAIN && !(p->margin_cap > 0.0))
+        return fail(sc, CDEM_E_INVALID, "deferred detection needs a positive margin cap");
+    if (p->mode == CDEM_DETECT_LEARNED) return fail(sc, CDEM_E_INVALID, "learned detection not available");
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    sc->det = *p;
+    sc->S.detect_mode = p->mode;
+    sc->S.plan.k_max = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
+    sc->S.plan.audit_period = p->audit_period;
+    sc->S.plan.safety = (float)p->safety;
+    sc->S.plan.margin_cap = (float)p->margin_cap;
+    sc->S.plan.margin_floor = (float)std::min(1e-7, 0.5 * p->margin_cap);
+    sc->S.plan.v_user = (float)p->v_max_user;
+    sc->S.plan.test_zero_margin = sc->test_no_guard ? 1 : 0;
+    set_bnd_margins(sc);
+    HIPCHK(hipMemcpyAsync((void *)sc->S.bnd, sc->bnd.data(), sc->bnd.size() * sizeof(Bnd), hipMemcpyHostToDevice, sc->stream));
+    if ((rc = build_grids(sc)) != CDEM_OK) return rc;
+    c.det_due = 1;
+    c.k_cur = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
+    return write_ctl(sc, c);
+}
+
+extern "C" int cdem_record_next_step(cdem_scene *sc, int on) {
+    if (!sc) return CDEM_E_INVALID;
+    DevScene &S = sc->S;
+    if (on && sc->rec_cap < S.cap) {
+        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F);
+        S.rec_state = (uint8_t *)dev_alloc(sc, S.cap);
+        S.rec_delta = (double *)dev_alloc(sc, 8 * S.cap);
+        S.rec_F = (double *)dev_alloc(sc, 24 * S.cap);
+        if (!S.rec_state || !S.rec_delta || !S.rec_F) return fail(sc, CDEM_E_OOM, "recording buffers");
+        sc->rec_cap = S.cap;
+    }
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    c.record = on ? 1 : 0;
+    return write_ctl(sc, c);
+}
+
+extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
+    if (!sc || !out) return fail(sc, CDEM_E_INVALID, "null argument");
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    memset(out, 0, sizeof *out);
+    out->clumps = sc->S.nc; out->spheres = sc->S.ns; out->bins = sc->S.n_cells;
+    out->candidates = c.n_entries_cur; out->steps = c.step; out->detections = c.detections;
+    out->guard_trips = c.guard_trips; out->fallbacks = c.fallbacks; out->audits = c.audits;
+    out->missed = c.missed; out->capacity = sc->S.cap; out->regrows = sc->regrows; out->k_current = c.k_cur;
+    return CDEM_OK;
+}
+
+extern "C" int cdem_read_state(cdem_scene *sc, const cdem_state_view *v, int where) {
+    if (!sc || !v || (where != CDEM_HOST && where != CDEM_DEVICE)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    const DevScene &S = sc->S;
+    int64_t nc = S.nc;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    if (where == CDEM_DEVICE) {
+        HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 0, sc->stream));
+        HIPCHK(hipStreamSynchronize(sc->stream));
+        return CDEM_OK;
+    }
+    std::vector<double> t(nc);
+    double *dst[4] = {v->x, v->q, v->v, v->w};
+    double *const *srcs[4][4] = {{&S.px, &S.py, &S.pz, nullptr}, {&S.qw, &S.qx, &S.qy, &S.qz},
+                                {&S.vx, &S.vy, &S.vz, nullptr}, {&S.wx, &S.wy, &S.wz, nullptr}};
+    int width[4] = {3, 4, 3, 3};
+    for (int a = 0; a < 4; a++) {
+        if (!dst[a]) continue;
+        for (int k = 0; k < width[a]; k++) {
+            HIPCHK(hipMemcpy(t.data(), *srcs[a][k], nc * 8, hipMemcpyDeviceToHost));
+            for (int64_t c = 0; c < nc; c++) dst[a][width[a] * c + k] = t[c];
+        }
+    }
+    return CDEM_OK;
+}
+
+extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int where) {
+    if (!sc || !v || (where != CDEM_HOST && where != CDEM_DEVICE)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    const DevScene &S = sc->S;
+    int64_t nc = S.nc;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    if (where == CDEM_DEVICE) {
+        HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 1, sc->stream));
+    } else {
+        if (v->q)
+            for (int64_t c = 0; c < nc; c++) {
+                double qn = 0;
+                for (int k = 0; k < 4; k++) qn += v->q[4 * c + k] * v->q[4 * c + k];
+                if (!(std::fabs(qn - 1.0) < 1e-10)) return fail(sc, CDEM_E_INVALID, "quaternions must be unit");
+            }
+        std::vector<double> t(nc);
+        const double *src[4] = {v->x, v->q, v->v, v->w};
+        double *const *dsts[4][4] = {{&S.px, &S.py, &S.pz, nullptr}, {&S.qw, &S.qx, &S.qy, &S.qz},
+                                    {&S.vx, &S.vy, &S.vz, nullptr}, {&S.wx, &S.wy, &S.wz, nullptr}};
+        int width[4] = {3, 4, 3, 3};
+        for (int a = 0; a < 4; a++) {
+            if (!src[a]) continue;
+            if (!finite_all(src[a], width[a] * (size_t)nc)) return fail(sc, CDEM_E_INVALID, "non-finite state");
+            for (int k = 0; k < width[a]; k++) {
+                for (int64_t c = 0; c < nc; c++) t[c] = src[a][width[a] * c + k];
+                HIPCHK(hipMemcpy(*dsts[a][k], t.data(), nc * 8, hipMemcpyHostToDevice));
+            }
+        }
+    }
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    c.det_due = 1;
+    return write_ctl(sc, c);
+}
+
+extern "C" int cdem_read_sphere_pos(cdem_scene *sc, double *xs) {
+    if (!sc || !xs) return fail(sc, CDEM_E_INVALID, "null argument");
+    const DevScene &S = sc->S;
+    HIPCHK(launch_pose(S, 0, sc->stream));
+    std::vector<double4> p(S.ns);
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    HIPCHK(hipMemcpy(p.data(), S.spos, S.ns * sizeof(double4), hipMemcpyDeviceToHost));
+    for (int64_t s = 0; s < S.ns; s++) { xs[3 * s] = p[s].x; xs[3 * s + 1] = p[s].y; xs[3 * s + 2] = p[s].z; }
+    return CDEM_OK;
+}
+
+extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
+    if (!sc || !v) return fail(sc, CDEM_E_INVALID, "null argument");
+    const DevScene &S = sc->S;
+    if (!sc->rec_cap) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    int cur = c.buf;
+    int64_t ne = c.n_entries_cur, ns = S.ns;
+    std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
+    std::vector<uint8_t> st(ne);
+    std::vector<double> dl(ne), F(3 * ne), H(3 * ne);
+    if (ns) {
+        HIPCHK(hipMemcpy(beg.data(), S.row_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cnt.data(), S.row_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
+    }
+    if (ne) {
+        HIPCHK(hipMemcpy(nb.data(), S.nbr[cur], 4 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(st.data(), S.rec_state, ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(F.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(H.data(), S.hist[cur], 24 * ne, hipMemcpyDeviceToHost));
+    }
+    struct Row { uint64_t key; int64_t e; };
+    std::vector<Row> rows;
+    for (int64_t s = 0; s < ns; s++)
+        for (uint32_t k = 0; k < cnt[s]; k++) {
+            int64_t e = (int64_t)beg[s] + k;
+            uint32_t t = nb[e];
+            if (!st[e]) continue;
+            uint64_t b;
+            if (t < (uint32_t)ns) {
+                if (t < (uint32_t)s) continue;  // the pair is listed from its lower id
+                b = t;
+            } else {
+                b = (uint64_t)ns + (uint64_t)sc->bnd_user[t - (uint32_t)ns];
+            }
+            rows.push_back({((uint64_t)s << 32) | b, e});
+        }
+    std::sort(rows.begin(), rows.end(), [](const Row &x, const Row &y) { return x.key < y.key; });
+    v->n = (int64_t)rows.size();
+    for (int64_t i = 0; i < std::min<int64_t>(v->n, v->cap); i++) {
+        int64_t e = rows[i].e;
+        if (v->a) v->a[i] = (uint32_t)(rows[i].key >> 32);
+        if (v->b) v->b[i] = (uint32_t)(rows[i].key & 0xffffffffu);
+        if (v->delta) v->delta[i] = dl[e];
+        for (int k = 0; k < 3; k++) {
+            if (v->F) v->F[3 * i + k] = F[3 * e + k];
+            if (v->u) v->u[3 * i + k] = H[3 * e + k];
+        }
+    }
+    return CDEM_OK;
+}
+
+extern "C" int cdem_read_clump_forces(cdem_scene *sc, double *F, double *T) {
+    if (!sc) return CDEM_E_INVALID;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    if (F) HIPCHK(hipMemcpy(F, sc->S.rec_cF, 24 * sc->S.nc, hipMemcpyDeviceToHost));
+    if (T) HIPCHK(hipMemcpy(T, sc->S.rec_cT, 24 * sc->S.nc, hipMemcpyDeviceToHost));
+    return CDEM_OK;
+}
+
+extern "C" int cdem_audit(cdem_scene *sc, cdem_audit_result *r) {
+    if (!sc || !r) return fail(sc, CDEM_E_INVALID, "null argument");
+    const DevScene &S = sc->S;
+    if (S.ns > 400000) return fail(sc, CDEM_E_INVALID, "exhaustive audit is limited to 400k spheres");
+    unsigned long long *cnt = (unsigned long long *)dev_alloc(sc, 3 * 8);
+    if (!cnt) return fail(sc, CDEM_E_OOM, "audit counters");
+    unsigned long long init[3] = {0, 0, ~0ull};
+    HIPCHK(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, sc->stream));
+    HIPCHK(launch_pose(S, 0, sc->stream));
+    HIPCHK(launch_audit_brute(S, cnt, (uint32_t *)(cnt + 2), sc->stream));
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    unsigned long long out[3];
+    HIPCHK(hipMemcpy(out, cnt, sizeof out, hipMemcpyDeviceToHost));
+    dev_free(sc, cnt);
+    r->true_contacts = (int64_t)out[0];
+    r->missed = (int64_t)out[1];
+    r->first_a = out[1] ? (uint32_t)(out[2] >> 32) : 0;
+    uint32_t fb = (uint32_t)(out[2] & 0xffffffffu);
+    if (out[1] && fb >= (uint32_t)S.ns) fb = (uint32_t)S.ns + (uint32_t)sc->bnd_user[fb - (uint32_t)S.ns];
+    r->first_b = out[1] ? fb : 0;
+    return out[1] ? CDEM_E_MISSED_CONTACT : CDEM_OK;
+}
+
+extern "C" int cdem_profile(cdem_scene *sc, int on) {
+    if (!sc) return CDEM_E_INVALID;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    delete sc->timer;
+    sc->timer = on ? new (std::nothrow) EventTimer() : nullptr;
+    if (on && !sc->timer) return fail(sc, CDEM_E_OOM, "timer");
+    return CDEM_OK;
+}
+
+extern "C" int cdem_profile_read(cdem_scene *sc, cdem_kernel_time *out, int cap, int *n) {
+    if (!sc || !n || (cap > 0 && !out)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    int k = 0;
+    if (sc->timer) {
+        HIPCHK(hipStreamSynchronize(sc->stream));
+        sc->timer->harvest();
+        for (int i = 0; i < K_COUNT; i++) {
+            if (!sc->timer->launches[i]) continue;
+            if (k < cap) {
+                memset(&out[k], 0, sizeof out[k]);
+                snprintf(out[k].name, sizeof out[k].name, "%s", kKernelNames[i]);
+                out[k].launches = sc->timer->launches[i];
+                out[k].total_ms = sc->timer->total_ms[i];
+            }
+            k++;
+        }
+    }
+    *n = k;
+    return CDEM_OK;
+}
+
+extern "C" int cdem_last_step_contacts(cdem_scene *sc, int64_t *n) {
+    if (!sc || !n) return CDEM_E_INVALID;
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    *n = c.contacts_last;
+    return CDEM_OK;
+}

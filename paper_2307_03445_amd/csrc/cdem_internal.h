@@ -1,0 +1,150 @@
+// Internal declarations of libcdem (HIP, gfx950).  Shared by the kernel
+// translation unit and the host runtime; not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cdem {
+
+constexpr int kMaxBnd = 64;
+constexpr int kNarrowBlock = 64;   // one wavefront per workgroup in the narrow phase
+constexpr int kMaxRow = 64;        // candidates one sphere may hold (per detection)
+constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
+
+// Analytic boundary as the kernels see it (geometry at t = 0 plus motion).
+struct Bnd {
+    int32_t type, scene;
+    double p[12];
+    double vel[3], omg[3];
+    double e, g, mu, beta;   // (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, damping ratio of CoR
+    float ef, gf, muf, betaf;
+    double margin;           // extra candidate margin covering the boundary's own motion
+};
+
+// Per-scene uniform grid (scenes never share a bin, so no pair crosses scenes).
+struct Grid {
+    double ox, oy, oz;       // lower corner
+    double inv;              // 1 / bin size
+    int32_t nx, ny, nz, pad;
+    int64_t cell0;           // first global bin id of the scene
+    int32_t bnd_beg, bnd_end;
+    double gx, gy, gz;       // gravity
+};
+
+// Device-resident control block: decides on the device whether a detection
+// runs this step, so that a captured sequence of launches stays static.
+struct Ctl {
+    int64_t step;            // completed steps
+    int64_t n_entries;       // entries written by the detection in progress
+    int64_t n_entries_cur;   // entries of the active set in use
+    int64_t detections, guard_trips, fallbacks, audits, missed;
+    int32_t buf;             // which of the two active-set buffers is current
+    int32_t det_due;         // a detection runs at the start of this step
+    int32_t since_det;       // steps completed since the last detection
+    int32_t k_cur;           // current detection interval
+    int32_t overflow;        // active-set storage overflowed: later kernels of the step skip
+    int32_t row_overflow;    // a sphere exceeded kMaxRow candidates
+    int32_t guard;           // a sphere moved past its margin this step
+    int32_t record;          // store per-contact data this step
+    int32_t nonfinite;       // a clump state became NaN/Inf
+    int32_t pad;
+    int64_t contacts_acc;    // true contacts (exact predicate, delta > 0) of the step in progress
+    int64_t contacts_last;   // ... of the last completed step (each pair counted from both sides)
+    uint32_t vmax_bits;      // max sphere speed of this step (float bits, >= 0)
+    uint32_t amax_bits;      // max sphere acceleration estimate of the step in progress
+    uint32_t amax_last;      // ... of the last completed step
+    float margin_cur;        // margin of every sphere at the last detection (fixed rule)
+    int64_t audit_true;      // true contacts seen by the last audit
+    int64_t audit_last_missed;
+};
+
+// Detection plan parameters (fixed rule), set by cdem_set_detection.
+struct Plan {
+    int32_t k_max;
+    int32_t audit_period;
+    float safety;
+    float margin_cap;
+    float margin_floor;
+    float v_user;            // a-priori speed bound (0 = measured)
+    int32_t test_zero_margin; // testing aid: margins forced to zero
+    int32_t pad;
+};
+
+// Everything a step kernel needs, by value (kernel argument).
+struct DevScene {
+    int64_t nc, ns;
+    int32_t n_scenes, n_bnd, precision, detect_mode;
+    double h;
+    int64_t n_cells;
+    int64_t cap;                     // entries per active-set buffer
+    // clump state (SoA)
+    double *px, *py, *pz, *qw, *qx, *qy, *qz, *vx, *vy, *vz, *wx, *wy, *wz;
+    // clump static
+    const double *mass, *ix, *iy, *iz;
+    const int64_t *sbeg;             // [nc+1]
+    const int32_t *presc;            // [nc] -1 or index
+    const double *presc_param;       // [n_presc][12]
+    const uint32_t *clump_tmpl, *clump_scene;
+    const uint32_t *tmpl_sbeg;
+    const double *tmpl_ofs;          // [n_ts][3]
+    const double *tmpl_rad;
+    // per clump, written by the pose kernel
+    double4 *kin;                    // [nc][3]: (x, M), (v, 0), (w_world, 0)
+    // sphere static
+    const uint32_t *owner, *sscene;
+    const double4 *mat64;            // (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, beta
+    const float4 *mat32;
+    // sphere dynamic
+    double4 *spos;                   // (x, y, z, R)
+    double4 *sdet;                   // position at the last detection
+    float *smargin;                  // margin assigned at the last detection
+    double *sF, *sT;                 // [ns][3] per-sphere sums (big clumps only)
+    // binning
+    const Grid *grids;
+    uint32_t *cell_of, *cell_count, *cell_start, *cell_fill;
+    uint32_t *sorted_id, *sorted_owner;
+    double4 *sorted_pos;
+    float *sorted_margin;
+    // active set: two buffers, current chosen by ctl->buf
+    uint32_t *row_beg[2], *row_cnt[2], *nbr[2];
+    double *hist[2];                 // [cap][3]
+    // recording
+    uint8_t *rec_state;
+    double *rec_delta, *rec_F;       // [cap], [cap][3]
+    double *rec_cF, *rec_cT;         // [nc][3]
+    const Bnd *bnd;
+    Ctl *ctl;
+    // big clumps
+    const int32_t *big_list;         // clump ids
+    int32_t n_big;
+    int32_t pad;
+    const float *crad;               // [nc] bounding radius of each clump about its CoM
+    Plan plan;
+};
+
+// Optional per-kernel timing: when non-null, launchers bracket every kernel
+// with events taken from the pool and note which kernel each pair belongs to.
+struct KernelTimer {
+    virtual void before(int kernel_id, hipStream_t st) = 0;
+    virtual void after(int kernel_id, hipStream_t st) = 0;
+    virtual ~KernelTimer() {}
+};
+enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
+                K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
+                K_COUNT };
+extern const char *const kKernelNames[K_COUNT];
+extern KernelTimer *g_timer;
+
+// Launchers (kernels.hip).  Every launcher enqueues on `st` and returns the
+// hipError_t of the launch.
+hipError_t launch_pose(const DevScene &S, int guard, hipStream_t st);
+hipError_t launch_detect(const DevScene &S, hipStream_t st);
+hipError_t launch_force_integrate(const DevScene &S, hipStream_t st);
+hipError_t launch_step_end(const DevScene &S, hipStream_t st);
+hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uint32_t *first, hipStream_t st);
+// Periodic binned exact audit (every plan.audit_period steps, decided on the device).
+hipError_t launch_audit_binned(const DevScene &S, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace cdem

@@ -1,0 +1,1041 @@
+// HIP kernels of the clumped-sphere DEM step (gfx950, wave64).
+//
+// One step (paper Sec. 2.1 / 2.2):
+//   k_pose           sphere centres x_s = x_c + A(q) o_s and per-clump kinematics
+//                    (multi-sphere clumps, Sec. 2.1); displacement guard when
+//                    detection is deferred;
+//   detection        (only when due) per-scene uniform bins: count, scan, scatter;
+//                    k_narrow tests the 27 neighbour bins of every sphere with the
+//                    enlarged geometry of Sec. 2.2, keeps each sphere's candidates
+//                    sorted by partner id in LDS, allocates rows with a wavefront
+//                    scan and carries the tangential history of surviving pairs;
+//   k_force_integrate per clump: every sphere's active-set row is evaluated with
+//                    the Hertz-Mindlin law (Eqs. normal_tangential_force_model1/2,
+//                    kinematicsContactInfo, updateUt, cappingOfut), summed per
+//                    sphere in ascending partner id and per clump in ascending
+//                    sphere id, then integrated (Eq. newton_law_1/2, symplectic
+//                    Euler with the gyroscopic term).
+//
+// Every pair is evaluated in both partners' rows with the lower sphere id as
+// body a, so the two copies are bit-identical and each row owns its history;
+// no atomics touch any floating-point result, so the step is deterministic.
+// Compiled with -ffp-contract=off: the FP64 path performs exactly the IEEE
+// operations written, in the order written.
+#include "cdem_internal.h"
+
+#include <math.h>
+
+namespace cdem {
+
+__device__ __forceinline__ bool aborted(const Ctl *c) { return c->overflow != 0; }
+
+// ---------------------------------------------------------------- rotation
+__device__ __forceinline__ void quat_mat(double w, double x, double y, double z, double *A) {
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y - w * z);
+    A[2] = 2.0 * (x * z + w * y);
+    A[3] = 2.0 * (x * y + w * z);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z - w * x);
+    A[6] = 2.0 * (x * z - w * y);
+    A[7] = 2.0 * (y * z + w * x);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// ---------------------------------------------------------------- pose (per sphere)
+__global__ void __launch_bounds__(256) k_pose(DevScene S, int guard) {
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    uint32_t c = S.owner[s];
+    double w = S.qw[c], x = S.qx[c], y = S.qy[c], z = S.qz[c];
+    double A[9];
+    quat_mat(w, x, y, z, A);
+    double X = S.px[c], Y = S.py[c], Z = S.pz[c];
+    int64_t s0 = S.sbeg[c];
+    if (s == s0) {
+        double wb0 = S.wx[c], wb1 = S.wy[c], wb2 = S.wz[c];
+        double ww0 = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
+        double ww1 = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
+        double ww2 = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
+        S.kin[3 * (int64_t)c + 0] = make_double4(X, Y, Z, S.mass[c]);
+        S.kin[3 * (int64_t)c + 1] = make_double4(S.vx[c], S.vy[c], S.vz[c], 0.0);
+        S.kin[3 * (int64_t)c + 2] = make_double4(ww0, ww1, ww2, 0.0);
+    }
+    uint32_t ts = S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - s0);
+    double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+    double xs = X + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+    double ys = Y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+    double zs = Z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+    S.spos[s] = make_double4(xs, ys, zs, S.tmpl_rad[ts]);
+    if (guard) {
+        double4 d = S.sdet[s];
+        double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double lim = 0.999 * (double)S.smargin[s];
+        if (!(d2 < lim * lim)) S.ctl->guard = 1;
+        // speed envelope of this sphere: |v_c + w x r|
+        double wb0 = S.wx[c], wb1 = S.wy[c], wb2 = S.wz[c];
+        double w0 = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
+        double w1 = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
+        double w2 = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
+        double r0 = xs - X, r1 = ys - Y, r2 = zs - Z;
+        double u0 = S.vx[c] + (w1 * r2 - w2 * r1), u1 = S.vy[c] + (w2 * r0 - w0 * r2), u2 = S.vz[c] + (w0 * r1 - w1 * r0);
+        float sp = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+        if (sp > __uint_as_float(S.ctl->vmax_bits)) atomicMax(&S.ctl->vmax_bits, __float_as_uint(sp));
+    }
+}
+
+// ---------------------------------------------------------------- boundaries
+// Signed distance of p from boundary b at time t (positive on the domain side)
+// and the unit normal from the wall into the domain.  Returns false where the
+// boundary cannot touch p.
+__device__ bool bnd_distance(const Bnd &B, double t, double px, double py, double pz, double &phi, double *n) {
+    const double *P = B.p;
+    double r0x = P[0] + t * B.vel[0], r0y = P[1] + t * B.vel[1], r0z = P[2] + t * B.vel[2];
+    double d0 = px - r0x, d1 = py - r0y, d2 = pz - r0z;
+    if (B.type == 0) {
+        phi = d0 * P[3] + d1 * P[4] + d2 * P[5];
+        n[0] = P[3]; n[1] = P[4]; n[2] = P[5];
+        return true;
+    }
+    double a0 = P[3], a1 = P[4], a2 = P[5];
+    double ta = d0 * a0 + d1 * a1 + d2 * a2;
+    double rho0 = d0 - ta * a0, rho1 = d1 - ta * a1, rho2 = d2 - ta * a2;
+    double r = sqrt(rho0 * rho0 + rho1 * rho1 + rho2 * rho2);
+    if (B.type == 1) {
+        if (!(r > 0.0)) return false;
+        phi = P[6] - r;
+        n[0] = -(rho0 / r); n[1] = -(rho1 / r); n[2] = -(rho2 / r);
+        return true;
+    }
+    double sn = P[6], cs = P[7];
+    if (B.type == 2) {
+        double H = P[8];
+        double rb = H * (sn / cs);
+        double lam = ta * cs + r * sn;
+        if (ta >= H) {
+            if (!(r > 0.0)) return false;
+            phi = r - rb;
+            n[0] = rho0 / r; n[1] = rho1 / r; n[2] = rho2 / r;
+            return true;
+        }
+        if (lam <= 0.0) {
+            double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            if (!(dd > 0.0)) return false;
+            phi = dd;
+            n[0] = d0 / dd; n[1] = d1 / dd; n[2] = d2 / dd;
+            return true;
+        }
+        if (!(r > 0.0)) return false;
+        if (lam <= H / cs) {
+            phi = r * cs - ta * sn;
+            n[0] = (rho0 / r) * cs - a0 * sn;
+            n[1] = (rho1 / r) * cs - a1 * sn;
+            n[2] = (rho2 / r) * cs - a2 * sn;
+            return true;
+        }
+        double dt = ta - H, dr = r - rb;
+        double dd = sqrt(dt * dt + dr * dr);
+        if (!(dd > 0.0)) return false;
+        phi = dd;
+        n[0] = (dt * a0 + dr * (rho0 / r)) / dd;
+        n[1] = (dt * a1 + dr * (rho1 / r)) / dd;
+        n[2] = (dt * a2 + dr * (rho2 / r)) / dd;
+        return true;
+    }
+    if (ta < P[8] || ta > P[9] || !(r > 0.0)) return false;
+    phi = ta * sn - r * cs;
+    n[0] = a0 * sn - (rho0 / r) * cs;
+    n[1] = a1 * sn - (rho1 / r) * cs;
+    n[2] = a2 * sn - (rho2 / r) * cs;
+    return true;
+}
+
+// ---------------------------------------------------------------- binning
+__device__ __forceinline__ void cell_coords(const Grid &g, double x, double y, double z, int &ix, int &iy, int &iz) {
+    double fx = floor((x - g.ox) * g.inv), fy = floor((y - g.oy) * g.inv), fz = floor((z - g.oz) * g.inv);
+    fx = fmin(fmax(fx, 0.0), (double)(g.nx - 1));
+    fy = fmin(fmax(fy, 0.0), (double)(g.ny - 1));
+    fz = fmin(fmax(fz, 0.0), (double)(g.nz - 1));
+    ix = (int)fx; iy = (int)fy; iz = (int)fz;
+}
+
+__device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
+__device__ __forceinline__ bool audit_due(const DevScene &S) {
+    return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
+}
+// which = 0: the detection chain; which = 1: the periodic audit's own binning
+__device__ __forceinline__ bool chain_active(const DevScene &S, int which) {
+    return which ? audit_due(S) : due(S.ctl);
+}
+
+__global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
+    if (!chain_active(S, which)) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < S.n_cells; k += stride) { S.cell_count[k] = 0; S.cell_fill[k] = 0; }
+    if (i == 0 && !which) { S.ctl->n_entries = 0; S.ctl->row_overflow = 0; }
+    if (i == 0 && which) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
+}
+
+__global__ void __launch_bounds__(256) k_cell_count(DevScene S, int which) {
+    if (!chain_active(S, which)) return;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    double4 p = S.spos[s];
+    const Grid &g = S.grids[S.sscene[s]];
+    int ix, iy, iz;
+    cell_coords(g, p.x, p.y, p.z, ix, iy, iz);
+    uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
+    S.cell_of[s] = cell;
+    atomicAdd(&S.cell_count[cell], 1u);
+}
+
+// Exclusive scan of cell_count -> cell_start in three passes (1024 bins per block).
+constexpr int kScanBlock = 256, kScanItems = 4, kScanTile = kScanBlock * kScanItems;
+
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        uint32_t add = t >= off ? sh[t - off] : 0u;
+        __syncthreads();
+        sh[t] += add;
+        __syncthreads();
+    }
+    total = sh[kScanBlock - 1];
+    uint32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_reduce(DevScene S, uint32_t *bsum, int which) {
+    if (!chain_active(S, which)) return;
+    __shared__ uint32_t sh[kScanBlock];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t v = 0;
+    for (int k = 0; k < kScanItems; k++) if (base + k < S.n_cells) v += S.cell_count[base + k];
+    uint32_t tot;
+    block_excl_scan(v, sh, tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_bsum(DevScene S, uint32_t *bsum, int64_t nblk, int which) {
+    if (!chain_active(S, which)) return;
+    __shared__ uint32_t sh[kScanBlock];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nblk; b0 += kScanBlock) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t v = i < nblk ? bsum[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, sh, tot);
+        if (i < nblk) bsum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void __launch_bounds__(kScanBlock) k_scan_final(DevScene S, const uint32_t *bsum, int which) {
+    if (!chain_active(S, which)) return;
+    __shared__ uint32_t sh[kScanBlock];
+    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    uint32_t loc[kScanItems];
+    uint32_t v = 0;
+    for (int k = 0; k < kScanItems; k++) {
+        loc[k] = base + k < S.n_cells ? S.cell_count[base + k] : 0u;
+        v += loc[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan(v, sh, tot) + bsum[blockIdx.x];
+    for (int k = 0; k < kScanItems; k++) {
+        if (base + k < S.n_cells) S.cell_start[base + k] = ex;
+        ex += loc[k];
+    }
+}
+
+// Scatter spheres into their bins.  For a detection, every sphere also takes
+// this detection's margin (fixed rule: one value; learned: per sphere) and
+// remembers where it stood, for the displacement guard.
+__global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *margin_src, int which) {
+    if (!chain_active(S, which)) return;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    uint32_t cell = S.cell_of[s];
+    uint32_t slot = S.cell_start[cell] + atomicAdd(&S.cell_fill[cell], 1u);
+    double4 p = S.spos[s];
+    S.sorted_id[slot] = (uint32_t)s;
+    S.sorted_owner[slot] = S.owner[s];
+    S.sorted_pos[slot] = p;
+    if (which) return;
+    float m = margin_src ? margin_src[s] : S.ctl->margin_cur;
+    S.sorted_margin[slot] = m;
+    S.smargin[s] = m;
+    S.sdet[s] = p;
+}
+
+// Fixed rule of the enlarged contact geometry: the margin covers k steps of
+// motion at the measured speed and acceleration envelopes,
+// m = safety k h v + (k h)^2 a / 2, with the longest k <= k_max whose margin
+// stays below the cap.  A sphere that still outruns it trips the guard.
+__global__ void k_plan(DevScene S) {
+    Ctl *c = S.ctl;
+    if (!due(c)) return;
+    if (S.detect_mode == 0) { c->margin_cur = 0.0f; c->k_cur = 1; return; }
+    float v = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
+    float a = __uint_as_float(c->amax_last);
+    int k = S.plan.k_max;
+    double m = 0.0;
+    for (; k >= 1; k--) {
+        double T = (double)k * S.h;
+        m = (double)S.plan.safety * (T * (double)v) + 0.5 * (double)a * T * T;
+        if (m <= (double)S.plan.margin_cap) break;
+    }
+    if (k < 1) { k = 1; m = S.plan.margin_cap; }
+    m = fmax(m, (double)S.plan.margin_floor);
+    if (S.plan.test_zero_margin) { m = 0.0; k = S.plan.k_max; }
+    c->margin_cur = (float)m;
+    c->k_cur = k;
+}
+
+// ---------------------------------------------------------------- narrow phase
+// Wave64 exclusive scan of per-lane counts; returns the lane's offset and the total.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &total) {
+    int lane = threadIdx.x & 63;
+    uint32_t x = v;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    total = __shfl(x, 63, 64);
+    return x - v;
+}
+
+__global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
+    if (!due(S.ctl)) return;
+    __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
+    const int tid = threadIdx.x;
+    int64_t i = (int64_t)blockIdx.x * kNarrowBlock + tid;
+    const int cur = S.ctl->buf, nxt = cur ^ 1;
+    int cnt = 0;
+    bool over = false;
+    uint32_t s = 0;
+    if (i < S.ns) {
+        s = S.sorted_id[i];
+        double4 P = S.sorted_pos[i];
+        uint32_t own = S.sorted_owner[i];
+        float ms = S.sorted_margin[i];
+        const Grid &g = S.grids[S.sscene[s]];
+        int ix, iy, iz;
+        cell_coords(g, P.x, P.y, P.z, ix, iy, iz);
+        int z0 = max(iz - 1, 0), z1 = min(iz + 1, g.nz - 1);
+        int y0 = max(iy - 1, 0), y1 = min(iy + 1, g.ny - 1);
+        int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.nx - 1);
+        for (int zz = z0; zz <= z1; zz++)
+            for (int yy = y0; yy <= y1; yy++) {
+                int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
+                uint32_t jb = S.cell_start[rowc + x0];
+                uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+                for (uint32_t j = jb; j < je; j++) {
+                    if (S.sorted_owner[j] == own) continue;
+                    double4 Q = S.sorted_pos[j];
+                    double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    double Sr = P.w + Q.w;
+                    Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
+                    if (d2 < Sr * Sr) {
+                        uint32_t t = S.sorted_id[j];
+                        if (cnt == kMaxRow) { over = true; continue; }
+                        int k = cnt;
+                        while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
+                            lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
+                            k--;
+                        }
+                        lst[k * kNarrowBlock + tid] = t;
+                        cnt++;
+                    }
+                }
+            }
+        double tnow = (double)S.ctl->step * S.h;
+        for (int b = g.bnd_beg; b < g.bnd_end; b++) {
+            double phi, n[3];
+            if (!bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n)) continue;
+            double lim = P.w + ((double)ms + S.bnd[b].margin);
+            if (phi < lim) {
+                if (cnt == kMaxRow) { over = true; continue; }
+                lst[cnt * kNarrowBlock + tid] = (uint32_t)(S.ns + b);
+                cnt++;
+            }
+        }
+    }
+    uint32_t total;
+    uint32_t off = wave_excl_scan((uint32_t)cnt, total);
+    unsigned long long base = 0;
+    if ((tid & 63) == 0 && total) base = atomicAdd((unsigned long long *)&S.ctl->n_entries, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    if (over) S.ctl->row_overflow = 1;
+    if (i >= S.ns) return;
+    if (base + total > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
+    uint32_t beg = (uint32_t)(base + off);
+    S.row_beg[nxt][s] = beg;
+    S.row_cnt[nxt][s] = (uint32_t)cnt;
+    // carry the tangential history of pairs already in the previous active set
+    uint32_t ob = S.row_beg[cur][s], oc = S.row_cnt[cur][s];
+    const uint32_t *onb = S.nbr[cur] + ob;
+    const double *oh = S.hist[cur] + 3 * (int64_t)ob;
+    uint32_t j = 0;
+    for (int k = 0; k < cnt; k++) {
+        uint32_t t = lst[k * kNarrowBlock + tid];
+        S.nbr[nxt][beg + k] = t;
+        while (j < oc && onb[j] < t) j++;
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+        if (j < oc && onb[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
+        double *nh = S.hist[nxt] + 3 * ((int64_t)beg + k);
+        nh[0] = h0; nh[1] = h1; nh[2] = h2;
+    }
+}
+
+__global__ void k_detect_end(DevScene S) {
+    Ctl *c = S.ctl;
+    if (!due(c) || c->overflow) return;
+    if (c->row_overflow) { c->overflow = 1; return; }
+    if (c->guard && !c->det_due) c->guard_trips++;
+    c->buf ^= 1;
+    c->n_entries_cur = c->n_entries;
+    c->detections++;
+    c->since_det = 0;
+    c->det_due = 0;
+    c->guard = 0;
+}
+
+// ---------------------------------------------------------------- contact law
+struct Acc { double F[3], T[3]; };
+
+__device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ void cross3f(const float *a, const float *b, float *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+// FP64 Hertz-Mindlin law: force on body b and updated history.
+__device__ void law64(const double *n, double delta, const double *vrel, double Rbar, double mbar,
+                      double estar, double gstar, double mu, double beta, double h, const double *u_old,
+                      double *F, double *u_new) {
+    const double kdamp = -2.0 * sqrt(5.0 / 6.0);
+    double vn_s = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    double vn[3], vt[3];
+    for (int i = 0; i < 3; i++) vn[i] = vn_s * n[i];
+    for (int i = 0; i < 3; i++) vt[i] = vrel[i] - vn[i];
+    double sq = sqrt(Rbar * delta);
+    double Sn = 2.0 * estar * sq;
+    double gn = kdamp * beta * sqrt(Sn * mbar);
+    double kn = (4.0 / 3.0) * estar * sq * delta;
+    double Fn[3];
+    for (int i = 0; i < 3; i++) Fn[i] = kn * n[i] - gn * vn[i];
+    double up[3];
+    for (int i = 0; i < 3; i++) up[i] = u_old[i] + h * vt[i];
+    double upn = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
+    double ut[3];
+    for (int i = 0; i < 3; i++) ut[i] = up[i] - upn * n[i];
+    double St = 8.0 * gstar * sq;
+    double gt = kdamp * beta * sqrt(St * mbar);
+    double Ft[3];
+    for (int i = 0; i < 3; i++) Ft[i] = -(St * ut[i]) - gt * vt[i];
+    double fn_norm = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
+    double ft_norm = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+    double cap = mu * fn_norm;
+    if (ft_norm > cap) {
+        double scale = cap / ft_norm;
+        for (int i = 0; i < 3; i++) Ft[i] = Ft[i] * scale;
+        double ut_norm = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        if (ut_norm > 0.0) {
+            double fac = (cap / St) / ut_norm;
+            for (int i = 0; i < 3; i++) u_new[i] = fac * ut[i];
+        } else {
+            for (int i = 0; i < 3; i++) u_new[i] = 0.0;
+        }
+    } else {
+        for (int i = 0; i < 3; i++) u_new[i] = ut[i];
+    }
+    for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
+}
+
+// FP32 law: force arithmetic in FP32; the history update, its projection and
+// the clamp of the history stay in FP64.
+__device__ void law32(const double *nd, double delta_d, const float *vrel, float Rbar, float mbar, float estar,
+                      float gstar, float mu, float beta, double h, const double *u_old, float *F, double *u_new) {
+    const float kdamp = -2.0f * sqrtf(5.0f / 6.0f);
+    float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
+    float delta = (float)delta_d;
+    float vn_s = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
+    float vn[3], vt[3];
+    for (int i = 0; i < 3; i++) vn[i] = vn_s * n[i];
+    for (int i = 0; i < 3; i++) vt[i] = vrel[i] - vn[i];
+    float sq = sqrtf(Rbar * delta);
+    float Sn = 2.0f * estar * sq;
+    float gn = kdamp * beta * sqrtf(Sn * mbar);
+    float kn = (4.0f / 3.0f) * estar * sq * delta;
+    float Fn[3];
+    for (int i = 0; i < 3; i++) Fn[i] = kn * n[i] - gn * vn[i];
+    double up[3];
+    for (int i = 0; i < 3; i++) up[i] = u_old[i] + h * (double)vt[i];
+    double upn = up[0] * nd[0] + up[1] * nd[1] + up[2] * nd[2];
+    double ut[3];
+    for (int i = 0; i < 3; i++) ut[i] = up[i] - upn * nd[i];
+    float St = 8.0f * gstar * sq;
+    float gt = kdamp * beta * sqrtf(St * mbar);
+    float Ft[3];
+    for (int i = 0; i < 3; i++) Ft[i] = -(St * (float)ut[i]) - gt * vt[i];
+    float fn_norm = sqrtf(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
+    float ft_norm = sqrtf(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
+    float cap = mu * fn_norm;
+    if (ft_norm > cap) {
+        float scale = cap / ft_norm;
+        for (int i = 0; i < 3; i++) Ft[i] = Ft[i] * scale;
+        double ut_norm = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
+        if (ut_norm > 0.0) {
+            double fac = (double)(cap / St) / ut_norm;
+            for (int i = 0; i < 3; i++) u_new[i] = fac * ut[i];
+        } else {
+            for (int i = 0; i < 3; i++) u_new[i] = 0.0;
+        }
+    } else {
+        for (int i = 0; i < 3; i++) u_new[i] = ut[i];
+    }
+    for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
+}
+
+// Evaluate row entry e of sphere s (owner c) and add its force and torque on s.
+// Pairs are computed with the lower sphere id as body a; boundaries are body a.
+template <bool FP32>
+__device__ __forceinline__ bool eval_entry(const DevScene &S, uint32_t s, uint32_t c, const double4 &Ps,
+                                           const double4 *kin_c, int64_t e, uint32_t t, double tnow,
+                                           double *h_io, bool rec, double *Fs, double *Ts) {
+    double u_old[3] = {h_io[0], h_io[1], h_io[2]};
+    double u_new[3];
+    double Fd[3];
+    double rs[3];           // lever arm of s
+    bool contact;
+    double delta = 0.0;
+    if (t < (uint32_t)S.ns) {
+        bool s_is_a = s < t;
+        uint32_t a = s_is_a ? s : t, b = s_is_a ? t : s;
+        double4 Pa = s_is_a ? Ps : S.spos[a];
+        double4 Pb = s_is_a ? S.spos[b] : Ps;
+        double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y, dz = Pb.z - Pa.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double Sr = Pa.w + Pb.w;
+        contact = d2 < Sr * Sr;
+        if (!contact) {
+            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
+            return false;
+        }
+        uint32_t ca = s_is_a ? c : S.owner[a], cb = s_is_a ? S.owner[b] : c;
+        const double4 *ka = s_is_a ? kin_c : S.kin + 3 * (int64_t)ca;
+        const double4 *kb = s_is_a ? S.kin + 3 * (int64_t)cb : kin_c;
+        double4 xa = ka[0], va = ka[1], wa = ka[2];
+        double4 xb = kb[0], vb = kb[1], wb = kb[2];
+        double d = sqrt(d2);
+        delta = Sr - d;
+        double n[3] = {dx / d, dy / d, dz / d};
+        double lever = Pa.w - 0.5 * delta;
+        double p[3] = {Pa.x + lever * n[0], Pa.y + lever * n[1], Pa.z + lever * n[2]};
+        double ra[3] = {p[0] - xa.x, p[1] - xa.y, p[2] - xa.z};
+        double rb[3] = {p[0] - xb.x, p[1] - xb.y, p[2] - xb.z};
+        for (int i = 0; i < 3; i++) rs[i] = s_is_a ? ra[i] : rb[i];
+        if (!(delta > 0.0)) {
+            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
+            if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
+            return false;
+        }
+        // contact kinematics in FP64 (the relative velocity of two similar
+        // velocities cancels); only the force law drops to FP32 when asked
+        double wva[3] = {wa.x, wa.y, wa.z}, wvb[3] = {wb.x, wb.y, wb.z}, ca3[3], cb3[3];
+        cross3(wva, ra, ca3);
+        cross3(wvb, rb, cb3);
+        double vrel[3] = {(vb.x + cb3[0]) - (va.x + ca3[0]), (vb.y + cb3[1]) - (va.y + ca3[1]),
+                          (vb.z + cb3[2]) - (va.z + ca3[2])};
+        if (!FP32) {
+            double Rbar = (Pa.w * Pb.w) / (Pa.w + Pb.w);
+            double mbar = (xa.w * xb.w) / (xa.w + xb.w);
+            double4 ma = S.mat64[a], mb = S.mat64[b];
+            double estar = 1.0 / (ma.x + mb.x), gstar = 1.0 / (ma.y + mb.y);
+            law64(n, delta, vrel, Rbar, mbar, estar, gstar, fmin(ma.z, mb.z), fmin(ma.w, mb.w), S.h, u_old, Fd, u_new);
+        } else {
+            float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
+            float Ra = (float)Pa.w, Rb = (float)Pb.w, Ma = (float)xa.w, Mb = (float)xb.w;
+            float Rbar = (Ra * Rb) / (Ra + Rb), mbar = (Ma * Mb) / (Ma + Mb);
+            float4 ma = S.mat32[a], mb = S.mat32[b];
+            float Ff[3];
+            law32(n, delta, vrf, Rbar, mbar, 1.0f / (ma.x + mb.x), 1.0f / (ma.y + mb.y), fminf(ma.z, mb.z),
+                  fminf(ma.w, mb.w), S.h, u_old, Ff, u_new);
+            Fd[0] = Ff[0]; Fd[1] = Ff[1]; Fd[2] = Ff[2];
+        }
+        if (rec) {
+            S.rec_state[e] = 1; S.rec_delta[e] = delta;
+            S.rec_F[3 * e] = Fd[0]; S.rec_F[3 * e + 1] = Fd[1]; S.rec_F[3 * e + 2] = Fd[2];
+        }
+        if (s_is_a) { Fd[0] = -Fd[0]; Fd[1] = -Fd[1]; Fd[2] = -Fd[2]; }
+    } else {
+        const Bnd &B = S.bnd[t - (uint32_t)S.ns];
+        double phi, n[3];
+        contact = bnd_distance(B, tnow, Ps.x, Ps.y, Ps.z, phi, n) && phi < Ps.w;
+        if (!contact) {
+            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
+            return false;
+        }
+        double R = Ps.w;
+        delta = R - phi;
+        double lever = R - 0.5 * delta;
+        double p[3] = {Ps.x - lever * n[0], Ps.y - lever * n[1], Ps.z - lever * n[2]};
+        double4 xc = kin_c[0], vc = kin_c[1], wc = kin_c[2];
+        double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
+        double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
+        double rb[3] = {p[0] - xc.x, p[1] - xc.y, p[2] - xc.z};
+        for (int i = 0; i < 3; i++) rs[i] = rb[i];
+        double pw[3], cb3[3], wv3[3] = {wc.x, wc.y, wc.z};
+        cross3(B.omg, ra, pw);
+        cross3(wv3, rb, cb3);
+        double wv[3] = {B.vel[0] + pw[0], B.vel[1] + pw[1], B.vel[2] + pw[2]};
+        double vrel[3] = {(vc.x + cb3[0]) - wv[0], (vc.y + cb3[1]) - wv[1], (vc.z + cb3[2]) - wv[2]};
+        if (!FP32) {
+            double4 ms = S.mat64[s];
+            law64(n, delta, vrel, R, xc.w, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z),
+                  fmin(B.beta, ms.w), S.h, u_old, Fd, u_new);
+        } else {
+            float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
+            float4 ms = S.mat32[s];
+            float Ff[3];
+            law32(n, delta, vrf, (float)R, (float)xc.w, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y),
+                  fminf(B.muf, ms.z), fminf(B.betaf, ms.w), S.h, u_old, Ff, u_new);
+            Fd[0] = Ff[0]; Fd[1] = Ff[1]; Fd[2] = Ff[2];
+        }
+        if (rec) {
+            S.rec_state[e] = 1; S.rec_delta[e] = delta;
+            S.rec_F[3 * e] = Fd[0]; S.rec_F[3 * e + 1] = Fd[1]; S.rec_F[3 * e + 2] = Fd[2];
+        }
+    }
+    h_io[0] = u_new[0]; h_io[1] = u_new[1]; h_io[2] = u_new[2];
+    double tq[3];
+    if (!FP32) {
+        cross3(rs, Fd, tq);
+    } else {
+        float rf[3] = {(float)rs[0], (float)rs[1], (float)rs[2]}, ff[3] = {(float)Fd[0], (float)Fd[1], (float)Fd[2]}, tf[3];
+        cross3f(rf, ff, tf);
+        tq[0] = tf[0]; tq[1] = tf[1]; tq[2] = tf[2];
+    }
+    for (int i = 0; i < 3; i++) { Fs[i] = Fs[i] + Fd[i]; Ts[i] = Ts[i] + tq[i]; }
+    return true;
+}
+
+// Sum of the contact forces and torques on sphere s over its row (ascending partner id).
+template <bool FP32>
+__device__ uint32_t sphere_sum(const DevScene &S, uint32_t s, uint32_t c, const double4 *kin_c, double tnow, bool rec,
+                               double *Fs, double *Ts) {
+    uint32_t ncont = 0;
+    const int cur = S.ctl->buf;
+    uint32_t beg = S.row_beg[cur][s], cnt = S.row_cnt[cur][s];
+    const uint32_t *nb = S.nbr[cur];
+    double *hs = S.hist[cur];
+    double4 Ps = S.spos[s];
+    for (uint32_t k = 0; k < cnt; k++) {
+        int64_t e = (int64_t)beg + k;
+        if (rec) S.rec_state[e] = 0;
+        double h3[3] = {hs[3 * e], hs[3 * e + 1], hs[3 * e + 2]};
+        double h0[3] = {h3[0], h3[1], h3[2]};
+        ncont += eval_entry<FP32>(S, s, c, Ps, kin_c, e, nb[e], tnow, h3, rec, Fs, Ts) ? 1u : 0u;
+        // store only when a bit changed (false positives keep a zero history untouched)
+        if (__double_as_longlong(h3[0]) != __double_as_longlong(h0[0]) ||
+            __double_as_longlong(h3[1]) != __double_as_longlong(h0[1]) ||
+            __double_as_longlong(h3[2]) != __double_as_longlong(h0[2])) {
+            hs[3 * e] = h3[0]; hs[3 * e + 1] = h3[1]; hs[3 * e + 2] = h3[2];
+        }
+    }
+    return ncont;
+}
+
+// Wave-level sum, one atomic per wavefront.
+__device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
+    unsigned long long v = n;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)&ctl->contacts_acc, v);
+}
+
+// Symplectic Euler of one clump from its total force and torque (world frame).
+// Returns an acceleration envelope of its spheres, |a_c| + |dw/dt| r_b + |w|^2 r_b.
+__device__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T) {
+    double h = S.h;
+    double M = S.mass[c];
+    double qw = S.qw[c], qx = S.qx[c], qy = S.qy[c], qz = S.qz[c];
+    double A[9];
+    quat_mat(qw, qx, qy, qz, A);
+    double v[3] = {S.vx[c], S.vy[c], S.vz[c]}, x[3] = {S.px[c], S.py[c], S.pz[c]};
+    double w[3] = {S.wx[c], S.wy[c], S.wz[c]};
+    int32_t pi = S.presc[c];
+    if (pi < 0) {
+        for (int i = 0; i < 3; i++) v[i] = v[i] + h * (F[i] / M);
+        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        double I[3] = {S.ix[c], S.iy[c], S.iz[c]};
+        double tb[3];
+        for (int i = 0; i < 3; i++) tb[i] = A[i] * T[0] + A[3 + i] * T[1] + A[6 + i] * T[2];
+        double L[3] = {I[0] * w[0], I[1] * w[1], I[2] * w[2]};
+        double gy[3];
+        cross3(w, L, gy);
+        for (int i = 0; i < 3; i++) w[i] = w[i] + h * ((tb[i] - gy[i]) / I[i]);
+    } else {
+        const double *P = S.presc_param + 12 * pi;
+        for (int i = 0; i < 3; i++) {
+            if (P[3 + i] != 0.0) v[i] = v[i] + h * ((F[i] + P[9 + i]) / M);
+            else v[i] = P[i];
+        }
+        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        for (int i = 0; i < 3; i++) w[i] = P[6 + i];
+    }
+    double acc_env = 0.0;
+    {
+        double dv0 = v[0] - S.vx[c], dv1 = v[1] - S.vy[c], dv2 = v[2] - S.vz[c];
+        double dw0 = w[0] - S.wx[c], dw1 = w[1] - S.wy[c], dw2 = w[2] - S.wz[c];
+        double rb = (double)S.crad[c];
+        acc_env = (sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2) + rb * sqrt(dw0 * dw0 + dw1 * dw1 + dw2 * dw2)) / h +
+                  rb * (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    }
+    double q[4] = {qw, qx, qy, qz};
+    double dq[4];
+    dq[0] = -(q[1] * w[0] + q[2] * w[1] + q[3] * w[2]);
+    dq[1] = q[0] * w[0] + q[2] * w[2] - q[3] * w[1];
+    dq[2] = q[0] * w[1] + q[3] * w[0] - q[1] * w[2];
+    dq[3] = q[0] * w[2] + q[1] * w[1] - q[2] * w[0];
+    double hh = 0.5 * h;
+    for (int i = 0; i < 4; i++) q[i] = q[i] + hh * dq[i];
+    double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+    for (int i = 0; i < 4; i++) q[i] = q[i] / qn;
+    S.px[c] = x[0]; S.py[c] = x[1]; S.pz[c] = x[2];
+    S.vx[c] = v[0]; S.vy[c] = v[1]; S.vz[c] = v[2];
+    S.wx[c] = w[0]; S.wy[c] = w[1]; S.wz[c] = w[2];
+    S.qw[c] = q[0]; S.qx[c] = q[1]; S.qy[c] = q[2]; S.qz[c] = q[3];
+    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
+          isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
+        S.ctl->nonfinite = 1;
+    return (float)acc_env * 1.000001f;
+}
+
+__device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
+    for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
+    if ((threadIdx.x & 63) == 0 && a > 0.0f && !(a <= __uint_as_float(S.ctl->amax_bits)))
+        atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
+}
+
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_force_integrate(DevScene S) {
+    if (aborted(S.ctl)) return;
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t ncont = 0;
+    float acc = 0.0f;
+    bool active = c < S.nc;
+    int64_t s0 = 0, s1 = 0;
+    if (active) {
+        s0 = S.sbeg[c];
+        s1 = S.sbeg[c + 1];
+        active = s1 - s0 <= kBigClump;  // big clumps go through k_force_big_spheres
+    }
+    if (active) {
+        bool rec = S.ctl->record != 0;
+        double tnow = (double)S.ctl->step * S.h;
+        const double4 *kin_c = S.kin + 3 * c;
+        double Fc[3] = {0.0, 0.0, 0.0}, Tc[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = s0; s < s1; s++) {
+            double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
+            ncont += sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, kin_c, tnow, rec, Fs, Ts);
+            for (int i = 0; i < 3; i++) { Fc[i] = Fc[i] + Fs[i]; Tc[i] = Tc[i] + Ts[i]; }
+        }
+        const Grid &g = S.grids[S.clump_scene[c]];
+        double M = S.mass[c];
+        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
+        if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
+        acc = integrate_clump(S, c, Fc, Tc);
+    }
+    count_contacts(S.ctl, ncont);  // every lane of the wavefront takes part
+    if (S.detect_mode != 0) wave_max_acc(S, acc);
+}
+
+// Clumps with many spheres (a wheel): per-sphere sums first, then one workgroup
+// per clump reduces them in a fixed tree order and integrates.
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_force_big_spheres(DevScene S) {
+    if (aborted(S.ctl)) return;
+    int32_t c = S.big_list[blockIdx.y];
+    int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    bool rec = S.ctl->record != 0;
+    double tnow = (double)S.ctl->step * S.h;
+    for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += (int64_t)gridDim.x * blockDim.x) {
+        double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
+        uint32_t nct = sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, S.kin + 3 * (int64_t)c, tnow, rec, Fs, Ts);
+        if (nct) atomicAdd((unsigned long long *)&S.ctl->contacts_acc, (unsigned long long)nct);
+        for (int i = 0; i < 3; i++) { S.sF[3 * s + i] = Fs[i]; S.sT[3 * s + i] = Ts[i]; }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
+    if (aborted(S.ctl)) return;
+    __shared__ double sh[6][256];
+    int32_t c = S.big_list[blockIdx.x];
+    int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x)
+        for (int i = 0; i < 3; i++) { acc[i] = acc[i] + S.sF[3 * s + i]; acc[3 + i] = acc[3 + i] + S.sT[3 * s + i]; }
+    for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = sh[i][threadIdx.x] + sh[i][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double Fc[3] = {sh[0][0], sh[1][0], sh[2][0]}, Tc[3] = {sh[3][0], sh[4][0], sh[5][0]};
+        const Grid &g = S.grids[S.clump_scene[c]];
+        double M = S.mass[c];
+        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
+        if (S.ctl->record) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
+        float a = integrate_clump(S, c, Fc, Tc);
+        if (S.detect_mode != 0 && a > __uint_as_float(S.ctl->amax_bits)) atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
+    }
+}
+
+__global__ void k_step_end(DevScene S) {
+    Ctl *c = S.ctl;
+    c->record = 0;
+    if (c->overflow) return;
+    c->contacts_last = c->contacts_acc;
+    c->contacts_acc = 0;
+    c->amax_last = c->amax_bits;
+    c->amax_bits = 0;
+    c->vmax_bits = 0;
+    c->step++;
+    c->since_det++;
+    c->det_due = (S.detect_mode == 0 || c->since_det >= c->k_cur) ? 1 : 0;
+    c->guard = 0;
+}
+
+// ---------------------------------------------------------------- audit
+// Exhaustive exact sweep: every true contact must be in the current active set.
+__global__ void __launch_bounds__(256) k_audit_brute(DevScene S, unsigned long long *counts, uint32_t *first) {
+    int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= S.ns) return;
+    const int cur = S.ctl->buf;
+    uint32_t beg = S.row_beg[cur][a], cnt = S.row_cnt[cur][a];
+    const uint32_t *nb = S.nbr[cur] + beg;
+    double4 P = S.spos[a];
+    uint32_t own = S.owner[a], sc = S.sscene[a];
+    unsigned long long found = 0, missed = 0;
+    auto check = [&](uint32_t t) {
+        found++;
+        uint32_t lo = 0, hi = cnt;
+        while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
+        if (!(lo < cnt && nb[lo] == t)) {
+            missed++;
+            unsigned long long key = ((unsigned long long)a << 32) | t;
+            atomicMin((unsigned long long *)first, key);
+        }
+    };
+    for (int64_t b = a + 1; b < S.ns; b++) {
+        if (S.owner[b] == own || S.sscene[b] != sc) continue;
+        double4 Q = S.spos[b];
+        double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        double Sr = P.w + Q.w;
+        if (d2 < Sr * Sr) check((uint32_t)b);
+    }
+    double tnow = (double)S.ctl->step * S.h;
+    const Grid &g = S.grids[sc];
+    for (int b = g.bnd_beg; b < g.bnd_end; b++) {
+        double phi, n[3];
+        if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) check((uint32_t)(S.ns + b));
+    }
+    if (found) atomicAdd(&counts[0], found);
+    if (missed) atomicAdd(&counts[1], missed);
+}
+
+__global__ void k_zero(uint8_t *p, size_t n) {
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0;
+}
+
+// ---------------------------------------------------------------- binned audit
+// Exact contacts of the current positions, found in freshly built bins with no
+// margin, must each be in both partners' rows of the active set.
+__global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
+    if (!audit_due(S)) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long found = 0, missed = 0;
+    if (i < S.ns) {
+        const int cur = S.ctl->buf;
+        uint32_t s = S.sorted_id[i];
+        double4 P = S.sorted_pos[i];
+        uint32_t own = S.sorted_owner[i];
+        uint32_t beg = S.row_beg[cur][s], cnt = S.row_cnt[cur][s];
+        const uint32_t *nb = S.nbr[cur] + beg;
+        auto in_row = [&](uint32_t t) {
+            uint32_t lo = 0, hi = cnt;
+            while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
+            return lo < cnt && nb[lo] == t;
+        };
+        const Grid &g = S.grids[S.sscene[s]];
+        int ix, iy, iz;
+        cell_coords(g, P.x, P.y, P.z, ix, iy, iz);
+        for (int zz = max(iz - 1, 0); zz <= min(iz + 1, g.nz - 1); zz++)
+            for (int yy = max(iy - 1, 0); yy <= min(iy + 1, g.ny - 1); yy++) {
+                int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
+                int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.nx - 1);
+                uint32_t jb = S.cell_start[rowc + x0], je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+                for (uint32_t j = jb; j < je; j++) {
+                    if (S.sorted_owner[j] == own) continue;
+                    double4 Q = S.sorted_pos[j];
+                    double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                    double d2 = dx * dx + dy * dy + dz * dz;
+                    double Sr = P.w + Q.w;
+                    if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
+                }
+            }
+        double tnow = (double)S.ctl->step * S.h;
+        for (int b = g.bnd_beg; b < g.bnd_end; b++) {
+            double phi, n[3];
+            if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) {
+                found++;
+                if (!in_row((uint32_t)(S.ns + b))) missed++;
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        found += __shfl_xor(found, off, 64);
+        missed += __shfl_xor(missed, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (found) atomicAdd((unsigned long long *)&S.ctl->audit_true, found);
+        if (missed) atomicAdd((unsigned long long *)&S.ctl->audit_last_missed, missed);
+    }
+}
+
+__global__ void k_audit_end(DevScene S) {
+    if (!audit_due(S)) return;
+    S.ctl->audits++;
+    S.ctl->missed += S.ctl->audit_last_missed;
+}
+
+// ---------------------------------------------------------------- launchers
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_count", "k_scan_reduce",
+                                           "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
+                                           "k_detect_end", "k_force_integrate", "k_force_big_spheres",
+                                           "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells"};
+KernelTimer *g_timer = nullptr;
+
+#define TIMED(id, launch)                           \
+    do {                                            \
+        if (g_timer) g_timer->before((id), st);     \
+        launch;                                     \
+        if (g_timer) g_timer->after((id), st);      \
+    } while (0)
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    if (!bytes) return hipSuccess;
+    unsigned nb = (unsigned)std::min<size_t>((bytes + 255) / 256, 65536);
+    hipLaunchKernelGGL(k_zero, dim3(nb), dim3(256), 0, st, (uint8_t *)p, bytes);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose(const DevScene &S, int guard, hipStream_t st) {
+    if (S.ns == 0) return hipSuccess;
+    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, guard));
+    return hipGetLastError();
+}
+
+// Bin every sphere of the current positions: zero, count, scan, scatter.
+static void binning(const DevScene &S, int which, hipStream_t st) {
+    unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
+    TIMED(K_DETECT_BEGIN, hipLaunchKernelGGL(k_detect_begin, dim3(zb), dim3(256), 0, st, S, which));
+    TIMED(K_CELL_COUNT, hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
+    int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
+    // the block-sum scratch lives after the cell arrays (allocated by the runtime)
+    uint32_t *bsum = S.cell_fill + S.n_cells;
+    TIMED(K_SCAN_REDUCE, hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S, bsum, which));
+    TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, st, S, bsum, nblk, which));
+    TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S,
+                                           (const uint32_t *)bsum, which));
+    TIMED(K_CELL_SCATTER, hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S,
+                                             (const float *)nullptr, which));
+}
+
+hipError_t launch_detect(const DevScene &S, hipStream_t st) {
+    if (S.ns == 0) return hipSuccess;
+    TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
+    binning(S, 0, st);
+    TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+    TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
+    if (S.ns == 0 || S.plan.audit_period <= 0) return hipSuccess;
+    binning(S, 1, st);
+    TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
+    hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
+    if (S.nc == 0) return hipSuccess;
+    if (S.precision == 1)
+        TIMED(K_FORCE, hipLaunchKernelGGL(k_force_integrate<true>, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S));
+    else
+        TIMED(K_FORCE, hipLaunchKernelGGL(k_force_integrate<false>, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S));
+    if (S.n_big) {
+        if (S.precision == 1)
+            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_force_big_spheres<true>, dim3(64, S.n_big), dim3(256), 0, st, S));
+        else
+            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_force_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
+        TIMED(K_INTEGRATE_BIG, hipLaunchKernelGGL(k_integrate_big, dim3(S.n_big), dim3(256), 0, st, S));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_end(const DevScene &S, hipStream_t st) {
+    TIMED(K_STEP_END, hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, st, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uint32_t *first, hipStream_t st) {
+    if (S.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_audit_brute, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, counts, first);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- state transfer
+// Row-major [n][3]/[n][4] device buffers <-> the scene's SoA clump state.
+__global__ void __launch_bounds__(256) k_pack_state(DevScene S, double *x, double *q, double *v, double *w, int unpack) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= S.nc) return;
+    double *fx[3] = {S.px, S.py, S.pz}, *fq[4] = {S.qw, S.qx, S.qy, S.qz};
+    double *fv[3] = {S.vx, S.vy, S.vz}, *fw[3] = {S.wx, S.wy, S.wz};
+    for (int k = 0; k < 3; k++) {
+        if (x) { if (unpack) fx[k][c] = x[3 * c + k]; else x[3 * c + k] = fx[k][c]; }
+        if (v) { if (unpack) fv[k][c] = v[3 * c + k]; else v[3 * c + k] = fv[k][c]; }
+        if (w) { if (unpack) fw[k][c] = w[3 * c + k]; else w[3 * c + k] = fw[k][c]; }
+    }
+    for (int k = 0; k < 4; k++)
+        if (q) { if (unpack) fq[k][c] = q[4 * c + k]; else q[4 * c + k] = fq[k][c]; }
+}
+
+hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack, hipStream_t st) {
+    if (S.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_state, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S, x, q, v, w, unpack);
+    return hipGetLastError();
+}
+
+}  // namespace cdem

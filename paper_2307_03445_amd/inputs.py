@@ -536,3 +536,196 @@ def two_sphere_headon(r=1e-3, v0=0.05, mat=CFG1_MAT, gap=1e-7, h=1e-6, r2=None):
     q = [(1, 0, 0, 0)] * 2
     return assemble([t1, t2], [0, 1], x, q, v, np.zeros((2, 3)), [mat, mat], (0, 0, 0),
                     (-0.01, -0.01, -0.01, 0.01, 0.01, 0.01), h, name="headon")
+
+
+# ---------------------------------------------------------------------------
+# Configuration 5: rover-scale bed (~11M clumps, ~34M spheres) with a wheel
+# ---------------------------------------------------------------------------
+
+def morton_order(x: np.ndarray, cell: float) -> np.ndarray:
+    """Permutation sorting points by the Morton (Z-order) code of their cell."""
+    c = np.floor((x - x.min(0)) / cell).astype(np.int64)
+    c = np.clip(c, 0, (1 << 20) - 1)
+
+    def spread(v):
+        v = v & 0x1FFFFF
+        v = (v | (v << 32)) & 0x1F00000000FFFF
+        v = (v | (v << 16)) & 0x1F0000FF0000FF
+        v = (v | (v << 8)) & 0x100F00F00F00F00F
+        v = (v | (v << 4)) & 0x10C30C30C30C30C3
+        v = (v | (v << 2)) & 0x1249249249249249
+        return v
+
+    code = spread(c[:, 0]) | (spread(c[:, 1]) << 1) | (spread(c[:, 2]) << 2)
+    return np.argsort(code, kind="stable")
+
+
+def wheel_template(n_spheres=20000, R=0.25, width=0.2, r=4e-3, n_grouser=12, mass=10.0):
+    """Rigid wheel made of spheres: a cylindrical rim (axle along body y) plus
+    n_grouser grouser rows standing out of it; principal axes are x, y, z.
+    Mass properties of a thin shell of the given mass."""
+    n_g_layers = 2
+    n_w = 50
+    n_rim = n_spheres - n_grouser * n_g_layers * (n_spheres // 1000)
+    n_gw = n_spheres // 1000                           # spheres across one grouser layer
+    n_theta = n_rim // n_w
+    n_rim = n_theta * n_w
+    n_gw = (n_spheres - n_rim) // (n_grouser * n_g_layers)
+    th = 2 * np.pi * np.arange(n_theta) / n_theta
+    yy = np.linspace(-width / 2, width / 2, n_w)
+    T, Y = np.meshgrid(th, yy, indexing="ij")
+    rim = np.stack([R * np.cos(T).ravel(), Y.ravel(), R * np.sin(T).ravel()], 1)
+    gth = 2 * np.pi * np.arange(n_grouser) / n_grouser
+    gy = np.linspace(-width / 2, width / 2, n_gw)
+    grs = []
+    for L in range(1, n_g_layers + 1):
+        rr = R + L * r
+        G, Yg = np.meshgrid(gth, gy, indexing="ij")
+        grs.append(np.stack([rr * np.cos(G).ravel(), Yg.ravel(), rr * np.sin(G).ravel()], 1))
+    off = np.concatenate([rim] + grs)
+    extra = n_spheres - off.shape[0]
+    if extra > 0:  # pad the rim's middle ring so the count is exact
+        ang = 2 * np.pi * (np.arange(extra) + 0.5) / extra
+        off = np.concatenate([off, np.stack([R * np.cos(ang), np.zeros(extra), R * np.sin(ang)], 1)])
+    off = off[:n_spheres]
+    I_axle = mass * R * R
+    I_other = mass * (R * R / 2 + width * width / 12)
+    return off, np.full(off.shape[0], r), float(mass), np.array([I_other, I_axle, I_other])
+
+
+def layered_lattice(g: np.random.Generator, templates, clump_template, footprint, gap=2e-4, z0=0.0):
+    """Spawn positions on a lattice of size-homogeneous layers.
+
+    Clumps are sorted by bounding radius and cut into layers of equal count;
+    each layer's spacing is 2 x its largest bounding radius + gap, so no two
+    clumps overlap; layers are stacked in random order.  Returns (x, q) in the
+    input order of ``clump_template``.
+    """
+    x0, y0, x1, y1 = footprint
+    rb_t = np.array([bounding_radius(t[0], t[1]) for t in templates])
+    rb = rb_t[clump_template]
+    n = len(clump_template)
+    order = np.argsort(rb, kind="stable")
+    layers = []
+    i = 0
+    while i < n:
+        # the layer size follows from the spacing its largest member needs
+        s_guess = 2 * rb[order[i]] + gap
+        per = max(1, int((x1 - x0) // s_guess)) * max(1, int((y1 - y0) // s_guess))
+        j = min(n, i + per)
+        s = 2 * rb[order[j - 1]] + gap
+        nxl, nyl = max(1, int((x1 - x0) // s)), max(1, int((y1 - y0) // s))
+        j = min(n, i + nxl * nyl)
+        layers.append((order[i:j], s, nxl, nyl))
+        i = j
+    perm = g.permutation(len(layers))
+    x = np.empty((n, 3))
+    z = z0
+    for li in perm:
+        ids, s, nxl, nyl = layers[li]
+        z += s / 2
+        k = np.arange(len(ids))
+        ox = x0 + ((x1 - x0) - nxl * s) / 2 + s / 2
+        oy = y0 + ((y1 - y0) - nyl * s) / 2 + s / 2
+        x[ids, 0] = ox + (k % nxl) * s
+        x[ids, 1] = oy + (k // nxl) * s
+        x[ids, 2] = z
+        z += s / 2
+    return x, random_unit_quaternions(g, n)
+
+
+def cfg5_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, h: float = 5e-6,
+                     cor: float = 0.2) -> SceneDesc:
+    """The preparation scene of the configuration-5 bed: one side x side patch
+    of the configuration-2 templates spawned on a size-layered lattice inside
+    a walled box, to be settled under gravity (with a larger step and a lower
+    CoR than the measured run, which only speeds up the preparation)."""
+    g = rng(5, replica)
+    tmpls = cfg2_templates(replica)
+    ct = g.integers(0, len(tmpls), n_clumps)
+    x, q = layered_lattice(g, tmpls, ct, (0.0, 0.0, side, side))
+    sizes = np.array([t[0].shape[0] for t in tmpls])
+    ns = int(sizes[ct].sum())
+    mat = np.empty((ns, 4))
+    mat[:, 0] = g.uniform(1e7, 5e7, ns)
+    mat[:, 1] = 0.3
+    mat[:, 2] = g.uniform(0.3, 0.8, ns)
+    mat[:, 3] = cor
+    top = float(x[:, 2].max()) + 0.02
+    walls = box_walls((0, 0, 0), (side, side, top), (5e7, 0.3, 0.5, cor))
+    return assemble(tmpls, ct, x, q, np.zeros((n_clumps, 3)), np.zeros((n_clumps, 3)), mat, (0, 0, -9.81),
+                    (0, 0, 0, side, side, top), h, bnd=walls, name=f"cfg5-patch-r{replica}")
+
+
+def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
+            bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True) -> SceneDesc:
+    """Configuration 5 (the metric's workload), tiled from a settled patch.
+
+    ``patch_x``/``patch_q`` are the settled clump poses of
+    :func:`cfg5_patch_scene` (same replica); the patch is Morton-sorted and
+    copied over the 4 m x 1 m bed (the paper prepares large beds from copies of
+    a settled base patch), truncated to ``n_clumps``.  Per-sphere-instance
+    E ~ U[1e7, 5e7] Pa, mu ~ U[0.3, 0.8]; nu = 0.3; CoR = 0.5; h = 1e-6 s;
+    clumps start at rest.  A rigid 20,000-sphere wheel (R = 0.25 m, width
+    0.2 m, 12 grousers, 10 kg) rests on the surface, driven at slip 0.2
+    (omega = 0.8 rad/s, v = (1 - 0.2) omega R) with a free vertical degree of
+    freedom under a total load of 100 N.
+    """
+    g = rng(5, 1000 + replica)
+    tmpls = cfg2_templates(replica)
+    ct_p = rng(5, replica).integers(0, len(tmpls), patch_x.shape[0])
+    order = morton_order(patch_x, 0.01)
+    xp, qp, ct_p = patch_x[order], patch_q[order], ct_p[order]
+    ntx, nty = int(round(bed[0] / side)), int(round(bed[1] / side))
+    tiles = [(i, j) for j in range(nty) for i in range(ntx)]
+    tiles = [tiles[k] for k in morton_order(np.array([(i, j, 0) for i, j in tiles], float), 1.0)]
+    X = np.concatenate([xp + np.array([i * side, j * side, 0.0]) for i, j in tiles])[:n_clumps]
+    Q = np.tile(qp, (len(tiles), 1))[:n_clumps]
+    CT = np.tile(ct_p, len(tiles))[:n_clumps]
+    nc = X.shape[0]
+    sizes = np.array([t[0].shape[0] for t in tmpls])
+    ns_bed = int(sizes[CT].sum())
+    mat = np.empty((ns_bed, 4))
+    mat[:, 0] = g.uniform(1e7, 5e7, ns_bed)
+    mat[:, 1] = 0.3
+    mat[:, 2] = g.uniform(0.3, 0.8, ns_bed)
+    mat[:, 3] = 0.5
+    V = np.zeros((nc, 3))
+    W = np.zeros((nc, 3))
+    templates = list(tmpls)
+    presc = None
+    top = float(X[:, 2].max())
+    if with_wheel:
+        wt = wheel_template(wheel_spheres)
+        templates.append(wt)
+        R, wr = 0.25, float(wt[1][0])
+        cx, cy = 1.0, bed[1] / 2
+        # column heights of the patch surface (the bed repeats the patch)
+        Rm = quat_matrix(qp)
+        P = np.concatenate([xp[k] + tmpls[ct_p[k]][0] @ Rm[k].T for k in range(len(ct_p))])
+        Rr = np.concatenate([tmpls[ct_p[k]][1] for k in range(len(ct_p))])
+        cell = 0.004
+        nx, ny = int(np.ceil(side / cell)) + 1, int(np.ceil(side / cell)) + 1
+        ix = np.clip(np.floor(P[:, 0] / cell).astype(int), 0, nx - 1)
+        iy = np.clip(np.floor(P[:, 1] / cell).astype(int), 0, ny - 1)
+        colh = np.zeros((nx, ny))
+        np.maximum.at(colh, (ix, iy), P[:, 2] + Rr)
+        wo = wt[0]
+        px = np.mod(cx + wo[:, 0], side)
+        py = np.mod(cy + wo[:, 1], side)
+        h_under = colh[np.clip((px / cell).astype(int), 0, nx - 1), np.clip((py / cell).astype(int), 0, ny - 1)]
+        zc = float((h_under + wr - 5e-4 - wo[:, 2]).max())
+        X = np.vstack([X, [cx, cy, zc]])
+        Q = np.vstack([Q, [1.0, 0.0, 0.0, 0.0]])
+        CT = np.r_[CT, len(tmpls)]
+        om = 0.8
+        vx = (1 - 0.2) * om * R
+        V = np.vstack([V, [vx, 0, 0]])
+        W = np.vstack([W, [0, om, 0]])
+        mat = np.vstack([mat, np.tile([5e7, 0.3, 0.8, 0.5], (wt[0].shape[0], 1))])
+        presc = [dict(clump=nc, v_fixed=(vx, 0, 0), free=(0, 0, 1), w_body=(0, om, 0),
+                      f_extra=(0, 0, -(100.0 - wt[2] * 9.81)))]
+        top = max(top, zc + R + 0.02)
+    walls = box_walls((0, 0, 0), (bed[0], bed[1], top + 0.05), (5e7, 0.3, 0.5, 0.5))
+    return assemble(templates, CT, X, Q, V, W, mat, (0, 0, -9.81), (0, 0, 0, bed[0], bed[1], top + 0.05),
+                    1e-6, bnd=walls, presc=presc, name=f"cfg5-r{replica}")
