@@ -49,7 +49,7 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
         return ns * 132
     if kernel == "k_narrow":
         return ns * 64 + cells * 8 + 28 * (E + Eold)
-    if kernel == "k_force_integrate":
+    if kernel in ("k_force_integrate", "k_force_waves"):
         return nc * 352 + ns * (44 + mat) + 28 * E + 24 * Cs
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)
@@ -144,6 +144,8 @@ def main():
     ap.add_argument("--clumps", type=int, default=11_000_000)
     ap.add_argument("--modes", default="plain,fixed")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--patch-cache", default=None,
+                    help="npz file holding the settled preparation patch (written if missing)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build is single-GPU).",
@@ -154,8 +156,15 @@ def main():
     from paper_2307_03445_amd import prep
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    px, pq, info = prep.settle_patch(log=log)
-    log(f"patch settled: {info}")
+    if args.patch_cache and os.path.exists(args.patch_cache):
+        z = np.load(args.patch_cache)
+        px, pq = z["x"], z["q"]
+        log(f"patch loaded from {args.patch_cache}")
+    else:
+        px, pq, info = prep.settle_patch(log=log)
+        log(f"patch settled: {info}")
+        if args.patch_cache:
+            np.savez(args.patch_cache, x=px, q=pq)
     desc = I.config5(px, pq, n_clumps=args.clumps)
     log(f"workload: {desc.n_clumps} clumps, {desc.n_spheres} spheres, built in {time.perf_counter() - t0:.1f} s")
     stats = dict(spheres=desc.n_spheres, clumps=desc.n_clumps, fp32=True)

@@ -389,6 +389,22 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         }
         crad[c] = (float)rb;
     }
+    // wave schedule of the force kernel: pack whole clumps into groups of at
+    // most 64 spheres, as (first, end) clump pairs; big clumps are skipped
+    std::vector<int32_t> wsched;
+    for (int64_t c = 0; c < nc;) {
+        if (sbeg[c + 1] - sbeg[c] > kBigClump) { c++; continue; }
+        int64_t start = c, n = 0;
+        while (c < nc) {
+            int64_t k = sbeg[c + 1] - sbeg[c];
+            if (k > kBigClump || n + k > 64) break;
+            n += k;
+            c++;
+        }
+        wsched.push_back((int32_t)start);
+        wsched.push_back((int32_t)c);
+    }
+    S.n_waves = (int64_t)wsched.size() / 2;
     S.plan.k_max = 1; S.plan.audit_period = 0; S.plan.safety = 1.5f;
     S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
     // ---- device arrays
@@ -431,6 +447,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     UP(bnd, sc->bnd.data(), sc->bnd.size());
     UP(big_list, big.data(), big.size());
     UP(crad, crad.data(), crad.size());
+    UP(wave_clump0, wsched.data(), wsched.size());
 #undef UP
     S.n_big = (int32_t)big.size();
     S.kin = (double4 *)dev_alloc(sc, 3 * sizeof(double4) * std::max<int64_t>(nc, 1));

@@ -121,6 +121,10 @@ struct DevScene {
     int32_t pad;
     const float *crad;               // [nc] bounding radius of each clump about its CoM
     Plan plan;
+    // wave schedule of the force kernel: wave w covers clumps wave_clump0[2w] ..
+    // wave_clump0[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
+    const int32_t *wave_clump0;
+    int64_t n_waves;
 };
 
 // Optional per-kernel timing: when non-null, launchers bracket every kernel

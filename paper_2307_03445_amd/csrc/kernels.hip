@@ -29,6 +29,12 @@ namespace cdem {
 
 __device__ __forceinline__ bool aborted(const Ctl *c) { return c->overflow != 0; }
 
+// Active-set buffer k of a double-buffered array.  A select keeps the pointer
+// in registers; indexing the by-value kernel argument with a runtime k would
+// copy the pointer pair to scratch memory.
+template <typename T>
+__device__ __forceinline__ T *pick(T *const (&a)[2], int k) { return k ? a[1] : a[0]; }
+
 // ---------------------------------------------------------------- rotation
 __device__ __forceinline__ void quat_mat(double w, double x, double y, double z, double *A) {
     A[0] = 1.0 - 2.0 * (y * y + z * z);
@@ -89,7 +95,7 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int guard) {
 // Signed distance of p from boundary b at time t (positive on the domain side)
 // and the unit normal from the wall into the domain.  Returns false where the
 // boundary cannot touch p.
-__device__ bool bnd_distance(const Bnd &B, double t, double px, double py, double pz, double &phi, double *n) {
+__device__ __forceinline__ bool bnd_distance(const Bnd &B, double t, double px, double py, double pz, double &phi, double *n) {
     const double *P = B.p;
     double r0x = P[0] + t * B.vel[0], r0y = P[1] + t * B.vel[1], r0z = P[2] + t * B.vel[2];
     double d0 = px - r0x, d1 = py - r0y, d2 = pz - r0z;
@@ -376,20 +382,20 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     if (i >= S.ns) return;
     if (base + total > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
     uint32_t beg = (uint32_t)(base + off);
-    S.row_beg[nxt][s] = beg;
-    S.row_cnt[nxt][s] = (uint32_t)cnt;
+    pick(S.row_beg, nxt)[s] = beg;
+    pick(S.row_cnt, nxt)[s] = (uint32_t)cnt;
     // carry the tangential history of pairs already in the previous active set
-    uint32_t ob = S.row_beg[cur][s], oc = S.row_cnt[cur][s];
-    const uint32_t *onb = S.nbr[cur] + ob;
-    const double *oh = S.hist[cur] + 3 * (int64_t)ob;
+    uint32_t ob = pick(S.row_beg, cur)[s], oc = pick(S.row_cnt, cur)[s];
+    const uint32_t *onb = pick(S.nbr, cur) + ob;
+    const double *oh = pick(S.hist, cur) + 3 * (int64_t)ob;
     uint32_t j = 0;
     for (int k = 0; k < cnt; k++) {
         uint32_t t = lst[k * kNarrowBlock + tid];
-        S.nbr[nxt][beg + k] = t;
+        pick(S.nbr, nxt)[beg + k] = t;
         while (j < oc && onb[j] < t) j++;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         if (j < oc && onb[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
-        double *nh = S.hist[nxt] + 3 * ((int64_t)beg + k);
+        double *nh = pick(S.hist, nxt) + 3 * ((int64_t)beg + k);
         nh[0] = h0; nh[1] = h1; nh[2] = h2;
     }
 }
@@ -423,7 +429,7 @@ __device__ __forceinline__ void cross3f(const float *a, const float *b, float *c
 }
 
 // FP64 Hertz-Mindlin law: force on body b and updated history.
-__device__ void law64(const double *n, double delta, const double *vrel, double Rbar, double mbar,
+__device__ __forceinline__ void law64(const double *n, double delta, const double *vrel, double Rbar, double mbar,
                       double estar, double gstar, double mu, double beta, double h, const double *u_old,
                       double *F, double *u_new) {
     const double kdamp = -2.0 * sqrt(5.0 / 6.0);
@@ -467,7 +473,7 @@ __device__ void law64(const double *n, double delta, const double *vrel, double 
 
 // FP32 law: force arithmetic in FP32; the history update, its projection and
 // the clamp of the history stay in FP64.
-__device__ void law32(const double *nd, double delta_d, const float *vrel, float Rbar, float mbar, float estar,
+__device__ __forceinline__ void law32(const double *nd, double delta_d, const float *vrel, float Rbar, float mbar, float estar,
                       float gstar, float mu, float beta, double h, const double *u_old, float *F, double *u_new) {
     const float kdamp = -2.0f * sqrtf(5.0f / 6.0f);
     float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
@@ -547,7 +553,8 @@ __device__ __forceinline__ bool eval_entry(const DevScene &S, uint32_t s, uint32
         double p[3] = {Pa.x + lever * n[0], Pa.y + lever * n[1], Pa.z + lever * n[2]};
         double ra[3] = {p[0] - xa.x, p[1] - xa.y, p[2] - xa.z};
         double rb[3] = {p[0] - xb.x, p[1] - xb.y, p[2] - xb.z};
-        for (int i = 0; i < 3; i++) rs[i] = s_is_a ? ra[i] : rb[i];
+        // lever arm of s: from its own clump's CoM (equals ra or rb exactly)
+        rs[0] = p[0] - kin_c[0].x; rs[1] = p[1] - kin_c[0].y; rs[2] = p[2] - kin_c[0].z;
         if (!(delta > 0.0)) {
             h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
             if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
@@ -635,13 +642,13 @@ __device__ __forceinline__ bool eval_entry(const DevScene &S, uint32_t s, uint32
 
 // Sum of the contact forces and torques on sphere s over its row (ascending partner id).
 template <bool FP32>
-__device__ uint32_t sphere_sum(const DevScene &S, uint32_t s, uint32_t c, const double4 *kin_c, double tnow, bool rec,
+__device__ __forceinline__ uint32_t sphere_sum(const DevScene &S, uint32_t s, uint32_t c, const double4 *kin_c, double tnow, bool rec,
                                double *Fs, double *Ts) {
     uint32_t ncont = 0;
     const int cur = S.ctl->buf;
-    uint32_t beg = S.row_beg[cur][s], cnt = S.row_cnt[cur][s];
-    const uint32_t *nb = S.nbr[cur];
-    double *hs = S.hist[cur];
+    uint32_t beg = pick(S.row_beg, cur)[s], cnt = pick(S.row_cnt, cur)[s];
+    const uint32_t *nb = pick(S.nbr, cur);
+    double *hs = pick(S.hist, cur);
     double4 Ps = S.spos[s];
     for (uint32_t k = 0; k < cnt; k++) {
         int64_t e = (int64_t)beg + k;
@@ -668,7 +675,7 @@ __device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
 
 // Symplectic Euler of one clump from its total force and torque (world frame).
 // Returns an acceleration envelope of its spheres, |a_c| + |dw/dt| r_b + |w|^2 r_b.
-__device__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T) {
+__device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T) {
     double h = S.h;
     double M = S.mass[c];
     double qw = S.qw[c], qx = S.qx[c], qy = S.qy[c], qz = S.qz[c];
@@ -728,6 +735,62 @@ __device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
     for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
     if ((threadIdx.x & 63) == 0 && a > 0.0f && !(a <= __uint_as_float(S.ctl->amax_bits)))
         atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
+}
+
+// One lane per sphere.  Waves are scheduled on clump boundaries (wave w
+// covers the whole clumps wave_clump0[2w] .. wave_clump0[2w+1]-1, at most 64
+// spheres), so the spheres of a clump sit in adjacent lanes: the clump's first
+// lane sums their forces and torques in ascending sphere id by shuffles, adds
+// gravity and integrates the clump.
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_force_waves(DevScene S) {
+    if (aborted(S.ctl)) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (w >= S.n_waves) return;  // whole wave leaves together
+    const int32_t c0 = S.wave_clump0[2 * w], c1 = S.wave_clump0[2 * w + 1];
+    const int64_t S0 = S.sbeg[c0], S1 = S.sbeg[c1];
+    const int64_t s = S0 + lane;
+    const bool active = s < S1;
+    const bool rec = S.ctl->record != 0;
+    const double tnow = (double)S.ctl->step * S.h;
+    double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
+    uint32_t ncont = 0;
+    int64_t c = 0, cb = 0;
+    int cnt = 0;
+    if (active) {
+        c = S.owner[s];
+        cb = S.sbeg[c];
+        cnt = (int)(S.sbeg[c + 1] - cb);
+        ncont = sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, S.kin + 3 * c, tnow, rec, Fs, Ts);
+    }
+    count_contacts(S.ctl, ncont);
+    const bool leader = active && s == cb;
+    // longest clump of the wave: the number of shuffle rounds
+    int mx = leader ? cnt : 0;
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    double Fc[3] = {Fs[0], Fs[1], Fs[2]}, Tc[3] = {Ts[0], Ts[1], Ts[2]};
+    if (leader) {  // the clump sum starts from zero, as in the reference order
+        for (int i = 0; i < 3; i++) { Fc[i] = 0.0 + Fs[i]; Tc[i] = 0.0 + Ts[i]; }
+    }
+    for (int j = 1; j < mx; j++) {
+        int src = min(lane + j, 63);
+        double f0 = __shfl(Fs[0], src, 64), f1 = __shfl(Fs[1], src, 64), f2 = __shfl(Fs[2], src, 64);
+        double t0 = __shfl(Ts[0], src, 64), t1 = __shfl(Ts[1], src, 64), t2 = __shfl(Ts[2], src, 64);
+        if (leader && j < cnt) {
+            Fc[0] = Fc[0] + f0; Fc[1] = Fc[1] + f1; Fc[2] = Fc[2] + f2;
+            Tc[0] = Tc[0] + t0; Tc[1] = Tc[1] + t1; Tc[2] = Tc[2] + t2;
+        }
+    }
+    float acc = 0.0f;
+    if (leader) {
+        const Grid &g = S.grids[S.clump_scene[c]];
+        double M = S.mass[c];
+        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
+        if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
+        acc = integrate_clump(S, c, Fc, Tc);
+    }
+    if (S.detect_mode != 0) wave_max_acc(S, acc);
 }
 
 template <bool FP32>
@@ -827,8 +890,8 @@ __global__ void __launch_bounds__(256) k_audit_brute(DevScene S, unsigned long l
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.ns) return;
     const int cur = S.ctl->buf;
-    uint32_t beg = S.row_beg[cur][a], cnt = S.row_cnt[cur][a];
-    const uint32_t *nb = S.nbr[cur] + beg;
+    uint32_t beg = pick(S.row_beg, cur)[a], cnt = pick(S.row_cnt, cur)[a];
+    const uint32_t *nb = pick(S.nbr, cur) + beg;
     double4 P = S.spos[a];
     uint32_t own = S.owner[a], sc = S.sscene[a];
     unsigned long long found = 0, missed = 0;
@@ -878,8 +941,8 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         uint32_t s = S.sorted_id[i];
         double4 P = S.sorted_pos[i];
         uint32_t own = S.sorted_owner[i];
-        uint32_t beg = S.row_beg[cur][s], cnt = S.row_cnt[cur][s];
-        const uint32_t *nb = S.nbr[cur] + beg;
+        uint32_t beg = pick(S.row_beg, cur)[s], cnt = pick(S.row_cnt, cur)[s];
+        const uint32_t *nb = pick(S.nbr, cur) + beg;
         auto in_row = [&](uint32_t t) {
             uint32_t lo = 0, hi = cnt;
             while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
@@ -932,7 +995,7 @@ static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b -
 
 const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_count", "k_scan_reduce",
                                            "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
-                                           "k_detect_end", "k_force_integrate", "k_force_big_spheres",
+                                           "k_detect_end", "k_force_waves", "k_force_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells"};
 KernelTimer *g_timer = nullptr;
 
@@ -991,10 +1054,13 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
 
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
-    if (S.precision == 1)
-        TIMED(K_FORCE, hipLaunchKernelGGL(k_force_integrate<true>, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S));
-    else
-        TIMED(K_FORCE, hipLaunchKernelGGL(k_force_integrate<false>, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S));
+    unsigned wb = (unsigned)((S.n_waves + 3) / 4);
+    if (wb) {
+        if (S.precision == 1)
+            TIMED(K_FORCE, hipLaunchKernelGGL(k_force_waves<true>, dim3(wb), dim3(256), 0, st, S));
+        else
+            TIMED(K_FORCE, hipLaunchKernelGGL(k_force_waves<false>, dim3(wb), dim3(256), 0, st, S));
+    }
     if (S.n_big) {
         if (S.precision == 1)
             TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_force_big_spheres<true>, dim3(64, S.n_big), dim3(256), 0, st, S));
