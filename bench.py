@@ -49,8 +49,16 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
         return ns * 132
     if kernel == "k_narrow":
         return ns * 64 + cells * 8 + 28 * (E + Eold)
-    if kernel in ("k_force_integrate", "k_force_waves"):
-        return nc * 352 + ns * (44 + mat) + 28 * E + 24 * Cs
+    if kernel == "k_pairs":
+        # per candidate pair: pair id, own/partner ids, mirror, two flags, history
+        # read; per contact pair: history write and two contributions; compulsory
+        # per-sphere and per-clump gathers (position+radius, material, owner, kinematics)
+        P, Cp = st["pairs"], Cs / 2.0
+        return P * 42 + Cp * (24 + 2 * (mat + 8)) + ns * (36 + mat) + nc * 96
+    if kernel == "k_reduce_waves":
+        # per entry: flag; per contact side: contribution; per sphere: row and owner;
+        # per clump: state read+write, mass properties, scene, bounding radius
+        return E * 1 + Cs * (mat + 8) + ns * 20 + nc * 264
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)
     if kernel == "k_detect_begin":
@@ -58,10 +66,12 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     return 0.0
 
 
-def run_path(desc, mode, steps, warmup, k_max=20, margin_cap=2e-4, audit_every=100):
+def run_path(desc, mode, steps, warmup, k_max=20, margin_cap=2e-4, audit_every=100, mlp=None):
     import torch
     from paper_2307_03445_amd._lib import Scene
     sc = Scene(desc, precision="fp32")
+    if mode == "learned":
+        sc.set_mlp(mlp)
     if mode != "plain":
         sc.set_detection(mode, k_max=k_max, safety=1.5, margin_cap=margin_cap, audit_period=audit_every)
     t0 = time.perf_counter()
@@ -102,10 +112,11 @@ def roofline(res, desc_stats, mode):
     prof = res["prof"]
     k, (n, ms) = max(prof.items(), key=lambda kv: kv[1][1])
     st = dict(desc_stats, entries=res["counts"]["candidates"], entries_old=res["counts"]["candidates"],
-              contact_sides=res["contact_sides"], guard=(mode != "plain"))
+              pairs=res["counts"]["pairs"], contact_sides=res["contact_sides"], guard=(mode != "plain"))
     # a detection kernel early-exits when no detection is due: count only real launches
     launches = n
-    if k in ("k_narrow", "k_cell_count", "k_cell_scatter", "k_detect_begin", "k_scan_reduce", "k_scan_final"):
+    if k in ("k_narrow", "k_mirror", "k_cell_count", "k_cell_scatter", "k_detect_begin", "k_scan_reduce",
+             "k_scan_final"):
         launches = max(1, res["detections"])
     b = algorithmic_bytes(k, st)
     avg_s = ms / 1e3 / launches
@@ -142,7 +153,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--clumps", type=int, default=11_000_000)
-    ap.add_argument("--modes", default="plain,fixed")
+    ap.add_argument("--modes", default="plain,fixed,learned")
+    ap.add_argument("--mlp", default=None, help="npz with envelope-MLP parameters (default: the package's "
+                                                "trained weights, else train now)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--patch-cache", default=None,
                     help="npz file holding the settled preparation patch (written if missing)")
@@ -168,9 +181,22 @@ def main():
     desc = I.config5(px, pq, n_clumps=args.clumps)
     log(f"workload: {desc.n_clumps} clumps, {desc.n_spheres} spheres, built in {time.perf_counter() - t0:.1f} s")
     stats = dict(spheres=desc.n_spheres, clumps=desc.n_clumps, fp32=True)
+    modes = args.modes.split(",")
+    mlp, mlp_info = None, None
+    if "learned" in modes:
+        from paper_2307_03445_amd import train
+        path = args.mlp or train.WEIGHTS
+        if os.path.exists(path):
+            mlp = np.load(path)["params"].astype(np.float32)
+            mlp_info = f"loaded {os.path.relpath(path, ROOT)}"
+        else:
+            t1 = time.perf_counter()
+            mlp, info = train.train(px, pq, log=log)
+            mlp_info = f"trained now in {time.perf_counter() - t1:.1f} s: {info}"
+        log(f"envelope MLP: {mlp_info}")
     results = {}
-    for mode in args.modes.split(","):
-        r = run_path(desc, mode, args.steps, args.warmup)
+    for mode in modes:
+        r = run_path(desc, mode, args.steps, args.warmup, mlp=mlp)
         results[mode] = r
     from paper_2307_03445_amd._lib import Scene  # noqa: F401  (native library is the path)
     main_mode = "learned" if "learned" in results else ("fixed" if "fixed" in results else "plain")
@@ -199,6 +225,7 @@ def main():
                       "guard_trips": v["guard_trips"], "candidates": v["counts"]["candidates"],
                       "contact_sides": v["contact_sides"], "missed": v["counts"]["missed"]}
                   for m, v in results.items()},
+        "envelope_mlp": mlp_info,
         "roofline": roofline(r, stats, main_mode),
     }
     if "plain" in results and main_mode != "plain":

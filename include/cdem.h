@@ -131,6 +131,7 @@ typedef struct cdem_counts {
     int64_t missed;       /* contacts found by audits but absent from the active set */
     int64_t capacity;     /* active-set entries that fit in the current storage */
     int64_t regrows;
+    int64_t pairs;        /* distinct candidate pairs of the active set (sphere pairs + boundary pairs) */
     int32_t k_current;    /* current detection interval */
     int32_t reserved;
 } cdem_counts;
@@ -197,6 +198,42 @@ int cdem_read_sphere_pos(cdem_scene *s, double *xs);
 /* Independent exact contact sweep (no binning, no margin) over the current
  * state, compared with the active set.  O(N^2): for small scenes and tests. */
 int cdem_audit(cdem_scene *s, cdem_audit_result *r);
+
+/* ---- learned detection interval: envelope MLP ---- */
+/* The MLP maps per-bin features (max sphere speed, max acceleration envelope,
+ * occupancy) to (log speed envelope, log acceleration envelope) over the next
+ * detection interval; the margin of a bin's spheres is
+ * safety k h v_env + (k h)^2 a_env / 2, which enlarges the contact geometry
+ * of the deferred active-set update (paper Sec. 2.2) per bin instead of with
+ * one global speed bound.  Parameters are float32, cdem_mlp_param_count() of
+ * them: mu[3], sigma[3] (input standardisation of u = (log(f0 + 1e-6),
+ * log(f1 + 1e-3), log(1 + f2))), W1[64][3], b1[64], W2[64][64], b2[64],
+ * W3[2][64], b3[2]. */
+int cdem_mlp_param_count(void);
+/* Load MLP parameters (host pointer, n = cdem_mlp_param_count()) into the scene. */
+int cdem_set_mlp(cdem_scene *s, const float *params, int64_t n);
+/* Device pointers: features [n][3] (raw), out [n][2].  Asynchronous on stream. */
+int cdem_mlp_forward(const float *params, const float *features, float *out, int64_t n, void *stream);
+/* Bytes of workspace cdem_mlp_backward needs for n samples. */
+size_t cdem_mlp_workspace_bytes(int64_t n);
+/* Gradient (device, cdem_mlp_param_count() floats) and loss (device, one float,
+ * may be NULL) of the mean pinball loss with quantile tau in (0, 1) of the
+ * MLP on features [n][3] against targets [n][2]; standardisation entries get
+ * zero gradient.  Deterministic. */
+int cdem_mlp_backward(const float *params, const float *features, const float *target, int64_t n, float tau,
+                      float *grad, float *loss, void *workspace, void *stream);
+/* One Adam update (step t >= 1, bias-corrected) of params with grad; m and v
+ * are the moment buffers (device, zero-initialised by the caller). */
+int cdem_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t t, float lr, float beta1,
+                  float beta2, float eps, void *stream);
+/* Training data from the scene's own trajectory: capture per-bin features of
+ * the current state, advance `horizon` steps, and label each occupied bin with
+ * the largest speed and acceleration envelope its spheres showed over those
+ * steps, as (log(v + 1e-6), log(a + 1e-3)).  Host buffers features [cap][3],
+ * labels [cap][2]; *n receives the number of occupied bins (call with cap = 0
+ * to size; the steps still run). */
+int cdem_collect_envelopes(cdem_scene *s, int32_t horizon, float *features, float *labels, int64_t cap,
+                           int64_t *n);
 
 /* ---- measurement (not part of the method) ---- */
 /* Per-kernel device time, measured with HIP events recorded on the launch

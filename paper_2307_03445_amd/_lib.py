@@ -52,7 +52,8 @@ class DetectParamsC(C.Structure):
 
 class CountsC(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("clumps", "spheres", "bins", "candidates", "steps", "detections",
-                                          "guard_trips", "fallbacks", "audits", "missed", "capacity", "regrows")] + \
+                                          "guard_trips", "fallbacks", "audits", "missed", "capacity", "regrows",
+                                          "pairs")] + \
                [("k_current", C.c_int32), ("reserved", C.c_int32)]
 
 
@@ -93,6 +94,13 @@ SIGNATURES = {
     "cdem_profile": (C.c_int, [P, C.c_int]),
     "cdem_profile_read": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_int)]),
     "cdem_last_step_contacts": (C.c_int, [P, C.POINTER(C.c_int64)]),
+    "cdem_mlp_param_count": (C.c_int, []),
+    "cdem_set_mlp": (C.c_int, [P, P, C.c_int64]),
+    "cdem_mlp_forward": (C.c_int, [P, P, P, C.c_int64, P]),
+    "cdem_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "cdem_mlp_backward": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P, P]),
+    "cdem_mlp_adam": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
 }
 
 _lib = None
@@ -287,3 +295,65 @@ class Scene:
         v = C.c_int64(0)
         self._check(self._L.cdem_last_step_contacts(self._h, C.byref(v)))
         return v.value
+
+    # ---------------------------------------------------------------- learned envelopes
+    def set_mlp(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        self._check(self._L.cdem_set_mlp(self._h, _ptr(p), p.size))
+
+    def collect_envelopes(self, horizon: int = 20):
+        """Per-bin features of the current state and the envelopes the bins'
+        spheres show over the next `horizon` steps (which this call runs)."""
+        n = C.c_int64(0)
+        cap = max(1, self.counts()["bins"])
+        f = np.empty((cap, 3), np.float32)
+        y = np.empty((cap, 2), np.float32)
+        self._check(self._L.cdem_collect_envelopes(self._h, int(horizon), _ptr(f), _ptr(y), cap, C.byref(n)))
+        return f[:n.value].copy(), y[:n.value].copy()
+
+
+def _dev(t):
+    return P(t.data_ptr())
+
+
+def _stream():
+    import torch
+    s = torch.cuda.current_stream().cuda_stream
+    return P(s) if s else None
+
+
+def mlp_param_count() -> int:
+    return load().cdem_mlp_param_count()
+
+
+def mlp_forward(params, features):
+    """params: device float32 tensor; features [n, 3] device float32 -> [n, 2]."""
+    import torch
+    L = load()
+    out = torch.empty((features.shape[0], 2), dtype=torch.float32, device=features.device)
+    rc = L.cdem_mlp_forward(_dev(params), _dev(features), _dev(out), features.shape[0], _stream())
+    if rc:
+        raise CdemError(rc, "cdem_mlp_forward")
+    return out
+
+
+def mlp_backward(params, features, target, tau):
+    """Gradient and loss of the mean pinball loss (device tensors)."""
+    import torch
+    L = load()
+    n = features.shape[0]
+    ws = torch.empty(int(L.cdem_mlp_workspace_bytes(n)) // 4 + 1, dtype=torch.float32, device=features.device)
+    grad = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=features.device)
+    rc = L.cdem_mlp_backward(_dev(params), _dev(features), _dev(target), n, float(tau), _dev(grad), _dev(loss),
+                             _dev(ws), _stream())
+    if rc:
+        raise CdemError(rc, "cdem_mlp_backward")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    rc = load().cdem_mlp_adam(_dev(params), _dev(grad), _dev(m), _dev(v), int(t), float(lr), float(beta1),
+                              float(beta2), float(eps), _stream())
+    if rc:
+        raise CdemError(rc, "cdem_mlp_adam")

@@ -70,6 +70,7 @@ struct EventTimer : KernelTimer {
 struct cdem_scene {
     EventTimer *timer = nullptr;
     bool test_no_guard = false;   // testing aid: deferred detection without the displacement guard
+    bool collecting = false;      // cdem_collect_envelopes in progress
     std::string err;
     cdem_allocator alloc{};
     bool custom_alloc = false;
@@ -205,6 +206,16 @@ static int build_grids(cdem_scene *sc) {
         S.cell_start = (uint32_t *)dev_alloc(sc, cell0 * 4);
         S.cell_fill = (uint32_t *)dev_alloc(sc, (cell0 + nblk) * 4);  // + scan block sums
         if (!S.cell_count || !S.cell_start || !S.cell_fill) return fail(sc, CDEM_E_OOM, "bin arrays");
+        dev_free(sc, S.bin_v); dev_free(sc, S.bin_a); dev_free(sc, S.bin_margin);
+        dev_free(sc, S.occ_t); dev_free(sc, S.lab_v); dev_free(sc, S.lab_a);
+        S.bin_v = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.bin_a = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.bin_margin = (float *)dev_alloc(sc, cell0 * 4);
+        S.occ_t = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.lab_v = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.lab_a = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        if (!S.bin_v || !S.bin_a || !S.bin_margin || !S.occ_t || !S.lab_v || !S.lab_a)
+            return fail(sc, CDEM_E_OOM, "bin arrays");
         sc->n_cells_alloc = cell0;
     }
     return CDEM_OK;
@@ -219,6 +230,18 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
         hs[k] = (double *)dev_alloc(sc, cap * 24);
         if (!nb[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
     }
+    // per-entry arrays derived at each detection (no content to keep)
+    dev_free(sc, S.eself); dev_free(sc, S.emirror); dev_free(sc, S.pairs); dev_free(sc, S.eflag);
+    dev_free(sc, S.cA); dev_free(sc, S.cB);
+    size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 4 : 8;  // contribution word size
+    S.eself = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.emirror = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.pairs = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.eflag = (uint8_t *)dev_alloc(sc, cap);
+    S.cA = dev_alloc(sc, cap * 4 * cw);
+    S.cB = dev_alloc(sc, cap * 2 * cw);
+    if (!S.eself || !S.emirror || !S.pairs || !S.eflag || !S.cA || !S.cB)
+        return fail(sc, CDEM_E_OOM, "active-set storage");
     if (keep) {
         // preserve the current buffer (rows point into it)
         Ctl c;
@@ -462,6 +485,10 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.rec_cF = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
     S.rec_cT = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
     S.ctl = (Ctl *)dev_alloc(sc, sizeof(Ctl));
+    S.sspeed = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.cacc = (float *)dev_alloc(sc, 4 * std::max<int64_t>(nc, 1));
+    S.cell_t = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    if (!S.sspeed || !S.cacc || !S.cell_t) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     for (int k = 0; k < 2; k++) {
         S.row_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
         S.row_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
@@ -492,7 +519,9 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
             launch_zero(S.row_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
             return bail(fail(sc, CDEM_E_HIP, "zero"));
     }
-    if (launch_zero(S.sdet, sizeof(double4) * ns, sc->stream) != hipSuccess ||
+    if (launch_zero(S.cacc, 4 * (size_t)nc, sc->stream) != hipSuccess ||
+        launch_zero(S.sspeed, 4 * (size_t)ns, sc->stream) != hipSuccess ||
+        launch_zero(S.sdet, sizeof(double4) * ns, sc->stream) != hipSuccess ||
         launch_zero(S.smargin, 4 * (size_t)ns, sc->stream) != hipSuccess)
         return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
@@ -529,9 +558,11 @@ static int enqueue_steps(cdem_scene *sc, int64_t n) {
     g_timer = sc->timer;
     for (int64_t i = 0; i < n; i++) {
         hipError_t e = launch_pose(S, guard, sc->stream);
+        if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, sc->stream);
         if (e == hipSuccess) e = launch_detect(S, sc->stream);
         if (e == hipSuccess) e = launch_audit_binned(S, sc->stream);
         if (e == hipSuccess) e = launch_force_integrate(S, sc->stream);
+        if (e == hipSuccess && sc->collecting) e = launch_collect_acc(S, sc->stream);
         if (e == hipSuccess) e = launch_step_end(S, sc->stream);
         if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
         if (sc->timer && sc->timer->used > 4096) {  // bound the event pool
@@ -561,6 +592,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         if (!c.overflow) break;
         if (c.row_overflow)
             return fail(sc, CDEM_E_CAPACITY, "a sphere has more than 64 candidate partners (margin or bin too large)");
+        if (c.asym) return fail(sc, CDEM_E_STATE, "active-set rows are not symmetric");
         // grow the active set and resume from the step that did not complete
         int64_t need = (int64_t)(1.3 * (double)c.n_entries) + 1024;
         int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
@@ -568,6 +600,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         sc->regrows++;
         c.overflow = 0;
         c.row_overflow = 0;
+        c.asym = 0;
         c.det_due = 1;
         c.record = 0;
         if ((rc = write_ctl(sc, c)) != CDEM_OK) return rc;
@@ -591,7 +624,8 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
         return fail(sc, CDEM_E_INVALID, "detection parameters out of range");
     if (p->mode != CDEM_DETECT_PLAIN && !(p->margin_cap > 0.0))
         return fail(sc, CDEM_E_INVALID, "deferred detection needs a positive margin cap");
-    if (p->mode == CDEM_DETECT_LEARNED) return fail(sc, CDEM_E_INVALID, "learned detection not available");
+    if (p->mode == CDEM_DETECT_LEARNED && !sc->S.mlp)
+        return fail(sc, CDEM_E_STATE, "learned detection needs MLP parameters (cdem_set_mlp)");
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
@@ -604,6 +638,8 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
     sc->S.plan.margin_floor = (float)std::min(1e-7, 0.5 * p->margin_cap);
     sc->S.plan.v_user = (float)p->v_max_user;
     sc->S.plan.test_zero_margin = sc->test_no_guard ? 1 : 0;
+    sc->S.store_speed = p->mode == CDEM_DETECT_LEARNED ? 1 : 0;
+    sc->S.store_acc = p->mode == CDEM_DETECT_LEARNED ? 1 : 0;
     set_bnd_margins(sc);
     HIPCHK(hipMemcpyAsync((void *)sc->S.bnd, sc->bnd.data(), sc->bnd.size() * sizeof(Bnd), hipMemcpyHostToDevice, sc->stream));
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
@@ -640,6 +676,7 @@ extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
     out->candidates = c.n_entries_cur; out->steps = c.step; out->detections = c.detections;
     out->guard_trips = c.guard_trips; out->fallbacks = c.fallbacks; out->audits = c.audits;
     out->missed = c.missed; out->capacity = sc->S.cap; out->regrows = sc->regrows; out->k_current = c.k_cur;
+    out->pairs = c.n_pairs_cur;
     return CDEM_OK;
 }
 
@@ -836,4 +873,76 @@ extern "C" int cdem_last_step_contacts(cdem_scene *sc, int64_t *n) {
     if (rc) return rc;
     *n = c.contacts_last;
     return CDEM_OK;
+}
+
+namespace cdem {
+hipError_t launch_collect_begin(const DevScene &S, hipStream_t st);
+}
+
+extern "C" int cdem_set_mlp(cdem_scene *sc, const float *params, int64_t n) {
+    if (!sc || !params || n != cdem_mlp_param_count()) return fail(sc, CDEM_E_INVALID, "MLP parameter count");
+    for (int64_t i = 0; i < n; i++)
+        if (!std::isfinite(params[i])) return fail(sc, CDEM_E_INVALID, "non-finite MLP parameter");
+    for (int k = 0; k < 3; k++)
+        if (!(params[3 + k] > 0.f)) return fail(sc, CDEM_E_INVALID, "MLP standardisation scale must be positive");
+    if (!sc->S.mlp) {
+        sc->S.mlp = (const float *)dev_alloc(sc, n * sizeof(float));
+        if (!sc->S.mlp) return fail(sc, CDEM_E_OOM, "MLP parameters");
+    }
+    HIPCHK(hipMemcpyAsync((void *)sc->S.mlp, params, n * sizeof(float), hipMemcpyHostToDevice, sc->stream));
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    return CDEM_OK;
+}
+
+extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *features, float *labels, int64_t cap,
+                                      int64_t *n) {
+    if (!sc || !n || horizon < 1 || cap < 0 || (cap > 0 && (!features || !labels)))
+        return fail(sc, CDEM_E_INVALID, "bad arguments");
+    DevScene &S = sc->S;
+    int32_t ss = S.store_speed, sa = S.store_acc;
+    S.store_speed = 1;
+    S.store_acc = 1;
+    auto restore = [&](int rc) { S.store_speed = ss; S.store_acc = sa; sc->collecting = false; return rc; };
+    int rc = cdem_step(sc, 1, nullptr);  // one step so that every clump has an acceleration envelope
+    if (rc) return restore(rc);
+    hipError_t e = launch_pose(S, 0, sc->stream);
+    if (e == hipSuccess) e = launch_collect_begin(S, sc->stream);
+    if (e != hipSuccess) return restore(fail(sc, CDEM_E_HIP, hipGetErrorString(e)));
+    int64_t nb = S.n_cells;
+    std::vector<uint32_t> fv(nb), fa(nb), occ(nb), lv(nb), la(nb);
+    if (hipStreamSynchronize(sc->stream) != hipSuccess ||
+        hipMemcpy(fv.data(), S.bin_v, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(fa.data(), S.bin_a, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(occ.data(), S.occ_t, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess)
+        return restore(fail(sc, CDEM_E_HIP, "feature copy"));
+    Ctl c;
+    if ((rc = read_ctl(sc, c)) != CDEM_OK) return restore(rc);
+    c.collecting = 1;
+    if ((rc = write_ctl(sc, c)) != CDEM_OK) return restore(rc);
+    sc->collecting = true;
+    rc = cdem_step(sc, horizon, nullptr);
+    sc->collecting = false;
+    int rc2 = read_ctl(sc, c);
+    c.collecting = 0;
+    if (!rc2) rc2 = write_ctl(sc, c);
+    if (rc) return restore(rc);
+    if (rc2) return restore(rc2);
+    if (hipMemcpy(lv.data(), S.lab_v, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(la.data(), S.lab_a, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess)
+        return restore(fail(sc, CDEM_E_HIP, "label copy"));
+    auto f32 = [](uint32_t b) { float x; memcpy(&x, &b, 4); return x; };
+    int64_t k = 0;
+    for (int64_t i = 0; i < nb; i++) {
+        if (!occ[i]) continue;
+        if (k < cap) {
+            features[3 * k] = f32(fv[i]);
+            features[3 * k + 1] = f32(fa[i]);
+            features[3 * k + 2] = (float)occ[i];
+            labels[2 * k] = std::log(f32(lv[i]) + 1e-6f);
+            labels[2 * k + 1] = std::log(f32(la[i]) + 1e-3f);
+        }
+        k++;
+    }
+    *n = k;
+    return restore(CDEM_OK);
 }

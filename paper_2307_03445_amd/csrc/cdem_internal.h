@@ -51,6 +51,10 @@ struct Ctl {
     int32_t pad;
     int64_t contacts_acc;    // true contacts (exact predicate, delta > 0) of the step in progress
     int64_t contacts_last;   // ... of the last completed step (each pair counted from both sides)
+    int64_t n_pairs;         // pairs of the detection in progress
+    int64_t n_pairs_cur;     // pairs of the active set in use
+    int32_t asym;            // an entry had no mirror (never expected): the step is abandoned
+    int32_t collecting;      // training-data capture in progress: accumulate horizon labels
     uint32_t vmax_bits;      // max sphere speed of this step (float bits, >= 0)
     uint32_t amax_bits;      // max sphere acceleration estimate of the step in progress
     uint32_t amax_last;      // ... of the last completed step
@@ -109,6 +113,12 @@ struct DevScene {
     // active set: two buffers, current chosen by ctl->buf
     uint32_t *row_beg[2], *row_cnt[2], *nbr[2];
     double *hist[2];                 // [cap][3]
+    // per entry of the current active set (rebuilt at every detection)
+    uint32_t *eself;                 // the row's own sphere
+    uint32_t *emirror;               // for a lower entry (s < t): t's entry for s
+    uint32_t *pairs;                 // lower entries (s < t, or boundaries): one per pair
+    uint8_t *eflag;                  // the entry's pair is in contact this step
+    void *cA, *cB;                   // contribution to the row's sphere: (F, Tx), (Ty, Tz)
     // recording
     uint8_t *rec_state;
     double *rec_delta, *rec_F;       // [cap], [cap][3]
@@ -121,6 +131,16 @@ struct DevScene {
     int32_t pad;
     const float *crad;               // [nc] bounding radius of each clump about its CoM
     Plan plan;
+    // learned envelopes and training-data collection
+    int32_t store_speed;             // pose writes each sphere's speed to sspeed
+    int32_t store_acc;               // integration writes each clump's acceleration envelope to cacc
+    float *sspeed;                   // [ns]
+    float *cacc;                     // [nc]
+    uint32_t *bin_v, *bin_a;         // [n_cells] max speed / acceleration in the bin (float bits)
+    float *bin_margin;               // [n_cells] margin of the bin's spheres this detection
+    const float *mlp;                // envelope MLP parameters (device), null if none loaded
+    uint32_t *cell_t, *occ_t;        // collection: bins of the spheres and bin occupancy at capture
+    uint32_t *lab_v, *lab_a;         // collection: max speed / acceleration over the horizon (float bits)
     // wave schedule of the force kernel: wave w covers clumps wave_clump0[2w] ..
     // wave_clump0[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
     const int32_t *wave_clump0;
@@ -136,7 +156,7 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_COUNT };
+                K_MIRROR, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 
@@ -149,6 +169,10 @@ hipError_t launch_step_end(const DevScene &S, hipStream_t st);
 hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uint32_t *first, hipStream_t st);
 // Periodic binned exact audit (every plan.audit_period steps, decided on the device).
 hipError_t launch_audit_binned(const DevScene &S, hipStream_t st);
+// Training-data capture: bin features of the current state, then per-step labels.
+hipError_t launch_collect_begin(const DevScene &S, hipStream_t st);
+hipError_t launch_collect_speed(const DevScene &S, hipStream_t st);
+hipError_t launch_collect_acc(const DevScene &S, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
 
 }  // namespace cdem

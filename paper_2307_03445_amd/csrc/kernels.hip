@@ -22,6 +22,7 @@
 // Compiled with -ffp-contract=off: the FP64 path performs exactly the IEEE
 // operations written, in the order written.
 #include "cdem_internal.h"
+#include "mlp_dev.h"
 
 #include <math.h>
 
@@ -79,7 +80,9 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int guard) {
         double d2 = dx * dx + dy * dy + dz * dz;
         double lim = 0.999 * (double)S.smargin[s];
         if (!(d2 < lim * lim)) S.ctl->guard = 1;
-        // speed envelope of this sphere: |v_c + w x r|
+    }
+    if (guard || S.store_speed) {
+        // speed of this sphere's centre: |v_c + w x r|
         double wb0 = S.wx[c], wb1 = S.wy[c], wb2 = S.wz[c];
         double w0 = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
         double w1 = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
@@ -87,6 +90,7 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int guard) {
         double r0 = xs - X, r1 = ys - Y, r2 = zs - Z;
         double u0 = S.vx[c] + (w1 * r2 - w2 * r1), u1 = S.vy[c] + (w2 * r0 - w0 * r2), u2 = S.vz[c] + (w0 * r1 - w1 * r0);
         float sp = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+        if (S.store_speed) S.sspeed[s] = sp;
         if (sp > __uint_as_float(S.ctl->vmax_bits)) atomicMax(&S.ctl->vmax_bits, __float_as_uint(sp));
     }
 }
@@ -171,17 +175,23 @@ __device__ __forceinline__ bool audit_due(const DevScene &S) {
     return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
 }
 // which = 0: the detection chain; which = 1: the periodic audit's own binning
+// which = 2: training-data capture (always runs when launched)
 __device__ __forceinline__ bool chain_active(const DevScene &S, int which) {
-    return which ? audit_due(S) : due(S.ctl);
+    return which == 2 ? true : which ? audit_due(S) : due(S.ctl);
 }
 
 __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
     if (!chain_active(S, which)) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < S.n_cells; k += stride) { S.cell_count[k] = 0; S.cell_fill[k] = 0; }
-    if (i == 0 && !which) { S.ctl->n_entries = 0; S.ctl->row_overflow = 0; }
-    if (i == 0 && which) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
+    const bool bins = which == 2 || (which == 0 && S.detect_mode == 2);
+    for (int64_t k = i; k < S.n_cells; k += stride) {
+        S.cell_count[k] = 0;
+        S.cell_fill[k] = 0;
+        if (bins) { S.bin_v[k] = 0; S.bin_a[k] = 0; }
+    }
+    if (i == 0 && !which) { S.ctl->n_entries = 0; S.ctl->n_pairs = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0; }
+    if (i == 0 && which == 1) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
 }
 
 __global__ void __launch_bounds__(256) k_cell_count(DevScene S, int which) {
@@ -273,7 +283,7 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_owner[slot] = S.owner[s];
     S.sorted_pos[slot] = p;
     if (which) return;
-    float m = margin_src ? margin_src[s] : S.ctl->margin_cur;
+    float m = S.detect_mode == 2 ? S.bin_margin[cell] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
     S.sorted_margin[slot] = m;
     S.smargin[s] = m;
     S.sdet[s] = p;
@@ -287,6 +297,7 @@ __global__ void k_plan(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c)) return;
     if (S.detect_mode == 0) { c->margin_cur = 0.0f; c->k_cur = 1; return; }
+    if (S.detect_mode == 2) { c->k_cur = S.plan.k_max; c->margin_cur = 0.0f; return; }  // per-bin margins
     float v = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
     float a = __uint_as_float(c->amax_last);
     int k = S.plan.k_max;
@@ -301,6 +312,83 @@ __global__ void k_plan(DevScene S) {
     if (S.plan.test_zero_margin) { m = 0.0; k = S.plan.k_max; }
     c->margin_cur = (float)m;
     c->k_cur = k;
+}
+
+// ---------------------------------------------------------------- learned envelopes
+// Per-bin features of the current state: max sphere speed, max acceleration
+// envelope of the spheres' clumps (last step), occupancy (the bin count).
+__global__ void __launch_bounds__(256) k_bin_features(DevScene S, int which) {
+    if (!(which == 2 || (due(S.ctl) && S.detect_mode == 2))) return;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    uint32_t cell = S.cell_of[s];
+    float v = S.sspeed[s], a = S.cacc[S.owner[s]];
+    if (v > 0.f) atomicMax(&S.bin_v[cell], __float_as_uint(v));
+    if (a > 0.f) atomicMax(&S.bin_a[cell], __float_as_uint(a));
+}
+
+// Margin of each occupied bin for this detection: the MLP predicts the bin's
+// speed and acceleration envelopes over the interval (never below what the
+// bin shows now); a non-finite or implausible prediction falls back to the
+// fixed rule's global envelopes.  m = safety k h v + (k h)^2 a / 2.
+__global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
+    Ctl *c = S.ctl;
+    if (!due(c) || S.detect_mode != 2) return;
+    __shared__ float P[kMlpParams];
+    for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) P[i] = S.mlp[i];
+    __syncthreads();
+    const double T = (double)c->k_cur * S.h;
+    const float vg = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
+    const float ag = __uint_as_float(c->amax_last);
+    uint32_t nfb = 0;
+    for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < S.n_cells;
+         cell += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t occ = S.cell_count[cell];
+        if (!occ) continue;
+        float vn = __uint_as_float(S.bin_v[cell]), an = __uint_as_float(S.bin_a[cell]);
+        float y0, y1;
+        mlp_forward(P, vn, an, (float)occ, y0, y1);
+        float ve = expf(y0), ae = expf(y1);
+        if (!(ve < 1e3f) || !(ae < 1e9f) || !(ve >= 0.f) || !(ae >= 0.f)) {  // NaN fails every test
+            ve = vg;
+            ae = ag;
+            nfb++;
+        }
+        ve = fmaxf(ve, vn);
+        ae = fmaxf(ae, an);
+        double m = (double)S.plan.safety * (T * (double)ve) + 0.5 * (double)ae * T * T;
+        m = fmin(fmax(m, (double)S.plan.margin_floor), (double)S.plan.margin_cap);
+        S.bin_margin[cell] = (float)m;
+    }
+    for (int off = 32; off > 0; off >>= 1) nfb += __shfl_xor(nfb, off, 64);
+    if ((threadIdx.x & 63) == 0 && nfb) atomicAdd((unsigned long long *)&c->fallbacks, (unsigned long long)nfb);
+}
+
+// Training-data capture: remember each sphere's bin and each bin's occupancy
+// at capture time, and clear the horizon labels.
+__global__ void __launch_bounds__(256) k_collect_init(DevScene S) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < S.ns; k += stride) S.cell_t[k] = S.cell_of[k];
+    for (int64_t k = i; k < S.n_cells; k += stride) { S.occ_t[k] = S.cell_count[k]; S.lab_v[k] = 0; S.lab_a[k] = 0; }
+}
+
+// Horizon labels: the largest speed / acceleration envelope any sphere of the
+// bin (as binned at capture) shows during the following steps.
+__global__ void __launch_bounds__(256) k_collect_speed(DevScene S) {
+    if (!S.ctl->collecting) return;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    float v = S.sspeed[s];
+    if (v > 0.f) atomicMax(&S.lab_v[S.cell_t[s]], __float_as_uint(v));
+}
+
+__global__ void __launch_bounds__(256) k_collect_acc(DevScene S) {
+    if (!S.ctl->collecting) return;
+    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    float a = S.cacc[S.owner[s]];
+    if (a > 0.f) atomicMax(&S.lab_a[S.cell_t[s]], __float_as_uint(a));
 }
 
 // ---------------------------------------------------------------- narrow phase
@@ -392,6 +480,8 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     for (int k = 0; k < cnt; k++) {
         uint32_t t = lst[k * kNarrowBlock + tid];
         pick(S.nbr, nxt)[beg + k] = t;
+        S.eself[beg + k] = s;
+        if (t < s) continue;  // a pair's history lives in its lower sphere's entry
         while (j < oc && onb[j] < t) j++;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         if (j < oc && onb[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
@@ -400,13 +490,48 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     }
 }
 
+// Pair list and mirror links of the new active set: every entry (s, t) with
+// t > s (or a boundary) is one pair; the entry (t, s) in t's row points back to
+// it, so one evaluation per pair can serve both rows.
+__global__ void __launch_bounds__(256) k_mirror(DevScene S) {
+    Ctl *ctl = S.ctl;
+    if (!due(ctl) || ctl->overflow || ctl->row_overflow) return;
+    const int nxt = ctl->buf ^ 1;
+    const uint32_t *nb = pick(S.nbr, nxt), *rbeg = pick(S.row_beg, nxt), *rcnt = pick(S.row_cnt, nxt);
+    const int64_t n = ctl->n_entries;
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t e = base + threadIdx.x;
+        bool valid = e < n, lower = false;
+        if (valid) {
+            uint32_t s = S.eself[e], t = nb[e];
+            lower = t > s;
+            if (!lower) {  // reverse entry: find s in t's (sorted) row
+                uint32_t b0 = rbeg[t], cnt = rcnt[t], lo = 0, hi = cnt;
+                while (lo < hi) {
+                    uint32_t mid = (lo + hi) >> 1;
+                    if (nb[b0 + mid] < s) lo = mid + 1; else hi = mid;
+                }
+                if (lo < cnt && nb[b0 + lo] == s) S.emirror[b0 + lo] = (uint32_t)e;
+                else ctl->asym = 1;  // rows not symmetric: the step is abandoned
+            }
+        }
+        unsigned long long m = __ballot(valid && lower);
+        unsigned long long pb = 0;
+        if (lane == 0 && m) pb = atomicAdd((unsigned long long *)&ctl->n_pairs, (unsigned long long)__popcll(m));
+        pb = __shfl(pb, 0, 64);
+        if (valid && lower) S.pairs[pb + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)e;
+    }
+}
+
 __global__ void k_detect_end(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || c->overflow) return;
-    if (c->row_overflow) { c->overflow = 1; return; }
+    if (c->row_overflow || c->asym) { c->overflow = 1; return; }
     if (c->guard && !c->det_due) c->guard_trips++;
     c->buf ^= 1;
     c->n_entries_cur = c->n_entries;
+    c->n_pairs_cur = c->n_pairs;
     c->detections++;
     c->since_det = 0;
     c->det_due = 0;
@@ -516,154 +641,163 @@ __device__ __forceinline__ void law32(const double *nd, double delta_d, const fl
     for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
 }
 
-// Evaluate row entry e of sphere s (owner c) and add its force and torque on s.
-// Pairs are computed with the lower sphere id as body a; boundaries are body a.
+// Per-entry contribution storage: force on the row's sphere (3) and its
+// torque about the sphere's clump CoM (3); FP32 mode stores floats.
+template <bool FP32> struct Contrib;
+template <> struct Contrib<true> {
+    using A = float4;
+    using B = float2;
+    static __device__ __forceinline__ void put(void *ca, void *cb, int64_t e, const double *f, const double *t) {
+        ((float4 *)ca)[e] = make_float4((float)f[0], (float)f[1], (float)f[2], (float)t[0]);
+        ((float2 *)cb)[e] = make_float2((float)t[1], (float)t[2]);
+    }
+};
+template <> struct Contrib<false> {
+    using A = double4;
+    using B = double2;
+    static __device__ __forceinline__ void put(void *ca, void *cb, int64_t e, const double *f, const double *t) {
+        ((double4 *)ca)[e] = make_double4(f[0], f[1], f[2], t[0]);
+        ((double2 *)cb)[e] = make_double2(t[1], t[2]);
+    }
+};
+
+// Torque r x f, in FP32 when the force law ran in FP32.
 template <bool FP32>
-__device__ __forceinline__ bool eval_entry(const DevScene &S, uint32_t s, uint32_t c, const double4 &Ps,
-                                           const double4 *kin_c, int64_t e, uint32_t t, double tnow,
-                                           double *h_io, bool rec, double *Fs, double *Ts) {
-    double u_old[3] = {h_io[0], h_io[1], h_io[2]};
-    double u_new[3];
-    double Fd[3];
-    double rs[3];           // lever arm of s
-    bool contact;
-    double delta = 0.0;
+__device__ __forceinline__ void torque(const double *r, const double *f, double *t) {
+    if (!FP32) {
+        cross3(r, f, t);
+    } else {
+        float rf[3] = {(float)r[0], (float)r[1], (float)r[2]}, ff[3] = {(float)f[0], (float)f[1], (float)f[2]}, tf[3];
+        cross3f(rf, ff, tf);
+        t[0] = tf[0]; t[1] = tf[1]; t[2] = tf[2];
+    }
+}
+
+// Evaluate candidate pair p of the active set once, for both bodies: entry e
+// is the lower sphere's row entry, mirror[e] the higher sphere's; a boundary
+// pair has the sphere as body b.  Writes the history at e, the contribution
+// and flag of each sphere's entry, and returns the contact sides it created.
+template <bool FP32>
+__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const uint32_t *nb, double *hist,
+                                              double tnow, bool rec) {
+    const uint32_t s = S.eself[e], t = nb[e];
+    double *h = hist + 3 * e;
     if (t < (uint32_t)S.ns) {
-        bool s_is_a = s < t;
-        uint32_t a = s_is_a ? s : t, b = s_is_a ? t : s;
-        double4 Pa = s_is_a ? Ps : S.spos[a];
-        double4 Pb = s_is_a ? S.spos[b] : Ps;
+        const uint32_t a = s, b = t;  // a < b by construction of the pair list
+        const int64_t m = S.emirror[e];
+        double4 Pa = S.spos[a], Pb = S.spos[b];
         double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y, dz = Pb.z - Pa.z;
         double d2 = dx * dx + dy * dy + dz * dz;
         double Sr = Pa.w + Pb.w;
-        contact = d2 < Sr * Sr;
-        if (!contact) {
-            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
-            return false;
+        if (!(d2 < Sr * Sr)) {  // a false positive of the enlarged geometry: no force, no history
+            S.eflag[e] = 0;
+            S.eflag[m] = 0;
+            if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
+            if (rec) S.rec_state[e] = 0;
+            return 0;
         }
-        uint32_t ca = s_is_a ? c : S.owner[a], cb = s_is_a ? S.owner[b] : c;
-        const double4 *ka = s_is_a ? kin_c : S.kin + 3 * (int64_t)ca;
-        const double4 *kb = s_is_a ? S.kin + 3 * (int64_t)cb : kin_c;
-        double4 xa = ka[0], va = ka[1], wa = ka[2];
-        double4 xb = kb[0], vb = kb[1], wb = kb[2];
         double d = sqrt(d2);
-        delta = Sr - d;
+        double delta = Sr - d;
+        if (!(delta > 0.0)) {
+            S.eflag[e] = 0;
+            S.eflag[m] = 0;
+            h[0] = 0.0; h[1] = 0.0; h[2] = 0.0;
+            if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
+            return 0;
+        }
+        const uint32_t ca = S.owner[a], cb = S.owner[b];
+        const double4 *ka = S.kin + 3 * (int64_t)ca, *kbp = S.kin + 3 * (int64_t)cb;
+        double4 xa = ka[0], va = ka[1], wa = ka[2];
+        double4 xb = kbp[0], vb = kbp[1], wb = kbp[2];
         double n[3] = {dx / d, dy / d, dz / d};
         double lever = Pa.w - 0.5 * delta;
         double p[3] = {Pa.x + lever * n[0], Pa.y + lever * n[1], Pa.z + lever * n[2]};
         double ra[3] = {p[0] - xa.x, p[1] - xa.y, p[2] - xa.z};
         double rb[3] = {p[0] - xb.x, p[1] - xb.y, p[2] - xb.z};
-        // lever arm of s: from its own clump's CoM (equals ra or rb exactly)
-        rs[0] = p[0] - kin_c[0].x; rs[1] = p[1] - kin_c[0].y; rs[2] = p[2] - kin_c[0].z;
-        if (!(delta > 0.0)) {
-            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
-            if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
-            return false;
-        }
-        // contact kinematics in FP64 (the relative velocity of two similar
-        // velocities cancels); only the force law drops to FP32 when asked
+        // contact kinematics in FP64 (relative velocities of similar speeds cancel)
         double wva[3] = {wa.x, wa.y, wa.z}, wvb[3] = {wb.x, wb.y, wb.z}, ca3[3], cb3[3];
         cross3(wva, ra, ca3);
         cross3(wvb, rb, cb3);
         double vrel[3] = {(vb.x + cb3[0]) - (va.x + ca3[0]), (vb.y + cb3[1]) - (va.y + ca3[1]),
                           (vb.z + cb3[2]) - (va.z + ca3[2])};
+        double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
         if (!FP32) {
             double Rbar = (Pa.w * Pb.w) / (Pa.w + Pb.w);
             double mbar = (xa.w * xb.w) / (xa.w + xb.w);
             double4 ma = S.mat64[a], mb = S.mat64[b];
-            double estar = 1.0 / (ma.x + mb.x), gstar = 1.0 / (ma.y + mb.y);
-            law64(n, delta, vrel, Rbar, mbar, estar, gstar, fmin(ma.z, mb.z), fmin(ma.w, mb.w), S.h, u_old, Fd, u_new);
+            law64(n, delta, vrel, Rbar, mbar, 1.0 / (ma.x + mb.x), 1.0 / (ma.y + mb.y), fmin(ma.z, mb.z),
+                  fmin(ma.w, mb.w), S.h, u_old, F, u_new);
         } else {
             float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
             float Ra = (float)Pa.w, Rb = (float)Pb.w, Ma = (float)xa.w, Mb = (float)xb.w;
-            float Rbar = (Ra * Rb) / (Ra + Rb), mbar = (Ma * Mb) / (Ma + Mb);
             float4 ma = S.mat32[a], mb = S.mat32[b];
             float Ff[3];
-            law32(n, delta, vrf, Rbar, mbar, 1.0f / (ma.x + mb.x), 1.0f / (ma.y + mb.y), fminf(ma.z, mb.z),
-                  fminf(ma.w, mb.w), S.h, u_old, Ff, u_new);
-            Fd[0] = Ff[0]; Fd[1] = Ff[1]; Fd[2] = Ff[2];
+            law32(n, delta, vrf, (Ra * Rb) / (Ra + Rb), (Ma * Mb) / (Ma + Mb), 1.0f / (ma.x + mb.x),
+                  1.0f / (ma.y + mb.y), fminf(ma.z, mb.z), fminf(ma.w, mb.w), S.h, u_old, Ff, u_new);
+            F[0] = Ff[0]; F[1] = Ff[1]; F[2] = Ff[2];
         }
+        h[0] = u_new[0]; h[1] = u_new[1]; h[2] = u_new[2];
+        double fa[3] = {-F[0], -F[1], -F[2]}, ta[3], tb[3];
+        torque<FP32>(ra, fa, ta);
+        torque<FP32>(rb, F, tb);
+        Contrib<FP32>::put(S.cA, S.cB, e, fa, ta);
+        Contrib<FP32>::put(S.cA, S.cB, m, F, tb);
+        S.eflag[e] = 1;
+        S.eflag[m] = 1;
         if (rec) {
             S.rec_state[e] = 1; S.rec_delta[e] = delta;
-            S.rec_F[3 * e] = Fd[0]; S.rec_F[3 * e + 1] = Fd[1]; S.rec_F[3 * e + 2] = Fd[2];
+            S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
         }
-        if (s_is_a) { Fd[0] = -Fd[0]; Fd[1] = -Fd[1]; Fd[2] = -Fd[2]; }
-    } else {
-        const Bnd &B = S.bnd[t - (uint32_t)S.ns];
-        double phi, n[3];
-        contact = bnd_distance(B, tnow, Ps.x, Ps.y, Ps.z, phi, n) && phi < Ps.w;
-        if (!contact) {
-            h_io[0] = 0.0; h_io[1] = 0.0; h_io[2] = 0.0;
-            return false;
-        }
-        double R = Ps.w;
-        delta = R - phi;
-        double lever = R - 0.5 * delta;
-        double p[3] = {Ps.x - lever * n[0], Ps.y - lever * n[1], Ps.z - lever * n[2]};
-        double4 xc = kin_c[0], vc = kin_c[1], wc = kin_c[2];
-        double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
-        double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
-        double rb[3] = {p[0] - xc.x, p[1] - xc.y, p[2] - xc.z};
-        for (int i = 0; i < 3; i++) rs[i] = rb[i];
-        double pw[3], cb3[3], wv3[3] = {wc.x, wc.y, wc.z};
-        cross3(B.omg, ra, pw);
-        cross3(wv3, rb, cb3);
-        double wv[3] = {B.vel[0] + pw[0], B.vel[1] + pw[1], B.vel[2] + pw[2]};
-        double vrel[3] = {(vc.x + cb3[0]) - wv[0], (vc.y + cb3[1]) - wv[1], (vc.z + cb3[2]) - wv[2]};
-        if (!FP32) {
-            double4 ms = S.mat64[s];
-            law64(n, delta, vrel, R, xc.w, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z),
-                  fmin(B.beta, ms.w), S.h, u_old, Fd, u_new);
-        } else {
-            float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
-            float4 ms = S.mat32[s];
-            float Ff[3];
-            law32(n, delta, vrf, (float)R, (float)xc.w, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y),
-                  fminf(B.muf, ms.z), fminf(B.betaf, ms.w), S.h, u_old, Ff, u_new);
-            Fd[0] = Ff[0]; Fd[1] = Ff[1]; Fd[2] = Ff[2];
-        }
-        if (rec) {
-            S.rec_state[e] = 1; S.rec_delta[e] = delta;
-            S.rec_F[3 * e] = Fd[0]; S.rec_F[3 * e + 1] = Fd[1]; S.rec_F[3 * e + 2] = Fd[2];
-        }
+        return 2;
     }
-    h_io[0] = u_new[0]; h_io[1] = u_new[1]; h_io[2] = u_new[2];
-    double tq[3];
-    if (!FP32) {
-        cross3(rs, Fd, tq);
-    } else {
-        float rf[3] = {(float)rs[0], (float)rs[1], (float)rs[2]}, ff[3] = {(float)Fd[0], (float)Fd[1], (float)Fd[2]}, tf[3];
-        cross3f(rf, ff, tf);
-        tq[0] = tf[0]; tq[1] = tf[1]; tq[2] = tf[2];
-    }
-    for (int i = 0; i < 3; i++) { Fs[i] = Fs[i] + Fd[i]; Ts[i] = Ts[i] + tq[i]; }
-    return true;
-}
-
-// Sum of the contact forces and torques on sphere s over its row (ascending partner id).
-template <bool FP32>
-__device__ __forceinline__ uint32_t sphere_sum(const DevScene &S, uint32_t s, uint32_t c, const double4 *kin_c, double tnow, bool rec,
-                               double *Fs, double *Ts) {
-    uint32_t ncont = 0;
-    const int cur = S.ctl->buf;
-    uint32_t beg = pick(S.row_beg, cur)[s], cnt = pick(S.row_cnt, cur)[s];
-    const uint32_t *nb = pick(S.nbr, cur);
-    double *hs = pick(S.hist, cur);
+    // boundary pair: the boundary is body a, sphere s is body b
+    const Bnd &B = S.bnd[t - (uint32_t)S.ns];
     double4 Ps = S.spos[s];
-    for (uint32_t k = 0; k < cnt; k++) {
-        int64_t e = (int64_t)beg + k;
+    double phi, n[3];
+    bool contact = bnd_distance(B, tnow, Ps.x, Ps.y, Ps.z, phi, n) && phi < Ps.w;
+    if (!contact) {
+        S.eflag[e] = 0;
+        if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
         if (rec) S.rec_state[e] = 0;
-        double h3[3] = {hs[3 * e], hs[3 * e + 1], hs[3 * e + 2]};
-        double h0[3] = {h3[0], h3[1], h3[2]};
-        ncont += eval_entry<FP32>(S, s, c, Ps, kin_c, e, nb[e], tnow, h3, rec, Fs, Ts) ? 1u : 0u;
-        // store only when a bit changed (false positives keep a zero history untouched)
-        if (__double_as_longlong(h3[0]) != __double_as_longlong(h0[0]) ||
-            __double_as_longlong(h3[1]) != __double_as_longlong(h0[1]) ||
-            __double_as_longlong(h3[2]) != __double_as_longlong(h0[2])) {
-            hs[3 * e] = h3[0]; hs[3 * e + 1] = h3[1]; hs[3 * e + 2] = h3[2];
-        }
+        return 0;
     }
-    return ncont;
+    double R = Ps.w;
+    double delta = R - phi;
+    double lever = R - 0.5 * delta;
+    double p[3] = {Ps.x - lever * n[0], Ps.y - lever * n[1], Ps.z - lever * n[2]};
+    const double4 *kc = S.kin + 3 * (int64_t)S.owner[s];
+    double4 xc = kc[0], vc = kc[1], wc = kc[2];
+    double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
+    double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
+    double rb[3] = {p[0] - xc.x, p[1] - xc.y, p[2] - xc.z};
+    double pw[3], cb3[3], wv3[3] = {wc.x, wc.y, wc.z};
+    cross3(B.omg, ra, pw);
+    cross3(wv3, rb, cb3);
+    double wv[3] = {B.vel[0] + pw[0], B.vel[1] + pw[1], B.vel[2] + pw[2]};
+    double vrel[3] = {(vc.x + cb3[0]) - wv[0], (vc.y + cb3[1]) - wv[1], (vc.z + cb3[2]) - wv[2]};
+    double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
+    if (!FP32) {
+        double4 ms = S.mat64[s];
+        law64(n, delta, vrel, R, xc.w, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z), fmin(B.beta, ms.w),
+              S.h, u_old, F, u_new);
+    } else {
+        float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
+        float4 ms = S.mat32[s];
+        float Ff[3];
+        law32(n, delta, vrf, (float)R, (float)xc.w, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y), fminf(B.muf, ms.z),
+              fminf(B.betaf, ms.w), S.h, u_old, Ff, u_new);
+        F[0] = Ff[0]; F[1] = Ff[1]; F[2] = Ff[2];
+    }
+    h[0] = u_new[0]; h[1] = u_new[1]; h[2] = u_new[2];
+    double tb[3];
+    torque<FP32>(rb, F, tb);
+    Contrib<FP32>::put(S.cA, S.cB, e, F, tb);
+    S.eflag[e] = 1;
+    if (rec) {
+        S.rec_state[e] = 1; S.rec_delta[e] = delta;
+        S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
+    }
+    return 1;
 }
 
 // Wave-level sum, one atomic per wavefront.
@@ -671,6 +805,43 @@ __device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
     unsigned long long v = n;
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)&ctl->contacts_acc, v);
+}
+
+// Every candidate pair of the active set, one lane per pair (grid-stride).
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_pairs(DevScene S) {
+    if (aborted(S.ctl)) return;
+    const int cur = S.ctl->buf;
+    const uint32_t *nb = pick(S.nbr, cur);
+    double *hist = pick(S.hist, cur);
+    const int64_t np = S.ctl->n_pairs_cur;
+    const bool rec = S.ctl->record != 0;
+    const double tnow = (double)S.ctl->step * S.h;
+    uint32_t ncont = 0;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += (int64_t)gridDim.x * blockDim.x) {
+        int64_t i = base + threadIdx.x;
+        if (i < np) ncont += eval_pair<FP32>(S, (int64_t)S.pairs[i], nb, hist, tnow, rec);
+    }
+    count_contacts(S.ctl, ncont);
+}
+
+// Sum of the flagged contributions in sphere s's row, ascending partner id.
+template <bool FP32>
+__device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, const uint32_t *rbeg, const uint32_t *rcnt,
+                                           double *Fs, double *Ts) {
+    using A = typename Contrib<FP32>::A;
+    using B = typename Contrib<FP32>::B;
+    const A *cA = (const A *)S.cA;
+    const B *cB = (const B *)S.cB;
+    uint32_t beg = rbeg[s], cnt = rcnt[s];
+    for (uint32_t k = 0; k < cnt; k++) {
+        int64_t e = (int64_t)beg + k;
+        if (!S.eflag[e]) continue;
+        A a = cA[e];
+        B b = cB[e];
+        Fs[0] = Fs[0] + (double)a.x; Fs[1] = Fs[1] + (double)a.y; Fs[2] = Fs[2] + (double)a.z;
+        Ts[0] = Ts[0] + (double)a.w; Ts[1] = Ts[1] + (double)b.x; Ts[2] = Ts[2] + (double)b.y;
+    }
 }
 
 // Symplectic Euler of one clump from its total force and torque (world frame).
@@ -728,7 +899,9 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
           isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
         S.ctl->nonfinite = 1;
-    return (float)acc_env * 1.000001f;
+    float aenv = (float)acc_env * 1.000001f;
+    if (S.store_acc) S.cacc[c] = aenv;
+    return aenv;
 }
 
 __device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
@@ -739,11 +912,11 @@ __device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
 
 // One lane per sphere.  Waves are scheduled on clump boundaries (wave w
 // covers the whole clumps wave_clump0[2w] .. wave_clump0[2w+1]-1, at most 64
-// spheres), so the spheres of a clump sit in adjacent lanes: the clump's first
-// lane sums their forces and torques in ascending sphere id by shuffles, adds
-// gravity and integrates the clump.
+// spheres), so the spheres of a clump sit in adjacent lanes: each lane sums its
+// sphere's row, then the clump's first lane sums its spheres in ascending id by
+// shuffles, adds gravity and integrates the clump.
 template <bool FP32>
-__global__ void __launch_bounds__(256) k_force_waves(DevScene S) {
+__global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     if (aborted(S.ctl)) return;
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -752,27 +925,22 @@ __global__ void __launch_bounds__(256) k_force_waves(DevScene S) {
     const int64_t S0 = S.sbeg[c0], S1 = S.sbeg[c1];
     const int64_t s = S0 + lane;
     const bool active = s < S1;
+    const int cur = S.ctl->buf;
     const bool rec = S.ctl->record != 0;
-    const double tnow = (double)S.ctl->step * S.h;
     double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-    uint32_t ncont = 0;
     int64_t c = 0, cb = 0;
     int cnt = 0;
     if (active) {
         c = S.owner[s];
         cb = S.sbeg[c];
         cnt = (int)(S.sbeg[c + 1] - cb);
-        ncont = sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, S.kin + 3 * c, tnow, rec, Fs, Ts);
+        sphere_sum<FP32>(S, (uint32_t)s, pick(S.row_beg, cur), pick(S.row_cnt, cur), Fs, Ts);
     }
-    count_contacts(S.ctl, ncont);
     const bool leader = active && s == cb;
-    // longest clump of the wave: the number of shuffle rounds
-    int mx = leader ? cnt : 0;
+    int mx = leader ? cnt : 0;  // longest clump of the wave: the number of shuffle rounds
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-    double Fc[3] = {Fs[0], Fs[1], Fs[2]}, Tc[3] = {Ts[0], Ts[1], Ts[2]};
-    if (leader) {  // the clump sum starts from zero, as in the reference order
-        for (int i = 0; i < 3; i++) { Fc[i] = 0.0 + Fs[i]; Tc[i] = 0.0 + Ts[i]; }
-    }
+    double Fc[3], Tc[3];
+    for (int i = 0; i < 3; i++) { Fc[i] = 0.0 + Fs[i]; Tc[i] = 0.0 + Ts[i]; }
     for (int j = 1; j < mx; j++) {
         int src = min(lane + j, 63);
         double f0 = __shfl(Fs[0], src, 64), f1 = __shfl(Fs[1], src, 64), f2 = __shfl(Fs[2], src, 64);
@@ -793,52 +961,17 @@ __global__ void __launch_bounds__(256) k_force_waves(DevScene S) {
     if (S.detect_mode != 0) wave_max_acc(S, acc);
 }
 
-template <bool FP32>
-__global__ void __launch_bounds__(256) k_force_integrate(DevScene S) {
-    if (aborted(S.ctl)) return;
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t ncont = 0;
-    float acc = 0.0f;
-    bool active = c < S.nc;
-    int64_t s0 = 0, s1 = 0;
-    if (active) {
-        s0 = S.sbeg[c];
-        s1 = S.sbeg[c + 1];
-        active = s1 - s0 <= kBigClump;  // big clumps go through k_force_big_spheres
-    }
-    if (active) {
-        bool rec = S.ctl->record != 0;
-        double tnow = (double)S.ctl->step * S.h;
-        const double4 *kin_c = S.kin + 3 * c;
-        double Fc[3] = {0.0, 0.0, 0.0}, Tc[3] = {0.0, 0.0, 0.0};
-        for (int64_t s = s0; s < s1; s++) {
-            double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-            ncont += sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, kin_c, tnow, rec, Fs, Ts);
-            for (int i = 0; i < 3; i++) { Fc[i] = Fc[i] + Fs[i]; Tc[i] = Tc[i] + Ts[i]; }
-        }
-        const Grid &g = S.grids[S.clump_scene[c]];
-        double M = S.mass[c];
-        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
-        if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
-        acc = integrate_clump(S, c, Fc, Tc);
-    }
-    count_contacts(S.ctl, ncont);  // every lane of the wavefront takes part
-    if (S.detect_mode != 0) wave_max_acc(S, acc);
-}
-
 // Clumps with many spheres (a wheel): per-sphere sums first, then one workgroup
 // per clump reduces them in a fixed tree order and integrates.
 template <bool FP32>
-__global__ void __launch_bounds__(256) k_force_big_spheres(DevScene S) {
+__global__ void __launch_bounds__(256) k_reduce_big_spheres(DevScene S) {
     if (aborted(S.ctl)) return;
     int32_t c = S.big_list[blockIdx.y];
     int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
-    bool rec = S.ctl->record != 0;
-    double tnow = (double)S.ctl->step * S.h;
+    const int cur = S.ctl->buf;
     for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += (int64_t)gridDim.x * blockDim.x) {
         double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-        uint32_t nct = sphere_sum<FP32>(S, (uint32_t)s, (uint32_t)c, S.kin + 3 * (int64_t)c, tnow, rec, Fs, Ts);
-        if (nct) atomicAdd((unsigned long long *)&S.ctl->contacts_acc, (unsigned long long)nct);
+        sphere_sum<FP32>(S, (uint32_t)s, pick(S.row_beg, cur), pick(S.row_cnt, cur), Fs, Ts);
         for (int i = 0; i < 3; i++) { S.sF[3 * s + i] = Fs[i]; S.sT[3 * s + i] = Ts[i]; }
     }
 }
@@ -992,11 +1125,14 @@ __global__ void k_audit_end(DevScene S) {
 
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+// grid of a grid-stride kernel over at most n items (the count lives on the device)
+static inline unsigned stride_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
 
 const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_count", "k_scan_reduce",
                                            "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
-                                           "k_detect_end", "k_force_waves", "k_force_big_spheres",
-                                           "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells"};
+                                           "k_detect_end", "k_pairs", "k_reduce_big_spheres",
+                                           "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
+                                           "k_mirror", "k_reduce_waves", "k_bin_features", "k_bin_margin"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1024,6 +1160,11 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
     unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
     TIMED(K_DETECT_BEGIN, hipLaunchKernelGGL(k_detect_begin, dim3(zb), dim3(256), 0, st, S, which));
     TIMED(K_CELL_COUNT, hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
+    if (which == 2 || (which == 0 && S.detect_mode == 2)) {
+        TIMED(K_BIN_FEATURES, hipLaunchKernelGGL(k_bin_features, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
+        if (which == 2) return;  // capture needs bins and features only
+        TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(stride_blocks(S.n_cells)), dim3(256), 0, st, S));
+    }
     int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
     // the block-sum scratch lives after the cell arrays (allocated by the runtime)
     uint32_t *bsum = S.cell_fill + S.n_cells;
@@ -1040,7 +1181,24 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
     binning(S, 0, st);
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+    TIMED(K_MIRROR, hipLaunchKernelGGL(k_mirror, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_begin(const DevScene &S, hipStream_t st) {
+    binning(S, 2, st);
+    hipLaunchKernelGGL(k_collect_init, dim3(stride_blocks(std::max<int64_t>(S.ns, S.n_cells))), dim3(256), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_speed(const DevScene &S, hipStream_t st) {
+    if (S.ns) hipLaunchKernelGGL(k_collect_speed, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_acc(const DevScene &S, hipStream_t st) {
+    if (S.ns) hipLaunchKernelGGL(k_collect_acc, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S);
     return hipGetLastError();
 }
 
@@ -1054,18 +1212,19 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
 
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
+    const bool f32 = S.precision == 1;
+    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
+    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
     if (wb) {
-        if (S.precision == 1)
-            TIMED(K_FORCE, hipLaunchKernelGGL(k_force_waves<true>, dim3(wb), dim3(256), 0, st, S));
-        else
-            TIMED(K_FORCE, hipLaunchKernelGGL(k_force_waves<false>, dim3(wb), dim3(256), 0, st, S));
+        if (f32) TIMED(K_REDUCE, hipLaunchKernelGGL(k_reduce_waves<true>, dim3(wb), dim3(256), 0, st, S));
+        else TIMED(K_REDUCE, hipLaunchKernelGGL(k_reduce_waves<false>, dim3(wb), dim3(256), 0, st, S));
     }
     if (S.n_big) {
-        if (S.precision == 1)
-            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_force_big_spheres<true>, dim3(64, S.n_big), dim3(256), 0, st, S));
+        if (f32)
+            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_reduce_big_spheres<true>, dim3(64, S.n_big), dim3(256), 0, st, S));
         else
-            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_force_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
+            TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_reduce_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
         TIMED(K_INTEGRATE_BIG, hipLaunchKernelGGL(k_integrate_big, dim3(S.n_big), dim3(256), 0, st, S));
     }
     return hipGetLastError();

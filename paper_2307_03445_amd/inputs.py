@@ -658,7 +658,8 @@ def cfg5_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05,
 
 
 def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
-            bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True) -> SceneDesc:
+            bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True,
+            wheel_x: float = 1.0) -> SceneDesc:
     """Configuration 5 (the metric's workload), tiled from a settled patch.
 
     ``patch_x``/``patch_q`` are the settled clump poses of
@@ -699,7 +700,7 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
         wt = wheel_template(wheel_spheres)
         templates.append(wt)
         R, wr = 0.25, float(wt[1][0])
-        cx, cy = 1.0, bed[1] / 2
+        cx, cy = wheel_x, bed[1] / 2
         # column heights of the patch surface (the bed repeats the patch)
         Rm = quat_matrix(qp)
         P = np.concatenate([xp[k] + tmpls[ct_p[k]][0] @ Rm[k].T for k in range(len(ct_p))])

@@ -1,0 +1,113 @@
+"""The envelope MLP's HIP kernels against the FP64 reference, and the learned
+detection interval: zero missed contacts (trajectory identical to per-step
+detection), fallback on unusable predictions, and what it gains over the
+fixed-margin rule."""
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+from paper_2307_03445_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _data(n=3000, seed=0):
+    g = np.random.default_rng(seed)
+    f = np.stack([g.lognormal(-3, 1.5, n), g.lognormal(3, 2, n), g.integers(0, 40, n).astype(float)], 1)
+    y = np.stack([np.log(f[:, 0] * 1.3 + 1e-6), np.log(f[:, 1] * 2 + 1e-3)], 1) + g.normal(0, 0.3, (n, 2))
+    return f.astype(np.float32), y.astype(np.float32)
+
+
+def _params(seed=1):
+    g = np.random.default_rng(seed)
+    p = M.init_params(g, mu=(-3.0, 3.0, 2.5), sig=(1.5, 2.0, 1.0))
+    p[M.OFF_B1:M.OFF_W2] = g.normal(0, 0.2, M.H)
+    p[M.OFF_B2:M.OFF_W3] = g.normal(0, 0.2, M.H)
+    return p.astype(np.float32)
+
+
+def test_forward_matches_fp64_reference():
+    from paper_2307_03445_amd import _lib
+    torch = _torch()
+    f, _ = _data()
+    p = _params()
+    out = _lib.mlp_forward(torch.tensor(p, device="cuda"), torch.tensor(f, device="cuda")).cpu().numpy()
+    ref, _ = M.forward(p.astype(np.float64), f.astype(np.float64))
+    assert np.abs(out - ref).max() <= 1e-4 * max(1.0, np.abs(ref).max())
+
+
+def test_backward_matches_fp64_reference_and_is_deterministic():
+    from paper_2307_03445_amd import _lib
+    torch = _torch()
+    f, y = _data()
+    p = _params()
+    pt, ft, yt = (torch.tensor(a, device="cuda") for a in (p, f, y))
+    g1, l1 = _lib.mlp_backward(pt, ft, yt, 0.99)
+    g2, l2 = _lib.mlp_backward(pt, ft, yt, 0.99)
+    assert torch.equal(g1, g2) and torch.equal(l1, l2)
+    Lref, gref = M.loss_and_grad(p.astype(np.float64), f.astype(np.float64), y.astype(np.float64), 0.99)
+    g = g1.cpu().numpy()
+    assert abs(float(l1.item()) - Lref) <= 1e-4 * abs(Lref)
+    assert np.abs(g - gref).max() <= 1e-4 * np.abs(gref).max(), np.abs(g - gref).max() / np.abs(gref).max()
+
+
+def test_adam_step_matches_definition():
+    from paper_2307_03445_amd import _lib
+    torch = _torch()
+    g = np.random.default_rng(4)
+    p = _params()
+    grad = g.normal(0, 1e-2, p.size).astype(np.float32)
+    m = g.normal(0, 1e-3, p.size).astype(np.float32)
+    v = np.abs(g.normal(0, 1e-4, p.size)).astype(np.float32)
+    pt, gt, mt, vt = (torch.tensor(a, device="cuda") for a in (p, grad, m, v))
+    _lib.mlp_adam(pt, gt, mt, vt, 3, lr=1e-2)
+    b1, b2, t = 0.9, 0.999, 3
+    m2 = b1 * m + (1 - b1) * grad
+    v2 = b2 * v + (1 - b2) * grad * grad
+    ref = p - 1e-2 * (m2 / (1 - b1 ** t)) / (np.sqrt(v2 / (1 - b2 ** t)) + 1e-8)
+    ref[:6] = p[:6]
+    assert np.allclose(pt.cpu().numpy(), ref, rtol=1e-5, atol=1e-7)
+
+
+def _scene(desc, prec="fp32"):
+    from paper_2307_03445_amd._lib import Scene
+    return Scene(desc, precision=prec)
+
+
+def test_learned_detection_equals_plain_and_falls_back():
+    """Learned margins (any weights) keep the trajectory identical to per-step
+    detection; unusable predictions fall back to the fixed rule per bin."""
+    d = I.config1(dense=True)
+    plain = _scene(d)
+    plain.step(150)
+    for params, expect_fallback in ((_params(), False), (np.full(M.N_PARAM, 50.0, np.float32), True)):
+        params = params.copy()
+        params[3:6] = np.abs(params[3:6]) + 0.5
+        sc = _scene(d)
+        sc.set_mlp(params)
+        sc.set_detection("learned", k_max=20, safety=1.5, margin_cap=1e-4, audit_period=10)
+        sc.step(150)
+        c = sc.counts()
+        assert c["missed"] == 0 and c["audits"] >= 14
+        assert (c["fallbacks"] > 0) == expect_fallback, c
+        sp, sl = plain.state(), sc.state()
+        for k in sp:
+            assert np.array_equal(sp[k], sl[k]), k
+
+
+def test_collect_envelopes_labels_cover_features():
+    d = I.config1(dense=True)
+    sc = _scene(d)
+    sc.step(10)
+    f, y = sc.collect_envelopes(20)
+    assert len(f) > 100 and f.shape == (len(f), 3) and y.shape == (len(f), 2)
+    assert np.all(f[:, 2] >= 1)
+    # the label is the max over the horizon, which includes speeds at least
+    # as large as those right after the capture; it is finite everywhere
+    assert np.all(np.isfinite(y))
+    assert sc.counts()["steps"] == 10 + 1 + 20

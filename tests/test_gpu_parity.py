@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     """libcdem.so loads and exports every function include/cdem.h declares (no GPU call)."""
     from paper_2307_03445_amd import _lib
     hdr = open(os.path.join(ROOT, "include", "cdem.h")).read()
-    names = set(re.findall(r"^\s*(?:int|const char \*|void)\s*(cdem_\w+)\s*\(", hdr, re.M))
+    names = set(re.findall(r"^\s*(?:int|const char \*|void|size_t)\s*(cdem_\w+)\s*\(", hdr, re.M))
     assert len(names) >= 15
     L = _lib.load()
     for n in names:
