@@ -182,6 +182,20 @@ int cdem_set_detection(cdem_scene *s, const cdem_detect_params *p);
  * cdem_read_contacts. */
 int cdem_record_next_step(cdem_scene *s, int on);
 
+/* Run steps as replays of a captured HIP graph of `steps_per_graph` steps
+ * (0 = launch kernel by kernel).  Detection scheduling lives on the device, so
+ * one captured sequence serves every step; the graph is re-captured whenever
+ * the scene's launch parameters change (regrow, detection settings, tuning).
+ * Results are identical either way. */
+int cdem_set_graph(cdem_scene *s, int32_t steps_per_graph);
+
+/* Autotuner: time `steps` steps for each candidate bin-size factor (bins of
+ * 1, 1.25 or 1.5 times the minimum 2 (R_max + margin cap)) and launch shape of
+ * the grid-stride kernels, and keep the fastest.  The tuning steps are
+ * ordinary steps of the simulation (results do not depend on the choice).
+ * *bin_factor and *stride_cap (may be NULL) receive the choice. */
+int cdem_autotune(cdem_scene *s, int32_t steps, double *bin_factor, int32_t *stride_cap);
+
 /* ---- reads and writes (synchronous) ---- */
 int cdem_get_counts(cdem_scene *s, cdem_counts *c);
 int cdem_read_state(cdem_scene *s, const cdem_state_view *v, int where);

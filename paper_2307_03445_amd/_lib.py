@@ -101,6 +101,8 @@ SIGNATURES = {
     "cdem_mlp_backward": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P, P]),
     "cdem_mlp_adam": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, P]),
     "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
+    "cdem_set_graph": (C.c_int, [P, C.c_int32]),
+    "cdem_autotune": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
 }
 
 _lib = None
@@ -295,6 +297,14 @@ class Scene:
         v = C.c_int64(0)
         self._check(self._L.cdem_last_step_contacts(self._h, C.byref(v)))
         return v.value
+
+    def set_graph(self, steps_per_graph: int):
+        self._check(self._L.cdem_set_graph(self._h, int(steps_per_graph)))
+
+    def autotune(self, steps: int = 5):
+        f, c = C.c_double(0), C.c_int32(0)
+        self._check(self._L.cdem_autotune(self._h, int(steps), C.byref(f), C.byref(c)))
+        return dict(bin_factor=f.value, stride_cap=c.value)
 
     # ---------------------------------------------------------------- learned envelopes
     def set_mlp(self, params):

@@ -69,6 +69,12 @@ struct EventTimer : KernelTimer {
 
 struct cdem_scene {
     EventTimer *timer = nullptr;
+    // graph replay
+    int32_t graph_steps = 0;
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    DevScene gkey{};               // launch parameters the graph was captured with
+    double bin_factor = 1.0;       // bins are bin_factor x the minimum size
     bool test_no_guard = false;   // testing aid: deferred detection without the displacement guard
     bool collecting = false;      // cdem_collect_envelopes in progress
     std::string err;
@@ -105,6 +111,8 @@ extern "C" const char *cdem_strerror(int code) {
 static std::string g_create_err = "no error";
 
 extern "C" const char *cdem_last_error(const cdem_scene *s) { return s ? s->err.c_str() : g_create_err.c_str(); }
+
+static void drop_graph(cdem_scene *sc);
 
 static int fail(cdem_scene *s, int code, const std::string &msg) {
     if (s) s->err = msg;
@@ -164,7 +172,7 @@ static bool finite_all(const double *p, size_t n) {
 // allocate the bin arrays when they grow.
 static int build_grids(cdem_scene *sc) {
     DevScene &S = sc->S;
-    double b = 2.0 * (sc->rmax + std::max(0.0, sc->det.margin_cap));
+    double b = 2.0 * (sc->rmax + std::max(0.0, sc->det.margin_cap)) * sc->bin_factor;
     if (!(b > 0.0)) b = 1.0;  // no spheres: any positive bin size will do
     int64_t cell0 = 0;
     for (int k = 0; k < S.n_scenes; k++) {
@@ -428,6 +436,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         wsched.push_back((int32_t)c);
     }
     S.n_waves = (int64_t)wsched.size() / 2;
+    S.stride_cap = 16384;
     S.plan.k_max = 1; S.plan.audit_period = 0; S.plan.safety = 1.5f;
     S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
     // ---- device arrays
@@ -532,6 +541,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
 extern "C" int cdem_destroy(cdem_scene *sc) {
     if (!sc) return CDEM_E_INVALID;
     (void)hipStreamSynchronize(sc->stream);
+    drop_graph(sc);
+    if (sc->gstream) { (void)hipStreamSynchronize(sc->gstream); (void)hipStreamDestroy(sc->gstream); }
     delete sc->timer;
     sc->timer = nullptr;
     auto owned = sc->owned;
@@ -552,26 +563,64 @@ static int write_ctl(cdem_scene *sc, const Ctl &c) {
     return CDEM_OK;
 }
 
-static int enqueue_steps(cdem_scene *sc, int64_t n) {
+// Enqueue the kernels of n steps on st (timed when a timer is set and we are
+// not capturing a graph).
+static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing) {
     const DevScene &S = sc->S;
     int guard = S.detect_mode != CDEM_DETECT_PLAIN && !sc->test_no_guard;
-    g_timer = sc->timer;
+    g_timer = capturing ? nullptr : sc->timer;
     for (int64_t i = 0; i < n; i++) {
-        hipError_t e = launch_pose(S, guard, sc->stream);
-        if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, sc->stream);
-        if (e == hipSuccess) e = launch_detect(S, sc->stream);
-        if (e == hipSuccess) e = launch_audit_binned(S, sc->stream);
-        if (e == hipSuccess) e = launch_force_integrate(S, sc->stream);
-        if (e == hipSuccess && sc->collecting) e = launch_collect_acc(S, sc->stream);
-        if (e == hipSuccess) e = launch_step_end(S, sc->stream);
+        hipError_t e = launch_pose(S, guard, st);
+        if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, st);
+        if (e == hipSuccess) e = launch_detect(S, st);
+        if (e == hipSuccess) e = launch_audit_binned(S, st);
+        if (e == hipSuccess) e = launch_force_integrate(S, st);
+        if (e == hipSuccess && sc->collecting) e = launch_collect_acc(S, st);
+        if (e == hipSuccess) e = launch_step_end(S, st);
         if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
-        if (sc->timer && sc->timer->used > 4096) {  // bound the event pool
-            HIPCHK(hipStreamSynchronize(sc->stream));
+        if (!capturing && sc->timer && sc->timer->used > 4096) {  // bound the event pool
+            HIPCHK(hipStreamSynchronize(st));
             sc->timer->harvest();
         }
     }
     g_timer = nullptr;
     return CDEM_OK;
+}
+
+static void drop_graph(cdem_scene *sc) {
+    if (sc->gexec) (void)hipGraphExecDestroy(sc->gexec);
+    sc->gexec = nullptr;
+}
+
+// Capture graph_steps steps once per set of launch parameters.
+static int ensure_graph(cdem_scene *sc) {
+    if (sc->gexec && memcmp(&sc->gkey, &sc->S, sizeof(DevScene)) == 0) return CDEM_OK;
+    drop_graph(sc);
+    if (!sc->gstream) HIPCHK(hipStreamCreateWithFlags(&sc->gstream, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(sc->gstream, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_on(sc, sc->graph_steps, sc->gstream, true);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(sc->gstream, &g);
+    if (rc) { if (g) (void)hipGraphDestroy(g); return rc; }
+    if (e != hipSuccess) return fail(sc, CDEM_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&sc->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) { sc->gexec = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
+    sc->gkey = sc->S;
+    return CDEM_OK;
+}
+
+static int enqueue_steps(cdem_scene *sc, int64_t n) {
+    // graphs carry no per-kernel events: a timed or collecting run goes eager
+    if (sc->graph_steps <= 0 || sc->timer || sc->collecting || n < sc->graph_steps)
+        return enqueue_on(sc, n, sc->stream, false);
+    int rc = ensure_graph(sc);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    int64_t reps = n / sc->graph_steps;
+    for (int64_t r = 0; r < reps; r++) HIPCHK(hipGraphLaunch(sc->gexec, sc->gstream));
+    HIPCHK(hipStreamSynchronize(sc->gstream));
+    return enqueue_on(sc, n - reps * sc->graph_steps, sc->stream, false);
 }
 
 extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
@@ -945,4 +994,58 @@ extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *fe
     }
     *n = k;
     return restore(CDEM_OK);
+}
+
+extern "C" int cdem_set_graph(cdem_scene *sc, int32_t steps_per_graph) {
+    if (!sc || steps_per_graph < 0 || steps_per_graph > 1000) return fail(sc, CDEM_E_INVALID, "steps per graph 0..1000");
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    drop_graph(sc);
+    sc->graph_steps = steps_per_graph;
+    return CDEM_OK;
+}
+
+extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, int32_t *stride_cap) {
+    if (!sc || steps < 1) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    const double factors[] = {1.0, 1.25, 1.5};
+    const int32_t caps[] = {2048, 8192, 16384};
+    double best = 1e300, bf = sc->bin_factor;
+    int32_t bc = sc->S.stride_cap;
+    int rc = cdem_step(sc, 1, nullptr);  // settle allocations before timing
+    if (rc) return rc;
+    if (!sc->gstream) HIPCHK(hipStreamCreateWithFlags(&sc->gstream, hipStreamNonBlocking));
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (double f : factors) {
+        sc->bin_factor = f;
+        if ((rc = build_grids(sc)) != CDEM_OK) break;
+        for (int32_t cap : caps) {
+            sc->S.stride_cap = cap;
+            Ctl c;
+            if ((rc = read_ctl(sc, c)) != CDEM_OK) break;
+            c.det_due = 1;  // the new bins need a detection
+            if ((rc = write_ctl(sc, c)) != CDEM_OK) break;
+            (void)hipEventRecord(e0, sc->stream);
+            if ((rc = cdem_step(sc, steps, nullptr)) != CDEM_OK) break;
+            (void)hipEventRecord(e1, sc->stream);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) { best = ms; bf = f; bc = cap; }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    sc->bin_factor = bf;
+    sc->S.stride_cap = bc;
+    if ((rc = build_grids(sc)) != CDEM_OK) return rc;
+    Ctl c;
+    if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
+    c.det_due = 1;
+    if ((rc = write_ctl(sc, c)) != CDEM_OK) return rc;
+    if (bin_factor) *bin_factor = bf;
+    if (stride_cap) *stride_cap = bc;
+    return CDEM_OK;
 }

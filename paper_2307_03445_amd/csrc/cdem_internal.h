@@ -145,6 +145,9 @@ struct DevScene {
     // wave_clump0[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
     const int32_t *wave_clump0;
     int64_t n_waves;
+    // launch shape of the grid-stride kernels (tunable; results do not depend on it)
+    int32_t stride_cap;              // maximum workgroups of k_pairs / k_mirror / k_bin_margin
+    int32_t pad3;
 };
 
 // Optional per-kernel timing: when non-null, launchers bracket every kernel

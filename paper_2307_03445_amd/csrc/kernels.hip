@@ -1126,7 +1126,9 @@ __global__ void k_audit_end(DevScene S) {
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // grid of a grid-stride kernel over at most n items (the count lives on the device)
-static inline unsigned stride_blocks(int64_t n) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 16384)); }
+static inline unsigned stride_blocks(int64_t n, int32_t cap = 16384) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap > 0 ? cap : 16384));
+}
 
 const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_count", "k_scan_reduce",
                                            "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
@@ -1181,7 +1183,7 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
     binning(S, 0, st);
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
-    TIMED(K_MIRROR, hipLaunchKernelGGL(k_mirror, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
+    TIMED(K_MIRROR, hipLaunchKernelGGL(k_mirror, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
     return hipGetLastError();
 }
@@ -1213,8 +1215,8 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
     const bool f32 = S.precision == 1;
-    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
-    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(stride_blocks(S.cap)), dim3(256), 0, st, S));
+    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
+    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
     if (wb) {
         if (f32) TIMED(K_REDUCE, hipLaunchKernelGGL(k_reduce_waves<true>, dim3(wb), dim3(256), 0, st, S));

@@ -730,3 +730,87 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
     walls = box_walls((0, 0, 0), (bed[0], bed[1], top + 0.05), (5e7, 0.3, 0.5, 0.5))
     return assemble(templates, CT, X, Q, V, W, mat, (0, 0, -9.81), (0, 0, 0, bed[0], bed[1], top + 0.05),
                     1e-6, bnd=walls, presc=presc, name=f"cfg5-r{replica}")
+
+
+# ---------------------------------------------------------------------------
+# Configuration 4: many independent funnel scenes of uneven size
+# ---------------------------------------------------------------------------
+
+def funnel_scene_parts(g: np.random.Generator, n_clumps: int, template, mu: float, scene: int):
+    """One repose-angle scene: clumps of one template on a lattice inside an
+    upward-opening funnel (half-angle 30 degrees from the vertical, outlet
+    radius 6 bounding radii), a plate 0.2 m below the outlet.  Returns the
+    clump poses, the boundaries and the scene's binning domain."""
+    rb = bounding_radius(template[0], template[1])
+    sp = 2.0 * rb + 2e-4
+    tan30 = math.tan(math.radians(30.0))
+    r_out = 6.0 * rb
+    z_out = 0.0
+    z_apex = z_out - r_out / tan30          # virtual apex of the funnel cone
+    x = []
+    z = z_out + rb + 1e-4
+    while len(x) < n_clumps:
+        r_in = (z - z_apex) * tan30 - rb - 1e-4   # sites keep clear of the wall
+        m = int(r_in // sp)
+        for i in range(-m, m + 1):
+            for j in range(-m, m + 1):
+                if (i * sp) ** 2 + (j * sp) ** 2 <= r_in ** 2 and len(x) < n_clumps:
+                    x.append((i * sp, j * sp, z))
+        z += sp
+    x = np.array(x)
+    q = random_unit_quaternions(g, n_clumps)
+    top = float(x[:, 2].max()) + rb + 0.01
+    s30, c30 = math.sin(math.radians(30.0)), math.cos(math.radians(30.0))
+    mat = (1e7, 0.3, mu, 0.5)
+    bnd = [dict(type=BND_FRUSTUM_IN, param=(0, 0, z_apex, 0, 0, 1, s30, c30, z_out - z_apex, top - z_apex),
+                mat=mat, scene=scene),
+           dict(type=BND_PLANE, param=(0, 0, z_out - 0.2, 0, 0, 1), mat=mat, scene=scene)]
+    rmax = (top - z_apex) * tan30 + 0.1
+    dom = (-rmax, -rmax, z_out - 0.2, rmax, rmax, top)
+    return x, q, bnd, dom
+
+
+def config4(replica: int = 0, n_scenes: int = 256, lo: int = 2000, hi: int = 60000, scale: float = 1.0,
+            res: int = 32) -> SceneDesc:
+    """Configuration 4: n_scenes independent funnel discharges batched in one
+    simulation.  Clump counts log-uniform in [lo, hi] (times `scale`); per
+    scene one template of 1-6 spheres (lognormal radii) and mu ~ U[0.2, 0.9];
+    E = 1e7, nu = 0.3, CoR = 0.5; clumps start at rest; h = 1e-6 s.  Scenes
+    share coordinates but never interact (each has its own bins)."""
+    g = rng(4, replica)
+    counts = np.exp(g.uniform(np.log(lo), np.log(hi), n_scenes)) * scale
+    counts = np.maximum(1, counts.astype(np.int64))
+    templates, X, Q, CT, CS, MAT, bnds, doms = [], [], [], [], [], [], [], []
+    for k in range(n_scenes):
+        nsph = int(g.integers(1, 7))
+        t = multisphere_template(g, nsph, res=res)
+        mu = float(g.uniform(0.2, 0.9))
+        x, q, bnd, dom = funnel_scene_parts(g, int(counts[k]), t, mu, k)
+        templates.append(t)
+        X.append(x); Q.append(q)
+        CT.append(np.full(len(x), k)); CS.append(np.full(len(x), k))
+        MAT.append(np.tile([1e7, 0.3, mu, 0.5], (len(x) * nsph, 1)))
+        bnds += bnd
+        doms.append(dom)
+    X = np.concatenate(X)
+    n = X.shape[0]
+    return assemble(templates, np.concatenate(CT), X, np.concatenate(Q), np.zeros((n, 3)), np.zeros((n, 3)),
+                    np.concatenate(MAT), np.tile([0.0, 0.0, -9.81], (n_scenes, 1)), np.array(doms), 1e-6,
+                    clump_scene=np.concatenate(CS), bnd=bnds, name=f"cfg4-r{replica}")
+
+
+def extract_scene(batch: SceneDesc, k: int) -> SceneDesc:
+    """Scene k of a batched description as a stand-alone description (same
+    templates, same per-sphere materials, its own boundaries)."""
+    sel = np.nonzero(batch.clump_scene == k)[0]
+    sb = batch.sphere_begin()
+    sph = np.concatenate([np.arange(sb[c], sb[c + 1]) for c in sel]) if len(sel) else np.zeros(0, np.int64)
+    bsel = np.nonzero(batch.bnd_scene == k)[0]
+    d = dataclasses.replace(
+        batch, clump_template=batch.clump_template[sel], clump_scene=np.zeros(len(sel), np.uint32),
+        x=batch.x[sel], q=batch.q[sel], v=batch.v[sel], w=batch.w[sel], sphere_mat=batch.sphere_mat[sph],
+        gravity=batch.gravity[k:k + 1], domain=batch.domain[k:k + 1], bnd_type=batch.bnd_type[bsel],
+        bnd_param=batch.bnd_param[bsel], bnd_mat=batch.bnd_mat[bsel], bnd_vel=batch.bnd_vel[bsel],
+        bnd_omega=batch.bnd_omega[bsel], bnd_scene=np.zeros(len(bsel), np.int32),
+        presc_clump=np.zeros(0, np.int32), presc_param=np.zeros((0, PRESC_NPARAM)), name=f"{batch.name}-s{k}")
+    return d.canonical()

@@ -1,0 +1,63 @@
+"""Batched independent scenes in one simulation: a scene inside the batch
+evolves bit for bit as when run alone, and matches the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03445_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(desc, prec="fp32"):
+    from paper_2307_03445_amd._lib import Scene
+    return Scene(desc, precision=prec)
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return I.config4(n_scenes=6, lo=150, hi=1500)
+
+
+@pytest.mark.parametrize("mode", ["plain", "fixed"])
+def test_scene_in_batch_equals_scene_alone(batch, mode):
+    b = _scene(batch)
+    if mode == "fixed":
+        b.set_detection("fixed", k_max=10, safety=1.5, margin_cap=1e-4, audit_period=10)
+    b.step(300)
+    sb = b.state()
+    for k in (0, 3, 5):
+        d = I.extract_scene(batch, k)
+        a = _scene(d)
+        if mode == "fixed":
+            a.set_detection("fixed", k_max=10, safety=1.5, margin_cap=1e-4, audit_period=10)
+        a.step(300)
+        sa = a.state()
+        sel = np.nonzero(batch.clump_scene == k)[0]
+        for key in sa:
+            assert np.array_equal(sa[key], sb[key][sel]), (k, key)
+    assert b.counts()["missed"] == 0
+
+
+def test_batched_matches_oracle_fp64(batch):
+    small = I.config4(n_scenes=3, lo=100, hi=300)
+    sc, o = _scene(small, "fp64"), oracle.Oracle(small)
+    sc.step(200)
+    o.step(200)
+    sg, so = sc.state(), o.state()
+    for key in sg:
+        assert np.array_equal(sg[key], so[key]), key
+
+
+def test_graph_replay_and_autotune_do_not_change_results(batch):
+    """Graph replay, the autotuner's bin size and launch shape change speed only."""
+    ref, g = _scene(batch), _scene(batch)
+    ref.step(120)
+    g.set_graph(20)
+    choice = g.autotune(5)          # 45 tuning steps: ordinary steps of the run
+    assert choice["bin_factor"] in (1.0, 1.25, 1.5)
+    done = g.counts()["steps"]
+    g.step(120 - done)
+    sr, sg = ref.state(), g.state()
+    for key in sr:
+        assert np.array_equal(sr[key], sg[key]), key
