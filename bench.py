@@ -159,7 +159,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--patch-cache", default=None,
                     help="npz file holding the settled preparation patch (written if missing)")
+    ap.add_argument("--copy-probe-gib", type=float, default=0.0,
+                    help="only run a plain device-to-device copy of this many GiB (counter calibration)")
     args = ap.parse_args()
+    if args.copy_probe_gib > 0:
+        import torch
+        n = int(args.copy_probe_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this build is single-GPU).",
               file=sys.stderr)

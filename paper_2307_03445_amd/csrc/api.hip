@@ -172,7 +172,10 @@ static bool finite_all(const double *p, size_t n) {
 // allocate the bin arrays when they grow.
 static int build_grids(cdem_scene *sc) {
     DevScene &S = sc->S;
-    double b = 2.0 * (sc->rmax + std::max(0.0, sc->det.margin_cap)) * sc->bin_factor;
+    // bins of R_max + margin cap: a sphere's candidates lie within its reach
+    // (R + m) + (R_max + m_cap), at most two bins away, and the scan visits
+    // only the bins that reach touches
+    double b = (sc->rmax + std::max(0.0, sc->det.margin_cap)) * sc->bin_factor;
     if (!(b > 0.0)) b = 1.0;  // no spheres: any positive bin size will do
     int64_t cell0 = 0;
     for (int k = 0; k < S.n_scenes; k++) {
@@ -189,6 +192,17 @@ static int build_grids(cdem_scene *sc) {
         }
         g.ox = d[0]; g.oy = d[1]; g.oz = d[2];
         g.inv = 1.0 / bb;
+        g.b = bb;
+        g.rm_max = sc->rmax + std::max(0.0, sc->det.margin_cap);
+        // FP32 prefilter slack: positions relative to the origin are rounded to
+        // float (half an ulp of the largest coordinate each), differences of
+        // two of them and the float distance add a few more ulps; 32 ulps of
+        // the domain's extent (plus one bin of sphere outside it) bounds all
+        {
+            double ext = std::max({d[3] - d[0], d[4] - d[1], d[5] - d[2]}) + 2.0 * bb;
+            g.pre_eps = (float)(32.0 * ext * std::ldexp(1.0, -24));
+            g.pre_lim = (float)(2.0 * ext);
+        }
         g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
         g.cell0 = cell0;
         cell0 += nx * ny * nz;
@@ -491,6 +505,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
     S.sorted_margin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * std::max<int64_t>(ns, 1));
+    if (!S.sorted_f4) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     S.rec_cF = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
     S.rec_cT = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
     S.ctl = (Ctl *)dev_alloc(sc, sizeof(Ctl));

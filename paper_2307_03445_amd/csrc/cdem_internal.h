@@ -30,6 +30,10 @@ struct Grid {
     int64_t cell0;           // first global bin id of the scene
     int32_t bnd_beg, bnd_end;
     double gx, gy, gz;       // gravity
+    float pre_eps;           // slack of the FP32 prefilter: bounds its rounding of positions relative to (ox, oy, oz)
+    float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
+    double b;                // bin size
+    double rm_max;           // largest radius + largest margin of any sphere (the partner side of a reach)
 };
 
 // Device-resident control block: decides on the device whether a detection
@@ -110,6 +114,7 @@ struct DevScene {
     uint32_t *sorted_id, *sorted_owner;
     double4 *sorted_pos;
     float *sorted_margin;
+    float4 *sorted_f4;               // FP32 prefilter record: position - grid origin, radius + margin
     // active set: two buffers, current chosen by ctl->buf
     uint32_t *row_beg[2], *row_cnt[2], *nbr[2];
     double *hist[2];                 // [cap][3]

@@ -170,6 +170,47 @@ __device__ __forceinline__ void cell_coords(const Grid &g, double x, double y, d
     ix = (int)fx; iy = (int)fy; iz = (int)fz;
 }
 
+// Visit the sorted-slot ranges of every bin row that a ball of radius `reach`
+// around (px, py, pz) touches: rows (iz, iy) within reach, and in each row the
+// contiguous x-range of bins the ball's section covers.  Edge bins extend to
+// infinity (positions outside the domain are clamped into them), so spheres
+// outside the domain are still found.  f(jb, je) receives each slot range.
+__device__ __forceinline__ double slab_gap(double p, double o, double b, int i, int n) {
+    double lo = (i == 0) ? -1e300 : o + (double)i * b;
+    double hi = (i == n - 1) ? 1e300 : o + (double)(i + 1) * b;
+    return p < lo ? lo - p : (p > hi ? p - hi : 0.0);
+}
+
+__device__ __forceinline__ int clamp_cell(double v, int n) {
+    v = floor(v);
+    v = fmin(fmax(v, 0.0), (double)(n - 1));
+    return (int)v;
+}
+
+template <typename F>
+__device__ __forceinline__ void scan_reach(const DevScene &S, const Grid &g, double px, double py, double pz,
+                                           double reach, F &&f) {
+    int z0 = clamp_cell((pz - reach - g.oz) * g.inv, g.nz), z1 = clamp_cell((pz + reach - g.oz) * g.inv, g.nz);
+    int y0 = clamp_cell((py - reach - g.oy) * g.inv, g.ny), y1 = clamp_cell((py + reach - g.oy) * g.inv, g.ny);
+    double r2 = reach * reach;
+    for (int zz = z0; zz <= z1; zz++) {
+        double gz = slab_gap(pz, g.oz, g.b, zz, g.nz);
+        double rz = r2 - gz * gz;
+        if (rz < 0.0) continue;
+        for (int yy = y0; yy <= y1; yy++) {
+            double gy = slab_gap(py, g.oy, g.b, yy, g.ny);
+            double ry = rz - gy * gy;
+            if (ry < 0.0) continue;
+            double rx = sqrt(ry);
+            int x0 = clamp_cell((px - rx - g.ox) * g.inv, g.nx), x1 = clamp_cell((px + rx - g.ox) * g.inv, g.nx);
+            int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
+            uint32_t jb = S.cell_start[rowc + x0];
+            uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+            f(jb, je);
+        }
+    }
+}
+
 __device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
 __device__ __forceinline__ bool audit_due(const DevScene &S) {
     return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
@@ -284,6 +325,8 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_pos[slot] = p;
     if (which) return;
     float m = S.detect_mode == 2 ? S.bin_margin[cell] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
+    const Grid &g = S.grids[S.sscene[s]];
+    S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
     S.smargin[s] = m;
     S.sdet[s] = p;
@@ -408,47 +451,54 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     if (!due(S.ctl)) return;
     __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
     const int tid = threadIdx.x;
+    // one thread per sphere id: ids are spatially coherent (clumps are laid out
+    // in Morton order), so a wavefront's neighbour scans share cache lines and
+    // the rows, and the pair list built from them, come out in that order
     int64_t i = (int64_t)blockIdx.x * kNarrowBlock + tid;
     const int cur = S.ctl->buf, nxt = cur ^ 1;
     int cnt = 0;
     bool over = false;
     uint32_t s = 0;
     if (i < S.ns) {
-        s = S.sorted_id[i];
-        double4 P = S.sorted_pos[i];
-        uint32_t own = S.sorted_owner[i];
-        float ms = S.sorted_margin[i];
+        s = (uint32_t)i;
+        double4 P = S.spos[s];
+        uint32_t own = S.owner[s];
+        float ms = S.smargin[s];
         const Grid &g = S.grids[S.sscene[s]];
-        int ix, iy, iz;
-        cell_coords(g, P.x, P.y, P.z, ix, iy, iz);
-        int z0 = max(iz - 1, 0), z1 = min(iz + 1, g.nz - 1);
-        int y0 = max(iy - 1, 0), y1 = min(iy + 1, g.ny - 1);
-        int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.nx - 1);
-        for (int zz = z0; zz <= z1; zz++)
-            for (int yy = y0; yy <= y1; yy++) {
-                int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
-                uint32_t jb = S.cell_start[rowc + x0];
-                uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
-                for (uint32_t j = jb; j < je; j++) {
-                    if (S.sorted_owner[j] == own) continue;
-                    double4 Q = S.sorted_pos[j];
-                    double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                    double d2 = dx * dx + dy * dy + dz * dz;
-                    double Sr = P.w + Q.w;
-                    Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
-                    if (d2 < Sr * Sr) {
-                        uint32_t t = S.sorted_id[j];
-                        if (cnt == kMaxRow) { over = true; continue; }
-                        int k = cnt;
-                        while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
-                            lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
-                            k--;
-                        }
-                        lst[k * kNarrowBlock + tid] = t;
-                        cnt++;
+        const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w + ms);
+        const float eps = g.pre_eps;
+        // far outside the domain the slack no longer bounds the rounding: exact test only
+        const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+        // reach of s: its own (R + m) plus the largest partner (R + m); a small
+        // absolute slack keeps the bin selection conservative under rounding
+        const double reach = (P.w + (double)ms) + g.rm_max + 1e-9;
+        scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
+            for (uint32_t j = jb; j < je; j++) {
+                // conservative FP32 test first: it can only admit extra candidates,
+                // which the exact FP64 predicate below then rejects
+                float4 Qf = S.sorted_f4[j];
+                float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z;
+                float fr = (Pf.w + Qf.w) + eps;
+                if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
+                if (S.sorted_owner[j] == own) continue;
+                double4 Q = S.sorted_pos[j];
+                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                double Sr = P.w + Q.w;
+                Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
+                if (d2 < Sr * Sr) {
+                    uint32_t t = S.sorted_id[j];
+                    if (cnt == kMaxRow) { over = true; continue; }
+                    int k = cnt;
+                    while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
+                        lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
+                        k--;
                     }
+                    lst[k * kNarrowBlock + tid] = t;
+                    cnt++;
                 }
             }
+        });
         double tnow = (double)S.ctl->step * S.h;
         for (int b = g.bnd_beg; b < g.bnd_end; b++) {
             double phi, n[3];
@@ -1071,9 +1121,9 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
     unsigned long long found = 0, missed = 0;
     if (i < S.ns) {
         const int cur = S.ctl->buf;
-        uint32_t s = S.sorted_id[i];
-        double4 P = S.sorted_pos[i];
-        uint32_t own = S.sorted_owner[i];
+        uint32_t s = (uint32_t)i;
+        double4 P = S.spos[s];
+        uint32_t own = S.owner[s];
         uint32_t beg = pick(S.row_beg, cur)[s], cnt = pick(S.row_cnt, cur)[s];
         const uint32_t *nb = pick(S.nbr, cur) + beg;
         auto in_row = [&](uint32_t t) {
@@ -1082,22 +1132,17 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
             return lo < cnt && nb[lo] == t;
         };
         const Grid &g = S.grids[S.sscene[s]];
-        int ix, iy, iz;
-        cell_coords(g, P.x, P.y, P.z, ix, iy, iz);
-        for (int zz = max(iz - 1, 0); zz <= min(iz + 1, g.nz - 1); zz++)
-            for (int yy = max(iy - 1, 0); yy <= min(iy + 1, g.ny - 1); yy++) {
-                int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
-                int x0 = max(ix - 1, 0), x1 = min(ix + 1, g.nx - 1);
-                uint32_t jb = S.cell_start[rowc + x0], je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
-                for (uint32_t j = jb; j < je; j++) {
-                    if (S.sorted_owner[j] == own) continue;
-                    double4 Q = S.sorted_pos[j];
-                    double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                    double d2 = dx * dx + dy * dy + dz * dz;
-                    double Sr = P.w + Q.w;
-                    if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
-                }
+        const double reach = P.w + g.rm_max + 1e-9;
+        scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
+            for (uint32_t j = jb; j < je; j++) {
+                if (S.sorted_owner[j] == own) continue;
+                double4 Q = S.sorted_pos[j];
+                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                double Sr = P.w + Q.w;
+                if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
             }
+        });
         double tnow = (double)S.ctl->step * S.h;
         for (int b = g.bnd_beg; b < g.bnd_end; b++) {
             double phi, n[3];

@@ -665,24 +665,36 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
     ``patch_x``/``patch_q`` are the settled clump poses of
     :func:`cfg5_patch_scene` (same replica); the patch is Morton-sorted and
     copied over the 4 m x 1 m bed (the paper prepares large beds from copies of
-    a settled base patch), truncated to ``n_clumps``.  Per-sphere-instance
+    a settled base patch), truncated to ``n_clumps``.  Copies are spaced by the
+    patch width plus the depth its spheres press into the patch walls, so no
+    two copies overlap (the bed is that much wider than nominal).  Per-sphere-instance
     E ~ U[1e7, 5e7] Pa, mu ~ U[0.3, 0.8]; nu = 0.3; CoR = 0.5; h = 1e-6 s;
     clumps start at rest.  A rigid 20,000-sphere wheel (R = 0.25 m, width
     0.2 m, 12 grousers, 10 kg) rests on the surface, driven at slip 0.2
     (omega = 0.8 rad/s, v = (1 - 0.2) omega R) with a free vertical degree of
-    freedom under a total load of 100 N.
+    freedom under a total load of 100 N; it starts 50 um above the local
+    surface and sinks in under its load.
     """
     g = rng(5, 1000 + replica)
     tmpls = cfg2_templates(replica)
     ct_p = rng(5, replica).integers(0, len(tmpls), patch_x.shape[0])
     order = morton_order(patch_x, 0.01)
     xp, qp, ct_p = patch_x[order], patch_q[order], ct_p[order]
+    # sphere centres of the patch: the settled spheres press into the patch's
+    # walls, so copies are placed one wall-penetration apart (no overlap at seams)
+    Rm = quat_matrix(qp)
+    P = np.concatenate([xp[k] + tmpls[ct_p[k]][0] @ Rm[k].T for k in range(len(ct_p))])
+    Rr = np.concatenate([tmpls[ct_p[k]][1] for k in range(len(ct_p))])
+    lo = np.array([max(0.0, -(P[:, a] - Rr).min()) for a in range(2)])
+    hi = np.array([max(0.0, (P[:, a] + Rr).max() - side) for a in range(2)])
+    pitch = side + lo + hi + 1e-6
     ntx, nty = int(round(bed[0] / side)), int(round(bed[1] / side))
     tiles = [(i, j) for j in range(nty) for i in range(ntx)]
     tiles = [tiles[k] for k in morton_order(np.array([(i, j, 0) for i, j in tiles], float), 1.0)]
-    X = np.concatenate([xp + np.array([i * side, j * side, 0.0]) for i, j in tiles])[:n_clumps]
+    X = np.concatenate([xp + np.array([lo[0] + i * pitch[0], lo[1] + j * pitch[1], 0.0]) for i, j in tiles])[:n_clumps]
     Q = np.tile(qp, (len(tiles), 1))[:n_clumps]
     CT = np.tile(ct_p, len(tiles))[:n_clumps]
+    bed = (ntx * pitch[0], nty * pitch[1])
     nc = X.shape[0]
     sizes = np.array([t[0].shape[0] for t in tmpls])
     ns_bed = int(sizes[CT].sum())
@@ -702,9 +714,6 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
         R, wr = 0.25, float(wt[1][0])
         cx, cy = wheel_x, bed[1] / 2
         # column heights of the patch surface (the bed repeats the patch)
-        Rm = quat_matrix(qp)
-        P = np.concatenate([xp[k] + tmpls[ct_p[k]][0] @ Rm[k].T for k in range(len(ct_p))])
-        Rr = np.concatenate([tmpls[ct_p[k]][1] for k in range(len(ct_p))])
         cell = 0.004
         nx, ny = int(np.ceil(side / cell)) + 1, int(np.ceil(side / cell)) + 1
         ix = np.clip(np.floor(P[:, 0] / cell).astype(int), 0, nx - 1)
@@ -712,10 +721,10 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
         colh = np.zeros((nx, ny))
         np.maximum.at(colh, (ix, iy), P[:, 2] + Rr)
         wo = wt[0]
-        px = np.mod(cx + wo[:, 0], side)
-        py = np.mod(cy + wo[:, 1], side)
+        px = np.mod(cx + wo[:, 0] - lo[0], pitch[0])
+        py = np.mod(cy + wo[:, 1] - lo[1], pitch[1])
         h_under = colh[np.clip((px / cell).astype(int), 0, nx - 1), np.clip((py / cell).astype(int), 0, ny - 1)]
-        zc = float((h_under + wr - 5e-4 - wo[:, 2]).max())
+        zc = float((h_under + wr + 5e-5 - wo[:, 2]).max())  # 50 um above the surface: it settles gently
         X = np.vstack([X, [cx, cy, zc]])
         Q = np.vstack([Q, [1.0, 0.0, 0.0, 0.0]])
         CT = np.r_[CT, len(tmpls)]
