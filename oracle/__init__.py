@@ -77,6 +77,8 @@ def lib():
             "dem_oracle_read_sphere_pos": (V, [P, P]),
             "dem_oracle_n_spheres": (I64, [P]),
             "dem_oracle_candidates": (I64, [P, P, P, P, I64]),
+            "dem_oracle_sample_spheres": (I64, [P, P, I64, P, P, I64, P, P, P, P, P]),
+            "dem_oracle_sample_clumps": (C.c_int, [P, P, I64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -179,3 +181,32 @@ class Oracle:
         a = np.empty(n, np.uint32); b = np.empty(n, np.uint32)
         lib().dem_oracle_candidates(self._h, _ptr(m), _ptr(a), _ptr(b), n)
         return a, b
+
+    def sample_spheres(self, ids):
+        """Forces, torques and contacts of the spheres `ids` at the current
+        state, by brute force over every partner (for scenes too large for
+        ``eval``).  Returns (F [n,3], T [n,3], contacts dict a, b, delta, F,
+        beg), where sample k's contacts are rows beg[k]:beg[k+1]."""
+        ids = np.ascontiguousarray(ids, np.int64)
+        n = len(ids)
+        F = np.empty((n, 3)); T = np.empty((n, 3))
+        cap = 64 * max(n, 1)
+        beg = np.empty(n + 1, np.int64)
+        while True:
+            a = np.empty(cap, np.uint32); b = np.empty(cap, np.uint32)
+            dl = np.empty(cap); cF = np.empty((cap, 3))
+            m = int(lib().dem_oracle_sample_spheres(self._h, _ptr(ids), n, _ptr(F), _ptr(T), cap, _ptr(beg),
+                                                    _ptr(a), _ptr(b), _ptr(dl), _ptr(cF)))
+            if m < 0:
+                raise ValueError(lib().dem_oracle_last_error().decode())
+            if m <= cap:
+                return F, T, dict(a=a[:m], b=b[:m], delta=dl[:m], F=cF[:m], beg=beg)
+            cap = m
+
+    def sample_clumps(self, clumps):
+        """Force (contacts + gravity) and torque of the clumps `clumps`."""
+        c = np.ascontiguousarray(clumps, np.int64)
+        F = np.empty((len(c), 3)); T = np.empty((len(c), 3))
+        if lib().dem_oracle_sample_clumps(self._h, _ptr(c), len(c), _ptr(F), _ptr(T)) != 0:
+            raise ValueError(lib().dem_oracle_last_error().decode())
+        return F, T

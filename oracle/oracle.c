@@ -434,6 +434,73 @@ static int64_t collect_pairs(const dem_oracle *o, const double *margin, uint64_t
     return total;
 }
 
+/* One candidate pair (a < b; b >= ns is boundary b - ns): penetration, and
+ * when it is positive the force on body b and the updated history (Sec. 2.1).
+ * ra, rb: lever arms from the bodies' reference points to the contact point. */
+static double pair_eval(const dem_oracle *o, int64_t a, int64_t b, double t, const double *u_old, double *F,
+                        double *un, double *ra, double *rb) {
+    int64_t ns = o->ns;
+    double h = o->h;
+    double n[3], delta, p[3], vrel[3];
+    double Rbar, mbar, estar, gstar, mu, beta;
+    if (b < ns) {
+        const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
+        double Ra = o->rad[a], Rb = o->rad[b];
+        uint32_t ca = o->owner[a], cb = o->owner[b];
+        double dx[3];
+        for (int i = 0; i < 3; i++) dx[i] = xb[i] - xa[i];
+        double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
+        delta = (Ra + Rb) - d;
+        for (int i = 0; i < 3; i++) n[i] = dx[i] / d;
+        double lever = Ra - 0.5 * delta;
+        for (int i = 0; i < 3; i++) p[i] = xa[i] + lever * n[i];
+        for (int i = 0; i < 3; i++) { ra[i] = p[i] - o->x[3 * ca + i]; rb[i] = p[i] - o->x[3 * cb + i]; }
+        double wa[3], wb[3];
+        cross(o->ww + 3 * ca, ra, wa);
+        cross(o->ww + 3 * cb, rb, wb);
+        for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cb + i] + wb[i]) - (o->v[3 * ca + i] + wa[i]);
+        Rbar = (Ra * Rb) / (Ra + Rb);
+        double Ma = o->mass[ca], Mb = o->mass[cb];
+        mbar = (Ma * Mb) / (Ma + Mb);
+        estar = 1.0 / (o->me[a] + o->me[b]);
+        gstar = 1.0 / (o->mg[a] + o->mg[b]);
+        mu = fmin(o->mmu[a], o->mmu[b]);
+        beta = fmin(o->mbeta[a], o->mbeta[b]);
+    } else {
+        /* boundary contact: the boundary is body a, the sphere is body b */
+        int32_t wi = (int32_t)(b - ns);
+        int64_t s = a;
+        const double *xsph = o->xs + 3 * s;
+        double R = o->rad[s], phi;
+        uint32_t cs = o->owner[s];
+        boundary_distance(o, wi, t, xsph, &phi, n);
+        delta = R - phi;
+        double lever = R - 0.5 * delta;
+        for (int i = 0; i < 3; i++) p[i] = xsph[i] - lever * n[i];
+        const double *P = o->bparam + NPARAM_BND * wi;
+        double cwall[3], wv[3], pw[3];
+        for (int i = 0; i < 3; i++) cwall[i] = P[i] + t * o->bvel[3 * wi + i];
+        for (int i = 0; i < 3; i++) { ra[i] = p[i] - cwall[i]; rb[i] = p[i] - o->x[3 * cs + i]; }
+        cross(o->bomega + 3 * wi, ra, pw);
+        double wb[3];
+        cross(o->ww + 3 * cs, rb, wb);
+        for (int i = 0; i < 3; i++) wv[i] = o->bvel[3 * wi + i] + pw[i];
+        for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cs + i] + wb[i]) - wv[i];
+        Rbar = R;
+        mbar = o->mass[cs];
+        estar = 1.0 / (o->be[wi] + o->me[s]);
+        gstar = 1.0 / (o->bg[wi] + o->mg[s]);
+        mu = fmin(o->bmu[wi], o->mmu[s]);
+        beta = fmin(o->bbeta[wi], o->mbeta[s]);
+    }
+    if (delta > 0.0) {
+        contact_law(n, delta, vrel, Rbar, mbar, estar, gstar, mu, beta, h, u_old, F, un);
+    } else {
+        for (int i = 0; i < 3; i++) { F[i] = 0.0; un[i] = 0.0; }
+    }
+    return delta;
+}
+
 /* ---------------- one evaluation ---------------- */
 
 int64_t dem_oracle_eval(dem_oracle *o) {
@@ -459,66 +526,9 @@ int64_t dem_oracle_eval(dem_oracle *o) {
         int64_t hi = find_history(o, key);
         double u_old[3] = {0.0, 0.0, 0.0};
         if (hi >= 0) for (int i = 0; i < 3; i++) u_old[i] = o->hu[3 * hi + i];
-        double n[3], delta, p[3], ra[3], rb[3], vrel[3];
-        double Rbar, mbar, estar, gstar, mu, beta;
         double *F = o->cF + 3 * k, *un = o->cu + 3 * k;
-        if (b < ns) {
-            const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
-            double Ra = o->rad[a], Rb = o->rad[b];
-            uint32_t ca = o->owner[a], cb = o->owner[b];
-            double dx[3];
-            for (int i = 0; i < 3; i++) dx[i] = xb[i] - xa[i];
-            double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
-            delta = (Ra + Rb) - d;
-            for (int i = 0; i < 3; i++) n[i] = dx[i] / d;
-            double lever = Ra - 0.5 * delta;
-            for (int i = 0; i < 3; i++) p[i] = xa[i] + lever * n[i];
-            for (int i = 0; i < 3; i++) { ra[i] = p[i] - o->x[3 * ca + i]; rb[i] = p[i] - o->x[3 * cb + i]; }
-            double wa[3], wb[3];
-            cross(o->ww + 3 * ca, ra, wa);
-            cross(o->ww + 3 * cb, rb, wb);
-            for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cb + i] + wb[i]) - (o->v[3 * ca + i] + wa[i]);
-            Rbar = (Ra * Rb) / (Ra + Rb);
-            double Ma = o->mass[ca], Mb = o->mass[cb];
-            mbar = (Ma * Mb) / (Ma + Mb);
-            estar = 1.0 / (o->me[a] + o->me[b]);
-            gstar = 1.0 / (o->mg[a] + o->mg[b]);
-            mu = fmin(o->mmu[a], o->mmu[b]);
-            beta = fmin(o->mbeta[a], o->mbeta[b]);
-        } else {
-            /* boundary contact: the boundary is body a, the sphere is body b */
-            int32_t wi = (int32_t)(b - ns);
-            int64_t s = a;
-            const double *xsph = o->xs + 3 * s;
-            double R = o->rad[s], phi;
-            uint32_t cs = o->owner[s];
-            boundary_distance(o, wi, t, xsph, &phi, n);
-            delta = R - phi;
-            double lever = R - 0.5 * delta;
-            for (int i = 0; i < 3; i++) p[i] = xsph[i] - lever * n[i];
-            const double *P = o->bparam + NPARAM_BND * wi;
-            double cwall[3], wv[3], pw[3];
-            for (int i = 0; i < 3; i++) cwall[i] = P[i] + t * o->bvel[3 * wi + i];
-            for (int i = 0; i < 3; i++) { ra[i] = p[i] - cwall[i]; rb[i] = p[i] - o->x[3 * cs + i]; }
-            cross(o->bomega + 3 * wi, ra, pw);
-            double wb[3];
-            cross(o->ww + 3 * cs, rb, wb);
-            for (int i = 0; i < 3; i++) wv[i] = o->bvel[3 * wi + i] + pw[i];
-            for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cs + i] + wb[i]) - wv[i];
-            Rbar = R;
-            mbar = o->mass[cs];
-            estar = 1.0 / (o->be[wi] + o->me[s]);
-            gstar = 1.0 / (o->bg[wi] + o->mg[s]);
-            mu = fmin(o->bmu[wi], o->mmu[s]);
-            beta = fmin(o->bbeta[wi], o->mbeta[s]);
-        }
+        double delta = pair_eval(o, a, b, t, u_old, F, un, o->cra + 3 * k, o->crb + 3 * k);
         o->cdelta[k] = delta;
-        for (int i = 0; i < 3; i++) { o->cra[3 * k + i] = ra[i]; o->crb[3 * k + i] = rb[i]; }
-        if (delta > 0.0) {
-            contact_law(n, delta, vrel, Rbar, mbar, estar, gstar, mu, beta, h, u_old, F, un);
-        } else {
-            for (int i = 0; i < 3; i++) { F[i] = 0.0; un[i] = 0.0; }
-        }
     }
 
     /* transposed index: contacts in which sphere s is the higher sphere id */
@@ -700,4 +710,141 @@ int64_t dem_oracle_candidates(dem_oracle *o, const double *margin, uint32_t *a, 
     }
     free(keys);
     return n;
+}
+
+/* ---------------- sampled evaluation (large scenes) ---------------- */
+
+typedef struct sample_row {
+    int64_t n, cap;
+    uint64_t *key;
+    double *delta, *F;
+} sample_row;
+
+static void row_push(sample_row *r, uint64_t key, double delta, const double *F) {
+    if (r->n == r->cap) {
+        r->cap = r->cap ? 2 * r->cap : 16;
+        r->key = (uint64_t *)realloc(r->key, r->cap * sizeof(uint64_t));
+        r->delta = (double *)realloc(r->delta, r->cap * sizeof(double));
+        r->F = (double *)realloc(r->F, 3 * r->cap * sizeof(double));
+        if (!r->key || !r->delta || !r->F) { fprintf(stderr, "oracle: out of memory\n"); abort(); }
+    }
+    r->key[r->n] = key;
+    r->delta[r->n] = delta;
+    for (int i = 0; i < 3; i++) r->F[3 * r->n + i] = F[i];
+    r->n++;
+}
+
+/* Force and torque on sphere s from every contact it has at the current state,
+ * summed in ascending partner id exactly as the full evaluation sums them;
+ * the contacts themselves go to row r. */
+static void sphere_sample(const dem_oracle *o, int64_t s, double t, double *Fs, double *Ts, sample_row *r) {
+    int64_t ns = o->ns;
+    uint32_t cs = o->owner[s], sc = o->scene[cs];
+    const double *xs = o->xs + 3 * s;
+    for (int i = 0; i < 3; i++) { Fs[i] = 0.0; Ts[i] = 0.0; }
+    for (int64_t p = 0; p <= ns + o->nb - 1; p++) {
+        if (p == s) continue;
+        int64_t a, b;
+        if (p < ns) {
+            a = s < p ? s : p;
+            b = s < p ? p : s;
+            /* the exact predicate of the contact set, evaluated from the lower sphere */
+            const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
+            double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double S = o->rad[a] + o->rad[b];
+            if (!(d2 < S * S)) continue;
+            uint32_t cp = o->owner[p];
+            if (cp == cs || o->scene[cp] != sc) continue;
+        } else {
+            int32_t w = (int32_t)(p - ns);
+            if ((uint32_t)o->bscene[w] != sc) continue;
+            double phi, n[3];
+            if (!boundary_distance(o, w, t, xs, &phi, n) || !(phi < o->rad[s])) continue;
+            a = s;
+            b = p;
+        }
+        uint64_t key = ((uint64_t)a << 32) | (uint64_t)b;
+        int64_t hi = find_history(o, key);
+        double u_old[3] = {0.0, 0.0, 0.0}, F[3], un[3], ra[3], rb[3];
+        if (hi >= 0) for (int i = 0; i < 3; i++) u_old[i] = o->hu[3 * hi + i];
+        double delta = pair_eval(o, a, b, t, u_old, F, un, ra, rb);
+        row_push(r, key, delta, F);
+        if (!(delta > 0.0)) continue;
+        double f[3], tq[3];
+        if (b == s || b >= ns) { /* s is body b */
+            for (int i = 0; i < 3; i++) f[i] = F[i];
+            cross(rb, f, tq);
+        } else {                 /* s is body a */
+            for (int i = 0; i < 3; i++) f[i] = -F[i];
+            cross(ra, f, tq);
+        }
+        for (int i = 0; i < 3; i++) { Fs[i] = Fs[i] + f[i]; Ts[i] = Ts[i] + tq[i]; }
+    }
+}
+
+int64_t dem_oracle_sample_spheres(dem_oracle *o, const int64_t *ids, int64_t n, double *F, double *T, int64_t cap,
+                                  int64_t *beg, uint32_t *ca, uint32_t *cb, double *cdelta, double *cF) {
+    if (n < 0) { set_err("sample: negative count"); return -1; }
+    for (int64_t k = 0; k < n; k++)
+        if (ids[k] < 0 || ids[k] >= o->ns) { set_err("sample: sphere id out of range"); return -1; }
+    compute_poses(o);
+    double t = (double)o->step * o->h;
+    sample_row *rows = (sample_row *)calloc((size_t)(n ? n : 1), sizeof(sample_row));
+    if (!rows) { set_err("sample: out of memory"); return -1; }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n; k++) {
+        double Fs[3], Ts[3];
+        sphere_sample(o, ids[k], t, Fs, Ts, &rows[k]);
+        for (int i = 0; i < 3; i++) {
+            if (F) F[3 * k + i] = Fs[i];
+            if (T) T[3 * k + i] = Ts[i];
+        }
+    }
+    int64_t m = 0;
+    for (int64_t k = 0; k < n; k++) {
+        if (beg) beg[k] = m;
+        for (int64_t j = 0; j < rows[k].n; j++, m++) {
+            if (m >= cap) continue;
+            if (ca) ca[m] = (uint32_t)(rows[k].key[j] >> 32);
+            if (cb) cb[m] = (uint32_t)(rows[k].key[j] & 0xffffffffu);
+            if (cdelta) cdelta[m] = rows[k].delta[j];
+            if (cF) for (int i = 0; i < 3; i++) cF[3 * m + i] = rows[k].F[3 * j + i];
+        }
+        free(rows[k].key); free(rows[k].delta); free(rows[k].F);
+    }
+    if (beg) beg[n] = m;
+    free(rows);
+    return m;
+}
+
+int dem_oracle_sample_clumps(dem_oracle *o, const int64_t *clumps, int64_t n, double *F, double *T) {
+    int64_t tot = 0;
+    for (int64_t k = 0; k < n; k++) {
+        if (clumps[k] < 0 || clumps[k] >= o->nc) { set_err("sample: clump id out of range"); return -1; }
+        tot += o->sbeg[clumps[k] + 1] - o->sbeg[clumps[k]];
+    }
+    int64_t *ids = (int64_t *)xmalloc((tot ? tot : 1) * sizeof(int64_t));
+    double *sF = (double *)xmalloc(3 * (tot ? tot : 1) * sizeof(double));
+    double *sT = (double *)xmalloc(3 * (tot ? tot : 1) * sizeof(double));
+    int64_t m = 0;
+    for (int64_t k = 0; k < n; k++)
+        for (int64_t s = o->sbeg[clumps[k]]; s < o->sbeg[clumps[k] + 1]; s++) ids[m++] = s;
+    if (dem_oracle_sample_spheres(o, ids, tot, sF, sT, 0, NULL, NULL, NULL, NULL, NULL) < 0) {
+        free(ids); free(sF); free(sT);
+        return -1;
+    }
+    /* per-clump sums in ascending sphere id, then gravity, as in the full evaluation */
+    m = 0;
+    for (int64_t k = 0; k < n; k++) {
+        int64_t c = clumps[k];
+        double Fc[3] = {0.0, 0.0, 0.0}, Tc[3] = {0.0, 0.0, 0.0};
+        for (int64_t s = o->sbeg[c]; s < o->sbeg[c + 1]; s++, m++)
+            for (int i = 0; i < 3; i++) { Fc[i] = Fc[i] + sF[3 * m + i]; Tc[i] = Tc[i] + sT[3 * m + i]; }
+        const double *g = o->grav + 3 * o->scene[c];
+        for (int i = 0; i < 3; i++) Fc[i] = Fc[i] + o->mass[c] * g[i];
+        for (int i = 0; i < 3; i++) { F[3 * k + i] = Fc[i]; T[3 * k + i] = Tc[i]; }
+    }
+    free(ids); free(sF); free(sT);
+    return 0;
 }

@@ -97,6 +97,22 @@ int64_t dem_oracle_n_spheres(const dem_oracle *o);
 int64_t dem_oracle_candidates(dem_oracle *o, const double *margin, uint32_t *a, uint32_t *b,
                               int64_t cap);
 
+/* Sampled evaluation for scenes too large for the O(N^2) sweep: for each
+ * sphere ids[k], its force and torque at the current state (F, T [n][3],
+ * identical to what dem_oracle_eval would give that sphere) and its contacts,
+ * listed sample by sample in ascending partner id as canonical (a, b) with
+ * the penetration and the force on b; beg [n+1] receives where each sample's
+ * list starts.  A pair of two sampled spheres appears once per sample.  Each candidate partner is tested by brute force: cost
+ * O(n * n_spheres).  Writes at most cap contacts; returns the total, or -1 on
+ * an invalid id.  Does not advance or commit history.  Output pointers may be
+ * NULL. */
+int64_t dem_oracle_sample_spheres(dem_oracle *o, const int64_t *ids, int64_t n, double *F, double *T,
+                                  int64_t cap, int64_t *beg, uint32_t *ca, uint32_t *cb, double *cdelta,
+                                  double *cF);
+/* Force (contacts + gravity) and torque of each clump clumps[k], [n][3], as
+ * dem_oracle_eval would give them.  Returns 0, or -1 on an invalid id. */
+int dem_oracle_sample_clumps(dem_oracle *o, const int64_t *clumps, int64_t n, double *F, double *T);
+
 #ifdef __cplusplus
 }
 #endif

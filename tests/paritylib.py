@@ -51,15 +51,20 @@ def state_errors(sg, so, r_min):
     )
 
 
+def sphere_radii(desc):
+    """Radius of every sphere instance (template radius of its clump's template)."""
+    sb = np.asarray(desc.sphere_begin(), np.int64)
+    owner = np.repeat(np.arange(desc.n_clumps), np.diff(sb))
+    local = np.arange(desc.n_spheres) - sb[owner]
+    tb = np.asarray(desc.tmpl_sphere_begin, np.int64)
+    return np.asarray(desc.tmpl_radius)[tb[np.asarray(desc.clump_template, np.int64)[owner]] + local]
+
+
 def hertz_scale(desc, c):
     """Elastic force scale (4/3) E* sqrt(Rbar delta) delta of every oracle contact
     (textbook Hertz with the pair's effective modulus), used to judge pairs whose
     net force is a near-cancellation of the spring and dashpot terms."""
-    sb = desc.sphere_begin()
-    R = np.empty(desc.n_spheres)
-    for k in range(desc.n_clumps):
-        t = desc.clump_template[k]
-        R[sb[k]:sb[k + 1]] = desc.tmpl_radius[desc.tmpl_sphere_begin[t]:desc.tmpl_sphere_begin[t + 1]]
+    R = sphere_radii(desc)
     ns = desc.n_spheres
     a, b = c["a"].astype(np.int64), c["b"].astype(np.int64)
     wall = b >= ns
