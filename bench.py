@@ -26,6 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# detection settings of the timed deferred paths (FP32 force arithmetic)
+DETECT = dict(k_max=20, safety=1.5, margin_cap=2e-4, audit_period=100)
 METRIC = "sphere-timesteps/s at 34M spheres, learned-CD vs plain, 0 missed contacts"
 
 
@@ -66,14 +68,21 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     return 0.0
 
 
-def run_path(desc, mode, steps, warmup, k_max=20, margin_cap=2e-4, audit_every=100, mlp=None):
-    import torch
+def make_scene(desc, mode, mlp=None):
+    """The scene as the benchmark times it: FP32 force arithmetic, detection `mode`."""
     from paper_2307_03445_amd._lib import Scene
     sc = Scene(desc, precision="fp32")
     if mode == "learned":
         sc.set_mlp(mlp)
     if mode != "plain":
-        sc.set_detection(mode, k_max=k_max, safety=1.5, margin_cap=margin_cap, audit_period=audit_every)
+        sc.set_detection(mode, **DETECT)
+    return sc
+
+
+def run_path(desc, mode, steps, warmup, mlp=None):
+    import torch
+    audit_every = DETECT["audit_period"]
+    sc = make_scene(desc, mode, mlp)
     t0 = time.perf_counter()
     sc.step(warmup)
     log(f"[{mode}] warmup {warmup} steps: {time.perf_counter() - t0:.2f} s")
@@ -108,6 +117,36 @@ def run_path(desc, mode, steps, warmup, k_max=20, margin_cap=2e-4, audit_every=1
                 guard_trips=c1["guard_trips"] - c0["guard_trips"])
 
 
+KERNEL_SOURCES = ("paper_2307_03445_amd/csrc/kernels.hip", "paper_2307_03445_amd/csrc/cdem_internal.h",
+                  "paper_2307_03445_amd/csrc/mlp_dev.h")
+COUNTERS = os.path.join(ROOT, "profiles", "counters_rover_bed.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the
+    counter reads for a device copy of known size), or None when there is no
+    summary for it or the kernels changed since it was taken."""
+    try:
+        with open(COUNTERS) as fh:
+            c = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if c.get("source_sha256") != kernel_source_hash() or kernel not in c.get("kernels", {}):
+        return None
+    k = c["kernels"][kernel]
+    return 1024.0 * (k["fetch_kib"] * c["fetch_scale"] + k["write_kib"] * c["write_scale"])
+
+
 def roofline(res, desc_stats, mode):
     prof = res["prof"]
     k, (n, ms) = max(prof.items(), key=lambda kv: kv[1][1])
@@ -122,7 +161,7 @@ def roofline(res, desc_stats, mode):
     avg_s = ms / 1e3 / launches
     gbs = b / avg_s / 1e9 if b else None
     return dict(bound="hbm", kernel=k, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(gbs / HBM_PEAK_GBS) if gbs else None, traffic=None,
+                frac=(gbs / HBM_PEAK_GBS) if gbs else None, traffic=measured_traffic(k),
                 bytes_per_launch=b, avg_launch_us=avg_s * 1e6)
 
 

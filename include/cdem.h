@@ -52,7 +52,7 @@ extern "C" {
 
 #define CDEM_DETECT_PLAIN 0   /* detect every step, no margin (Sec. 2.2, traditional scheme) */
 #define CDEM_DETECT_FIXED 1   /* detect every k steps, margin from the global maximum speed */
-#define CDEM_DETECT_LEARNED 2 /* detect every k steps, per-bin margins from the MLP envelope */
+#define CDEM_DETECT_LEARNED 2 /* detect every k steps, per-region margins from the MLP envelope */
 
 #define CDEM_BND_PLANE 0      /* p0[3], n[3]: plane, unit normal into the domain */
 #define CDEM_BND_CYL_IN 1     /* p0[3], a[3], R: domain inside a cylinder */
@@ -190,7 +190,7 @@ int cdem_record_next_step(cdem_scene *s, int on);
 int cdem_set_graph(cdem_scene *s, int32_t steps_per_graph);
 
 /* Autotuner: time `steps` steps for each candidate bin-size factor (bins of
- * 1, 1.25 or 1.5 times the minimum 2 (R_max + margin cap)) and launch shape of
+ * 1, 1.25 or 1.5 times the minimum R_max + margin cap) and launch shape of
  * the grid-stride kernels, and keep the fastest.  The tuning steps are
  * ordinary steps of the simulation (results do not depend on the choice).
  * *bin_factor and *stride_cap (may be NULL) receive the choice. */
@@ -206,6 +206,13 @@ int cdem_read_contacts(cdem_scene *s, cdem_contacts_view *v);
 /* Per-clump force (contacts + gravity) and torque of the last recorded step,
  * host buffers [n_clumps][3]. */
 int cdem_read_clump_forces(cdem_scene *s, double *F, double *T);
+/* Per-boundary force (what the spheres exert on it: the sum of minus the
+ * contact forces on its spheres) and torque about its reference point (its
+ * first three parameters, moved with its translation) at the last recorded
+ * step; host buffers [n_bnd][3] in the description's boundary order.  The sum
+ * runs in a fixed order: reproducible, equal to an ascending sum up to
+ * rounding. */
+int cdem_read_boundary_forces(cdem_scene *s, double *F, double *T);
 /* Sphere centres of the current state, host buffer [n_spheres][3]. */
 int cdem_read_sphere_pos(cdem_scene *s, double *xs);
 
@@ -213,13 +220,28 @@ int cdem_read_sphere_pos(cdem_scene *s, double *xs);
  * state, compared with the active set.  O(N^2): for small scenes and tests. */
 int cdem_audit(cdem_scene *s, cdem_audit_result *r);
 
+/* ---- checkpoints ---- */
+/* Serialise the scene's dynamic state into a host buffer: clump state, step
+ * counter, detection schedule and settings, the active set with its FP64
+ * tangential history, the MLP parameters and the tuned launch settings.
+ * With cap = 0 only *len (the size needed) is set.  A scene created from the
+ * same description that loads the blob continues bit for bit as the saved
+ * scene would have (the restored active set is rebuilt, with its history,
+ * before the next step; results do not depend on when a rebuild happens). */
+int cdem_save(cdem_scene *s, void *buf, size_t cap, size_t *len);
+/* Restore a blob written by cdem_save into a scene created from the same
+ * description (checked through a fingerprint of the static description,
+ * counts and precision: CDEM_E_INVALID otherwise).  The blob is borrowed. */
+int cdem_load(cdem_scene *s, const void *buf, size_t len);
+
 /* ---- learned detection interval: envelope MLP ---- */
-/* The MLP maps per-bin features (max sphere speed, max acceleration envelope,
- * occupancy) to (log speed envelope, log acceleration envelope) over the next
- * detection interval; the margin of a bin's spheres is
+/* The MLP maps features of an envelope region (a block of 2 x 2 x 2 bins of
+ * the scene's grid: max sphere speed, max acceleration envelope, number of
+ * spheres) to (log speed envelope, log acceleration envelope) over the next
+ * detection interval; the margin of the region's spheres is
  * safety k h v_env + (k h)^2 a_env / 2, which enlarges the contact geometry
- * of the deferred active-set update (paper Sec. 2.2) per bin instead of with
- * one global speed bound.  Parameters are float32, cdem_mlp_param_count() of
+ * of the deferred active-set update (paper Sec. 2.2) per region instead of
+ * with one global speed bound.  Parameters are float32, cdem_mlp_param_count() of
  * them: mu[3], sigma[3] (input standardisation of u = (log(f0 + 1e-6),
  * log(f1 + 1e-3), log(1 + f2))), W1[64][3], b1[64], W2[64][64], b2[64],
  * W3[2][64], b3[2]. */
@@ -240,12 +262,13 @@ int cdem_mlp_backward(const float *params, const float *features, const float *t
  * are the moment buffers (device, zero-initialised by the caller). */
 int cdem_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t t, float lr, float beta1,
                   float beta2, float eps, void *stream);
-/* Training data from the scene's own trajectory: capture per-bin features of
- * the current state, advance `horizon` steps, and label each occupied bin with
- * the largest speed and acceleration envelope its spheres showed over those
- * steps, as (log(v + 1e-6), log(a + 1e-3)).  Host buffers features [cap][3],
- * labels [cap][2]; *n receives the number of occupied bins (call with cap = 0
- * to size; the steps still run). */
+/* Training data from the scene's own trajectory: capture the features of
+ * every envelope region of the current state, advance `horizon` steps, and
+ * label each occupied region with the largest speed and acceleration envelope
+ * its spheres (as binned at capture) showed over those steps, as
+ * (log(v + 1e-6), log(a + 1e-3)).  Host buffers features [cap][3],
+ * labels [cap][2]; *n receives the number of occupied regions (call with
+ * cap = 0 to size; the steps still run). */
 int cdem_collect_envelopes(cdem_scene *s, int32_t horizon, float *features, float *labels, int64_t cap,
                            int64_t *n);
 

@@ -73,6 +73,7 @@ def lib():
             "dem_oracle_read_contacts": (V, [P, P, P, P, P, P]),
             "dem_oracle_read_clump_forces": (V, [P, P, P]),
             "dem_oracle_read_sphere_forces": (V, [P, P, P]),
+            "dem_oracle_read_boundary_forces": (V, [P, P, P]),
             "dem_oracle_read_state": (V, [P, P, P, P, P]),
             "dem_oracle_read_sphere_pos": (V, [P, P]),
             "dem_oracle_n_spheres": (I64, [P]),
@@ -162,6 +163,12 @@ class Oracle:
     def sphere_forces(self):
         F = np.empty((self.n_spheres, 3)); T = np.empty((self.n_spheres, 3))
         lib().dem_oracle_read_sphere_forces(self._h, _ptr(F), _ptr(T))
+        return F, T
+
+    def boundary_forces(self):
+        """Force on each boundary and torque about its reference point (last evaluation)."""
+        F = np.empty((self.n_bnd, 3)); T = np.empty((self.n_bnd, 3))
+        lib().dem_oracle_read_boundary_forces(self._h, _ptr(F), _ptr(T))
         return F, T
 
     def state(self) -> dict:

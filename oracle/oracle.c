@@ -687,6 +687,21 @@ void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T) {
     if (T) memcpy(T, o->sT, 3 * o->ns * sizeof(double));
 }
 
+void dem_oracle_read_boundary_forces(const dem_oracle *o, double *F, double *T) {
+    /* Newton's third law on each boundary contact of the last evaluation, in
+     * ascending contact order: the boundary receives -F (F acts on the sphere)
+     * at the contact point, lever arm cra = p - (boundary reference point) */
+    for (int64_t i = 0; i < 3 * (int64_t)o->nb; i++) { F[i] = 0.0; T[i] = 0.0; }
+    for (int64_t k = 0; k < o->ncont; k++) {
+        int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu);
+        if (b < o->ns || !(o->cdelta[k] > 0.0)) continue;
+        int64_t w = b - o->ns;
+        double f[3] = {-o->cF[3 * k], -o->cF[3 * k + 1], -o->cF[3 * k + 2]}, tq[3];
+        cross(o->cra + 3 * k, f, tq);
+        for (int i = 0; i < 3; i++) { F[3 * w + i] = F[3 * w + i] + f[i]; T[3 * w + i] = T[3 * w + i] + tq[i]; }
+    }
+}
+
 void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w) {
     if (x) memcpy(x, o->x, 3 * o->nc * sizeof(double));
     if (q) memcpy(q, o->q, 4 * o->nc * sizeof(double));

@@ -86,6 +86,10 @@ void dem_oracle_read_contacts(const dem_oracle *o, uint32_t *a, uint32_t *b, dou
                               double *F, double *u);
 void dem_oracle_read_clump_forces(const dem_oracle *o, double *F, double *T);
 void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T);
+/* Force exerted on each boundary by the spheres (minus the contact forces on
+ * them) and its torque about the boundary's reference point, from the last
+ * evaluation; [n_bnd][3] each, in the description's boundary order. */
+void dem_oracle_read_boundary_forces(const dem_oracle *o, double *F, double *T);
 void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w);
 void dem_oracle_read_sphere_pos(const dem_oracle *o, double *xs);
 int64_t dem_oracle_n_spheres(const dem_oracle *o);

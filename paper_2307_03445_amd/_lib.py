@@ -103,6 +103,9 @@ SIGNATURES = {
     "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
     "cdem_set_graph": (C.c_int, [P, C.c_int32]),
     "cdem_autotune": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
+    "cdem_save": (C.c_int, [P, P, C.c_size_t, C.POINTER(C.c_size_t)]),
+    "cdem_read_boundary_forces": (C.c_int, [P, P, P]),
+    "cdem_load": (C.c_int, [P, P, C.c_size_t]),
 }
 
 _lib = None
@@ -265,6 +268,13 @@ class Scene:
         self._check(self._L.cdem_read_contacts(self._h, C.byref(v)))
         return out
 
+    def boundary_forces(self):
+        """Force on each boundary and torque about its reference point at the recorded step."""
+        n = self.n_bnd
+        F = np.zeros((n, 3)); T = np.zeros((n, 3))
+        self._check(self._L.cdem_read_boundary_forces(self._h, _ptr(F), _ptr(T)))
+        return F, T
+
     def clump_forces(self):
         F, T = np.empty((self.n_clumps, 3)), np.empty((self.n_clumps, 3))
         self._check(self._L.cdem_read_clump_forces(self._h, _ptr(F), _ptr(T)))
@@ -307,6 +317,18 @@ class Scene:
         return dict(bin_factor=f.value, stride_cap=c.value)
 
     # ---------------------------------------------------------------- learned envelopes
+    def save(self) -> bytes:
+        """Checkpoint of the scene's dynamic state (see cdem_save)."""
+        n = C.c_size_t(0)
+        self._check(self._L.cdem_save(self._h, None, 0, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(self._L.cdem_save(self._h, buf, n.value, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        """Restore a checkpoint written by :meth:`save` of a scene with the same description."""
+        self._check(self._L.cdem_load(self._h, blob, len(blob)))
+
     def set_mlp(self, params):
         p = np.ascontiguousarray(params, np.float32)
         self._check(self._L.cdem_set_mlp(self._h, _ptr(p), p.size))

@@ -90,10 +90,55 @@ struct cdem_scene {
     std::vector<Bnd> bnd;
     double rmax = 0.0;
     int64_t n_cells_alloc = 0;
+    int64_t n_regions_alloc = 0;
     int64_t rec_cap = 0;
     std::vector<void *> owned;         // every device allocation, freed on destroy
     int64_t regrows = 0;
+    uint64_t fingerprint = 0;          // of the description's static parts (checkpoints must match)
 };
+
+// FNV-1a over raw bytes: identifies the static description a checkpoint belongs to.
+static uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = (const unsigned char *)p;
+    for (size_t i = 0; i < n; i++) { h ^= b[i]; h *= 1099511628211ull; }
+    return h;
+}
+
+static uint64_t desc_fingerprint(const cdem_scene_desc *d, int64_t ns) {
+    uint64_t h = 14695981039346656037ull;
+    uint32_t nts = d->tmpl_sphere_begin[d->n_templates];
+    h = fnv1a(h, &d->h, 8);
+    h = fnv1a(h, &d->n_templates, 4);
+    h = fnv1a(h, d->tmpl_sphere_begin, 4 * ((size_t)d->n_templates + 1));
+    h = fnv1a(h, d->tmpl_offset, 24 * (size_t)nts);
+    h = fnv1a(h, d->tmpl_radius, 8 * (size_t)nts);
+    h = fnv1a(h, d->tmpl_mass, 8 * (size_t)d->n_templates);
+    h = fnv1a(h, d->tmpl_inertia, 24 * (size_t)d->n_templates);
+    h = fnv1a(h, &d->n_clumps, 8);
+    if (d->n_clumps) {
+        h = fnv1a(h, d->clump_template, 4 * (size_t)d->n_clumps);
+        h = fnv1a(h, d->clump_scene, 4 * (size_t)d->n_clumps);
+    }
+    if (ns) h = fnv1a(h, d->sphere_mat, 32 * (size_t)ns);
+    h = fnv1a(h, &d->n_scenes, 4);
+    h = fnv1a(h, d->gravity, 24 * (size_t)d->n_scenes);
+    h = fnv1a(h, d->domain, 48 * (size_t)d->n_scenes);
+    h = fnv1a(h, &d->n_bnd, 4);
+    if (d->n_bnd) {
+        h = fnv1a(h, d->bnd_type, 4 * (size_t)d->n_bnd);
+        h = fnv1a(h, d->bnd_param, 96 * (size_t)d->n_bnd);
+        h = fnv1a(h, d->bnd_mat, 32 * (size_t)d->n_bnd);
+        h = fnv1a(h, d->bnd_vel, 24 * (size_t)d->n_bnd);
+        h = fnv1a(h, d->bnd_omega, 24 * (size_t)d->n_bnd);
+        h = fnv1a(h, d->bnd_scene, 4 * (size_t)d->n_bnd);
+    }
+    h = fnv1a(h, &d->n_presc, 4);
+    if (d->n_presc) {
+        h = fnv1a(h, d->presc_clump, 4 * (size_t)d->n_presc);
+        h = fnv1a(h, d->presc_param, 96 * (size_t)d->n_presc);
+    }
+    return h;
+}
 
 static const char *kErrNames[] = {"ok", "invalid argument", "out of device memory", "HIP runtime error",
                                   "active-set capacity exceeded", "missed contact", "non-finite state",
@@ -177,7 +222,7 @@ static int build_grids(cdem_scene *sc) {
     // only the bins that reach touches
     double b = (sc->rmax + std::max(0.0, sc->det.margin_cap)) * sc->bin_factor;
     if (!(b > 0.0)) b = 1.0;  // no spheres: any positive bin size will do
-    int64_t cell0 = 0;
+    int64_t cell0 = 0, reg0 = 0;
     for (int k = 0; k < S.n_scenes; k++) {
         Grid &g = sc->grids[k];
         const double *d = &sc->dom[6 * k];
@@ -206,7 +251,14 @@ static int build_grids(cdem_scene *sc) {
         g.nx = (int32_t)nx; g.ny = (int32_t)ny; g.nz = (int32_t)nz;
         g.cell0 = cell0;
         cell0 += nx * ny * nz;
+        g.rnx = (int32_t)((nx + kRegionBins - 1) / kRegionBins);
+        g.rny = (int32_t)((ny + kRegionBins - 1) / kRegionBins);
+        g.rnz = (int32_t)((nz + kRegionBins - 1) / kRegionBins);
+        g.rpad = 0;
+        g.reg0 = reg0;
+        reg0 += (int64_t)g.rnx * g.rny * g.rnz;
     }
+    S.n_regions = reg0;
     if (cell0 >= ((int64_t)1 << 32)) return fail(sc, CDEM_E_INVALID, "too many bins");
     S.n_cells = cell0;
     int rc = CDEM_OK;
@@ -228,17 +280,21 @@ static int build_grids(cdem_scene *sc) {
         S.cell_start = (uint32_t *)dev_alloc(sc, cell0 * 4);
         S.cell_fill = (uint32_t *)dev_alloc(sc, (cell0 + nblk) * 4);  // + scan block sums
         if (!S.cell_count || !S.cell_start || !S.cell_fill) return fail(sc, CDEM_E_OOM, "bin arrays");
-        dev_free(sc, S.bin_v); dev_free(sc, S.bin_a); dev_free(sc, S.bin_margin);
-        dev_free(sc, S.occ_t); dev_free(sc, S.lab_v); dev_free(sc, S.lab_a);
-        S.bin_v = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.bin_a = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.bin_margin = (float *)dev_alloc(sc, cell0 * 4);
-        S.occ_t = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.lab_v = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.lab_a = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        if (!S.bin_v || !S.bin_a || !S.bin_margin || !S.occ_t || !S.lab_v || !S.lab_a)
-            return fail(sc, CDEM_E_OOM, "bin arrays");
         sc->n_cells_alloc = cell0;
+    }
+    if (reg0 > sc->n_regions_alloc) {
+        dev_free(sc, S.bin_v); dev_free(sc, S.bin_a); dev_free(sc, S.reg_occ); dev_free(sc, S.bin_margin);
+        dev_free(sc, S.occ_t); dev_free(sc, S.lab_v); dev_free(sc, S.lab_a);
+        S.bin_v = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        S.bin_a = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        S.reg_occ = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        S.bin_margin = (float *)dev_alloc(sc, reg0 * 4);
+        S.occ_t = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        S.lab_v = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        S.lab_a = (uint32_t *)dev_alloc(sc, reg0 * 4);
+        if (!S.bin_v || !S.bin_a || !S.reg_occ || !S.bin_margin || !S.occ_t || !S.lab_v || !S.lab_a)
+            return fail(sc, CDEM_E_OOM, "region arrays");
+        sc->n_regions_alloc = reg0;
     }
     return CDEM_OK;
 }
@@ -253,16 +309,15 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
         if (!nb[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
     }
     // per-entry arrays derived at each detection (no content to keep)
-    dev_free(sc, S.eself); dev_free(sc, S.emirror); dev_free(sc, S.pairs); dev_free(sc, S.eflag);
+    dev_free(sc, S.eself); dev_free(sc, S.emirror); dev_free(sc, S.eflag);
     dev_free(sc, S.cA); dev_free(sc, S.cB);
     size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 4 : 8;  // contribution word size
     S.eself = (uint32_t *)dev_alloc(sc, cap * 4);
     S.emirror = (uint32_t *)dev_alloc(sc, cap * 4);
-    S.pairs = (uint32_t *)dev_alloc(sc, cap * 4);
     S.eflag = (uint8_t *)dev_alloc(sc, cap);
     S.cA = dev_alloc(sc, cap * 4 * cw);
     S.cB = dev_alloc(sc, cap * 2 * cw);
-    if (!S.eself || !S.emirror || !S.pairs || !S.eflag || !S.cA || !S.cB)
+    if (!S.eself || !S.emirror || !S.eflag || !S.cA || !S.cB)
         return fail(sc, CDEM_E_OOM, "active-set storage");
     if (keep) {
         // preserve the current buffer (rows point into it)
@@ -281,8 +336,8 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     for (int k = 0; k < 2; k++) { S.nbr[k] = nb[k]; S.hist[k] = hs[k]; }
     S.cap = cap;
     if (sc->rec_cap) {  // recording arrays follow the capacity
-        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F);
-        S.rec_state = nullptr; S.rec_delta = nullptr; S.rec_F = nullptr;
+        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
+        S.rec_state = nullptr; S.rec_delta = nullptr; S.rec_F = nullptr; S.rec_R = nullptr;
         sc->rec_cap = 0;
     }
     return CDEM_OK;
@@ -386,6 +441,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         mat32[s] = make_float4((float)e, (float)g, (float)m[2], (float)b);
     }
     sc->rmax = rmax;
+    sc->fingerprint = desc_fingerprint(d, ns);
     // boundaries sorted by scene
     std::vector<int32_t> order(d->n_bnd);
     for (int k = 0; k < d->n_bnd; k++) order[k] = k;
@@ -513,7 +569,11 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.sspeed = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cacc = (float *)dev_alloc(sc, 4 * std::max<int64_t>(nc, 1));
     S.cell_t = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    if (!S.sspeed || !S.cacc || !S.cell_t) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    // spheres with more than kMaxRow candidates are rare (a large sphere among
+    // many small ones); a list of ns/32 (at least 4096) of them per detection
+    S.over_cap = std::max<int64_t>(4096, ns / 32);
+    S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
+    if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     for (int k = 0; k < 2; k++) {
         S.row_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
         S.row_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
@@ -656,7 +716,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         if (c.nonfinite) return fail(sc, CDEM_E_NAN, "non-finite clump state");
         if (!c.overflow) break;
         if (c.row_overflow)
-            return fail(sc, CDEM_E_CAPACITY, "a sphere has more than 64 candidate partners (margin or bin too large)");
+            return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 32 candidate partners (margin too large)");
         if (c.asym) return fail(sc, CDEM_E_STATE, "active-set rows are not symmetric");
         // grow the active set and resume from the step that did not complete
         int64_t need = (int64_t)(1.3 * (double)c.n_entries) + 1024;
@@ -717,11 +777,12 @@ extern "C" int cdem_record_next_step(cdem_scene *sc, int on) {
     if (!sc) return CDEM_E_INVALID;
     DevScene &S = sc->S;
     if (on && sc->rec_cap < S.cap) {
-        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F);
+        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
         S.rec_state = (uint8_t *)dev_alloc(sc, S.cap);
         S.rec_delta = (double *)dev_alloc(sc, 8 * S.cap);
         S.rec_F = (double *)dev_alloc(sc, 24 * S.cap);
-        if (!S.rec_state || !S.rec_delta || !S.rec_F) return fail(sc, CDEM_E_OOM, "recording buffers");
+        S.rec_R = (double *)dev_alloc(sc, 24 * S.cap);
+        if (!S.rec_state || !S.rec_delta || !S.rec_F || !S.rec_R) return fail(sc, CDEM_E_OOM, "recording buffers");
         sc->rec_cap = S.cap;
     }
     Ctl c;
@@ -870,6 +931,36 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
     return CDEM_OK;
 }
 
+extern "C" int cdem_read_boundary_forces(cdem_scene *sc, double *F, double *T) {
+    if (!sc) return CDEM_E_INVALID;
+    const DevScene &S = sc->S;
+    if (!sc->rec_cap) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
+    const int nb = S.n_bnd;
+    if (nb == 0) return CDEM_OK;
+    double *part = (double *)dev_alloc(sc, sizeof(double) * 6 * kBndParts * (size_t)nb);
+    double *out = (double *)dev_alloc(sc, sizeof(double) * 6 * (size_t)nb);
+    std::vector<double> h(6 * (size_t)nb);
+    int rc = CDEM_OK;
+    if (!part || !out) {
+        rc = fail(sc, CDEM_E_OOM, "boundary force buffers");
+    } else if (launch_bnd_forces(S, part, out, sc->stream) != hipSuccess ||
+               hipStreamSynchronize(sc->stream) != hipSuccess ||
+               hipMemcpy(h.data(), out, h.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) {
+        rc = fail(sc, CDEM_E_HIP, "boundary force reduction");
+    }
+    dev_free(sc, part);
+    dev_free(sc, out);
+    if (rc) return rc;
+    for (int b = 0; b < nb; b++) {
+        const int u = sc->bnd_user[b];
+        for (int k = 0; k < 3; k++) {
+            if (F) F[3 * u + k] = h[6 * b + k];
+            if (T) T[3 * u + k] = h[6 * b + 3 + k];
+        }
+    }
+    return CDEM_OK;
+}
+
 extern "C" int cdem_read_clump_forces(cdem_scene *sc, double *F, double *T) {
     if (!sc) return CDEM_E_INVALID;
     HIPCHK(hipStreamSynchronize(sc->stream));
@@ -973,7 +1064,7 @@ extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *fe
     hipError_t e = launch_pose(S, 0, sc->stream);
     if (e == hipSuccess) e = launch_collect_begin(S, sc->stream);
     if (e != hipSuccess) return restore(fail(sc, CDEM_E_HIP, hipGetErrorString(e)));
-    int64_t nb = S.n_cells;
+    int64_t nb = S.n_regions;
     std::vector<uint32_t> fv(nb), fa(nb), occ(nb), lv(nb), la(nb);
     if (hipStreamSynchronize(sc->stream) != hipSuccess ||
         hipMemcpy(fv.data(), S.bin_v, 4 * nb, hipMemcpyDeviceToHost) != hipSuccess ||
@@ -1064,4 +1155,132 @@ extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, 
     if (bin_factor) *bin_factor = bf;
     if (stride_cap) *stride_cap = bc;
     return CDEM_OK;
+}
+
+// ---------------------------------------------------------------- checkpoints
+namespace {
+struct SaveHeader {
+    char magic[8];
+    int32_t abi, precision;
+    int64_t nc, ns, n_bnd, n_scenes;
+    uint64_t fingerprint;
+    int64_t entries;
+    cdem_detect_params det;
+    int32_t has_mlp, stride_cap;
+    double bin_factor;
+    Ctl ctl;
+};
+constexpr char kSaveMagic[8] = {'C', 'D', 'E', 'M', 'S', 'A', 'V', '1'};
+
+size_t save_size(const DevScene &S, int64_t entries, bool mlp) {
+    return sizeof(SaveHeader) + 13 * 8 * (size_t)S.nc + 8 * (size_t)S.ns + 4 * (size_t)entries +
+           24 * (size_t)entries + (mlp ? 4 * (size_t)cdem_mlp_param_count() : 0);
+}
+}  // namespace
+
+// Device arrays of the clump state in checkpoint order: x, q, v, w (13 columns).
+static void state_arrays(const DevScene &S, double *out[13]) {
+    double *a[13] = {S.px, S.py, S.pz, S.qw, S.qx, S.qy, S.qz, S.vx, S.vy, S.vz, S.wx, S.wy, S.wz};
+    for (int i = 0; i < 13; i++) out[i] = a[i];
+}
+
+extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
+    if (!sc || !len || (cap > 0 && !buf)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    const DevScene &S = sc->S;
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    const int64_t E = c.n_entries_cur;
+    const bool mlp = S.mlp != nullptr;
+    const size_t need = save_size(S, E, mlp);
+    *len = need;
+    if (cap == 0) return CDEM_OK;
+    if (cap < need) return fail(sc, CDEM_E_INVALID, "checkpoint buffer too small");
+    SaveHeader hd{};
+    memcpy(hd.magic, kSaveMagic, 8);
+    hd.abi = CDEM_ABI_VERSION;
+    hd.precision = S.precision;
+    hd.nc = S.nc; hd.ns = S.ns; hd.n_bnd = S.n_bnd; hd.n_scenes = S.n_scenes;
+    hd.fingerprint = sc->fingerprint;
+    hd.entries = E;
+    hd.det = sc->det;
+    hd.has_mlp = mlp ? 1 : 0;
+    hd.stride_cap = S.stride_cap;
+    hd.bin_factor = sc->bin_factor;
+    hd.ctl = c;
+    char *o = (char *)buf;
+    memcpy(o, &hd, sizeof hd);
+    o += sizeof hd;
+    double *arr[13];
+    state_arrays(S, arr);
+    for (int i = 0; i < 13; i++) {
+        if (S.nc) HIPCHK(hipMemcpy(o, arr[i], 8 * S.nc, hipMemcpyDeviceToHost));
+        o += 8 * S.nc;
+    }
+    const int cur = c.buf;
+    if (S.ns) {
+        HIPCHK(hipMemcpy(o, S.row_beg[cur], 4 * S.ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o + 4 * S.ns, S.row_cnt[cur], 4 * S.ns, hipMemcpyDeviceToHost));
+    }
+    o += 8 * S.ns;
+    if (E) {
+        HIPCHK(hipMemcpy(o, S.nbr[cur], 4 * E, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o + 4 * E, S.hist[cur], 24 * E, hipMemcpyDeviceToHost));
+    }
+    o += 28 * E;
+    if (mlp) HIPCHK(hipMemcpy(o, S.mlp, 4 * (size_t)cdem_mlp_param_count(), hipMemcpyDeviceToHost));
+    return CDEM_OK;
+}
+
+extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
+    if (!sc || !buf || len < sizeof(SaveHeader)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    SaveHeader hd;
+    memcpy(&hd, buf, sizeof hd);
+    DevScene &S = sc->S;
+    if (memcmp(hd.magic, kSaveMagic, 8) != 0 || hd.abi != CDEM_ABI_VERSION)
+        return fail(sc, CDEM_E_INVALID, "not a checkpoint of this library version");
+    if (hd.precision != S.precision || hd.nc != S.nc || hd.ns != S.ns || hd.n_bnd != S.n_bnd ||
+        hd.n_scenes != S.n_scenes || hd.fingerprint != sc->fingerprint)
+        return fail(sc, CDEM_E_INVALID, "checkpoint belongs to another scene description");
+    const int64_t E = hd.entries;
+    if (E < 0 || E >= ((int64_t)1 << 32) || len != save_size(S, E, hd.has_mlp != 0))
+        return fail(sc, CDEM_E_INVALID, "checkpoint size does not match its header");
+    const char *p = (const char *)buf + sizeof hd;
+    const char *rows = p + 13 * 8 * (size_t)S.nc;
+    const uint32_t *rb = (const uint32_t *)rows, *rn = (const uint32_t *)(rows + 4 * S.ns);
+    for (int64_t s = 0; s < S.ns; s++)
+        if ((uint64_t)rb[s] + rn[s] > (uint64_t)E) return fail(sc, CDEM_E_INVALID, "checkpoint rows out of range");
+    int rc;
+    if (hd.has_mlp) {
+        const float *w = (const float *)(rows + 8 * S.ns + 28 * (size_t)E);
+        if ((rc = cdem_set_mlp(sc, w, (size_t)cdem_mlp_param_count())) != CDEM_OK) return rc;
+    }
+    sc->bin_factor = hd.bin_factor > 0.0 ? hd.bin_factor : 1.0;
+    S.stride_cap = hd.stride_cap > 0 ? hd.stride_cap : 16384;
+    if ((rc = cdem_set_detection(sc, &hd.det)) != CDEM_OK) return rc;
+    if (E > S.cap && (rc = alloc_active_set(sc, E + E / 4 + 1024, false)) != CDEM_OK) return rc;
+    Ctl c;
+    if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
+    const int cur = c.buf;
+    double *arr[13];
+    state_arrays(S, arr);
+    for (int i = 0; i < 13; i++)
+        if (S.nc) HIPCHK(hipMemcpy(arr[i], p + 8 * S.nc * (size_t)i, 8 * S.nc, hipMemcpyHostToDevice));
+    if (S.ns) {
+        HIPCHK(hipMemcpy(S.row_beg[cur], rb, 4 * S.ns, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.row_cnt[cur], rn, 4 * S.ns, hipMemcpyHostToDevice));
+    }
+    if (E) {
+        HIPCHK(hipMemcpy(S.nbr[cur], rows + 8 * S.ns, 4 * E, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.hist[cur], rows + 8 * S.ns + 4 * E, 24 * E, hipMemcpyHostToDevice));
+    }
+    // resume the saved schedule on this scene's buffers; the active set is
+    // rebuilt (with the saved history carried over) before the next step
+    Ctl n = hd.ctl;
+    n.buf = cur;
+    n.n_entries_cur = E;
+    n.det_due = 1;
+    n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;
+    n.guard = 0;
+    return write_ctl(sc, n);
 }

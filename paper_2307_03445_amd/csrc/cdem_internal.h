@@ -9,8 +9,9 @@ namespace cdem {
 
 constexpr int kMaxBnd = 64;
 constexpr int kNarrowBlock = 64;   // one wavefront per workgroup in the narrow phase
-constexpr int kMaxRow = 64;        // candidates one sphere may hold (per detection)
+constexpr int kMaxRow = 32;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
+constexpr int kRegionBins = 2;     // edge of an envelope region of the learned margins, in bins
 
 // Analytic boundary as the kernels see it (geometry at t = 0 plus motion).
 struct Bnd {
@@ -34,6 +35,8 @@ struct Grid {
     float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
     double b;                // bin size
     double rm_max;           // largest radius + largest margin of any sphere (the partner side of a reach)
+    int32_t rnx, rny, rnz, rpad;  // envelope regions: blocks of kRegionBins^3 bins
+    int64_t reg0;            // first global region id of the scene
 };
 
 // Device-resident control block: decides on the device whether a detection
@@ -48,11 +51,11 @@ struct Ctl {
     int32_t since_det;       // steps completed since the last detection
     int32_t k_cur;           // current detection interval
     int32_t overflow;        // active-set storage overflowed: later kernels of the step skip
-    int32_t row_overflow;    // a sphere exceeded kMaxRow candidates
+    int32_t row_overflow;    // more spheres exceeded kMaxRow candidates than the overflow list holds
     int32_t guard;           // a sphere moved past its margin this step
     int32_t record;          // store per-contact data this step
     int32_t nonfinite;       // a clump state became NaN/Inf
-    int32_t pad;
+    int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
     int64_t contacts_acc;    // true contacts (exact predicate, delta > 0) of the step in progress
     int64_t contacts_last;   // ... of the last completed step (each pair counted from both sides)
     int64_t n_pairs;         // pairs of the detection in progress
@@ -120,13 +123,15 @@ struct DevScene {
     double *hist[2];                 // [cap][3]
     // per entry of the current active set (rebuilt at every detection)
     uint32_t *eself;                 // the row's own sphere
+    uint32_t *over_list;             // [over_cap] spheres whose rows k_narrow_over fills
+    int64_t over_cap;
     uint32_t *emirror;               // for a lower entry (s < t): t's entry for s
-    uint32_t *pairs;                 // lower entries (s < t, or boundaries): one per pair
     uint8_t *eflag;                  // the entry's pair is in contact this step
     void *cA, *cB;                   // contribution to the row's sphere: (F, Tx), (Ty, Tz)
     // recording
     uint8_t *rec_state;
     double *rec_delta, *rec_F;       // [cap], [cap][3]
+    double *rec_R;                   // [cap][3] boundary entries: contact point relative to the boundary's reference point
     double *rec_cF, *rec_cT;         // [nc][3]
     const Bnd *bnd;
     Ctl *ctl;
@@ -141,10 +146,12 @@ struct DevScene {
     int32_t store_acc;               // integration writes each clump's acceleration envelope to cacc
     float *sspeed;                   // [ns]
     float *cacc;                     // [nc]
-    uint32_t *bin_v, *bin_a;         // [n_cells] max speed / acceleration in the bin (float bits)
-    float *bin_margin;               // [n_cells] margin of the bin's spheres this detection
+    int64_t n_regions;               // envelope regions (learned margins), over all scenes
+    uint32_t *bin_v, *bin_a;         // [n_regions] max speed / acceleration in the region (float bits)
+    uint32_t *reg_occ;               // [n_regions] spheres in the region
+    float *bin_margin;               // [n_regions] margin of the region's spheres this detection
     const float *mlp;                // envelope MLP parameters (device), null if none loaded
-    uint32_t *cell_t, *occ_t;        // collection: bins of the spheres and bin occupancy at capture
+    uint32_t *cell_t, *occ_t;        // collection: regions of the spheres and region occupancy at capture
     uint32_t *lab_v, *lab_a;         // collection: max speed / acceleration over the horizon (float bits)
     // wave schedule of the force kernel: wave w covers clumps wave_clump0[2w] ..
     // wave_clump0[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
@@ -164,7 +171,7 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_MIRROR, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_COUNT };
+                K_MIRROR, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 
@@ -182,5 +189,8 @@ hipError_t launch_collect_begin(const DevScene &S, hipStream_t st);
 hipError_t launch_collect_speed(const DevScene &S, hipStream_t st);
 hipError_t launch_collect_acc(const DevScene &S, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+// Force and torque on every boundary from the recorded step: partial [n_bnd][kBndParts][6], out [n_bnd][6].
+constexpr int kBndParts = 64;
+hipError_t launch_bnd_forces(const DevScene &S, double *partial, double *out, hipStream_t st);
 
 }  // namespace cdem

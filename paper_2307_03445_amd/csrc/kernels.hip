@@ -211,6 +211,27 @@ __device__ __forceinline__ void scan_reach(const DevScene &S, const Grid &g, dou
     }
 }
 
+// Envelope region (block of kRegionBins^3 bins of the scene's grid) of a bin.
+__device__ __forceinline__ int64_t region_of(const Grid &g, uint32_t cell) {
+    // a scene holds at most 2^27 bins: 32-bit division suffices
+    uint32_t r = (uint32_t)((int64_t)cell - g.cell0);
+    uint32_t ix = r % (uint32_t)g.nx, t = r / (uint32_t)g.nx;
+    uint32_t iy = t % (uint32_t)g.ny, iz = t / (uint32_t)g.ny;
+    return g.reg0 + ix / kRegionBins + (int64_t)g.rnx * (iy / kRegionBins + (int64_t)g.rny * (iz / kRegionBins));
+}
+
+// The hardware hands workgroup i of a launch to XCD i mod 8, and each XCD has
+// its own L2.  xcd_block() renumbers the workgroups so that every XCD works on
+// one contiguous range of logical blocks: neighbouring items (spheres of one
+// bin, pairs of nearby spheres, the spheres of a clump) then share one L2
+// instead of being fetched by several.  A bijection of [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t x = b % kXcds, k = b / kXcds, per = n / kXcds, rem = n % kXcds;
+    return x * per + min(x, rem) + k;
+}
+
 __device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
 __device__ __forceinline__ bool audit_due(const DevScene &S) {
     return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
@@ -229,9 +250,12 @@ __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
     for (int64_t k = i; k < S.n_cells; k += stride) {
         S.cell_count[k] = 0;
         S.cell_fill[k] = 0;
-        if (bins) { S.bin_v[k] = 0; S.bin_a[k] = 0; }
     }
-    if (i == 0 && !which) { S.ctl->n_entries = 0; S.ctl->n_pairs = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0; }
+    if (bins)
+        for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
+    if (i == 0 && !which) {
+        S.ctl->n_entries = 0; S.ctl->n_pairs = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0; S.ctl->n_over = 0;
+    }
     if (i == 0 && which == 1) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
 }
 
@@ -324,8 +348,8 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_owner[slot] = S.owner[s];
     S.sorted_pos[slot] = p;
     if (which) return;
-    float m = S.detect_mode == 2 ? S.bin_margin[cell] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
     const Grid &g = S.grids[S.sscene[s]];
+    float m = S.detect_mode == 2 ? S.bin_margin[region_of(g, cell)] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
     S.smargin[s] = m;
@@ -340,7 +364,11 @@ __global__ void k_plan(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c)) return;
     if (S.detect_mode == 0) { c->margin_cur = 0.0f; c->k_cur = 1; return; }
-    if (S.detect_mode == 2) { c->k_cur = S.plan.k_max; c->margin_cur = 0.0f; return; }  // per-bin margins
+    if (S.detect_mode == 2) {  // per-region margins; k_bin_margin may shorten the interval
+        c->k_cur = S.plan.k_max;
+        c->margin_cur = 0.0f;
+        return;
+    }
     float v = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
     float a = __uint_as_float(c->amax_last);
     int k = S.plan.k_max;
@@ -358,37 +386,43 @@ __global__ void k_plan(DevScene S) {
 }
 
 // ---------------------------------------------------------------- learned envelopes
-// Per-bin features of the current state: max sphere speed, max acceleration
-// envelope of the spheres' clumps (last step), occupancy (the bin count).
+// Features of the envelope regions (blocks of kRegionBins^3 bins): max sphere
+// speed, max acceleration envelope of the spheres' clumps (last step),
+// occupancy (spheres in the region).
 __global__ void __launch_bounds__(256) k_bin_features(DevScene S, int which) {
     if (!(which == 2 || (due(S.ctl) && S.detect_mode == 2))) return;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S.ns) return;
-    uint32_t cell = S.cell_of[s];
+    int64_t r = region_of(S.grids[S.sscene[s]], S.cell_of[s]);
     float v = S.sspeed[s], a = S.cacc[S.owner[s]];
-    if (v > 0.f) atomicMax(&S.bin_v[cell], __float_as_uint(v));
-    if (a > 0.f) atomicMax(&S.bin_a[cell], __float_as_uint(a));
+    if (v > 0.f) atomicMax(&S.bin_v[r], __float_as_uint(v));
+    if (a > 0.f) atomicMax(&S.bin_a[r], __float_as_uint(a));
+    atomicAdd(&S.reg_occ[r], 1u);
 }
 
-// Margin of each occupied bin for this detection: the MLP predicts the bin's
-// speed and acceleration envelopes over the interval (never below what the
-// bin shows now); a non-finite or implausible prediction falls back to the
-// fixed rule's global envelopes.  m = safety k h v + (k h)^2 a / 2.
+// Envelopes of each occupied region for this detection: the MLP predicts the
+// region's speed and acceleration envelopes over the interval (never below
+// what the region shows now); a non-finite or implausible prediction falls
+// back to the fixed rule's global envelopes.  The envelopes replace the
+// features in bin_v / bin_a.  The interval becomes the longest k <= k_max
+// whose margin m = safety k h v + (k h)^2 a / 2 stays within the cap in every
+// region (reduced on the device; k_plan starts it at k_max).
 __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || S.detect_mode != 2) return;
     __shared__ float P[kMlpParams];
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) P[i] = S.mlp[i];
     __syncthreads();
-    const double T = (double)c->k_cur * S.h;
     const float vg = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
     const float ag = __uint_as_float(c->amax_last);
+    const int kmax = S.plan.k_max;
     uint32_t nfb = 0;
-    for (int64_t cell = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; cell < S.n_cells;
-         cell += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t occ = S.cell_count[cell];
+    int kmin = kmax;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t occ = S.reg_occ[r];
         if (!occ) continue;
-        float vn = __uint_as_float(S.bin_v[cell]), an = __uint_as_float(S.bin_a[cell]);
+        float vn = __uint_as_float(S.bin_v[r]), an = __uint_as_float(S.bin_a[r]);
         float y0, y1;
         mlp_forward(P, vn, an, (float)occ, y0, y1);
         float ve = expf(y0), ae = expf(y1);
@@ -399,25 +433,52 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
         }
         ve = fmaxf(ve, vn);
         ae = fmaxf(ae, an);
-        double m = (double)S.plan.safety * (T * (double)ve) + 0.5 * (double)ae * T * T;
-        m = fmin(fmax(m, (double)S.plan.margin_floor), (double)S.plan.margin_cap);
-        S.bin_margin[cell] = (float)m;
+        S.bin_v[r] = __float_as_uint(ve);
+        S.bin_a[r] = __float_as_uint(ae);
+        int k = kmax;
+        for (; k > 1; k--) {
+            const double T = (double)k * S.h;
+            if ((double)S.plan.safety * (T * (double)ve) + 0.5 * (double)ae * T * T <= (double)S.plan.margin_cap) break;
+        }
+        kmin = min(kmin, k);
     }
-    for (int off = 32; off > 0; off >>= 1) nfb += __shfl_xor(nfb, off, 64);
-    if ((threadIdx.x & 63) == 0 && nfb) atomicAdd((unsigned long long *)&c->fallbacks, (unsigned long long)nfb);
+    for (int off = 32; off > 0; off >>= 1) {
+        nfb += __shfl_xor(nfb, off, 64);
+        kmin = min(kmin, __shfl_xor(kmin, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (nfb) atomicAdd((unsigned long long *)&c->fallbacks, (unsigned long long)nfb);
+        if (kmin < kmax) atomicMin(&c->k_cur, kmin);
+    }
 }
 
-// Training-data capture: remember each sphere's bin and each bin's occupancy
-// at capture time, and clear the horizon labels.
+// Margin of every occupied region for the interval chosen above (clamped to
+// [floor, cap]: a region that still needs more relies on the guard).
+__global__ void __launch_bounds__(256) k_region_margin(DevScene S) {
+    const Ctl *c = S.ctl;
+    if (!due(c) || S.detect_mode != 2) return;
+    const double T = (double)c->k_cur * S.h;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (!S.reg_occ[r]) continue;
+        const double ve = (double)__uint_as_float(S.bin_v[r]), ae = (double)__uint_as_float(S.bin_a[r]);
+        double m = (double)S.plan.safety * (T * ve) + 0.5 * ae * T * T;
+        m = fmin(fmax(m, (double)S.plan.margin_floor), (double)S.plan.margin_cap);
+        S.bin_margin[r] = S.plan.test_zero_margin ? 0.0f : (float)m;
+    }
+}
+
+// Training-data capture: remember each sphere's region and each region's
+// occupancy at capture time, and clear the horizon labels.
 __global__ void __launch_bounds__(256) k_collect_init(DevScene S) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t k = i; k < S.ns; k += stride) S.cell_t[k] = S.cell_of[k];
-    for (int64_t k = i; k < S.n_cells; k += stride) { S.occ_t[k] = S.cell_count[k]; S.lab_v[k] = 0; S.lab_a[k] = 0; }
+    for (int64_t k = i; k < S.ns; k += stride) S.cell_t[k] = (uint32_t)region_of(S.grids[S.sscene[k]], S.cell_of[k]);
+    for (int64_t k = i; k < S.n_regions; k += stride) { S.occ_t[k] = S.reg_occ[k]; S.lab_v[k] = 0; S.lab_a[k] = 0; }
 }
 
 // Horizon labels: the largest speed / acceleration envelope any sphere of the
-// bin (as binned at capture) shows during the following steps.
+// region (as binned at capture) shows during the following steps.
 __global__ void __launch_bounds__(256) k_collect_speed(DevScene S) {
     if (!S.ctl->collecting) return;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -447,91 +508,64 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &total) 
     return x - v;
 }
 
-__global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
-    if (!due(S.ctl)) return;
-    __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
-    const int tid = threadIdx.x;
-    // one thread per sphere id: ids are spatially coherent (clumps are laid out
-    // in Morton order), so a wavefront's neighbour scans share cache lines and
-    // the rows, and the pair list built from them, come out in that order
-    int64_t i = (int64_t)blockIdx.x * kNarrowBlock + tid;
-    const int cur = S.ctl->buf, nxt = cur ^ 1;
-    int cnt = 0;
-    bool over = false;
-    uint32_t s = 0;
-    if (i < S.ns) {
-        s = (uint32_t)i;
-        double4 P = S.spos[s];
-        uint32_t own = S.owner[s];
-        float ms = S.smargin[s];
-        const Grid &g = S.grids[S.sscene[s]];
-        const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w + ms);
-        const float eps = g.pre_eps;
-        // far outside the domain the slack no longer bounds the rounding: exact test only
-        const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
-        // reach of s: its own (R + m) plus the largest partner (R + m); a small
-        // absolute slack keeps the bin selection conservative under rounding
-        const double reach = (P.w + (double)ms) + g.rm_max + 1e-9;
-        scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
-            for (uint32_t j = jb; j < je; j++) {
-                // conservative FP32 test first: it can only admit extra candidates,
-                // which the exact FP64 predicate below then rejects
-                float4 Qf = S.sorted_f4[j];
-                float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z;
-                float fr = (Pf.w + Qf.w) + eps;
-                if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
-                if (S.sorted_owner[j] == own) continue;
-                double4 Q = S.sorted_pos[j];
-                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                double d2 = dx * dx + dy * dy + dz * dz;
-                double Sr = P.w + Q.w;
-                Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
-                if (d2 < Sr * Sr) {
-                    uint32_t t = S.sorted_id[j];
-                    if (cnt == kMaxRow) { over = true; continue; }
-                    int k = cnt;
-                    while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
-                        lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
-                        k--;
-                    }
-                    lst[k * kNarrowBlock + tid] = t;
-                    cnt++;
-                }
-            }
-        });
-        double tnow = (double)S.ctl->step * S.h;
-        for (int b = g.bnd_beg; b < g.bnd_end; b++) {
-            double phi, n[3];
-            if (!bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n)) continue;
-            double lim = P.w + ((double)ms + S.bnd[b].margin);
-            if (phi < lim) {
-                if (cnt == kMaxRow) { over = true; continue; }
-                lst[cnt * kNarrowBlock + tid] = (uint32_t)(S.ns + b);
-                cnt++;
-            }
+// Candidate partners of sphere s for the detection in progress, in no
+// particular order: spheres of other clumps inside the enlarged contact
+// geometry, d^2 < ((R_s + R_t) + (m_s + m_t))^2, then boundaries with
+// phi < R_s + (m_s + boundary margin).  emit(t) is called once per candidate.
+template <class Emit>
+__device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s, Emit emit) {
+    const double4 P = S.spos[s];
+    const uint32_t own = S.owner[s];
+    const float ms = S.smargin[s];
+    const Grid &g = S.grids[S.sscene[s]];
+    const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w + ms);
+    const float eps = g.pre_eps;
+    // far outside the domain the slack no longer bounds the rounding: exact test only
+    const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+    // reach of s: its own (R + m) plus the largest partner (R + m); a small
+    // absolute slack keeps the bin selection conservative under rounding
+    const double reach = (P.w + (double)ms) + g.rm_max + 1e-9;
+    scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
+        for (uint32_t j = jb; j < je; j++) {
+            // conservative FP32 test first: it can only admit extra candidates,
+            // which the exact FP64 predicate below then rejects
+            float4 Qf = S.sorted_f4[j];
+            float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z;
+            float fr = (Pf.w + Qf.w) + eps;
+            if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
+            if (S.sorted_owner[j] == own) continue;
+            double4 Q = S.sorted_pos[j];
+            double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double Sr = P.w + Q.w;
+            Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
+            if (d2 < Sr * Sr) emit(S.sorted_id[j]);
         }
+    });
+    const double tnow = (double)S.ctl->step * S.h;
+    for (int b = g.bnd_beg; b < g.bnd_end; b++) {
+        double phi, n[3];
+        if (!bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n)) continue;
+        if (phi < P.w + ((double)ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
     }
-    uint32_t total;
-    uint32_t off = wave_excl_scan((uint32_t)cnt, total);
-    unsigned long long base = 0;
-    if ((tid & 63) == 0 && total) base = atomicAdd((unsigned long long *)&S.ctl->n_entries, (unsigned long long)total);
-    base = __shfl(base, 0, 64);
-    if (over) S.ctl->row_overflow = 1;
-    if (i >= S.ns) return;
-    if (base + total > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
-    uint32_t beg = (uint32_t)(base + off);
-    pick(S.row_beg, nxt)[s] = beg;
-    pick(S.row_cnt, nxt)[s] = (uint32_t)cnt;
-    // carry the tangential history of pairs already in the previous active set
-    uint32_t ob = pick(S.row_beg, cur)[s], oc = pick(S.row_cnt, cur)[s];
+}
+
+// Write the new row of s (partners ascending, from get(k)) and carry the
+// tangential history of pairs that were already in the previous active set.
+// A pair's history lives in its lower sphere's entry.
+template <class Get>
+__device__ __forceinline__ void write_row(const DevScene &S, uint32_t s, uint32_t beg, int cnt, Get get) {
+    const int cur = S.ctl->buf, nxt = cur ^ 1;
+    const uint32_t ob = pick(S.row_beg, cur)[s], oc = pick(S.row_cnt, cur)[s];
     const uint32_t *onb = pick(S.nbr, cur) + ob;
     const double *oh = pick(S.hist, cur) + 3 * (int64_t)ob;
+    uint32_t *nn = pick(S.nbr, nxt);
     uint32_t j = 0;
     for (int k = 0; k < cnt; k++) {
-        uint32_t t = lst[k * kNarrowBlock + tid];
-        pick(S.nbr, nxt)[beg + k] = t;
+        const uint32_t t = get(k);
+        nn[beg + k] = t;
         S.eself[beg + k] = s;
-        if (t < s) continue;  // a pair's history lives in its lower sphere's entry
+        if (t < s) continue;
         while (j < oc && onb[j] < t) j++;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         if (j < oc && onb[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
@@ -540,9 +574,77 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     }
 }
 
-// Pair list and mirror links of the new active set: every entry (s, t) with
-// t > s (or a boundary) is one pair; the entry (t, s) in t's row points back to
-// it, so one evaluation per pair can serve both rows.
+// Narrow phase, one thread per sphere id: ids are spatially coherent (clumps
+// are laid out in Morton order), so a wavefront's neighbour scans share cache
+// lines and the rows come out in that order.  Up to kMaxRow candidates are
+// kept sorted in LDS; a sphere with more gets its row allocated here and
+// filled by k_narrow_over.  Rows are allocated with one atomic per wavefront.
+__global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
+    if (!due(S.ctl)) return;
+    __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
+    const int tid = threadIdx.x;
+    const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
+    const int nxt = S.ctl->buf ^ 1;
+    int cnt = 0;
+    const uint32_t s = (uint32_t)i;
+    if (i < S.ns) {
+        narrow_candidates(S, s, [&](uint32_t t) {
+            if (cnt < kMaxRow) {
+                int k = cnt;
+                while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
+                    lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
+                    k--;
+                }
+                lst[k * kNarrowBlock + tid] = t;
+            }
+            cnt++;
+        });
+    }
+    uint32_t total;
+    const uint32_t off = wave_excl_scan((uint32_t)cnt, total);
+    unsigned long long base = 0;
+    if ((tid & 63) == 0 && total) base = atomicAdd((unsigned long long *)&S.ctl->n_entries, (unsigned long long)total);
+    base = __shfl(base, 0, 64);
+    if (i >= S.ns) return;
+    if (base + total > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
+    const uint32_t beg = (uint32_t)(base + off);
+    pick(S.row_beg, nxt)[s] = beg;
+    pick(S.row_cnt, nxt)[s] = (uint32_t)cnt;
+    if (cnt > kMaxRow) {
+        const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_over, 1u);
+        if (k < (uint32_t)S.over_cap) S.over_list[k] = s;
+        else S.ctl->row_overflow = 1;
+        return;
+    }
+    write_row(S, s, beg, cnt, [&](int k) { return lst[k * kNarrowBlock + tid]; });
+}
+
+// Rows of the spheres with more than kMaxRow candidates: the same scan, with
+// the row kept sorted in place in the active set.
+__global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
+    const Ctl *c = S.ctl;
+    if (!due(c) || c->overflow || c->row_overflow) return;
+    const int nxt = c->buf ^ 1;
+    const int64_t n = min((int64_t)c->n_over, (int64_t)S.over_cap);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = S.over_list[k];
+        const uint32_t beg = pick(S.row_beg, nxt)[s], cnt = pick(S.row_cnt, nxt)[s];
+        uint32_t *row = pick(S.nbr, nxt) + beg;
+        uint32_t m = 0;
+        narrow_candidates(S, s, [&](uint32_t t) {
+            if (m >= cnt) return;  // cannot happen: the predicate is the one that sized the row
+            uint32_t q = m;
+            while (q > 0 && row[q - 1] > t) { row[q] = row[q - 1]; q--; }
+            row[q] = t;
+            m++;
+        });
+        write_row(S, s, beg, (int)m, [&](int q) { return row[q]; });
+    }
+}
+
+// Mirror links of the new active set: every entry (s, t) with t > s (or a
+// boundary) is one pair; the entry (t, s) in t's row points back to it, so one
+// evaluation per pair can serve both rows.  Also counts the pairs.
 __global__ void __launch_bounds__(256) k_mirror(DevScene S) {
     Ctl *ctl = S.ctl;
     if (!due(ctl) || ctl->overflow || ctl->row_overflow) return;
@@ -550,7 +652,7 @@ __global__ void __launch_bounds__(256) k_mirror(DevScene S) {
     const uint32_t *nb = pick(S.nbr, nxt), *rbeg = pick(S.row_beg, nxt), *rcnt = pick(S.row_cnt, nxt);
     const int64_t n = ctl->n_entries;
     const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
         int64_t e = base + threadIdx.x;
         bool valid = e < n, lower = false;
         if (valid) {
@@ -567,10 +669,7 @@ __global__ void __launch_bounds__(256) k_mirror(DevScene S) {
             }
         }
         unsigned long long m = __ballot(valid && lower);
-        unsigned long long pb = 0;
-        if (lane == 0 && m) pb = atomicAdd((unsigned long long *)&ctl->n_pairs, (unsigned long long)__popcll(m));
-        pb = __shfl(pb, 0, 64);
-        if (valid && lower) S.pairs[pb + __popcll(m & ((1ull << lane) - 1))] = (uint32_t)e;
+        if (lane == 0 && m) atomicAdd((unsigned long long *)&ctl->n_pairs, (unsigned long long)__popcll(m));
     }
 }
 
@@ -846,6 +945,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     if (rec) {
         S.rec_state[e] = 1; S.rec_delta[e] = delta;
         S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
+        S.rec_R[3 * e] = ra[0]; S.rec_R[3 * e + 1] = ra[1]; S.rec_R[3 * e + 2] = ra[2];
     }
     return 1;
 }
@@ -857,20 +957,47 @@ __device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
     if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)&ctl->contacts_acc, v);
 }
 
-// Every candidate pair of the active set, one lane per pair (grid-stride).
+// Every candidate pair of the active set, evaluated once.  A pair is the
+// lower sphere's entry (partner id above its own; boundary partners always
+// are).  Each workgroup walks the entries in chunks of kPairChunk in memory
+// order, which is sphere-id order and so spatially coherent, compacts the
+// chunk's lower entries in LDS and evaluates them with every lane busy.
+constexpr int kPairChunk = 512;
 template <bool FP32>
 __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
     if (aborted(S.ctl)) return;
+    __shared__ uint16_t lst[kPairChunk];
+    __shared__ uint32_t wcnt[2][4];
     const int cur = S.ctl->buf;
     const uint32_t *nb = pick(S.nbr, cur);
     double *hist = pick(S.hist, cur);
-    const int64_t np = S.ctl->n_pairs_cur;
+    const int64_t n = S.ctl->n_entries_cur;
     const bool rec = S.ctl->record != 0;
     const double tnow = (double)S.ctl->step * S.h;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t ncont = 0;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < np; base += (int64_t)gridDim.x * blockDim.x) {
-        int64_t i = base + threadIdx.x;
-        if (i < np) ncont += eval_pair<FP32>(S, (int64_t)S.pairs[i], nb, hist, tnow, rec);
+    for (int64_t base = (int64_t)xcd_block() * kPairChunk; base < n; base += (int64_t)gridDim.x * kPairChunk) {
+        bool low[2];
+        uint32_t pos[2];
+        for (int h = 0; h < 2; h++) {
+            const int64_t e = base + h * 256 + threadIdx.x;
+            low[h] = e < n && nb[e] > S.eself[e];
+            const unsigned long long m = __ballot(low[h]);
+            pos[h] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
+            if (lane == 0) wcnt[h][wid] = (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        uint32_t tot = 0, off[2] = {0, 0};
+        for (int h = 0; h < 2; h++)
+            for (int w = 0; w < 4; w++) {
+                if (w == wid) off[h] = tot;
+                tot += wcnt[h][w];
+            }
+        for (int h = 0; h < 2; h++)
+            if (low[h]) lst[off[h] + pos[h]] = (uint16_t)(h * 256 + threadIdx.x);
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < tot; k += 256) ncont += eval_pair<FP32>(S, base + lst[k], nb, hist, tnow, rec);
+        __syncthreads();  // lst and wcnt are rewritten by the next chunk
     }
     count_contacts(S.ctl, ncont);
 }
@@ -969,7 +1096,7 @@ template <bool FP32>
 __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     if (aborted(S.ctl)) return;
     const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t w = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
     if (w >= S.n_waves) return;  // whole wave leaves together
     const int32_t c0 = S.wave_clump0[2 * w], c1 = S.wave_clump0[2 * w + 1];
     const int64_t S0 = S.sbeg[c0], S1 = S.sbeg[c1];
@@ -1117,7 +1244,7 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // margin, must each be in both partners' rows of the active set.
 __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
     if (!audit_due(S)) return;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     unsigned long long found = 0, missed = 0;
     if (i < S.ns) {
         const int cur = S.ctl->buf;
@@ -1175,11 +1302,61 @@ static inline unsigned stride_blocks(int64_t n, int32_t cap = 16384) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap > 0 ? cap : 16384));
 }
 
+// ---------------------------------------------------------------- boundary forces
+// Force the spheres exert on boundary blockIdx.x at the recorded step (minus
+// the force on each sphere) and its torque about the boundary's reference
+// point.  Workgroup (b, part) sums a contiguous range of spheres, each lane a
+// contiguous sub-range in ascending id; lanes then combine in a fixed tree:
+// the result is reproducible run to run.  Boundary entries sit at the end of
+// every row (their partner ids exceed every sphere id).
+__global__ void __launch_bounds__(256) k_bnd_partial(DevScene S, double *partial) {
+    __shared__ double red[6][256];
+    const uint32_t tgt = (uint32_t)S.ns + blockIdx.x;
+    const int cur = S.ctl->buf;
+    const uint32_t *rb = pick(S.row_beg, cur), *rc = pick(S.row_cnt, cur), *nb = pick(S.nbr, cur);
+    const int64_t per_part = (S.ns + kBndParts - 1) / kBndParts;
+    const int64_t p0 = (int64_t)blockIdx.y * per_part, p1 = min(S.ns, p0 + per_part);
+    const int64_t per_lane = (per_part + 255) / 256;
+    const int64_t s0 = p0 + (int64_t)threadIdx.x * per_lane, s1 = min(p1, s0 + per_lane);
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t s = s0; s < s1; s++) {
+        const uint32_t beg = rb[s], cnt = rc[s];
+        for (uint32_t k = cnt; k-- > 0;) {
+            const int64_t e = (int64_t)beg + k;
+            const uint32_t t = nb[e];
+            if (t < (uint32_t)S.ns) break;
+            if (t != tgt || S.rec_state[e] != 1 || !(S.rec_delta[e] > 0.0)) continue;
+            const double f[3] = {-S.rec_F[3 * e], -S.rec_F[3 * e + 1], -S.rec_F[3 * e + 2]};
+            const double r[3] = {S.rec_R[3 * e], S.rec_R[3 * e + 1], S.rec_R[3 * e + 2]};
+            double tq[3];
+            cross3(r, f, tq);
+            for (int i = 0; i < 3; i++) { acc[i] = acc[i] + f[i]; acc[3 + i] = acc[3 + i] + tq[i]; }
+        }
+    }
+    for (int i = 0; i < 6; i++) red[i][threadIdx.x] = acc[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int i = 0; i < 6; i++) red[i][threadIdx.x] = red[i][threadIdx.x] + red[i][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) partial[((int64_t)blockIdx.x * kBndParts + blockIdx.y) * 6 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void k_bnd_final(int n_bnd, const double *partial, double *out) {
+    const int b = blockIdx.x, i = threadIdx.x;
+    if (b >= n_bnd || i >= 6) return;
+    double a = 0.0;
+    for (int p = 0; p < kBndParts; p++) a = a + partial[((int64_t)b * kBndParts + p) * 6 + i];
+    out[6 * b + i] = a;
+}
+
 const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_count", "k_scan_reduce",
                                            "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
-                                           "k_mirror", "k_reduce_waves", "k_bin_features", "k_bin_margin"};
+                                           "k_mirror", "k_reduce_waves", "k_bin_features", "k_bin_margin",
+                                           "k_narrow_over", "k_region_margin"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1210,7 +1387,8 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
     if (which == 2 || (which == 0 && S.detect_mode == 2)) {
         TIMED(K_BIN_FEATURES, hipLaunchKernelGGL(k_bin_features, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
         if (which == 2) return;  // capture needs bins and features only
-        TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(stride_blocks(S.n_cells)), dim3(256), 0, st, S));
+        TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
+        TIMED(K_REGION_MARGIN, hipLaunchKernelGGL(k_region_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
     }
     int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
     // the block-sum scratch lives after the cell arrays (allocated by the runtime)
@@ -1228,14 +1406,22 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
     binning(S, 0, st);
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+    TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
     TIMED(K_MIRROR, hipLaunchKernelGGL(k_mirror, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
     return hipGetLastError();
 }
 
+hipError_t launch_bnd_forces(const DevScene &S, double *partial, double *out, hipStream_t st) {
+    if (S.n_bnd == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bnd_partial, dim3(S.n_bnd, kBndParts), dim3(256), 0, st, S, partial);
+    hipLaunchKernelGGL(k_bnd_final, dim3(S.n_bnd), dim3(64), 0, st, S.n_bnd, (const double *)partial, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_collect_begin(const DevScene &S, hipStream_t st) {
     binning(S, 2, st);
-    hipLaunchKernelGGL(k_collect_init, dim3(stride_blocks(std::max<int64_t>(S.ns, S.n_cells))), dim3(256), 0, st, S);
+    hipLaunchKernelGGL(k_collect_init, dim3(stride_blocks(std::max<int64_t>(S.ns, S.n_regions))), dim3(256), 0, st, S);
     return hipGetLastError();
 }
 
@@ -1260,8 +1446,9 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
     const bool f32 = S.precision == 1;
-    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
-    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
+    const unsigned pb = stride_blocks((S.cap + 1) / 2, S.stride_cap);  // kPairChunk entries per block and pass
+    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
+    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
     if (wb) {
         if (f32) TIMED(K_REDUCE, hipLaunchKernelGGL(k_reduce_waves<true>, dim3(wb), dim3(256), 0, st, S));

@@ -657,6 +657,18 @@ def cfg5_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05,
                     (0, 0, 0, side, side, top), h, bnd=walls, name=f"cfg5-patch-r{replica}")
 
 
+def cfg5_deposited_patch(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, sink_max: float = 2e-5):
+    """A configuration-5 patch built on the CPU alone: the clumps of
+    :func:`cfg5_patch_scene` (same templates, same template draw) dropped one
+    by one with :func:`deposit`.  Much looser than the settled patch, but every
+    clump rests in contact; for checks whose input must not come from a
+    simulation run.  Returns (x[n,3], q[n,4])."""
+    g = rng(5, replica)
+    tmpls = cfg2_templates(replica)
+    ct = g.integers(0, len(tmpls), n_clumps)
+    return deposit(g, tmpls, ct, (0.0, 0.0, side, side), sink_max)
+
+
 def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
             bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True,
             wheel_x: float = 1.0) -> SceneDesc:

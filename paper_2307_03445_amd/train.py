@@ -1,9 +1,10 @@
 """Training of the envelope MLP on trajectories of the plain method.
 
 Data: a scene is run with per-step detection; at regular captures the
-library records, for every occupied bin, the current features (max sphere
-speed, max acceleration envelope, occupancy) and the largest speed and
-acceleration its spheres reach over the next `horizon` steps
+library records, for every occupied envelope region (2 x 2 x 2 bins), the
+current features (max sphere speed, max acceleration envelope, occupancy)
+and the largest speed and acceleration its spheres reach over the next
+`horizon` steps
 (``Scene.collect_envelopes``).  Fit: mean pinball loss at quantile tau (the
 envelopes should err high), Adam, all arithmetic in the library's HIP kernels
 (``cdem_mlp_backward`` / ``cdem_mlp_adam``); torch tensors only hold the data.
@@ -37,7 +38,7 @@ def collect(desc, captures=6, horizon=20, gap=40, precision="fp32", log=None):
         F.append(f)
         Y.append(y)
         if log:
-            log(f"capture {k}: {len(f)} bins, label speed p50 {np.exp(np.median(y[:, 0])):.3g} "
+            log(f"capture {k}: {len(f)} regions, label speed p50 {np.exp(np.median(y[:, 0])):.3g} "
                 f"max {np.exp(y[:, 0].max()):.3g} m/s")
     sc.close()
     return np.concatenate(F), np.concatenate(Y)
@@ -89,7 +90,7 @@ def fit(F, Y, tau=0.99, steps=3000, batch=8192, lr=2e-3, seed=0, log=None):
             hist.append(float(loss.item()))
             if log:
                 log(f"adam step {t}: pinball loss {hist[-1]:.4f} ({time.perf_counter() - t0:.1f} s)")
-    # coverage on all data: fraction of bins whose label the envelope covers
+    # coverage on all data: fraction of regions whose label the envelope covers
     out = _lib.mlp_forward(params, Ft).cpu().numpy()
     cover = (out >= Y).mean(0)
     return params.cpu().numpy(), dict(loss=hist, coverage_speed=float(cover[0]), coverage_acc=float(cover[1]),

@@ -1,0 +1,111 @@
+"""Parity at the full size of the rover-scale bed (11M clumps, ~34.5M spheres
+and the 20,000-sphere wheel), in the launch configuration the throughput
+benchmark times: FP32 force arithmetic, learned detection interval with the
+package's envelope MLP, the benchmark's margin cap, interval bound and audit
+period.
+
+The O(N^2) oracle cannot sweep this scene, so it evaluates sampled spheres
+and clumps by brute force over every partner; the rest is checked through
+properties that hold at any size (the deferred path reproduces per-step
+detection bit for bit, and the audits find no missed contact).  The bed is
+tiled from a patch built by CPU deposition, so no oracle input comes from a
+simulation on the GPU.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import bench
+import oracle
+from paper_2307_03445_amd import inputs as I
+from paritylib import FORCE_RTOL, check_pair_forces, pair_keys
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bed():
+    x, q = I.cfg5_deposited_patch()
+    return I.config5(x, q)
+
+
+@pytest.fixture(scope="module")
+def mlp():
+    from paper_2307_03445_amd import train
+    p = train.load_weights()
+    assert p is not None, "the package's envelope-MLP weights are missing"
+    return p
+
+
+def _subset(c, m):
+    return {k: v[m] for k, v in c.items() if k != "beg"}
+
+
+def test_first_step_sampled_contacts_and_forces(bed, mlp):
+    sc = bench.make_scene(bed, "learned", mlp)
+    sc.record_next_step()
+    sc.step(1)
+    cg = sc.contacts()
+    Fg, Tg = sc.clump_forces()
+    sc.close()
+    print(f"full size: {bed.n_spheres} spheres, {len(cg['a'])} contacts on the first step", flush=True)
+    assert bed.n_spheres > 34_000_000 and len(cg["a"]) > 1_000_000
+
+    g = np.random.default_rng(2307)
+    sb = np.asarray(bed.sphere_begin(), np.int64)
+    n_bed = bed.n_clumps - 1  # the last clump is the wheel
+    clumps = np.sort(g.choice(n_bed, 150, replace=False))
+    clump_spheres = np.concatenate([np.arange(sb[c], sb[c + 1]) for c in clumps])
+    ids = np.unique(np.r_[g.choice(bed.n_spheres, 400, replace=False), clump_spheres,
+                          g.integers(sb[n_bed], sb[n_bed + 1], 8)])
+    oracle.set_threads(min(16, os.cpu_count() or 1))
+    o = oracle.Oracle(bed)
+    Fs, Ts, co = o.sample_spheres(ids)
+    Fo, To = o.sample_clumps(clumps)
+
+    # contact pairs of the sampled spheres: identical sets
+    ko_all = pair_keys(co)
+    ko, first = np.unique(ko_all, return_index=True)
+    mask = np.isin(cg["a"], ids) | np.isin(cg["b"], ids)
+    cgs = _subset(cg, mask)
+    kg = pair_keys(cgs)
+    assert np.array_equal(kg, ko), (len(kg), len(ko), np.setdiff1d(kg, ko)[:5], np.setdiff1d(ko, kg)[:5])
+    assert len(ko) > 300
+    # per-pair forces (pairs are ascending on both sides)
+    cos = _subset(co, first)
+    info = check_pair_forces(cgs, cos, bed)
+    print("pairs", len(ko), info, flush=True)
+
+    # clump force and torque: contact forces of the clump's spheres plus gravity
+    own = np.repeat(np.arange(len(ids)), np.diff(co["beg"]))
+    mag = np.linalg.norm(co["F"], axis=1)
+    fsum = np.bincount(own, weights=mag, minlength=len(ids))
+    pos = np.searchsorted(ids, clump_spheres)
+    cl_of = np.repeat(np.arange(len(clumps)), np.diff(sb)[clumps])
+    scale = np.bincount(cl_of, weights=fsum[pos], minlength=len(clumps))
+    m = bed.tmpl_mass[bed.clump_template[clumps].astype(int)]
+    scale = scale + m * 9.81
+    ef = np.linalg.norm(Fg[clumps] - Fo, axis=1) / scale
+    crad = np.array([I.bounding_radius(bed.tmpl_offset[bed.tmpl_sphere_begin[t]:bed.tmpl_sphere_begin[t + 1]],
+                                       bed.tmpl_radius[bed.tmpl_sphere_begin[t]:bed.tmpl_sphere_begin[t + 1]])
+                     for t in bed.clump_template[clumps].astype(int)])
+    et = np.linalg.norm(Tg[clumps] - To, axis=1) / (scale * crad)
+    print("clumps", float(ef.max()), float(et.max()), flush=True)
+    assert ef.max() <= FORCE_RTOL and et.max() <= FORCE_RTOL
+
+
+def test_learned_reproduces_plain_bitwise_at_full_size(bed, mlp):
+    steps = 101  # crosses an audit at step 100 and several deferred detections
+    out = {}
+    for mode in ("plain", "learned"):
+        sc = bench.make_scene(bed, mode, mlp)
+        sc.step(steps)
+        out[mode] = (sc.state(), sc.counts())
+        sc.close()
+        print(mode, out[mode][1], flush=True)
+    (sp, cp), (sl, cl) = out["plain"], out["learned"]
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(sp[k], sl[k]), k
+    assert cl["missed"] == 0 and cl["audits"] >= 2
+    assert cl["detections"] < cp["detections"] // 4

@@ -254,3 +254,72 @@ def test_big_prescribed_clump(prec):
     Fo, _ = o.clump_forces()
     scale = _clump_scale(d, co)
     assert clump_force_error(Fg, Fo, scale).max() <= FORCE_RTOL
+
+
+def _crowded_scene(n_small=70, n_big=3):
+    """Large spheres each touched by more partners than the narrow phase sorts
+    in LDS (its overflow path), on a Fibonacci lattice of small spheres."""
+    big, small = I.sphere_template(5e-3), I.sphere_template(8e-4)
+    k = np.arange(n_small) + 0.5
+    phi = np.arccos(1 - 2 * k / n_small)
+    th = np.pi * (1 + 5 ** 0.5) * k
+    dirs = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    X, CT = [], []
+    for j in range(n_big):
+        c = np.array([0.02 + 0.02 * j, 0.03, 0.03])
+        X.append(c)
+        CT.append(0)
+        X.extend(c + (5e-3 + 8e-4 - 5e-6) * dirs)
+        CT.extend([1] * n_small)
+    X = np.array(X)
+    nc = len(X)
+    g = np.random.default_rng(7)
+    v = g.uniform(-0.01, 0.01, (nc, 3))
+    mat = np.tile(np.array(I.CFG1_MAT), (nc, 1))
+    return I.assemble([big, small], CT, X, np.tile([1.0, 0, 0, 0], (nc, 1)), v, np.zeros((nc, 3)), mat,
+                      (0, 0, 0), (0, 0, 0, 0.08, 0.06, 0.06), 1e-6)
+
+
+@gpu
+@pytest.mark.parametrize("mode", ["plain", "fixed"])
+def test_spheres_with_more_candidates_than_lds_rows(mode):
+    d = _crowded_scene()
+    sc, o = _scene(d, "fp64"), oracle.Oracle(d)
+    if mode == "fixed":
+        sc.set_detection("fixed", k_max=10, safety=1.5, margin_cap=2e-4, audit_period=5)
+    sc.record_next_step()
+    sc.step(1)
+    o.eval()
+    cg, co = sc.contacts(), o.contacts()
+    per = np.bincount(np.r_[co["a"], co["b"]].astype(int), minlength=d.n_spheres)
+    assert per.max() > 64
+    compare_pairs(cg, co)
+    assert np.array_equal(cg["F"], co["F"]) and np.array_equal(cg["u"], co["u"])
+    sc.step(20)
+    o.step(21)
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(sc.state()[k], o.state()[k]), k
+    assert sc.counts()["missed"] == 0
+
+
+@gpu
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_boundary_forces(dense, prec):
+    sc, o = _scene(dense, prec), oracle.Oracle(dense)
+    sc.step(30)
+    o.step(30)
+    sc.record_next_step()
+    sc.step(1)
+    o.eval()
+    Fg, Tg = sc.boundary_forces()
+    Fo, To = o.boundary_forces()
+    co = o.contacts()
+    wall = co["b"] >= dense.n_spheres
+    w = (co["b"][wall] - dense.n_spheres).astype(int)
+    mag = np.bincount(w, weights=np.linalg.norm(co["F"][wall], axis=1), minlength=dense.n_bnd)
+    assert mag[0] > 0  # the floor carries the pile
+    lever = np.abs(dense.domain[0, 3:] - dense.domain[0, :3]).max() + np.abs(dense.bnd_param[:, :3]).max()
+    tol = 1e-12 if prec == "fp64" else FORCE_RTOL
+    ef = np.linalg.norm(Fg - Fo, axis=1) / np.maximum(mag, 1e-300)
+    et = np.linalg.norm(Tg - To, axis=1) / np.maximum(mag * lever, 1e-300)
+    assert ef.max() <= tol and et.max() <= tol, (ef, et)

@@ -224,6 +224,28 @@ def test_resting_clump_static_balance():
     assert np.abs(F).max() < 1e-6 * M * g and np.abs(T).max() < 1e-6 * M * g * r
 
 
+def test_boundary_force_and_torque_of_resting_clump():
+    """The floor under a resting clump carries its weight, (0, 0, -M g), and
+    the torque about the floor's reference point p0 is p_c x F for a clump
+    whose contact forces balance about its centre p_c: with p0 = (a, b, 0)
+    and the clump above the origin, T = (b M g, -a M g, 0)."""
+    r, E, nu, g = 1e-3, 1e7, 0.3, 9.81
+    t = _tri_clump(r)
+    M = t[2]
+    dl = (3 * (M * g / 3) / (4 * estar_same(E, nu) * math.sqrt(r))) ** (2.0 / 3.0)
+    a, b = 0.01, 0.02
+    walls = [dict(type=I.BND_PLANE, param=(a, b, 0, 0, 0, 1), mat=(E, nu, 0.5, 0.5))]
+    d = I.assemble([t], [0], [(0, 0, r - 1.3 * dl)], [(1, 0, 0, 0)], [(0, 0, 0)], [(0, 0, 0)],
+                   [(E, nu, 0.5, 0.5)] * 3, (0, 0, -g), (-0.1, -0.1, -0.1, 0.1, 0.1, 0.1), 1e-6, bnd=walls)
+    o = oracle.Oracle(d)
+    o.step(30000)
+    o.eval()
+    Fb, Tb = o.boundary_forces()
+    W = M * g
+    assert np.allclose(Fb[0], (0.0, 0.0, -W), rtol=0, atol=1e-6 * W)
+    assert np.allclose(Tb[0], (b * W, -a * W, 0.0), rtol=0, atol=1e-6 * W * r)
+
+
 @pytest.mark.parametrize("theta_deg,mu,slides", [(30.0, 0.3, True), (15.0, 0.5, False)])
 def test_clump_on_incline(theta_deg, mu, slides):
     """A flat three-sphere clump on an incline (gravity tilted): it slides with
