@@ -177,7 +177,7 @@ def cpu_baseline(seconds_target=15.0):
     t0 = time.perf_counter()
     o.step(20)
     per = (time.perf_counter() - t0) / 20
-    n = int(max(20, min(1000, seconds_target / max(per, 1e-6))))
+    n = int(max(20, min(20000, seconds_target / max(per, 1e-6))))
     t0 = time.perf_counter()
     o.step(n)
     dt = time.perf_counter() - t0
