@@ -301,39 +301,41 @@ static int build_grids(cdem_scene *sc) {
 
 static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     DevScene &S = sc->S;
-    uint32_t *nb[2];
+    uint32_t *pt[2];
     double *hs[2];
     for (int k = 0; k < 2; k++) {
-        nb[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        pt[k] = (uint32_t *)dev_alloc(sc, cap * 4);
         hs[k] = (double *)dev_alloc(sc, cap * 24);
-        if (!nb[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
+        if (!pt[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
     }
-    // per-entry arrays derived at each detection (no content to keep)
-    dev_free(sc, S.eself); dev_free(sc, S.emirror); dev_free(sc, S.eflag);
-    dev_free(sc, S.cA); dev_free(sc, S.cB);
-    size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 4 : 8;  // contribution word size
-    S.eself = (uint32_t *)dev_alloc(sc, cap * 4);
-    S.emirror = (uint32_t *)dev_alloc(sc, cap * 4);
-    S.eflag = (uint8_t *)dev_alloc(sc, cap);
-    S.cA = dev_alloc(sc, cap * 4 * cw);
-    S.cB = dev_alloc(sc, cap * 2 * cw);
-    if (!S.eself || !S.emirror || !S.eflag || !S.cA || !S.cB)
+    // per-pair and upper-segment arrays rebuilt at each detection (no content to keep)
+    dev_free(sc, S.ps); dev_free(sc, S.cS); dev_free(sc, S.cTs); dev_free(sc, S.cTt);
+    dev_free(sc, S.ut); dev_free(sc, S.us); dev_free(sc, S.um);
+    const size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 16 : 32;  // float4 / double4
+    S.ps = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.cS = dev_alloc(sc, cap * cw);
+    S.cTs = dev_alloc(sc, cap * cw);
+    S.cTt = dev_alloc(sc, cap * cw);
+    S.ut = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.us = (uint32_t *)dev_alloc(sc, cap * 4);
+    S.um = (uint32_t *)dev_alloc(sc, cap * 4);
+    if (!S.ps || !S.cS || !S.cTs || !S.cTt || !S.ut || !S.us || !S.um)
         return fail(sc, CDEM_E_OOM, "active-set storage");
     if (keep) {
-        // preserve the current buffer (rows point into it)
+        // preserve the current pairs and their history (lower segments point into them)
         Ctl c;
         if (hipMemcpy(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return fail(sc, CDEM_E_HIP, "ctl read");
         int cur = c.buf;
-        size_t n = (size_t)std::min<int64_t>(c.n_entries_cur, S.cap);
+        size_t n = (size_t)std::min<int64_t>(c.n_pairs_cur, S.cap);
         if (n) {
-            if (hipMemcpyAsync(nb[cur], S.nbr[cur], n * 4, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess ||
+            if (hipMemcpyAsync(pt[cur], S.pt[cur], n * 4, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess ||
                 hipMemcpyAsync(hs[cur], S.hist[cur], n * 24, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess)
                 return fail(sc, CDEM_E_HIP, "active-set copy");
         }
         if (hipStreamSynchronize(sc->stream) != hipSuccess) return fail(sc, CDEM_E_HIP, "sync");
-        for (int k = 0; k < 2; k++) { dev_free(sc, S.nbr[k]); dev_free(sc, S.hist[k]); }
+        for (int k = 0; k < 2; k++) { dev_free(sc, S.pt[k]); dev_free(sc, S.hist[k]); }
     }
-    for (int k = 0; k < 2; k++) { S.nbr[k] = nb[k]; S.hist[k] = hs[k]; }
+    for (int k = 0; k < 2; k++) { S.pt[k] = pt[k]; S.hist[k] = hs[k]; }
     S.cap = cap;
     if (sc->rec_cap) {  // recording arrays follow the capacity
         dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
@@ -575,12 +577,14 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
     if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     for (int k = 0; k < 2; k++) {
-        S.row_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-        S.row_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.lo_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.lo_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     }
+    S.up_beg = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.up_cnt = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     if (!S.kin || !S.spos || !S.sdet || !S.smargin || !S.cell_of || !S.sorted_id || !S.sorted_owner ||
-        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.row_beg[0] || !S.row_beg[1] ||
-        !S.row_cnt[0] || !S.row_cnt[1])
+        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.lo_beg[0] || !S.lo_beg[1] ||
+        !S.lo_cnt[0] || !S.lo_cnt[1] || !S.up_beg || !S.up_cnt)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     if (!big.empty()) {
         S.sF = (double *)dev_alloc(sc, 24 * ns);
@@ -591,7 +595,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     // testing aid: deferred detection with zero margin and no guard, which
     // misses contacts on purpose so the audit's failure path can be tested
     sc->test_no_guard = getenv("CDEM_TEST_NO_GUARD") != nullptr;
-    int64_t cap0 = std::max<int64_t>(16 * ns, 1024);
+    int64_t cap0 = std::max<int64_t>(4 * ns, 1024);  // pairs; grown on demand
     if (const char *ev = getenv("CDEM_INITIAL_CAPACITY")) cap0 = std::max<int64_t>(atoll(ev), 64);  // testing aid
     if ((rc = alloc_active_set(sc, cap0, false)) != CDEM_OK) return bail(rc);
     Ctl c;
@@ -600,10 +604,13 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     c.k_cur = 1;
     if (hipMemcpyAsync(S.ctl, &c, sizeof c, hipMemcpyHostToDevice, sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "ctl"));
     for (int k = 0; k < 2; k++) {
-        if (launch_zero(S.row_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
-            launch_zero(S.row_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
+        if (launch_zero(S.lo_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
+            launch_zero(S.lo_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
             return bail(fail(sc, CDEM_E_HIP, "zero"));
     }
+    if (launch_zero(S.up_beg, 4 * (size_t)ns, sc->stream) != hipSuccess ||
+        launch_zero(S.up_cnt, 4 * (size_t)ns, sc->stream) != hipSuccess)
+        return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (launch_zero(S.cacc, 4 * (size_t)nc, sc->stream) != hipSuccess ||
         launch_zero(S.sspeed, 4 * (size_t)ns, sc->stream) != hipSuccess ||
         launch_zero(S.sdet, sizeof(double4) * ns, sc->stream) != hipSuccess ||
@@ -719,7 +726,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
             return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 32 candidate partners (margin too large)");
         if (c.asym) return fail(sc, CDEM_E_STATE, "active-set rows are not symmetric");
         // grow the active set and resume from the step that did not complete
-        int64_t need = (int64_t)(1.3 * (double)c.n_entries) + 1024;
+        int64_t need = (int64_t)(1.3 * (double)std::max(c.n_up, c.n_pairs)) + 1024;
         int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
         if ((rc = alloc_active_set(sc, cap, true)) != CDEM_OK) return rc;
         sc->regrows++;
@@ -799,7 +806,7 @@ extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
     if (rc) return rc;
     memset(out, 0, sizeof *out);
     out->clumps = sc->S.nc; out->spheres = sc->S.ns; out->bins = sc->S.n_cells;
-    out->candidates = c.n_entries_cur; out->steps = c.step; out->detections = c.detections;
+    out->candidates = c.n_pairs_cur + c.n_up_cur; out->steps = c.step; out->detections = c.detections;
     out->guard_trips = c.guard_trips; out->fallbacks = c.fallbacks; out->audits = c.audits;
     out->missed = c.missed; out->capacity = sc->S.cap; out->regrows = sc->regrows; out->k_current = c.k_cur;
     out->pairs = c.n_pairs_cur;
@@ -885,16 +892,16 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
     int rc = read_ctl(sc, c);
     if (rc) return rc;
     int cur = c.buf;
-    int64_t ne = c.n_entries_cur, ns = S.ns;
+    int64_t ne = c.n_pairs_cur, ns = S.ns;
     std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
     std::vector<uint8_t> st(ne);
     std::vector<double> dl(ne), F(3 * ne), H(3 * ne);
     if (ns) {
-        HIPCHK(hipMemcpy(beg.data(), S.row_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(cnt.data(), S.row_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(beg.data(), S.lo_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cnt.data(), S.lo_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
     }
     if (ne) {
-        HIPCHK(hipMemcpy(nb.data(), S.nbr[cur], 4 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(nb.data(), S.pt[cur], 4 * ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(st.data(), S.rec_state, ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(F.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
@@ -907,9 +914,8 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
             int64_t e = (int64_t)beg[s] + k;
             uint32_t t = nb[e];
             if (!st[e]) continue;
-            uint64_t b;
+            uint64_t b;  // pairs are listed once, in the lower sphere's segment
             if (t < (uint32_t)ns) {
-                if (t < (uint32_t)s) continue;  // the pair is listed from its lower id
                 b = t;
             } else {
                 b = (uint64_t)ns + (uint64_t)sc->bnd_user[t - (uint32_t)ns];
@@ -1190,7 +1196,7 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
-    const int64_t E = c.n_entries_cur;
+    const int64_t E = c.n_pairs_cur;
     const bool mlp = S.mlp != nullptr;
     const size_t need = save_size(S, E, mlp);
     *len = need;
@@ -1219,12 +1225,12 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     }
     const int cur = c.buf;
     if (S.ns) {
-        HIPCHK(hipMemcpy(o, S.row_beg[cur], 4 * S.ns, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(o + 4 * S.ns, S.row_cnt[cur], 4 * S.ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o, S.lo_beg[cur], 4 * S.ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o + 4 * S.ns, S.lo_cnt[cur], 4 * S.ns, hipMemcpyDeviceToHost));
     }
     o += 8 * S.ns;
     if (E) {
-        HIPCHK(hipMemcpy(o, S.nbr[cur], 4 * E, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o, S.pt[cur], 4 * E, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(o + 4 * E, S.hist[cur], 24 * E, hipMemcpyDeviceToHost));
     }
     o += 28 * E;
@@ -1267,18 +1273,18 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     for (int i = 0; i < 13; i++)
         if (S.nc) HIPCHK(hipMemcpy(arr[i], p + 8 * S.nc * (size_t)i, 8 * S.nc, hipMemcpyHostToDevice));
     if (S.ns) {
-        HIPCHK(hipMemcpy(S.row_beg[cur], rb, 4 * S.ns, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(S.row_cnt[cur], rn, 4 * S.ns, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.lo_beg[cur], rb, 4 * S.ns, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.lo_cnt[cur], rn, 4 * S.ns, hipMemcpyHostToDevice));
     }
     if (E) {
-        HIPCHK(hipMemcpy(S.nbr[cur], rows + 8 * S.ns, 4 * E, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.pt[cur], rows + 8 * S.ns, 4 * E, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(S.hist[cur], rows + 8 * S.ns + 4 * E, 24 * E, hipMemcpyHostToDevice));
     }
     // resume the saved schedule on this scene's buffers; the active set is
     // rebuilt (with the saved history carried over) before the next step
     Ctl n = hd.ctl;
     n.buf = cur;
-    n.n_entries_cur = E;
+    n.n_pairs_cur = E;
     n.det_due = 1;
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;
     n.guard = 0;

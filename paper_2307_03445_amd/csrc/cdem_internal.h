@@ -43,8 +43,8 @@ struct Grid {
 // runs this step, so that a captured sequence of launches stays static.
 struct Ctl {
     int64_t step;            // completed steps
-    int64_t n_entries;       // entries written by the detection in progress
-    int64_t n_entries_cur;   // entries of the active set in use
+    int64_t n_up;            // upper-segment entries written by the detection in progress
+    int64_t n_up_cur;        // upper-segment entries of the active set in use
     int64_t detections, guard_trips, fallbacks, audits, missed;
     int32_t buf;             // which of the two active-set buffers is current
     int32_t det_due;         // a detection runs at the start of this step
@@ -68,6 +68,7 @@ struct Ctl {
     float margin_cur;        // margin of every sphere at the last detection (fixed rule)
     int64_t audit_true;      // true contacts seen by the last audit
     int64_t audit_last_missed;
+    int64_t n_ss;            // sphere-sphere pairs written by the detection in progress
 };
 
 // Detection plan parameters (fixed rule), set by cdem_set_detection.
@@ -88,7 +89,7 @@ struct DevScene {
     int32_t n_scenes, n_bnd, precision, detect_mode;
     double h;
     int64_t n_cells;
-    int64_t cap;                     // entries per active-set buffer
+    int64_t cap;                     // pairs (and upper-segment entries) per active-set buffer
     // clump state (SoA)
     double *px, *py, *pz, *qw, *qx, *qy, *qz, *vx, *vy, *vz, *wx, *wy, *wz;
     // clump static
@@ -118,20 +119,27 @@ struct DevScene {
     double4 *sorted_pos;
     float *sorted_margin;
     float4 *sorted_f4;               // FP32 prefilter record: position - grid origin, radius + margin
-    // active set: two buffers, current chosen by ctl->buf
-    uint32_t *row_beg[2], *row_cnt[2], *nbr[2];
-    double *hist[2];                 // [cap][3]
-    // per entry of the current active set (rebuilt at every detection)
-    uint32_t *eself;                 // the row's own sphere
+    // Active set, pair-major.  Each candidate pair is stored once, in the
+    // "lower segment" of its lower-id sphere (partners above that id,
+    // ascending, boundaries last), with its tangential history; the higher
+    // sphere lists the pair in its "upper segment" (partners below its id,
+    // ascending) through a link to the pair.  The lower segments come in two
+    // buffers, current chosen by ctl->buf: a detection builds the new set
+    // while carrying the history over from the current one.
+    uint32_t *lo_beg[2], *lo_cnt[2];  // [ns] each sphere's lower segment in the pair arrays
+    uint32_t *pt[2];                  // [cap] partner of the pair: sphere id, or ns + boundary
+    double *hist[2];                  // [cap][3]
+    uint32_t *ps;                     // [cap] the pair's lower sphere (current set)
+    void *cS, *cTs, *cTt;             // [cap] per pair this step: force on the lower sphere (w: 1 if in contact),
+                                      // torque on the lower sphere, torque on the partner sphere (float4 / double4)
+    uint32_t *up_beg, *up_cnt;        // [ns] each sphere's upper segment (current set)
+    uint32_t *ut, *us, *um;           // [cap] upper entries: partner (lower id), own sphere, linked pair
     uint32_t *over_list;             // [over_cap] spheres whose rows k_narrow_over fills
     int64_t over_cap;
-    uint32_t *emirror;               // for a lower entry (s < t): t's entry for s
-    uint8_t *eflag;                  // the entry's pair is in contact this step
-    void *cA, *cB;                   // contribution to the row's sphere: (F, Tx), (Ty, Tz)
     // recording
-    uint8_t *rec_state;
-    double *rec_delta, *rec_F;       // [cap], [cap][3]
-    double *rec_R;                   // [cap][3] boundary entries: contact point relative to the boundary's reference point
+    uint8_t *rec_state;              // per pair of the recorded step
+    double *rec_delta, *rec_F;       // [cap], [cap][3] (F: on the partner body b)
+    double *rec_R;                   // [cap][3] boundary pairs: contact point relative to the boundary's reference point
     double *rec_cF, *rec_cT;         // [nc][3]
     const Bnd *bnd;
     Ctl *ctl;
@@ -158,7 +166,7 @@ struct DevScene {
     const int32_t *wave_clump0;
     int64_t n_waves;
     // launch shape of the grid-stride kernels (tunable; results do not depend on it)
-    int32_t stride_cap;              // maximum workgroups of k_pairs / k_mirror / k_bin_margin
+    int32_t stride_cap;              // maximum workgroups of k_pairs / k_link / k_bin_margin
     int32_t pad3;
 };
 
@@ -171,7 +179,7 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_MIRROR, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_COUNT };
+                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 

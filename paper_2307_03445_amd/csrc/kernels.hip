@@ -254,7 +254,8 @@ __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
     if (bins)
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
     if (i == 0 && !which) {
-        S.ctl->n_entries = 0; S.ctl->n_pairs = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0; S.ctl->n_over = 0;
+        S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_ss = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
+        S.ctl->n_over = 0;
     }
     if (i == 0 && which == 1) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
 }
@@ -550,42 +551,50 @@ __device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s,
     }
 }
 
-// Write the new row of s (partners ascending, from get(k)) and carry the
-// tangential history of pairs that were already in the previous active set.
-// A pair's history lives in its lower sphere's entry.
+// Write the new segments of sphere s from its ascending candidates get(k):
+// the first n_up (partners below s) to its upper segment at ub, the other
+// n_lo (partners above s, boundaries last) to its lower segment at lb as
+// pairs of the new set, each with the tangential history the pair has in the
+// current set (zero for a new pair).
 template <class Get>
-__device__ __forceinline__ void write_row(const DevScene &S, uint32_t s, uint32_t beg, int cnt, Get get) {
+__device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32_t ub, int n_up, uint32_t lb, int n_lo,
+                                           Get get) {
     const int cur = S.ctl->buf, nxt = cur ^ 1;
-    const uint32_t ob = pick(S.row_beg, cur)[s], oc = pick(S.row_cnt, cur)[s];
-    const uint32_t *onb = pick(S.nbr, cur) + ob;
+    for (int k = 0; k < n_up; k++) {
+        S.ut[ub + k] = get(k);
+        S.us[ub + k] = s;
+    }
+    const uint32_t ob = pick(S.lo_beg, cur)[s], oc = pick(S.lo_cnt, cur)[s];
+    const uint32_t *opt = pick(S.pt, cur) + ob;
     const double *oh = pick(S.hist, cur) + 3 * (int64_t)ob;
-    uint32_t *nn = pick(S.nbr, nxt);
+    uint32_t *npt = pick(S.pt, nxt);
+    double *nh = pick(S.hist, nxt);
     uint32_t j = 0;
-    for (int k = 0; k < cnt; k++) {
-        const uint32_t t = get(k);
-        nn[beg + k] = t;
-        S.eself[beg + k] = s;
-        if (t < s) continue;
-        while (j < oc && onb[j] < t) j++;
+    for (int k = 0; k < n_lo; k++) {
+        const uint32_t t = get(n_up + k);
+        const int64_t p = (int64_t)lb + k;
+        npt[p] = t;
+        S.ps[p] = s;
+        while (j < oc && opt[j] < t) j++;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
-        if (j < oc && onb[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
-        double *nh = pick(S.hist, nxt) + 3 * ((int64_t)beg + k);
-        nh[0] = h0; nh[1] = h1; nh[2] = h2;
+        if (j < oc && opt[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
+        nh[3 * p] = h0; nh[3 * p + 1] = h1; nh[3 * p + 2] = h2;
     }
 }
 
 // Narrow phase, one thread per sphere id: ids are spatially coherent (clumps
 // are laid out in Morton order), so a wavefront's neighbour scans share cache
-// lines and the rows come out in that order.  Up to kMaxRow candidates are
-// kept sorted in LDS; a sphere with more gets its row allocated here and
-// filled by k_narrow_over.  Rows are allocated with one atomic per wavefront.
+// lines and the pairs come out in that order.  Up to kMaxRow candidates are
+// kept sorted in LDS; a sphere with more gets its segments allocated here and
+// filled by k_narrow_over.  Segments are allocated with one atomic per
+// wavefront and kind (upper entries, pairs).
 __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     if (!due(S.ctl)) return;
     __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
     const int nxt = S.ctl->buf ^ 1;
-    int cnt = 0;
+    int cnt = 0, nup = 0, nss = 0;
     const uint32_t s = (uint32_t)i;
     if (i < S.ns) {
         narrow_candidates(S, s, [&](uint32_t t) {
@@ -598,29 +607,41 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
                 lst[k * kNarrowBlock + tid] = t;
             }
             cnt++;
+            nup += t < s;
+            nss += t > s && t < (uint32_t)S.ns;
         });
     }
-    uint32_t total;
-    const uint32_t off = wave_excl_scan((uint32_t)cnt, total);
-    unsigned long long base = 0;
-    if ((tid & 63) == 0 && total) base = atomicAdd((unsigned long long *)&S.ctl->n_entries, (unsigned long long)total);
-    base = __shfl(base, 0, 64);
+    const int nlo = cnt - nup;
+    uint32_t totu, totl, totss;
+    const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
+    const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
+    (void)wave_excl_scan((uint32_t)nss, totss);
+    unsigned long long bu = 0, bl = 0;
+    if ((tid & 63) == 0) {
+        if (totu) bu = atomicAdd((unsigned long long *)&S.ctl->n_up, (unsigned long long)totu);
+        if (totl) bl = atomicAdd((unsigned long long *)&S.ctl->n_pairs, (unsigned long long)totl);
+        if (totss) atomicAdd((unsigned long long *)&S.ctl->n_ss, (unsigned long long)totss);
+    }
+    bu = __shfl(bu, 0, 64);
+    bl = __shfl(bl, 0, 64);
     if (i >= S.ns) return;
-    if (base + total > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
-    const uint32_t beg = (uint32_t)(base + off);
-    pick(S.row_beg, nxt)[s] = beg;
-    pick(S.row_cnt, nxt)[s] = (uint32_t)cnt;
+    if (bu + totu > (unsigned long long)S.cap || bl + totl > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
+    const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
+    S.up_beg[s] = ub;
+    S.up_cnt[s] = (uint32_t)nup;
+    pick(S.lo_beg, nxt)[s] = lb;
+    pick(S.lo_cnt, nxt)[s] = (uint32_t)nlo;
     if (cnt > kMaxRow) {
         const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_over, 1u);
         if (k < (uint32_t)S.over_cap) S.over_list[k] = s;
         else S.ctl->row_overflow = 1;
         return;
     }
-    write_row(S, s, beg, cnt, [&](int k) { return lst[k * kNarrowBlock + tid]; });
+    write_rows(S, s, ub, nup, lb, nlo, [&](int k) { return lst[k * kNarrowBlock + tid]; });
 }
 
-// Rows of the spheres with more than kMaxRow candidates: the same scan, with
-// the row kept sorted in place in the active set.
+// Segments of the spheres with more than kMaxRow candidates: the same scan,
+// each segment kept sorted in place in the active set.
 __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
     const Ctl *c = S.ctl;
     if (!due(c) || c->overflow || c->row_overflow) return;
@@ -628,58 +649,55 @@ __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
     const int64_t n = min((int64_t)c->n_over, (int64_t)S.over_cap);
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = S.over_list[k];
-        const uint32_t beg = pick(S.row_beg, nxt)[s], cnt = pick(S.row_cnt, nxt)[s];
-        uint32_t *row = pick(S.nbr, nxt) + beg;
-        uint32_t m = 0;
+        const uint32_t ub = S.up_beg[s], nu = S.up_cnt[s];
+        const uint32_t lb = pick(S.lo_beg, nxt)[s], nl = pick(S.lo_cnt, nxt)[s];
+        uint32_t *urow = S.ut + ub;
+        uint32_t *lrow = pick(S.pt, nxt) + lb;
+        uint32_t mu = 0, ml = 0;
+        // the predicate is the one that sized the segments: the counts cannot be exceeded
         narrow_candidates(S, s, [&](uint32_t t) {
-            if (m >= cnt) return;  // cannot happen: the predicate is the one that sized the row
+            uint32_t *row = t < s ? urow : lrow;
+            uint32_t &m = t < s ? mu : ml;
+            if (m >= (t < s ? nu : nl)) return;
             uint32_t q = m;
             while (q > 0 && row[q - 1] > t) { row[q] = row[q - 1]; q--; }
             row[q] = t;
             m++;
         });
-        write_row(S, s, beg, (int)m, [&](int q) { return row[q]; });
+        write_rows(S, s, ub, (int)mu, lb, (int)ml, [&](int q) { return q < (int)mu ? urow[q] : lrow[q - (int)mu]; });
     }
 }
 
-// Mirror links of the new active set: every entry (s, t) with t > s (or a
-// boundary) is one pair; the entry (t, s) in t's row points back to it, so one
-// evaluation per pair can serve both rows.  Also counts the pairs.
-__global__ void __launch_bounds__(256) k_mirror(DevScene S) {
+// Links of the new active set: upper entry (s, t), t < s, points to the
+// pair (t, s) in t's lower segment (binary search), so that both spheres sum
+// the one evaluation of the pair.
+__global__ void __launch_bounds__(256) k_link(DevScene S) {
     Ctl *ctl = S.ctl;
     if (!due(ctl) || ctl->overflow || ctl->row_overflow) return;
     const int nxt = ctl->buf ^ 1;
-    const uint32_t *nb = pick(S.nbr, nxt), *rbeg = pick(S.row_beg, nxt), *rcnt = pick(S.row_cnt, nxt);
-    const int64_t n = ctl->n_entries;
-    const int lane = threadIdx.x & 63;
-    for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
-        int64_t e = base + threadIdx.x;
-        bool valid = e < n, lower = false;
-        if (valid) {
-            uint32_t s = S.eself[e], t = nb[e];
-            lower = t > s;
-            if (!lower) {  // reverse entry: find s in t's (sorted) row
-                uint32_t b0 = rbeg[t], cnt = rcnt[t], lo = 0, hi = cnt;
-                while (lo < hi) {
-                    uint32_t mid = (lo + hi) >> 1;
-                    if (nb[b0 + mid] < s) lo = mid + 1; else hi = mid;
-                }
-                if (lo < cnt && nb[b0 + lo] == s) S.emirror[b0 + lo] = (uint32_t)e;
-                else ctl->asym = 1;  // rows not symmetric: the step is abandoned
-            }
+    const uint32_t *pt = pick(S.pt, nxt), *lb = pick(S.lo_beg, nxt), *lc = pick(S.lo_cnt, nxt);
+    const int64_t n = ctl->n_up;
+    for (int64_t u = (int64_t)xcd_block() * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = S.us[u], t = S.ut[u];
+        const uint32_t b0 = lb[t], cnt = lc[t];
+        uint32_t lo = 0, hi = cnt;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (pt[b0 + mid] < s) lo = mid + 1; else hi = mid;
         }
-        unsigned long long m = __ballot(valid && lower);
-        if (lane == 0 && m) atomicAdd((unsigned long long *)&ctl->n_pairs, (unsigned long long)__popcll(m));
+        if (lo < cnt && pt[b0 + lo] == s) S.um[u] = b0 + lo;
+        else ctl->asym = 1;  // segments not symmetric: the step is abandoned
     }
 }
 
 __global__ void k_detect_end(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || c->overflow) return;
+    if (c->n_ss != c->n_up) c->asym = 1;  // every sphere pair has exactly one upper entry
     if (c->row_overflow || c->asym) { c->overflow = 1; return; }
     if (c->guard && !c->det_due) c->guard_trips++;
     c->buf ^= 1;
-    c->n_entries_cur = c->n_entries;
+    c->n_up_cur = c->n_up;
     c->n_pairs_cur = c->n_pairs;
     c->detections++;
     c->since_det = 0;
@@ -790,24 +808,20 @@ __device__ __forceinline__ void law32(const double *nd, double delta_d, const fl
     for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
 }
 
-// Per-entry contribution storage: force on the row's sphere (3) and its
-// torque about the sphere's clump CoM (3); FP32 mode stores floats.
+// Per-pair contribution storage: force on the pair's lower sphere with the
+// contact flag in w, that sphere's torque about its clump CoM, and the
+// partner sphere's torque (its force is minus the first); FP32 mode stores
+// floats.
 template <bool FP32> struct Contrib;
 template <> struct Contrib<true> {
-    using A = float4;
-    using B = float2;
-    static __device__ __forceinline__ void put(void *ca, void *cb, int64_t e, const double *f, const double *t) {
-        ((float4 *)ca)[e] = make_float4((float)f[0], (float)f[1], (float)f[2], (float)t[0]);
-        ((float2 *)cb)[e] = make_float2((float)t[1], (float)t[2]);
+    using V = float4;
+    static __device__ __forceinline__ V make(const double *a, double w) {
+        return make_float4((float)a[0], (float)a[1], (float)a[2], (float)w);
     }
 };
 template <> struct Contrib<false> {
-    using A = double4;
-    using B = double2;
-    static __device__ __forceinline__ void put(void *ca, void *cb, int64_t e, const double *f, const double *t) {
-        ((double4 *)ca)[e] = make_double4(f[0], f[1], f[2], t[0]);
-        ((double2 *)cb)[e] = make_double2(t[1], t[2]);
-    }
+    using V = double4;
+    static __device__ __forceinline__ V make(const double *a, double w) { return make_double4(a[0], a[1], a[2], w); }
 };
 
 // Torque r x f, in FP32 when the force law ran in FP32.
@@ -822,25 +836,26 @@ __device__ __forceinline__ void torque(const double *r, const double *f, double 
     }
 }
 
-// Evaluate candidate pair p of the active set once, for both bodies: entry e
-// is the lower sphere's row entry, mirror[e] the higher sphere's; a boundary
-// pair has the sphere as body b.  Writes the history at e, the contribution
-// and flag of each sphere's entry, and returns the contact sides it created.
+// Evaluate pair e of the active set once, for both bodies: sphere pairs
+// have the lower sphere as body a; a boundary pair has the sphere as body b.
+// Writes the pair's history and contributions, and returns the contact
+// sides it created.
 template <bool FP32>
-__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const uint32_t *nb, double *hist,
+__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const uint32_t *pt, double *hist,
                                               double tnow, bool rec) {
-    const uint32_t s = S.eself[e], t = nb[e];
+    using V = typename Contrib<FP32>::V;
+    V *cS = (V *)S.cS, *cTs = (V *)S.cTs, *cTt = (V *)S.cTt;
+    const double zero3[3] = {0.0, 0.0, 0.0};
+    const uint32_t s = S.ps[e], t = pt[e];
     double *h = hist + 3 * e;
     if (t < (uint32_t)S.ns) {
-        const uint32_t a = s, b = t;  // a < b by construction of the pair list
-        const int64_t m = S.emirror[e];
+        const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
         double4 Pa = S.spos[a], Pb = S.spos[b];
         double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y, dz = Pb.z - Pa.z;
         double d2 = dx * dx + dy * dy + dz * dz;
         double Sr = Pa.w + Pb.w;
         if (!(d2 < Sr * Sr)) {  // a false positive of the enlarged geometry: no force, no history
-            S.eflag[e] = 0;
-            S.eflag[m] = 0;
+            cS[e] = Contrib<FP32>::make(zero3, 0.0);
             if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
             if (rec) S.rec_state[e] = 0;
             return 0;
@@ -848,8 +863,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         double d = sqrt(d2);
         double delta = Sr - d;
         if (!(delta > 0.0)) {
-            S.eflag[e] = 0;
-            S.eflag[m] = 0;
+            cS[e] = Contrib<FP32>::make(zero3, 0.0);
             h[0] = 0.0; h[1] = 0.0; h[2] = 0.0;
             if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
             return 0;
@@ -889,10 +903,9 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         double fa[3] = {-F[0], -F[1], -F[2]}, ta[3], tb[3];
         torque<FP32>(ra, fa, ta);
         torque<FP32>(rb, F, tb);
-        Contrib<FP32>::put(S.cA, S.cB, e, fa, ta);
-        Contrib<FP32>::put(S.cA, S.cB, m, F, tb);
-        S.eflag[e] = 1;
-        S.eflag[m] = 1;
+        cS[e] = Contrib<FP32>::make(fa, 1.0);
+        cTs[e] = Contrib<FP32>::make(ta, 0.0);
+        cTt[e] = Contrib<FP32>::make(tb, 0.0);
         if (rec) {
             S.rec_state[e] = 1; S.rec_delta[e] = delta;
             S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
@@ -905,7 +918,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     double phi, n[3];
     bool contact = bnd_distance(B, tnow, Ps.x, Ps.y, Ps.z, phi, n) && phi < Ps.w;
     if (!contact) {
-        S.eflag[e] = 0;
+        cS[e] = Contrib<FP32>::make(zero3, 0.0);
         if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
         if (rec) S.rec_state[e] = 0;
         return 0;
@@ -940,8 +953,8 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     h[0] = u_new[0]; h[1] = u_new[1]; h[2] = u_new[2];
     double tb[3];
     torque<FP32>(rb, F, tb);
-    Contrib<FP32>::put(S.cA, S.cB, e, F, tb);
-    S.eflag[e] = 1;
+    cS[e] = Contrib<FP32>::make(F, 1.0);
+    cTs[e] = Contrib<FP32>::make(tb, 0.0);
     if (rec) {
         S.rec_state[e] = 1; S.rec_delta[e] = delta;
         S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
@@ -957,67 +970,49 @@ __device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
     if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)&ctl->contacts_acc, v);
 }
 
-// Every candidate pair of the active set, evaluated once.  A pair is the
-// lower sphere's entry (partner id above its own; boundary partners always
-// are).  Each workgroup walks the entries in chunks of kPairChunk in memory
-// order, which is sphere-id order and so spatially coherent, compacts the
-// chunk's lower entries in LDS and evaluates them with every lane busy.
-constexpr int kPairChunk = 512;
+// Every candidate pair of the active set, evaluated once, one lane per pair
+// (grid-stride in memory order, which follows the sphere ids and so is
+// spatially coherent).
 template <bool FP32>
 __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
     if (aborted(S.ctl)) return;
-    __shared__ uint16_t lst[kPairChunk];
-    __shared__ uint32_t wcnt[2][4];
     const int cur = S.ctl->buf;
-    const uint32_t *nb = pick(S.nbr, cur);
+    const uint32_t *pt = pick(S.pt, cur);
     double *hist = pick(S.hist, cur);
-    const int64_t n = S.ctl->n_entries_cur;
+    const int64_t n = S.ctl->n_pairs_cur;
     const bool rec = S.ctl->record != 0;
     const double tnow = (double)S.ctl->step * S.h;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t ncont = 0;
-    for (int64_t base = (int64_t)xcd_block() * kPairChunk; base < n; base += (int64_t)gridDim.x * kPairChunk) {
-        bool low[2];
-        uint32_t pos[2];
-        for (int h = 0; h < 2; h++) {
-            const int64_t e = base + h * 256 + threadIdx.x;
-            low[h] = e < n && nb[e] > S.eself[e];
-            const unsigned long long m = __ballot(low[h]);
-            pos[h] = (uint32_t)__popcll(m & ((1ull << lane) - 1));
-            if (lane == 0) wcnt[h][wid] = (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        uint32_t tot = 0, off[2] = {0, 0};
-        for (int h = 0; h < 2; h++)
-            for (int w = 0; w < 4; w++) {
-                if (w == wid) off[h] = tot;
-                tot += wcnt[h][w];
-            }
-        for (int h = 0; h < 2; h++)
-            if (low[h]) lst[off[h] + pos[h]] = (uint16_t)(h * 256 + threadIdx.x);
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < tot; k += 256) ncont += eval_pair<FP32>(S, base + lst[k], nb, hist, tnow, rec);
-        __syncthreads();  // lst and wcnt are rewritten by the next chunk
-    }
+    for (int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        ncont += eval_pair<FP32>(S, e, pt, hist, tnow, rec);
     count_contacts(S.ctl, ncont);
 }
 
-// Sum of the flagged contributions in sphere s's row, ascending partner id.
+// Force and torque on sphere s from its contacts, summed in ascending
+// partner id: the upper segment (partners below s; the pair's force on s is
+// minus the stored force on the partner), then the lower segment (partners
+// above s, boundaries last).
 template <bool FP32>
-__device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, const uint32_t *rbeg, const uint32_t *rcnt,
-                                           double *Fs, double *Ts) {
-    using A = typename Contrib<FP32>::A;
-    using B = typename Contrib<FP32>::B;
-    const A *cA = (const A *)S.cA;
-    const B *cB = (const B *)S.cB;
-    uint32_t beg = rbeg[s], cnt = rcnt[s];
-    for (uint32_t k = 0; k < cnt; k++) {
-        int64_t e = (int64_t)beg + k;
-        if (!S.eflag[e]) continue;
-        A a = cA[e];
-        B b = cB[e];
+__device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, int cur, double *Fs, double *Ts) {
+    using V = typename Contrib<FP32>::V;
+    const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
+    const uint32_t ub = S.up_beg[s], nu = S.up_cnt[s];
+    for (uint32_t k = 0; k < nu; k++) {
+        const int64_t e = S.um[ub + k];
+        const V a = cS[e];
+        if (a.w == 0) continue;
+        const V b = cTt[e];
+        Fs[0] = Fs[0] + (double)(-a.x); Fs[1] = Fs[1] + (double)(-a.y); Fs[2] = Fs[2] + (double)(-a.z);
+        Ts[0] = Ts[0] + (double)b.x; Ts[1] = Ts[1] + (double)b.y; Ts[2] = Ts[2] + (double)b.z;
+    }
+    const uint32_t lb = pick(S.lo_beg, cur)[s], nl = pick(S.lo_cnt, cur)[s];
+    for (uint32_t k = 0; k < nl; k++) {
+        const int64_t e = (int64_t)lb + k;
+        const V a = cS[e];
+        if (a.w == 0) continue;
+        const V b = cTs[e];
         Fs[0] = Fs[0] + (double)a.x; Fs[1] = Fs[1] + (double)a.y; Fs[2] = Fs[2] + (double)a.z;
-        Ts[0] = Ts[0] + (double)a.w; Ts[1] = Ts[1] + (double)b.x; Ts[2] = Ts[2] + (double)b.y;
+        Ts[0] = Ts[0] + (double)b.x; Ts[1] = Ts[1] + (double)b.y; Ts[2] = Ts[2] + (double)b.z;
     }
 }
 
@@ -1111,7 +1106,7 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
         c = S.owner[s];
         cb = S.sbeg[c];
         cnt = (int)(S.sbeg[c + 1] - cb);
-        sphere_sum<FP32>(S, (uint32_t)s, pick(S.row_beg, cur), pick(S.row_cnt, cur), Fs, Ts);
+        sphere_sum<FP32>(S, (uint32_t)s, cur, Fs, Ts);
     }
     const bool leader = active && s == cb;
     int mx = leader ? cnt : 0;  // longest clump of the wave: the number of shuffle rounds
@@ -1148,7 +1143,7 @@ __global__ void __launch_bounds__(256) k_reduce_big_spheres(DevScene S) {
     const int cur = S.ctl->buf;
     for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += (int64_t)gridDim.x * blockDim.x) {
         double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-        sphere_sum<FP32>(S, (uint32_t)s, pick(S.row_beg, cur), pick(S.row_cnt, cur), Fs, Ts);
+        sphere_sum<FP32>(S, (uint32_t)s, cur, Fs, Ts);
         for (int i = 0; i < 3; i++) { S.sF[3 * s + i] = Fs[i]; S.sT[3 * s + i] = Ts[i]; }
     }
 }
@@ -1200,8 +1195,9 @@ __global__ void __launch_bounds__(256) k_audit_brute(DevScene S, unsigned long l
     int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (a >= S.ns) return;
     const int cur = S.ctl->buf;
-    uint32_t beg = pick(S.row_beg, cur)[a], cnt = pick(S.row_cnt, cur)[a];
-    const uint32_t *nb = pick(S.nbr, cur) + beg;
+    // every exact contact (a, b) with b above a is a pair of a's lower segment
+    uint32_t beg = pick(S.lo_beg, cur)[a], cnt = pick(S.lo_cnt, cur)[a];
+    const uint32_t *nb = pick(S.pt, cur) + beg;
     double4 P = S.spos[a];
     uint32_t own = S.owner[a], sc = S.sscene[a];
     unsigned long long found = 0, missed = 0;
@@ -1251,9 +1247,12 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         uint32_t s = (uint32_t)i;
         double4 P = S.spos[s];
         uint32_t own = S.owner[s];
-        uint32_t beg = pick(S.row_beg, cur)[s], cnt = pick(S.row_cnt, cur)[s];
-        const uint32_t *nb = pick(S.nbr, cur) + beg;
-        auto in_row = [&](uint32_t t) {
+        const uint32_t lb = pick(S.lo_beg, cur)[s], lc = pick(S.lo_cnt, cur)[s];
+        const uint32_t *lrow = pick(S.pt, cur) + lb, *urow = S.ut + S.up_beg[s];
+        const uint32_t uc = S.up_cnt[s];
+        auto in_row = [&](uint32_t t) {  // t in s's upper (t < s) or lower segment
+            const uint32_t *nb = t < s ? urow : lrow;
+            const uint32_t cnt = t < s ? uc : lc;
             uint32_t lo = 0, hi = cnt;
             while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
             return lo < cnt && nb[lo] == t;
@@ -1307,13 +1306,13 @@ static inline unsigned stride_blocks(int64_t n, int32_t cap = 16384) {
 // the force on each sphere) and its torque about the boundary's reference
 // point.  Workgroup (b, part) sums a contiguous range of spheres, each lane a
 // contiguous sub-range in ascending id; lanes then combine in a fixed tree:
-// the result is reproducible run to run.  Boundary entries sit at the end of
-// every row (their partner ids exceed every sphere id).
+// the result is reproducible run to run.  Boundary pairs sit at the end of
+// every lower segment (their partner ids exceed every sphere id).
 __global__ void __launch_bounds__(256) k_bnd_partial(DevScene S, double *partial) {
     __shared__ double red[6][256];
     const uint32_t tgt = (uint32_t)S.ns + blockIdx.x;
     const int cur = S.ctl->buf;
-    const uint32_t *rb = pick(S.row_beg, cur), *rc = pick(S.row_cnt, cur), *nb = pick(S.nbr, cur);
+    const uint32_t *rb = pick(S.lo_beg, cur), *rc = pick(S.lo_cnt, cur), *nb = pick(S.pt, cur);
     const int64_t per_part = (S.ns + kBndParts - 1) / kBndParts;
     const int64_t p0 = (int64_t)blockIdx.y * per_part, p1 = min(S.ns, p0 + per_part);
     const int64_t per_lane = (per_part + 255) / 256;
@@ -1355,7 +1354,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_scan_bsum", "k_scan_final", "k_cell_scatter", "k_narrow",
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
-                                           "k_mirror", "k_reduce_waves", "k_bin_features", "k_bin_margin",
+                                           "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
                                            "k_narrow_over", "k_region_margin"};
 KernelTimer *g_timer = nullptr;
 
@@ -1407,7 +1406,7 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     binning(S, 0, st);
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
     TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
-    TIMED(K_MIRROR, hipLaunchKernelGGL(k_mirror, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
+    TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
     return hipGetLastError();
 }
@@ -1446,7 +1445,7 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
     const bool f32 = S.precision == 1;
-    const unsigned pb = stride_blocks((S.cap + 1) / 2, S.stride_cap);  // kPairChunk entries per block and pass
+    const unsigned pb = stride_blocks(S.cap, S.stride_cap);
     if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
     else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
