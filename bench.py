@@ -38,9 +38,13 @@ def log(*a):
 # ---------------------------------------------------------------- byte models
 def algorithmic_bytes(kernel: str, st: dict) -> float:
     """Bytes a launch of `kernel` must move at minimum: every array it reads or
-    writes touched once (gathers of neighbour data counted as cache hits)."""
+    writes touched once (gathers of neighbour data counted as cache hits).
+    P pairs of the active set, U of them sphere pairs (each also listed in the
+    higher sphere's upper segment), C contact pairs, v one contribution vector
+    (force or torque with a fourth word: float4 or double4)."""
     ns, nc, cells = st["spheres"], st["clumps"], st["bins"]
-    E, Eold, Cs = st["entries"], st["entries_old"], st["contact_sides"]
+    P, U, C = st["pairs"], st["upper"], st["contact_sides"] / 2.0
+    v = 16 if st["fp32"] else 32
     mat = 16 if st["fp32"] else 32
     guard = st["guard"]
     if kernel == "k_pose":
@@ -50,17 +54,22 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     if kernel == "k_cell_scatter":
         return ns * 132
     if kernel == "k_narrow":
-        return ns * 64 + cells * 8 + 28 * (E + Eold)
+        # positions, margins, bin starts; new pairs (partner, own id, history),
+        # upper entries (partner, own id), the current pairs merged for history
+        return ns * 88 + cells * 8 + 32 * P + 8 * U + 28 * P
+    if kernel == "k_link":
+        return U * 28
     if kernel == "k_pairs":
-        # per candidate pair: pair id, own/partner ids, mirror, two flags, history
-        # read; per contact pair: history write and two contributions; compulsory
-        # per-sphere and per-clump gathers (position+radius, material, owner, kinematics)
-        P, Cp = st["pairs"], Cs / 2.0
-        return P * 42 + Cp * (24 + 2 * (mat + 8)) + ns * (36 + mat) + nc * 96
+        # per pair: own id, partner, history read, force and torque of the lower
+        # sphere; per sphere pair the partner's torque; per contact the history
+        # write; compulsory per-sphere and per-clump gathers (position+radius,
+        # material, owner, kinematics)
+        return P * (8 + 24 + 2 * v) + U * v + C * 24 + ns * (32 + mat + 4) + nc * 96
     if kernel == "k_reduce_waves":
-        # per entry: flag; per contact side: contribution; per sphere: row and owner;
-        # per clump: state read+write, mass properties, scene, bounding radius
-        return E * 1 + Cs * (mat + 8) + ns * 20 + nc * 264
+        # per upper entry: link, the pair's force and the partner's torque; per
+        # pair: force and torque of the lower sphere; per sphere: segment bounds
+        # and owner; per clump: state read+write, mass properties, scene, bounding radius
+        return U * (4 + 2 * v) + P * 2 * v + ns * 20 + nc * 264
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)
     if kernel == "k_detect_begin":
@@ -150,11 +159,12 @@ def measured_traffic(kernel: str):
 def roofline(res, desc_stats, mode):
     prof = res["prof"]
     k, (n, ms) = max(prof.items(), key=lambda kv: kv[1][1])
-    st = dict(desc_stats, entries=res["counts"]["candidates"], entries_old=res["counts"]["candidates"],
-              pairs=res["counts"]["pairs"], contact_sides=res["contact_sides"], guard=(mode != "plain"))
+    cnt = res["counts"]
+    st = dict(desc_stats, pairs=cnt["pairs"], upper=cnt["candidates"] - cnt["pairs"],
+              contact_sides=res["contact_sides"], guard=(mode != "plain"))
     # a detection kernel early-exits when no detection is due: count only real launches
     launches = n
-    if k in ("k_narrow", "k_mirror", "k_cell_count", "k_cell_scatter", "k_detect_begin", "k_scan_reduce",
+    if k in ("k_narrow", "k_link", "k_cell_count", "k_cell_scatter", "k_detect_begin", "k_scan_reduce",
              "k_scan_final"):
         launches = max(1, res["detections"])
     b = algorithmic_bytes(k, st)
