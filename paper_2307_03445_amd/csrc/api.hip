@@ -650,10 +650,10 @@ static int write_ctl(cdem_scene *sc, const Ctl &c) {
 // not capturing a graph).
 static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing) {
     const DevScene &S = sc->S;
-    int guard = S.detect_mode != CDEM_DETECT_PLAIN && !sc->test_no_guard;
+
     g_timer = capturing ? nullptr : sc->timer;
     for (int64_t i = 0; i < n; i++) {
-        hipError_t e = launch_pose(S, guard, st);
+        hipError_t e = launch_pose(S, st);
         if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, st);
         if (e == hipSuccess) e = launch_detect(S, st);
         if (e == hipSuccess) e = launch_audit_binned(S, st);
@@ -772,11 +772,13 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
     sc->S.plan.test_zero_margin = sc->test_no_guard ? 1 : 0;
     sc->S.store_speed = p->mode == CDEM_DETECT_LEARNED ? 1 : 0;
     sc->S.store_acc = p->mode == CDEM_DETECT_LEARNED ? 1 : 0;
+    sc->S.guard_on = p->mode != CDEM_DETECT_PLAIN && !sc->test_no_guard ? 1 : 0;
     set_bnd_margins(sc);
     HIPCHK(hipMemcpyAsync((void *)sc->S.bnd, sc->bnd.data(), sc->bnd.size() * sizeof(Bnd), hipMemcpyHostToDevice, sc->stream));
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
     c.det_due = 1;
     c.k_cur = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
+    c.pose_fresh = 0;  // guard and speed settings changed: recompute this step's poses
     return write_ctl(sc, c);
 }
 
@@ -870,13 +872,14 @@ extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int wh
     int rc = read_ctl(sc, c);
     if (rc) return rc;
     c.det_due = 1;
+    c.pose_fresh = 0;
     return write_ctl(sc, c);
 }
 
 extern "C" int cdem_read_sphere_pos(cdem_scene *sc, double *xs) {
     if (!sc || !xs) return fail(sc, CDEM_E_INVALID, "null argument");
     const DevScene &S = sc->S;
-    HIPCHK(launch_pose(S, 0, sc->stream));
+    HIPCHK(launch_pose(S, sc->stream));
     std::vector<double4> p(S.ns);
     HIPCHK(hipStreamSynchronize(sc->stream));
     HIPCHK(hipMemcpy(p.data(), S.spos, S.ns * sizeof(double4), hipMemcpyDeviceToHost));
@@ -983,7 +986,7 @@ extern "C" int cdem_audit(cdem_scene *sc, cdem_audit_result *r) {
     if (!cnt) return fail(sc, CDEM_E_OOM, "audit counters");
     unsigned long long init[3] = {0, 0, ~0ull};
     HIPCHK(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, sc->stream));
-    HIPCHK(launch_pose(S, 0, sc->stream));
+    HIPCHK(launch_pose(S, sc->stream));
     HIPCHK(launch_audit_brute(S, cnt, (uint32_t *)(cnt + 2), sc->stream));
     HIPCHK(hipStreamSynchronize(sc->stream));
     unsigned long long out[3];
@@ -1067,7 +1070,7 @@ extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *fe
     auto restore = [&](int rc) { S.store_speed = ss; S.store_acc = sa; sc->collecting = false; return rc; };
     int rc = cdem_step(sc, 1, nullptr);  // one step so that every clump has an acceleration envelope
     if (rc) return restore(rc);
-    hipError_t e = launch_pose(S, 0, sc->stream);
+    hipError_t e = launch_pose(S, sc->stream);
     if (e == hipSuccess) e = launch_collect_begin(S, sc->stream);
     if (e != hipSuccess) return restore(fail(sc, CDEM_E_HIP, hipGetErrorString(e)));
     int64_t nb = S.n_regions;
@@ -1288,5 +1291,8 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     n.det_due = 1;
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;
     n.guard = 0;
+    n.guard_next = 0;
+    n.vmax_next = 0;
+    n.pose_fresh = 0;
     return write_ctl(sc, n);
 }

@@ -69,6 +69,10 @@ struct Ctl {
     int64_t audit_true;      // true contacts seen by the last audit
     int64_t audit_last_missed;
     int64_t n_ss;            // sphere-sphere pairs written by the detection in progress
+    int32_t pose_fresh;      // sphere poses, kinematics, guard and speeds already match the state
+    int32_t guard_next;      // guard of the next step, found while computing its poses
+    uint32_t vmax_next;      // max sphere speed of the next step (float bits)
+    int32_t pad2;
 };
 
 // Detection plan parameters (fixed rule), set by cdem_set_detection.
@@ -146,7 +150,7 @@ struct DevScene {
     // big clumps
     const int32_t *big_list;         // clump ids
     int32_t n_big;
-    int32_t pad;
+    int32_t guard_on;                // the displacement guard is checked (deferred detection)
     const float *crad;               // [nc] bounding radius of each clump about its CoM
     Plan plan;
     // learned envelopes and training-data collection
@@ -179,13 +183,13 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_COUNT };
+                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_POSE_BIG, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 
 // Launchers (kernels.hip).  Every launcher enqueues on `st` and returns the
 // hipError_t of the launch.
-hipError_t launch_pose(const DevScene &S, int guard, hipStream_t st);
+hipError_t launch_pose(const DevScene &S, hipStream_t st);
 hipError_t launch_detect(const DevScene &S, hipStream_t st);
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st);
 hipError_t launch_step_end(const DevScene &S, hipStream_t st);

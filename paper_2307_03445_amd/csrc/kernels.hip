@@ -50,49 +50,97 @@ __device__ __forceinline__ void quat_mat(double w, double x, double y, double z,
 }
 
 // ---------------------------------------------------------------- pose (per sphere)
-__global__ void __launch_bounds__(256) k_pose(DevScene S, int guard) {
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S.ns) return;
-    uint32_t c = S.owner[s];
-    double w = S.qw[c], x = S.qx[c], y = S.qy[c], z = S.qz[c];
-    double A[9];
-    quat_mat(w, x, y, z, A);
-    double X = S.px[c], Y = S.py[c], Z = S.pz[c];
-    int64_t s0 = S.sbeg[c];
-    if (s == s0) {
-        double wb0 = S.wx[c], wb1 = S.wy[c], wb2 = S.wz[c];
-        double ww0 = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
-        double ww1 = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
-        double ww2 = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
-        S.kin[3 * (int64_t)c + 0] = make_double4(X, Y, Z, S.mass[c]);
-        S.kin[3 * (int64_t)c + 1] = make_double4(S.vx[c], S.vy[c], S.vz[c], 0.0);
-        S.kin[3 * (int64_t)c + 2] = make_double4(ww0, ww1, ww2, 0.0);
-    }
-    uint32_t ts = S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - s0);
-    double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
-    double xs = X + (A[0] * o0 + A[1] * o1 + A[2] * o2);
-    double ys = Y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
-    double zs = Z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+// Pose of sphere s (template sphere ts) of a clump with rotation A, CoM X,
+// velocity V and world angular velocity Wv: centre and radius to spos; with
+// the guard on, whether it has moved past its margin since the last
+// detection; with the guard or the speed store on, the speed of its centre.
+struct PoseOut { bool trip; float speed; };
+__device__ __forceinline__ PoseOut sphere_pose(const DevScene &S, int64_t s, uint32_t ts, const double *A,
+                                               const double *X, const double *V, const double *Wv) {
+    const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+    const double xs = X[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+    const double ys = X[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+    const double zs = X[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
     S.spos[s] = make_double4(xs, ys, zs, S.tmpl_rad[ts]);
-    if (guard) {
-        double4 d = S.sdet[s];
-        double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
-        double d2 = dx * dx + dy * dy + dz * dz;
-        double lim = 0.999 * (double)S.smargin[s];
-        if (!(d2 < lim * lim)) S.ctl->guard = 1;
+    PoseOut r{false, 0.0f};
+    if (S.guard_on) {
+        const double4 d = S.sdet[s];
+        const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
+        const double d2 = dx * dx + dy * dy + dz * dz;
+        const double lim = 0.999 * (double)S.smargin[s];
+        r.trip = !(d2 < lim * lim);
     }
-    if (guard || S.store_speed) {
-        // speed of this sphere's centre: |v_c + w x r|
-        double wb0 = S.wx[c], wb1 = S.wy[c], wb2 = S.wz[c];
-        double w0 = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
-        double w1 = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
-        double w2 = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
-        double r0 = xs - X, r1 = ys - Y, r2 = zs - Z;
-        double u0 = S.vx[c] + (w1 * r2 - w2 * r1), u1 = S.vy[c] + (w2 * r0 - w0 * r2), u2 = S.vz[c] + (w0 * r1 - w1 * r0);
-        float sp = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
-        if (S.store_speed) S.sspeed[s] = sp;
-        if (sp > __uint_as_float(S.ctl->vmax_bits)) atomicMax(&S.ctl->vmax_bits, __float_as_uint(sp));
+    if (S.guard_on || S.store_speed) {
+        // speed of the centre: |v_c + w x r|
+        const double r0 = xs - X[0], r1 = ys - X[1], r2 = zs - X[2];
+        const double u0 = V[0] + (Wv[1] * r2 - Wv[2] * r1), u1 = V[1] + (Wv[2] * r0 - Wv[0] * r2),
+                     u2 = V[2] + (Wv[0] * r1 - Wv[1] * r0);
+        r.speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+        if (S.store_speed) S.sspeed[s] = r.speed;
     }
+    return r;
+}
+
+// World angular velocity A w_body.
+__device__ __forceinline__ void world_omega(const double *A, double wb0, double wb1, double wb2, double *Wv) {
+    Wv[0] = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
+    Wv[1] = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
+    Wv[2] = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
+}
+
+// Raise a device-wide float maximum kept as bits in the control block.  The
+// current value is read at device scope first (a plain load may see a stale
+// per-XCD L2 copy), so the atomic is issued only by the few values that
+// still raise it.
+__device__ __forceinline__ void raise_max(uint32_t *slot, float v) {
+    if (!(v > 0.0f)) return;
+    const uint32_t cur = __hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v > __uint_as_float(cur)) atomicMax(slot, __float_as_uint(v));
+}
+
+// Workgroup-aggregated guard flag and speed maximum into the control block
+// (every thread of the workgroup calls it).
+__device__ __forceinline__ void pose_flags(int32_t *guard, uint32_t *vmax, PoseOut r) {
+    __shared__ float wmax[16];
+    __shared__ int wtrip[16];
+    const unsigned long long trips = __ballot(r.trip);
+    float v = r.speed;
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    const int wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) { wmax[wid] = v; wtrip[wid] = trips != 0; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float m = 0.0f;
+        int t = 0;
+        for (int k = 0; k < nw; k++) { m = fmaxf(m, wmax[k]); t |= wtrip[k]; }
+        if (t) *guard = 1;
+        raise_max(vmax, m);
+    }
+}
+
+// Poses of the current state, one lane per sphere.  Only needed when the
+// host changed the state or the scene's settings: otherwise the integration
+// of the previous step already left them (ctl->pose_fresh).
+__global__ void __launch_bounds__(256) k_pose(DevScene S) {
+    if (S.ctl->pose_fresh) return;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    PoseOut r{false, 0.0f};
+    if (s < S.ns) {
+        const uint32_t c = S.owner[s];
+        double A[9];
+        quat_mat(S.qw[c], S.qx[c], S.qy[c], S.qz[c], A);
+        const double X[3] = {S.px[c], S.py[c], S.pz[c]}, V[3] = {S.vx[c], S.vy[c], S.vz[c]};
+        double Wv[3];
+        world_omega(A, S.wx[c], S.wy[c], S.wz[c], Wv);
+        const int64_t s0 = S.sbeg[c];
+        if (s == s0) {
+            S.kin[3 * (int64_t)c + 0] = make_double4(X[0], X[1], X[2], S.mass[c]);
+            S.kin[3 * (int64_t)c + 1] = make_double4(V[0], V[1], V[2], 0.0);
+            S.kin[3 * (int64_t)c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
+        }
+        r = sphere_pose(S, s, S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - s0), A, X, V, Wv);
+    }
+    pose_flags(&S.ctl->guard, &S.ctl->vmax_bits, r);
 }
 
 // ---------------------------------------------------------------- boundaries
@@ -1018,7 +1066,8 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, int cu
 
 // Symplectic Euler of one clump from its total force and torque (world frame).
 // Returns an acceleration envelope of its spheres, |a_c| + |dw/dt| r_b + |w|^2 r_b.
-__device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T) {
+__device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T,
+                                                 double *next = nullptr) {
     double h = S.h;
     double M = S.mass[c];
     double qw = S.qw[c], qx = S.qx[c], qy = S.qy[c], qz = S.qz[c];
@@ -1068,6 +1117,10 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     S.vx[c] = v[0]; S.vy[c] = v[1]; S.vz[c] = v[2];
     S.wx[c] = w[0]; S.wy[c] = w[1]; S.wz[c] = w[2];
     S.qw[c] = q[0]; S.qx[c] = q[1]; S.qy[c] = q[2]; S.qz[c] = q[3];
+    if (next) {  // the new state, for the next step's poses: x, q, v, w_body
+        for (int i = 0; i < 3; i++) { next[i] = x[i]; next[7 + i] = v[i]; next[10 + i] = w[i]; }
+        for (int i = 0; i < 4; i++) next[3 + i] = q[i];
+    }
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
           isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
         S.ctl->nonfinite = 1;
@@ -1078,8 +1131,7 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
 
 __device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
     for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
-    if ((threadIdx.x & 63) == 0 && a > 0.0f && !(a <= __uint_as_float(S.ctl->amax_bits)))
-        atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
+    if ((threadIdx.x & 63) == 0) raise_max(&S.ctl->amax_bits, a);
 }
 
 // One lane per sphere.  Waves are scheduled on clump boundaries (wave w
@@ -1092,9 +1144,10 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     if (aborted(S.ctl)) return;
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
-    if (w >= S.n_waves) return;  // whole wave leaves together
-    const int32_t c0 = S.wave_clump0[2 * w], c1 = S.wave_clump0[2 * w + 1];
-    const int64_t S0 = S.sbeg[c0], S1 = S.sbeg[c1];
+    // a wave past the schedule has no sphere, but still joins the workgroup's flag reduction
+    const bool live = w < S.n_waves;
+    const int32_t c0 = live ? S.wave_clump0[2 * w] : 0, c1 = live ? S.wave_clump0[2 * w + 1] : 0;
+    const int64_t S0 = S.sbeg[c0], S1 = live ? S.sbeg[c1] : S0;
     const int64_t s = S0 + lane;
     const bool active = s < S1;
     const int cur = S.ctl->buf;
@@ -1123,14 +1176,60 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
         }
     }
     float acc = 0.0f;
+    double nx[13];
+    for (int i = 0; i < 13; i++) nx[i] = 0.0;
     if (leader) {
         const Grid &g = S.grids[S.clump_scene[c]];
         double M = S.mass[c];
         Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
         if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
-        acc = integrate_clump(S, c, Fc, Tc);
+        acc = integrate_clump(S, c, Fc, Tc, nx);
     }
     if (S.detect_mode != 0) wave_max_acc(S, acc);
+    // The next step's poses from the state just integrated, which the clump's
+    // spheres (adjacent lanes) take from their leader lane: this saves the
+    // pose kernel's second pass over the clump state.
+    const int ldr = active ? (int)(cb - S0) : lane;
+    for (int i = 0; i < 13; i++) nx[i] = __shfl(nx[i], ldr, 64);
+    PoseOut r{false, 0.0f};
+    if (active) {
+        double A[9], Wv[3];
+        quat_mat(nx[3], nx[4], nx[5], nx[6], A);
+        world_omega(A, nx[10], nx[11], nx[12], Wv);
+        if (leader) {
+            S.kin[3 * c + 0] = make_double4(nx[0], nx[1], nx[2], S.mass[c]);
+            S.kin[3 * c + 1] = make_double4(nx[7], nx[8], nx[9], 0.0);
+            S.kin[3 * c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
+        }
+        r = sphere_pose(S, s, S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - cb), A, nx, nx + 7, Wv);
+    }
+    pose_flags(&S.ctl->guard_next, &S.ctl->vmax_next, r);
+}
+
+// Next-step poses of the spheres of the clumps too big for one wavefront
+// (after k_integrate_big), from the integrated state in memory.
+__global__ void __launch_bounds__(256) k_pose_big(DevScene S) {
+    if (aborted(S.ctl)) return;
+    const int32_t c = S.big_list[blockIdx.y];
+    const int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    double A[9], Wv[3];
+    quat_mat(S.qw[c], S.qx[c], S.qy[c], S.qz[c], A);
+    world_omega(A, S.wx[c], S.wy[c], S.wz[c], Wv);
+    const double X[3] = {S.px[c], S.py[c], S.pz[c]}, V[3] = {S.vx[c], S.vy[c], S.vz[c]};
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        S.kin[3 * (int64_t)c + 0] = make_double4(X[0], X[1], X[2], S.mass[c]);
+        S.kin[3 * (int64_t)c + 1] = make_double4(V[0], V[1], V[2], 0.0);
+        S.kin[3 * (int64_t)c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
+    }
+    const uint32_t tb = S.tmpl_sbeg[S.clump_tmpl[c]];
+    // every lane runs the same number of rounds so the wave-level flags see all lanes
+    const int64_t n = s1 - s0, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t k = base + threadIdx.x;
+        PoseOut r{false, 0.0f};
+        if (k < n) r = sphere_pose(S, s0 + k, tb + (uint32_t)k, A, X, V, Wv);
+        pose_flags(&S.ctl->guard_next, &S.ctl->vmax_next, r);
+    }
 }
 
 // Clumps with many spheres (a wheel): per-sphere sums first, then one workgroup
@@ -1182,11 +1281,15 @@ __global__ void k_step_end(DevScene S) {
     c->contacts_acc = 0;
     c->amax_last = c->amax_bits;
     c->amax_bits = 0;
-    c->vmax_bits = 0;
+    // the integration computed the next step's poses, speeds and guard
+    c->vmax_bits = c->vmax_next;
+    c->vmax_next = 0;
+    c->guard = c->guard_next;
+    c->guard_next = 0;
+    c->pose_fresh = 1;
     c->step++;
     c->since_det++;
     c->det_due = (S.detect_mode == 0 || c->since_det >= c->k_cur) ? 1 : 0;
-    c->guard = 0;
 }
 
 // ---------------------------------------------------------------- audit
@@ -1355,7 +1458,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
-                                           "k_narrow_over", "k_region_margin"};
+                                           "k_narrow_over", "k_region_margin", "k_pose_big"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1372,9 +1475,9 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_pose(const DevScene &S, int guard, hipStream_t st) {
+hipError_t launch_pose(const DevScene &S, hipStream_t st) {
     if (S.ns == 0) return hipSuccess;
-    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, guard));
+    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
     return hipGetLastError();
 }
 
@@ -1459,6 +1562,7 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
         else
             TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_reduce_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
         TIMED(K_INTEGRATE_BIG, hipLaunchKernelGGL(k_integrate_big, dim3(S.n_big), dim3(256), 0, st, S));
+        TIMED(K_POSE_BIG, hipLaunchKernelGGL(k_pose_big, dim3(16, S.n_big), dim3(256), 0, st, S));
     }
     return hipGetLastError();
 }
