@@ -660,18 +660,30 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         });
     }
     const int nlo = cnt - nup;
+    // segment allocation: scans within each wavefront, then one atomic per
+    // workgroup and counter (same-address atomics serialise device-wide)
+    __shared__ uint32_t wtot[3][kNarrowBlock / 64];
+    __shared__ unsigned long long wbase[2][kNarrowBlock / 64];
     uint32_t totu, totl, totss;
     const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
     const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
     (void)wave_excl_scan((uint32_t)nss, totss);
-    unsigned long long bu = 0, bl = 0;
-    if ((tid & 63) == 0) {
-        if (totu) bu = atomicAdd((unsigned long long *)&S.ctl->n_up, (unsigned long long)totu);
-        if (totl) bl = atomicAdd((unsigned long long *)&S.ctl->n_pairs, (unsigned long long)totl);
-        if (totss) atomicAdd((unsigned long long *)&S.ctl->n_ss, (unsigned long long)totss);
+    const int wid = tid >> 6;
+    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; wtot[2][wid] = totss; }
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long su = 0, sl = 0, sss = 0;
+        for (int k = 0; k < kNarrowBlock / 64; k++) { su += wtot[0][k]; sl += wtot[1][k]; sss += wtot[2][k]; }
+        unsigned long long bu0 = su ? atomicAdd((unsigned long long *)&S.ctl->n_up, su) : 0ull;
+        unsigned long long bl0 = sl ? atomicAdd((unsigned long long *)&S.ctl->n_pairs, sl) : 0ull;
+        if (sss) atomicAdd((unsigned long long *)&S.ctl->n_ss, sss);
+        for (int k = 0; k < kNarrowBlock / 64; k++) {
+            wbase[0][k] = bu0; bu0 += wtot[0][k];
+            wbase[1][k] = bl0; bl0 += wtot[1][k];
+        }
     }
-    bu = __shfl(bu, 0, 64);
-    bl = __shfl(bl, 0, 64);
+    __syncthreads();
+    const unsigned long long bu = wbase[0][wid], bl = wbase[1][wid];
     if (i >= S.ns) return;
     if (bu + totu > (unsigned long long)S.cap || bl + totl > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
     const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
@@ -1012,10 +1024,21 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
 }
 
 // Wave-level sum, one atomic per wavefront.
-__device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
-    unsigned long long v = n;
+// Workgroup-level sum, one atomic per workgroup (every thread calls it).
+__device__ __forceinline__ void block_add(unsigned long long *slot, unsigned long long v) {
+    __shared__ unsigned long long part[16];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)&ctl->contacts_acc, v);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int k = 0; k < (int)((blockDim.x + 63) >> 6); k++) t += part[k];
+        if (t) atomicAdd(slot, t);
+    }
+}
+
+__device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
+    block_add((unsigned long long *)&ctl->contacts_acc, n);
 }
 
 // Every candidate pair of the active set, evaluated once, one lane per pair
@@ -1381,14 +1404,9 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        found += __shfl_xor(found, off, 64);
-        missed += __shfl_xor(missed, off, 64);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        if (found) atomicAdd((unsigned long long *)&S.ctl->audit_true, found);
-        if (missed) atomicAdd((unsigned long long *)&S.ctl->audit_last_missed, missed);
-    }
+    block_add((unsigned long long *)&S.ctl->audit_true, found);
+    __syncthreads();  // block_add's partials are reused
+    block_add((unsigned long long *)&S.ctl->audit_last_missed, missed);
 }
 
 __global__ void k_audit_end(DevScene S) {
