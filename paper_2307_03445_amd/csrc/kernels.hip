@@ -1068,22 +1068,42 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, int cu
     using V = typename Contrib<FP32>::V;
     const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
     const uint32_t ub = S.up_beg[s], nu = S.up_cnt[s];
-    for (uint32_t k = 0; k < nu; k++) {
-        const int64_t e = S.um[ub + k];
-        const V a = cS[e];
-        if (a.w == 0) continue;
-        const V b = cTt[e];
-        Fs[0] = Fs[0] + (double)(-a.x); Fs[1] = Fs[1] + (double)(-a.y); Fs[2] = Fs[2] + (double)(-a.z);
-        Ts[0] = Ts[0] + (double)b.x; Ts[1] = Ts[1] + (double)b.y; Ts[2] = Ts[2] + (double)b.z;
-    }
     const uint32_t lb = pick(S.lo_beg, cur)[s], nl = pick(S.lo_cnt, cur)[s];
-    for (uint32_t k = 0; k < nl; k++) {
-        const int64_t e = (int64_t)lb + k;
-        const V a = cS[e];
-        if (a.w == 0) continue;
-        const V b = cTs[e];
-        Fs[0] = Fs[0] + (double)a.x; Fs[1] = Fs[1] + (double)a.y; Fs[2] = Fs[2] + (double)a.z;
-        Ts[0] = Ts[0] + (double)b.x; Ts[1] = Ts[1] + (double)b.y; Ts[2] = Ts[2] + (double)b.z;
+    // Entries are taken in batches whose loads are all issued before the first
+    // is used (the sums stay in ascending partner order); the first lower batch
+    // is loaded together with the upper links.
+    constexpr uint32_t kB = 4;
+    V la[kB], lt[kB];
+#pragma unroll
+    for (uint32_t j = 0; j < kB; j++)
+        if (j < nl) { la[j] = cS[(int64_t)lb + j]; lt[j] = cTs[(int64_t)lb + j]; }
+    for (uint32_t k0 = 0; k0 < nu; k0 += kB) {
+        int64_t e[kB];
+#pragma unroll
+        for (uint32_t j = 0; j < kB; j++) e[j] = k0 + j < nu ? (int64_t)S.um[ub + k0 + j] : -1;
+        V a[kB], b[kB];
+#pragma unroll
+        for (uint32_t j = 0; j < kB; j++)
+            if (e[j] >= 0) { a[j] = cS[e[j]]; b[j] = cTt[e[j]]; }
+#pragma unroll
+        for (uint32_t j = 0; j < kB; j++) {
+            if (e[j] < 0 || a[j].w == 0) continue;
+            Fs[0] = Fs[0] + (double)(-a[j].x); Fs[1] = Fs[1] + (double)(-a[j].y); Fs[2] = Fs[2] + (double)(-a[j].z);
+            Ts[0] = Ts[0] + (double)b[j].x; Ts[1] = Ts[1] + (double)b[j].y; Ts[2] = Ts[2] + (double)b[j].z;
+        }
+    }
+    for (uint32_t k0 = 0; k0 < nl; k0 += kB) {
+        if (k0 > 0) {
+#pragma unroll
+            for (uint32_t j = 0; j < kB; j++)
+                if (k0 + j < nl) { la[j] = cS[(int64_t)lb + k0 + j]; lt[j] = cTs[(int64_t)lb + k0 + j]; }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < kB; j++) {
+            if (k0 + j >= nl || la[j].w == 0) continue;
+            Fs[0] = Fs[0] + (double)la[j].x; Fs[1] = Fs[1] + (double)la[j].y; Fs[2] = Fs[2] + (double)la[j].z;
+            Ts[0] = Ts[0] + (double)lt[j].x; Ts[1] = Ts[1] + (double)lt[j].y; Ts[2] = Ts[2] + (double)lt[j].z;
+        }
     }
 }
 
