@@ -508,6 +508,11 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         wsched.push_back((int32_t)c);
     }
     S.n_waves = (int64_t)wsched.size() / 2;
+    S.n_rblocks = (S.n_waves + 3) / 4;            // workgroups of the reduction (four waves each)
+    S.n_ablocks = (ns + 255) / 256;               // workgroups of the audit
+    S.part_r = (uint32_t *)dev_alloc(sc, 12 * std::max<int64_t>(S.n_rblocks, 1));
+    S.part_a = (unsigned long long *)dev_alloc(sc, 16 * std::max<int64_t>(S.n_ablocks, 1));
+    if (!S.part_r || !S.part_a) return bail(fail(sc, CDEM_E_OOM, "partials"));
     S.stride_cap = 16384;
     S.plan.k_max = 1; S.plan.audit_period = 0; S.plan.safety = 1.5f;
     S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
@@ -1033,11 +1038,22 @@ extern "C" int cdem_profile_read(cdem_scene *sc, cdem_kernel_time *out, int cap,
 
 extern "C" int cdem_last_step_contacts(cdem_scene *sc, int64_t *n) {
     if (!sc || !n) return CDEM_E_INVALID;
+    *n = 0;
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
-    *n = c.contacts_last;
-    return CDEM_OK;
+    if (c.step == 0 || c.n_pairs_cur == 0) return CDEM_OK;  // nothing evaluated yet
+    constexpr int kBlk = 1024;
+    unsigned long long *part = (unsigned long long *)dev_alloc(sc, kBlk * sizeof(unsigned long long));
+    if (!part) return fail(sc, CDEM_E_OOM, "contact count partials");
+    std::vector<unsigned long long> h(kBlk);
+    if (launch_count_contacts(sc->S, part, kBlk, sc->stream) != hipSuccess ||
+        hipStreamSynchronize(sc->stream) != hipSuccess ||
+        hipMemcpy(h.data(), part, kBlk * sizeof(unsigned long long), hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(sc, CDEM_E_HIP, "contact count");
+    dev_free(sc, part);
+    for (unsigned long long v : h) *n += (int64_t)v;
+    return rc;
 }
 
 namespace cdem {

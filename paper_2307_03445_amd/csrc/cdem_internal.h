@@ -8,7 +8,7 @@
 namespace cdem {
 
 constexpr int kMaxBnd = 64;
-constexpr int kNarrowBlock = 256;  // narrow-phase workgroup: four wavefronts share one segment allocation
+constexpr int kNarrowBlock = 512;  // narrow-phase workgroup: eight wavefronts share one segment allocation
 constexpr int kMaxRow = 32;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
 constexpr int kRegionBins = 2;     // edge of an envelope region of the learned margins, in bins
@@ -56,8 +56,7 @@ struct Ctl {
     int32_t record;          // store per-contact data this step
     int32_t nonfinite;       // a clump state became NaN/Inf
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
-    int64_t contacts_acc;    // true contacts (exact predicate, delta > 0) of the step in progress
-    int64_t contacts_last;   // ... of the last completed step (each pair counted from both sides)
+    int64_t pad_c0, pad_c1;
     int64_t n_pairs;         // pairs of the detection in progress
     int64_t n_pairs_cur;     // pairs of the active set in use
     int32_t asym;            // an entry had no mirror (never expected): the step is abandoned
@@ -68,7 +67,7 @@ struct Ctl {
     float margin_cur;        // margin of every sphere at the last detection (fixed rule)
     int64_t audit_true;      // true contacts seen by the last audit
     int64_t audit_last_missed;
-    int64_t n_ss;            // sphere-sphere pairs written by the detection in progress
+    int64_t n_bp;            // boundary pairs written by the detection in progress
     int32_t pose_fresh;      // sphere poses, kinematics, guard and speeds already match the state
     int32_t guard_next;      // guard of the next step, found while computing its poses
     uint32_t vmax_next;      // max sphere speed of the next step (float bits)
@@ -138,6 +137,12 @@ struct DevScene {
                                       // torque on the lower sphere, torque on the partner sphere (float4 / double4)
     uint32_t *up_beg, *up_cnt;        // [ns] each sphere's upper segment (current set)
     uint32_t *ut, *us, *um;           // [cap] upper entries: partner (lower id), own sphere, linked pair
+    // per-workgroup partial results, reduced by the next single-workgroup kernel
+    // (device-wide same-address atomics serialise; these do not)
+    uint32_t *part_r;                 // [n_rblocks][3] reduction: max acceleration, max speed, guard trip
+    int64_t n_rblocks;
+    unsigned long long *part_a;       // [n_ablocks][2] audit: true contacts, missed
+    int64_t n_ablocks;
     uint32_t *over_list;             // [over_cap] spheres whose rows k_narrow_over fills
     int64_t over_cap;
     // recording
@@ -201,6 +206,8 @@ hipError_t launch_collect_begin(const DevScene &S, hipStream_t st);
 hipError_t launch_collect_speed(const DevScene &S, hipStream_t st);
 hipError_t launch_collect_acc(const DevScene &S, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+// Contact sides of the last evaluated step: one partial per workgroup into part[nblk].
+hipError_t launch_count_contacts(const DevScene &S, unsigned long long *part, int nblk, hipStream_t st);
 // Force and torque on every boundary from the recorded step: partial [n_bnd][kBndParts][6], out [n_bnd][6].
 constexpr int kBndParts = 64;
 hipError_t launch_bnd_forces(const DevScene &S, double *partial, double *out, hipStream_t st);

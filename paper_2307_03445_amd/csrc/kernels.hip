@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
     if (bins)
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
     if (i == 0 && !which) {
-        S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_ss = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
+        S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_bp = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
         S.ctl->n_over = 0;
     }
     if (i == 0 && which == 1) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
@@ -642,7 +642,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
     const int nxt = S.ctl->buf ^ 1;
-    int cnt = 0, nup = 0, nss = 0;
+    int cnt = 0, nup = 0, nbp = 0;
     const uint32_t s = (uint32_t)i;
     if (i < S.ns) {
         narrow_candidates(S, s, [&](uint32_t t) {
@@ -656,7 +656,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
             }
             cnt++;
             nup += t < s;
-            nss += t > s && t < (uint32_t)S.ns;
+            nbp += t >= (uint32_t)S.ns;
         });
     }
     const int nlo = cnt - nup;
@@ -664,19 +664,19 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     // workgroup and counter (same-address atomics serialise device-wide)
     __shared__ uint32_t wtot[3][kNarrowBlock / 64];
     __shared__ unsigned long long wbase[2][kNarrowBlock / 64];
-    uint32_t totu, totl, totss;
+    uint32_t totu, totl, totbp;
     const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
     const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
-    (void)wave_excl_scan((uint32_t)nss, totss);
+    (void)wave_excl_scan((uint32_t)nbp, totbp);
     const int wid = tid >> 6;
-    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; wtot[2][wid] = totss; }
+    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; wtot[2][wid] = totbp; }
     __syncthreads();
     if (tid == 0) {
-        unsigned long long su = 0, sl = 0, sss = 0;
-        for (int k = 0; k < kNarrowBlock / 64; k++) { su += wtot[0][k]; sl += wtot[1][k]; sss += wtot[2][k]; }
+        unsigned long long su = 0, sl = 0, sbp = 0;
+        for (int k = 0; k < kNarrowBlock / 64; k++) { su += wtot[0][k]; sl += wtot[1][k]; sbp += wtot[2][k]; }
         unsigned long long bu0 = su ? atomicAdd((unsigned long long *)&S.ctl->n_up, su) : 0ull;
         unsigned long long bl0 = sl ? atomicAdd((unsigned long long *)&S.ctl->n_pairs, sl) : 0ull;
-        if (sss) atomicAdd((unsigned long long *)&S.ctl->n_ss, sss);
+        if (sbp) atomicAdd((unsigned long long *)&S.ctl->n_bp, sbp);  // rare: workgroups next to a boundary
         for (int k = 0; k < kNarrowBlock / 64; k++) {
             wbase[0][k] = bu0; bu0 += wtot[0][k];
             wbase[1][k] = bl0; bl0 += wtot[1][k];
@@ -753,7 +753,7 @@ __global__ void __launch_bounds__(256) k_link(DevScene S) {
 __global__ void k_detect_end(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || c->overflow) return;
-    if (c->n_ss != c->n_up) c->asym = 1;  // every sphere pair has exactly one upper entry
+    if (c->n_pairs - c->n_bp != c->n_up) c->asym = 1;  // every sphere pair has exactly one upper entry
     if (c->row_overflow || c->asym) { c->overflow = 1; return; }
     if (c->guard && !c->det_due) c->guard_trips++;
     c->buf ^= 1;
@@ -1024,22 +1024,6 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
 }
 
 // Wave-level sum, one atomic per wavefront.
-// Workgroup-level sum, one atomic per workgroup (every thread calls it).
-__device__ __forceinline__ void block_add(unsigned long long *slot, unsigned long long v) {
-    __shared__ unsigned long long part[16];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int k = 0; k < (int)((blockDim.x + 63) >> 6); k++) t += part[k];
-        if (t) atomicAdd(slot, t);
-    }
-}
-
-__device__ __forceinline__ void count_contacts(Ctl *ctl, uint32_t n) {
-    block_add((unsigned long long *)&ctl->contacts_acc, n);
-}
 
 // Every candidate pair of the active set, evaluated once, one lane per pair
 // (grid-stride in memory order, which follows the sphere ids and so is
@@ -1053,10 +1037,27 @@ __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
     const int64_t n = S.ctl->n_pairs_cur;
     const bool rec = S.ctl->record != 0;
     const double tnow = (double)S.ctl->step * S.h;
-    uint32_t ncont = 0;
     for (int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        ncont += eval_pair<FP32>(S, e, pt, hist, tnow, rec);
-    count_contacts(S.ctl, ncont);
+        (void)eval_pair<FP32>(S, e, pt, hist, tnow, rec);
+}
+
+// Contact sides of the last evaluated step (each sphere pair in contact counts
+// twice, a boundary contact once), from the pairs' contact flags; one partial
+// per workgroup.
+template <bool FP32>
+__global__ void __launch_bounds__(256) k_count_contacts(DevScene S, unsigned long long *part) {
+    using V = typename Contrib<FP32>::V;
+    const V *cS = (const V *)S.cS;
+    const uint32_t *pt = pick(S.pt, S.ctl->buf);
+    const int64_t n = S.ctl->n_pairs_cur;
+    unsigned long long v = 0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        if (cS[e].w != 0) v += pt[e] < (uint32_t)S.ns ? 2 : 1;
+    __shared__ unsigned long long sh[4];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // Force and torque on sphere s from its contacts, summed in ascending
@@ -1172,10 +1173,6 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     return aenv;
 }
 
-__device__ __forceinline__ void wave_max_acc(const DevScene &S, float a) {
-    for (int off = 32; off > 0; off >>= 1) a = fmaxf(a, __shfl_xor(a, off, 64));
-    if ((threadIdx.x & 63) == 0) raise_max(&S.ctl->amax_bits, a);
-}
 
 // One lane per sphere.  Waves are scheduled on clump boundaries (wave w
 // covers the whole clumps wave_clump0[2w] .. wave_clump0[2w+1]-1, at most 64
@@ -1228,7 +1225,6 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
         if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
         acc = integrate_clump(S, c, Fc, Tc, nx);
     }
-    if (S.detect_mode != 0) wave_max_acc(S, acc);
     // The next step's poses from the state just integrated, which the clump's
     // spheres (adjacent lanes) take from their leader lane: this saves the
     // pose kernel's second pass over the clump state.
@@ -1246,7 +1242,24 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
         }
         r = sphere_pose(S, s, S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - cb), A, nx, nx + 7, Wv);
     }
-    pose_flags(&S.ctl->guard_next, &S.ctl->vmax_next, r);
+    // workgroup partials of the acceleration and speed maxima and the guard,
+    // reduced by k_step_end
+    __shared__ float pa[4], pv[4];
+    __shared__ uint32_t pt_[4];
+    float am = acc, vm = r.speed;
+    for (int off = 32; off > 0; off >>= 1) {
+        am = fmaxf(am, __shfl_xor(am, off, 64));
+        vm = fmaxf(vm, __shfl_xor(vm, off, 64));
+    }
+    const unsigned long long trips = __ballot(r.trip);
+    if (lane == 0) { pa[threadIdx.x >> 6] = am; pv[threadIdx.x >> 6] = vm; pt_[threadIdx.x >> 6] = trips != 0; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *o = S.part_r + 3 * (int64_t)blockIdx.x;
+        o[0] = __float_as_uint(fmaxf(fmaxf(pa[0], pa[1]), fmaxf(pa[2], pa[3])));
+        o[1] = __float_as_uint(fmaxf(fmaxf(pv[0], pv[1]), fmaxf(pv[2], pv[3])));
+        o[2] = pt_[0] | pt_[1] | pt_[2] | pt_[3];
+    }
 }
 
 // Next-step poses of the spheres of the clumps too big for one wavefront
@@ -1316,18 +1329,40 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     }
 }
 
-__global__ void k_step_end(DevScene S) {
+// End of step: fold the workgroup partials of the reduction (maxima are of
+// non-negative floats, so their bit patterns order like the values), then the
+// schedule.  One workgroup.
+__global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     Ctl *c = S.ctl;
+    const bool ok = !c->overflow;
+    uint32_t am = 0, vm = 0, tr = 0;
+    if (ok)
+        for (int64_t k = threadIdx.x; k < S.n_rblocks; k += blockDim.x) {
+            const uint32_t *o = S.part_r + 3 * k;
+            am = max(am, o[0]);
+            vm = max(vm, o[1]);
+            tr |= o[2];
+        }
+    __shared__ uint32_t sh[3][16];
+    for (int off = 32; off > 0; off >>= 1) {
+        am = max(am, (uint32_t)__shfl_xor((int)am, off, 64));
+        vm = max(vm, (uint32_t)__shfl_xor((int)vm, off, 64));
+        tr |= (uint32_t)__shfl_xor((int)tr, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = am; sh[1][threadIdx.x >> 6] = vm; sh[2][threadIdx.x >> 6] = tr; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) { am = max(am, sh[0][k]); vm = max(vm, sh[1][k]); tr |= sh[2][k]; }
+    am = max(am, sh[0][0]); vm = max(vm, sh[1][0]); tr |= sh[2][0];
     c->record = 0;
-    if (c->overflow) return;
-    c->contacts_last = c->contacts_acc;
-    c->contacts_acc = 0;
-    c->amax_last = c->amax_bits;
+    if (!ok) return;
+    // the clumps too big for one wavefront report through the atomic slots
+    c->amax_last = S.detect_mode != 0 ? max(c->amax_bits, am) : 0u;
     c->amax_bits = 0;
     // the integration computed the next step's poses, speeds and guard
-    c->vmax_bits = c->vmax_next;
+    c->vmax_bits = max(c->vmax_next, vm);
     c->vmax_next = 0;
-    c->guard = c->guard_next;
+    c->guard = (c->guard_next | (int32_t)tr) != 0;
     c->guard_next = 0;
     c->pose_fresh = 1;
     c->step++;
@@ -1424,15 +1459,35 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
             }
         }
     }
-    block_add((unsigned long long *)&S.ctl->audit_true, found);
-    __syncthreads();  // block_add's partials are reused
-    block_add((unsigned long long *)&S.ctl->audit_last_missed, missed);
+    __shared__ unsigned long long sh[2][4];
+    for (int off = 32; off > 0; off >>= 1) {
+        found += __shfl_xor(found, off, 64);
+        missed += __shfl_xor(missed, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = found; sh[1][threadIdx.x >> 6] = missed; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        S.part_a[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+        S.part_a[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
 }
 
-__global__ void k_audit_end(DevScene S) {
+__global__ void __launch_bounds__(1024) k_audit_end(DevScene S) {
     if (!audit_due(S)) return;
-    S.ctl->audits++;
-    S.ctl->missed += S.ctl->audit_last_missed;
+    unsigned long long f = 0, m = 0;
+    for (int64_t k = threadIdx.x; k < S.n_ablocks; k += blockDim.x) { f += S.part_a[2 * k]; m += S.part_a[2 * k + 1]; }
+    __shared__ unsigned long long sh[2][16];
+    for (int off = 32; off > 0; off >>= 1) { f += __shfl_xor(f, off, 64); m += __shfl_xor(m, off, 64); }
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = f; sh[1][threadIdx.x >> 6] = m; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long tf = 0, tm = 0;
+        for (int k = 0; k < (int)(blockDim.x >> 6); k++) { tf += sh[0][k]; tm += sh[1][k]; }
+        S.ctl->audit_true = (int64_t)tf;
+        S.ctl->audit_last_missed = (int64_t)tm;
+        S.ctl->audits++;
+        S.ctl->missed += (int64_t)tm;
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1559,6 +1614,12 @@ hipError_t launch_bnd_forces(const DevScene &S, double *partial, double *out, hi
     return hipGetLastError();
 }
 
+hipError_t launch_count_contacts(const DevScene &S, unsigned long long *part, int nblk, hipStream_t st) {
+    if (S.precision == 1) hipLaunchKernelGGL(k_count_contacts<true>, dim3(nblk), dim3(256), 0, st, S, part);
+    else hipLaunchKernelGGL(k_count_contacts<false>, dim3(nblk), dim3(256), 0, st, S, part);
+    return hipGetLastError();
+}
+
 hipError_t launch_collect_begin(const DevScene &S, hipStream_t st) {
     binning(S, 2, st);
     hipLaunchKernelGGL(k_collect_init, dim3(stride_blocks(std::max<int64_t>(S.ns, S.n_regions))), dim3(256), 0, st, S);
@@ -1579,7 +1640,7 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     if (S.ns == 0 || S.plan.audit_period <= 0) return hipSuccess;
     binning(S, 1, st);
     TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
-    hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1), 0, st, S);
+    hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1024), 0, st, S);
     return hipGetLastError();
 }
 
@@ -1606,7 +1667,7 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
 }
 
 hipError_t launch_step_end(const DevScene &S, hipStream_t st) {
-    TIMED(K_STEP_END, hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, st, S));
+    TIMED(K_STEP_END, hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1024), 0, st, S));
     return hipGetLastError();
 }
 
