@@ -577,8 +577,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.cacc = (float *)dev_alloc(sc, 4 * std::max<int64_t>(nc, 1));
     S.cell_t = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     // spheres with more than kMaxRow candidates are rare (a large sphere among
-    // many small ones); a list of ns/32 (at least 4096) of them per detection
-    S.over_cap = std::max<int64_t>(4096, ns / 32);
+    // many small ones); a list of ns/8 (at least 4096) of them per detection
+    S.over_cap = std::max<int64_t>(4096, ns / 8);
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
     if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     for (int k = 0; k < 2; k++) {
@@ -728,7 +728,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         if (c.nonfinite) return fail(sc, CDEM_E_NAN, "non-finite clump state");
         if (!c.overflow) break;
         if (c.row_overflow)
-            return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 32 candidate partners (margin too large)");
+            return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 16 candidate partners (margin too large)");
         if (c.asym) return fail(sc, CDEM_E_STATE, "active-set rows are not symmetric");
         // grow the active set and resume from the step that did not complete
         int64_t need = (int64_t)(1.3 * (double)std::max(c.n_up, c.n_pairs)) + 1024;

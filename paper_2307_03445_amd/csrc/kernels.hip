@@ -438,15 +438,37 @@ __global__ void k_plan(DevScene S) {
 // Features of the envelope regions (blocks of kRegionBins^3 bins): max sphere
 // speed, max acceleration envelope of the spheres' clumps (last step),
 // occupancy (spheres in the region).
+// Neighbouring spheres mostly share a region: the lanes of a wavefront first
+// combine runs of equal region (maxima by shuffles, counts from the run
+// heads), and only each run's first lane updates the region.
 __global__ void __launch_bounds__(256) k_bin_features(DevScene S, int which) {
     if (!(which == 2 || (due(S.ctl) && S.detect_mode == 2))) return;
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S.ns) return;
-    int64_t r = region_of(S.grids[S.sscene[s]], S.cell_of[s]);
-    float v = S.sspeed[s], a = S.cacc[S.owner[s]];
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int64_t r = -1;
+    float v = 0.f, a = 0.f;
+    if (s < S.ns) {
+        r = region_of(S.grids[S.sscene[s]], S.cell_of[s]);
+        v = S.sspeed[s];
+        a = S.cacc[S.owner[s]];
+    }
+    const int rl = (int)r, rh = (int)(r >> 32);
+    const int pl = __shfl_up(rl, 1, 64), ph = __shfl_up(rh, 1, 64);
+    const bool head = lane == 0 || pl != rl || ph != rh;
+    const unsigned long long heads = __ballot(head);
+    // run maxima: combine with lanes further down the same run
+    for (int off = 1; off < 64; off <<= 1) {
+        const int ol = __shfl_down(rl, off, 64), oh = __shfl_down(rh, off, 64);
+        const float ov = __shfl_down(v, off, 64), oa = __shfl_down(a, off, 64);
+        if (lane + off < 64 && ol == rl && oh == rh) { v = fmaxf(v, ov); a = fmaxf(a, oa); }
+    }
+    if (!head || r < 0) return;
+    const unsigned long long later = lane < 63 ? heads >> (lane + 1) : 0ull;
+    const int next = later ? lane + 1 + __builtin_ctzll(later) : 64;
+    const uint32_t n = (uint32_t)(next - lane);  // the run (an invalid lane has r < 0: a run of its own)
     if (v > 0.f) atomicMax(&S.bin_v[r], __float_as_uint(v));
     if (a > 0.f) atomicMax(&S.bin_a[r], __float_as_uint(a));
-    atomicAdd(&S.reg_occ[r], 1u);
+    atomicAdd(&S.reg_occ[r], n);
 }
 
 // Envelopes of each occupied region for this detection: the MLP predicts the
