@@ -504,8 +504,17 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
             n += k;
             c++;
         }
-        wsched.push_back((int32_t)start);
-        wsched.push_back((int32_t)c);
+        wsched.push_back((int32_t)sbeg[start]);
+        wsched.push_back((int32_t)sbeg[c]);
+    }
+    std::vector<uint32_t> sinfo(ns), sts(ns);
+    for (int64_t c = 0; c < nc; c++) {
+        const int64_t k = sbeg[c + 1] - sbeg[c];
+        const uint32_t t = d->clump_template[c];
+        for (int64_t s = sbeg[c]; s < sbeg[c + 1]; s++) {
+            sinfo[s] = k <= kBigClump ? (uint32_t)(s - sbeg[c]) | ((uint32_t)k << 8) : 0u;
+            sts[s] = d->tmpl_sphere_begin[t] + (uint32_t)(s - sbeg[c]);
+        }
     }
     S.n_waves = (int64_t)wsched.size() / 2;
     S.n_rblocks = (S.n_waves + 3) / 4;            // workgroups of the reduction (four waves each)
@@ -556,7 +565,9 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     UP(bnd, sc->bnd.data(), sc->bnd.size());
     UP(big_list, big.data(), big.size());
     UP(crad, crad.data(), crad.size());
-    UP(wave_clump0, wsched.data(), wsched.size());
+    UP(wave_s, wsched.data(), wsched.size());
+    UP(sinfo, sinfo.data(), sinfo.size());
+    UP(sts, sts.data(), sts.size());
 #undef UP
     S.n_big = (int32_t)big.size();
     S.kin = (double4 *)dev_alloc(sc, 3 * sizeof(double4) * std::max<int64_t>(nc, 1));

@@ -170,9 +170,11 @@ struct DevScene {
     const float *mlp;                // envelope MLP parameters (device), null if none loaded
     uint32_t *cell_t, *occ_t;        // collection: regions of the spheres and region occupancy at capture
     uint32_t *lab_v, *lab_a;         // collection: max speed / acceleration over the horizon (float bits)
-    // wave schedule of the force kernel: wave w covers clumps wave_clump0[2w] ..
-    // wave_clump0[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
-    const int32_t *wave_clump0;
+    // wave schedule of the reduction: wave w covers spheres wave_s[2w] ..
+    // wave_s[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
+    const int32_t *wave_s;
+    const uint32_t *sinfo;           // [ns] index of the sphere in its clump | clump size << 8 (clumps of <= 64)
+    const uint32_t *sts;             // [ns] template sphere of each sphere
     int64_t n_waves;
     // launch shape of the grid-stride kernels (tunable; results do not depend on it)
     int32_t stride_cap;              // maximum workgroups of k_pairs / k_link / k_bin_margin

@@ -55,19 +55,31 @@ __device__ __forceinline__ void quat_mat(double w, double x, double y, double z,
 // the guard on, whether it has moved past its margin since the last
 // detection; with the guard or the speed store on, the speed of its centre.
 struct PoseOut { bool trip; float speed; };
-__device__ __forceinline__ PoseOut sphere_pose(const DevScene &S, int64_t s, uint32_t ts, const double *A,
+// What the pose of one sphere reads: its template offset and radius and, for
+// the guard, where it stood at the last detection and its margin.
+struct PoseIn { double o0, o1, o2, rad; double4 det; float margin; };
+__device__ __forceinline__ PoseIn pose_in(const DevScene &S, int64_t s, uint32_t ts) {
+    PoseIn p;
+    p.o0 = S.tmpl_ofs[3 * ts]; p.o1 = S.tmpl_ofs[3 * ts + 1]; p.o2 = S.tmpl_ofs[3 * ts + 2];
+    p.rad = S.tmpl_rad[ts];
+    if (S.guard_on) { p.det = S.sdet[s]; p.margin = S.smargin[s]; }
+    else { p.det = make_double4(0.0, 0.0, 0.0, 0.0); p.margin = 0.0f; }
+    return p;
+}
+
+__device__ __forceinline__ PoseOut sphere_pose(const DevScene &S, int64_t s, const PoseIn &in, const double *A,
                                                const double *X, const double *V, const double *Wv) {
-    const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+    const double o0 = in.o0, o1 = in.o1, o2 = in.o2;
     const double xs = X[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
     const double ys = X[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
     const double zs = X[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
-    S.spos[s] = make_double4(xs, ys, zs, S.tmpl_rad[ts]);
+    S.spos[s] = make_double4(xs, ys, zs, in.rad);
     PoseOut r{false, 0.0f};
     if (S.guard_on) {
-        const double4 d = S.sdet[s];
+        const double4 d = in.det;
         const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
         const double d2 = dx * dx + dy * dy + dz * dz;
-        const double lim = 0.999 * (double)S.smargin[s];
+        const double lim = 0.999 * (double)in.margin;
         r.trip = !(d2 < lim * lim);
     }
     if (S.guard_on || S.store_speed) {
@@ -138,7 +150,7 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S) {
             S.kin[3 * (int64_t)c + 1] = make_double4(V[0], V[1], V[2], 0.0);
             S.kin[3 * (int64_t)c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
         }
-        r = sphere_pose(S, s, S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - s0), A, X, V, Wv);
+        r = sphere_pose(S, s, pose_in(S, s, S.sts[s]), A, X, V, Wv);
     }
     pose_flags(&S.ctl->guard, &S.ctl->vmax_bits, r);
 }
@@ -1087,11 +1099,10 @@ __global__ void __launch_bounds__(256) k_count_contacts(DevScene S, unsigned lon
 // minus the stored force on the partner), then the lower segment (partners
 // above s, boundaries last).
 template <bool FP32>
-__device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t s, int cur, double *Fs, double *Ts) {
+__device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint32_t nu, uint32_t lb, uint32_t nl,
+                                           double *Fs, double *Ts) {
     using V = typename Contrib<FP32>::V;
     const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
-    const uint32_t ub = S.up_beg[s], nu = S.up_cnt[s];
-    const uint32_t lb = pick(S.lo_beg, cur)[s], nl = pick(S.lo_cnt, cur)[s];
     // Entries are taken in batches whose loads are all issued before the first
     // is used (the sums stay in ascending partner order); the first lower batch
     // is loaded together with the upper links.
@@ -1197,7 +1208,7 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
 
 
 // One lane per sphere.  Waves are scheduled on clump boundaries (wave w
-// covers the whole clumps wave_clump0[2w] .. wave_clump0[2w+1]-1, at most 64
+// covers the spheres wave_s[2w] .. wave_s[2w+1]-1, whole clumps, at most 64
 // spheres), so the spheres of a clump sit in adjacent lanes: each lane sums its
 // sphere's row, then the clump's first lane sums its spheres in ascending id by
 // shuffles, adds gravity and integrates the clump.
@@ -1208,21 +1219,25 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     const int64_t w = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
     // a wave past the schedule has no sphere, but still joins the workgroup's flag reduction
     const bool live = w < S.n_waves;
-    const int32_t c0 = live ? S.wave_clump0[2 * w] : 0, c1 = live ? S.wave_clump0[2 * w + 1] : 0;
-    const int64_t S0 = S.sbeg[c0], S1 = live ? S.sbeg[c1] : S0;
+    const int64_t S0 = live ? S.wave_s[2 * w] : 0, S1 = live ? S.wave_s[2 * w + 1] : 0;
     const int64_t s = S0 + lane;
     const bool active = s < S1;
     const int cur = S.ctl->buf;
     const bool rec = S.ctl->record != 0;
-    double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-    int64_t c = 0, cb = 0;
-    int cnt = 0;
+    // everything that depends on the sphere alone is loaded up front, together
+    uint32_t info = 0, ts = 0, ub = 0, nu = 0, lb = 0, nl = 0;
+    int64_t c = 0;
     if (active) {
         c = S.owner[s];
-        cb = S.sbeg[c];
-        cnt = (int)(S.sbeg[c + 1] - cb);
-        sphere_sum<FP32>(S, (uint32_t)s, cur, Fs, Ts);
+        info = S.sinfo[s];
+        ts = S.sts[s];
+        ub = S.up_beg[s]; nu = S.up_cnt[s];
+        lb = pick(S.lo_beg, cur)[s]; nl = pick(S.lo_cnt, cur)[s];
     }
+    const int64_t cb = s - (int64_t)(info & 0xffu);  // the clump's first sphere
+    const int cnt = (int)(info >> 8);                 // and its sphere count
+    double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
+    if (active) sphere_sum<FP32>(S, ub, nu, lb, nl, Fs, Ts);
     const bool leader = active && s == cb;
     int mx = leader ? cnt : 0;  // longest clump of the wave: the number of shuffle rounds
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
@@ -1250,6 +1265,8 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     // The next step's poses from the state just integrated, which the clump's
     // spheres (adjacent lanes) take from their leader lane: this saves the
     // pose kernel's second pass over the clump state.
+    PoseIn pin{};
+    if (active) pin = pose_in(S, s, ts);
     const int ldr = active ? (int)(cb - S0) : lane;
     for (int i = 0; i < 13; i++) nx[i] = __shfl(nx[i], ldr, 64);
     PoseOut r{false, 0.0f};
@@ -1262,7 +1279,7 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
             S.kin[3 * c + 1] = make_double4(nx[7], nx[8], nx[9], 0.0);
             S.kin[3 * c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
         }
-        r = sphere_pose(S, s, S.tmpl_sbeg[S.clump_tmpl[c]] + (uint32_t)(s - cb), A, nx, nx + 7, Wv);
+        r = sphere_pose(S, s, pin, A, nx, nx + 7, Wv);
     }
     // workgroup partials of the acceleration and speed maxima and the guard,
     // reduced by k_step_end
@@ -1305,7 +1322,7 @@ __global__ void __launch_bounds__(256) k_pose_big(DevScene S) {
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         const int64_t k = base + threadIdx.x;
         PoseOut r{false, 0.0f};
-        if (k < n) r = sphere_pose(S, s0 + k, tb + (uint32_t)k, A, X, V, Wv);
+        if (k < n) r = sphere_pose(S, s0 + k, pose_in(S, s0 + k, tb + (uint32_t)k), A, X, V, Wv);
         pose_flags(&S.ctl->guard_next, &S.ctl->vmax_next, r);
     }
 }
@@ -1320,7 +1337,7 @@ __global__ void __launch_bounds__(256) k_reduce_big_spheres(DevScene S) {
     const int cur = S.ctl->buf;
     for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += (int64_t)gridDim.x * blockDim.x) {
         double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-        sphere_sum<FP32>(S, (uint32_t)s, cur, Fs, Ts);
+        sphere_sum<FP32>(S, S.up_beg[s], S.up_cnt[s], pick(S.lo_beg, cur)[s], pick(S.lo_cnt, cur)[s], Fs, Ts);
         for (int i = 0; i < 3; i++) { S.sF[3 * s + i] = Fs[i]; S.sT[3 * s + i] = Ts[i]; }
     }
 }
