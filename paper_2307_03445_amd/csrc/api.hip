@@ -239,6 +239,7 @@ static int build_grids(cdem_scene *sc) {
         g.inv = 1.0 / bb;
         g.b = bb;
         g.rm_max = sc->rmax + std::max(0.0, sc->det.margin_cap);
+        g.r_max = sc->rmax;
         // FP32 prefilter slack: positions relative to the origin are rounded to
         // float (half an ulp of the largest coordinate each), differences of
         // two of them and the float distance add a few more ulps; 32 ulps of
@@ -519,7 +520,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.n_waves = (int64_t)wsched.size() / 2;
     S.n_rblocks = (S.n_waves + 3) / 4;            // workgroups of the reduction (four waves each)
     S.n_ablocks = (ns + 255) / 256;               // workgroups of the audit
-    S.part_r = (uint32_t *)dev_alloc(sc, 12 * std::max<int64_t>(S.n_rblocks, 1));
+    S.part_r = (uint32_t *)dev_alloc(sc, 12 * (S.n_rblocks + 256));  // + the folded partials
     S.part_a = (unsigned long long *)dev_alloc(sc, 16 * std::max<int64_t>(S.n_ablocks, 1));
     if (!S.part_r || !S.part_a) return bail(fail(sc, CDEM_E_OOM, "partials"));
     S.stride_cap = 16384;

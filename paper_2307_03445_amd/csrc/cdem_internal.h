@@ -35,6 +35,7 @@ struct Grid {
     float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
     double b;                // bin size
     double rm_max;           // largest radius + largest margin of any sphere (the partner side of a reach)
+    double r_max;            // largest radius (the partner side of the audit's reach)
     int32_t rnx, rny, rnz, rpad;  // envelope regions: blocks of kRegionBins^3 bins
     int64_t reg0;            // first global region id of the scene
 };
@@ -139,7 +140,7 @@ struct DevScene {
     uint32_t *ut, *us, *um;           // [cap] upper entries: partner (lower id), own sphere, linked pair
     // per-workgroup partial results, reduced by the next single-workgroup kernel
     // (device-wide same-address atomics serialise; these do not)
-    uint32_t *part_r;                 // [n_rblocks][3] reduction: max acceleration, max speed, guard trip
+    uint32_t *part_r;                 // [n_rblocks + 256][3] reduction: max acceleration, max speed, guard trip
     int64_t n_rblocks;
     unsigned long long *part_a;       // [n_ablocks][2] audit: true contacts, missed
     int64_t n_ablocks;

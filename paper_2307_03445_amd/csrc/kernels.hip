@@ -408,8 +408,11 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_id[slot] = (uint32_t)s;
     S.sorted_owner[slot] = S.owner[s];
     S.sorted_pos[slot] = p;
-    if (which) return;
     const Grid &g = S.grids[S.sscene[s]];
+    if (which) {  // the audit's binning: prefilter records without margin
+        S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w);
+        return;
+    }
     float m = S.detect_mode == 2 ? S.bin_margin[region_of(g, cell)] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
@@ -1368,16 +1371,43 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     }
 }
 
-// End of step: fold the workgroup partials of the reduction (maxima are of
-// non-negative floats, so their bit patterns order like the values), then the
-// schedule.  One workgroup.
+// The reduction's workgroup partials folded into kFold partials (maxima are
+// of non-negative floats, so their bit patterns order like the values).
+constexpr int kFold = 256;
+__global__ void __launch_bounds__(256) k_fold_partials(DevScene S) {
+    if (S.ctl->overflow) return;
+    uint32_t am = 0, vm = 0, tr = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_rblocks; k += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t *o = S.part_r + 3 * k;
+        am = max(am, o[0]);
+        vm = max(vm, o[1]);
+        tr |= o[2];
+    }
+    __shared__ uint32_t sh[3][4];
+    for (int off = 32; off > 0; off >>= 1) {
+        am = max(am, (uint32_t)__shfl_xor((int)am, off, 64));
+        vm = max(vm, (uint32_t)__shfl_xor((int)vm, off, 64));
+        tr |= (uint32_t)__shfl_xor((int)tr, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = am; sh[1][threadIdx.x >> 6] = vm; sh[2][threadIdx.x >> 6] = tr; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *o = S.part_r + 3 * (S.n_rblocks + blockIdx.x);
+        o[0] = max(max(sh[0][0], sh[0][1]), max(sh[0][2], sh[0][3]));
+        o[1] = max(max(sh[1][0], sh[1][1]), max(sh[1][2], sh[1][3]));
+        o[2] = sh[2][0] | sh[2][1] | sh[2][2] | sh[2][3];
+    }
+}
+
+// End of step: fold the partials of the reduction, then the schedule.  One
+// workgroup.
 __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     Ctl *c = S.ctl;
     const bool ok = !c->overflow;
     uint32_t am = 0, vm = 0, tr = 0;
-    if (ok)
-        for (int64_t k = threadIdx.x; k < S.n_rblocks; k += blockDim.x) {
-            const uint32_t *o = S.part_r + 3 * k;
+    if (ok && S.n_rblocks > 0)
+        for (int64_t k = threadIdx.x; k < kFold; k += blockDim.x) {
+            const uint32_t *o = S.part_r + 3 * (S.n_rblocks + k);
             am = max(am, o[0]);
             vm = max(vm, o[1]);
             tr |= o[2];
@@ -1478,9 +1508,15 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
             return lo < cnt && nb[lo] == t;
         };
         const Grid &g = S.grids[S.sscene[s]];
-        const double reach = P.w + g.rm_max + 1e-9;
+        const double reach = P.w + g.r_max + 1e-9;
+        // the FP32 prefilter of the narrow phase, without margins
+        const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
+        const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
         scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
             for (uint32_t j = jb; j < je; j++) {
+                const float4 Qf = S.sorted_f4[j];
+                const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+                if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
                 if (S.sorted_owner[j] == own) continue;
                 double4 Q = S.sorted_pos[j];
                 double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
@@ -1706,6 +1742,7 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
 }
 
 hipError_t launch_step_end(const DevScene &S, hipStream_t st) {
+    if (S.n_rblocks > 0) TIMED(K_STEP_END, hipLaunchKernelGGL(k_fold_partials, dim3(kFold), dim3(256), 0, st, S));
     TIMED(K_STEP_END, hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1024), 0, st, S));
     return hipGetLastError();
 }
