@@ -483,19 +483,24 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     }
     std::vector<int32_t> big;
     for (int64_t c = 0; c < nc; c++) if (sbeg[c + 1] - sbeg[c] > kBigClump) big.push_back((int32_t)c);
-    std::vector<float> crad(nc);
-    for (int64_t c = 0; c < nc; c++) {
-        uint32_t t = d->clump_template[c];
-        double rb = 0;
+    // per template: the largest |o_s| + R_s (acceleration envelope) and the
+    // largest |o_s| (displacement guard) of its spheres, stored as floats
+    std::vector<double> r_acc(nt), r_ctr(nt);
+    for (int32_t t = 0; t < nt; t++) {
+        double ra = 0, rc = 0;
         for (uint32_t i = d->tmpl_sphere_begin[t]; i < d->tmpl_sphere_begin[t + 1]; i++) {
             const double *o = d->tmpl_offset + 3 * i;
-            rb = std::max(rb, std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]) + d->tmpl_radius[i]);
+            const double r = std::sqrt(o[0] * o[0] + o[1] * o[1] + o[2] * o[2]);
+            ra = std::max(ra, r + d->tmpl_radius[i]);
+            rc = std::max(rc, r);
         }
-        crad[c] = (float)rb;
+        r_acc[t] = (double)(float)ra;
+        r_ctr[t] = (double)std::nextafter((float)rc, 3.0e38f);  // rounded up
     }
     // wave schedule of the force kernel: pack whole clumps into groups of at
     // most 64 spheres, as (first, end) clump pairs; big clumps are skipped
     std::vector<int32_t> wsched;
+    std::vector<uint32_t> wclump;
     for (int64_t c = 0; c < nc;) {
         if (sbeg[c + 1] - sbeg[c] > kBigClump) { c++; continue; }
         int64_t start = c, n = 0;
@@ -507,6 +512,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         }
         wsched.push_back((int32_t)sbeg[start]);
         wsched.push_back((int32_t)sbeg[c]);
+        wclump.push_back((uint32_t)start);
     }
     std::vector<uint32_t> sinfo(ns), sts(ns);
     for (int64_t c = 0; c < nc; c++) {
@@ -528,29 +534,38 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
     // ---- device arrays
     int rc = CDEM_OK;
-    std::vector<double> tmp(nc);
-    double **soa[13] = {&S.px, &S.py, &S.pz, &S.qw, &S.qx, &S.qy, &S.qz, &S.vx, &S.vy, &S.vz, &S.wx, &S.wy, &S.wz};
-    const double *srcs[13] = {d->x, d->x, d->x, d->q, d->q, d->q, d->q, d->v, d->v, d->v, d->w, d->w, d->w};
-    int comp[13] = {0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 0, 1, 2}, stride[13] = {3, 3, 3, 4, 4, 4, 4, 3, 3, 3, 3, 3, 3};
-    for (int a = 0; a < 13; a++) {
-        for (int64_t c = 0; c < nc; c++) tmp[c] = srcs[a][stride[a] * c + comp[a]];
-        *soa[a] = upload(sc, tmp.data(), nc, rc);
-        if (!*soa[a]) return bail(rc);
-        if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
+    {
+        // clump records, (x, M), (v, r_acc), q, (w_body, r_ctr), uploaded in slices
+        const int64_t slice = 1 << 20;
+        std::vector<double4> rec(4 * std::min<int64_t>(std::max<int64_t>(nc, 1), slice));
+        S.cst = (double4 *)dev_alloc(sc, 4 * sizeof(double4) * std::max<int64_t>(nc, 1));
+        if (!S.cst) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+        for (int64_t c0 = 0; c0 < nc; c0 += slice) {
+            const int64_t n = std::min(slice, nc - c0);
+            for (int64_t k = 0; k < n; k++) {
+                const int64_t c = c0 + k;
+                const uint32_t t = d->clump_template[c];
+                const double *x = d->x + 3 * c, *q = d->q + 4 * c, *v = d->v + 3 * c, *w = d->w + 3 * c;
+                rec[4 * k + 0] = make_double4(x[0], x[1], x[2], d->tmpl_mass[t]);
+                rec[4 * k + 1] = make_double4(v[0], v[1], v[2], r_acc[t]);
+                rec[4 * k + 2] = make_double4(q[0], q[1], q[2], q[3]);
+                rec[4 * k + 3] = make_double4(w[0], w[1], w[2], r_ctr[t]);
+            }
+            if (hipMemcpy(S.cst + 4 * c0, rec.data(), 4 * sizeof(double4) * n, hipMemcpyHostToDevice) != hipSuccess)
+                return bail(fail(sc, CDEM_E_HIP, "upload"));
+        }
     }
-    std::vector<double> mass(nc), ix(nc), iy(nc), iz(nc);
-    for (int64_t c = 0; c < nc; c++) {
-        uint32_t t = d->clump_template[c];
-        mass[c] = d->tmpl_mass[t];
-        ix[c] = d->tmpl_inertia[3 * t]; iy[c] = d->tmpl_inertia[3 * t + 1]; iz[c] = d->tmpl_inertia[3 * t + 2];
-    }
+    std::vector<double4> tmi(nt);
+    for (int32_t t = 0; t < nt; t++)
+        tmi[t] = make_double4(d->tmpl_mass[t], d->tmpl_inertia[3 * t], d->tmpl_inertia[3 * t + 1],
+                              d->tmpl_inertia[3 * t + 2]);
 #define UP(field, src, n)                                   \
     do {                                                    \
         auto *p_ = upload(sc, (src), (n), rc);              \
         if (!p_) return bail(rc);                           \
         S.field = p_;                                       \
     } while (0)
-    UP(mass, mass.data(), nc); UP(ix, ix.data(), nc); UP(iy, iy.data(), nc); UP(iz, iz.data(), nc);
+    UP(tmpl_mi, tmi.data(), nt);
     UP(sbeg, sbeg.data(), nc + 1);
     UP(presc, presc.data(), nc);
     UP(presc_param, d->presc_param, 12 * (size_t)d->n_presc);
@@ -565,15 +580,21 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     UP(mat32, mat32.data(), ns);
     UP(bnd, sc->bnd.data(), sc->bnd.size());
     UP(big_list, big.data(), big.size());
-    UP(crad, crad.data(), crad.size());
+    {
+        std::vector<int64_t> bsb(big.size() + 1, 0);
+        for (size_t k = 0; k < big.size(); k++) bsb[k + 1] = bsb[k] + (sbeg[big[k] + 1] - sbeg[big[k]]);
+        UP(big_sbeg, bsb.data(), bsb.size());
+        S.bdet = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(bsb.back(), 1));
+        if (!S.bdet) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    }
     UP(wave_s, wsched.data(), wsched.size());
+    UP(wave_c, wclump.data(), wclump.size());
     UP(sinfo, sinfo.data(), sinfo.size());
     UP(sts, sts.data(), sts.size());
 #undef UP
     S.n_big = (int32_t)big.size();
-    S.kin = (double4 *)dev_alloc(sc, 3 * sizeof(double4) * std::max<int64_t>(nc, 1));
     S.spos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
-    S.sdet = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
+    S.cdet = (double4 *)dev_alloc(sc, 2 * sizeof(double4) * std::max<int64_t>(nc, 1));
     S.smargin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cell_of = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_id = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
@@ -599,7 +620,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     }
     S.up_beg = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.up_cnt = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    if (!S.kin || !S.spos || !S.sdet || !S.smargin || !S.cell_of || !S.sorted_id || !S.sorted_owner ||
+    if (!S.cdet || !S.spos || !S.smargin || !S.cell_of || !S.sorted_id || !S.sorted_owner ||
         !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.lo_beg[0] || !S.lo_beg[1] ||
         !S.lo_cnt[0] || !S.lo_cnt[1] || !S.up_beg || !S.up_cnt)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
@@ -630,7 +651,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (launch_zero(S.cacc, 4 * (size_t)nc, sc->stream) != hipSuccess ||
         launch_zero(S.sspeed, 4 * (size_t)ns, sc->stream) != hipSuccess ||
-        launch_zero(S.sdet, sizeof(double4) * ns, sc->stream) != hipSuccess ||
+        launch_zero(S.cdet, 2 * sizeof(double4) * nc, sc->stream) != hipSuccess ||
         launch_zero(S.smargin, 4 * (size_t)ns, sc->stream) != hipSuccess)
         return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
@@ -670,7 +691,7 @@ static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing)
 
     g_timer = capturing ? nullptr : sc->timer;
     for (int64_t i = 0; i < n; i++) {
-        hipError_t e = launch_pose(S, st);
+        hipError_t e = launch_pose(S, st, false);
         if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, st);
         if (e == hipSuccess) e = launch_detect(S, st);
         if (e == hipSuccess) e = launch_audit_binned(S, st);
@@ -795,7 +816,6 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
     c.det_due = 1;
     c.k_cur = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
-    c.pose_fresh = 0;  // guard and speed settings changed: recompute this step's poses
     return write_ctl(sc, c);
 }
 
@@ -832,29 +852,57 @@ extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
     return CDEM_OK;
 }
 
+// The clump state as row-major host arrays x [nc][3], q [nc][4], v [nc][3],
+// w [nc][3] (any may be null), through a device staging buffer.
+static int state_to_host(cdem_scene *sc, double *x, double *q, double *v, double *w) {
+    const DevScene &S = sc->S;
+    const int64_t nc = S.nc;
+    if (nc == 0) return CDEM_OK;
+    double *stage = (double *)dev_alloc(sc, 13 * 8 * (size_t)nc);
+    if (!stage) return fail(sc, CDEM_E_OOM, "state staging buffer");
+    double *dx = stage, *dq = stage + 3 * nc, *dv = stage + 7 * nc, *dw = stage + 10 * nc;
+    hipError_t e = launch_pack_state(S, dx, dq, dv, dw, 0, sc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    double *dst[4] = {x, q, v, w}, *src[4] = {dx, dq, dv, dw};
+    const int width[4] = {3, 4, 3, 3};
+    for (int a = 0; a < 4 && e == hipSuccess; a++)
+        if (dst[a]) e = hipMemcpy(dst[a], src[a], 8 * width[a] * (size_t)nc, hipMemcpyDeviceToHost);
+    dev_free(sc, stage);
+    if (e != hipSuccess) return fail(sc, CDEM_E_HIP, hipGetErrorString(e));
+    return CDEM_OK;
+}
+
+static int state_from_host(cdem_scene *sc, const double *x, const double *q, const double *v, const double *w) {
+    const DevScene &S = sc->S;
+    const int64_t nc = S.nc;
+    if (nc == 0) return CDEM_OK;
+    double *stage = (double *)dev_alloc(sc, 13 * 8 * (size_t)nc);
+    if (!stage) return fail(sc, CDEM_E_OOM, "state staging buffer");
+    double *dx = stage, *dq = stage + 3 * nc, *dv = stage + 7 * nc, *dw = stage + 10 * nc;
+    const double *src[4] = {x, q, v, w};
+    double *dst[4] = {dx, dq, dv, dw};
+    const int width[4] = {3, 4, 3, 3};
+    hipError_t e = hipSuccess;
+    for (int a = 0; a < 4 && e == hipSuccess; a++)
+        if (src[a]) e = hipMemcpy(dst[a], src[a], 8 * width[a] * (size_t)nc, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = launch_pack_state(S, x ? dx : nullptr, q ? dq : nullptr, v ? dv : nullptr, w ? dw : nullptr, 1, sc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    dev_free(sc, stage);
+    if (e != hipSuccess) return fail(sc, CDEM_E_HIP, hipGetErrorString(e));
+    return CDEM_OK;
+}
+
 extern "C" int cdem_read_state(cdem_scene *sc, const cdem_state_view *v, int where) {
     if (!sc || !v || (where != CDEM_HOST && where != CDEM_DEVICE)) return fail(sc, CDEM_E_INVALID, "bad arguments");
     const DevScene &S = sc->S;
-    int64_t nc = S.nc;
     HIPCHK(hipStreamSynchronize(sc->stream));
     if (where == CDEM_DEVICE) {
         HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 0, sc->stream));
         HIPCHK(hipStreamSynchronize(sc->stream));
         return CDEM_OK;
     }
-    std::vector<double> t(nc);
-    double *dst[4] = {v->x, v->q, v->v, v->w};
-    double *const *srcs[4][4] = {{&S.px, &S.py, &S.pz, nullptr}, {&S.qw, &S.qx, &S.qy, &S.qz},
-                                {&S.vx, &S.vy, &S.vz, nullptr}, {&S.wx, &S.wy, &S.wz, nullptr}};
-    int width[4] = {3, 4, 3, 3};
-    for (int a = 0; a < 4; a++) {
-        if (!dst[a]) continue;
-        for (int k = 0; k < width[a]; k++) {
-            HIPCHK(hipMemcpy(t.data(), *srcs[a][k], nc * 8, hipMemcpyDeviceToHost));
-            for (int64_t c = 0; c < nc; c++) dst[a][width[a] * c + k] = t[c];
-        }
-    }
-    return CDEM_OK;
+    return state_to_host(sc, v->x, v->q, v->v, v->w);
 }
 
 extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int where) {
@@ -871,32 +919,24 @@ extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int wh
                 for (int k = 0; k < 4; k++) qn += v->q[4 * c + k] * v->q[4 * c + k];
                 if (!(std::fabs(qn - 1.0) < 1e-10)) return fail(sc, CDEM_E_INVALID, "quaternions must be unit");
             }
-        std::vector<double> t(nc);
         const double *src[4] = {v->x, v->q, v->v, v->w};
-        double *const *dsts[4][4] = {{&S.px, &S.py, &S.pz, nullptr}, {&S.qw, &S.qx, &S.qy, &S.qz},
-                                    {&S.vx, &S.vy, &S.vz, nullptr}, {&S.wx, &S.wy, &S.wz, nullptr}};
-        int width[4] = {3, 4, 3, 3};
-        for (int a = 0; a < 4; a++) {
-            if (!src[a]) continue;
-            if (!finite_all(src[a], width[a] * (size_t)nc)) return fail(sc, CDEM_E_INVALID, "non-finite state");
-            for (int k = 0; k < width[a]; k++) {
-                for (int64_t c = 0; c < nc; c++) t[c] = src[a][width[a] * c + k];
-                HIPCHK(hipMemcpy(*dsts[a][k], t.data(), nc * 8, hipMemcpyHostToDevice));
-            }
-        }
+        const int width[4] = {3, 4, 3, 3};
+        for (int a = 0; a < 4; a++)
+            if (src[a] && !finite_all(src[a], width[a] * (size_t)nc)) return fail(sc, CDEM_E_INVALID, "non-finite state");
+        int rc = state_from_host(sc, v->x, v->q, v->v, v->w);
+        if (rc) return rc;
     }
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
     c.det_due = 1;
-    c.pose_fresh = 0;
     return write_ctl(sc, c);
 }
 
 extern "C" int cdem_read_sphere_pos(cdem_scene *sc, double *xs) {
     if (!sc || !xs) return fail(sc, CDEM_E_INVALID, "null argument");
     const DevScene &S = sc->S;
-    HIPCHK(launch_pose(S, sc->stream));
+    HIPCHK(launch_pose(S, sc->stream, true));
     std::vector<double4> p(S.ns);
     HIPCHK(hipStreamSynchronize(sc->stream));
     HIPCHK(hipMemcpy(p.data(), S.spos, S.ns * sizeof(double4), hipMemcpyDeviceToHost));
@@ -1003,7 +1043,7 @@ extern "C" int cdem_audit(cdem_scene *sc, cdem_audit_result *r) {
     if (!cnt) return fail(sc, CDEM_E_OOM, "audit counters");
     unsigned long long init[3] = {0, 0, ~0ull};
     HIPCHK(hipMemcpyAsync(cnt, init, sizeof init, hipMemcpyHostToDevice, sc->stream));
-    HIPCHK(launch_pose(S, sc->stream));
+    HIPCHK(launch_pose(S, sc->stream, true));
     HIPCHK(launch_audit_brute(S, cnt, (uint32_t *)(cnt + 2), sc->stream));
     HIPCHK(hipStreamSynchronize(sc->stream));
     unsigned long long out[3];
@@ -1098,7 +1138,7 @@ extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *fe
     auto restore = [&](int rc) { S.store_speed = ss; S.store_acc = sa; sc->collecting = false; return rc; };
     int rc = cdem_step(sc, 1, nullptr);  // one step so that every clump has an acceleration envelope
     if (rc) return restore(rc);
-    hipError_t e = launch_pose(S, sc->stream);
+    hipError_t e = launch_pose(S, sc->stream, true);
     if (e == hipSuccess) e = launch_collect_begin(S, sc->stream);
     if (e != hipSuccess) return restore(fail(sc, CDEM_E_HIP, hipGetErrorString(e)));
     int64_t nb = S.n_regions;
@@ -1207,19 +1247,13 @@ struct SaveHeader {
     double bin_factor;
     Ctl ctl;
 };
-constexpr char kSaveMagic[8] = {'C', 'D', 'E', 'M', 'S', 'A', 'V', '1'};
+constexpr char kSaveMagic[8] = {'C', 'D', 'E', 'M', 'S', 'A', 'V', '2'};
 
 size_t save_size(const DevScene &S, int64_t entries, bool mlp) {
     return sizeof(SaveHeader) + 13 * 8 * (size_t)S.nc + 8 * (size_t)S.ns + 4 * (size_t)entries +
            24 * (size_t)entries + (mlp ? 4 * (size_t)cdem_mlp_param_count() : 0);
 }
 }  // namespace
-
-// Device arrays of the clump state in checkpoint order: x, q, v, w (13 columns).
-static void state_arrays(const DevScene &S, double *out[13]) {
-    double *a[13] = {S.px, S.py, S.pz, S.qw, S.qx, S.qy, S.qz, S.vx, S.vy, S.vz, S.wx, S.wy, S.wz};
-    for (int i = 0; i < 13; i++) out[i] = a[i];
-}
 
 extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     if (!sc || !len || (cap > 0 && !buf)) return fail(sc, CDEM_E_INVALID, "bad arguments");
@@ -1248,11 +1282,11 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     char *o = (char *)buf;
     memcpy(o, &hd, sizeof hd);
     o += sizeof hd;
-    double *arr[13];
-    state_arrays(S, arr);
-    for (int i = 0; i < 13; i++) {
-        if (S.nc) HIPCHK(hipMemcpy(o, arr[i], 8 * S.nc, hipMemcpyDeviceToHost));
-        o += 8 * S.nc;
+    {  // the clump state: x [nc][3], q [nc][4], v [nc][3], w [nc][3]
+        double *st = (double *)o;
+        const int64_t nc = S.nc;
+        if ((rc = state_to_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc)) != CDEM_OK) return rc;
+        o += 13 * 8 * (size_t)nc;
     }
     const int cur = c.buf;
     if (S.ns) {
@@ -1299,10 +1333,11 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     Ctl c;
     if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
     const int cur = c.buf;
-    double *arr[13];
-    state_arrays(S, arr);
-    for (int i = 0; i < 13; i++)
-        if (S.nc) HIPCHK(hipMemcpy(arr[i], p + 8 * S.nc * (size_t)i, 8 * S.nc, hipMemcpyHostToDevice));
+    {
+        const double *st = (const double *)p;
+        const int64_t nc = S.nc;
+        if ((rc = state_from_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc)) != CDEM_OK) return rc;
+    }
     if (S.ns) {
         HIPCHK(hipMemcpy(S.lo_beg[cur], rb, 4 * S.ns, hipMemcpyHostToDevice));
         HIPCHK(hipMemcpy(S.lo_cnt[cur], rn, 4 * S.ns, hipMemcpyHostToDevice));
@@ -1320,7 +1355,5 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;
     n.guard = 0;
     n.guard_next = 0;
-    n.vmax_next = 0;
-    n.pose_fresh = 0;
     return write_ctl(sc, n);
 }

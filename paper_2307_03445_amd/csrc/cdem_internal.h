@@ -53,7 +53,7 @@ struct Ctl {
     int32_t k_cur;           // current detection interval
     int32_t overflow;        // active-set storage overflowed: later kernels of the step skip
     int32_t row_overflow;    // more spheres exceeded kMaxRow candidates than the overflow list holds
-    int32_t guard;           // a sphere moved past its margin this step
+    int32_t guard;           // a clump may have moved past its margin: re-detect
     int32_t record;          // store per-contact data this step
     int32_t nonfinite;       // a clump state became NaN/Inf
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
@@ -62,16 +62,14 @@ struct Ctl {
     int64_t n_pairs_cur;     // pairs of the active set in use
     int32_t asym;            // an entry had no mirror (never expected): the step is abandoned
     int32_t collecting;      // training-data capture in progress: accumulate horizon labels
-    uint32_t vmax_bits;      // max sphere speed of this step (float bits, >= 0)
+    uint32_t vmax_bits;      // max sphere speed of the current state (float bits, >= 0), set by k_pose
     uint32_t amax_bits;      // max sphere acceleration estimate of the step in progress
     uint32_t amax_last;      // ... of the last completed step
     float margin_cur;        // margin of every sphere at the last detection (fixed rule)
     int64_t audit_true;      // true contacts seen by the last audit
     int64_t audit_last_missed;
     int64_t n_bp;            // boundary pairs written by the detection in progress
-    int32_t pose_fresh;      // sphere poses, kinematics, guard and speeds already match the state
-    int32_t guard_next;      // guard of the next step, found while computing its poses
-    uint32_t vmax_next;      // max sphere speed of the next step (float bits)
+    int32_t guard_next;      // guard trips of the clumps integrated outside the wave reduction
     int32_t pad2;
 };
 
@@ -94,10 +92,13 @@ struct DevScene {
     double h;
     int64_t n_cells;
     int64_t cap;                     // pairs (and upper-segment entries) per active-set buffer
-    // clump state (SoA)
-    double *px, *py, *pz, *qw, *qx, *qy, *qz, *vx, *vy, *vz, *wx, *wy, *wz;
+    // Clump state: one 128-byte record per clump, four double4:
+    // (x, M), (v, r_acc), (q), (w_body, r_ctr); M the mass, r_acc the largest
+    // |o_s| + R_s and r_ctr the largest |o_s| of its spheres (static words
+    // kept with the state so that one aligned record serves every reader).
+    double4 *cst;                    // [nc][4]
     // clump static
-    const double *mass, *ix, *iy, *iz;
+    const double4 *tmpl_mi;          // [n_templates]: mass, principal moments of inertia
     const int64_t *sbeg;             // [nc+1]
     const int32_t *presc;            // [nc] -1 or index
     const double *presc_param;       // [n_presc][12]
@@ -105,16 +106,14 @@ struct DevScene {
     const uint32_t *tmpl_sbeg;
     const double *tmpl_ofs;          // [n_ts][3]
     const double *tmpl_rad;
-    // per clump, written by the pose kernel
-    double4 *kin;                    // [nc][3]: (x, M), (v, 0), (w_world, 0)
     // sphere static
     const uint32_t *owner, *sscene;
     const double4 *mat64;            // (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, beta
     const float4 *mat32;
     // sphere dynamic
-    double4 *spos;                   // (x, y, z, R)
-    double4 *sdet;                   // position at the last detection
+    double4 *spos;                   // (x, y, z, R), written by k_pose when a step needs positions
     float *smargin;                  // margin assigned at the last detection
+    double4 *cdet;                   // [nc][2] clump pose at the last detection: (x, 0), q
     double *sF, *sT;                 // [ns][3] per-sphere sums (big clumps only)
     // binning
     const Grid *grids;
@@ -155,12 +154,13 @@ struct DevScene {
     Ctl *ctl;
     // big clumps
     const int32_t *big_list;         // clump ids
+    const int64_t *big_sbeg;         // [n_big+1] first sphere of each big clump in bdet
+    double4 *bdet;                   // sphere poses of the big clumps at the last detection
     int32_t n_big;
     int32_t guard_on;                // the displacement guard is checked (deferred detection)
-    const float *crad;               // [nc] bounding radius of each clump about its CoM
     Plan plan;
     // learned envelopes and training-data collection
-    int32_t store_speed;             // pose writes each sphere's speed to sspeed
+    int32_t store_speed;             // k_pose writes each sphere's speed to sspeed
     int32_t store_acc;               // integration writes each clump's acceleration envelope to cacc
     float *sspeed;                   // [ns]
     float *cacc;                     // [nc]
@@ -174,6 +174,7 @@ struct DevScene {
     // wave schedule of the reduction: wave w covers spheres wave_s[2w] ..
     // wave_s[2w+1]-1 (whole clumps, at most 64 spheres; big clumps excluded)
     const int32_t *wave_s;
+    const uint32_t *wave_c;          // [n_waves] first clump of each wave
     const uint32_t *sinfo;           // [ns] index of the sphere in its clump | clump size << 8 (clumps of <= 64)
     const uint32_t *sts;             // [ns] template sphere of each sphere
     int64_t n_waves;
@@ -191,13 +192,16 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_POSE_BIG, K_COUNT };
+                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 
 // Launchers (kernels.hip).  Every launcher enqueues on `st` and returns the
 // hipError_t of the launch.
-hipError_t launch_pose(const DevScene &S, hipStream_t st);
+// Sphere poses (spos) and, where the settings ask, speeds.  In a step
+// (force = false) the kernel works only when the step needs positions (a
+// detection, an audit, training-data capture); readouts pass force = true.
+hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force);
 hipError_t launch_detect(const DevScene &S, hipStream_t st);
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st);
 hipError_t launch_step_end(const DevScene &S, hipStream_t st);

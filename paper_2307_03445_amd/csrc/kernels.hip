@@ -50,54 +50,31 @@ __device__ __forceinline__ void quat_mat(double w, double x, double y, double z,
 }
 
 // ---------------------------------------------------------------- pose (per sphere)
-// Pose of sphere s (template sphere ts) of a clump with rotation A, CoM X,
-// velocity V and world angular velocity Wv: centre and radius to spos; with
-// the guard on, whether it has moved past its margin since the last
-// detection; with the guard or the speed store on, the speed of its centre.
-struct PoseOut { bool trip; float speed; };
-// What the pose of one sphere reads: its template offset and radius and, for
-// the guard, where it stood at the last detection and its margin.
-struct PoseIn { double o0, o1, o2, rad; double4 det; float margin; };
-__device__ __forceinline__ PoseIn pose_in(const DevScene &S, int64_t s, uint32_t ts) {
-    PoseIn p;
-    p.o0 = S.tmpl_ofs[3 * ts]; p.o1 = S.tmpl_ofs[3 * ts + 1]; p.o2 = S.tmpl_ofs[3 * ts + 2];
-    p.rad = S.tmpl_rad[ts];
-    if (S.guard_on) { p.det = S.sdet[s]; p.margin = S.smargin[s]; }
-    else { p.det = make_double4(0.0, 0.0, 0.0, 0.0); p.margin = 0.0f; }
-    return p;
-}
-
-__device__ __forceinline__ PoseOut sphere_pose(const DevScene &S, int64_t s, const PoseIn &in, const double *A,
-                                               const double *X, const double *V, const double *Wv) {
-    const double o0 = in.o0, o1 = in.o1, o2 = in.o2;
-    const double xs = X[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
-    const double ys = X[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
-    const double zs = X[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
-    S.spos[s] = make_double4(xs, ys, zs, in.rad);
-    PoseOut r{false, 0.0f};
-    if (S.guard_on) {
-        const double4 d = in.det;
-        const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
-        const double d2 = dx * dx + dy * dy + dz * dz;
-        const double lim = 0.999 * (double)in.margin;
-        r.trip = !(d2 < lim * lim);
-    }
-    if (S.guard_on || S.store_speed) {
-        // speed of the centre: |v_c + w x r|
-        const double r0 = xs - X[0], r1 = ys - X[1], r2 = zs - X[2];
-        const double u0 = V[0] + (Wv[1] * r2 - Wv[2] * r1), u1 = V[1] + (Wv[2] * r0 - Wv[0] * r2),
-                     u2 = V[2] + (Wv[0] * r1 - Wv[1] * r0);
-        r.speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
-        if (S.store_speed) S.sspeed[s] = r.speed;
-    }
-    return r;
-}
-
-// World angular velocity A w_body.
-__device__ __forceinline__ void world_omega(const double *A, double wb0, double wb1, double wb2, double *Wv) {
-    Wv[0] = A[0] * wb0 + A[1] * wb1 + A[2] * wb2;
-    Wv[1] = A[3] * wb0 + A[4] * wb1 + A[5] * wb2;
-    Wv[2] = A[6] * wb0 + A[7] * wb1 + A[8] * wb2;
+// Kinematics of sphere s from its clump's state record: centre x_s = x_c +
+// A(q) o_s and radius, and the clump's CoM, mass, velocity and world angular
+// velocity A(q) w_body.  Every kernel that needs a sphere's pose computes it
+// this one way, so the positions of a detection, of the force kernel and of
+// a readout are the same numbers.
+struct SphereKin { double p[3], R, xc[3], M, v[3], W[3]; };
+__device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
+    const uint32_t c = S.owner[s], ts = S.sts[s];
+    const double4 *r = S.cst + 4 * (int64_t)c;
+    const double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
+    const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+    SphereKin k;
+    k.R = S.tmpl_rad[ts];
+    double A[9];
+    quat_mat(k2.x, k2.y, k2.z, k2.w, A);
+    k.p[0] = k0.x + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+    k.p[1] = k0.y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+    k.p[2] = k0.z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+    k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
+    k.M = k0.w;
+    k.v[0] = k1.x; k.v[1] = k1.y; k.v[2] = k1.z;
+    k.W[0] = A[0] * k3.x + A[1] * k3.y + A[2] * k3.z;
+    k.W[1] = A[3] * k3.x + A[4] * k3.y + A[5] * k3.z;
+    k.W[2] = A[6] * k3.x + A[7] * k3.y + A[8] * k3.z;
+    return k;
 }
 
 // Raise a device-wide float maximum kept as bits in the control block.  The
@@ -110,49 +87,40 @@ __device__ __forceinline__ void raise_max(uint32_t *slot, float v) {
     if (v > __uint_as_float(cur)) atomicMax(slot, __float_as_uint(v));
 }
 
-// Workgroup-aggregated guard flag and speed maximum into the control block
-// (every thread of the workgroup calls it).
-__device__ __forceinline__ void pose_flags(int32_t *guard, uint32_t *vmax, PoseOut r) {
-    __shared__ float wmax[16];
-    __shared__ int wtrip[16];
-    const unsigned long long trips = __ballot(r.trip);
-    float v = r.speed;
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    const int wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    if ((threadIdx.x & 63) == 0) { wmax[wid] = v; wtrip[wid] = trips != 0; }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float m = 0.0f;
-        int t = 0;
-        for (int k = 0; k < nw; k++) { m = fmaxf(m, wmax[k]); t |= wtrip[k]; }
-        if (t) *guard = 1;
-        raise_max(vmax, m);
-    }
+// Positions need refreshing at the start of a step that detects, audits or
+// captures training data; the other steps never read them.
+__device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
+__device__ __forceinline__ bool audit_due(const DevScene &S) {
+    return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
 }
 
-// Poses of the current state, one lane per sphere.  Only needed when the
-// host changed the state or the scene's settings: otherwise the integration
-// of the previous step already left them (ctl->pose_fresh).
-__global__ void __launch_bounds__(256) k_pose(DevScene S) {
-    if (S.ctl->pose_fresh) return;
+// Poses of the current state, one lane per sphere, and the speed of each
+// sphere's centre |v_c + w x (x_s - x_c)| where the settings use it (learned
+// envelopes and training data per sphere, the fixed rule's maximum).
+__global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
+    const Ctl *ctl = S.ctl;
+    if (!force && !(due(ctl) || audit_due(S) || ctl->collecting)) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    PoseOut r{false, 0.0f};
+    const bool speeds = S.store_speed || ctl->collecting || S.detect_mode == 1;
+    float speed = 0.0f;
     if (s < S.ns) {
-        const uint32_t c = S.owner[s];
-        double A[9];
-        quat_mat(S.qw[c], S.qx[c], S.qy[c], S.qz[c], A);
-        const double X[3] = {S.px[c], S.py[c], S.pz[c]}, V[3] = {S.vx[c], S.vy[c], S.vz[c]};
-        double Wv[3];
-        world_omega(A, S.wx[c], S.wy[c], S.wz[c], Wv);
-        const int64_t s0 = S.sbeg[c];
-        if (s == s0) {
-            S.kin[3 * (int64_t)c + 0] = make_double4(X[0], X[1], X[2], S.mass[c]);
-            S.kin[3 * (int64_t)c + 1] = make_double4(V[0], V[1], V[2], 0.0);
-            S.kin[3 * (int64_t)c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
+        const SphereKin k = sphere_kin(S, (uint32_t)s);
+        S.spos[s] = make_double4(k.p[0], k.p[1], k.p[2], k.R);
+        if (speeds) {
+            const double r0 = k.p[0] - k.xc[0], r1 = k.p[1] - k.xc[1], r2 = k.p[2] - k.xc[2];
+            const double u0 = k.v[0] + (k.W[1] * r2 - k.W[2] * r1), u1 = k.v[1] + (k.W[2] * r0 - k.W[0] * r2),
+                         u2 = k.v[2] + (k.W[0] * r1 - k.W[1] * r0);
+            speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+            if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
         }
-        r = sphere_pose(S, s, pose_in(S, s, S.sts[s]), A, X, V, Wv);
     }
-    pose_flags(&S.ctl->guard, &S.ctl->vmax_bits, r);
+    if (S.detect_mode != 1) return;
+    // the fixed rule's global speed maximum: one filtered atomic per workgroup
+    __shared__ float wmax[4];
+    for (int off = 32; off > 0; off >>= 1) speed = fmaxf(speed, __shfl_xor(speed, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = speed;
+    __syncthreads();
+    if (threadIdx.x == 0) raise_max(&S.ctl->vmax_bits, fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
 }
 
 // ---------------------------------------------------------------- boundaries
@@ -292,10 +260,6 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return x * per + min(x, rem) + k;
 }
 
-__device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
-__device__ __forceinline__ bool audit_due(const DevScene &S) {
-    return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
-}
 // which = 0: the detection chain; which = 1: the periodic audit's own binning
 // which = 2: training-data capture (always runs when launched)
 __device__ __forceinline__ bool chain_active(const DevScene &S, int which) {
@@ -396,8 +360,8 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_final(DevScene S, const uin
 }
 
 // Scatter spheres into their bins.  For a detection, every sphere also takes
-// this detection's margin (fixed rule: one value; learned: per sphere) and
-// remembers where it stood, for the displacement guard.
+// this detection's margin (fixed rule: one value; learned: per sphere), from
+// which the integration sets its clump's displacement guard.
 __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *margin_src, int which) {
     if (!chain_active(S, which)) return;
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -417,7 +381,6 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
     S.smargin[s] = m;
-    S.sdet[s] = p;
 }
 
 // Fixed rule of the enlarged contact geometry: the margin covers k steps of
@@ -947,10 +910,10 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     double *h = hist + 3 * e;
     if (t < (uint32_t)S.ns) {
         const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
-        double4 Pa = S.spos[a], Pb = S.spos[b];
-        double dx = Pb.x - Pa.x, dy = Pb.y - Pa.y, dz = Pb.z - Pa.z;
+        const SphereKin ka = sphere_kin(S, a), kb = sphere_kin(S, b);
+        double dx = kb.p[0] - ka.p[0], dy = kb.p[1] - ka.p[1], dz = kb.p[2] - ka.p[2];
         double d2 = dx * dx + dy * dy + dz * dz;
-        double Sr = Pa.w + Pb.w;
+        double Sr = ka.R + kb.R;
         if (!(d2 < Sr * Sr)) {  // a false positive of the enlarged geometry: no force, no history
             cS[e] = Contrib<FP32>::make(zero3, 0.0);
             if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
@@ -965,31 +928,27 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
             if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
             return 0;
         }
-        const uint32_t ca = S.owner[a], cb = S.owner[b];
-        const double4 *ka = S.kin + 3 * (int64_t)ca, *kbp = S.kin + 3 * (int64_t)cb;
-        double4 xa = ka[0], va = ka[1], wa = ka[2];
-        double4 xb = kbp[0], vb = kbp[1], wb = kbp[2];
         double n[3] = {dx / d, dy / d, dz / d};
-        double lever = Pa.w - 0.5 * delta;
-        double p[3] = {Pa.x + lever * n[0], Pa.y + lever * n[1], Pa.z + lever * n[2]};
-        double ra[3] = {p[0] - xa.x, p[1] - xa.y, p[2] - xa.z};
-        double rb[3] = {p[0] - xb.x, p[1] - xb.y, p[2] - xb.z};
+        double lever = ka.R - 0.5 * delta;
+        double p[3] = {ka.p[0] + lever * n[0], ka.p[1] + lever * n[1], ka.p[2] + lever * n[2]};
+        double ra[3] = {p[0] - ka.xc[0], p[1] - ka.xc[1], p[2] - ka.xc[2]};
+        double rb[3] = {p[0] - kb.xc[0], p[1] - kb.xc[1], p[2] - kb.xc[2]};
         // contact kinematics in FP64 (relative velocities of similar speeds cancel)
-        double wva[3] = {wa.x, wa.y, wa.z}, wvb[3] = {wb.x, wb.y, wb.z}, ca3[3], cb3[3];
-        cross3(wva, ra, ca3);
-        cross3(wvb, rb, cb3);
-        double vrel[3] = {(vb.x + cb3[0]) - (va.x + ca3[0]), (vb.y + cb3[1]) - (va.y + ca3[1]),
-                          (vb.z + cb3[2]) - (va.z + ca3[2])};
+        double ca3[3], cb3[3];
+        cross3(ka.W, ra, ca3);
+        cross3(kb.W, rb, cb3);
+        double vrel[3] = {(kb.v[0] + cb3[0]) - (ka.v[0] + ca3[0]), (kb.v[1] + cb3[1]) - (ka.v[1] + ca3[1]),
+                          (kb.v[2] + cb3[2]) - (ka.v[2] + ca3[2])};
         double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
         if (!FP32) {
-            double Rbar = (Pa.w * Pb.w) / (Pa.w + Pb.w);
-            double mbar = (xa.w * xb.w) / (xa.w + xb.w);
+            double Rbar = (ka.R * kb.R) / (ka.R + kb.R);
+            double mbar = (ka.M * kb.M) / (ka.M + kb.M);
             double4 ma = S.mat64[a], mb = S.mat64[b];
             law64(n, delta, vrel, Rbar, mbar, 1.0 / (ma.x + mb.x), 1.0 / (ma.y + mb.y), fmin(ma.z, mb.z),
                   fmin(ma.w, mb.w), S.h, u_old, F, u_new);
         } else {
             float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
-            float Ra = (float)Pa.w, Rb = (float)Pb.w, Ma = (float)xa.w, Mb = (float)xb.w;
+            float Ra = (float)ka.R, Rb = (float)kb.R, Ma = (float)ka.M, Mb = (float)kb.M;
             float4 ma = S.mat32[a], mb = S.mat32[b];
             float Ff[3];
             law32(n, delta, vrf, (Ra * Rb) / (Ra + Rb), (Ma * Mb) / (Ma + Mb), 1.0f / (ma.x + mb.x),
@@ -1011,39 +970,37 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     }
     // boundary pair: the boundary is body a, sphere s is body b
     const Bnd &B = S.bnd[t - (uint32_t)S.ns];
-    double4 Ps = S.spos[s];
+    const SphereKin ks = sphere_kin(S, s);
     double phi, n[3];
-    bool contact = bnd_distance(B, tnow, Ps.x, Ps.y, Ps.z, phi, n) && phi < Ps.w;
+    bool contact = bnd_distance(B, tnow, ks.p[0], ks.p[1], ks.p[2], phi, n) && phi < ks.R;
     if (!contact) {
         cS[e] = Contrib<FP32>::make(zero3, 0.0);
         if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
         if (rec) S.rec_state[e] = 0;
         return 0;
     }
-    double R = Ps.w;
+    double R = ks.R;
     double delta = R - phi;
     double lever = R - 0.5 * delta;
-    double p[3] = {Ps.x - lever * n[0], Ps.y - lever * n[1], Ps.z - lever * n[2]};
-    const double4 *kc = S.kin + 3 * (int64_t)S.owner[s];
-    double4 xc = kc[0], vc = kc[1], wc = kc[2];
+    double p[3] = {ks.p[0] - lever * n[0], ks.p[1] - lever * n[1], ks.p[2] - lever * n[2]};
     double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
     double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
-    double rb[3] = {p[0] - xc.x, p[1] - xc.y, p[2] - xc.z};
-    double pw[3], cb3[3], wv3[3] = {wc.x, wc.y, wc.z};
+    double rb[3] = {p[0] - ks.xc[0], p[1] - ks.xc[1], p[2] - ks.xc[2]};
+    double pw[3], cb3[3];
     cross3(B.omg, ra, pw);
-    cross3(wv3, rb, cb3);
+    cross3(ks.W, rb, cb3);
     double wv[3] = {B.vel[0] + pw[0], B.vel[1] + pw[1], B.vel[2] + pw[2]};
-    double vrel[3] = {(vc.x + cb3[0]) - wv[0], (vc.y + cb3[1]) - wv[1], (vc.z + cb3[2]) - wv[2]};
+    double vrel[3] = {(ks.v[0] + cb3[0]) - wv[0], (ks.v[1] + cb3[1]) - wv[1], (ks.v[2] + cb3[2]) - wv[2]};
     double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
     if (!FP32) {
         double4 ms = S.mat64[s];
-        law64(n, delta, vrel, R, xc.w, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z), fmin(B.beta, ms.w),
+        law64(n, delta, vrel, R, ks.M, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z), fmin(B.beta, ms.w),
               S.h, u_old, F, u_new);
     } else {
         float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
         float4 ms = S.mat32[s];
         float Ff[3];
-        law32(n, delta, vrf, (float)R, (float)xc.w, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y), fminf(B.muf, ms.z),
+        law32(n, delta, vrf, (float)R, (float)ks.M, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y), fminf(B.muf, ms.z),
               fminf(B.betaf, ms.w), S.h, u_old, Ff, u_new);
         F[0] = Ff[0]; F[1] = Ff[1]; F[2] = Ff[2];
     }
@@ -1144,22 +1101,31 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
     }
 }
 
-// Symplectic Euler of one clump from its total force and torque (world frame).
-// Returns an acceleration envelope of its spheres, |a_c| + |dw/dt| r_b + |w|^2 r_b.
-__device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, const double *F, const double *T,
-                                                 double *next = nullptr) {
-    double h = S.h;
-    double M = S.mass[c];
-    double qw = S.qw[c], qx = S.qx[c], qy = S.qy[c], qz = S.qz[c];
+// Symplectic Euler of clump c from the sum F, T of its contact forces and
+// torques (world frame), plus gravity; the record is read and rewritten in
+// place.  Returns an acceleration envelope of its spheres, |a_c| + |dw/dt|
+// r_acc + |w|^2 r_acc.  `pose` (if given) takes the new CoM and orientation
+// (x', q') and the old ones (x, q).
+__device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, double *F, const double *T,
+                                                 double *pose = nullptr) {
+    const double h = S.h;
+    double4 *rec = S.cst + 4 * c;
+    const double4 k0 = rec[0], k1 = rec[1], k2 = rec[2], k3 = rec[3];
+    const int32_t pi = S.presc[c];
+    const Grid &g = S.grids[S.clump_scene[c]];
+    const double M = k0.w;
+    F[0] = F[0] + M * g.gx; F[1] = F[1] + M * g.gy; F[2] = F[2] + M * g.gz;
+    if (S.ctl->record)
+        for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = F[i]; S.rec_cT[3 * c + i] = T[i]; }
     double A[9];
-    quat_mat(qw, qx, qy, qz, A);
-    double v[3] = {S.vx[c], S.vy[c], S.vz[c]}, x[3] = {S.px[c], S.py[c], S.pz[c]};
-    double w[3] = {S.wx[c], S.wy[c], S.wz[c]};
-    int32_t pi = S.presc[c];
+    quat_mat(k2.x, k2.y, k2.z, k2.w, A);
+    double v[3] = {k1.x, k1.y, k1.z}, x[3] = {k0.x, k0.y, k0.z};
+    double w[3] = {k3.x, k3.y, k3.z};
     if (pi < 0) {
+        const double4 mi = S.tmpl_mi[S.clump_tmpl[c]];
         for (int i = 0; i < 3; i++) v[i] = v[i] + h * (F[i] / M);
         for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
-        double I[3] = {S.ix[c], S.iy[c], S.iz[c]};
+        double I[3] = {mi.y, mi.z, mi.w};
         double tb[3];
         for (int i = 0; i < 3; i++) tb[i] = A[i] * T[0] + A[3 + i] * T[1] + A[6 + i] * T[2];
         double L[3] = {I[0] * w[0], I[1] * w[1], I[2] * w[2]};
@@ -1177,13 +1143,13 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     }
     double acc_env = 0.0;
     {
-        double dv0 = v[0] - S.vx[c], dv1 = v[1] - S.vy[c], dv2 = v[2] - S.vz[c];
-        double dw0 = w[0] - S.wx[c], dw1 = w[1] - S.wy[c], dw2 = w[2] - S.wz[c];
-        double rb = (double)S.crad[c];
+        double dv0 = v[0] - k1.x, dv1 = v[1] - k1.y, dv2 = v[2] - k1.z;
+        double dw0 = w[0] - k3.x, dw1 = w[1] - k3.y, dw2 = w[2] - k3.z;
+        double rb = k1.w;
         acc_env = (sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2) + rb * sqrt(dw0 * dw0 + dw1 * dw1 + dw2 * dw2)) / h +
                   rb * (w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     }
-    double q[4] = {qw, qx, qy, qz};
+    double q[4] = {k2.x, k2.y, k2.z, k2.w};
     double dq[4];
     dq[0] = -(q[1] * w[0] + q[2] * w[1] + q[3] * w[2]);
     dq[1] = q[0] * w[0] + q[2] * w[2] - q[3] * w[1];
@@ -1193,13 +1159,15 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     for (int i = 0; i < 4; i++) q[i] = q[i] + hh * dq[i];
     double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     for (int i = 0; i < 4; i++) q[i] = q[i] / qn;
-    S.px[c] = x[0]; S.py[c] = x[1]; S.pz[c] = x[2];
-    S.vx[c] = v[0]; S.vy[c] = v[1]; S.vz[c] = v[2];
-    S.wx[c] = w[0]; S.wy[c] = w[1]; S.wz[c] = w[2];
-    S.qw[c] = q[0]; S.qx[c] = q[1]; S.qy[c] = q[2]; S.qz[c] = q[3];
-    if (next) {  // the new state, for the next step's poses: x, q, v, w_body
-        for (int i = 0; i < 3; i++) { next[i] = x[i]; next[7 + i] = v[i]; next[10 + i] = w[i]; }
-        for (int i = 0; i < 4; i++) next[3 + i] = q[i];
+    rec[0] = make_double4(x[0], x[1], x[2], M);
+    rec[1] = make_double4(v[0], v[1], v[2], k1.w);
+    rec[2] = make_double4(q[0], q[1], q[2], q[3]);
+    rec[3] = make_double4(w[0], w[1], w[2], k3.w);
+    if (pose) {
+        for (int i = 0; i < 3; i++) pose[i] = x[i];
+        for (int i = 0; i < 4; i++) pose[3 + i] = q[i];
+        pose[7] = k0.x; pose[8] = k0.y; pose[9] = k0.z;
+        pose[10] = k2.x; pose[11] = k2.y; pose[12] = k2.z; pose[13] = k2.w;
     }
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
           isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
@@ -1209,12 +1177,11 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, c
     return aenv;
 }
 
-
 // One lane per sphere.  Waves are scheduled on clump boundaries (wave w
 // covers the spheres wave_s[2w] .. wave_s[2w+1]-1, whole clumps, at most 64
-// spheres), so the spheres of a clump sit in adjacent lanes: each lane sums its
-// sphere's row, then the clump's first lane sums its spheres in ascending id by
-// shuffles, adds gravity and integrates the clump.
+// spheres, starting with clump wave_c[w]), so the spheres of a clump sit in
+// adjacent lanes: each lane sums its sphere's row, then the clump's first
+// lane sums its spheres in ascending id by shuffles and integrates the clump.
 template <bool FP32>
 __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     if (aborted(S.ctl)) return;
@@ -1226,22 +1193,25 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     const int64_t s = S0 + lane;
     const bool active = s < S1;
     const int cur = S.ctl->buf;
-    const bool rec = S.ctl->record != 0;
-    // everything that depends on the sphere alone is loaded up front, together
-    uint32_t info = 0, ts = 0, ub = 0, nu = 0, lb = 0, nl = 0;
-    int64_t c = 0;
+    // on the step of a detection the guard takes the detection's poses
+    const bool fresh = S.guard_on && S.ctl->since_det == 0;
+    uint32_t info = 0, ub = 0, nu = 0, lb = 0, nl = 0;
+    uint32_t c0 = 0;
+    float m = 3.0e38f;
     if (active) {
-        c = S.owner[s];
         info = S.sinfo[s];
-        ts = S.sts[s];
         ub = S.up_beg[s]; nu = S.up_cnt[s];
         lb = pick(S.lo_beg, cur)[s]; nl = pick(S.lo_cnt, cur)[s];
+        if (S.guard_on) m = S.smargin[s];
     }
-    const int64_t cb = s - (int64_t)(info & 0xffu);  // the clump's first sphere
-    const int cnt = (int)(info >> 8);                 // and its sphere count
+    if (live) c0 = S.wave_c[w];
+    const int cnt = (int)(info >> 8);  // the clump's sphere count
     double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
     if (active) sphere_sum<FP32>(S, ub, nu, lb, nl, Fs, Ts);
-    const bool leader = active && s == cb;
+    const bool leader = active && (info & 0xffu) == 0;
+    // the leader's clump: the wave's first clump plus the leaders in lanes below
+    const unsigned long long leaders = __ballot(leader);
+    const int64_t c = (int64_t)c0 + __popcll(leaders & ((1ull << lane) - 1ull));
     int mx = leader ? cnt : 0;  // longest clump of the wave: the number of shuffle rounds
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
     double Fc[3], Tc[3];
@@ -1256,77 +1226,63 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
         }
     }
     float acc = 0.0f;
-    double nx[13];
-    for (int i = 0; i < 13; i++) nx[i] = 0.0;
+    // leader: the new CoM and orientation, then those at the last detection
+    double g[14];
+    for (int i = 0; i < 14; i++) g[i] = 0.0;
+    uint32_t tb = 0;
     if (leader) {
-        const Grid &g = S.grids[S.clump_scene[c]];
-        double M = S.mass[c];
-        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
-        if (rec) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
-        acc = integrate_clump(S, c, Fc, Tc, nx);
-    }
-    // The next step's poses from the state just integrated, which the clump's
-    // spheres (adjacent lanes) take from their leader lane: this saves the
-    // pose kernel's second pass over the clump state.
-    PoseIn pin{};
-    if (active) pin = pose_in(S, s, ts);
-    const int ldr = active ? (int)(cb - S0) : lane;
-    for (int i = 0; i < 13; i++) nx[i] = __shfl(nx[i], ldr, 64);
-    PoseOut r{false, 0.0f};
-    if (active) {
-        double A[9], Wv[3];
-        quat_mat(nx[3], nx[4], nx[5], nx[6], A);
-        world_omega(A, nx[10], nx[11], nx[12], Wv);
-        if (leader) {
-            S.kin[3 * c + 0] = make_double4(nx[0], nx[1], nx[2], S.mass[c]);
-            S.kin[3 * c + 1] = make_double4(nx[7], nx[8], nx[9], 0.0);
-            S.kin[3 * c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
+        acc = integrate_clump(S, c, Fc, Tc, g);
+        if (S.guard_on) {
+            tb = S.tmpl_sbeg[S.clump_tmpl[c]];
+            double4 *cd = S.cdet + 2 * c;
+            if (fresh) {  // the detection saw the state before this step's update
+                cd[0] = make_double4(g[7], g[8], g[9], 0.0);
+                cd[1] = make_double4(g[10], g[11], g[12], g[13]);
+            } else {
+                const double4 d0 = cd[0], d1 = cd[1];
+                g[7] = d0.x; g[8] = d0.y; g[9] = d0.z;
+                g[10] = d1.x; g[11] = d1.y; g[12] = d1.z; g[13] = d1.w;
+            }
         }
-        r = sphere_pose(S, s, pin, A, nx, nx + 7, Wv);
     }
-    // workgroup partials of the acceleration and speed maxima and the guard,
-    // reduced by k_step_end
-    __shared__ float pa[4], pv[4];
+    // Displacement guard: every sphere's centre now against where it stood at
+    // the last detection (both from its clump's pose, the same arithmetic as
+    // every other pose), tripping at 0.999 times its margin.
+    bool trip = false;
+    if (S.guard_on) {
+        const int ldr = active ? lane - (int)(info & 0xffu) : lane;
+        for (int i = 0; i < 14; i++) g[i] = __shfl(g[i], ldr, 64);
+        const uint32_t tbl = (uint32_t)__shfl((int)tb, ldr, 64);
+        if (active) {
+            const uint32_t ts = tbl + (info & 0xffu);
+            const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+            double A[9], D[9];
+            quat_mat(g[3], g[4], g[5], g[6], A);
+            quat_mat(g[10], g[11], g[12], g[13], D);
+            const double xs = g[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+            const double ys = g[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+            const double zs = g[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+            const double xd = g[7] + (D[0] * o0 + D[1] * o1 + D[2] * o2);
+            const double yd = g[8] + (D[3] * o0 + D[4] * o1 + D[5] * o2);
+            const double zd = g[9] + (D[6] * o0 + D[7] * o1 + D[8] * o2);
+            const double dx = xs - xd, dy = ys - yd, dz = zs - zd;
+            const double lim = 0.999 * (double)m;
+            trip = !(dx * dx + dy * dy + dz * dz < lim * lim);
+        }
+    }
+    // workgroup partials of the acceleration maximum and the guard, reduced by k_step_end
+    __shared__ float pa[4];
     __shared__ uint32_t pt_[4];
-    float am = acc, vm = r.speed;
-    for (int off = 32; off > 0; off >>= 1) {
-        am = fmaxf(am, __shfl_xor(am, off, 64));
-        vm = fmaxf(vm, __shfl_xor(vm, off, 64));
-    }
-    const unsigned long long trips = __ballot(r.trip);
-    if (lane == 0) { pa[threadIdx.x >> 6] = am; pv[threadIdx.x >> 6] = vm; pt_[threadIdx.x >> 6] = trips != 0; }
+    float am = acc;
+    for (int off = 32; off > 0; off >>= 1) am = fmaxf(am, __shfl_xor(am, off, 64));
+    const unsigned long long trips = __ballot(trip);
+    if (lane == 0) { pa[threadIdx.x >> 6] = am; pt_[threadIdx.x >> 6] = trips != 0; }
     __syncthreads();
     if (threadIdx.x == 0) {
         uint32_t *o = S.part_r + 3 * (int64_t)blockIdx.x;
         o[0] = __float_as_uint(fmaxf(fmaxf(pa[0], pa[1]), fmaxf(pa[2], pa[3])));
-        o[1] = __float_as_uint(fmaxf(fmaxf(pv[0], pv[1]), fmaxf(pv[2], pv[3])));
+        o[1] = 0u;
         o[2] = pt_[0] | pt_[1] | pt_[2] | pt_[3];
-    }
-}
-
-// Next-step poses of the spheres of the clumps too big for one wavefront
-// (after k_integrate_big), from the integrated state in memory.
-__global__ void __launch_bounds__(256) k_pose_big(DevScene S) {
-    if (aborted(S.ctl)) return;
-    const int32_t c = S.big_list[blockIdx.y];
-    const int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
-    double A[9], Wv[3];
-    quat_mat(S.qw[c], S.qx[c], S.qy[c], S.qz[c], A);
-    world_omega(A, S.wx[c], S.wy[c], S.wz[c], Wv);
-    const double X[3] = {S.px[c], S.py[c], S.pz[c]}, V[3] = {S.vx[c], S.vy[c], S.vz[c]};
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        S.kin[3 * (int64_t)c + 0] = make_double4(X[0], X[1], X[2], S.mass[c]);
-        S.kin[3 * (int64_t)c + 1] = make_double4(V[0], V[1], V[2], 0.0);
-        S.kin[3 * (int64_t)c + 2] = make_double4(Wv[0], Wv[1], Wv[2], 0.0);
-    }
-    const uint32_t tb = S.tmpl_sbeg[S.clump_tmpl[c]];
-    // every lane runs the same number of rounds so the wave-level flags see all lanes
-    const int64_t n = s1 - s0, stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
-        const int64_t k = base + threadIdx.x;
-        PoseOut r{false, 0.0f};
-        if (k < n) r = sphere_pose(S, s0 + k, pose_in(S, s0 + k, tb + (uint32_t)k), A, X, V, Wv);
-        pose_flags(&S.ctl->guard_next, &S.ctl->vmax_next, r);
     }
 }
 
@@ -1350,6 +1306,7 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     __shared__ double sh[6][256];
     int32_t c = S.big_list[blockIdx.x];
     int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    const bool fresh = S.guard_on && S.ctl->since_det == 0;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x)
         for (int i = 0; i < 3; i++) { acc[i] = acc[i] + S.sF[3 * s + i]; acc[3 + i] = acc[3 + i] + S.sT[3 * s + i]; }
@@ -1360,15 +1317,40 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
             for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = sh[i][threadIdx.x] + sh[i][threadIdx.x + w];
         __syncthreads();
     }
+    __shared__ double nx[7];
     if (threadIdx.x == 0) {
         double Fc[3] = {sh[0][0], sh[1][0], sh[2][0]}, Tc[3] = {sh[3][0], sh[4][0], sh[5][0]};
-        const Grid &g = S.grids[S.clump_scene[c]];
-        double M = S.mass[c];
-        Fc[0] = Fc[0] + M * g.gx; Fc[1] = Fc[1] + M * g.gy; Fc[2] = Fc[2] + M * g.gz;
-        if (S.ctl->record) for (int i = 0; i < 3; i++) { S.rec_cF[3 * c + i] = Fc[i]; S.rec_cT[3 * c + i] = Tc[i]; }
-        float a = integrate_clump(S, c, Fc, Tc);
+        double pz[14];
+        float a = integrate_clump(S, c, Fc, Tc, pz);
+        for (int i = 0; i < 7; i++) nx[i] = pz[i];
         if (S.detect_mode != 0 && a > __uint_as_float(S.ctl->amax_bits)) atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
     }
+    if (!S.guard_on) return;
+    // A big clump turns its far spheres through regions of very different
+    // margins (a wheel), so its guard is per sphere: the displacement of each
+    // sphere since the detection (its pose then was saved on the step of the
+    // detection) against 0.999 times its own margin.
+    __syncthreads();
+    double A[9];
+    quat_mat(nx[3], nx[4], nx[5], nx[6], A);
+    const uint32_t tb = S.tmpl_sbeg[S.clump_tmpl[c]];
+    double4 *det = S.bdet + S.big_sbeg[blockIdx.x];
+    int trip = 0;
+    for (int64_t k = threadIdx.x; k < s1 - s0; k += blockDim.x) {
+        const int64_t s = s0 + k;
+        const uint32_t ts = tb + (uint32_t)k;
+        const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+        const double xs = nx[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+        const double ys = nx[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+        const double zs = nx[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+        double4 d;
+        if (fresh) { d = S.spos[s]; det[k] = d; }
+        else d = det[k];
+        const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
+        const double lim = 0.999 * (double)S.smargin[s];
+        if (!(dx * dx + dy * dy + dz * dz < lim * lim)) trip = 1;
+    }
+    if (__syncthreads_or(trip) && threadIdx.x == 0) S.ctl->guard_next = 1;
 }
 
 // The reduction's workgroup partials folded into kFold partials (maxima are
@@ -1428,12 +1410,10 @@ __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     // the clumps too big for one wavefront report through the atomic slots
     c->amax_last = S.detect_mode != 0 ? max(c->amax_bits, am) : 0u;
     c->amax_bits = 0;
-    // the integration computed the next step's poses, speeds and guard
-    c->vmax_bits = max(c->vmax_next, vm);
-    c->vmax_next = 0;
+    (void)vm;
+    c->vmax_bits = 0;  // measured again by k_pose when the next detection needs it
     c->guard = (c->guard_next | (int32_t)tr) != 0;
     c->guard_next = 0;
-    c->pose_fresh = 1;
     c->step++;
     c->since_det++;
     c->det_due = (S.detect_mode == 0 || c->since_det >= c->k_cur) ? 1 : 0;
@@ -1626,7 +1606,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
-                                           "k_narrow_over", "k_region_margin", "k_pose_big"};
+                                           "k_narrow_over", "k_region_margin"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1643,9 +1623,9 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_pose(const DevScene &S, hipStream_t st) {
+hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force) {
     if (S.ns == 0) return hipSuccess;
-    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
+    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, force ? 1 : 0));
     return hipGetLastError();
 }
 
@@ -1736,7 +1716,6 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
         else
             TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_reduce_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
         TIMED(K_INTEGRATE_BIG, hipLaunchKernelGGL(k_integrate_big, dim3(S.n_big), dim3(256), 0, st, S));
-        TIMED(K_POSE_BIG, hipLaunchKernelGGL(k_pose_big, dim3(16, S.n_big), dim3(256), 0, st, S));
     }
     return hipGetLastError();
 }
@@ -1754,19 +1733,25 @@ hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uin
 }
 
 // ---------------------------------------------------------------- state transfer
-// Row-major [n][3]/[n][4] device buffers <-> the scene's SoA clump state.
+// Row-major [n][3]/[n][4] device buffers <-> the clump records (null buffers
+// are skipped; the static words of a record are kept).
 __global__ void __launch_bounds__(256) k_pack_state(DevScene S, double *x, double *q, double *v, double *w, int unpack) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= S.nc) return;
-    double *fx[3] = {S.px, S.py, S.pz}, *fq[4] = {S.qw, S.qx, S.qy, S.qz};
-    double *fv[3] = {S.vx, S.vy, S.vz}, *fw[3] = {S.wx, S.wy, S.wz};
-    for (int k = 0; k < 3; k++) {
-        if (x) { if (unpack) fx[k][c] = x[3 * c + k]; else x[3 * c + k] = fx[k][c]; }
-        if (v) { if (unpack) fv[k][c] = v[3 * c + k]; else v[3 * c + k] = fv[k][c]; }
-        if (w) { if (unpack) fw[k][c] = w[3 * c + k]; else w[3 * c + k] = fw[k][c]; }
+    double4 *r = S.cst + 4 * c;
+    double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
+    if (!unpack) {
+        if (x) { x[3 * c] = k0.x; x[3 * c + 1] = k0.y; x[3 * c + 2] = k0.z; }
+        if (v) { v[3 * c] = k1.x; v[3 * c + 1] = k1.y; v[3 * c + 2] = k1.z; }
+        if (q) { q[4 * c] = k2.x; q[4 * c + 1] = k2.y; q[4 * c + 2] = k2.z; q[4 * c + 3] = k2.w; }
+        if (w) { w[3 * c] = k3.x; w[3 * c + 1] = k3.y; w[3 * c + 2] = k3.z; }
+        return;
     }
-    for (int k = 0; k < 4; k++)
-        if (q) { if (unpack) fq[k][c] = q[4 * c + k]; else q[4 * c + k] = fq[k][c]; }
+    if (x) { k0.x = x[3 * c]; k0.y = x[3 * c + 1]; k0.z = x[3 * c + 2]; }
+    if (v) { k1.x = v[3 * c]; k1.y = v[3 * c + 1]; k1.z = v[3 * c + 2]; }
+    if (q) { k2.x = q[4 * c]; k2.y = q[4 * c + 1]; k2.z = q[4 * c + 2]; k2.w = q[4 * c + 3]; }
+    if (w) { k3.x = w[3 * c]; k3.y = w[3 * c + 1]; k3.z = w[3 * c + 2]; }
+    r[0] = k0; r[1] = k1; r[2] = k2; r[3] = k3;
 }
 
 hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack, hipStream_t st) {
