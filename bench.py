@@ -46,9 +46,10 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     P, U, C = st["pairs"], st["upper"], st["contact_sides"] / 2.0
     v = 16 if st["fp32"] else 32
     mat = 16 if st["fp32"] else 32
-    guard = st["guard"]
+    guard, learned = st["guard"], st.get("learned", False)
     if kernel == "k_pose":
-        return ns * (36 + (36 if guard else 0)) + nc * 220
+        # per sphere: owner, template sphere, position write (+ speed); per clump its record
+        return ns * (8 + 32 + (4 if guard else 0)) + nc * 128
     if kernel == "k_cell_count":
         return ns * 48
     if kernel == "k_cell_scatter":
@@ -62,14 +63,17 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     if kernel == "k_pairs":
         # per pair: own id, partner, history read, force and torque of the lower
         # sphere; per sphere pair the partner's torque; per contact the history
-        # write; compulsory per-sphere and per-clump gathers (position+radius,
-        # material, owner, kinematics)
-        return P * (8 + 24 + 2 * v) + U * v + C * 24 + ns * (32 + mat + 4) + nc * 96
+        # write; compulsory per-sphere and per-clump gathers (owner, template
+        # sphere, material; the clump record)
+        return P * (8 + 24 + 2 * v) + U * v + C * 24 + ns * (8 + mat) + nc * 128
     if kernel == "k_reduce_waves":
         # per upper entry: link, the pair's force and the partner's torque; per
-        # pair: force and torque of the lower sphere; per sphere: segment bounds
-        # and owner; per clump: state read+write, mass properties, scene, bounding radius
-        return U * (4 + 2 * v) + P * 2 * v + ns * 20 + nc * 264
+        # pair: force and torque of the lower sphere; per sphere: clump position
+        # and segment bounds (+ margin for the guard); per clump: record read
+        # and write, template, scene, prescribed-motion index (+ its pose at the
+        # last detection for the guard, + acceleration envelope when learned)
+        return (U * (4 + 2 * v) + P * 2 * v + ns * (20 + (4 if guard else 0)) +
+                nc * (268 + (64 if guard else 0) + (4 if learned else 0)))
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)
     if kernel == "k_detect_begin":
@@ -161,9 +165,11 @@ def roofline(res, desc_stats, mode):
     k, (n, ms) = max(prof.items(), key=lambda kv: kv[1][1])
     cnt = res["counts"]
     st = dict(desc_stats, pairs=cnt["pairs"], upper=cnt["candidates"] - cnt["pairs"],
-              contact_sides=res["contact_sides"], guard=(mode != "plain"))
+              contact_sides=res["contact_sides"], guard=(mode != "plain"), learned=(mode == "learned"))
     # a detection kernel early-exits when no detection is due: count only real launches
     launches = n
+    if k == "k_pose":  # works on the steps that detect or audit
+        launches = max(1, res["detections"] + res["counts"].get("audits", 0))
     if k in ("k_narrow", "k_link", "k_cell_count", "k_cell_scatter", "k_detect_begin", "k_scan_reduce",
              "k_scan_final"):
         launches = max(1, res["detections"])

@@ -101,7 +101,7 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
     const Ctl *ctl = S.ctl;
     if (!force && !(due(ctl) || audit_due(S) || ctl->collecting)) return;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool speeds = S.store_speed || ctl->collecting || S.detect_mode == 1;
+    const bool speeds = S.store_speed || ctl->collecting || S.detect_mode != 0;
     float speed = 0.0f;
     if (s < S.ns) {
         const SphereKin k = sphere_kin(S, (uint32_t)s);
@@ -114,8 +114,9 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
             if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
         }
     }
-    if (S.detect_mode != 1) return;
-    // the fixed rule's global speed maximum: one filtered atomic per workgroup
+    if (S.detect_mode == 0) return;
+    // the global speed maximum (the fixed rule, and the learned rule's
+    // fallback): one filtered atomic per workgroup
     __shared__ float wmax[4];
     for (int off = 32; off > 0; off >>= 1) speed = fmaxf(speed, __shfl_xor(speed, off, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = speed;
