@@ -562,42 +562,70 @@ __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t &total) 
 // particular order: spheres of other clumps inside the enlarged contact
 // geometry, d^2 < ((R_s + R_t) + (m_s + m_t))^2, then boundaries with
 // phi < R_s + (m_s + boundary margin).  emit(t) is called once per candidate.
+// What the narrow phase knows of the sphere it works for.
+struct NarrowSelf {
+    double4 P;        // centre, radius
+    float4 Pf;        // FP32 prefilter record: centre - grid origin, radius + margin
+    uint32_t own;     // clump
+    float ms;         // margin
+    bool exact_only;  // far outside the domain the FP32 slack no longer bounds the rounding
+    double reach;     // its own (R + m) plus the largest partner (R + m), plus a small slack
+};
+__device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid &g, uint32_t s) {
+    NarrowSelf n;
+    n.P = S.spos[s];
+    n.own = S.owner[s];
+    n.ms = S.smargin[s];
+    n.Pf = make_float4((float)(n.P.x - g.ox), (float)(n.P.y - g.oy), (float)(n.P.z - g.oz), (float)n.P.w + n.ms);
+    n.exact_only = !(fabsf(n.Pf.x) < g.pre_lim && fabsf(n.Pf.y) < g.pre_lim && fabsf(n.Pf.z) < g.pre_lim);
+    n.reach = (n.P.w + (double)n.ms) + g.rm_max + 1e-9;
+    return n;
+}
+
+// The conservative FP32 test of sorted slot j: it can only admit extra
+// candidates, which the exact FP64 predicate then rejects.
+__device__ __forceinline__ bool narrow_prefilter(const DevScene &S, const Grid &g, const NarrowSelf &n, uint32_t j) {
+    const float4 Qf = S.sorted_f4[j];
+    const float fx = Qf.x - n.Pf.x, fy = Qf.y - n.Pf.y, fz = Qf.z - n.Pf.z;
+    const float fr = (n.Pf.w + Qf.w) + g.pre_eps;
+    return n.exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
+}
+
+// The exact predicate of the enlarged geometry for slot j (another clump,
+// d^2 < ((R_s + R_t) + (m_s + m_t))^2); returns the partner's id or ~0u.
+__device__ __forceinline__ uint32_t narrow_exact(const DevScene &S, const NarrowSelf &n, uint32_t j) {
+    if (S.sorted_owner[j] == n.own) return ~0u;
+    const double4 Q = S.sorted_pos[j];
+    const double dx = Q.x - n.P.x, dy = Q.y - n.P.y, dz = Q.z - n.P.z;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    double Sr = n.P.w + Q.w;
+    Sr = Sr + ((double)n.ms + (double)S.sorted_margin[j]);
+    return d2 < Sr * Sr ? S.sorted_id[j] : ~0u;
+}
+
+// Boundary candidates of sphere s: phi < R_s + (m_s + boundary margin).
 template <class Emit>
-__device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s, Emit emit) {
-    const double4 P = S.spos[s];
-    const uint32_t own = S.owner[s];
-    const float ms = S.smargin[s];
-    const Grid &g = S.grids[S.sscene[s]];
-    const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w + ms);
-    const float eps = g.pre_eps;
-    // far outside the domain the slack no longer bounds the rounding: exact test only
-    const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
-    // reach of s: its own (R + m) plus the largest partner (R + m); a small
-    // absolute slack keeps the bin selection conservative under rounding
-    const double reach = (P.w + (double)ms) + g.rm_max + 1e-9;
-    scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
-        for (uint32_t j = jb; j < je; j++) {
-            // conservative FP32 test first: it can only admit extra candidates,
-            // which the exact FP64 predicate below then rejects
-            float4 Qf = S.sorted_f4[j];
-            float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z;
-            float fr = (Pf.w + Qf.w) + eps;
-            if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
-            if (S.sorted_owner[j] == own) continue;
-            double4 Q = S.sorted_pos[j];
-            double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            double Sr = P.w + Q.w;
-            Sr = Sr + ((double)ms + (double)S.sorted_margin[j]);
-            if (d2 < Sr * Sr) emit(S.sorted_id[j]);
-        }
-    });
+__device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid &g, const NarrowSelf &n, Emit emit) {
     const double tnow = (double)S.ctl->step * S.h;
     for (int b = g.bnd_beg; b < g.bnd_end; b++) {
-        double phi, n[3];
-        if (!bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n)) continue;
-        if (phi < P.w + ((double)ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
+        double phi, nv[3];
+        if (!bnd_distance(S.bnd[b], tnow, n.P.x, n.P.y, n.P.z, phi, nv)) continue;
+        if (phi < n.P.w + ((double)n.ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
     }
+}
+
+template <class Emit>
+__device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s, Emit emit) {
+    const Grid &g = S.grids[S.sscene[s]];
+    const NarrowSelf n = narrow_self(S, g, s);
+    scan_reach(S, g, n.P.x, n.P.y, n.P.z, n.reach, [&](uint32_t jb, uint32_t je) {
+        for (uint32_t j = jb; j < je; j++) {
+            if (!narrow_prefilter(S, g, n, j)) continue;
+            const uint32_t t = narrow_exact(S, n, j);
+            if (t != ~0u) emit(t);
+        }
+    });
+    narrow_boundaries(S, g, n, emit);
 }
 
 // Write the new segments of sphere s from its ascending candidates get(k):
@@ -646,7 +674,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     int cnt = 0, nup = 0, nbp = 0;
     const uint32_t s = (uint32_t)i;
     if (i < S.ns) {
-        narrow_candidates(S, s, [&](uint32_t t) {
+        auto emit = [&](uint32_t t) {
             if (cnt < kMaxRow) {
                 int k = cnt;
                 while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
@@ -658,7 +686,32 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
             cnt++;
             nup += t < s;
             nbp += t >= (uint32_t)S.ns;
+        };
+        const Grid &g = S.grids[S.sscene[s]];
+        const NarrowSelf n = narrow_self(S, g, s);
+        // First the cheap FP32 test over every slot in reach, keeping the slots
+        // that pass in the LDS list; then the exact test over that short list.
+        // Split this way, a wavefront runs the exact test and the sorted insert
+        // as often as its busiest lane has prefilter hits, not as often as it
+        // has slots in reach.
+        int npre = 0;
+        scan_reach(S, g, n.P.x, n.P.y, n.P.z, n.reach, [&](uint32_t jb, uint32_t je) {
+            for (uint32_t j = jb; j < je; j++) {
+                if (!narrow_prefilter(S, g, n, j)) continue;
+                if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
+                npre++;
+            }
         });
+        if (npre <= kMaxRow) {
+            // an insert writes at most at the position of the slot just read
+            for (int k = 0; k < npre; k++) {
+                const uint32_t t = narrow_exact(S, n, lst[k * kNarrowBlock + tid]);
+                if (t != ~0u) emit(t);
+            }
+            narrow_boundaries(S, g, n, emit);
+        } else {
+            narrow_candidates(S, s, emit);  // many slots pass the prefilter: one exact pass
+        }
     }
     const int nlo = cnt - nup;
     // segment allocation: scans within each wavefront, then one atomic per
@@ -1471,6 +1524,7 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // margin, must each be in both partners' rows of the active set.
 __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
     if (!audit_due(S)) return;
+    __shared__ uint32_t alst[kMaxRow * 256];
     int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     unsigned long long found = 0, missed = 0;
     if (i < S.ns) {
@@ -1493,19 +1547,36 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         // the FP32 prefilter of the narrow phase, without margins
         const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
         const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+        auto prefilter = [&](uint32_t j) {
+            const float4 Qf = S.sorted_f4[j];
+            const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+            return exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
+        };
+        auto exact = [&](uint32_t j) {
+            if (S.sorted_owner[j] == own) return;
+            double4 Q = S.sorted_pos[j];
+            double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+            double d2 = dx * dx + dy * dy + dz * dz;
+            double Sr = P.w + Q.w;
+            if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
+        };
+        // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
+        int npre = 0;
         scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
             for (uint32_t j = jb; j < je; j++) {
-                const float4 Qf = S.sorted_f4[j];
-                const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
-                if (!exact_only && !(fx * fx + fy * fy + fz * fz < fr * fr)) continue;
-                if (S.sorted_owner[j] == own) continue;
-                double4 Q = S.sorted_pos[j];
-                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                double d2 = dx * dx + dy * dy + dz * dz;
-                double Sr = P.w + Q.w;
-                if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
+                if (!prefilter(j)) continue;
+                if (npre < kMaxRow) alst[npre * 256 + threadIdx.x] = j;
+                npre++;
             }
         });
+        if (npre <= kMaxRow) {
+            for (int k = 0; k < npre; k++) exact(alst[k * 256 + threadIdx.x]);
+        } else {
+            scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
+                for (uint32_t j = jb; j < je; j++)
+                    if (prefilter(j)) exact(j);
+            });
+        }
         double tnow = (double)S.ctl->step * S.h;
         for (int b = g.bnd_beg; b < g.bnd_end; b++) {
             double phi, n[3];
