@@ -56,8 +56,8 @@ __device__ __forceinline__ void quat_mat(double w, double x, double y, double z,
 // this one way, so the positions of a detection, of the force kernel and of
 // a readout are the same numbers.
 struct SphereKin { double p[3], R, xc[3], M, v[3], W[3]; };
-__device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
-    const uint32_t c = S.owner[s], ts = S.sts[s];
+// ... of the sphere that is template sphere ts of clump c
+__device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c, uint32_t ts) {
     const double4 *r = S.cst + 4 * (int64_t)c;
     const double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
     const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
@@ -75,6 +75,9 @@ __device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
     k.W[1] = A[3] * k3.x + A[4] * k3.y + A[5] * k3.z;
     k.W[2] = A[6] * k3.x + A[7] * k3.y + A[8] * k3.z;
     return k;
+}
+__device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
+    return sphere_kin_of(S, S.owner[s], S.sts[s]);
 }
 
 // Raise a device-wide float maximum kept as bits in the control block.  The
@@ -954,17 +957,26 @@ __device__ __forceinline__ void torque(const double *r, const double *f, double 
 // have the lower sphere as body a; a boundary pair has the sphere as body b.
 // Writes the pair's history and contributions, and returns the contact
 // sides it created.
+// Ids of a pair and the clumps and template spheres of its spheres (b unused
+// for a boundary pair).
+struct PairIds { uint32_t s, t, ca, ta, cb, tb; };
+__device__ __forceinline__ PairIds pair_ids(const DevScene &S, uint32_t s, uint32_t t) {
+    PairIds q{s, t, S.owner[s], S.sts[s], 0u, 0u};
+    if (t < (uint32_t)S.ns) { q.cb = S.owner[t]; q.tb = S.sts[t]; }
+    return q;
+}
+
 template <bool FP32>
-__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const uint32_t *pt, double *hist,
+__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
                                               double tnow, bool rec) {
     using V = typename Contrib<FP32>::V;
     V *cS = (V *)S.cS, *cTs = (V *)S.cTs, *cTt = (V *)S.cTt;
     const double zero3[3] = {0.0, 0.0, 0.0};
-    const uint32_t s = S.ps[e], t = pt[e];
+    const uint32_t s = id.s, t = id.t;
     double *h = hist + 3 * e;
     if (t < (uint32_t)S.ns) {
         const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
-        const SphereKin ka = sphere_kin(S, a), kb = sphere_kin(S, b);
+        const SphereKin ka = sphere_kin_of(S, id.ca, id.ta), kb = sphere_kin_of(S, id.cb, id.tb);
         double dx = kb.p[0] - ka.p[0], dy = kb.p[1] - ka.p[1], dz = kb.p[2] - ka.p[2];
         double d2 = dx * dx + dy * dy + dz * dz;
         double Sr = ka.R + kb.R;
@@ -1024,7 +1036,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     }
     // boundary pair: the boundary is body a, sphere s is body b
     const Bnd &B = S.bnd[t - (uint32_t)S.ns];
-    const SphereKin ks = sphere_kin(S, s);
+    const SphereKin ks = sphere_kin_of(S, id.ca, id.ta);
     double phi, n[3];
     bool contact = bnd_distance(B, tnow, ks.p[0], ks.p[1], ks.p[2], phi, n) && phi < ks.R;
     if (!contact) {
@@ -1085,8 +1097,21 @@ __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
     const int64_t n = S.ctl->n_pairs_cur;
     const bool rec = S.ctl->record != 0;
     const double tnow = (double)S.ctl->step * S.h;
-    for (int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
-        (void)eval_pair<FP32>(S, e, pt, hist, tnow, rec);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    // Software pipeline over the grid-stride loop: while pair e is evaluated,
+    // the clumps of the next pair and the ids of the one after are in flight.
+    PairIds now{};
+    uint32_t s2 = 0, t2 = 0;
+    if (e < n) now = pair_ids(S, S.ps[e], pt[e]);
+    if (e + stride < n) { s2 = S.ps[e + stride]; t2 = pt[e + stride]; }
+    for (; e < n; e += stride) {
+        PairIds nxt{};
+        if (e + stride < n) nxt = pair_ids(S, s2, t2);
+        if (e + 2 * stride < n) { s2 = S.ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
+        (void)eval_pair<FP32>(S, e, now, hist, tnow, rec);
+        now = nxt;
+    }
 }
 
 // Contact sides of the last evaluated step (each sphere pair in contact counts
@@ -1266,19 +1291,25 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     // the leader's clump: the wave's first clump plus the leaders in lanes below
     const unsigned long long leaders = __ballot(leader);
     const int64_t c = (int64_t)c0 + __popcll(leaders & ((1ull << lane) - 1ull));
-    int mx = leader ? cnt : 0;  // longest clump of the wave: the number of shuffle rounds
-    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    // the clump sums, through LDS: each lane stores its sphere's sums, the
+    // leader adds its clump's lanes in ascending order (the wave only reads
+    // what its own lanes wrote, so no barrier is needed, only program order)
+    // one LDS buffer: rows 0-2 carry the sums, later rows 0-6 the poses
+    __shared__ double2 xs[7][256];
+    xs[0][threadIdx.x] = make_double2(Fs[0], Fs[1]);
+    xs[1][threadIdx.x] = make_double2(Fs[2], Ts[0]);
+    xs[2][threadIdx.x] = make_double2(Ts[1], Ts[2]);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double Fc[3], Tc[3];
     for (int i = 0; i < 3; i++) { Fc[i] = 0.0 + Fs[i]; Tc[i] = 0.0 + Ts[i]; }
-    for (int j = 1; j < mx; j++) {
-        int src = min(lane + j, 63);
-        double f0 = __shfl(Fs[0], src, 64), f1 = __shfl(Fs[1], src, 64), f2 = __shfl(Fs[2], src, 64);
-        double t0 = __shfl(Ts[0], src, 64), t1 = __shfl(Ts[1], src, 64), t2 = __shfl(Ts[2], src, 64);
-        if (leader && j < cnt) {
-            Fc[0] = Fc[0] + f0; Fc[1] = Fc[1] + f1; Fc[2] = Fc[2] + f2;
-            Tc[0] = Tc[0] + t0; Tc[1] = Tc[1] + t1; Tc[2] = Tc[2] + t2;
+    if (leader)
+        for (int j = 1; j < cnt; j++) {
+            const double2 a = xs[0][threadIdx.x + j], b = xs[1][threadIdx.x + j], d = xs[2][threadIdx.x + j];
+            Fc[0] = Fc[0] + a.x; Fc[1] = Fc[1] + a.y; Fc[2] = Fc[2] + b.x;
+            Tc[0] = Tc[0] + b.y; Tc[1] = Tc[1] + d.x; Tc[2] = Tc[2] + d.y;
         }
-    }
     float acc = 0.0f;
     // leader: the new CoM and orientation, then those at the last detection
     double g[14];
@@ -1304,10 +1335,21 @@ __global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
     // every other pose), tripping at 0.999 times its margin.
     bool trip = false;
     if (S.guard_on) {
-        const int ldr = active ? lane - (int)(info & 0xffu) : lane;
-        for (int i = 0; i < 14; i++) g[i] = __shfl(g[i], ldr, 64);
-        const uint32_t tbl = (uint32_t)__shfl((int)tb, ldr, 64);
+        // the leader's poses to its lanes, through LDS (after every leader of
+        // the wave has read the sums)
+        double2(*gs)[256] = xs;
+        __shared__ uint32_t tbs[256];
+        if (leader) {
+            for (int i = 0; i < 7; i++) gs[i][threadIdx.x] = make_double2(g[2 * i], g[2 * i + 1]);
+            tbs[threadIdx.x] = tb;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         if (active) {
+            const int ldr = (int)threadIdx.x - (int)(info & 0xffu);
+            for (int i = 0; i < 7; i++) { const double2 v = gs[i][ldr]; g[2 * i] = v.x; g[2 * i + 1] = v.y; }
+            const uint32_t tbl = tbs[ldr];
             const uint32_t ts = tbl + (info & 0xffu);
             const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
             double A[9], D[9];
