@@ -243,6 +243,45 @@ __device__ __forceinline__ void scan_reach(const DevScene &S, const Grid &g, dou
     }
 }
 
+// The same visit in FP32, on positions relative to the grid origin, for the
+// FP32 prefilter passes: the caller widens the reach by twice the prefilter
+// slack, which bounds the rounding of every quantity here, so the rows and
+// x-ranges visited include all those of the FP64 visit (a few more at most).
+__device__ __forceinline__ float slab_gap32(float p, float b, int i, int n) {
+    const float lo = (i == 0) ? -3.0e38f : (float)i * b;
+    const float hi = (i == n - 1) ? 3.0e38f : (float)(i + 1) * b;
+    return p < lo ? lo - p : (p > hi ? p - hi : 0.0f);
+}
+__device__ __forceinline__ int clamp_cell32(float v, int n) {
+    v = floorf(v);
+    v = fminf(fmaxf(v, 0.0f), (float)(n - 1));
+    return (int)v;
+}
+template <typename F>
+__device__ __forceinline__ void scan_reach32(const DevScene &S, const Grid &g, float px, float py, float pz,
+                                             float reach, F &&f) {
+    const float inv = (float)g.inv, b = (float)g.b;
+    const int z0 = clamp_cell32((pz - reach) * inv, g.nz), z1 = clamp_cell32((pz + reach) * inv, g.nz);
+    const int y0 = clamp_cell32((py - reach) * inv, g.ny), y1 = clamp_cell32((py + reach) * inv, g.ny);
+    const float r2 = reach * reach;
+    for (int zz = z0; zz <= z1; zz++) {
+        const float gz = slab_gap32(pz, b, zz, g.nz);
+        const float rz = r2 - gz * gz;
+        if (rz < 0.0f) continue;
+        for (int yy = y0; yy <= y1; yy++) {
+            const float gy = slab_gap32(py, b, yy, g.ny);
+            const float ry = rz - gy * gy;
+            if (ry < 0.0f) continue;
+            const float rx = sqrtf(ry);
+            const int x0 = clamp_cell32((px - rx) * inv, g.nx), x1 = clamp_cell32((px + rx) * inv, g.nx);
+            const int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
+            const uint32_t jb = S.cell_start[rowc + x0];
+            const uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+            f(jb, je);
+        }
+    }
+}
+
 // Envelope region (block of kRegionBins^3 bins of the scene's grid) of a bin.
 __device__ __forceinline__ int64_t region_of(const Grid &g, uint32_t cell) {
     // a scene holds at most 2^27 bins: 32-bit division suffices
@@ -331,17 +370,41 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(DevScene S, uint32_t
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
 }
 
-__global__ void __launch_bounds__(kScanBlock) k_scan_bsum(DevScene S, uint32_t *bsum, int64_t nblk, int which) {
+// Exclusive scan of the block sums in place: one workgroup of 1024 lanes,
+// eight consecutive sums per lane per round.
+constexpr int kBsumBlock = 1024, kBsumItems = 8;
+__global__ void __launch_bounds__(kBsumBlock) k_scan_bsum(DevScene S, uint32_t *bsum, int64_t nblk, int which) {
     if (!chain_active(S, which)) return;
-    __shared__ uint32_t sh[kScanBlock];
+    __shared__ uint32_t wt[kBsumBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nblk; b0 += kScanBlock) {
-        int64_t i = b0 + threadIdx.x;
-        uint32_t v = i < nblk ? bsum[i] : 0u;
-        uint32_t tot;
-        uint32_t ex = block_excl_scan(v, sh, tot);
-        if (i < nblk) bsum[i] = carry + ex;
+    for (int64_t b0 = 0; b0 < nblk; b0 += (int64_t)kBsumBlock * kBsumItems) {
+        const int64_t i0 = b0 + (int64_t)threadIdx.x * kBsumItems;
+        uint32_t loc[kBsumItems], v = 0;
+        for (int k = 0; k < kBsumItems; k++) {
+            loc[k] = i0 + k < nblk ? bsum[i0 + k] : 0u;
+            v += loc[k];
+        }
+        uint32_t x = v;  // inclusive wave scan
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wt[wid] = x;
+        __syncthreads();
+        uint32_t below = 0, tot = 0;
+        for (int k = 0; k < kBsumBlock / 64; k++) {
+            const uint32_t t = wt[k];
+            if (k < wid) below += t;
+            tot += t;
+        }
+        uint32_t ex = carry + below + (x - v);
+        for (int k = 0; k < kBsumItems; k++) {
+            if (i0 + k < nblk) bsum[i0 + k] = ex;
+            ex += loc[k];
+        }
         carry += tot;
+        __syncthreads();  // wt is rewritten by the next round
     }
 }
 
@@ -698,14 +761,15 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         // as often as its busiest lane has prefilter hits, not as often as it
         // has slots in reach.
         int npre = 0;
-        scan_reach(S, g, n.P.x, n.P.y, n.P.z, n.reach, [&](uint32_t jb, uint32_t je) {
-            for (uint32_t j = jb; j < je; j++) {
-                if (!narrow_prefilter(S, g, n, j)) continue;
-                if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
-                npre++;
-            }
-        });
-        if (npre <= kMaxRow) {
+        if (!n.exact_only)
+            scan_reach32(S, g, n.Pf.x, n.Pf.y, n.Pf.z, (float)n.reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
+                for (uint32_t j = jb; j < je; j++) {
+                    if (!narrow_prefilter(S, g, n, j)) continue;
+                    if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
+                    npre++;
+                }
+            });
+        if (!n.exact_only && npre <= kMaxRow) {
             // an insert writes at most at the position of the slot just read
             for (int k = 0; k < npre; k++) {
                 const uint32_t t = narrow_exact(S, n, lst[k * kNarrowBlock + tid]);
@@ -1402,7 +1466,6 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     __shared__ double sh[6][256];
     int32_t c = S.big_list[blockIdx.x];
     int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
-    const bool fresh = S.guard_on && S.ctl->since_det == 0;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x)
         for (int i = 0; i < 3; i++) { acc[i] = acc[i] + S.sF[3 * s + i]; acc[3 + i] = acc[3 + i] + S.sT[3 * s + i]; }
@@ -1413,26 +1476,32 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
             for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = sh[i][threadIdx.x] + sh[i][threadIdx.x + w];
         __syncthreads();
     }
-    __shared__ double nx[7];
     if (threadIdx.x == 0) {
         double Fc[3] = {sh[0][0], sh[1][0], sh[2][0]}, Tc[3] = {sh[3][0], sh[4][0], sh[5][0]};
-        double pz[14];
-        float a = integrate_clump(S, c, Fc, Tc, pz);
-        for (int i = 0; i < 7; i++) nx[i] = pz[i];
+        float a = integrate_clump(S, c, Fc, Tc);
         if (S.detect_mode != 0 && a > __uint_as_float(S.ctl->amax_bits)) atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
     }
-    if (!S.guard_on) return;
-    // A big clump turns its far spheres through regions of very different
-    // margins (a wheel), so its guard is per sphere: the displacement of each
-    // sphere since the detection (its pose then was saved on the step of the
-    // detection) against 0.999 times its own margin.
-    __syncthreads();
+}
+
+// Guard of the clumps too big for one wavefront, after their integration,
+// one slice of spheres per workgroup.  Such a clump turns its far spheres
+// through regions of very different margins (a wheel), so, as for every
+// other clump, each sphere's displacement since the detection (its pose then
+// is saved on the step of the detection) is held against 0.999 times its own
+// margin.
+__global__ void __launch_bounds__(256) k_guard_big(DevScene S) {
+    if (aborted(S.ctl) || !S.guard_on) return;
+    const int32_t c = S.big_list[blockIdx.y];
+    const int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    const bool fresh = S.ctl->since_det == 0;
+    const double4 k0 = S.cst[4 * (int64_t)c], k2 = S.cst[4 * (int64_t)c + 2];
     double A[9];
-    quat_mat(nx[3], nx[4], nx[5], nx[6], A);
+    quat_mat(k2.x, k2.y, k2.z, k2.w, A);
+    const double nx[3] = {k0.x, k0.y, k0.z};
     const uint32_t tb = S.tmpl_sbeg[S.clump_tmpl[c]];
-    double4 *det = S.bdet + S.big_sbeg[blockIdx.x];
+    double4 *det = S.bdet + S.big_sbeg[blockIdx.y];
     int trip = 0;
-    for (int64_t k = threadIdx.x; k < s1 - s0; k += blockDim.x) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s1 - s0; k += (int64_t)gridDim.x * blockDim.x) {
         const int64_t s = s0 + k;
         const uint32_t ts = tb + (uint32_t)k;
         const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
@@ -1604,14 +1673,15 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         };
         // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
         int npre = 0;
-        scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
-            for (uint32_t j = jb; j < je; j++) {
-                if (!prefilter(j)) continue;
-                if (npre < kMaxRow) alst[npre * 256 + threadIdx.x] = j;
-                npre++;
-            }
-        });
-        if (npre <= kMaxRow) {
+        if (!exact_only)
+            scan_reach32(S, g, Pf.x, Pf.y, Pf.z, (float)reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
+                for (uint32_t j = jb; j < je; j++) {
+                    if (!prefilter(j)) continue;
+                    if (npre < kMaxRow) alst[npre * 256 + threadIdx.x] = j;
+                    npre++;
+                }
+            });
+        if (!exact_only && npre <= kMaxRow) {
             for (int k = 0; k < npre; k++) exact(alst[k * 256 + threadIdx.x]);
         } else {
             scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
@@ -1720,7 +1790,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
-                                           "k_narrow_over", "k_region_margin"};
+                                           "k_narrow_over", "k_region_margin", "k_guard_big"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1758,7 +1828,7 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
     // the block-sum scratch lives after the cell arrays (allocated by the runtime)
     uint32_t *bsum = S.cell_fill + S.n_cells;
     TIMED(K_SCAN_REDUCE, hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S, bsum, which));
-    TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kScanBlock), 0, st, S, bsum, nblk, which));
+    TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBsumBlock), 0, st, S, bsum, nblk, which));
     TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S,
                                            (const uint32_t *)bsum, which));
     TIMED(K_CELL_SCATTER, hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S,
@@ -1830,6 +1900,7 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
         else
             TIMED(K_FORCE_BIG, hipLaunchKernelGGL(k_reduce_big_spheres<false>, dim3(64, S.n_big), dim3(256), 0, st, S));
         TIMED(K_INTEGRATE_BIG, hipLaunchKernelGGL(k_integrate_big, dim3(S.n_big), dim3(256), 0, st, S));
+        if (S.guard_on) TIMED(K_GUARD_BIG, hipLaunchKernelGGL(k_guard_big, dim3(16, S.n_big), dim3(256), 0, st, S));
     }
     return hipGetLastError();
 }
