@@ -527,7 +527,10 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || S.detect_mode != 2) return;
     __shared__ float P[kMlpParams];
+    __shared__ __align__(16) float Wt[kMlpH * kMlpH];  // second-layer weights, transposed
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) P[i] = S.mlp[i];
+    for (int k = threadIdx.x; k < kMlpH * kMlpH; k += blockDim.x)
+        Wt[(k % kMlpH) * kMlpH + k / kMlpH] = S.mlp[kMlpOffW2 + k];
     __syncthreads();
     const float vg = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
     const float ag = __uint_as_float(c->amax_last);
@@ -538,9 +541,12 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
          r += (int64_t)gridDim.x * blockDim.x) {
         uint32_t occ = S.reg_occ[r];
         if (!occ) continue;
+        // keeps the LDS weights from being hoisted out of the region loop
+        // into registers (they would spill)
+        __asm__ volatile("" ::: "memory");
         float vn = __uint_as_float(S.bin_v[r]), an = __uint_as_float(S.bin_a[r]);
         float y0, y1;
-        mlp_forward(P, vn, an, (float)occ, y0, y1);
+        mlp_forward_t(P, Wt, vn, an, (float)occ, y0, y1);
         float ve = expf(y0), ae = expf(y1);
         if (!(ve < 1e3f) || !(ae < 1e9f) || !(ve >= 0.f) || !(ae >= 0.f)) {  // NaN fails every test
             ve = vg;

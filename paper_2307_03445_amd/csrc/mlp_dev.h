@@ -54,4 +54,41 @@ __device__ __forceinline__ void mlp_forward(const float *P, float f0, float f1, 
     y1 = a1;
 }
 
+// The same forward pass with the second layer's weights transposed (Wt[i][j]
+// = W2[j][i], staged so by the caller): the first layer is evaluated one unit
+// at a time and spread over all 64 accumulators of the second, which keeps
+// the registers at the 64 accumulators.  Every sum is taken in the same order
+// as in mlp_forward, so the results are identical.
+__device__ __forceinline__ void mlp_forward_t(const float *P, const float *Wt, float f0, float f1, float f2, float &y0,
+                                              float &y1) {
+    float x[3];
+    mlp_input(P, f0, f1, f2, x);
+    float z[kMlpH];
+#pragma unroll
+    for (int j = 0; j < kMlpH; j++) z[j] = P[kMlpOffB2 + j];
+#pragma unroll 1
+    for (int i = 0; i < kMlpH; i++) {
+        const float *w = P + kMlpOffW1 + 3 * i;
+        const float h = fmaxf(P[kMlpOffB1 + i] + w[0] * x[0] + w[1] * x[1] + w[2] * x[2], 0.0f);
+        const float4 *wr = (const float4 *)(Wt + kMlpH * i);
+#pragma unroll
+        for (int j4 = 0; j4 < kMlpH / 4; j4++) {
+            const float4 q = wr[j4];
+            z[4 * j4] = fmaf(q.x, h, z[4 * j4]);
+            z[4 * j4 + 1] = fmaf(q.y, h, z[4 * j4 + 1]);
+            z[4 * j4 + 2] = fmaf(q.z, h, z[4 * j4 + 2]);
+            z[4 * j4 + 3] = fmaf(q.w, h, z[4 * j4 + 3]);
+        }
+    }
+    float a0 = P[kMlpOffB3], a1 = P[kMlpOffB3 + 1];
+#pragma unroll
+    for (int j = 0; j < kMlpH; j++) {
+        const float h = fmaxf(z[j], 0.0f);
+        a0 = fmaf(P[kMlpOffW3 + j], h, a0);
+        a1 = fmaf(P[kMlpOffW3 + kMlpH + j], h, a1);
+    }
+    y0 = a0;
+    y1 = a1;
+}
+
 }  // namespace cdem
