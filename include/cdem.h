@@ -283,6 +283,11 @@ typedef struct cdem_kernel_time {
 
 /* on != 0 starts (and clears) per-kernel timing; on == 0 stops it. */
 int cdem_profile(cdem_scene *s, int on);
+/* Starts (and clears) timing of the named kernels only (comma-separated
+ * names as cdem_profile_read reports them; null or "" = every kernel), so
+ * that the events around the other kernels do not slow the steps.  Unknown
+ * names only: CDEM_E_INVALID, timing off. */
+int cdem_profile_kernels(cdem_scene *s, const char *names);
 /* Copies up to cap records into out (host), *n receives the number of kernels. */
 int cdem_profile_read(cdem_scene *s, cdem_kernel_time *out, int cap, int *n);
 /* True contacts (exact predicate, positive overlap) of the last completed

@@ -92,6 +92,7 @@ SIGNATURES = {
     "cdem_read_sphere_pos": (C.c_int, [P, P]),
     "cdem_audit": (C.c_int, [P, P]),
     "cdem_profile": (C.c_int, [P, C.c_int]),
+    "cdem_profile_kernels": (C.c_int, [P, C.c_char_p]),
     "cdem_profile_read": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_int)]),
     "cdem_last_step_contacts": (C.c_int, [P, C.POINTER(C.c_int64)]),
     "cdem_mlp_param_count": (C.c_int, []),
@@ -293,8 +294,12 @@ class Scene:
         return dict(true_contacts=r.true_contacts, missed=r.missed, first=(r.first_a, r.first_b))
 
     # ---------------------------------------------------------------- measurement
-    def profile(self, on: bool = True):
-        self._check(self._L.cdem_profile(self._h, 1 if on else 0))
+    def profile(self, on: bool = True, only=None):
+        """Per-kernel event timing on/off; `only`: names of the kernels to time."""
+        if on and only:
+            self._check(self._L.cdem_profile_kernels(self._h, ",".join(only).encode()))
+        else:
+            self._check(self._L.cdem_profile(self._h, 1 if on else 0))
 
     def profile_read(self) -> dict:
         n = C.c_int(0)

@@ -36,6 +36,8 @@ struct EventTimer : KernelTimer {
     size_t used = 0;            // events in use (two per kernel launch)
     double total_ms[K_COUNT] = {};
     int64_t launches[K_COUNT] = {};
+    bool sel[K_COUNT];          // kernels that are timed
+    EventTimer() { for (int i = 0; i < K_COUNT; i++) sel[i] = true; }
     hipEvent_t next() {
         if (used == pool.size()) {
             hipEvent_t e;
@@ -45,10 +47,12 @@ struct EventTimer : KernelTimer {
         return pool[used++];
     }
     void before(int id, hipStream_t st) override {
+        if (!sel[id]) return;
         hipEvent_t e = next();
         if (e) { (void)hipEventRecord(e, st); ids.push_back(id); } else ids.push_back(-1);
     }
-    void after(int, hipStream_t st) override {
+    void after(int id, hipStream_t st) override {
+        if (!sel[id]) return;
         hipEvent_t e = next();
         if (e) (void)hipEventRecord(e, st);
     }
@@ -1064,6 +1068,31 @@ extern "C" int cdem_profile(cdem_scene *sc, int on) {
     delete sc->timer;
     sc->timer = on ? new (std::nothrow) EventTimer() : nullptr;
     if (on && !sc->timer) return fail(sc, CDEM_E_OOM, "timer");
+    return CDEM_OK;
+}
+
+extern "C" int cdem_profile_kernels(cdem_scene *sc, const char *names) {
+    if (!sc) return CDEM_E_INVALID;
+    int rc = cdem_profile(sc, 1);
+    if (rc || !names || !*names) return rc;
+    bool any = false;
+    for (int i = 0; i < K_COUNT; i++) {
+        sc->timer->sel[i] = false;
+        const size_t len = strlen(kKernelNames[i]);
+        for (const char *p = names; *p;) {
+            const char *q = strchr(p, ',');
+            const size_t l = q ? (size_t)(q - p) : strlen(p);
+            if (l == len && strncmp(p, kKernelNames[i], l) == 0) sc->timer->sel[i] = true;
+            if (!q) break;
+            p = q + 1;
+        }
+        any = any || sc->timer->sel[i];
+    }
+    if (!any) {
+        delete sc->timer;
+        sc->timer = nullptr;
+        return fail(sc, CDEM_E_INVALID, "no kernel of that name");
+    }
     return CDEM_OK;
 }
 

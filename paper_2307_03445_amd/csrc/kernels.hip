@@ -1332,7 +1332,7 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, d
 // adjacent lanes: each lane sums its sphere's row, then the clump's first
 // lane sums its spheres in ascending id by shuffles and integrates the clump.
 template <bool FP32>
-__global__ void __launch_bounds__(256) k_reduce_waves(DevScene S) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))) k_reduce_waves(DevScene S) {
     if (aborted(S.ctl)) return;
     const int lane = threadIdx.x & 63;
     const int64_t w = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
