@@ -97,36 +97,6 @@ __device__ __forceinline__ bool audit_due(const DevScene &S) {
     return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
 }
 
-// Poses of the current state, one lane per sphere, and the speed of each
-// sphere's centre |v_c + w x (x_s - x_c)| where the settings use it (learned
-// envelopes and training data per sphere, the fixed rule's maximum).
-__global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
-    const Ctl *ctl = S.ctl;
-    if (!force && !(due(ctl) || audit_due(S) || ctl->collecting)) return;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool speeds = S.store_speed || ctl->collecting || S.detect_mode != 0;
-    float speed = 0.0f;
-    if (s < S.ns) {
-        const SphereKin k = sphere_kin(S, (uint32_t)s);
-        S.spos[s] = make_double4(k.p[0], k.p[1], k.p[2], k.R);
-        if (speeds) {
-            const double r0 = k.p[0] - k.xc[0], r1 = k.p[1] - k.xc[1], r2 = k.p[2] - k.xc[2];
-            const double u0 = k.v[0] + (k.W[1] * r2 - k.W[2] * r1), u1 = k.v[1] + (k.W[2] * r0 - k.W[0] * r2),
-                         u2 = k.v[2] + (k.W[0] * r1 - k.W[1] * r0);
-            speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
-            if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
-        }
-    }
-    if (S.detect_mode == 0) return;
-    // the global speed maximum (the fixed rule, and the learned rule's
-    // fallback): one filtered atomic per workgroup
-    __shared__ float wmax[4];
-    for (int off = 32; off > 0; off >>= 1) speed = fmaxf(speed, __shfl_xor(speed, off, 64));
-    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = speed;
-    __syncthreads();
-    if (threadIdx.x == 0) raise_max(&S.ctl->vmax_bits, fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
-}
-
 // ---------------------------------------------------------------- boundaries
 // Signed distance of p from boundary b at time t (positive on the domain side)
 // and the unit normal from the wall into the domain.  Returns false where the
@@ -305,8 +275,101 @@ __device__ __forceinline__ uint32_t xcd_block() {
 
 // which = 0: the detection chain; which = 1: the periodic audit's own binning
 // which = 2: training-data capture (always runs when launched)
+// (on a step that also detects, the audit uses the detection's bins: the
+// sorted records then carry the margins, which only widens its prefilter)
 __device__ __forceinline__ bool chain_active(const DevScene &S, int which) {
-    return which == 2 ? true : which ? audit_due(S) : due(S.ctl);
+    return which == 2 ? true : which ? audit_due(S) && S.ctl->since_det != 0 : due(S.ctl);
+}
+
+// Start of a step that bins the spheres (a detection or an audit): clear the
+// bin counters, the region features of the learned margins and the step's
+// detection or audit counters.  k_pose then counts the spheres into the bins.
+__global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
+    const bool det = due(S.ctl), aud = audit_due(S);
+    if (!(det || aud)) return;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < S.n_cells; k += stride) {
+        S.cell_count[k] = 0;
+        S.cell_fill[k] = 0;
+    }
+    if (det && S.detect_mode == 2)
+        for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
+    if (i == 0 && det) {
+        S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_bp = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
+        S.ctl->n_over = 0;
+    }
+    if (i == 0 && aud) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
+}
+
+// Poses of the current state, one lane per sphere, and the speed of each
+// sphere's centre |v_c + w x (x_s - x_c)| where the settings use it (learned
+// envelopes and training data per sphere, the fixed rule's maximum).  On a
+// step that bins the spheres the same pass finds each sphere's bin and counts
+// it, and on a learned detection also collects the region features (maximum
+// speed, maximum acceleration envelope of the spheres' clumps at the last
+// step, sphere count): neighbouring spheres mostly share a region, so the
+// lanes of a wavefront first combine runs of equal region and only each run's
+// first lane updates it.
+__global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
+    const Ctl *ctl = S.ctl;
+    const bool det = due(ctl), aud = audit_due(S);
+    if (!force && !(det || aud || ctl->collecting)) return;
+    const bool bin = !force && (det || aud);
+    const bool feat = bin && det && S.detect_mode == 2;
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const bool speeds = S.store_speed || ctl->collecting || S.detect_mode != 0;
+    float speed = 0.0f, acc = 0.0f;
+    int64_t r = -1;
+    if (s < S.ns) {
+        const uint32_t c = S.owner[s], ts = S.sts[s];
+        const SphereKin k = sphere_kin_of(S, c, ts);
+        S.spos[s] = make_double4(k.p[0], k.p[1], k.p[2], k.R);
+        if (speeds) {
+            const double r0 = k.p[0] - k.xc[0], r1 = k.p[1] - k.xc[1], r2 = k.p[2] - k.xc[2];
+            const double u0 = k.v[0] + (k.W[1] * r2 - k.W[2] * r1), u1 = k.v[1] + (k.W[2] * r0 - k.W[0] * r2),
+                         u2 = k.v[2] + (k.W[0] * r1 - k.W[1] * r0);
+            speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+            if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
+        }
+        if (bin) {
+            const Grid &g = S.grids[S.sscene[s]];
+            int ix, iy, iz;
+            cell_coords(g, k.p[0], k.p[1], k.p[2], ix, iy, iz);
+            const uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
+            S.cell_of[s] = cell;
+            atomicAdd(&S.cell_count[cell], 1u);
+            if (feat) { r = region_of(g, cell); acc = S.cacc[c]; }
+        }
+    }
+    if (feat) {
+        float v = speed, a = acc;
+        const int rl = (int)r, rh = (int)(r >> 32);
+        const int pl = __shfl_up(rl, 1, 64), ph = __shfl_up(rh, 1, 64);
+        const bool head = lane == 0 || pl != rl || ph != rh;
+        const unsigned long long heads = __ballot(head);
+        for (int off = 1; off < 64; off <<= 1) {  // run maxima, from the lanes further down the run
+            const int ol = __shfl_down(rl, off, 64), oh = __shfl_down(rh, off, 64);
+            const float ov = __shfl_down(v, off, 64), oa = __shfl_down(a, off, 64);
+            if (lane + off < 64 && ol == rl && oh == rh) { v = fmaxf(v, ov); a = fmaxf(a, oa); }
+        }
+        if (head && r >= 0) {
+            const unsigned long long later = lane < 63 ? heads >> (lane + 1) : 0ull;
+            const int next = later ? lane + 1 + __builtin_ctzll(later) : 64;
+            if (v > 0.f) atomicMax(&S.bin_v[r], __float_as_uint(v));
+            if (a > 0.f) atomicMax(&S.bin_a[r], __float_as_uint(a));
+            atomicAdd(&S.reg_occ[r], (uint32_t)(next - lane));
+        }
+    }
+    if (S.detect_mode == 0) return;
+    // the global speed maximum (the fixed rule, and the learned rule's
+    // fallback): one filtered atomic per workgroup
+    __shared__ float wmax[4];
+    for (int off = 32; off > 0; off >>= 1) speed = fmaxf(speed, __shfl_xor(speed, off, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = speed;
+    __syncthreads();
+    if (threadIdx.x == 0) raise_max(&S.ctl->vmax_bits, fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3])));
 }
 
 __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
@@ -1796,7 +1859,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
-                                           "k_narrow_over", "k_region_margin", "k_guard_big"};
+                                           "k_narrow_over", "k_region_margin", "k_guard_big", "k_bins_begin"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -1815,18 +1878,28 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force) {
     if (S.ns == 0) return hipSuccess;
+    if (!force) {
+        unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
+        TIMED(K_BINS_BEGIN, hipLaunchKernelGGL(k_bins_begin, dim3(zb), dim3(256), 0, st, S));
+    }
     TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, force ? 1 : 0));
     return hipGetLastError();
 }
 
-// Bin every sphere of the current positions: zero, count, scan, scatter.
+// Bin every sphere of the current positions.  In a step (which = 0: the
+// detection, 1: the audit) the bins were cleared and counted by k_bins_begin
+// and k_pose: scan and scatter (a detection first turns the learned region
+// features into margins).  Training-data capture (which = 2) needs the bin
+// counts and the features only: clear, count, features.
 static void binning(const DevScene &S, int which, hipStream_t st) {
-    unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
-    TIMED(K_DETECT_BEGIN, hipLaunchKernelGGL(k_detect_begin, dim3(zb), dim3(256), 0, st, S, which));
-    TIMED(K_CELL_COUNT, hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
-    if (which == 2 || (which == 0 && S.detect_mode == 2)) {
+    if (which == 2) {
+        unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
+        TIMED(K_DETECT_BEGIN, hipLaunchKernelGGL(k_detect_begin, dim3(zb), dim3(256), 0, st, S, which));
+        TIMED(K_CELL_COUNT, hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
         TIMED(K_BIN_FEATURES, hipLaunchKernelGGL(k_bin_features, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, which));
-        if (which == 2) return;  // capture needs bins and features only
+        return;
+    }
+    if (which == 0 && S.detect_mode == 2) {
         TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
         TIMED(K_REGION_MARGIN, hipLaunchKernelGGL(k_region_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
     }
