@@ -51,8 +51,9 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     mat = 16 if st["fp32"] else 32
     guard, learned = st["guard"], st.get("learned", False)
     if kernel == "k_pose":
-        # per sphere: owner, template sphere, position write (+ speed); per clump its record
-        return ns * (8 + 32 + (4 if guard else 0)) + nc * 128
+        # per sphere: owner, template sphere, position write (+ speed), scene
+        # and bin write (the count's atomic); per clump its record
+        return ns * (8 + 32 + (4 if guard else 0) + 8) + nc * 128
     if kernel == "k_cell_count":
         return ns * 48
     if kernel == "k_cell_scatter":
