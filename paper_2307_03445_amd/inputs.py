@@ -835,3 +835,102 @@ def extract_scene(batch: SceneDesc, k: int) -> SceneDesc:
         bnd_omega=batch.bnd_omega[bsel], bnd_scene=np.zeros(len(bsel), np.int32),
         presc_clump=np.zeros(0, np.int32), presc_param=np.zeros((0, PRESC_NPARAM)), name=f"{batch.name}-s{k}")
     return d.canonical()
+
+
+# ---------------------------------------------------------------------------
+# Long-run statistics: a settled box (packing fraction) and a collapsed
+# column (heap angle), in the materials and clumps of configuration 1
+# ---------------------------------------------------------------------------
+
+STATS_H = 1e-5  # time step of the statistics runs (about 40 steps per contact at these stiffnesses)
+
+
+def stats_scene(kind: str, replica: int = 0, n_clumps: int = 120, res: int = 16) -> SceneDesc:
+    """One seeded scene of the long-run statistics.
+
+    ``kind="box"``: clumps on a simple-cubic lattice in a 3 cm x 3 cm box
+    (floor and four walls), velocity noise U[-0.05, 0.05] m/s per component;
+    they fall and settle into a bed.  ``kind="heap"``: the same kind of clumps
+    at rest in a column six sites wide against the back wall of a slot one
+    site deep (a quasi-two-dimensional dam break); the column collapses onto
+    the floor, open towards +x, and leaves a slope.  Configuration-1 clumps (three spheres of one
+    radius in U[1, 2] mm, centres 0.6 r off the centre) and materials
+    (E = 1e7 Pa, nu = 0.3, mu = 0.5, CoR = 0.5), gravity -9.81 z, h = 1e-5 s."""
+    if kind not in ("box", "heap"):
+        raise ValueError("kind is 'box' or 'heap'")
+    g = rng(6 if kind == "box" else 7, replica)
+    tmpls = _cfg1_templates(g, n_clumps, res)
+    rb = max(bounding_radius(t[0], t[1]) for t in tmpls)
+    spacing = 2.0 * rb + 1e-4
+    mat = np.tile(np.array(CFG1_MAT), (3 * n_clumps, 1))
+    if kind == "box":
+        L = 0.03
+        nxy = int(L // spacing)
+        nz = -(-n_clumps // (nxy * nxy))
+        origin = (L / 2 - spacing * (nxy - 1) / 2, L / 2 - spacing * (nxy - 1) / 2, spacing / 2 + 5e-5)
+        sites = lattice_sites(nxy, nxy, nz, spacing, origin)
+        x = sites[g.permutation(sites.shape[0])[:n_clumps]]
+        v = g.uniform(-0.05, 0.05, (n_clumps, 3))
+        top = nz * spacing + 0.01
+        bnd = box_walls((0, 0, 0), (L, L, top), CFG1_MAT)
+        dom = (0, 0, 0, L, L, top)
+    else:
+        # a column against the back wall x = 0 of a slot one site deep
+        # (walls y = 0 and y = W), open towards +x over the floor
+        nx_ = 6
+        nz = -(-n_clumps // nx_)
+        W = spacing + 2e-4
+        origin = (spacing / 2 + 5e-5, W / 2, spacing / 2 + 5e-5)
+        x = lattice_sites(nx_, 1, nz, spacing, origin)[:n_clumps]
+        v = np.zeros((n_clumps, 3))
+        top = nz * spacing + 0.01
+        Lx = 0.15
+        bnd = [dict(type=BND_PLANE, param=(0, 0, 0, 0, 0, 1), mat=CFG1_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, 0, 0, 1, 0, 0), mat=CFG1_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, 0, 0, 0, 1, 0), mat=CFG1_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, W, 0, 0, -1, 0), mat=CFG1_MAT, scene=0)]
+        dom = (0, 0, 0, Lx, W, top)
+    q = random_unit_quaternions(g, n_clumps)
+    w = np.zeros((n_clumps, 3))
+    return assemble(tmpls, np.arange(n_clumps), x, q, v, w, mat, (0, 0, -9.81), dom, STATS_H, bnd=bnd,
+                    name=f"stats-{kind}-r{replica}")
+
+
+def batch(descs) -> SceneDesc:
+    """Independent scenes as one batched description (scene k = descs[k]);
+    every input is copied, nothing is computed."""
+    descs = [d.canonical() for d in descs]
+    if len({d.h for d in descs}) != 1:
+        raise ValueError("batched scenes share the time step")
+    nts = np.cumsum([0] + [d.n_templates for d in descs])
+    begin = [np.zeros(1, np.uint32)]
+    off = 0
+    for d in descs:
+        begin.append(d.tmpl_sphere_begin[1:].astype(np.int64) + off)
+        off += int(d.tmpl_sphere_begin[-1])
+    cs, bs = [], []
+    for k, d in enumerate(descs):
+        if d.n_scenes != 1:
+            raise ValueError("batch takes single-scene descriptions")
+        cs.append(np.full(d.n_clumps, k, np.uint32))
+        bs.append(np.full(d.n_bnd, k, np.int32))
+    out = SceneDesc(
+        h=descs[0].h,
+        tmpl_sphere_begin=np.concatenate(begin).astype(np.uint32),
+        tmpl_offset=np.concatenate([d.tmpl_offset for d in descs]),
+        tmpl_radius=np.concatenate([d.tmpl_radius for d in descs]),
+        tmpl_mass=np.concatenate([d.tmpl_mass for d in descs]),
+        tmpl_inertia=np.concatenate([d.tmpl_inertia for d in descs]),
+        clump_template=np.concatenate([d.clump_template.astype(np.int64) + nts[k] for k, d in enumerate(descs)]),
+        clump_scene=np.concatenate(cs),
+        x=np.concatenate([d.x for d in descs]), q=np.concatenate([d.q for d in descs]),
+        v=np.concatenate([d.v for d in descs]), w=np.concatenate([d.w for d in descs]),
+        sphere_mat=np.concatenate([d.sphere_mat for d in descs]),
+        gravity=np.concatenate([d.gravity for d in descs]), domain=np.concatenate([d.domain for d in descs]),
+        bnd_type=np.concatenate([d.bnd_type for d in descs]), bnd_param=np.concatenate([d.bnd_param for d in descs]),
+        bnd_mat=np.concatenate([d.bnd_mat for d in descs]), bnd_vel=np.concatenate([d.bnd_vel for d in descs]),
+        bnd_omega=np.concatenate([d.bnd_omega for d in descs]), bnd_scene=np.concatenate(bs),
+        name="batch-" + "+".join(d.name for d in descs))
+    if any(d.presc_clump.size for d in descs):
+        raise ValueError("batch takes scenes without prescribed clumps")
+    return out.canonical()
