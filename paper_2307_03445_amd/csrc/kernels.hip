@@ -719,11 +719,29 @@ __device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid 
 
 // The conservative FP32 test of sorted slot j: it can only admit extra
 // candidates, which the exact FP64 predicate then rejects.
-__device__ __forceinline__ bool narrow_prefilter(const DevScene &S, const Grid &g, const NarrowSelf &n, uint32_t j) {
-    const float4 Qf = S.sorted_f4[j];
+__device__ __forceinline__ bool narrow_prefilter_rec(const Grid &g, const NarrowSelf &n, float4 Qf) {
     const float fx = Qf.x - n.Pf.x, fy = Qf.y - n.Pf.y, fz = Qf.z - n.Pf.z;
     const float fr = (n.Pf.w + Qf.w) + g.pre_eps;
     return n.exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
+}
+__device__ __forceinline__ bool narrow_prefilter(const DevScene &S, const Grid &g, const NarrowSelf &n, uint32_t j) {
+    return narrow_prefilter_rec(g, n, S.sorted_f4[j]);
+}
+
+// Visit the slots [jb, je) four at a time, the four records loaded before
+// any is tested (more loads in flight per lane); f(j, passed) in slot order.
+constexpr uint32_t kSlotBatch = 4;
+template <typename T, typename F>
+__device__ __forceinline__ void slot_batches(const float4 *rec, uint32_t jb, uint32_t je, T &&test, F &&f) {
+    for (uint32_t j = jb; j < je; j += kSlotBatch) {
+        float4 q[kSlotBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kSlotBatch; u++)
+            if (j + u < je) q[u] = rec[j + u];
+#pragma unroll
+        for (uint32_t u = 0; u < kSlotBatch; u++)
+            if (j + u < je && test(q[u])) f(j + u);
+    }
 }
 
 // The exact predicate of the enlarged geometry for slot j (another clump,
@@ -832,11 +850,11 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         int npre = 0;
         if (!n.exact_only)
             scan_reach32(S, g, n.Pf.x, n.Pf.y, n.Pf.z, (float)n.reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
-                for (uint32_t j = jb; j < je; j++) {
-                    if (!narrow_prefilter(S, g, n, j)) continue;
-                    if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
-                    npre++;
-                }
+                slot_batches(S.sorted_f4, jb, je, [&](float4 q) { return narrow_prefilter_rec(g, n, q); },
+                             [&](uint32_t j) {
+                                 if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
+                                 npre++;
+                             });
             });
         if (!n.exact_only && npre <= kMaxRow) {
             // an insert writes at most at the position of the slot just read
@@ -1744,11 +1762,13 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         int npre = 0;
         if (!exact_only)
             scan_reach32(S, g, Pf.x, Pf.y, Pf.z, (float)reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
-                for (uint32_t j = jb; j < je; j++) {
-                    if (!prefilter(j)) continue;
+                slot_batches(S.sorted_f4, jb, je, [&](float4 Qf) {
+                    const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+                    return fx * fx + fy * fy + fz * fz < fr * fr;
+                }, [&](uint32_t j) {
                     if (npre < kMaxRow) alst[npre * 256 + threadIdx.x] = j;
                     npre++;
-                }
+                });
             });
         if (!exact_only && npre <= kMaxRow) {
             for (int k = 0; k < npre; k++) exact(alst[k * 256 + threadIdx.x]);

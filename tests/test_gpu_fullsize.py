@@ -109,3 +109,28 @@ def test_learned_reproduces_plain_bitwise_at_full_size(bed, mlp):
         assert np.array_equal(sp[k], sl[k]), k
     assert cl["missed"] == 0 and cl["audits"] >= 2
     assert cl["detections"] < cp["detections"] // 4
+
+
+def test_learned_gains_over_the_fixed_rule(bed, mlp):
+    """What the trained network gains over the method without it: at the same
+    interval bound, margin cap and audits, the learned per-region margins keep
+    fewer candidate pairs in the active set than the fixed rule's global
+    margin (fewer false positives for the force kernel to evaluate), with the
+    same trajectory and no missed contact.  This bed starts at rest, so over
+    its first 101 steps the fixed rule's global speed is still low and the gain
+    is a few per cent; on the benchmark's settled bed with the wheel moving it
+    is about a fifth of the candidates (the benchmark reports both modes)."""
+    steps = 101
+    out = {}
+    for mode in ("fixed", "learned"):
+        sc = bench.make_scene(bed, mode, mlp)
+        sc.step(steps)
+        out[mode] = (sc.state(), sc.counts())
+        sc.close()
+        print(mode, out[mode][1], flush=True)
+    (sf, cf), (sl, cl) = out["fixed"], out["learned"]
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(sf[k], sl[k]), k
+    assert cf["missed"] == 0 and cl["missed"] == 0
+    assert cl["candidates"] < cf["candidates"], (cl["candidates"], cf["candidates"])
+    assert cl["detections"] <= cf["detections"] + 1
