@@ -279,12 +279,12 @@ static int build_grids(cdem_scene *sc) {
     if (cell0 > sc->n_cells_alloc) {
         dev_free(sc, S.cell_count);
         dev_free(sc, S.cell_start);
-        dev_free(sc, S.cell_fill);
+        dev_free(sc, S.scan_bsum);
         int64_t nblk = (cell0 + 1023) / 1024 + 1;
         S.cell_count = (uint32_t *)dev_alloc(sc, cell0 * 4);
         S.cell_start = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.cell_fill = (uint32_t *)dev_alloc(sc, (cell0 + nblk) * 4);  // + scan block sums
-        if (!S.cell_count || !S.cell_start || !S.cell_fill) return fail(sc, CDEM_E_OOM, "bin arrays");
+        S.scan_bsum = (uint32_t *)dev_alloc(sc, nblk * 4);
+        if (!S.cell_count || !S.cell_start || !S.scan_bsum) return fail(sc, CDEM_E_OOM, "bin arrays");
         sc->n_cells_alloc = cell0;
     }
     if (reg0 > sc->n_regions_alloc) {
@@ -601,6 +601,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.cdet = (double4 *)dev_alloc(sc, 2 * sizeof(double4) * std::max<int64_t>(nc, 1));
     S.smargin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cell_of = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.cell_rank = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_id = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
@@ -624,7 +625,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     }
     S.up_beg = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.up_cnt = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    if (!S.cdet || !S.spos || !S.smargin || !S.cell_of || !S.sorted_id || !S.sorted_owner ||
+    if (!S.cdet || !S.spos || !S.smargin || !S.cell_of || !S.cell_rank || !S.sorted_id || !S.sorted_owner ||
         !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.lo_beg[0] || !S.lo_beg[1] ||
         !S.lo_cnt[0] || !S.lo_cnt[1] || !S.up_beg || !S.up_cnt)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));

@@ -117,7 +117,9 @@ struct DevScene {
     double *sF, *sT;                 // [ns][3] per-sphere sums (big clumps only)
     // binning
     const Grid *grids;
-    uint32_t *cell_of, *cell_count, *cell_start, *cell_fill;
+    uint32_t *cell_of, *cell_count, *cell_start;
+    uint32_t *scan_bsum;             // block sums of the bin-count scan
+    uint32_t *cell_rank;             // [ns] each sphere's rank within its bin, taken when counting
     uint32_t *sorted_id, *sorted_owner;
     double4 *sorted_pos;
     float *sorted_margin;

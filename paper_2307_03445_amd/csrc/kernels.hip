@@ -291,7 +291,6 @@ __global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = i; k < S.n_cells; k += stride) {
         S.cell_count[k] = 0;
-        S.cell_fill[k] = 0;
     }
     if (det && S.detect_mode == 2)
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
@@ -339,7 +338,7 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
             cell_coords(g, k.p[0], k.p[1], k.p[2], ix, iy, iz);
             const uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
             S.cell_of[s] = cell;
-            atomicAdd(&S.cell_count[cell], 1u);
+            S.cell_rank[s] = atomicAdd(&S.cell_count[cell], 1u);
             if (feat) { r = region_of(g, cell); acc = S.cacc[c]; }
         }
     }
@@ -379,7 +378,6 @@ __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
     const bool bins = which == 2 || (which == 0 && S.detect_mode == 2);
     for (int64_t k = i; k < S.n_cells; k += stride) {
         S.cell_count[k] = 0;
-        S.cell_fill[k] = 0;
     }
     if (bins)
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
@@ -400,7 +398,7 @@ __global__ void __launch_bounds__(256) k_cell_count(DevScene S, int which) {
     cell_coords(g, p.x, p.y, p.z, ix, iy, iz);
     uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
     S.cell_of[s] = cell;
-    atomicAdd(&S.cell_count[cell], 1u);
+    S.cell_rank[s] = atomicAdd(&S.cell_count[cell], 1u);
 }
 
 // Exclusive scan of cell_count -> cell_start in three passes (1024 bins per block).
@@ -497,7 +495,7 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S.ns) return;
     uint32_t cell = S.cell_of[s];
-    uint32_t slot = S.cell_start[cell] + atomicAdd(&S.cell_fill[cell], 1u);
+    uint32_t slot = S.cell_start[cell] + S.cell_rank[s];  // its rank within the bin, from the count
     double4 p = S.spos[s];
     S.sorted_id[slot] = (uint32_t)s;
     S.sorted_owner[slot] = S.owner[s];
@@ -755,6 +753,20 @@ __device__ __forceinline__ uint32_t narrow_exact(const DevScene &S, const Narrow
     Sr = Sr + ((double)n.ms + (double)S.sorted_margin[j]);
     return d2 < Sr * Sr ? S.sorted_id[j] : ~0u;
 }
+// The same test with the slot's record loaded beforehand (so that the loads
+// of several slots are in flight together).
+struct SlotRec { double4 Q; uint32_t own, id; float m; };
+__device__ __forceinline__ SlotRec load_slot(const DevScene &S, uint32_t j) {
+    return SlotRec{S.sorted_pos[j], S.sorted_owner[j], S.sorted_id[j], S.sorted_margin[j]};
+}
+__device__ __forceinline__ uint32_t narrow_exact_rec(const NarrowSelf &n, const SlotRec &r) {
+    if (r.own == n.own) return ~0u;
+    const double dx = r.Q.x - n.P.x, dy = r.Q.y - n.P.y, dz = r.Q.z - n.P.z;
+    const double d2 = dx * dx + dy * dy + dz * dz;
+    double Sr = n.P.w + r.Q.w;
+    Sr = Sr + ((double)n.ms + (double)r.m);
+    return d2 < Sr * Sr ? r.id : ~0u;
+}
 
 // Boundary candidates of sphere s: phi < R_s + (m_s + boundary margin).
 template <class Emit>
@@ -857,10 +869,19 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
                              });
             });
         if (!n.exact_only && npre <= kMaxRow) {
-            // an insert writes at most at the position of the slot just read
-            for (int k = 0; k < npre; k++) {
-                const uint32_t t = narrow_exact(S, n, lst[k * kNarrowBlock + tid]);
-                if (t != ~0u) emit(t);
+            // two listed slots per round, both read before either is inserted:
+            // an insert writes at most at the position of the later slot read
+            for (int k = 0; k < npre; k += 2) {
+                const bool two = k + 1 < npre;
+                const uint32_t j0 = lst[k * kNarrowBlock + tid];
+                const uint32_t j1 = two ? lst[(k + 1) * kNarrowBlock + tid] : j0;
+                const SlotRec r0 = load_slot(S, j0), r1 = load_slot(S, j1);
+                const uint32_t t0 = narrow_exact_rec(n, r0);
+                if (t0 != ~0u) emit(t0);
+                if (two) {
+                    const uint32_t t1 = narrow_exact_rec(n, r1);
+                    if (t1 != ~0u) emit(t1);
+                }
             }
             narrow_boundaries(S, g, n, emit);
         } else {
@@ -1771,7 +1792,23 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
                 });
             });
         if (!exact_only && npre <= kMaxRow) {
-            for (int k = 0; k < npre; k++) exact(alst[k * 256 + threadIdx.x]);
+            // two listed slots per round, their records loaded together
+            for (int k = 0; k < npre; k += 2) {
+                const bool two = k + 1 < npre;
+                const uint32_t j0 = alst[k * 256 + threadIdx.x], j1 = two ? alst[(k + 1) * 256 + threadIdx.x] : j0;
+                const uint32_t o0 = S.sorted_owner[j0], o1 = S.sorted_owner[j1];
+                const double4 Q0 = S.sorted_pos[j0], Q1 = S.sorted_pos[j1];
+                const uint32_t i0 = S.sorted_id[j0], i1 = S.sorted_id[j1];
+                for (int u = 0; u < (two ? 2 : 1); u++) {
+                    const uint32_t o = u ? o1 : o0, id = u ? i1 : i0;
+                    const double4 Q = u ? Q1 : Q0;
+                    if (o == own) continue;
+                    const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                    const double d2 = dx * dx + dy * dy + dz * dz;
+                    const double Sr = P.w + Q.w;
+                    if (d2 < Sr * Sr) { found++; if (!in_row(id)) missed++; }
+                }
+            }
         } else {
             scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
                 for (uint32_t j = jb; j < je; j++)
@@ -1924,8 +1961,7 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
         TIMED(K_REGION_MARGIN, hipLaunchKernelGGL(k_region_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
     }
     int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
-    // the block-sum scratch lives after the cell arrays (allocated by the runtime)
-    uint32_t *bsum = S.cell_fill + S.n_cells;
+    uint32_t *bsum = S.scan_bsum;
     TIMED(K_SCAN_REDUCE, hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S, bsum, which));
     TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBsumBlock), 0, st, S, bsum, nblk, which));
     TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S,
