@@ -282,7 +282,7 @@ static int build_grids(cdem_scene *sc) {
         dev_free(sc, S.scan_bsum);
         int64_t nblk = (cell0 + 1023) / 1024 + 1;
         S.cell_count = (uint32_t *)dev_alloc(sc, cell0 * 4);
-        S.cell_start = (uint32_t *)dev_alloc(sc, cell0 * 4);
+        S.cell_start = (uint32_t *)dev_alloc(sc, (cell0 + 1) * 4);  // + the end of the last bin
         S.scan_bsum = (uint32_t *)dev_alloc(sc, nblk * 4);
         if (!S.cell_count || !S.cell_start || !S.scan_bsum) return fail(sc, CDEM_E_OOM, "bin arrays");
         sc->n_cells_alloc = cell0;

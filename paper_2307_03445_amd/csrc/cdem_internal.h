@@ -117,7 +117,8 @@ struct DevScene {
     double *sF, *sT;                 // [ns][3] per-sphere sums (big clumps only)
     // binning
     const Grid *grids;
-    uint32_t *cell_of, *cell_count, *cell_start;
+    uint32_t *cell_of, *cell_count;
+    uint32_t *cell_start;            // [n_cells + 1] exclusive scan of the counts, then the total
     uint32_t *scan_bsum;             // block sums of the bin-count scan
     uint32_t *cell_rank;             // [ns] each sphere's rank within its bin, taken when counting
     uint32_t *sorted_id, *sorted_owner;

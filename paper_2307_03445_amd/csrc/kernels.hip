@@ -207,7 +207,7 @@ __device__ __forceinline__ void scan_reach(const DevScene &S, const Grid &g, dou
             int x0 = clamp_cell((px - rx - g.ox) * g.inv, g.nx), x1 = clamp_cell((px + rx - g.ox) * g.inv, g.nx);
             int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
             uint32_t jb = S.cell_start[rowc + x0];
-            uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+            uint32_t je = S.cell_start[rowc + x1 + 1];
             f(jb, je);
         }
     }
@@ -246,7 +246,7 @@ __device__ __forceinline__ void scan_reach32(const DevScene &S, const Grid &g, f
             const int x0 = clamp_cell32((px - rx) * inv, g.nx), x1 = clamp_cell32((px + rx) * inv, g.nx);
             const int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
             const uint32_t jb = S.cell_start[rowc + x0];
-            const uint32_t je = S.cell_start[rowc + x1] + S.cell_count[rowc + x1];
+            const uint32_t je = S.cell_start[rowc + x1 + 1];  // the next bin's start
             f(jb, je);
         }
     }
@@ -484,6 +484,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_final(DevScene S, const uin
     for (int k = 0; k < kScanItems; k++) {
         if (base + k < S.n_cells) S.cell_start[base + k] = ex;
         ex += loc[k];
+        if (base + k == S.n_cells - 1) S.cell_start[S.n_cells] = ex;  // the end of the last bin
     }
 }
 

@@ -323,3 +323,24 @@ def test_boundary_forces(dense, prec):
     ef = np.linalg.norm(Fg - Fo, axis=1) / np.maximum(mag, 1e-300)
     et = np.linalg.norm(Tg - To, axis=1) / np.maximum(mag * lever, 1e-300)
     assert ef.max() <= tol and et.max() <= tol, (ef, et)
+
+
+@gpu
+def test_profile_selected_kernels_only(dense):
+    """Per-kernel timing of named kernels only (what the benchmark's timed
+    region uses) records just those; unknown names are refused; timing never
+    changes results."""
+    from paper_2307_03445_amd._lib import CdemError
+    a, b = _scene(dense, "fp32"), _scene(dense, "fp32")
+    a.profile(True, only=("k_pairs", "k_reduce_waves"))
+    a.step(5)
+    prof = a.profile_read()
+    assert set(prof) == {"k_pairs", "k_reduce_waves"}, prof
+    assert all(n == 5 and ms > 0 for n, ms in prof.values()), prof
+    with pytest.raises(CdemError):
+        a.profile(True, only=("no_such_kernel",))
+    b.step(5)
+    sa, sb = a.state(), b.state()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    a.close(); b.close()
