@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(DevScene S, uint32_t
 }
 
 // Exclusive scan of the block sums in place: one workgroup of 1024 lanes,
-// eight consecutive sums per lane per round.
+// eight consecutive sums per lane per pass.
 constexpr int kBsumBlock = 1024, kBsumItems = 8;
 __global__ void __launch_bounds__(kBsumBlock) k_scan_bsum(DevScene S, uint32_t *bsum, int64_t nblk, int which) {
     if (!chain_active(S, which)) return;
@@ -465,7 +465,7 @@ __global__ void __launch_bounds__(kBsumBlock) k_scan_bsum(DevScene S, uint32_t *
             ex += loc[k];
         }
         carry += tot;
-        __syncthreads();  // wt is rewritten by the next round
+        __syncthreads();  // wt is rewritten by the next pass
     }
 }
 
@@ -870,7 +870,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
                              });
             });
         if (!n.exact_only && npre <= kMaxRow) {
-            // two listed slots per round, both read before either is inserted:
+            // two listed slots at a time, both read before either is inserted:
             // an insert writes at most at the position of the later slot read
             for (int k = 0; k < npre; k += 2) {
                 const bool two = k + 1 < npre;
@@ -1793,7 +1793,7 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
                 });
             });
         if (!exact_only && npre <= kMaxRow) {
-            // two listed slots per round, their records loaded together
+            // two listed slots at a time, their records loaded together
             for (int k = 0; k < npre; k += 2) {
                 const bool two = k + 1 < npre;
                 const uint32_t j0 = alst[k * 256 + threadIdx.x], j1 = two ? alst[(k + 1) * 256 + threadIdx.x] : j0;
