@@ -102,7 +102,12 @@ def run_path(desc, mode, steps, warmup, mlp=None):
     sc = make_scene(desc, mode, mlp)
     t0 = time.perf_counter()
     sc.step(warmup)
-    log(f"[{mode}] warmup {warmup} steps: {time.perf_counter() - t0:.2f} s")
+    # bin size and launch shape from the library's autotuner (its trials are
+    # ordinary steps, each of one detection and the steps up to the next at
+    # the interval bound), then steps to settle before timing
+    tune = sc.autotune(DETECT["k_max"])
+    sc.step(warmup)
+    log(f"[{mode}] warmup {2 * warmup} steps and autotuning ({tune}): {time.perf_counter() - t0:.2f} s")
     c0 = sc.counts()
     # Inside the timed region only the kernel the roofline is quoted for is
     # bracketed by events (events around every kernel cost about 5 % of a
@@ -142,7 +147,7 @@ def run_path(desc, mode, steps, warmup, mlp=None):
     for k, (n, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         log(f"    {k:22s} launches {n:6d} total {ms:9.2f} ms  avg {ms / n * 1e3:9.1f} us")
     return dict(seconds=dt, prof=prof, prof_timed=prof_timed, counts=c1, detections=dets,
-                contact_sides=contact_sides, guard_trips=c1["guard_trips"] - c0["guard_trips"])
+                contact_sides=contact_sides, guard_trips=c1["guard_trips"] - c0["guard_trips"], tune=tune)
 
 
 KERNEL_SOURCES = ("paper_2307_03445_amd/csrc/kernels.hip", "paper_2307_03445_amd/csrc/cdem_internal.h",
@@ -310,7 +315,8 @@ def main():
         "paths": {m: {"sphere_steps_per_s": desc.n_spheres * args.steps / v["seconds"],
                       "ms_per_step": v["seconds"] / args.steps * 1e3, "detections": v["detections"],
                       "guard_trips": v["guard_trips"], "candidates": v["counts"]["candidates"],
-                      "contact_sides": v["contact_sides"], "missed": v["counts"]["missed"]}
+                      "contact_sides": v["contact_sides"], "missed": v["counts"]["missed"],
+                      "autotune": v["tune"]}
                   for m, v in results.items()},
         "envelope_mlp": mlp_info,
         "roofline": roofline(r, stats, main_mode),
