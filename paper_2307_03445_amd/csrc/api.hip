@@ -1220,8 +1220,8 @@ extern "C" int cdem_set_graph(cdem_scene *sc, int32_t steps_per_graph) {
 
 extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, int32_t *stride_cap) {
     if (!sc || steps < 1) return fail(sc, CDEM_E_INVALID, "bad arguments");
-    const double factors[] = {1.0, 1.25, 1.5};
-    const int32_t caps[] = {2048, 8192, 16384};
+    const double factors[] = {1.0, 1.25, 1.5, 1.75};
+    const int32_t caps[] = {2048, 4096, 8192, 16384};
     double best = 1e300, bf = sc->bin_factor;
     int32_t bc = sc->S.stride_cap;
     int rc = cdem_step(sc, 1, nullptr);  // settle allocations before timing
