@@ -1,7 +1,7 @@
 """Throughput of the clumped-sphere DEM timestep on one MI355X.
 
 Workload (default): the rover-scale bed, ~11M clumps / ~34M spheres of the
-eight configuration-2 templates tiled from a patch settled on the GPU, with a
+eight bed templates tiled from a patch settled on the GPU, with a
 20,000-sphere wheel driven at slip 0.2; FP32 force arithmetic, FP64 state and
 history.  One step = pose, detection (every step in plain mode, when due in
 deferred modes), Hertz-Mindlin force with tangential history, reduction onto
@@ -50,6 +50,7 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     v = 16 if st["fp32"] else 32
     mat = 16 if st["fp32"] else 32
     guard, learned = st["guard"], st.get("learned", False)
+    det_frac = st.get("detect_fraction", 1.0)  # share of the launches on a step with a detection
     if kernel == "k_pose":
         # per sphere: owner, template sphere, position write (+ speed), scene
         # and bin write (the count's atomic); per clump its record
@@ -73,10 +74,11 @@ def algorithmic_bytes(kernel: str, st: dict) -> float:
     if kernel == "k_reduce_waves":
         # per upper entry: link, the pair's force and the partner's torque; per
         # pair: force and torque of the lower sphere; per sphere: clump position
-        # and segment bounds (+ margin for the guard); per clump: record read
-        # and write, template, scene, prescribed-motion index (+ its pose at the
-        # last detection for the guard, + acceleration envelope when learned)
-        return (U * (4 + 2 * v) + P * 2 * v + ns * (20 + (4 if guard else 0)) +
+        # and segment bounds (+ margin for the guard on a detection's step:
+        # later steps test a per-clump bound first); per clump: record read and
+        # write, template, scene, prescribed-motion index (+ its pose at the last
+        # detection for the guard, + acceleration envelope when learned)
+        return (U * (4 + 2 * v) + P * 2 * v + ns * (20 + (4 * det_frac if guard else 0)) +
                 nc * (268 + (64 if guard else 0) + (4 if learned else 0)))
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)
@@ -147,7 +149,8 @@ def run_path(desc, mode, steps, warmup, mlp=None):
     for k, (n, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
         log(f"    {k:22s} launches {n:6d} total {ms:9.2f} ms  avg {ms / n * 1e3:9.1f} us")
     return dict(seconds=dt, prof=prof, prof_timed=prof_timed, counts=c1, detections=dets,
-                contact_sides=contact_sides, guard_trips=c1["guard_trips"] - c0["guard_trips"], tune=tune)
+                contact_sides=contact_sides, guard_trips=c1["guard_trips"] - c0["guard_trips"], tune=tune,
+                steps=steps)
 
 
 KERNEL_SOURCES = ("paper_2307_03445_amd/csrc/kernels.hip", "paper_2307_03445_amd/csrc/cdem_internal.h",
@@ -190,7 +193,8 @@ def roofline(res, desc_stats, mode):
         n, ms = res["prof_timed"][k]
     cnt = res["counts"]
     st = dict(desc_stats, pairs=cnt["pairs"], upper=cnt["candidates"] - cnt["pairs"],
-              contact_sides=res["contact_sides"], guard=(mode != "plain"), learned=(mode == "learned"))
+              contact_sides=res["contact_sides"], guard=(mode != "plain"), learned=(mode == "learned"),
+              detect_fraction=min(1.0, res["detections"] / max(1, res["steps"])))
     # a detection kernel early-exits when no detection is due: count only real launches
     launches = n
     if k == "k_pose":  # works on the steps that detect or audit
@@ -212,7 +216,7 @@ def cpu_baseline(seconds_target=15.0):
     oracle.build(force=False)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     oracle.set_threads(cores)
-    d = I.config1()
+    d = I.walled_box()
     o = oracle.Oracle(d)
     o.step(5)
     t0 = time.perf_counter()
@@ -223,7 +227,7 @@ def cpu_baseline(seconds_target=15.0):
     o.step(n)
     dt = time.perf_counter() - t0
     return dict(value=d.n_spheres * n / dt, unit="sphere-timesteps/s", cores=cores, kind="oracle",
-                sample=f"configuration 1 (2,000 three-sphere clumps, 6,000 spheres, lattice in a walled box), "
+                sample=f"walled box (2,000 three-sphere clumps, 6,000 spheres, lattice in a walled box), "
                        f"{n} steps of FP64 O(N^2) brute force, {dt:.1f} s")
 
 
@@ -270,7 +274,7 @@ def main():
         log(f"patch settled: {info}")
         if args.patch_cache:
             np.savez(args.patch_cache, x=px, q=pq)
-    desc = I.config5(px, pq, n_clumps=args.clumps)
+    desc = I.rover_bed(px, pq, n_clumps=args.clumps)
     log(f"workload: {desc.n_clumps} clumps, {desc.n_spheres} spheres, built in {time.perf_counter() - t0:.1f} s")
     stats = dict(spheres=desc.n_spheres, clumps=desc.n_clumps, fp32=True)
     modes = args.modes.split(",")

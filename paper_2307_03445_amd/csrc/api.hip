@@ -638,6 +638,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     // testing aid: deferred detection with zero margin and no guard, which
     // misses contacts on purpose so the audit's failure path can be tested
     sc->test_no_guard = getenv("CDEM_TEST_NO_GUARD") != nullptr;
+    // testing aid: the displacement guard without its per-clump bound
+    sc->S.guard_exact = getenv("CDEM_TEST_EXACT_GUARD") != nullptr ? 1 : 0;
     int64_t cap0 = std::max<int64_t>(4 * ns, 1024);  // pairs; grown on demand
     if (const char *ev = getenv("CDEM_INITIAL_CAPACITY")) cap0 = std::max<int64_t>(atoll(ev), 64);  // testing aid
     if ((rc = alloc_active_set(sc, cap0, false)) != CDEM_OK) return bail(rc);

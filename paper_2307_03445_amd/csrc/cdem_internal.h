@@ -161,6 +161,7 @@ struct DevScene {
     double4 *bdet;                   // sphere poses of the big clumps at the last detection
     int32_t n_big;
     int32_t guard_on;                // the displacement guard is checked (deferred detection)
+    int32_t guard_exact;             // testing aid: every clump takes the per-sphere guard test
     Plan plan;
     // learned envelopes and training-data collection
     int32_t store_speed;             // k_pose writes each sphere's speed to sspeed

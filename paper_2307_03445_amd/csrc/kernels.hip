@@ -1356,10 +1356,12 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
 // Symplectic Euler of clump c from the sum F, T of its contact forces and
 // torques (world frame), plus gravity; the record is read and rewritten in
 // place.  Returns an acceleration envelope of its spheres, |a_c| + |dw/dt|
-// r_acc + |w|^2 r_acc.  `pose` (if given) takes the new CoM and orientation
-// (x', q') and the old ones (x, q).
+// r_acc + |w|^2 r_acc.  `pose` takes the new CoM and orientation (x', q')
+// and the old ones (x, q), `rctr` the bound r_ctr on the distance of a sphere
+// centre from the CoM (both are private arrays of the caller, never null: a
+// null test on them would keep them out of registers).
 __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, double *F, const double *T,
-                                                 double *pose = nullptr) {
+                                                 double *pose, double *rctr) {
     const double h = S.h;
     double4 *rec = S.cst + 4 * c;
     const double4 k0 = rec[0], k1 = rec[1], k2 = rec[2], k3 = rec[3];
@@ -1415,12 +1417,13 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, d
     rec[1] = make_double4(v[0], v[1], v[2], k1.w);
     rec[2] = make_double4(q[0], q[1], q[2], q[3]);
     rec[3] = make_double4(w[0], w[1], w[2], k3.w);
-    if (pose) {
+    {
         for (int i = 0; i < 3; i++) pose[i] = x[i];
         for (int i = 0; i < 4; i++) pose[3 + i] = q[i];
         pose[7] = k0.x; pose[8] = k0.y; pose[9] = k0.z;
         pose[10] = k2.x; pose[11] = k2.y; pose[12] = k2.z; pose[13] = k2.w;
     }
+    *rctr = k3.w;
     if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
           isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
         S.ctl->nonfinite = 1;
@@ -1454,7 +1457,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
         info = S.sinfo[s];
         ub = S.up_beg[s]; nu = S.up_cnt[s];
         lb = pick(S.lo_beg, cur)[s]; nl = pick(S.lo_cnt, cur)[s];
-        if (S.guard_on) m = S.smargin[s];
+        if (fresh) m = S.smargin[s];
     }
     if (live) c0 = S.wave_c[w];
     const int cnt = (int)(info >> 8);  // the clump's sphere count
@@ -1472,57 +1475,83 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     xs[0][threadIdx.x] = make_double2(Fs[0], Fs[1]);
     xs[1][threadIdx.x] = make_double2(Fs[2], Ts[0]);
     xs[2][threadIdx.x] = make_double2(Ts[1], Ts[2]);
+    if (fresh) xs[3][threadIdx.x] = make_double2((double)m, 0.0);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     double Fc[3], Tc[3];
     for (int i = 0; i < 3; i++) { Fc[i] = 0.0 + Fs[i]; Tc[i] = 0.0 + Ts[i]; }
-    if (leader)
+    double mmin = (double)m;  // the clump's smallest margin (steps of a detection)
+    if (leader) {
         for (int j = 1; j < cnt; j++) {
             const double2 a = xs[0][threadIdx.x + j], b = xs[1][threadIdx.x + j], d = xs[2][threadIdx.x + j];
             Fc[0] = Fc[0] + a.x; Fc[1] = Fc[1] + a.y; Fc[2] = Fc[2] + b.x;
             Tc[0] = Tc[0] + b.y; Tc[1] = Tc[1] + d.x; Tc[2] = Tc[2] + d.y;
         }
+        if (fresh)
+            for (int j = 1; j < cnt; j++) mmin = fmin(mmin, xs[3][threadIdx.x + j].x);
+    }
     float acc = 0.0f;
     // leader: the new CoM and orientation, then those at the last detection
     double g[14];
+#pragma unroll
     for (int i = 0; i < 14; i++) g[i] = 0.0;
+    double rc = 0.0;
     uint32_t tb = 0;
+    bool exact = false;  // the leader's clump needs the per-sphere test
     if (leader) {
-        acc = integrate_clump(S, c, Fc, Tc, g);
+        acc = integrate_clump(S, c, Fc, Tc, g, &rc);
         if (S.guard_on) {
-            tb = S.tmpl_sbeg[S.clump_tmpl[c]];
             double4 *cd = S.cdet + 2 * c;
             if (fresh) {  // the detection saw the state before this step's update
-                cd[0] = make_double4(g[7], g[8], g[9], 0.0);
+                cd[0] = make_double4(g[7], g[8], g[9], mmin);
                 cd[1] = make_double4(g[10], g[11], g[12], g[13]);
+                exact = true;
             } else {
                 const double4 d0 = cd[0], d1 = cd[1];
                 g[7] = d0.x; g[8] = d0.y; g[9] = d0.z;
                 g[10] = d1.x; g[11] = d1.y; g[12] = d1.z; g[13] = d1.w;
+                // A bound on every sphere's displacement: the CoM's, plus
+                // 2 sin(theta/2) r_ctr for the rotation theta between the two
+                // orientations (|sin(theta/2)| is the norm of the vector part
+                // of conj(q_det) q).  Below 0.999 times the clump's smallest
+                // margin, with room for the rounding of either side, no
+                // sphere can trip and the per-sphere test is skipped.
+                const double ex = g[0] - d0.x, ey = g[1] - d0.y, ez = g[2] - d0.z;
+                const double vx = d1.x * g[4] - g[3] * d1.y - (d1.z * g[6] - d1.w * g[5]);
+                const double vy = d1.x * g[5] - g[3] * d1.z - (d1.w * g[4] - d1.y * g[6]);
+                const double vz = d1.x * g[6] - g[3] * d1.w - (d1.y * g[5] - d1.z * g[4]);
+                const double bound = sqrt(ex * ex + ey * ey + ez * ez) +
+                                     2.0 * sqrt(vx * vx + vy * vy + vz * vz) * rc;
+                exact = S.guard_exact || !(bound * (1.0 + 1e-9) + 1e-12 < 0.999 * d0.w);
             }
+            if (exact) tb = S.tmpl_sbeg[S.clump_tmpl[c]];
         }
     }
     // Displacement guard: every sphere's centre now against where it stood at
     // the last detection (both from its clump's pose, the same arithmetic as
-    // every other pose), tripping at 0.999 times its margin.
+    // every other pose), tripping at 0.999 times its margin; a wavefront
+    // whose clumps all pass the bound above skips it.
     bool trip = false;
-    if (S.guard_on) {
+    if (S.guard_on && __ballot(exact) != 0) {
         // the leader's poses to its lanes, through LDS (after every leader of
         // the wave has read the sums)
         double2(*gs)[256] = xs;
         __shared__ uint32_t tbs[256];
         if (leader) {
+#pragma unroll
             for (int i = 0; i < 7; i++) gs[i][threadIdx.x] = make_double2(g[2 * i], g[2 * i + 1]);
-            tbs[threadIdx.x] = tb;
+            tbs[threadIdx.x] = exact ? tb : 0xffffffffu;  // all ones: the clump passed the bound
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (active) {
-            const int ldr = (int)threadIdx.x - (int)(info & 0xffu);
+        const int ldr = (int)threadIdx.x - (int)(info & 0xffu);
+        const uint32_t tbl = active ? tbs[ldr] : 0xffffffffu;
+        if (tbl != 0xffffffffu) {
+            if (!fresh) m = S.smargin[s];
+#pragma unroll
             for (int i = 0; i < 7; i++) { const double2 v = gs[i][ldr]; g[2 * i] = v.x; g[2 * i + 1] = v.y; }
-            const uint32_t tbl = tbs[ldr];
             const uint32_t ts = tbl + (info & 0xffu);
             const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
             double A[9], D[9];
@@ -1587,7 +1616,8 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     }
     if (threadIdx.x == 0) {
         double Fc[3] = {sh[0][0], sh[1][0], sh[2][0]}, Tc[3] = {sh[3][0], sh[4][0], sh[5][0]};
-        float a = integrate_clump(S, c, Fc, Tc);
+        double pose[14], rc;  // unused
+        float a = integrate_clump(S, c, Fc, Tc, pose, &rc);
         if (S.detect_mode != 0 && a > __uint_as_float(S.ctl->amax_bits)) atomicMax(&S.ctl->amax_bits, __float_as_uint(a));
     }
 }

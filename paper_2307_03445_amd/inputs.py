@@ -53,9 +53,11 @@ PRESC_NPARAM = 12
 DENSITY = 2600.0
 
 
-def rng(config_index: int, replica: int = 0) -> np.random.Generator:
-    """Generator for configuration ``config_index`` (1-based) and replica."""
-    return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(config_index, replica)))
+def rng(stream: int, replica: int = 0) -> np.random.Generator:
+    """Generator of seed stream ``stream`` (one per workload: 1 walled box,
+    2 bed templates, 4 funnels, 5 rover bed, 6 and 7 statistics scenes) and
+    replica."""
+    return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(stream, replica)))
 
 
 @dataclass
@@ -400,7 +402,7 @@ def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_m
 # Configuration 1: 2,000 three-sphere clumps in a 5 cm box (CPU-checkable)
 # ---------------------------------------------------------------------------
 
-CFG1_MAT = (1e7, 0.3, 0.5, 0.5)
+BOX_MAT = (1e7, 0.3, 0.5, 0.5)
 
 
 def _unit_three_sphere_props(dirs: np.ndarray, res: int = 32):
@@ -436,7 +438,7 @@ def _unit_three_sphere_props(dirs: np.ndarray, res: int = 32):
     return vol, com, I
 
 
-def _cfg1_templates(g: np.random.Generator, n: int, res: int = 32):
+def _box_templates(g: np.random.Generator, n: int, res: int = 32):
     """n three-sphere templates, radius r ~ U[1,2] mm shared by the three spheres,
     centres offset 0.6 r along independent random unit axes; recentred on the
     CoM and rotated to principal axes (mass properties by voxel integration)."""
@@ -454,7 +456,7 @@ def _cfg1_templates(g: np.random.Generator, n: int, res: int = 32):
     return out
 
 
-def config1(replica: int = 0, n_clumps: int = 2000, dense: bool = False, res: int = 32,
+def walled_box(replica: int = 0, n_clumps: int = 2000, dense: bool = False, res: int = 32,
             vel_noise: float = 0.05) -> SceneDesc:
     """Configuration 1 (plain method, CPU-checkable).
 
@@ -472,9 +474,9 @@ def config1(replica: int = 0, n_clumps: int = 2000, dense: bool = False, res: in
     the pile, with the same velocity noise.
     """
     g = rng(1, replica)
-    tmpls = _cfg1_templates(g, n_clumps, res)
+    tmpls = _box_templates(g, n_clumps, res)
     L = 0.05
-    mat = np.tile(np.array(CFG1_MAT), (3 * n_clumps, 1))
+    mat = np.tile(np.array(BOX_MAT), (3 * n_clumps, 1))
     if dense:
         x, q = deposit(g, tmpls, np.arange(n_clumps), (0.0, 0.0, L, L), 0.02 * 1e-3)
         top = float(x[:, 2].max()) + 0.02
@@ -490,17 +492,17 @@ def config1(replica: int = 0, n_clumps: int = 2000, dense: bool = False, res: in
         top = nz * spacing + 0.01
     v = g.uniform(-vel_noise, vel_noise, (n_clumps, 3))
     w = np.zeros((n_clumps, 3))
-    walls = box_walls((0, 0, 0), (L, L, top), CFG1_MAT)
+    walls = box_walls((0, 0, 0), (L, L, top), BOX_MAT)
     return assemble(tmpls, np.arange(n_clumps), x, q, v, w, mat, (0, 0, -9.81),
                     (0, 0, 0, L, L, top), 1e-6, bnd=walls,
-                    name=f"cfg1{'-dense' if dense else ''}-r{replica}")
+                    name=f"box{'-dense' if dense else ''}-r{replica}")
 
 
 # ---------------------------------------------------------------------------
-# Shared templates of configurations 2-5
+# Shared templates of the bed, funnel and rover workloads
 # ---------------------------------------------------------------------------
 
-CFG2_COUNTS = (1, 2, 3, 3, 3, 3, 4, 6)
+BED_SPHERE_COUNTS = (1, 2, 3, 3, 3, 3, 4, 6)
 
 
 def lognormal_radii(g: np.random.Generator, n: int, median=2e-3, sigma=0.3):
@@ -518,16 +520,16 @@ def multisphere_template(g: np.random.Generator, count: int, radii=None, res: in
     return principal_template(0.6 * r[:, None] * dirs, r, DENSITY, res)
 
 
-def cfg2_templates(replica: int = 0, res: int = 64):
+def bed_templates(replica: int = 0, res: int = 64):
     g = rng(2, replica)
-    return [multisphere_template(g, c, res=res) for c in CFG2_COUNTS]
+    return [multisphere_template(g, c, res=res) for c in BED_SPHERE_COUNTS]
 
 
 # ---------------------------------------------------------------------------
 # Small hand-built scenes used to pin the oracle against closed forms
 # ---------------------------------------------------------------------------
 
-def two_sphere_headon(r=1e-3, v0=0.05, mat=CFG1_MAT, gap=1e-7, h=1e-6, r2=None):
+def two_sphere_headon(r=1e-3, v0=0.05, mat=BOX_MAT, gap=1e-7, h=1e-6, r2=None):
     """Two single-sphere clumps approaching head-on along x, no gravity."""
     r2 = r if r2 is None else r2
     t1, t2 = sphere_template(r), sphere_template(r2)
@@ -634,14 +636,14 @@ def layered_lattice(g: np.random.Generator, templates, clump_template, footprint
     return x, random_unit_quaternions(g, n)
 
 
-def cfg5_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, h: float = 5e-6,
+def rover_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, h: float = 5e-6,
                      cor: float = 0.2) -> SceneDesc:
-    """The preparation scene of the configuration-5 bed: one side x side patch
-    of the configuration-2 templates spawned on a size-layered lattice inside
+    """The preparation scene of the rover bed: one side x side patch
+    of the bed templates spawned on a size-layered lattice inside
     a walled box, to be settled under gravity (with a larger step and a lower
     CoR than the measured run, which only speeds up the preparation)."""
     g = rng(5, replica)
-    tmpls = cfg2_templates(replica)
+    tmpls = bed_templates(replica)
     ct = g.integers(0, len(tmpls), n_clumps)
     x, q = layered_lattice(g, tmpls, ct, (0.0, 0.0, side, side))
     sizes = np.array([t[0].shape[0] for t in tmpls])
@@ -654,28 +656,28 @@ def cfg5_patch_scene(replica: int = 0, n_clumps: int = 6875, side: float = 0.05,
     top = float(x[:, 2].max()) + 0.02
     walls = box_walls((0, 0, 0), (side, side, top), (5e7, 0.3, 0.5, cor))
     return assemble(tmpls, ct, x, q, np.zeros((n_clumps, 3)), np.zeros((n_clumps, 3)), mat, (0, 0, -9.81),
-                    (0, 0, 0, side, side, top), h, bnd=walls, name=f"cfg5-patch-r{replica}")
+                    (0, 0, 0, side, side, top), h, bnd=walls, name=f"rover-patch-r{replica}")
 
 
-def cfg5_deposited_patch(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, sink_max: float = 2e-5):
-    """A configuration-5 patch built on the CPU alone: the clumps of
-    :func:`cfg5_patch_scene` (same templates, same template draw) dropped one
+def rover_deposited_patch(replica: int = 0, n_clumps: int = 6875, side: float = 0.05, sink_max: float = 2e-5):
+    """A rover-bed patch built on the CPU alone: the clumps of
+    :func:`rover_patch_scene` (same templates, same template draw) dropped one
     by one with :func:`deposit`.  Much looser than the settled patch, but every
     clump rests in contact; for checks whose input must not come from a
     simulation run.  Returns (x[n,3], q[n,4])."""
     g = rng(5, replica)
-    tmpls = cfg2_templates(replica)
+    tmpls = bed_templates(replica)
     ct = g.integers(0, len(tmpls), n_clumps)
     return deposit(g, tmpls, ct, (0.0, 0.0, side, side), sink_max)
 
 
-def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
+def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
             bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True,
             wheel_x: float = 1.0) -> SceneDesc:
     """Configuration 5 (the metric's workload), tiled from a settled patch.
 
     ``patch_x``/``patch_q`` are the settled clump poses of
-    :func:`cfg5_patch_scene` (same replica); the patch is Morton-sorted and
+    :func:`rover_patch_scene` (same replica); the patch is Morton-sorted and
     copied over the 4 m x 1 m bed (the paper prepares large beds from copies of
     a settled base patch), truncated to ``n_clumps``.  Copies are spaced by the
     patch width plus the depth its spheres press into the patch walls, so no
@@ -688,7 +690,7 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
     surface and sinks in under its load.
     """
     g = rng(5, 1000 + replica)
-    tmpls = cfg2_templates(replica)
+    tmpls = bed_templates(replica)
     ct_p = rng(5, replica).integers(0, len(tmpls), patch_x.shape[0])
     order = morton_order(patch_x, 0.01)
     xp, qp, ct_p = patch_x[order], patch_q[order], ct_p[order]
@@ -750,7 +752,7 @@ def config5(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps
         top = max(top, zc + R + 0.02)
     walls = box_walls((0, 0, 0), (bed[0], bed[1], top + 0.05), (5e7, 0.3, 0.5, 0.5))
     return assemble(templates, CT, X, Q, V, W, mat, (0, 0, -9.81), (0, 0, 0, bed[0], bed[1], top + 0.05),
-                    1e-6, bnd=walls, presc=presc, name=f"cfg5-r{replica}")
+                    1e-6, bnd=walls, presc=presc, name=f"rover-r{replica}")
 
 
 # ---------------------------------------------------------------------------
@@ -791,7 +793,7 @@ def funnel_scene_parts(g: np.random.Generator, n_clumps: int, template, mu: floa
     return x, q, bnd, dom
 
 
-def config4(replica: int = 0, n_scenes: int = 256, lo: int = 2000, hi: int = 60000, scale: float = 1.0,
+def funnel_batch(replica: int = 0, n_scenes: int = 256, lo: int = 2000, hi: int = 60000, scale: float = 1.0,
             res: int = 32) -> SceneDesc:
     """Configuration 4: n_scenes independent funnel discharges batched in one
     simulation.  Clump counts log-uniform in [lo, hi] (times `scale`); per
@@ -817,7 +819,7 @@ def config4(replica: int = 0, n_scenes: int = 256, lo: int = 2000, hi: int = 600
     n = X.shape[0]
     return assemble(templates, np.concatenate(CT), X, np.concatenate(Q), np.zeros((n, 3)), np.zeros((n, 3)),
                     np.concatenate(MAT), np.tile([0.0, 0.0, -9.81], (n_scenes, 1)), np.array(doms), 1e-6,
-                    clump_scene=np.concatenate(CS), bnd=bnds, name=f"cfg4-r{replica}")
+                    clump_scene=np.concatenate(CS), bnd=bnds, name=f"funnels-r{replica}")
 
 
 def extract_scene(batch: SceneDesc, k: int) -> SceneDesc:
@@ -839,7 +841,7 @@ def extract_scene(batch: SceneDesc, k: int) -> SceneDesc:
 
 # ---------------------------------------------------------------------------
 # Long-run statistics: a settled box (packing fraction) and a collapsed
-# column (heap angle), in the materials and clumps of configuration 1
+# column (heap angle), in the materials and clumps of the walled box
 # ---------------------------------------------------------------------------
 
 STATS_H = 1e-5  # time step of the statistics runs (about 40 steps per contact at these stiffnesses)
@@ -859,10 +861,10 @@ def stats_scene(kind: str, replica: int = 0, n_clumps: int = 120, res: int = 16)
     if kind not in ("box", "heap"):
         raise ValueError("kind is 'box' or 'heap'")
     g = rng(6 if kind == "box" else 7, replica)
-    tmpls = _cfg1_templates(g, n_clumps, res)
+    tmpls = _box_templates(g, n_clumps, res)
     rb = max(bounding_radius(t[0], t[1]) for t in tmpls)
     spacing = 2.0 * rb + 1e-4
-    mat = np.tile(np.array(CFG1_MAT), (3 * n_clumps, 1))
+    mat = np.tile(np.array(BOX_MAT), (3 * n_clumps, 1))
     if kind == "box":
         L = 0.03
         nxy = int(L // spacing)
@@ -872,7 +874,7 @@ def stats_scene(kind: str, replica: int = 0, n_clumps: int = 120, res: int = 16)
         x = sites[g.permutation(sites.shape[0])[:n_clumps]]
         v = g.uniform(-0.05, 0.05, (n_clumps, 3))
         top = nz * spacing + 0.01
-        bnd = box_walls((0, 0, 0), (L, L, top), CFG1_MAT)
+        bnd = box_walls((0, 0, 0), (L, L, top), BOX_MAT)
         dom = (0, 0, 0, L, L, top)
     else:
         # a column against the back wall x = 0 of a slot one site deep
@@ -885,10 +887,10 @@ def stats_scene(kind: str, replica: int = 0, n_clumps: int = 120, res: int = 16)
         v = np.zeros((n_clumps, 3))
         top = nz * spacing + 0.01
         Lx = 0.15
-        bnd = [dict(type=BND_PLANE, param=(0, 0, 0, 0, 0, 1), mat=CFG1_MAT, scene=0),
-               dict(type=BND_PLANE, param=(0, 0, 0, 1, 0, 0), mat=CFG1_MAT, scene=0),
-               dict(type=BND_PLANE, param=(0, 0, 0, 0, 1, 0), mat=CFG1_MAT, scene=0),
-               dict(type=BND_PLANE, param=(0, W, 0, 0, -1, 0), mat=CFG1_MAT, scene=0)]
+        bnd = [dict(type=BND_PLANE, param=(0, 0, 0, 0, 0, 1), mat=BOX_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, 0, 0, 1, 0, 0), mat=BOX_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, 0, 0, 0, 1, 0), mat=BOX_MAT, scene=0),
+               dict(type=BND_PLANE, param=(0, W, 0, 0, -1, 0), mat=BOX_MAT, scene=0)]
         dom = (0, 0, 0, Lx, W, top)
     q = random_unit_quaternions(g, n_clumps)
     w = np.zeros((n_clumps, 3))

@@ -3,7 +3,7 @@
 The paper prepares its large test beds by settling batches of clumps under
 gravity and copying the settled base patch (Sec. 4.1).  ``settle_patch`` runs
 that settling for one small patch on the GPU through the C ABI; the caller
-tiles the result (``inputs.config5``).
+tiles the result (``inputs.rover_bed``).
 """
 from __future__ import annotations
 
@@ -17,8 +17,8 @@ from ._lib import Scene
 
 def settle_patch(replica: int = 0, n_clumps: int = 6875, min_steps: int = 60000, max_steps: int = 300000,
                  chunk: int = 10000, v_stop: float = 0.05, log=None):
-    """Settle the configuration-5 preparation patch; returns (x, q, info)."""
-    d = I.cfg5_patch_scene(replica, n_clumps=n_clumps)
+    """Settle the rover-bed preparation patch; returns (x, q, info)."""
+    d = I.rover_patch_scene(replica, n_clumps=n_clumps)
     sc = Scene(d, precision="fp32")
     t0 = time.perf_counter()
     steps, vmax = 0, float("inf")

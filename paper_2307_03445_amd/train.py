@@ -99,9 +99,9 @@ def fit(F, Y, tau=0.99, steps=3000, batch=8192, lr=2e-3, seed=0, log=None):
 
 def training_scenes(patch_x, patch_q):
     """A reduced rover bed with the wheel (the flow the envelopes must learn)
-    and the contact-rich configuration-1 pile."""
-    return [I.config5(patch_x, patch_q, n_clumps=96 * patch_x.shape[0], bed=(0.8, 0.3), wheel_x=0.3),
-            I.config1(dense=True)]
+    and the contact-rich walled-box pile."""
+    return [I.rover_bed(patch_x, patch_q, n_clumps=96 * patch_x.shape[0], bed=(0.8, 0.3), wheel_x=0.3),
+            I.walled_box(dense=True)]
 
 
 def train(patch_x, patch_q, log=None, captures=6, steps=3000):
@@ -126,7 +126,7 @@ def load_weights(path=WEIGHTS):
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--patch", required=True, help="npz with the settled configuration-5 patch (x, q)")
+    ap.add_argument("--patch", required=True, help="npz with the settled rover-bed patch (x, q)")
     ap.add_argument("--out", default=WEIGHTS)
     a = ap.parse_args()
     z = np.load(a.patch)

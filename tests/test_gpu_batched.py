@@ -16,7 +16,7 @@ def _scene(desc, prec="fp32"):
 
 @pytest.fixture(scope="module")
 def batch():
-    return I.config4(n_scenes=6, lo=150, hi=1500)
+    return I.funnel_batch(n_scenes=6, lo=150, hi=1500)
 
 
 @pytest.mark.parametrize("mode", ["plain", "fixed"])
@@ -40,7 +40,7 @@ def test_scene_in_batch_equals_scene_alone(batch, mode):
 
 
 def test_batched_matches_oracle_fp64(batch):
-    small = I.config4(n_scenes=3, lo=100, hi=300)
+    small = I.funnel_batch(n_scenes=3, lo=100, hi=300)
     sc, o = _scene(small, "fp64"), oracle.Oracle(small)
     sc.step(200)
     o.step(200)

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def dense():
-    return I.config1(dense=True)
+    return I.walled_box(dense=True)
 
 
 def _params():
@@ -57,7 +57,7 @@ def test_load_rejects_foreign_or_truncated_blob(dense):
     a = _make(dense, "fp64", "plain")
     a.step(5)
     blob = a.save()
-    other = I.config1(replica=1, dense=True)  # same counts, other templates
+    other = I.walled_box(replica=1, dense=True)  # same counts, other templates
     b = _make(other, "fp64", "plain")
     for bad in (blob[:-8], blob[:100], b"x" * len(blob)):
         with pytest.raises(Exception):

@@ -16,7 +16,7 @@ def _scene(desc, prec="fp64"):
 
 @pytest.fixture(scope="module")
 def dense():
-    return I.config1(dense=True)
+    return I.walled_box(dense=True)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -37,7 +37,7 @@ def test_fixed_rule_bitwise_equals_plain(dense, prec):
 def test_guard_forces_early_redetection():
     """Clumps released at rest with overlaps: the first detection sees zero
     speed, so only the displacement guard keeps the active set complete."""
-    d = I.config1(dense=True, vel_noise=0.0)
+    d = I.walled_box(dense=True, vel_noise=0.0)
     plain, fixed = _scene(d), _scene(d)
     fixed.set_detection("fixed", k_max=20, safety=1.0, margin_cap=1e-4, audit_period=5)
     plain.step(100)
@@ -47,6 +47,29 @@ def test_guard_forces_early_redetection():
     sp, sf = plain.state(), fixed.state()
     for k in sp:
         assert np.array_equal(sp[k], sf[k]), k
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_guard_bound_keeps_the_per_sphere_trip_schedule(prec, monkeypatch):
+    """The guard skips the per-sphere test for clumps whose CoM displacement
+    plus rotation bound stays below their smallest margin; a testing switch
+    turns the bound off, and the guard must trip on exactly the same steps."""
+    d = I.walled_box(dense=True, vel_noise=0.0)
+    monkeypatch.setenv("CDEM_TEST_EXACT_GUARD", "1")
+    ref = _scene(d, prec)
+    monkeypatch.delenv("CDEM_TEST_EXACT_GUARD")
+    fast = _scene(d, prec)
+    for sc in (ref, fast):
+        sc.set_detection("fixed", k_max=20, safety=1.0, margin_cap=1e-4, audit_period=5)
+    for step in range(150):
+        ref.step(1)
+        fast.step(1)
+        cr, cf = ref.counts(), fast.counts()
+        assert (cr["guard_trips"], cr["detections"]) == (cf["guard_trips"], cf["detections"]), (step, cr, cf)
+    assert cf["guard_trips"] >= 1 and cf["missed"] == 0, cf
+    sr, sf = ref.state(), fast.state()
+    for k in sr:
+        assert np.array_equal(sr[k], sf[k]), k
 
 
 def test_audit_reports_misses_when_guard_disabled(dense, monkeypatch):

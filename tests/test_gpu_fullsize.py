@@ -26,8 +26,8 @@ pytestmark = pytest.mark.gpu
 
 @pytest.fixture(scope="module")
 def bed():
-    x, q = I.cfg5_deposited_patch()
-    return I.config5(x, q)
+    x, q = I.rover_deposited_patch()
+    return I.rover_bed(x, q)
 
 
 @pytest.fixture(scope="module")

@@ -82,7 +82,7 @@ def _scene(desc, prec="fp32"):
 def test_learned_detection_equals_plain_and_falls_back():
     """Learned margins (any weights) keep the trajectory identical to per-step
     detection; unusable predictions fall back to the fixed rule per bin."""
-    d = I.config1(dense=True)
+    d = I.walled_box(dense=True)
     plain = _scene(d)
     plain.step(150)
     for params, expect_fallback in ((_params(), False), (np.full(M.N_PARAM, 50.0, np.float32), True)):
@@ -101,7 +101,7 @@ def test_learned_detection_equals_plain_and_falls_back():
 
 
 def test_collect_envelopes_labels_cover_features():
-    d = I.config1(dense=True)
+    d = I.walled_box(dense=True)
     sc = _scene(d)
     sc.step(10)
     f, y = sc.collect_envelopes(20)

@@ -66,7 +66,7 @@ def _clump_scale(desc, c):
 
 @pytest.fixture(scope="module")
 def dense():
-    return I.config1(dense=True)
+    return I.walled_box(dense=True)
 
 
 @gpu
@@ -132,9 +132,9 @@ def test_hundred_steps_state_and_pairs(dense, prec):
 
 
 @gpu
-def test_config1_lattice_thousand_steps_fp64():
+def test_walled_box_lattice_thousand_steps_fp64():
     """Configuration 1 as specified (lattice, 1,000 steps, FP64): bitwise equal to the oracle."""
-    d = I.config1()
+    d = I.walled_box()
     sc = _scene(d)
     o = oracle.Oracle(d)
     sc.step(1000)
@@ -185,7 +185,7 @@ def test_empty_scene_and_single_clump():
     sc.step(3)
     assert sc.counts()["steps"] == 3
     d1 = I.assemble([t], [0], [(0.5, 0.5, 0.5)], [(1, 0, 0, 0)], [(0.1, 0, 0)], [(0, 0, 0)],
-                    [I.CFG1_MAT], (0, 0, -9.81), (0, 0, 0, 1, 1, 1), 1e-6)
+                    [I.BOX_MAT], (0, 0, -9.81), (0, 0, 0, 1, 1, 1), 1e-6)
     sc, o = _scene(d1), oracle.Oracle(d1)
     sc.step(10)
     o.step(10)
@@ -227,8 +227,8 @@ def _wheel_scene(n_rim=96, seed=3):
     w[-1] = (0, 2.0, 0)
     ct = np.r_[np.zeros(300, int), np.ones(300, int), 2]
     ns = 300 + 900 + n_rim
-    mat = np.tile(np.array(I.CFG1_MAT), (ns, 1))
-    walls = I.box_walls((0, 0, 0), (0.06, 0.02, 0.2), I.CFG1_MAT)
+    mat = np.tile(np.array(I.BOX_MAT), (ns, 1))
+    walls = I.box_walls((0, 0, 0), (0.06, 0.02, 0.2), I.BOX_MAT)
     return I.assemble(templates, ct, xs, qs, v, w, mat, (0, 0, -9.81), (0, 0, 0, 0.06, 0.02, 0.2), 1e-6,
                       bnd=walls, presc=[dict(clump=600, v_fixed=(0.05, 0, 0), free=(0, 0, 1), w_body=(0, 2.0, 0),
                                              f_extra=(0, 0, -0.2))])
@@ -275,7 +275,7 @@ def _crowded_scene(n_small=70, n_big=3):
     nc = len(X)
     g = np.random.default_rng(7)
     v = g.uniform(-0.01, 0.01, (nc, 3))
-    mat = np.tile(np.array(I.CFG1_MAT), (nc, 1))
+    mat = np.tile(np.array(I.BOX_MAT), (nc, 1))
     return I.assemble([big, small], CT, X, np.tile([1.0, 0, 0, 0], (nc, 1)), v, np.zeros((nc, 3)), mat,
                       (0, 0, 0), (0, 0, 0, 0.08, 0.06, 0.06), 1e-6)
 

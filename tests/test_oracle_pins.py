@@ -532,7 +532,7 @@ def test_prescribed_body_motion():
 def test_sphere_positions_match_independent_rotation():
     """x_s = x_c + R(q) o_s with R from scipy's quaternion convention (scalar last)."""
     from scipy.spatial.transform import Rotation
-    d = I.config1(n_clumps=50)
+    d = I.walled_box(n_clumps=50)
     o = oracle.Oracle(d)
     xs = o.sphere_pos()
     sb = d.sphere_begin()

@@ -9,7 +9,7 @@ from paper_2307_03445_amd import inputs as I
 
 
 def _setup(steps):
-    d = I.config1(dense=True, n_clumps=400)
+    d = I.walled_box(dense=True, n_clumps=400)
     o = oracle.Oracle(d)
     o.step(steps)
     n = o.eval()
