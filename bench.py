@@ -245,7 +245,27 @@ def main():
                     help="npz file holding the settled preparation patch (written if missing)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
                     help="only run a plain device-to-device copy of this many GiB (counter calibration)")
+    ap.add_argument("--copy-bandwidth-gib", type=float, default=0.0,
+                    help="only time device-to-device copies of this many GiB (achievable HBM bandwidth)")
     args = ap.parse_args()
+    if args.copy_bandwidth_gib > 0:
+        import torch
+        n = int(args.copy_bandwidth_gib * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 20
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        sec = e0.elapsed_time(e1) / 1e3 / reps
+        print(json.dumps({"copy_bytes_read_and_written": 8 * n, "seconds_per_copy": sec,
+                          "GB_per_s": 8 * n / sec / 1e9, "copies_timed": reps}))
+        return
     if args.copy_probe_gib > 0:
         import torch
         n = int(args.copy_probe_gib * (1 << 30)) // 4
