@@ -1318,7 +1318,7 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
     // Entries are taken in batches whose loads are all issued before the first
     // is used (the sums stay in ascending partner order); the first lower batch
     // is loaded together with the upper links.
-    constexpr uint32_t kB = 4;
+    constexpr uint32_t kB = 3;  // four spill registers in the reduction; three do not
     V la[kB], lt[kB];
 #pragma unroll
     for (uint32_t j = 0; j < kB; j++)
