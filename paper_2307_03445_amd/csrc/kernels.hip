@@ -1316,13 +1316,11 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
     using V = typename Contrib<FP32>::V;
     const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
     // Entries are taken in batches whose loads are all issued before the first
-    // is used (the sums stay in ascending partner order); the first lower batch
-    // is loaded together with the upper links.
-    constexpr uint32_t kB = 3;  // four spill registers in the reduction; three do not
+    // is used (the sums stay in ascending partner order).  Six per batch keep
+    // the reduction at five waves per SIMD with no spilled register (eight
+    // spill; holding the first lower batch through the upper one spills too).
+    constexpr uint32_t kB = 6;
     V la[kB], lt[kB];
-#pragma unroll
-    for (uint32_t j = 0; j < kB; j++)
-        if (j < nl) { la[j] = cS[(int64_t)lb + j]; lt[j] = cTs[(int64_t)lb + j]; }
     for (uint32_t k0 = 0; k0 < nu; k0 += kB) {
         int64_t e[kB];
 #pragma unroll
@@ -1339,11 +1337,9 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
         }
     }
     for (uint32_t k0 = 0; k0 < nl; k0 += kB) {
-        if (k0 > 0) {
 #pragma unroll
-            for (uint32_t j = 0; j < kB; j++)
-                if (k0 + j < nl) { la[j] = cS[(int64_t)lb + k0 + j]; lt[j] = cTs[(int64_t)lb + k0 + j]; }
-        }
+        for (uint32_t j = 0; j < kB; j++)
+            if (k0 + j < nl) { la[j] = cS[(int64_t)lb + k0 + j]; lt[j] = cTs[(int64_t)lb + k0 + j]; }
 #pragma unroll
         for (uint32_t j = 0; j < kB; j++) {
             if (k0 + j >= nl || la[j].w == 0) continue;
