@@ -1581,7 +1581,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
 }
 
 // Clumps with many spheres (a wheel): per-sphere sums first, then one workgroup
-// per clump reduces them in a fixed tree order and integrates.
+// per clump sums them (in ascending sphere id in the all-FP64 mode, in a
+// fixed tree order otherwise) and integrates.
 template <bool FP32>
 __global__ void __launch_bounds__(256) k_reduce_big_spheres(DevScene S) {
     if (aborted(S.ctl)) return;
@@ -1601,17 +1602,36 @@ __global__ void __launch_bounds__(256) k_integrate_big(DevScene S) {
     int32_t c = S.big_list[blockIdx.x];
     int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x)
-        for (int i = 0; i < 3; i++) { acc[i] = acc[i] + S.sF[3 * s + i]; acc[3 + i] = acc[3 + i] + S.sT[3 * s + i]; }
-    for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = acc[i];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w)
-            for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = sh[i][threadIdx.x] + sh[i][threadIdx.x + w];
+    if (S.precision != 1) {
+        // all-FP64 mode (precision 1 is FP32 force): the spheres in ascending id, as for every other clump
+        // (256 sphere sums at a time staged in LDS, added in order by one lane)
+        for (int64_t b = s0; b < s1; b += blockDim.x) {
+            const int64_t s = b + threadIdx.x;
+            if (s < s1)
+                for (int i = 0; i < 3; i++) { sh[i][threadIdx.x] = S.sF[3 * s + i]; sh[3 + i][threadIdx.x] = S.sT[3 * s + i]; }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int n = (int)(s1 - b < (int64_t)blockDim.x ? s1 - b : (int64_t)blockDim.x);
+                for (int j = 0; j < n; j++)
+                    for (int i = 0; i < 6; i++) acc[i] = acc[i] + sh[i][j];
+            }
+            __syncthreads();
+        }
+    } else {
+        // FP32-force mode: a fixed tree order (the same every run)
+        for (int64_t s = s0 + threadIdx.x; s < s1; s += blockDim.x)
+            for (int i = 0; i < 3; i++) { acc[i] = acc[i] + S.sF[3 * s + i]; acc[3 + i] = acc[3 + i] + S.sT[3 * s + i]; }
+        for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = acc[i];
         __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w)
+                for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = sh[i][threadIdx.x] + sh[i][threadIdx.x + w];
+            __syncthreads();
+        }
+        for (int i = 0; i < 6; i++) acc[i] = sh[i][0];
     }
     if (threadIdx.x == 0) {
-        double Fc[3] = {sh[0][0], sh[1][0], sh[2][0]}, Tc[3] = {sh[3][0], sh[4][0], sh[5][0]};
+        double Fc[3] = {acc[0], acc[1], acc[2]}, Tc[3] = {acc[3], acc[4], acc[5]};
         double pose[14], rc;  // unused
         float a = integrate_clump(S, c, Fc, Tc, pose, &rc);
         if (S.detect_mode != 0 && a > __uint_as_float(S.ctl->amax_bits)) atomicMax(&S.ctl->amax_bits, __float_as_uint(a));

@@ -243,6 +243,10 @@ def test_big_prescribed_clump(prec):
     o.step(40)
     err = state_errors(sc.state(), o.state(), 1e-3)
     assert max(err.values()) <= STATE_TOL, err
+    if prec == "fp64":  # the big clump's spheres summed in ascending id, as by the oracle
+        sg, so = sc.state(), o.state()
+        for k in sg:
+            assert np.array_equal(sg[k], so[k]), k
     sc.record_next_step()
     sc.step(1)
     o.eval()
@@ -254,6 +258,62 @@ def test_big_prescribed_clump(prec):
     Fo, _ = o.clump_forces()
     scale = _clump_scale(d, co)
     assert clump_force_error(Fg, Fo, scale).max() <= FORCE_RTOL
+
+
+def _wave_boundary_scene():
+    """Two free flat clumps falling onto a layer of single spheres: one of 64
+    spheres (exactly one wavefront of the reduction) and one of 65 (the
+    workgroup path: per-sphere sums, a tree sum and a guard kernel of its
+    own)."""
+    r = 1e-3
+    gx, gy = np.meshgrid(np.arange(8) * 1.6e-3, np.arange(8) * 1.6e-3)
+    grid = np.stack([gx.ravel(), gy.ravel(), np.zeros(64)], 1)
+    p64 = I.principal_template(grid, np.full(64, r), res=32)
+    p65 = I.principal_template(np.vstack([grid, [[5.6e-3, 5.6e-3, 1.6e-3]]]), np.full(65, r), res=32)
+    templates = [I.sphere_template(r), p64, p65]
+    fx, fy = np.meshgrid(np.arange(12) * 2.2e-3 + 2e-3, np.arange(6) * 2.2e-3 + 2e-3)
+    X = [np.stack([fx.ravel(), fy.ravel(), np.full(fx.size, 0.99e-3)], 1)]  # pressed 10 um into the floor
+    top = 0.99e-3 + r
+    for t, x0 in ((p64, 0.010), (p65, 0.0215)):
+        X.append(np.array([[x0, 0.008, top + 5e-6 - (t[0][:, 2] - t[1]).min()]]))  # 5 um above the layer
+    x = np.vstack(X)
+    nc = x.shape[0]
+    v = np.zeros((nc, 3))
+    v[-2:] = (0.0, 0.0, -0.4)
+    mat = np.tile(np.array(I.BOX_MAT), (72 + 64 + 65, 1))
+    walls = I.box_walls((0, 0, 0), (0.03, 0.02, 0.05), I.BOX_MAT)
+    return I.assemble(templates, np.r_[np.zeros(72, int), 1, 2], x, np.tile([1.0, 0, 0, 0], (nc, 1)), v,
+                      np.zeros((nc, 3)), mat, (0, 0, -9.81), (0, 0, 0, 0.03, 0.02, 0.05), 1e-6, bnd=walls)
+
+
+@gpu
+def test_clumps_at_the_wavefront_size_boundary():
+    """FP64 trajectories of the 64- and 65-sphere clumps bit for bit against
+    the oracle once both press into the layer, and deferred detection (the
+    65-sphere clump guarded by its own kernel) bit for bit against per-step
+    detection."""
+    d = _wave_boundary_scene()
+    sc, o = _scene(d), oracle.Oracle(d)
+    sc.step(60)
+    o.step(60)
+    sg, so = sc.state(), o.state()
+    for k in sg:
+        assert np.array_equal(sg[k], so[k]), k
+    sc.record_next_step()
+    sc.step(1)
+    o.eval()
+    cg, co = sc.contacts(), o.contacts()
+    compare_pairs(cg, co)
+    hi = np.maximum(co["a"], co["b"])
+    assert ((hi >= 72) & (hi < 136)).any() and ((hi >= 136) & (hi < 201)).any()  # both clumps in contact
+    fx = _scene(d)
+    fx.set_detection("fixed", k_max=10, safety=1.5, margin_cap=1e-4, audit_period=5)
+    fx.step(61)
+    c = fx.counts()
+    assert c["detections"] < 61 and c["missed"] == 0, c
+    sf, sg = fx.state(), sc.state()
+    for k in sg:
+        assert np.array_equal(sf[k], sg[k]), k
 
 
 def _crowded_scene(n_small=70, n_big=3):
