@@ -231,6 +231,26 @@ def cpu_baseline(seconds_target=15.0):
                        f"{n} steps of FP64 O(N^2) brute force, {dt:.1f} s")
 
 
+def gpu_on_cpu_sample(steps=2000):
+    """The GPU on the oracle's own sample: the walled box in the all-FP64 mode
+    with per-step detection (6,000 spheres: a launch-bound size, far below
+    what fills the chip), for a like-for-like rate beside the oracle's."""
+    import torch
+    from paper_2307_03445_amd import inputs as I
+    from paper_2307_03445_amd._lib import Scene
+    sc = Scene(I.walled_box(), precision="fp64")
+    sc.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ns = sc.counts()["spheres"]
+    sc.close()
+    return dict(value=ns * steps / dt, unit="sphere-timesteps/s", precision="fp64", detection="plain",
+                sample=f"walled box, {steps} steps (launch-bound at 6,000 spheres)")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,6 +369,7 @@ def main():
         line["speedup_vs_plain"] = results["plain"]["seconds"] / r["seconds"]
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
+        line["gpu_on_cpu_sample"] = gpu_on_cpu_sample()
     print(json.dumps(line), flush=True)
 
 
