@@ -287,26 +287,32 @@ def _wave_boundary_scene():
 
 
 @gpu
-def test_clumps_at_the_wavefront_size_boundary():
-    """FP64 trajectories of the 64- and 65-sphere clumps bit for bit against
-    the oracle once both press into the layer, and deferred detection (the
-    65-sphere clump guarded by its own kernel) bit for bit against per-step
-    detection."""
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_clumps_at_the_wavefront_size_boundary(prec):
+    """Trajectories of the 64- and 65-sphere clumps against the oracle once
+    both press into the layer (FP64 bit for bit, FP32 force within the state
+    tolerance), and deferred detection (the 65-sphere clump guarded by its own
+    kernel) bit for bit against per-step detection."""
     d = _wave_boundary_scene()
-    sc, o = _scene(d), oracle.Oracle(d)
+    sc, o = _scene(d, prec), oracle.Oracle(d)
     sc.step(60)
     o.step(60)
     sg, so = sc.state(), o.state()
-    for k in sg:
-        assert np.array_equal(sg[k], so[k]), k
+    if prec == "fp64":
+        for k in sg:
+            assert np.array_equal(sg[k], so[k]), k
+    else:
+        err = state_errors(sg, so, 1e-3)
+        assert max(err.values()) <= STATE_TOL, err
     sc.record_next_step()
     sc.step(1)
-    o.eval()
-    cg, co = sc.contacts(), o.contacts()
-    compare_pairs(cg, co)
-    hi = np.maximum(co["a"], co["b"])
+    cg = sc.contacts()
+    if prec == "fp64":  # FP32 trajectories differ by rounding: borderline contacts may differ
+        o.eval()
+        compare_pairs(cg, o.contacts())
+    hi = np.maximum(cg["a"], cg["b"])
     assert ((hi >= 72) & (hi < 136)).any() and ((hi >= 136) & (hi < 201)).any()  # both clumps in contact
-    fx = _scene(d)
+    fx = _scene(d, prec)
     fx.set_detection("fixed", k_max=10, safety=1.5, margin_cap=1e-4, audit_period=5)
     fx.step(61)
     c = fx.counts()
