@@ -1102,6 +1102,17 @@ __device__ __forceinline__ void law32(const double *nd, double delta_d, const fl
 // contact flag in w, that sphere's torque about its clump CoM, and the
 // partner sphere's torque (its force is minus the first); FP32 mode stores
 // floats.
+// Stores that mark their lines non-temporal: the pair contributions are
+// read once, by the next kernel, long after the L2 has turned over.
+__device__ __forceinline__ void store_nt(float4 *p, float4 v) {
+    __builtin_nontemporal_store(v.x, &p->x); __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z); __builtin_nontemporal_store(v.w, &p->w);
+}
+__device__ __forceinline__ void store_nt(double4 *p, double4 v) {
+    __builtin_nontemporal_store(v.x, &p->x); __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z); __builtin_nontemporal_store(v.w, &p->w);
+}
+
 template <bool FP32> struct Contrib;
 template <> struct Contrib<true> {
     using V = float4;
@@ -1198,9 +1209,9 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         double fa[3] = {-F[0], -F[1], -F[2]}, ta[3], tb[3];
         torque<FP32>(ra, fa, ta);
         torque<FP32>(rb, F, tb);
-        cS[e] = Contrib<FP32>::make(fa, 1.0);
-        cTs[e] = Contrib<FP32>::make(ta, 0.0);
-        cTt[e] = Contrib<FP32>::make(tb, 0.0);
+        store_nt(cS + e, Contrib<FP32>::make(fa, 1.0));
+        store_nt(cTs + e, Contrib<FP32>::make(ta, 0.0));
+        store_nt(cTt + e, Contrib<FP32>::make(tb, 0.0));
         if (rec) {
             S.rec_state[e] = 1; S.rec_delta[e] = delta;
             S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
