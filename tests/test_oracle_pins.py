@@ -146,6 +146,83 @@ def test_coulomb_cap_and_history_clamp():
     assert np.allclose(u[:2] / np.linalg.norm(u), slip, atol=1e-12) and u[2] == 0.0
 
 
+def _tangential_oscillator(cor, E=2e7, nu=0.25, r=1.5e-3, dl=3e-6, v0=1e-3, mu=0.9, h=1e-6, periods=4):
+    """A sphere pressed into a plane at a fixed overlap (its height and spin
+    held by prescribed motion, free along x, no gravity), launched along x.
+    Below the Coulomb cap the tangential spring-dashpot gives the damped
+    oscillator M x'' + gamma_t x' + S_t x = 0.  Returns the velocity along x
+    (a damped sinusoid like x itself, but its maxima are free of the one-step
+    lag between the tangential history and the position), the time step, and
+    the oscillator's undamped angular frequency and mass."""
+    t = I.sphere_template(r)
+    M = t[2]
+    d = I.assemble([t], [0], [(0, 0, r - dl)], [(1, 0, 0, 0)], [(v0, 0, 0)], [(0, 0, 0)], [(E, nu, mu, cor)],
+                   (0, 0, 0), (-0.1, -0.1, -0.1, 0.1, 0.1, 0.1), h,
+                   bnd=[dict(type=I.BND_PLANE, param=(0, 0, 0, 0, 0, 1), mat=(E, nu, mu, cor))],
+                   presc=[dict(clump=0, v_fixed=(0, 0, 0), free=(1, 0, 0), w_body=(0, 0, 0))])
+    St = 8.0 * gstar_same(E, nu) * math.sqrt(r * dl)  # Mindlin tangential stiffness
+    wn = math.sqrt(St / M)
+    n = int(periods * 2 * math.pi / wn / h)
+    o = oracle.Oracle(d)
+    xs, vs = np.empty(n), np.empty(n)
+    for k in range(n):
+        o.step(1)
+        s = o.state()
+        xs[k], vs[k] = s["x"][0, 0], s["v"][0, 0]
+    # the cap never engaged: the spring part alone stays well below mu |F_n|
+    Fn = 4.0 / 3.0 * estar_same(E, nu) * math.sqrt(r * dl) * dl
+    assert St * np.abs(xs).max() < 0.5 * mu * Fn
+    return vs, h, wn, M
+
+
+def _peaks(xs):
+    """Times (in steps, parabolic interpolation) and heights of the local maxima."""
+    k = np.nonzero((xs[1:-1] > xs[:-2]) & (xs[1:-1] >= xs[2:]))[0] + 1
+    a, b, c = xs[k - 1], xs[k], xs[k + 1]
+    off = 0.5 * (a - c) / (a - 2 * b + c)
+    return k + off, b - 0.25 * (a - c) * off
+
+
+@pytest.mark.parametrize("cor", [0.3, 0.5, 0.8])
+def test_tangential_dashpot_damping_ratio(cor):
+    """The tangential dashpot gamma_t = -2 sqrt(5/6) beta sqrt(S_t mbar), with
+    beta = ln e / sqrt(ln^2 e + pi^2) and mbar the clump mass against a wall,
+    gives a damping ratio zeta = sqrt(5/6) |beta| to the tangential
+    spring S_t = 8 G* sqrt(R delta).  A damped oscillator's successive maxima
+    fall one damped period 2 pi / (w_n sqrt(1 - zeta^2)) apart and shrink by
+    the log decrement 2 pi zeta / sqrt(1 - zeta^2).  Using S_n in gamma_t
+    (zeta off by sqrt(S_n / S_t), 8 % here) or dropping sqrt(5/6) (9.5 %)
+    fails the 1 % bound on zeta; a wrong S_t fails the period."""
+    xs, h, wn, M = _tangential_oscillator(cor)
+    le = math.log(cor)
+    beta = le / math.sqrt(le * le + math.pi ** 2)
+    zeta = math.sqrt(5.0 / 6.0) * abs(beta)
+    t, x = _peaks(xs)
+    assert len(t) >= 3
+    period = np.diff(t) * h
+    Td = 2 * math.pi / (wn * math.sqrt(1 - zeta ** 2))
+    assert np.all(np.abs(period / Td - 1) < 2e-3), (period, Td)
+    lam = np.log(x[:-1] / x[1:])
+    zeta_fit = lam / np.sqrt(4 * math.pi ** 2 + lam ** 2)
+    assert np.all(np.abs(zeta_fit / zeta - 1) < 1e-2), (zeta_fit, zeta)
+
+
+def test_tangential_dashpot_converges_first_order():
+    """Halving h moves the fitted damping ratio toward sqrt(5/6) |beta| at
+    first order (symplectic Euler with the history advanced by h v_t)."""
+    cor = 0.5
+    le = math.log(cor)
+    zeta = math.sqrt(5.0 / 6.0) * abs(le / math.sqrt(le * le + math.pi ** 2))
+    errs = []
+    for h in (4e-6, 2e-6, 1e-6):
+        xs, _, _, _ = _tangential_oscillator(cor, h=h, periods=3)
+        _, x = _peaks(xs)
+        lam = math.log(x[0] / x[1])
+        errs.append(abs(lam / math.sqrt(4 * math.pi ** 2 + lam ** 2) - zeta))
+    assert errs[2] < errs[1] < errs[0]
+    assert 1.5 < errs[0] / errs[1] < 2.7 and 1.5 < errs[1] / errs[2] < 2.7, errs
+
+
 def test_material_symmetry_and_mixing():
     """Swapping the two materials leaves |F| unchanged; the effective modulus is
     the textbook 1/((1-nu_a^2)/E_a + (1-nu_b^2)/E_b)."""
