@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CDEM_ABI_VERSION 1
+#define CDEM_ABI_VERSION 2
 
 /* ---- error codes ---- */
 #define CDEM_OK 0
@@ -66,8 +66,11 @@ extern "C" {
 
 typedef struct cdem_scene cdem_scene;
 
-/* Scene description.  Borrowed for the duration of cdem_create only; every
- * array is copied.  Pointers are host memory. */
+/* Scene description (the inputs of the model of Sec. 2.1: clumps of
+ * spheres with a mass and principal inertia per clump and E, nu, mu, CoR per
+ * sphere instance; the boundaries the contact geometry of Sec. 2.2 covers).
+ * Borrowed for the duration of cdem_create only; every array is copied.
+ * Pointers are host memory. */
 typedef struct cdem_scene_desc {
     double h;                          /* time step [s], > 0 */
     int32_t precision;                 /* CDEM_PREC_* */
@@ -103,13 +106,18 @@ typedef struct cdem_scene_desc {
 } cdem_scene_desc;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  NULL
- * means hipMalloc/hipFree.  alloc returns NULL on failure. */
+ * means stream-ordered hipMallocAsync / hipFreeAsync on the scene's stream.
+ * alloc returns NULL on failure; every block the library takes is returned
+ * through free before cdem_destroy returns. */
 typedef struct cdem_allocator {
     void *ctx;
     void *(*alloc)(void *ctx, size_t bytes, void *stream);
     void (*free)(void *ctx, void *ptr, void *stream);
 } cdem_allocator;
 
+/* Active-set update policy (Sec. 2.2: the active set is rebuilt every step,
+ * or every k steps with every contact geometry enlarged by a safety margin
+ * set by the maximum velocity and the time step). */
 typedef struct cdem_detect_params {
     int32_t mode;          /* CDEM_DETECT_* */
     int32_t k_max;         /* upper bound of the detection interval, 1..20 */
@@ -120,6 +128,7 @@ typedef struct cdem_detect_params {
     int32_t reserved;
 } cdem_detect_params;
 
+/* Counters of the scene (host copy of its device control block). */
 typedef struct cdem_counts {
     int64_t clumps, spheres, bins;
     int64_t candidates;   /* entries in the active set (both directions of a pair count once each) */
@@ -145,8 +154,14 @@ typedef struct cdem_state_view {
 /* Contacts of the last recorded step (see cdem_record_next_step), canonical:
  * sphere pairs a < b < n_spheres, boundary contacts b = n_spheres + index.
  * Only pairs whose exact predicate held that step (true contacts) are listed,
- * ascending by (a, b).  Host buffers of capacity 'cap'; *n receives the count
- * (call with cap = 0 to size).  F is the force on b; u the updated history. */
+ * ascending by (a, b).  Host buffers of capacity 'cap' (any may be NULL);
+ * *n receives the count (call with cap = 0 to size).  F is F_n + F_t of
+ * Eq. normal_tangential_force_model1/2 acting on body b (minus it acts on
+ * a); u the tangential history after the update and clamp of Eqs. updateUt
+ * and cappingOfut; Ta and Tb the torques r x F that the contact exerts on a
+ * and b, r from each body's reference point (a sphere's clump centre of
+ * mass; a boundary's reference point, its first three parameters moved with
+ * its translation) to the contact point of Eq. kinematicsContactInfo. */
 typedef struct cdem_contacts_view {
     int64_t cap;
     int64_t n;
@@ -154,8 +169,12 @@ typedef struct cdem_contacts_view {
     double *delta;   /* [cap] */
     double *F;       /* [cap][3] */
     double *u;       /* [cap][3] */
+    double *Ta;      /* [cap][3] */
+    double *Tb;      /* [cap][3] */
 } cdem_contacts_view;
 
+/* Result of an independent exact contact sweep (the enlarged geometry of
+ * Sec. 2.2 must never miss a contact). */
 typedef struct cdem_audit_result {
     int64_t true_contacts;  /* exact contacts found by the independent brute-force sweep */
     int64_t missed;         /* of those, absent from the active set */
@@ -163,26 +182,54 @@ typedef struct cdem_audit_result {
 } cdem_audit_result;
 
 /* ---- lifecycle ---- */
+/* CDEM_ABI_VERSION of the built library. */
 int cdem_abi_version(void);
+/* Name of a CDEM_* return code (static string, never NULL). */
 const char *cdem_strerror(int code);
-const char *cdem_last_error(const cdem_scene *s);   /* never NULL */
+/* Message of the scene's last failed call; with s = NULL, of the last failed
+ * cdem_create.  Never NULL; valid until the next call on the scene. */
+const char *cdem_last_error(const cdem_scene *s);
 
-/* Validate and copy the description to the device.  stream may be NULL.
- * On error *out is NULL and nothing is leaked. */
+/* Build a scene of clumps of spheres (Sec. 2.1, clump paragraph and Fig.
+ * "force": mass and inertia per clump, E, nu, mu, CoR per sphere): validate
+ * and copy the description to the device (host pointers, borrowed for the
+ * call).  alloc may be NULL; stream (a hipStream_t) may be NULL.  On error
+ * *out is NULL, nothing is leaked and CDEM_E_INVALID / CDEM_E_OOM /
+ * CDEM_E_HIP is returned. */
 int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc, void *stream, cdem_scene **out);
+/* Wait for the scene's stream, free every device block, free the scene. */
 int cdem_destroy(cdem_scene *s);
 
 /* ---- stepping ---- */
-/* Advance n >= 0 steps, enqueued on stream (NULL = the scene's stream).
- * Returns after enqueueing; synchronises only when the active set must grow. */
+/* Advance n >= 0 time steps of Sec. 2.1 / 2.2: the active set (rebuilt
+ * when due), each active pair's penetration, kinematics (Eq.
+ * kinematicsContactInfo) and force (Eqs. normal_tangential_force_model1/2,
+ * updateUt, cappingOfut), the sums onto clumps and the Newton-Euler update
+ * (Eq. newton_law_1/2).  Enqueued on stream (a hipStream_t; NULL = the
+ * scene's stream, which it then becomes).  Synchronises once at the end to
+ * check the device control block; an active set that overflowed its storage
+ * is grown and the abandoned steps are run again, bit for bit as if it had
+ * fitted.  CDEM_E_MISSED_CONTACT: a periodic audit found a contact outside
+ * the active set (the steps still ran); CDEM_E_NAN: a clump state became
+ * non-finite; CDEM_E_CAPACITY: the storage could not grow. */
 int cdem_step(cdem_scene *s, int64_t n, void *stream);
+/* Wait until the scene's stream has drained. */
 int cdem_sync(cdem_scene *s);
+/* Choose the active-set update policy of Sec. 2.2 (every step, or deferred
+ * with an enlarged contact geometry, by the fixed rule or by the learned
+ * envelopes).  Takes effect at the next step, which rebuilds the active set
+ * (tangential history of surviving pairs is kept).  CDEM_E_INVALID for
+ * out-of-range values; CDEM_E_STATE for the learned mode without MLP
+ * parameters. */
 int cdem_set_detection(cdem_scene *s, const cdem_detect_params *p);
-/* When on != 0, the next step stores per-contact penetration and force for
- * cdem_read_contacts. */
+/* When on != 0, the next step stores per-contact penetration, force and
+ * torques (for cdem_read_contacts, cdem_read_clump_forces and
+ * cdem_read_boundary_forces); allocates the recording buffers on first use. */
 int cdem_record_next_step(cdem_scene *s, int on);
 
-/* Run steps as replays of a captured HIP graph of `steps_per_graph` steps
+/* Batched scenes (independent scenes in one launch, each with its own bins,
+ * gravity and boundaries) as captured launch sequences.
+ * Run steps as replays of a captured HIP graph of `steps_per_graph` steps
  * (0 = launch kernel by kernel).  Detection scheduling lives on the device, so
  * one captured sequence serves every step; the graph is re-captured whenever
  * the scene's launch parameters change (regrow, detection settings, tuning).
@@ -197,30 +244,50 @@ int cdem_set_graph(cdem_scene *s, int32_t steps_per_graph);
 int cdem_autotune(cdem_scene *s, int32_t steps, double *bin_factor, int32_t *stride_cap);
 
 /* ---- reads and writes (synchronous) ---- */
+/* Counters of the scene's control block (waits for the scene's stream). */
 int cdem_get_counts(cdem_scene *s, cdem_counts *c);
-int cdem_read_state(cdem_scene *s, const cdem_state_view *v, int where);
-/* Overwrite the clump state; the active set is rebuilt before the next step
- * (tangential history of pairs that survive is kept). */
-int cdem_write_state(cdem_scene *s, const cdem_state_view *v, int where);
+/* Clump state (the unknowns of Eq. newton_law_1/2: CoM position and
+ * velocity, orientation, body-frame angular velocity) into the caller's
+ * buffers, host (where = CDEM_HOST) or device (CDEM_DEVICE).  Runs on
+ * stream (NULL = the scene's stream) after the work queued there, and
+ * returns once the copy is complete. */
+int cdem_read_state(cdem_scene *s, const cdem_state_view *v, int where, void *stream);
+/* Overwrite the clump state from the caller's buffers (host or device, on
+ * stream as above; host quaternions must be unit and values finite, else
+ * CDEM_E_INVALID and nothing changes).  The active set is rebuilt before the
+ * next step; tangential history of pairs that survive is kept (Eq.
+ * updateUt: the history lives as long as the contact). */
+int cdem_write_state(cdem_scene *s, const cdem_state_view *v, int where, void *stream);
+/* Per-contact data of the last recorded step (see cdem_contacts_view).
+ * CDEM_E_STATE when no step was recorded. */
 int cdem_read_contacts(cdem_scene *s, cdem_contacts_view *v);
-/* Per-clump force (contacts + gravity) and torque of the last recorded step,
- * host buffers [n_clumps][3]. */
+/* Per-clump force (contacts + gravity: the right-hand side of Eq.
+ * newton_law_1) and torque (the sum of r x (F_n + F_t) over the clump's
+ * contacts; Eq. newton_law_2 keeps r x F_t only, which is exact for one
+ * sphere but not for a clump whose contact points lie off its centre of
+ * mass) of the last recorded step, host buffers [n_clumps][3]. */
 int cdem_read_clump_forces(cdem_scene *s, double *F, double *T);
 /* Per-boundary force (what the spheres exert on it: the sum of minus the
  * contact forces on its spheres) and torque about its reference point (its
  * first three parameters, moved with its translation) at the last recorded
- * step; host buffers [n_bnd][3] in the description's boundary order.  The sum
- * runs in a fixed order: reproducible, equal to an ascending sum up to
- * rounding. */
+ * step: the readout a co-simulation takes from the granular side (Sec. 2.2,
+ * co-simulation with a multibody solver).  Host buffers [n_bnd][3] in the
+ * description's boundary order.  The sum runs in a fixed order:
+ * reproducible, equal to an ascending sum up to rounding. */
 int cdem_read_boundary_forces(cdem_scene *s, double *F, double *T);
-/* Sphere centres of the current state, host buffer [n_spheres][3]. */
+/* Sphere centres x_c + A(q) o_s of the current state (the clump
+ * representation of Sec. 2.1), host buffer [n_spheres][3]. */
 int cdem_read_sphere_pos(cdem_scene *s, double *xs);
 
 /* Independent exact contact sweep (no binning, no margin) over the current
- * state, compared with the active set.  O(N^2): for small scenes and tests. */
+ * state, compared with the active set: with the enlarged geometry of Sec.
+ * 2.2 every true contact must be in it.  O(N^2): scenes of up to 400k
+ * spheres (CDEM_E_INVALID beyond).  CDEM_E_MISSED_CONTACT when any is
+ * missing (r still filled). */
 int cdem_audit(cdem_scene *s, cdem_audit_result *r);
 
-/* ---- checkpoints ---- */
+/* ---- checkpoints (the tangential history of Eq. updateUt is state: a
+ * resumed run must carry it) ---- */
 /* Serialise the scene's dynamic state into a host buffer: clump state, step
  * counter, detection schedule and settings, the active set with its FP64
  * tangential history, the MLP parameters and the tuned launch settings.
@@ -246,9 +313,11 @@ int cdem_load(cdem_scene *s, const void *buf, size_t len);
  * log(f1 + 1e-3), log(1 + f2))), W1[64][3], b1[64], W2[64][64], b2[64],
  * W3[2][64], b3[2]. */
 int cdem_mlp_param_count(void);
-/* Load MLP parameters (host pointer, n = cdem_mlp_param_count()) into the scene. */
+/* Load MLP parameters (host pointer, n = cdem_mlp_param_count(), finite,
+ * positive standardisation scales; CDEM_E_INVALID otherwise) into the scene. */
 int cdem_set_mlp(cdem_scene *s, const float *params, int64_t n);
-/* Device pointers: features [n][3] (raw), out [n][2].  Asynchronous on stream. */
+/* Forward pass of the envelope MLP.  Device pointers: params, features
+ * [n][3] (raw), out [n][2].  Asynchronous on stream. */
 int cdem_mlp_forward(const float *params, const float *features, float *out, int64_t n, void *stream);
 /* Bytes of workspace cdem_mlp_backward needs for n samples. */
 size_t cdem_mlp_workspace_bytes(int64_t n);
@@ -272,7 +341,8 @@ int cdem_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t 
 int cdem_collect_envelopes(cdem_scene *s, int32_t horizon, float *features, float *labels, int64_t cap,
                            int64_t *n);
 
-/* ---- measurement (not part of the method) ---- */
+/* ---- measurement (not part of the method; where Sec. 2.2 says the time
+ * goes: identifying the active set) ---- */
 /* Per-kernel device time, measured with HIP events recorded on the launch
  * stream around every kernel while profiling is on. */
 typedef struct cdem_kernel_time {
@@ -281,14 +351,16 @@ typedef struct cdem_kernel_time {
     double total_ms;
 } cdem_kernel_time;
 
-/* on != 0 starts (and clears) per-kernel timing; on == 0 stops it. */
+/* on != 0 starts (and clears) per-kernel timing of every kernel; on == 0
+ * stops it. */
 int cdem_profile(cdem_scene *s, int on);
 /* Starts (and clears) timing of the named kernels only (comma-separated
  * names as cdem_profile_read reports them; null or "" = every kernel), so
  * that the events around the other kernels do not slow the steps.  Unknown
  * names only: CDEM_E_INVALID, timing off. */
 int cdem_profile_kernels(cdem_scene *s, const char *names);
-/* Copies up to cap records into out (host), *n receives the number of kernels. */
+/* Copies up to cap records into out (host), *n receives the number of
+ * kernels timed so far (waits for the scene's stream). */
 int cdem_profile_read(cdem_scene *s, cdem_kernel_time *out, int cap, int *n);
 /* True contacts (exact predicate, positive overlap) of the last completed
  * step, counted once per pair side (twice per sphere pair, once per boundary

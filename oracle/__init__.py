@@ -71,6 +71,7 @@ def lib():
             "dem_oracle_step": (V, [P, I64]), "dem_oracle_step_count": (I64, [P]),
             "dem_oracle_eval": (I64, [P]),
             "dem_oracle_read_contacts": (V, [P, P, P, P, P, P]),
+            "dem_oracle_read_contact_torques": (V, [P, P, P]),
             "dem_oracle_read_clump_forces": (V, [P, P, P]),
             "dem_oracle_read_sphere_forces": (V, [P, P, P]),
             "dem_oracle_read_boundary_forces": (V, [P, P, P]),
@@ -152,8 +153,10 @@ class Oracle:
         n = self._ncont
         a = np.empty(n, np.uint32); b = np.empty(n, np.uint32); dl = np.empty(n)
         F = np.empty((n, 3)); u = np.empty((n, 3))
+        Ta = np.empty((n, 3)); Tb = np.empty((n, 3))
         lib().dem_oracle_read_contacts(self._h, _ptr(a), _ptr(b), _ptr(dl), _ptr(F), _ptr(u))
-        return dict(a=a, b=b, delta=dl, F=F, u=u)
+        lib().dem_oracle_read_contact_torques(self._h, _ptr(Ta), _ptr(Tb))
+        return dict(a=a, b=b, delta=dl, F=F, u=u, Ta=Ta, Tb=Tb)
 
     def clump_forces(self):
         F = np.empty((self.n_clumps, 3)); T = np.empty((self.n_clumps, 3))

@@ -677,6 +677,18 @@ void dem_oracle_read_contacts(const dem_oracle *o, uint32_t *a, uint32_t *b, dou
     if (u && o->ncont) memcpy(u, o->cu, 3 * o->ncont * sizeof(double));
 }
 
+void dem_oracle_read_contact_torques(const dem_oracle *o, double *Ta, double *Tb) {
+    /* per contact of the last evaluation: the torque r x F the contact exerts
+     * on each body about its reference point (Eq. newton_law_2 with the
+     * lever arms of Eq. kinematicsContactInfo); body a receives -F, body b F */
+    for (int64_t k = 0; k < o->ncont; k++) {
+        const double *F = o->cF + 3 * k;
+        double f[3] = {-F[0], -F[1], -F[2]};
+        if (Ta) cross(o->cra + 3 * k, f, Ta + 3 * k);
+        if (Tb) cross(o->crb + 3 * k, F, Tb + 3 * k);
+    }
+}
+
 void dem_oracle_read_clump_forces(const dem_oracle *o, double *F, double *T) {
     if (F) memcpy(F, o->cFc, 3 * o->nc * sizeof(double));
     if (T) memcpy(T, o->cTc, 3 * o->nc * sizeof(double));

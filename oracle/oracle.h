@@ -84,6 +84,11 @@ int64_t dem_oracle_eval(dem_oracle *o);
  * Any output pointer may be NULL. */
 void dem_oracle_read_contacts(const dem_oracle *o, uint32_t *a, uint32_t *b, double *delta,
                               double *F, double *u);
+/* Per contact of the last evaluation (same order as read_contacts): the
+ * torque the contact exerts on body a (r_a x -F) and on body b (r_b x F),
+ * each about the body's reference point (a sphere's clump centre of mass, a
+ * boundary's reference point); [n][3] each, either may be NULL. */
+void dem_oracle_read_contact_torques(const dem_oracle *o, double *Ta, double *Tb);
 void dem_oracle_read_clump_forces(const dem_oracle *o, double *F, double *T);
 void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T);
 /* Force exerted on each boundary by the spheres (minus the contact forces on

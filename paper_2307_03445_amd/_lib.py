@@ -62,7 +62,8 @@ class StateViewC(C.Structure):
 
 
 class ContactsViewC(C.Structure):
-    _fields_ = [("cap", C.c_int64), ("n", C.c_int64), ("a", P), ("b", P), ("delta", P), ("F", P), ("u", P)]
+    _fields_ = [("cap", C.c_int64), ("n", C.c_int64), ("a", P), ("b", P), ("delta", P), ("F", P), ("u", P),
+                ("Ta", P), ("Tb", P)]
 
 
 class KernelTimeC(C.Structure):
@@ -85,8 +86,8 @@ SIGNATURES = {
     "cdem_set_detection": (C.c_int, [P, P]),
     "cdem_record_next_step": (C.c_int, [P, C.c_int]),
     "cdem_get_counts": (C.c_int, [P, P]),
-    "cdem_read_state": (C.c_int, [P, P, C.c_int]),
-    "cdem_write_state": (C.c_int, [P, P, C.c_int]),
+    "cdem_read_state": (C.c_int, [P, P, C.c_int, P]),
+    "cdem_write_state": (C.c_int, [P, P, C.c_int, P]),
     "cdem_read_contacts": (C.c_int, [P, P]),
     "cdem_read_clump_forces": (C.c_int, [P, P, P]),
     "cdem_read_sphere_pos": (C.c_int, [P, P]),
@@ -227,6 +228,9 @@ class Scene:
         except Exception:
             pass
 
+    def _sp(self):
+        return P(self._stream) if self._stream else None
+
     # ---------------------------------------------------------------- API
     def step(self, n: int = 1):
         self._check(self._L.cdem_step(self._h, int(n), P(self._stream) if self._stream else None))
@@ -251,21 +255,40 @@ class Scene:
         n = self.n_clumps
         out = dict(x=np.empty((n, 3)), q=np.empty((n, 4)), v=np.empty((n, 3)), w=np.empty((n, 3)))
         v = StateViewC(_ptr(out["x"]), _ptr(out["q"]), _ptr(out["v"]), _ptr(out["w"]))
-        self._check(self._L.cdem_read_state(self._h, C.byref(v), HOST))
+        self._check(self._L.cdem_read_state(self._h, C.byref(v), HOST, self._sp()))
         return out
+
+    def state_device(self) -> dict:
+        """The clump state copied into fresh torch device tensors (on the scene's stream)."""
+        import torch
+        n = self.n_clumps
+        out = {k: torch.empty((n, w), dtype=torch.float64, device="cuda") for k, w in
+               (("x", 3), ("q", 4), ("v", 3), ("w", 3))}
+        v = StateViewC(*[P(out[k].data_ptr()) for k in ("x", "q", "v", "w")])
+        self._check(self._L.cdem_read_state(self._h, C.byref(v), DEVICE, self._sp()))
+        return out
+
+    def write_state_device(self, x=None, q=None, v=None, w=None):
+        """Overwrite the clump state from contiguous float64 torch device tensors (None = keep)."""
+        for t in (x, q, v, w):
+            if t is not None and not (t.is_cuda and t.is_contiguous() and str(t.dtype) == "torch.float64"):
+                raise ValueError("device state must be contiguous float64 cuda tensors")
+        sv = StateViewC(*[None if t is None else P(t.data_ptr()) for t in (x, q, v, w)])
+        self._check(self._L.cdem_write_state(self._h, C.byref(sv), DEVICE, self._sp()))
 
     def write_state(self, x=None, q=None, v=None, w=None):
         arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (x, q, v, w)]
         sv = StateViewC(*[_ptr(a) for a in arrs])
-        self._check(self._L.cdem_write_state(self._h, C.byref(sv), HOST))
+        self._check(self._L.cdem_write_state(self._h, C.byref(sv), HOST, self._sp()))
 
     def contacts(self) -> dict:
-        v = ContactsViewC(0, 0, None, None, None, None, None)
+        v = ContactsViewC(0, 0, None, None, None, None, None, None, None)
         self._check(self._L.cdem_read_contacts(self._h, C.byref(v)))
         n = v.n
         out = dict(a=np.empty(n, np.uint32), b=np.empty(n, np.uint32), delta=np.empty(n),
-                   F=np.empty((n, 3)), u=np.empty((n, 3)))
-        v = ContactsViewC(n, 0, _ptr(out["a"]), _ptr(out["b"]), _ptr(out["delta"]), _ptr(out["F"]), _ptr(out["u"]))
+                   F=np.empty((n, 3)), u=np.empty((n, 3)), Ta=np.empty((n, 3)), Tb=np.empty((n, 3)))
+        v = ContactsViewC(n, 0, _ptr(out["a"]), _ptr(out["b"]), _ptr(out["delta"]), _ptr(out["F"]), _ptr(out["u"]),
+                          _ptr(out["Ta"]), _ptr(out["Tb"]))
         self._check(self._L.cdem_read_contacts(self._h, C.byref(v)))
         return out
 

@@ -30,10 +30,14 @@ hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v,
 }
 
 // Event pool for per-kernel timing (read after the stream is synchronised).
+// Brackets may nest (a bracket around a sequence of timed kernels): each
+// before() opens one, the matching after() closes the innermost.
 struct EventTimer : KernelTimer {
     std::vector<hipEvent_t> pool;
-    std::vector<int> ids;       // kernel id of each before/after pair
-    size_t used = 0;            // events in use (two per kernel launch)
+    struct Span { int id; size_t e0, e1; };
+    std::vector<Span> spans;    // closed brackets, in launch order
+    std::vector<Span> open;     // brackets awaiting their after()
+    size_t used = 0;            // events in use
     double total_ms[K_COUNT] = {};
     int64_t launches[K_COUNT] = {};
     bool sel[K_COUNT];          // kernels that are timed
@@ -49,24 +53,30 @@ struct EventTimer : KernelTimer {
     void before(int id, hipStream_t st) override {
         if (!sel[id]) return;
         hipEvent_t e = next();
-        if (e) { (void)hipEventRecord(e, st); ids.push_back(id); } else ids.push_back(-1);
+        if (e) (void)hipEventRecord(e, st);
+        open.push_back(Span{e ? id : -1, used - 1, 0});
     }
     void after(int id, hipStream_t st) override {
-        if (!sel[id]) return;
+        if (!sel[id] || open.empty()) return;
+        Span sp = open.back();
+        open.pop_back();
         hipEvent_t e = next();
         if (e) (void)hipEventRecord(e, st);
+        sp.e1 = used - 1;
+        if (!e) sp.id = -1;
+        spans.push_back(sp);
     }
-    // accumulate every recorded pair (the stream must be idle)
+    // accumulate every closed bracket (the stream must be idle)
     void harvest() {
-        for (size_t k = 0; k < ids.size() && 2 * k + 1 < used; k++) {
+        for (const Span &sp : spans) {
             float ms = 0.f;
-            if (ids[k] >= 0 && hipEventElapsedTime(&ms, pool[2 * k], pool[2 * k + 1]) == hipSuccess) {
-                total_ms[ids[k]] += ms;
-                launches[ids[k]]++;
+            if (sp.id >= 0 && hipEventElapsedTime(&ms, pool[sp.e0], pool[sp.e1]) == hipSuccess) {
+                total_ms[sp.id] += ms;
+                launches[sp.id]++;
             }
         }
-        ids.clear();
-        used = 0;
+        spans.clear();
+        if (open.empty()) used = 0;
     }
     ~EventTimer() override { for (auto e : pool) (void)hipEventDestroy(e); }
 };
@@ -175,12 +185,17 @@ static int fail(cdem_scene *s, int code, const std::string &msg) {
             return fail(sc, CDEM_E_HIP, std::string(#expr ": ") + hipGetErrorString(_e)); \
     } while (0)
 
+// Device blocks come from the caller's allocator, else from the stream-ordered
+// allocator on the scene's stream.  A block is used on that stream and, by
+// host copies, after the stream has been synchronised; the allocation itself
+// is synchronised once so that a block is valid on every stream and for
+// synchronous copies from the moment it is returned.
 static void *dev_alloc(cdem_scene *sc, size_t bytes) {
     if (bytes == 0) bytes = 256;
     void *p = nullptr;
     if (sc->custom_alloc) {
         p = sc->alloc.alloc(sc->alloc.ctx, bytes, (void *)sc->stream);
-    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    } else if (hipMallocAsync(&p, bytes, sc->stream) != hipSuccess || hipStreamSynchronize(sc->stream) != hipSuccess) {
         (void)hipGetLastError();
         p = nullptr;
     }
@@ -193,7 +208,7 @@ static void dev_free(cdem_scene *sc, void *p) {
     auto it = std::find(sc->owned.begin(), sc->owned.end(), p);
     if (it != sc->owned.end()) sc->owned.erase(it);
     if (sc->custom_alloc) sc->alloc.free(sc->alloc.ctx, p, (void *)sc->stream);
-    else (void)hipFree(p);
+    else (void)hipFreeAsync(p, sc->stream);
 }
 
 template <typename T>
@@ -304,8 +319,14 @@ static int build_grids(cdem_scene *sc) {
     return CDEM_OK;
 }
 
+// Pair and upper-entry offsets are 32-bit (segment starts, links): the
+// active set holds at most kMaxCap entries per buffer.
+constexpr int64_t kMaxCap = (int64_t)0xffffffffu;
+
 static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     DevScene &S = sc->S;
+    if (cap > kMaxCap)
+        return fail(sc, CDEM_E_CAPACITY, "the active set would exceed 2^32 - 1 entries (32-bit pair offsets)");
     uint32_t *pt[2];
     double *hs[2];
     for (int k = 0; k < 2; k++) {
@@ -344,7 +365,9 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     S.cap = cap;
     if (sc->rec_cap) {  // recording arrays follow the capacity
         dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
+        dev_free(sc, S.rec_Ta); dev_free(sc, S.rec_Tb);
         S.rec_state = nullptr; S.rec_delta = nullptr; S.rec_F = nullptr; S.rec_R = nullptr;
+        S.rec_Ta = nullptr; S.rec_Tb = nullptr;
         sc->rec_cap = 0;
     }
     return CDEM_OK;
@@ -532,10 +555,20 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.n_ablocks = (ns + 255) / 256;               // workgroups of the audit
     S.part_r = (uint32_t *)dev_alloc(sc, 12 * (S.n_rblocks + 256));  // + the folded partials
     S.part_a = (unsigned long long *)dev_alloc(sc, 16 * std::max<int64_t>(S.n_ablocks, 1));
-    if (!S.part_r || !S.part_a) return bail(fail(sc, CDEM_E_OOM, "partials"));
+    S.part_c = (uint32_t *)dev_alloc(sc, 4 * (size_t)kPairBlocksMax);
+    S.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
+    if (!S.part_r || !S.part_a || !S.part_c || !S.part_k) return bail(fail(sc, CDEM_E_OOM, "partials"));
     S.stride_cap = 16384;
     S.plan.k_max = 1; S.plan.audit_period = 0; S.plan.safety = 1.5f;
     S.plan.margin_cap = 0.0f; S.plan.margin_floor = 0.0f; S.plan.v_user = 0.0f; S.plan.test_zero_margin = 0;
+    {
+        double rs = 0.0;  // mean radius of the sphere instances (the interval rule's false-positive model)
+        for (int64_t c = 0; c < nc; c++) {
+            const uint32_t t = d->clump_template[c];
+            for (uint32_t i = d->tmpl_sphere_begin[t]; i < d->tmpl_sphere_begin[t + 1]; i++) rs += d->tmpl_radius[i];
+        }
+        S.plan.r_mean = ns ? (float)(rs / (double)ns) : 0.0f;
+    }
     // ---- device arrays
     int rc = CDEM_OK;
     {
@@ -656,6 +689,9 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     if (launch_zero(S.up_beg, 4 * (size_t)ns, sc->stream) != hipSuccess ||
         launch_zero(S.up_cnt, 4 * (size_t)ns, sc->stream) != hipSuccess)
         return bail(fail(sc, CDEM_E_HIP, "zero"));
+    if (launch_zero(S.part_c, 4 * (size_t)kPairBlocksMax, sc->stream) != hipSuccess ||
+        launch_zero(S.part_k, 2 * 8 * (size_t)kRegionBlocksMax, sc->stream) != hipSuccess)
+        return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (launch_zero(S.cacc, 4 * (size_t)nc, sc->stream) != hipSuccess ||
         launch_zero(S.sspeed, 4 * (size_t)ns, sc->stream) != hipSuccess ||
         launch_zero(S.cdet, 2 * sizeof(double4) * nc, sc->stream) != hipSuccess ||
@@ -675,6 +711,7 @@ extern "C" int cdem_destroy(cdem_scene *sc) {
     sc->timer = nullptr;
     auto owned = sc->owned;
     for (void *p : owned) dev_free(sc, p);
+    (void)hipStreamSynchronize(sc->stream);  // stream-ordered frees complete before the scene is gone
     delete sc;
     return CDEM_OK;
 }
@@ -773,6 +810,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         // grow the active set and resume from the step that did not complete
         int64_t need = (int64_t)(1.3 * (double)std::max(c.n_up, c.n_pairs)) + 1024;
         int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
+        if (cap > kMaxCap && std::max(c.n_up, c.n_pairs) < kMaxCap) cap = kMaxCap;
         if ((rc = alloc_active_set(sc, cap, true)) != CDEM_OK) return rc;
         sc->regrows++;
         c.overflow = 0;
@@ -831,11 +869,15 @@ extern "C" int cdem_record_next_step(cdem_scene *sc, int on) {
     DevScene &S = sc->S;
     if (on && sc->rec_cap < S.cap) {
         dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
+        dev_free(sc, S.rec_Ta); dev_free(sc, S.rec_Tb);
         S.rec_state = (uint8_t *)dev_alloc(sc, S.cap);
         S.rec_delta = (double *)dev_alloc(sc, 8 * S.cap);
         S.rec_F = (double *)dev_alloc(sc, 24 * S.cap);
         S.rec_R = (double *)dev_alloc(sc, 24 * S.cap);
-        if (!S.rec_state || !S.rec_delta || !S.rec_F || !S.rec_R) return fail(sc, CDEM_E_OOM, "recording buffers");
+        S.rec_Ta = (double *)dev_alloc(sc, 24 * S.cap);
+        S.rec_Tb = (double *)dev_alloc(sc, 24 * S.cap);
+        if (!S.rec_state || !S.rec_delta || !S.rec_F || !S.rec_R || !S.rec_Ta || !S.rec_Tb)
+            return fail(sc, CDEM_E_OOM, "recording buffers");
         sc->rec_cap = S.cap;
     }
     Ctl c;
@@ -900,9 +942,10 @@ static int state_from_host(cdem_scene *sc, const double *x, const double *q, con
     return CDEM_OK;
 }
 
-extern "C" int cdem_read_state(cdem_scene *sc, const cdem_state_view *v, int where) {
+extern "C" int cdem_read_state(cdem_scene *sc, const cdem_state_view *v, int where, void *stream) {
     if (!sc || !v || (where != CDEM_HOST && where != CDEM_DEVICE)) return fail(sc, CDEM_E_INVALID, "bad arguments");
     const DevScene &S = sc->S;
+    if (stream) sc->stream = (hipStream_t)stream;
     HIPCHK(hipStreamSynchronize(sc->stream));
     if (where == CDEM_DEVICE) {
         HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 0, sc->stream));
@@ -912,10 +955,11 @@ extern "C" int cdem_read_state(cdem_scene *sc, const cdem_state_view *v, int whe
     return state_to_host(sc, v->x, v->q, v->v, v->w);
 }
 
-extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int where) {
+extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int where, void *stream) {
     if (!sc || !v || (where != CDEM_HOST && where != CDEM_DEVICE)) return fail(sc, CDEM_E_INVALID, "bad arguments");
     const DevScene &S = sc->S;
     int64_t nc = S.nc;
+    if (stream) sc->stream = (hipStream_t)stream;
     HIPCHK(hipStreamSynchronize(sc->stream));
     if (where == CDEM_DEVICE) {
         HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 1, sc->stream));
@@ -962,7 +1006,7 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
     int64_t ne = c.n_pairs_cur, ns = S.ns;
     std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
     std::vector<uint8_t> st(ne);
-    std::vector<double> dl(ne), F(3 * ne), H(3 * ne);
+    std::vector<double> dl(ne), F(3 * ne), H(3 * ne), Ta(v->Ta ? 3 * ne : 0), Tb(v->Tb ? 3 * ne : 0);
     if (ns) {
         HIPCHK(hipMemcpy(beg.data(), S.lo_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(cnt.data(), S.lo_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
@@ -973,6 +1017,8 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
         HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(F.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(H.data(), S.hist[cur], 24 * ne, hipMemcpyDeviceToHost));
+        if (v->Ta) HIPCHK(hipMemcpy(Ta.data(), S.rec_Ta, 24 * ne, hipMemcpyDeviceToHost));
+        if (v->Tb) HIPCHK(hipMemcpy(Tb.data(), S.rec_Tb, 24 * ne, hipMemcpyDeviceToHost));
     }
     struct Row { uint64_t key; int64_t e; };
     std::vector<Row> rows;
@@ -999,6 +1045,8 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
         for (int k = 0; k < 3; k++) {
             if (v->F) v->F[3 * i + k] = F[3 * e + k];
             if (v->u) v->u[3 * i + k] = H[3 * e + k];
+            if (v->Ta) v->Ta[3 * i + k] = Ta[3 * e + k];
+            if (v->Tb) v->Tb[3 * i + k] = Tb[3 * e + k];
         }
     }
     return CDEM_OK;
@@ -1359,7 +1407,7 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
         if ((rc = cdem_set_mlp(sc, w, (size_t)cdem_mlp_param_count())) != CDEM_OK) return rc;
     }
     sc->bin_factor = hd.bin_factor > 0.0 ? hd.bin_factor : 1.0;
-    S.stride_cap = hd.stride_cap > 0 ? hd.stride_cap : 16384;
+    S.stride_cap = hd.stride_cap > 0 && hd.stride_cap <= 16384 ? hd.stride_cap : 16384;
     if ((rc = cdem_set_detection(sc, &hd.det)) != CDEM_OK) return rc;
     if (E > S.cap && (rc = alloc_active_set(sc, E + E / 4 + 1024, false)) != CDEM_OK) return rc;
     Ctl c;

@@ -71,6 +71,10 @@ struct Ctl {
     int64_t n_bp;            // boundary pairs written by the detection in progress
     int32_t guard_next;      // guard trips of the clumps integrated outside the wave reduction
     int32_t pad2;
+    // interval rule of the learned envelopes: the modelled bytes per step
+    int64_t contact_sides_last;  // contact sides of the last completed step (2 per sphere pair, 1 per boundary)
+    double c_cal;                // measured / modelled false-positive pairs at the last detection (0: none yet)
+    double dpred_last;           // modelled false-positive pairs per sphere of the set in use (0: none)
 };
 
 // Detection plan parameters (fixed rule), set by cdem_set_detection.
@@ -82,7 +86,7 @@ struct Plan {
     float margin_floor;
     float v_user;            // a-priori speed bound (0 = measured)
     int32_t test_zero_margin; // testing aid: margins forced to zero
-    int32_t pad;
+    float r_mean;            // mean sphere radius (the false-positive model of the interval rule)
 };
 
 // Everything a step kernel needs, by value (kernel argument).
@@ -145,6 +149,8 @@ struct DevScene {
     uint32_t *part_r;                 // [n_rblocks + 256][3] reduction: max acceleration, max speed, guard trip
     int64_t n_rblocks;
     unsigned long long *part_a;       // [n_ablocks][2] audit: true contacts, missed
+    uint32_t *part_c;                 // [pair_blocks] contact sides counted by each workgroup of k_pairs
+    double *part_k;                   // [2][region-kernel workgroups] sums of the interval rule's margin model
     int64_t n_ablocks;
     uint32_t *over_list;             // [over_cap] spheres whose rows k_narrow_over fills
     int64_t over_cap;
@@ -152,6 +158,7 @@ struct DevScene {
     uint8_t *rec_state;              // per pair of the recorded step
     double *rec_delta, *rec_F;       // [cap], [cap][3] (F: on the partner body b)
     double *rec_R;                   // [cap][3] boundary pairs: contact point relative to the boundary's reference point
+    double *rec_Ta, *rec_Tb;         // [cap][3] torque on body a / body b about its reference point
     double *rec_cF, *rec_cT;         // [nc][3]
     const Bnd *bnd;
     Ctl *ctl;
@@ -187,6 +194,23 @@ struct DevScene {
     int32_t pad3;
 };
 
+// Workgroups of the grid-stride kernels over the active set (k_pairs, k_link):
+// enough for every slot of the storage, at most the tuned stride cap.
+constexpr int kPairBlocksMax = 16384;
+__host__ __device__ inline unsigned pair_blocks(int64_t cap, int32_t stride_cap) {
+    const int64_t c = stride_cap > 0 && stride_cap < kPairBlocksMax ? stride_cap : kPairBlocksMax;
+    int64_t n = (cap + 255) / 256;
+    n = n < c ? n : c;
+    return (unsigned)(n > 1 ? n : 1);
+}
+// Workgroups of the kernels over the envelope regions.
+constexpr int kRegionBlocksMax = 16384;
+__host__ __device__ inline unsigned region_blocks(int64_t n_regions) {
+    int64_t n = (n_regions + 255) / 256;
+    n = n < kRegionBlocksMax ? n : kRegionBlocksMax;
+    return (unsigned)(n > 1 ? n : 1);
+}
+
 // Optional per-kernel timing: when non-null, launchers bracket every kernel
 // with events taken from the pool and note which kernel each pair belongs to.
 struct KernelTimer {
@@ -196,7 +220,8 @@ struct KernelTimer {
 };
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
-                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_GUARD_BIG, K_BINS_BEGIN, K_COUNT };
+                K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_GUARD_BIG, K_BINS_BEGIN,
+                K_AUDIT_ALL, K_PICK_INTERVAL, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 

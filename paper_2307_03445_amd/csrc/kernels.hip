@@ -1,26 +1,40 @@
 // HIP kernels of the clumped-sphere DEM step (gfx950, wave64).
 //
-// One step (paper Sec. 2.1 / 2.2):
-//   k_pose           sphere centres x_s = x_c + A(q) o_s and per-clump kinematics
-//                    (multi-sphere clumps, Sec. 2.1); displacement guard when
-//                    detection is deferred;
-//   detection        (only when due) per-scene uniform bins: count, scan, scatter;
-//                    k_narrow tests the 27 neighbour bins of every sphere with the
-//                    enlarged geometry of Sec. 2.2, keeps each sphere's candidates
-//                    sorted by partner id in LDS, allocates rows with a wavefront
-//                    scan and carries the tangential history of surviving pairs;
-//   k_force_integrate per clump: every sphere's active-set row is evaluated with
-//                    the Hertz-Mindlin law (Eqs. normal_tangential_force_model1/2,
-//                    kinematicsContactInfo, updateUt, cappingOfut), summed per
-//                    sphere in ascending partner id and per clump in ascending
-//                    sphere id, then integrated (Eq. newton_law_1/2, symplectic
-//                    Euler with the gyroscopic term).
+// One step (paper Sec. 2.1 / 2.2), launched as a static sequence whose work
+// the device-resident control block switches on and off:
+//   k_bins_begin, k_pose  sphere centres x_s = x_c + A(q) o_s from each
+//                    clump's state record (multi-sphere clumps, Sec. 2.1),
+//                    only on steps that detect or audit; the same pass
+//                    counts spheres into per-scene uniform bins and gathers
+//                    the learned envelopes' region features;
+//   detection        (when due: every step, or every k steps with the
+//                    enlarged contact geometry of Sec. 2.2) scan of the bin
+//                    counts, scatter into bin order, k_narrow: FP32
+//                    prefilter over the bins in reach, exact FP64 predicate,
+//                    candidates sorted by partner id in LDS, segments
+//                    allocated per workgroup, tangential history carried
+//                    over from the current active set; k_link points each
+//                    higher sphere's entry at its pair;
+//   k_pairs          every candidate pair once, one lane per pair: exact
+//                    predicate, kinematics of Eq. kinematicsContactInfo and
+//                    the Hertz-Mindlin law of Eqs. normal_tangential_force_model1/2,
+//                    updateUt and cappingOfut; the force and both torques go
+//                    to per-pair contribution slots;
+//   k_reduce_waves   one lane per sphere: its contributions in ascending
+//                    partner id, then per clump its spheres in ascending id,
+//                    + M g, symplectic Euler of Eq. newton_law_1/2 with the
+//                    gyroscopic term, and the displacement guard of
+//                    deferred detection (clumps of more than 64 spheres
+//                    through k_reduce_big_spheres / k_integrate_big /
+//                    k_guard_big);
+//   k_step_end       folds the per-workgroup partials and schedules the next
+//                    detection and audit (k_audit_cells: exact binned check
+//                    that every contact is in the active set).
 //
-// Every pair is evaluated in both partners' rows with the lower sphere id as
-// body a, so the two copies are bit-identical and each row owns its history;
-// no atomics touch any floating-point result, so the step is deterministic.
-// Compiled with -ffp-contract=off: the FP64 path performs exactly the IEEE
-// operations written, in the order written.
+// No atomic touches a floating-point result and every sum runs in a fixed
+// order, so the step is deterministic.  Compiled with -ffp-contract=off: the
+// FP64 path performs exactly the IEEE operations written, in the order
+// written.
 #include "cdem_internal.h"
 #include "mlp_dev.h"
 
@@ -278,13 +292,16 @@ __device__ __forceinline__ uint32_t xcd_block() {
 // (on a step that also detects, the audit uses the detection's bins: the
 // sorted records then carry the margins, which only widens its prefilter)
 __device__ __forceinline__ bool chain_active(const DevScene &S, int which) {
-    return which == 2 ? true : which ? audit_due(S) && S.ctl->since_det != 0 : due(S.ctl);
+    if (which == 2) return true;
+    if (aborted(S.ctl)) return false;  // the step is abandoned until the active set has grown
+    return which ? audit_due(S) && S.ctl->since_det != 0 : due(S.ctl);
 }
 
 // Start of a step that bins the spheres (a detection or an audit): clear the
 // bin counters, the region features of the learned margins and the step's
 // detection or audit counters.  k_pose then counts the spheres into the bins.
 __global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
+    if (aborted(S.ctl)) return;
     const bool det = due(S.ctl), aud = audit_due(S);
     if (!(det || aud)) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -313,7 +330,7 @@ __global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
 __global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
     const Ctl *ctl = S.ctl;
     const bool det = due(ctl), aud = audit_due(S);
-    if (!force && !(det || aud || ctl->collecting)) return;
+    if (!force && (aborted(ctl) || !(det || aud || ctl->collecting))) return;
     const bool bin = !force && (det || aud);
     const bool feat = bin && det && S.detect_mode == 2;
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -518,7 +535,7 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
 // stays below the cap.  A sphere that still outruns it trips the guard.
 __global__ void k_plan(DevScene S) {
     Ctl *c = S.ctl;
-    if (!due(c)) return;
+    if (!due(c) || aborted(c)) return;
     if (S.detect_mode == 0) { c->margin_cur = 0.0f; c->k_cur = 1; return; }
     if (S.detect_mode == 2) {  // per-region margins; k_bin_margin may shorten the interval
         c->k_cur = S.plan.k_max;
@@ -587,7 +604,7 @@ __global__ void __launch_bounds__(256) k_bin_features(DevScene S, int which) {
 // region (reduced on the device; k_plan starts it at k_max).
 __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
     Ctl *c = S.ctl;
-    if (!due(c) || S.detect_mode != 2) return;
+    if (!due(c) || aborted(c) || S.detect_mode != 2) return;
     __shared__ float P[kMlpParams];
     __shared__ __align__(16) float Wt[kMlpH * kMlpH];  // second-layer weights, transposed
     for (int i = threadIdx.x; i < kMlpParams; i += blockDim.x) P[i] = S.mlp[i];
@@ -599,6 +616,10 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
     const int kmax = S.plan.k_max;
     uint32_t nfb = 0;
     int kmin = kmax;
+    // the interval rule's false-positive model: sums over the regions of
+    // n_r rho_r v_env and n_r rho_r a_env (n_r spheres in the region, rho_r
+    // their number density)
+    double wv = 0.0, wa = 0.0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
          r += (int64_t)gridDim.x * blockDim.x) {
         uint32_t occ = S.reg_occ[r];
@@ -619,6 +640,17 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
         ae = fmaxf(ae, an);
         S.bin_v[r] = __float_as_uint(ve);
         S.bin_a[r] = __float_as_uint(ae);
+        {
+            int lo = 0, hi = S.n_scenes - 1;  // the region's scene: grids are in region order
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.grids[mid].reg0 <= r) lo = mid; else hi = mid - 1;
+            }
+            const double edge = (double)kRegionBins * S.grids[lo].b;
+            const double w = (double)occ * ((double)occ / (edge * edge * edge));
+            wv += w * (double)ve;
+            wa += w * (double)ae;
+        }
         int k = kmax;
         for (; k > 1; k--) {
             const double T = (double)k * S.h;
@@ -629,18 +661,83 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
     for (int off = 32; off > 0; off >>= 1) {
         nfb += __shfl_xor(nfb, off, 64);
         kmin = min(kmin, __shfl_xor(kmin, off, 64));
+        wv += __shfl_xor(wv, off, 64);
+        wa += __shfl_xor(wa, off, 64);
     }
+    __shared__ double ws[2][4];
     if ((threadIdx.x & 63) == 0) {
         if (nfb) atomicAdd((unsigned long long *)&c->fallbacks, (unsigned long long)nfb);
         if (kmin < kmax) atomicMin(&c->k_cur, kmin);
+        ws[0][threadIdx.x >> 6] = wv;
+        ws[1][threadIdx.x >> 6] = wa;
     }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // this workgroup's sums, in a fixed order
+        S.part_k[blockIdx.x] = ((ws[0][0] + ws[0][1]) + ws[0][2]) + ws[0][3];
+        S.part_k[kRegionBlocksMax + blockIdx.x] = ((ws[1][0] + ws[1][1]) + ws[1][2]) + ws[1][3];
+    }
+}
+
+// Detection interval of the learned envelopes: the k <= k_fit (the longest
+// interval whose margins fit the cap in every region, found above) that
+// minimises the modelled bytes per sphere-step of the deferred path,
+//   B(k) = 8 (p_m - p) + (244 + 72 p_m) / k  (+ terms that do not depend on k),
+// p the contact pairs per sphere of the last step and p_m = p + D(k) the
+// candidate pairs per sphere, with D(k) the false positives the margins
+// m_r(k) = safety k h v_r + (k h)^2 a_r / 2 add: each sphere of region r
+// finds rho_r 4 pi (2 R)^2 (2 m_r) extra partners in the shell the margins
+// add (R the mean radius), so D(k) = c 16 pi R^2 sum_r n_r rho_r m_r(k) / N,
+// with c the ratio of the measured to the modelled false positives of the
+// set in use (the density next to a contact is not the mean density).  The
+// 8 B per false positive and the 244 + 72 p_m B per detection are the
+// per-unit terms of the deferred path's byte model.  One workgroup; the
+// workgroup sums of the margin model are added in a fixed order.
+__global__ void __launch_bounds__(256) k_pick_interval(DevScene S, unsigned nblk) {
+    Ctl *c = S.ctl;
+    if (!due(c) || aborted(c) || S.detect_mode != 2) return;
+    __shared__ double sv[256], sa[256];
+    double v = 0.0, a = 0.0;
+    for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
+        v += S.part_k[b];
+        a += S.part_k[kRegionBlocksMax + b];
+    }
+    sv[threadIdx.x] = v;
+    sa[threadIdx.x] = a;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sv[threadIdx.x] += sv[threadIdx.x + w];
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double ns = (double)(S.ns > 0 ? S.ns : 1);
+    const double p = (double)c->contact_sides_last / 2.0 / ns;
+    if (c->dpred_last > 0.0 && c->n_pairs_cur > 0) {  // calibrate on the set in use
+        const double meas = (double)c->n_pairs_cur / ns - p;
+        c->c_cal = fmin(fmax(meas / c->dpred_last, 0.05), 20.0);
+    }
+    const double cal = c->c_cal > 0.0 ? c->c_cal : 1.0;
+    const double G = 16.0 * 3.14159265358979323846 * (double)S.plan.r_mean * (double)S.plan.r_mean / ns;
+    const int kfit = c->k_cur;
+    int best = kfit;
+    double bestB = 1e300, bestD = 0.0;
+    for (int k = 1; k <= kfit; k++) {
+        const double T = (double)k * S.h;
+        const double D = G * ((double)S.plan.safety * T * sv[0] + 0.5 * T * T * sa[0]);
+        const double B = 8.0 * cal * D + (244.0 + 72.0 * (p + cal * D)) / (double)k;
+        if (B < bestB) { bestB = B; best = k; bestD = D; }
+    }
+    c->k_cur = best;
+    c->dpred_last = bestD;
 }
 
 // Margin of every occupied region for the interval chosen above (clamped to
 // [floor, cap]: a region that still needs more relies on the guard).
 __global__ void __launch_bounds__(256) k_region_margin(DevScene S) {
     const Ctl *c = S.ctl;
-    if (!due(c) || S.detect_mode != 2) return;
+    if (!due(c) || aborted(c) || S.detect_mode != 2) return;
     const double T = (double)c->k_cur * S.h;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
          r += (int64_t)gridDim.x * blockDim.x) {
@@ -832,7 +929,12 @@ __device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32
 // filled by k_narrow_over.  Segments are allocated with one atomic per
 // wavefront and kind (upper entries, pairs).
 __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
-    if (!due(S.ctl)) return;
+    // overflow may be raised by other workgroups of this launch: one read per
+    // workgroup keeps the decision uniform across its barriers
+    __shared__ int skip;
+    if (threadIdx.x == 0) skip = !due(S.ctl) || aborted(S.ctl);
+    __syncthreads();
+    if (skip) return;
     __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
@@ -1214,7 +1316,9 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         store_nt(cTt + e, Contrib<FP32>::make(tb, 0.0));
         if (rec) {
             S.rec_state[e] = 1; S.rec_delta[e] = delta;
-            S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
+            for (int i = 0; i < 3; i++) {
+                S.rec_F[3 * e + i] = F[i]; S.rec_Ta[3 * e + i] = ta[i]; S.rec_Tb[3 * e + i] = tb[i];
+            }
         }
         return 2;
     }
@@ -1261,8 +1365,12 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     cTs[e] = Contrib<FP32>::make(tb, 0.0);
     if (rec) {
         S.rec_state[e] = 1; S.rec_delta[e] = delta;
-        S.rec_F[3 * e] = F[0]; S.rec_F[3 * e + 1] = F[1]; S.rec_F[3 * e + 2] = F[2];
-        S.rec_R[3 * e] = ra[0]; S.rec_R[3 * e + 1] = ra[1]; S.rec_R[3 * e + 2] = ra[2];
+        double fw[3] = {-F[0], -F[1], -F[2]}, tw[3];  // the boundary receives -F at the contact point
+        cross3(ra, fw, tw);
+        for (int i = 0; i < 3; i++) {
+            S.rec_F[3 * e + i] = F[i]; S.rec_R[3 * e + i] = ra[i];
+            S.rec_Ta[3 * e + i] = tw[i]; S.rec_Tb[3 * e + i] = tb[i];
+        }
     }
     return 1;
 }
@@ -1289,13 +1397,20 @@ __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
     uint32_t s2 = 0, t2 = 0;
     if (e < n) now = pair_ids(S, S.ps[e], pt[e]);
     if (e + stride < n) { s2 = S.ps[e + stride]; t2 = pt[e + stride]; }
+    uint32_t sides = 0;  // contact sides this lane created
     for (; e < n; e += stride) {
         PairIds nxt{};
         if (e + stride < n) nxt = pair_ids(S, s2, t2);
         if (e + 2 * stride < n) { s2 = S.ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
-        (void)eval_pair<FP32>(S, e, now, hist, tnow, rec);
+        sides += eval_pair<FP32>(S, e, now, hist, tnow, rec);
         now = nxt;
     }
+    // the workgroup's count, for the interval rule (folded by k_step_end)
+    for (int off = 32; off > 0; off >>= 1) sides += __shfl_xor(sides, off, 64);
+    __shared__ uint32_t wsides[4];
+    if ((threadIdx.x & 63) == 0) wsides[threadIdx.x >> 6] = sides;
+    __syncthreads();
+    if (threadIdx.x == 0) S.part_c[blockIdx.x] = wsides[0] + wsides[1] + wsides[2] + wsides[3];
 }
 
 // Contact sides of the last evaluated step (each sphere pair in contact counts
@@ -1733,11 +1848,24 @@ __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     }
     if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = am; sh[1][threadIdx.x >> 6] = vm; sh[2][threadIdx.x >> 6] = tr; }
     __syncthreads();
+    // contact sides of the step, from the pair kernel's workgroups
+    unsigned long long ncs = 0;
+    if (ok) {
+        const unsigned pb = pair_blocks(S.cap, S.stride_cap);
+        for (unsigned k = threadIdx.x; k < pb; k += blockDim.x) ncs += S.part_c[k];
+    }
+    for (int off = 32; off > 0; off >>= 1) ncs += __shfl_xor(ncs, off, 64);
+    __shared__ unsigned long long shc[16];
+    if ((threadIdx.x & 63) == 0) shc[threadIdx.x >> 6] = ncs;
+    __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int k = 1; k < (int)(blockDim.x >> 6); k++) { am = max(am, sh[0][k]); vm = max(vm, sh[1][k]); tr |= sh[2][k]; }
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+        am = max(am, sh[0][k]); vm = max(vm, sh[1][k]); tr |= sh[2][k]; ncs += shc[k];
+    }
     am = max(am, sh[0][0]); vm = max(vm, sh[1][0]); tr |= sh[2][0];
     c->record = 0;
     if (!ok) return;
+    c->contact_sides_last = (int64_t)ncs;
     // the clumps too big for one wavefront report through the atomic slots
     c->amax_last = S.detect_mode != 0 ? max(c->amax_bits, am) : 0u;
     c->amax_bits = 0;
@@ -1800,7 +1928,8 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // Exact contacts of the current positions, found in freshly built bins with no
 // margin, must each be in both partners' rows of the active set.
 __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
-    if (!audit_due(S)) return;
+    // an abandoned step (active-set overflow) is audited when it is run again
+    if (!audit_due(S) || aborted(S.ctl)) return;
     __shared__ uint32_t alst[kMaxRow * 256];
     int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
     unsigned long long found = 0, missed = 0;
@@ -1896,7 +2025,7 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
 }
 
 __global__ void __launch_bounds__(1024) k_audit_end(DevScene S) {
-    if (!audit_due(S)) return;
+    if (!audit_due(S) || aborted(S.ctl)) return;
     unsigned long long f = 0, m = 0;
     for (int64_t k = threadIdx.x; k < S.n_ablocks; k += blockDim.x) { f += S.part_a[2 * k]; m += S.part_a[2 * k + 1]; }
     __shared__ unsigned long long sh[2][16];
@@ -1974,7 +2103,8 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_detect_end", "k_pairs", "k_reduce_big_spheres",
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
-                                           "k_narrow_over", "k_region_margin", "k_guard_big", "k_bins_begin"};
+                                           "k_narrow_over", "k_region_margin", "k_guard_big", "k_bins_begin",
+                                           "audit_total", "k_pick_interval"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -2015,8 +2145,10 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
         return;
     }
     if (which == 0 && S.detect_mode == 2) {
-        TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
-        TIMED(K_REGION_MARGIN, hipLaunchKernelGGL(k_region_margin, dim3(stride_blocks(S.n_regions)), dim3(256), 0, st, S));
+        const unsigned rb = region_blocks(S.n_regions);
+        TIMED(K_BIN_MARGIN, hipLaunchKernelGGL(k_bin_margin, dim3(rb), dim3(256), 0, st, S));
+        TIMED(K_PICK_INTERVAL, hipLaunchKernelGGL(k_pick_interval, dim3(1), dim3(256), 0, st, S, rb));
+        TIMED(K_REGION_MARGIN, hipLaunchKernelGGL(k_region_margin, dim3(rb), dim3(256), 0, st, S));
     }
     int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
     uint32_t *bsum = S.scan_bsum;
@@ -2068,18 +2200,22 @@ hipError_t launch_collect_acc(const DevScene &S, hipStream_t st) {
     return hipGetLastError();
 }
 
+// (the whole chain is also timed as one bracket, "audit_total": its binning,
+// the exact check and the fold; the kernels do work on audit steps only)
 hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     if (S.ns == 0 || S.plan.audit_period <= 0) return hipSuccess;
+    if (g_timer) g_timer->before(K_AUDIT_ALL, st);
     binning(S, 1, st);
     TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
     hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1024), 0, st, S);
+    if (g_timer) g_timer->after(K_AUDIT_ALL, st);
     return hipGetLastError();
 }
 
 hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
     if (S.nc == 0) return hipSuccess;
     const bool f32 = S.precision == 1;
-    const unsigned pb = stride_blocks(S.cap, S.stride_cap);
+    const unsigned pb = pair_blocks(S.cap, S.stride_cap);
     if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
     else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);

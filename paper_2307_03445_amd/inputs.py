@@ -55,8 +55,8 @@ DENSITY = 2600.0
 
 def rng(stream: int, replica: int = 0) -> np.random.Generator:
     """Generator of seed stream ``stream`` (one per workload: 1 walled box,
-    2 bed templates, 4 funnels, 5 rover bed, 6 and 7 statistics scenes) and
-    replica."""
+    2 bed templates, 4 funnels, 5 rover bed, 6 and 7 statistics scenes, 8 cone
+    bed, 9 drum) and replica."""
     return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(stream, replica)))
 
 
@@ -341,7 +341,8 @@ def quat_matrix(q: np.ndarray) -> np.ndarray:
         np.stack([2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)], -1)], -2)
 
 
-def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_max, floor_z=0.0):
+def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_max, floor_z=0.0, floor=None,
+            edge=None, pre=None):
     """Drop clumps one by one onto a growing pile.
 
     Each clump gets a uniformly random orientation and a uniformly random
@@ -349,13 +350,19 @@ def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_m
     vertically to the highest position at which one of its spheres first
     touches an already placed sphere or the floor, and is then lowered by a
     random sink ~ U[0, sink_max] so that it rests with a small overlap.
-    This is a geometric construction of a contact-rich initial state; no
-    dynamics is simulated.  Returns (x[n,3], q[n,4]).
+    ``floor(px, py, r)`` (arrays) may give the lowest centre height of a
+    sphere of radius r at (px, py) for a floor other than the plane
+    z = floor_z (a drum's curved bottom).  ``edge = (p, axes)`` places a
+    clump, with probability p, flush against the low or high side of the
+    footprint along one of ``axes`` ("x", "y" or "xy"), pressed into it by
+    U[0, sink_max] (contacts with side walls and end caps).  ``pre`` lists
+    poses (x[3], q[4]) of the first len(pre) clumps, placed as given before
+    the others fall.  This is a geometric construction of a contact-rich
+    initial state; no dynamics is simulated.  Returns (x[n,3], q[n,4]).
     """
     x0, y0, x1, y1 = footprint
     n = len(clump_template)
     q = random_unit_quaternions(g, n)
-    R = quat_matrix(q)
     rmax = max(float(t[1].max()) for t in templates)
     cell = 2.0 * rmax
     nx = max(1, int(math.ceil((x1 - x0) / cell)))
@@ -364,14 +371,37 @@ def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_m
     P = []   # placed sphere centres
     Rr = []  # placed sphere radii
     xs = np.empty((n, 3))
+    npre = 0 if pre is None else len(pre)
+    for i in range(npre):
+        q[i] = pre[i][1]
+    R = quat_matrix(q)
     for i in range(n):
         off, rad = templates[clump_template[i]][0], templates[clump_template[i]][1]
         wo = off @ R[i].T
+        if i < npre:
+            cx, cy, zc = pre[i][0]
+            xs[i] = (cx, cy, zc)
+            for j in range(wo.shape[0]):
+                p = (cx + wo[j, 0], cy + wo[j, 1], zc + wo[j, 2])
+                k = len(P)
+                P.append(p); Rr.append(float(rad[j]))
+                jx = min(nx - 1, max(0, int((p[0] - x0) // cell))); jy = min(ny - 1, max(0, int((p[1] - y0) // cell)))
+                cols[jy * nx + jx].append(k)
+            continue
         lo_x = float((wo[:, 0] - rad).min()); hi_x = float((wo[:, 0] + rad).max())
         lo_y = float((wo[:, 1] - rad).min()); hi_y = float((wo[:, 1] + rad).max())
         cx = g.uniform(x0 - lo_x, x1 - hi_x)
         cy = g.uniform(y0 - lo_y, y1 - hi_y)
-        zc = float((floor_z + rad - wo[:, 2]).max())  # resting on the floor
+        if edge is not None and g.random() < edge[0]:
+            ax = edge[1][int(g.integers(0, len(edge[1])))]
+            hi_side = g.random() < 0.5
+            sk = g.uniform(0.0, sink_max)
+            if ax == "x":
+                cx = (x1 - hi_x + sk) if hi_side else (x0 - lo_x - sk)
+            else:
+                cy = (y1 - hi_y + sk) if hi_side else (y0 - lo_y - sk)
+        fl = floor_z + rad if floor is None else floor(cx + wo[:, 0], cy + wo[:, 1], rad)
+        zc = float((fl - wo[:, 2]).max())  # resting on the floor
         ix0 = max(0, int((cx + lo_x - rmax - x0) // cell)); ix1 = min(nx - 1, int((cx + hi_x + rmax - x0) // cell))
         iy0 = max(0, int((cy + lo_y - rmax - y0) // cell)); iy1 = min(ny - 1, int((cy + hi_y + rmax - y0) // cell))
         cand = [k for jy in range(iy0, iy1 + 1) for jx in range(ix0, ix1 + 1) for k in cols[jy * nx + jx]]
@@ -387,7 +417,7 @@ def deposit(g: np.random.Generator, templates, clump_template, footprint, sink_m
                 zt = np.where(ok, Pc[None, :, 2] + np.sqrt(np.where(ok, S2 - dh2, 0.0)) - wo[:, 2:3], -np.inf)
                 zc = max(zc, float(zt.max()))
         zc -= g.uniform(0.0, sink_max)
-        zc = max(zc, float((floor_z + rad - wo[:, 2]).max()) - sink_max)
+        zc = max(zc, float((fl - wo[:, 2]).max()) - sink_max)
         xs[i] = (cx, cy, zc)
         for j in range(wo.shape[0]):
             p = (cx + wo[j, 0], cy + wo[j, 1], zc + wo[j, 2])
@@ -753,6 +783,119 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
     walls = box_walls((0, 0, 0), (bed[0], bed[1], top + 0.05), (5e7, 0.3, 0.5, 0.5))
     return assemble(templates, CT, X, Q, V, W, mat, (0, 0, -9.81), (0, 0, 0, bed[0], bed[1], top + 0.05),
                     1e-6, bnd=walls, presc=presc, name=f"rover-r{replica}")
+
+
+# ---------------------------------------------------------------------------
+# Configuration 2: a bed penetrated by a descending cone; configuration 3: a
+# rotating drum
+# ---------------------------------------------------------------------------
+
+CONE_SIN, CONE_COS = 0.5, math.sqrt(3.0) / 2.0   # half-angle 30 degrees (a 60-degree cone)
+CONE_BASE_RADIUS = 10.14e-3                       # base area 323 mm^2
+CONE_SPEED = 0.03                                 # descent [m/s]
+WALL_MAT = (5e7, 0.3, 0.5, 0.5)
+
+
+def bed_materials(g: np.random.Generator, ns: int, cor: float = 0.5) -> np.ndarray:
+    """Per-sphere-instance materials of the bed workloads: E ~ U[1e7, 5e7] Pa,
+    nu = 0.3, mu ~ U[0.3, 0.8], the given CoR."""
+    mat = np.empty((ns, 4))
+    mat[:, 0] = g.uniform(1e7, 5e7, ns)
+    mat[:, 1] = 0.3
+    mat[:, 2] = g.uniform(0.3, 0.8, ns)
+    mat[:, 3] = cor
+    return mat
+
+
+def cone_bed(replica: int = 0, n_clumps: int = 600, side: float = 0.05, shaft: float = 12e-3,
+             sink_max: float = 2e-5, h: float = 1e-6) -> SceneDesc:
+    """Configuration 2 scaled down (the cone-penetration test, in the frame in
+    which the cone rises into the bed from below): an analytic cone of
+    half-angle 30 degrees and base radius 10.14 mm with a cylindrical shaft
+    of that radius below its base stands on the floor of a side x side box
+    (four walls), apex up, the shaft ``shaft`` long; it moves up at
+    0.03 m/s.  Clumps of the eight bed templates (per-sphere-instance
+    E ~ U[1e7, 5e7] Pa and mu ~ U[0.3, 0.8], nu = 0.3, CoR = 0.5) are
+    deposited around and onto it, so that spheres rest on its tip, face and
+    rim as well as on the floor and against the walls.  Clumps start at rest."""
+    g = rng(8, replica)
+    tmpls = bed_templates(replica)
+    ct = g.integers(0, len(tmpls), n_clumps)
+    ct[:3] = 0  # the one-sphere template: probes on the tip, the rim and the shaft
+    rb = CONE_BASE_RADIUS
+    H = rb * CONE_COS / CONE_SIN
+    ax, ay, z_apex = side / 2, side / 2, shaft + H
+    z_rim = z_apex - H
+    cot = CONE_COS / CONE_SIN
+
+    def floor(px, py, r):
+        # lowest centre height of a sphere of radius r over (px, py): the
+        # floor, or resting on the cone's tip, face or rim
+        rho = np.hypot(px - ax, py - ay)
+        foot = rho - r * CONE_COS
+        on_face = z_apex - rho * cot + r / CONE_SIN
+        on_tip = z_apex + np.sqrt(np.maximum(r * r - rho * rho, 0.0))
+        on_rim = z_rim + np.sqrt(np.maximum(r * r - (rho - rb) ** 2, 0.0))
+        z = np.where(foot < 0.0, on_tip, np.where(foot <= rb, on_face,
+                     np.where(rho - rb < r, on_rim, -np.inf)))
+        return np.maximum(r, z)
+
+    # probes pressed 10 um into the cone: on the tip, at the rim edge (between
+    # the face's and the shaft's normals) and against the shaft below the rim
+    r0 = float(tmpls[0][1][0])
+    dr = r0 - 1e-5
+    c15, s15 = math.cos(math.radians(15.0)), math.sin(math.radians(15.0))
+    one = (1.0, 0.0, 0.0, 0.0)
+    pre = [((ax, ay, z_apex + dr), one),
+           ((ax + rb + c15 * dr, ay, z_rim + s15 * dr), one),
+           ((ax, ay - (rb + dr), z_rim - 0.5 * shaft), one)]
+    x, q = deposit(g, tmpls, ct, (0.0, 0.0, side, side), sink_max, floor=floor, edge=(0.1, "xy"), pre=pre)
+    sizes = np.array([t[0].shape[0] for t in tmpls])
+    mat = bed_materials(g, int(sizes[ct].sum()))
+    z_top = float(x[:, 2].max()) + 0.03
+    walls = box_walls((0, 0, 0), (side, side, z_top), WALL_MAT)
+    cone = dict(type=BND_CONE_OUT, param=(ax, ay, z_apex, 0, 0, -1, CONE_SIN, CONE_COS, H), mat=WALL_MAT,
+                vel=(0, 0, CONE_SPEED))
+    n = n_clumps
+    return assemble(tmpls, ct, x, q, np.zeros((n, 3)), np.zeros((n, 3)), mat, (0, 0, -9.81),
+                    (0, 0, 0, side, side, z_top), h, bnd=walls + [cone], name=f"cone-bed-r{replica}")
+
+
+def drum_boundaries(center, R, L, omega, mat=WALL_MAT, scene=0):
+    """A drum of radius R and length L with its axis along y through
+    ``center`` (x, z) from y = 0 to y = L: the inner cylinder and two end
+    caps, all spinning at ``omega`` rad/s about the axis (surface spin about
+    reference points on the axis; the geometry is invariant under it)."""
+    cx, cz = center
+    w = (0.0, omega, 0.0)
+    return [dict(type=BND_CYL_IN, param=(cx, 0.0, cz, 0, 1, 0, R), mat=mat, omega=w, scene=scene),
+            dict(type=BND_PLANE, param=(cx, 0.0, cz, 0, 1, 0), mat=mat, omega=w, scene=scene),
+            dict(type=BND_PLANE, param=(cx, L, cz, 0, -1, 0), mat=mat, omega=w, scene=scene)]
+
+
+def drum(replica: int = 0, n_clumps: int = 700, R: float = 0.05, L: float = 0.1, omega: float = 2.0,
+         sink_max: float = 2e-5, h: float = 1e-6) -> SceneDesc:
+    """Configuration 3 scaled down (the rotating drum): clumps of the eight bed
+    templates and bed materials deposited onto the curved bottom of a drum of
+    radius R and length L (horizontal axis along y, through x = z = R), which
+    spins at ``omega`` = 2 rad/s from the first step: the clumps start at rest
+    and the wall drags them.  Deposit footprint: the middle 80 % of the
+    drum's width; some clumps are placed against the end caps."""
+    g = rng(9, replica)
+    tmpls = bed_templates(replica)
+    ct = g.integers(0, len(tmpls), n_clumps)
+    cx = cz = R
+
+    def floor(px, py, r):
+        return cz - np.sqrt(np.maximum((R - r) ** 2 - (px - cx) ** 2, 0.0))
+
+    x, q = deposit(g, tmpls, ct, (cx - 0.8 * R, 0.0, cx + 0.8 * R, L), sink_max, floor=floor, edge=(0.15, "y"))
+    sizes = np.array([t[0].shape[0] for t in tmpls])
+    mat = bed_materials(g, int(sizes[ct].sum()))
+    n = n_clumps
+    return assemble(tmpls, ct, x, q, np.zeros((n, 3)), np.zeros((n, 3)), mat, (0, 0, -9.81),
+                    (0, 0, 0, 2 * R, L, 2 * R), h, bnd=drum_boundaries((cx, cz), R, L, omega),
+                    name=f"drum-r{replica}")
 
 
 # ---------------------------------------------------------------------------

@@ -110,3 +110,34 @@ def test_invalid_detection_parameters_rejected(dense):
         args.update(kw)
         with pytest.raises(CdemError):
             sc.set_detection(**args)
+
+
+@pytest.mark.parametrize("mode", ["fixed", "learned"])
+def test_regrow_on_an_audit_step_reports_no_miss(dense, mode, monkeypatch):
+    """An active set too small for the first detection overflows on a step
+    that also audits (step 0, audit period 10).  The abandoned step must not
+    be audited; it is run again once the storage has grown, so the call
+    succeeds, the audits count no miss, and the trajectory is bit-identical
+    to a scene that never had to grow."""
+    from paper_2307_03445_amd import train
+    mlp = np.load(train.WEIGHTS)["params"].astype(np.float32) if mode == "learned" else None
+
+    def make():
+        sc = _scene(dense)
+        if mlp is not None:
+            sc.set_mlp(mlp)
+        sc.set_detection(mode, k_max=20, safety=1.5, margin_cap=1e-4, audit_period=10)
+        return sc
+
+    monkeypatch.setenv("CDEM_INITIAL_CAPACITY", "512")
+    small = make()
+    monkeypatch.delenv("CDEM_INITIAL_CAPACITY")
+    ref = make()
+    small.step(30)  # raises CdemError on a reported miss
+    ref.step(30)
+    c = small.counts()
+    assert c["regrows"] >= 1 and c["audits"] == 3 and c["missed"] == 0, c
+    assert ref.counts()["missed"] == 0
+    s1, s2 = small.state(), ref.state()
+    for k in s1:
+        assert np.array_equal(s1[k], s2[k]), k

@@ -111,26 +111,42 @@ def test_learned_reproduces_plain_bitwise_at_full_size(bed, mlp):
     assert cl["detections"] < cp["detections"] // 4
 
 
+def _timed(sc, steps):
+    import time
+
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sc.step(steps)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
 def test_learned_gains_over_the_fixed_rule(bed, mlp):
-    """What the trained network gains over the method without it: at the same
-    interval bound, margin cap and audits, the learned per-region margins keep
-    fewer candidate pairs in the active set than the fixed rule's global
-    margin (fewer false positives for the force kernel to evaluate), with the
-    same trajectory and no missed contact.  This bed starts at rest, so over
-    its first 101 steps the fixed rule's global speed is still low and the gain
-    is a few per cent; on the benchmark's settled bed with the wheel moving it
-    is about a fifth of the candidates (the benchmark reports both modes)."""
-    steps = 101
+    """What the trained network gains over the method without it.  The fixed
+    rule is the paper's: one margin for every sphere from the largest speed,
+    here the a-priori bound a user gives the solver (2.5 m/s; bounded and
+    known), so its interval is held below the bound of 20 steps by the margin
+    cap (50 um).  The learned per-region envelopes ignore that bound (they fall back
+    to it only for an implausible prediction), keep small margins where the
+    bed rests and choose the interval that minimises the modelled bytes per
+    step: a longer interval, fewer candidate pairs and a shorter step, with
+    the same trajectory and no missed contact."""
+    steps, timed = 101, 40
+    detect = dict(bench.DETECT, margin_cap=5e-5, v_max_user=2.5)
     out = {}
     for mode in ("fixed", "learned"):
-        sc = bench.make_scene(bed, mode, mlp)
+        sc = bench.make_scene(bed, mode, mlp, detect)
         sc.step(steps)
-        out[mode] = (sc.state(), sc.counts())
+        c = sc.counts()
+        ms = _timed(sc, timed) * 1e3
+        out[mode] = (sc.state(), c, ms)
         sc.close()
-        print(mode, out[mode][1], flush=True)
-    (sf, cf), (sl, cl) = out["fixed"], out["learned"]
+        print(mode, c, f"{ms:.2f} ms/step", flush=True)
+    (sf, cf, tf), (sl, cl, tl) = out["fixed"], out["learned"]
     for k in ("x", "q", "v", "w"):
         assert np.array_equal(sf[k], sl[k]), k
-    assert cf["missed"] == 0 and cl["missed"] == 0
+    assert cf["missed"] == 0 and cl["missed"] == 0 and cf["audits"] >= 2 and cl["audits"] >= 2
+    assert cf["k_current"] < bench.DETECT["k_max"] and cl["k_current"] > cf["k_current"], (cf, cl)
     assert cl["candidates"] < cf["candidates"], (cl["candidates"], cf["candidates"])
-    assert cl["detections"] <= cf["detections"] + 1
+    assert tl < tf, (tl, tf)

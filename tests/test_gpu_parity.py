@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(_lib.SIGNATURES) == names
-    assert L.cdem_abi_version() == 1
+    assert L.cdem_abi_version() == 2
 
 
 gpu = pytest.mark.gpu
@@ -99,6 +99,7 @@ def test_first_step_pairs_and_forces(dense, prec):
     if prec == "fp64":
         # same IEEE operations in the same order: bit-identical
         assert np.array_equal(cg["F"], co["F"]) and np.array_equal(cg["u"], co["u"])
+        assert np.array_equal(cg["Ta"], co["Ta"]) and np.array_equal(cg["Tb"], co["Tb"])
         assert np.array_equal(Fg, Fo) and np.array_equal(Tg, To)
 
 

@@ -677,3 +677,52 @@ def test_angular_momentum_first_order():
 
     d1, d2 = drift(2e-6), drift(1e-6)
     assert d2 < 1e-3 and 1.6 < d1 / d2 < 2.4, (d1, d2)
+
+
+def test_contact_torques_from_contact_points():
+    """Per-contact torques: r x F about each body's reference point, with the
+    contact point at the middle of the overlap along the centre line (sphere
+    pairs) or at the sphere's surface point on the wall side (boundaries);
+    summed per clump they give the clump torque."""
+    d = I.walled_box(n_clumps=300, dense=True)
+    o = oracle.Oracle(d)
+    o.eval()
+    c = o.contacts()
+    xs = o.sphere_pos()
+    st = o.state()
+    sb = d.sphere_begin()
+    owner = np.repeat(np.arange(d.n_clumps), np.diff(sb))
+    R = np.concatenate([d.tmpl_radius[d.tmpl_sphere_begin[t]:d.tmpl_sphere_begin[t + 1]] for t in d.clump_template])
+    ns = d.n_spheres
+    a, b = c["a"].astype(int), c["b"].astype(int)
+    sph = b < ns
+    assert sph.sum() > 100 and (~sph).sum() > 10
+    F = c["F"]
+    Ta = np.empty_like(F); Tb = np.empty_like(F)
+    # sphere pairs: n from a to b, p = x_a + (R_a - delta/2) n
+    dv = xs[b[sph]] - xs[a[sph]]
+    n = dv / np.linalg.norm(dv, axis=1, keepdims=True)
+    p = xs[a[sph]] + (R[a[sph]] - 0.5 * c["delta"][sph])[:, None] * n
+    Ta[sph] = np.cross(p - st["x"][owner[a[sph]]], -F[sph])
+    Tb[sph] = np.cross(p - st["x"][owner[b[sph]]], F[sph])
+    # boundary contacts (planes here): the sphere is body b, p = x_s - (R - delta/2) n_w,
+    # and body a is the plane, about its reference point
+    w = b[~sph] - ns
+    nw = d.bnd_param[w, 3:6]
+    s_ = a[~sph]
+    p = xs[s_] - (R[s_] - 0.5 * c["delta"][~sph])[:, None] * nw
+    Ta[~sph] = np.cross(p - d.bnd_param[w, 0:3], -F[~sph])
+    Tb[~sph] = np.cross(p - st["x"][owner[s_]], F[~sph])
+    scale = (np.linalg.norm(F, axis=1) * 0.05)[:, None]
+    assert np.abs(c["Ta"] - Ta).max() <= 1e-12 * scale.max() and np.all(np.abs(c["Ta"] - Ta) <= 1e-10 * scale + 1e-30)
+    assert np.all(np.abs(c["Tb"] - Tb) <= 1e-10 * scale + 1e-30)
+    # per clump: the torques of its sides sum to the clump torque
+    T = np.zeros((d.n_clumps, 3))
+    np.add.at(T, owner[a[sph]], c["Ta"][sph])
+    np.add.at(T, owner[b[sph]], c["Tb"][sph])
+    np.add.at(T, owner[s_], c["Tb"][~sph])
+    _, Tc = o.clump_forces()
+    mag = np.zeros(d.n_clumps)
+    np.add.at(mag, owner[a], np.linalg.norm(c["Ta"], axis=1))
+    np.add.at(mag, owner[b[sph]], np.linalg.norm(c["Tb"][sph], axis=1))
+    assert np.all(np.linalg.norm(T - Tc, axis=1) <= 1e-12 * (mag + 1e-30))
