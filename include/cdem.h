@@ -92,7 +92,7 @@ typedef struct cdem_scene_desc {
     const double *gravity;             /* [n_scenes][3] */
     const double *domain;              /* [n_scenes][6] lo[3], hi[3]: binning box (spheres outside are
                                           still handled, in the edge bins) */
-    int32_t n_bnd;                     /* <= 64 */
+    int32_t n_bnd;                     /* <= 4096 (over all scenes) */
     const int32_t *bnd_type;           /* [n_bnd] CDEM_BND_* */
     const double *bnd_param;           /* [n_bnd][12] geometry at t = 0 */
     const double *bnd_mat;             /* [n_bnd][4] E, nu, mu, CoR */

@@ -395,7 +395,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     if (d->n_templates < 1 || !d->tmpl_sphere_begin || d->tmpl_sphere_begin[0] != 0) return invalid("templates");
     if (d->n_clumps < 0 || d->n_clumps >= ((int64_t)1 << 31)) return invalid("clump count");
     if (d->n_scenes < 1 || !d->gravity || !d->domain) return invalid("scenes");
-    if (d->n_bnd < 0 || d->n_bnd > kMaxBnd) return invalid("at most 64 boundaries");
+    if (d->n_bnd < 0 || d->n_bnd > kMaxBnd) return invalid("at most 4096 boundaries");
     int nt = d->n_templates;
     for (int t = 0; t < nt; t++)
         if (d->tmpl_sphere_begin[t + 1] <= d->tmpl_sphere_begin[t]) return invalid("empty template");

@@ -7,7 +7,7 @@
 
 namespace cdem {
 
-constexpr int kMaxBnd = 64;
+constexpr int kMaxBnd = 4096;
 constexpr int kNarrowBlock = 512;  // narrow-phase workgroup: eight wavefronts share one segment allocation
 constexpr int kMaxRow = 16;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
