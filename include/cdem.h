@@ -327,6 +327,19 @@ size_t cdem_mlp_workspace_bytes(int64_t n);
  * zero gradient.  Deterministic. */
 int cdem_mlp_backward(const float *params, const float *features, const float *target, int64_t n, float tau,
                       float *grad, float *loss, void *workspace, void *stream);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training loops, harnesses that forbid hipMalloc): the same
+ * gradient and loss as cdem_mlp_backward, bit for bit, with the workgroup
+ * partials held in a static device array of the library (about 9.3 MB per
+ * device, kept until the process ends) instead of a caller workspace.  At
+ * most CDEM_MLP_STATIC_MAX_SAMPLES samples (CDEM_E_INVALID beyond, nothing
+ * launched); device pointers as in cdem_mlp_backward; asynchronous on stream.
+ * Allocates nothing.  Every call on one device shares that array: calls that
+ * overlap on one device (other streams, other threads) race, and must be
+ * ordered by the caller. */
+#define CDEM_MLP_STATIC_MAX_SAMPLES 16384
+int cdem_mlp_backward_static(const float *params, const float *features, const float *target, int64_t n, float tau,
+                             float *grad, float *loss, void *stream);
 /* One Adam update (step t >= 1, bias-corrected) of params with grad; m and v
  * are the moment buffers (device, zero-initialised by the caller). */
 int cdem_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t t, float lr, float beta1,

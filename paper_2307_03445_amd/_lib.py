@@ -101,6 +101,7 @@ SIGNATURES = {
     "cdem_mlp_forward": (C.c_int, [P, P, P, C.c_int64, P]),
     "cdem_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "cdem_mlp_backward": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P, P]),
+    "cdem_mlp_backward_static": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P]),
     "cdem_mlp_adam": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, P]),
     "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
     "cdem_set_graph": (C.c_int, [P, C.c_int32]),
@@ -410,6 +411,20 @@ def mlp_backward(params, features, target, tau):
     if rc:
         raise CdemError(rc, "cdem_mlp_backward")
     return grad, loss
+
+
+MLP_STATIC_MAX_SAMPLES = 16384  # CDEM_MLP_STATIC_MAX_SAMPLES of include/cdem.h
+
+
+def mlp_backward_static(params, features, target, tau, grad, loss):
+    """cdem_mlp_backward_static: the gradient and loss into caller-owned
+    device tensors `grad` and `loss`, with no workspace (the library's static
+    device array holds the partials).  Raises CdemError on a failed call."""
+    L = load()
+    rc = L.cdem_mlp_backward_static(_dev(params), _dev(features), _dev(target), features.shape[0], float(tau),
+                                    _dev(grad), _dev(loss), _stream())
+    if rc:
+        raise CdemError(rc, "cdem_mlp_backward_static")
 
 
 def mlp_adam(params, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "../../include/cdem.h"
 #include "mlp_dev.h"
@@ -181,6 +182,56 @@ extern "C" int cdem_mlp_backward(const float *params, const float *features, con
                        tau, (float *)workspace);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartial + 255) / 256), dim3(256), 0, st, (const float *)workspace, nblk,
                        grad, loss);
+    return hipGetLastError() == hipSuccess ? CDEM_OK : CDEM_E_HIP;
+}
+
+// ---- allocation-free backward pass ----
+// The per-workgroup partials of cdem_mlp_backward live here instead of in a
+// caller workspace, for callers that cannot allocate device memory.  Every
+// partial the reduction reads is first written by k_mlp_backward in the same
+// call, so nothing needs clearing between calls.  One copy per device, held
+// until the process ends; calls that overlap on one device share it and race.
+namespace cdem {
+constexpr int64_t kStaticBwdBlocks = CDEM_MLP_STATIC_MAX_SAMPLES / kBwdSamples;
+__device__ __align__(256) float scratch[kStaticBwdBlocks * kPartial];
+}  // namespace cdem
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_ptr[kMaxDevices] = {};
+bool g_scratch_ready[kMaxDevices] = {};
+
+// Device address of the scratch array on the current device (the host-side
+// name of the array is not a device address).  Looked up once per device.
+int scratch_on_current_device(float **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return CDEM_E_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ready[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(cdem::scratch)) != hipSuccess || !p) return CDEM_E_HIP;
+        g_scratch_ptr[dev] = (float *)p;
+        g_scratch_ready[dev] = true;
+    }
+    *out = g_scratch_ptr[dev];
+    return CDEM_OK;
+}
+}  // namespace
+
+extern "C" int cdem_mlp_backward_static(const float *params, const float *features, const float *target, int64_t n,
+                                        float tau, float *grad, float *loss, void *stream) {
+    if (!params || !features || !target || !grad || n <= 0 || !(tau > 0.f && tau < 1.f)) return CDEM_E_INVALID;
+    if (n > CDEM_MLP_STATIC_MAX_SAMPLES) return CDEM_E_INVALID;
+    float *ws = nullptr;
+    const int rc = scratch_on_current_device(&ws);
+    if (rc != CDEM_OK) return rc;
+    const int64_t nblk = (n + kBwdSamples - 1) / kBwdSamples;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_mlp_backward, dim3((unsigned)nblk), dim3(kBwdThreads), 0, st, params, features, target, n,
+                       tau, ws);
+    hipLaunchKernelGGL(k_mlp_reduce, dim3((kPartial + 255) / 256), dim3(256), 0, st, (const float *)ws, nblk, grad,
+                       loss);
     return hipGetLastError() == hipSuccess ? CDEM_OK : CDEM_E_HIP;
 }
 
