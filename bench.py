@@ -117,10 +117,11 @@ def survey_kernel_bytes(kernel: str, st: dict) -> float:
     return 0.0
 
 
-def make_scene(desc, mode, mlp=None, detect=None):
-    """The scene as the benchmark times it: FP32 force arithmetic, detection `mode`."""
+def make_scene(desc, mode, mlp=None, detect=None, precision="fp32"):
+    """The scene as the benchmark times it: FP32 force arithmetic (unless
+    `precision` says otherwise), detection `mode`."""
     from paper_2307_03445_amd._lib import Scene
-    sc = Scene(desc, precision="fp32")
+    sc = Scene(desc, precision=precision)
     if mode == "learned":
         sc.set_mlp(mlp)
     if mode != "plain":
@@ -140,7 +141,7 @@ def _steps_reporting_misses(sc, n, label):
         log(f"[{label}] audit reported missed contacts: {e}")
 
 
-def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=None):
+def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=None, precision="fp32"):
     """Time `steps` steps of one path after warmup and the autotuner.
 
     Inside the timed region only the roofline kernel is bracketed by events
@@ -153,7 +154,7 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
     label = label or mode
     detect = detect or DETECT
     period = detect["audit_period"] if mode != "plain" else 0
-    sc = make_scene(desc, mode, mlp, detect)
+    sc = make_scene(desc, mode, mlp, detect, precision)
     t0 = time.perf_counter()
     sc.step(warmup)
     # bin size and launch shape from the library's autotuner (its trials are
@@ -355,12 +356,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--clumps", type=int, default=11_000_000)
-    ap.add_argument("--modes", default="plain,fixed,learned,learned_graph,batched",
+    ap.add_argument("--modes", default="plain,fixed,learned,learned_graph,batched,precision",
                     help="paths to time: plain, fixed, learned (rover bed), learned_graph (the learned path "
-                         "replayed from captured graphs), batched (256 funnel scenes, learned, graphs)")
+                         "replayed from captured graphs), batched (256 funnel scenes, learned, graphs), precision "
+                         "(the 4M-clump drum, learned, all-FP64 vs FP32 force arithmetic)")
     ap.add_argument("--mlp", default=None, help="npz with envelope-MLP parameters (default: the package's "
                                                 "trained weights, else train now)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--funnel-settle-s", type=float, default=0.05,
+                    help="simulated seconds the funnel batch runs (at h = 5e-6 s) before it is timed")
     ap.add_argument("--patch-cache", default=None,
                     help="npz file holding the settled preparation patch (written if missing)")
     ap.add_argument("--copy-probe-gib", type=float, default=0.0,
@@ -407,14 +411,15 @@ def main():
     modes = args.modes.split(",")
     rover_modes = [m for m in modes if m in ("plain", "fixed", "learned", "learned_graph")]
     mlp, mlp_info = None, None
-    if any(m in modes for m in ("learned", "learned_graph", "batched")):
+    if any(m in modes for m in ("learned", "learned_graph", "batched", "precision")):
         from paper_2307_03445_amd import train
         path = args.mlp or train.WEIGHTS
         if os.path.exists(path):
             mlp = np.load(path)["params"].astype(np.float32)
             mlp_info = f"loaded {os.path.relpath(path, ROOT)}"
     results, desc = {}, None
-    if rover_modes:
+    px = pq = None
+    if rover_modes or "precision" in modes:
         t0 = time.perf_counter()
         if args.patch_cache and os.path.exists(args.patch_cache):
             z = np.load(args.patch_cache)
@@ -430,6 +435,7 @@ def main():
             t1 = time.perf_counter()
             mlp, info = train.train(px, pq, log=log)
             mlp_info = f"trained now in {time.perf_counter() - t1:.1f} s: {info}"
+    if rover_modes:
         desc = I.rover_bed(px, pq, n_clumps=args.clumps)
         log(f"workload: {desc.n_clumps} clumps, {desc.n_spheres} spheres, built in {time.perf_counter() - t0:.1f} s")
         log(f"envelope MLP: {mlp_info}")
@@ -441,17 +447,39 @@ def main():
     if "batched" in modes:
         t0 = time.perf_counter()
         bdesc = I.funnel_batch()
+        # the scenes mid-discharge: off the spawn lattice, packed into the
+        # funnels and flowing through the outlets
+        bdesc, binfo = prep.settle_funnels(bdesc, seconds=args.funnel_settle_s)
         log(f"batched workload: {bdesc.n_scenes} funnel scenes, {bdesc.n_clumps} clumps, {bdesc.n_spheres} "
-            f"spheres, built in {time.perf_counter() - t0:.1f} s")
+            f"spheres, built and run {args.funnel_settle_s} s into the discharge in {time.perf_counter() - t0:.1f} s "
+            f"({binfo})")
         rb = run_path(bdesc, "learned", args.steps, args.warmup, mlp=mlp, graph=args.steps, label="batched")
         bstats = dict(spheres=bdesc.n_spheres, clumps=bdesc.n_clumps, fp32=True, bins=rb["counts"]["bins"])
         batched = dict(path_line(rb, bdesc.n_spheres, bstats, "learned"),
                        workload=f"{bdesc.n_scenes} independent funnel scenes of 2k-60k clumps (log-uniform), "
-                                f"{bdesc.n_clumps} clumps, {bdesc.n_spheres} spheres, learned interval, one "
-                                f"captured graph of {args.steps} steps per replay",
+                                f"{bdesc.n_clumps} clumps, {bdesc.n_spheres} spheres, {args.funnel_settle_s} s "
+                                f"into the discharge, learned interval, one captured graph of {args.steps} steps "
+                                f"per replay",
                        roofline=roofline(rb, bstats, "learned"))
+    precision = None
+    if "precision" in modes:
+        t0 = time.perf_counter()
+        ddesc = I.drum_bed(px, pq)
+        log(f"precision workload: drum of {ddesc.n_clumps} clumps, {ddesc.n_spheres} spheres, built in "
+            f"{time.perf_counter() - t0:.1f} s")
+        precision = {"workload": f"rotating drum (R = 0.4 m, L = 3 m, 2 rad/s) filled with {ddesc.n_clumps} clumps, "
+                                 f"{ddesc.n_spheres} spheres (copies of the settled bed patch), learned interval"}
+        for prec in ("fp64", "fp32"):
+            rp = run_path(ddesc, "learned", args.steps, args.warmup, mlp=mlp, label=f"drum-{prec}",
+                          precision=prec)
+            pstats = dict(spheres=ddesc.n_spheres, clumps=ddesc.n_clumps, fp32=(prec == "fp32"),
+                          bins=rp["counts"]["bins"])
+            precision[prec] = dict(path_line(rp, ddesc.n_spheres, pstats, "learned"),
+                                   roofline=roofline(rp, pstats, "learned"))
+        precision["fp32_over_fp64"] = (precision["fp32"]["sphere_steps_per_s"] /
+                                       precision["fp64"]["sphere_steps_per_s"])
     if not results:
-        line = {"metric": METRIC, "batched": batched}
+        line = {"metric": METRIC, "batched": batched, "precision": precision}
         print(json.dumps(line), flush=True)
         return
     main_mode = "learned" if "learned" in results else (
@@ -487,6 +515,8 @@ def main():
         line["speedup_vs_plain"] = main["sphere_steps_per_s"] / paths["plain"]["sphere_steps_per_s"]
     if batched:
         line["batched"] = batched
+    if precision:
+        line["precision"] = precision
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
         line["cpu_baseline_1core"] = cpu_baseline(seconds_target=10.0, cores=1)

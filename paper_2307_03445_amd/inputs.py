@@ -898,6 +898,53 @@ def drum(replica: int = 0, n_clumps: int = 700, R: float = 0.05, L: float = 0.1,
                     name=f"drum-r{replica}")
 
 
+def drum_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 4_000_000,
+             R: float = 0.4, L: float = 3.0, omega: float = 2.0, side: float = 0.05) -> SceneDesc:
+    """Configuration 3 at its size (the precision study): a drum of radius
+    R = 0.4 m and length L = 3 m (horizontal axis along y through
+    x = z = R), spinning at 2 rad/s from the first step, holding ``n_clumps``
+    clumps of the eight bed templates with per-sphere-instance bed materials.
+    The drum is filled from copies of a patch (``patch_x``/``patch_q``, the
+    clump poses of a rover-bed patch of the same replica, as from
+    :func:`rover_deposited_patch`), laid side by side over the drum's
+    section and length with the same seam spacing as the rover bed; a clump
+    is kept when its bounding sphere lies inside the drum, and the lowest
+    ``n_clumps`` of those are the fill (about half the drum).  Clumps start
+    at rest."""
+    g = rng(9, 1000 + replica)
+    tmpls = bed_templates(replica)
+    ct_p = rng(5, replica).integers(0, len(tmpls), patch_x.shape[0])
+    order = morton_order(patch_x, 0.01)
+    xp, qp, ct_p = patch_x[order], patch_q[order], ct_p[order]
+    Rm = quat_matrix(qp)
+    P = np.concatenate([xp[k] + tmpls[ct_p[k]][0] @ Rm[k].T for k in range(len(ct_p))])
+    Rr = np.concatenate([tmpls[ct_p[k]][1] for k in range(len(ct_p))])
+    lo = np.array([max(0.0, -(P[:, a] - Rr).min()) for a in range(2)])
+    hi = np.array([max(0.0, (P[:, a] + Rr).max() - side) for a in range(2)])
+    pitch = side + lo + hi + 1e-6
+    rb = np.array([bounding_radius(t[0], t[1]) for t in tmpls])[ct_p]
+    ntx, nty = int(np.ceil(2 * R / pitch[0])), int(np.ceil(L / pitch[1]))
+    cx = cz = R
+    X, Q, CT = [], [], []
+    for j in range(nty):
+        for i in range(ntx):
+            x = xp + np.array([lo[0] + i * pitch[0], lo[1] + j * pitch[1], 0.0])
+            keep = (np.hypot(x[:, 0] - cx, x[:, 2] - cz) <= R - rb - 1e-4) & (x[:, 1] >= rb + 1e-4) & \
+                   (x[:, 1] <= L - rb - 1e-4)
+            X.append(x[keep]); Q.append(qp[keep]); CT.append(ct_p[keep])
+    X, Q, CT = np.concatenate(X), np.concatenate(Q), np.concatenate(CT)
+    low = np.argsort(X[:, 2], kind="stable")[:n_clumps]
+    X, Q, CT = X[low], Q[low], CT[low]
+    m = morton_order(X, 0.01)
+    X, Q, CT = X[m], Q[m], CT[m]
+    nc = X.shape[0]
+    sizes = np.array([t[0].shape[0] for t in tmpls])
+    mat = bed_materials(g, int(sizes[CT].sum()))
+    return assemble(tmpls, CT, X, Q, np.zeros((nc, 3)), np.zeros((nc, 3)), mat, (0, 0, -9.81),
+                    (0, 0, 0, 2 * R, L, 2 * R), 1e-6, bnd=drum_boundaries((cx, cz), R, L, omega),
+                    name=f"drum-bed-r{replica}")
+
+
 # ---------------------------------------------------------------------------
 # Configuration 4: many independent funnel scenes of uneven size
 # ---------------------------------------------------------------------------
@@ -980,6 +1027,49 @@ def extract_scene(batch: SceneDesc, k: int) -> SceneDesc:
         bnd_omega=batch.bnd_omega[bsel], bnd_scene=np.zeros(len(bsel), np.int32),
         presc_clump=np.zeros(0, np.int32), presc_param=np.zeros((0, PRESC_NPARAM)), name=f"{batch.name}-s{k}")
     return d.canonical()
+
+
+def funnel_deposited(batch: SceneDesc, k: int, sink_max: float = 2e-5) -> SceneDesc:
+    """Scene k of a funnel batch, stand-alone, with its clumps deposited into
+    its funnel on the CPU (``deposit``) instead of spawned on a lattice: a
+    clump whose spheres clear the outlet falls through it onto the plate, so
+    a column of clumps stands on the plate under the outlet and the funnel
+    is filled above it.  Same templates, materials and boundaries (the funnel
+    wall is extended to the deposit's top); clumps start at rest.  A
+    contact-rich state built without simulating anything."""
+    e = extract_scene(batch, k)
+    fi = int(np.nonzero(e.bnd_type == BND_FRUSTUM_IN)[0][0])
+    pi = int(np.nonzero(e.bnd_type == BND_PLANE)[0][0])
+    fr, pl = e.bnd_param[fi].copy(), e.bnd_param[pi]
+    z_apex, sn, cs, t0 = fr[2], fr[6], fr[7], fr[8]
+    z_out, z_plate = z_apex + t0, pl[2]
+    tb = np.asarray(e.tmpl_sphere_begin, np.int64)
+    tmpls = [(e.tmpl_offset[tb[t]:tb[t + 1]], e.tmpl_radius[tb[t]:tb[t + 1]]) for t in range(len(tb) - 1)]
+    rb = max(bounding_radius(o, r) for o, r in tmpls)
+
+    def floor(px, py, r):
+        # resting on the funnel wall (the cone's surface at distance r along
+        # its inward normal) where that height is above the outlet, else on
+        # the plate below it
+        rho = np.hypot(px, py)
+        zw = z_apex + (r + rho * cs) / sn
+        return np.where(zw >= z_out, zw, z_plate + r)
+
+    # a square footprint inside the funnel's section at the top of the spawn lattice
+    half = 0.7 * (fr[9] - rb) * (sn / cs) / math.sqrt(2.0)
+    g = rng(10, k)
+    x, q = deposit(g, tmpls, np.asarray(e.clump_template, np.int64), (-half, -half, half, half), sink_max,
+                   floor=floor)
+    top = float(x[:, 2].max()) + rb + 0.01
+    fr[9] = max(fr[9], top - z_apex)
+    P = e.bnd_param.copy()
+    P[fi] = fr
+    dom = e.domain.copy()
+    rmax = fr[9] * (sn / cs) + 0.1
+    dom[0] = (-rmax, -rmax, z_plate, rmax, rmax, z_apex + fr[9])
+    n = e.n_clumps
+    return dataclasses.replace(e, x=x, q=q, v=np.zeros((n, 3)), w=np.zeros((n, 3)), bnd_param=P, domain=dom,
+                               name=f"{e.name}-deposited").canonical()
 
 
 # ---------------------------------------------------------------------------

@@ -36,3 +36,30 @@ def settle_patch(replica: int = 0, n_clumps: int = 6875, min_steps: int = 60000,
                 height=float(st["x"][:, 2].max()), n_clumps=d.n_clumps, n_spheres=d.n_spheres)
     sc.close()
     return st["x"], st["q"], info
+
+
+def settle_funnels(desc, seconds: float = 0.05, h: float = 5e-6, chunk: int = 2000, log=None):
+    """Run a batched funnel description for `seconds` of simulated time at a
+    coarser step h (fixed-rule deferred detection, FP32 forces): the clumps
+    drop off their spawn lattice, pack into the funnels and start to
+    discharge through the outlets.  Returns the description with that state
+    (positions, orientations, velocities) and its own time step, and info."""
+    import dataclasses
+    d = dataclasses.replace(desc, h=h)
+    sc = Scene(d, precision="fp32")
+    sc.set_detection("fixed", k_max=20, safety=1.5, margin_cap=2e-4, audit_period=0)
+    n = int(round(seconds / h))
+    t0 = time.perf_counter()
+    done = 0
+    while done < n:
+        k = min(chunk, n - done)
+        sc.step(k)
+        done += k
+        if log:
+            log(f"funnel settle: {done}/{n} steps, {time.perf_counter() - t0:.1f} s")
+    st = sc.state()
+    info = dict(steps=n, h=h, seconds=time.perf_counter() - t0, contacts=sc.last_step_contacts(),
+                max_speed=float(np.linalg.norm(st["v"], axis=1).max()))
+    sc.close()
+    out = dataclasses.replace(desc, x=st["x"], q=st["q"], v=st["v"], w=st["w"])
+    return out, info

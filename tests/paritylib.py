@@ -35,8 +35,12 @@ def clump_force_error(Fg, Fo, scale):
 
 
 def rotation_angle(qa, qb):
-    d = np.abs((qa * qb).sum(1)).clip(0, 1)
-    return 2 * np.arccos(d)
+    """Angle of the rotation between unit quaternions qa and qb: four times
+    the arcsine of half the chord between qa and +-qb (exact near zero, where
+    an arccosine of their dot product loses half the digits)."""
+    s = np.where((qa * qb).sum(1) < 0, -1.0, 1.0)[:, None]
+    chord = np.linalg.norm(qa - s * qb, axis=1)
+    return 4 * np.arcsin((chord / 2).clip(0, 1))
 
 
 def state_errors(sg, so, r_min):
