@@ -354,6 +354,42 @@ int cdem_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t 
 int cdem_collect_envelopes(cdem_scene *s, int32_t horizon, float *features, float *labels, int64_t cap,
                            int64_t *n);
 
+/* ---- user force law (the paper's extension point: the contact force model
+ * is a user-replaceable function of the contact's kinematics, Sec. 2.2) ----
+ * A force law is the source text of one HIP device function,
+ *
+ *   __device__ void cdem_user_law(const double *n, double delta,
+ *       const double *vrel, double Rbar, double mbar, double estar,
+ *       double gstar, double mu, double beta, double h,
+ *       const double *u_old, double *F, double *u_new);
+ *
+ * (it may define helpers before it).  Called once per contact and step, in
+ * FP64 in both precision modes, with the contact geometry of Eq.
+ * kinematicsContactInfo: n[3] the unit normal from body a to body b (a
+ * boundary is body a), delta > 0 the overlap, vrel[3] the velocity of b
+ * relative to a at the contact point; Rbar and mbar the effective radius and
+ * mass (clump masses; a boundary is flat and infinitely heavy); estar and
+ * gstar the pair's effective Young's and shear moduli; mu and beta the
+ * smaller friction coefficient and damping ratio ln e / sqrt(ln^2 e + pi^2)
+ * of the two materials; h the time step; u_old[3] the pair's tangential
+ * history (zero when the contact is new).  It writes F[3], the force on body b
+ * (minus F acts on a, at the same contact point; torques follow from it),
+ * and u_new[3], the history the pair carries to its next step (a pair that
+ * leaves contact loses it).  The law is compiled at run time with hiprtc for
+ * gfx950, with the library's floating-point flags (no contraction), into the
+ * library's own pair kernel.
+ *
+ * Compile only (no device needed): CDEM_OK, or CDEM_E_INVALID with the
+ * compiler's messages in log (a buffer of log_cap bytes, may be NULL). */
+int cdem_check_force_law(const char *source, char *log, size_t log_cap);
+/* Compile the law and make the scene's pair kernel use it from the next
+ * step on (source NULL or "" restores the built-in Hertz-Mindlin law of Eqs.
+ * normal_tangential_force_model1/2, updateUt and cappingOfut).
+ * CDEM_E_INVALID (scene unchanged) when it does not compile, with the
+ * compiler's messages in log; CDEM_E_HIP when the code object cannot be
+ * loaded.  Waits for the scene's stream. */
+int cdem_set_force_law(cdem_scene *s, const char *source, char *log, size_t log_cap);
+
 /* ---- measurement (not part of the method; where Sec. 2.2 says the time
  * goes: identifying the active set) ---- */
 /* Per-kernel device time, measured with HIP events recorded on the launch

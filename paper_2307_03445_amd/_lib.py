@@ -102,6 +102,8 @@ SIGNATURES = {
     "cdem_mlp_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "cdem_mlp_backward": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P, P]),
     "cdem_mlp_backward_static": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P]),
+    "cdem_check_force_law": (C.c_int, [C.c_char_p, C.c_char_p, C.c_size_t]),
+    "cdem_set_force_law": (C.c_int, [P, C.c_char_p, C.c_char_p, C.c_size_t]),
     "cdem_mlp_adam": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, P]),
     "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
     "cdem_set_graph": (C.c_int, [P, C.c_int32]),
@@ -358,6 +360,16 @@ class Scene:
         """Restore a checkpoint written by :meth:`save` of a scene with the same description."""
         self._check(self._L.cdem_load(self._h, blob, len(blob)))
 
+    def set_force_law(self, source):
+        """Compile a user force law (the source of `cdem_user_law`, see
+        include/cdem.h) into the pair kernel; None restores the built-in law.
+        Raises CdemError with the compiler's messages when it does not compile."""
+        log = C.create_string_buffer(1 << 16)
+        rc = self._L.cdem_set_force_law(self._h, source.encode() if source else None, log, len(log))
+        if rc:
+            raise CdemError(rc, f"{self._L.cdem_last_error(self._h).decode()}\n{log.value.decode()}")
+        return log.value.decode()
+
     def set_mlp(self, params):
         p = np.ascontiguousarray(params, np.float32)
         self._check(self._L.cdem_set_mlp(self._h, _ptr(p), p.size))
@@ -411,6 +423,13 @@ def mlp_backward(params, features, target, tau):
     if rc:
         raise CdemError(rc, "cdem_mlp_backward")
     return grad, loss
+
+
+def check_force_law(source: str):
+    """Compile a user force law without a device: (ok, compiler messages)."""
+    log = C.create_string_buffer(1 << 16)
+    rc = load().cdem_check_force_law(source.encode(), log, len(log))
+    return rc == 0, log.value.decode()
 
 
 MLP_STATIC_MAX_SAMPLES = 16384  # CDEM_MLP_STATIC_MAX_SAMPLES of include/cdem.h

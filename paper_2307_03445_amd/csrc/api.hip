@@ -9,6 +9,7 @@
 // active-set overflow, which it repairs by growing the storage and resuming
 // from the first step that did not complete.
 #include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <cmath>
@@ -21,6 +22,7 @@
 
 #include "../../include/cdem.h"
 #include "cdem_internal.h"
+#include "rtc_embed.inc"
 
 using namespace cdem;
 
@@ -109,6 +111,9 @@ struct cdem_scene {
     std::vector<void *> owned;         // every device allocation, freed on destroy
     int64_t regrows = 0;
     uint64_t fingerprint = 0;          // of the description's static parts (checkpoints must match)
+    // user force law compiled at run time (null: the built-in law)
+    hipModule_t law_module = nullptr;
+    hipFunction_t law_pairs = nullptr;
 };
 
 // FNV-1a over raw bytes: identifies the static description a checkpoint belongs to.
@@ -709,6 +714,7 @@ extern "C" int cdem_destroy(cdem_scene *sc) {
     if (sc->gstream) { (void)hipStreamSynchronize(sc->gstream); (void)hipStreamDestroy(sc->gstream); }
     delete sc->timer;
     sc->timer = nullptr;
+    if (sc->law_module) (void)hipModuleUnload(sc->law_module);
     auto owned = sc->owned;
     for (void *p : owned) dev_free(sc, p);
     (void)hipStreamSynchronize(sc->stream);  // stream-ordered frees complete before the scene is gone
@@ -739,7 +745,7 @@ static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing)
         if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, st);
         if (e == hipSuccess) e = launch_detect(S, st);
         if (e == hipSuccess) e = launch_audit_binned(S, st);
-        if (e == hipSuccess) e = launch_force_integrate(S, st);
+        if (e == hipSuccess) e = launch_force_integrate(S, st, sc->law_pairs);
         if (e == hipSuccess && sc->collecting) e = launch_collect_acc(S, st);
         if (e == hipSuccess) e = launch_step_end(S, st);
         if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
@@ -1436,4 +1442,115 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     n.guard = 0;
     n.guard_next = 0;
     return write_ctl(sc, n);
+}
+
+// ---------------------------------------------------------------- user force law
+// The pair kernel of the step with the force law replaced by a device
+// function the caller supplies, compiled at run time with hiprtc for gfx950
+// with the library's own floating-point flags.  The kernel source is the
+// library's pair evaluation (headers embedded at build time) instantiated with
+// the user's law.
+static const char kRtcMain[] = R"CDEM_RTC_MAIN(
+#include "pair_dev.h"
+namespace cdem {
+struct UserLaw {
+    static constexpr bool kFP32 = false;
+    __device__ static __forceinline__ void f64(const double *n, double delta, const double *vrel, double Rbar,
+                                               double mbar, double estar, double gstar, double mu, double beta,
+                                               double h, const double *u_old, double *F, double *u_new) {
+        ::cdem_user_law(n, delta, vrel, Rbar, mbar, estar, gstar, mu, beta, h, u_old, F, u_new);
+    }
+};
+}  // namespace cdem
+extern "C" __global__ void __launch_bounds__(256) cdem_user_pairs64(cdem::DevScene S) {
+    cdem::pairs_body<false, cdem::UserLaw>(S);
+}
+extern "C" __global__ void __launch_bounds__(256) cdem_user_pairs32(cdem::DevScene S) {
+    cdem::pairs_body<true, cdem::UserLaw>(S);
+}
+)CDEM_RTC_MAIN";
+
+static const char kRtcLawDecl[] =
+    "__device__ void cdem_user_law(const double *n, double delta, const double *vrel, double Rbar, double mbar,\n"
+    "                              double estar, double gstar, double mu, double beta, double h,\n"
+    "                              const double *u_old, double *F, double *u_new);\n";
+
+static void copy_log(const std::string &log, char *out, size_t cap) {
+    if (!out || cap == 0) return;
+    size_t n = std::min(cap - 1, log.size());
+    memcpy(out, log.data(), n);
+    out[n] = 0;
+}
+
+// Compile the user law into a code object; false with the compiler's log on error.
+static bool compile_law(const char *source, std::vector<char> &code, std::string &log) {
+    std::string src = std::string(kRtcLawDecl) + "#line 1 \"user_law\"\n" + source + "\n#line 1 \"cdem_pairs\"\n" +
+                      kRtcMain;
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, src.c_str(), "cdem_user_pairs.hip", kRtcHeaderCount, kRtcHeaderTexts,
+                            kRtcHeaderNames) != HIPRTC_SUCCESS) {
+        log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    const char *opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                          "-fhip-fp32-correctly-rounded-divide-sqrt", "-Xclang", "-target-feature", "-Xclang",
+                          "-packed-fp32-ops"};
+    hiprtcResult r = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    size_t ls = 0;
+    hiprtcGetProgramLogSize(prog, &ls);
+    log.assign(ls, '\0');
+    if (ls) hiprtcGetProgramLog(prog, &log[0]);
+    while (!log.empty() && log.back() == '\0') log.pop_back();
+    bool ok = r == HIPRTC_SUCCESS;
+    if (ok) {
+        size_t cs = 0;
+        ok = hiprtcGetCodeSize(prog, &cs) == HIPRTC_SUCCESS && cs > 0;
+        if (ok) {
+            code.resize(cs);
+            ok = hiprtcGetCode(prog, code.data()) == HIPRTC_SUCCESS;
+        }
+        if (!ok && log.empty()) log = "no code object produced";
+    }
+    hiprtcDestroyProgram(&prog);
+    return ok;
+}
+
+extern "C" int cdem_check_force_law(const char *source, char *log, size_t log_cap) {
+    copy_log("", log, log_cap);
+    if (!source || !*source) return CDEM_E_INVALID;
+    std::vector<char> code;
+    std::string lg;
+    bool ok = compile_law(source, code, lg);
+    copy_log(lg, log, log_cap);
+    return ok ? CDEM_OK : CDEM_E_INVALID;
+}
+
+extern "C" int cdem_set_force_law(cdem_scene *sc, const char *source, char *log, size_t log_cap) {
+    if (!sc) return CDEM_E_INVALID;
+    copy_log("", log, log_cap);
+    hipModule_t mod = nullptr;
+    hipFunction_t fn = nullptr;
+    if (source && *source) {
+        std::vector<char> code;
+        std::string lg;
+        if (!compile_law(source, code, lg)) {
+            copy_log(lg, log, log_cap);
+            return fail(sc, CDEM_E_INVALID, "the force law did not compile: " + lg.substr(0, 2000));
+        }
+        copy_log(lg, log, log_cap);
+        HIPCHK(hipStreamSynchronize(sc->stream));
+        if (hipModuleLoadData(&mod, code.data()) != hipSuccess)
+            return fail(sc, CDEM_E_HIP, "hipModuleLoadData of the compiled force law failed");
+        const char *name = sc->S.precision == 1 ? "cdem_user_pairs32" : "cdem_user_pairs64";
+        if (hipModuleGetFunction(&fn, mod, name) != hipSuccess) {
+            (void)hipModuleUnload(mod);
+            return fail(sc, CDEM_E_HIP, "compiled force law has no pair kernel");
+        }
+    }
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    drop_graph(sc);  // captured launches name the previous pair kernel
+    if (sc->law_module) (void)hipModuleUnload(sc->law_module);
+    sc->law_module = mod;
+    sc->law_pairs = fn;
+    return CDEM_OK;
 }

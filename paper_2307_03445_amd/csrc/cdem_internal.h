@@ -2,7 +2,9 @@
 // translation unit and the host runtime; not part of the public ABI.
 #pragma once
 
+#ifndef __HIPCC_RTC__  // (the run-time compiler provides the HIP device environment itself)
 #include <hip/hip_runtime.h>
+#endif
 #include <stdint.h>
 
 namespace cdem {
@@ -211,6 +213,7 @@ __host__ __device__ inline unsigned region_blocks(int64_t n_regions) {
     return (unsigned)(n > 1 ? n : 1);
 }
 
+#ifndef __HIPCC_RTC__  // host side of the library only
 // Optional per-kernel timing: when non-null, launchers bracket every kernel
 // with events taken from the pool and note which kernel each pair belongs to.
 struct KernelTimer {
@@ -232,7 +235,10 @@ extern KernelTimer *g_timer;
 // detection, an audit, training-data capture); readouts pass force = true.
 hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force);
 hipError_t launch_detect(const DevScene &S, hipStream_t st);
-hipError_t launch_force_integrate(const DevScene &S, hipStream_t st);
+// user_pairs: the pair kernel of a user force law compiled at run time (its
+// DevScene argument by value, 256 lanes per workgroup), or null for the
+// built-in law.
+hipError_t launch_force_integrate(const DevScene &S, hipStream_t st, hipFunction_t user_pairs);
 hipError_t launch_step_end(const DevScene &S, hipStream_t st);
 hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uint32_t *first, hipStream_t st);
 // Periodic binned exact audit (every plan.audit_period steps, decided on the device).
@@ -247,5 +253,6 @@ hipError_t launch_count_contacts(const DevScene &S, unsigned long long *part, in
 // Force and torque on every boundary from the recorded step: partial [n_bnd][kBndParts][6], out [n_bnd][6].
 constexpr int kBndParts = 64;
 hipError_t launch_bnd_forces(const DevScene &S, double *partial, double *out, hipStream_t st);
+#endif  // __HIPCC_RTC__
 
 }  // namespace cdem

@@ -37,62 +37,12 @@
 // written.
 #include "cdem_internal.h"
 #include "mlp_dev.h"
+#include "pair_dev.h"
+#include "step_dev.h"
 
 #include <math.h>
 
 namespace cdem {
-
-__device__ __forceinline__ bool aborted(const Ctl *c) { return c->overflow != 0; }
-
-// Active-set buffer k of a double-buffered array.  A select keeps the pointer
-// in registers; indexing the by-value kernel argument with a runtime k would
-// copy the pointer pair to scratch memory.
-template <typename T>
-__device__ __forceinline__ T *pick(T *const (&a)[2], int k) { return k ? a[1] : a[0]; }
-
-// ---------------------------------------------------------------- rotation
-__device__ __forceinline__ void quat_mat(double w, double x, double y, double z, double *A) {
-    A[0] = 1.0 - 2.0 * (y * y + z * z);
-    A[1] = 2.0 * (x * y - w * z);
-    A[2] = 2.0 * (x * z + w * y);
-    A[3] = 2.0 * (x * y + w * z);
-    A[4] = 1.0 - 2.0 * (x * x + z * z);
-    A[5] = 2.0 * (y * z - w * x);
-    A[6] = 2.0 * (x * z - w * y);
-    A[7] = 2.0 * (y * z + w * x);
-    A[8] = 1.0 - 2.0 * (x * x + y * y);
-}
-
-// ---------------------------------------------------------------- pose (per sphere)
-// Kinematics of sphere s from its clump's state record: centre x_s = x_c +
-// A(q) o_s and radius, and the clump's CoM, mass, velocity and world angular
-// velocity A(q) w_body.  Every kernel that needs a sphere's pose computes it
-// this one way, so the positions of a detection, of the force kernel and of
-// a readout are the same numbers.
-struct SphereKin { double p[3], R, xc[3], M, v[3], W[3]; };
-// ... of the sphere that is template sphere ts of clump c
-__device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c, uint32_t ts) {
-    const double4 *r = S.cst + 4 * (int64_t)c;
-    const double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
-    const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
-    SphereKin k;
-    k.R = S.tmpl_rad[ts];
-    double A[9];
-    quat_mat(k2.x, k2.y, k2.z, k2.w, A);
-    k.p[0] = k0.x + (A[0] * o0 + A[1] * o1 + A[2] * o2);
-    k.p[1] = k0.y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
-    k.p[2] = k0.z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
-    k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
-    k.M = k0.w;
-    k.v[0] = k1.x; k.v[1] = k1.y; k.v[2] = k1.z;
-    k.W[0] = A[0] * k3.x + A[1] * k3.y + A[2] * k3.z;
-    k.W[1] = A[3] * k3.x + A[4] * k3.y + A[5] * k3.z;
-    k.W[2] = A[6] * k3.x + A[7] * k3.y + A[8] * k3.z;
-    return k;
-}
-__device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
-    return sphere_kin_of(S, S.owner[s], S.sts[s]);
-}
 
 // Raise a device-wide float maximum kept as bits in the control block.  The
 // current value is read at device scope first (a plain load may see a stale
@@ -109,72 +59,6 @@ __device__ __forceinline__ void raise_max(uint32_t *slot, float v) {
 __device__ __forceinline__ bool due(const Ctl *c) { return (c->det_due | c->guard) != 0; }
 __device__ __forceinline__ bool audit_due(const DevScene &S) {
     return S.plan.audit_period > 0 && (S.ctl->step % S.plan.audit_period) == 0;
-}
-
-// ---------------------------------------------------------------- boundaries
-// Signed distance of p from boundary b at time t (positive on the domain side)
-// and the unit normal from the wall into the domain.  Returns false where the
-// boundary cannot touch p.
-__device__ __forceinline__ bool bnd_distance(const Bnd &B, double t, double px, double py, double pz, double &phi, double *n) {
-    const double *P = B.p;
-    double r0x = P[0] + t * B.vel[0], r0y = P[1] + t * B.vel[1], r0z = P[2] + t * B.vel[2];
-    double d0 = px - r0x, d1 = py - r0y, d2 = pz - r0z;
-    if (B.type == 0) {
-        phi = d0 * P[3] + d1 * P[4] + d2 * P[5];
-        n[0] = P[3]; n[1] = P[4]; n[2] = P[5];
-        return true;
-    }
-    double a0 = P[3], a1 = P[4], a2 = P[5];
-    double ta = d0 * a0 + d1 * a1 + d2 * a2;
-    double rho0 = d0 - ta * a0, rho1 = d1 - ta * a1, rho2 = d2 - ta * a2;
-    double r = sqrt(rho0 * rho0 + rho1 * rho1 + rho2 * rho2);
-    if (B.type == 1) {
-        if (!(r > 0.0)) return false;
-        phi = P[6] - r;
-        n[0] = -(rho0 / r); n[1] = -(rho1 / r); n[2] = -(rho2 / r);
-        return true;
-    }
-    double sn = P[6], cs = P[7];
-    if (B.type == 2) {
-        double H = P[8];
-        double rb = H * (sn / cs);
-        double lam = ta * cs + r * sn;
-        if (ta >= H) {
-            if (!(r > 0.0)) return false;
-            phi = r - rb;
-            n[0] = rho0 / r; n[1] = rho1 / r; n[2] = rho2 / r;
-            return true;
-        }
-        if (lam <= 0.0) {
-            double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
-            if (!(dd > 0.0)) return false;
-            phi = dd;
-            n[0] = d0 / dd; n[1] = d1 / dd; n[2] = d2 / dd;
-            return true;
-        }
-        if (!(r > 0.0)) return false;
-        if (lam <= H / cs) {
-            phi = r * cs - ta * sn;
-            n[0] = (rho0 / r) * cs - a0 * sn;
-            n[1] = (rho1 / r) * cs - a1 * sn;
-            n[2] = (rho2 / r) * cs - a2 * sn;
-            return true;
-        }
-        double dt = ta - H, dr = r - rb;
-        double dd = sqrt(dt * dt + dr * dr);
-        if (!(dd > 0.0)) return false;
-        phi = dd;
-        n[0] = (dt * a0 + dr * (rho0 / r)) / dd;
-        n[1] = (dt * a1 + dr * (rho1 / r)) / dd;
-        n[2] = (dt * a2 + dr * (rho2 / r)) / dd;
-        return true;
-    }
-    if (ta < P[8] || ta > P[9] || !(r > 0.0)) return false;
-    phi = ta * sn - r * cs;
-    n[0] = a0 * sn - (rho0 / r) * cs;
-    n[1] = a1 * sn - (rho1 / r) * cs;
-    n[2] = a2 * sn - (rho2 / r) * cs;
-    return true;
 }
 
 // ---------------------------------------------------------------- binning
@@ -275,17 +159,6 @@ __device__ __forceinline__ int64_t region_of(const Grid &g, uint32_t cell) {
     return g.reg0 + ix / kRegionBins + (int64_t)g.rnx * (iy / kRegionBins + (int64_t)g.rny * (iz / kRegionBins));
 }
 
-// The hardware hands workgroup i of a launch to XCD i mod 8, and each XCD has
-// its own L2.  xcd_block() renumbers the workgroups so that every XCD works on
-// one contiguous range of logical blocks: neighbouring items (spheres of one
-// bin, pairs of nearby spheres, the spheres of a clump) then share one L2
-// instead of being fetched by several.  A bijection of [0, gridDim.x).
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_block() {
-    const uint32_t b = blockIdx.x, n = gridDim.x;
-    const uint32_t x = b % kXcds, k = b / kXcds, per = n / kXcds, rem = n % kXcds;
-    return x * per + min(x, rem) + k;
-}
 
 // which = 0: the detection chain; which = 1: the periodic audit's own binning
 // which = 2: training-data capture (always runs when launched)
@@ -1097,320 +970,9 @@ __global__ void k_detect_end(DevScene S) {
     c->guard = 0;
 }
 
-// ---------------------------------------------------------------- contact law
-struct Acc { double F[3], T[3]; };
-
-__device__ __forceinline__ void cross3(const double *a, const double *b, double *c) {
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-__device__ __forceinline__ void cross3f(const float *a, const float *b, float *c) {
-    c[0] = a[1] * b[2] - a[2] * b[1];
-    c[1] = a[2] * b[0] - a[0] * b[2];
-    c[2] = a[0] * b[1] - a[1] * b[0];
-}
-
-// FP64 Hertz-Mindlin law: force on body b and updated history.
-__device__ __forceinline__ void law64(const double *n, double delta, const double *vrel, double Rbar, double mbar,
-                      double estar, double gstar, double mu, double beta, double h, const double *u_old,
-                      double *F, double *u_new) {
-    const double kdamp = -2.0 * sqrt(5.0 / 6.0);
-    double vn_s = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
-    double vn[3], vt[3];
-    for (int i = 0; i < 3; i++) vn[i] = vn_s * n[i];
-    for (int i = 0; i < 3; i++) vt[i] = vrel[i] - vn[i];
-    double sq = sqrt(Rbar * delta);
-    double Sn = 2.0 * estar * sq;
-    double gn = kdamp * beta * sqrt(Sn * mbar);
-    double kn = (4.0 / 3.0) * estar * sq * delta;
-    double Fn[3];
-    for (int i = 0; i < 3; i++) Fn[i] = kn * n[i] - gn * vn[i];
-    double up[3];
-    for (int i = 0; i < 3; i++) up[i] = u_old[i] + h * vt[i];
-    double upn = up[0] * n[0] + up[1] * n[1] + up[2] * n[2];
-    double ut[3];
-    for (int i = 0; i < 3; i++) ut[i] = up[i] - upn * n[i];
-    double St = 8.0 * gstar * sq;
-    double gt = kdamp * beta * sqrt(St * mbar);
-    double Ft[3];
-    for (int i = 0; i < 3; i++) Ft[i] = -(St * ut[i]) - gt * vt[i];
-    double fn_norm = sqrt(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
-    double ft_norm = sqrt(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
-    double cap = mu * fn_norm;
-    if (ft_norm > cap) {
-        double scale = cap / ft_norm;
-        for (int i = 0; i < 3; i++) Ft[i] = Ft[i] * scale;
-        double ut_norm = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-        if (ut_norm > 0.0) {
-            double fac = (cap / St) / ut_norm;
-            for (int i = 0; i < 3; i++) u_new[i] = fac * ut[i];
-        } else {
-            for (int i = 0; i < 3; i++) u_new[i] = 0.0;
-        }
-    } else {
-        for (int i = 0; i < 3; i++) u_new[i] = ut[i];
-    }
-    for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
-}
-
-// FP32 law: force arithmetic in FP32; the history update, its projection and
-// the clamp of the history stay in FP64.
-__device__ __forceinline__ void law32(const double *nd, double delta_d, const float *vrel, float Rbar, float mbar, float estar,
-                      float gstar, float mu, float beta, double h, const double *u_old, float *F, double *u_new) {
-    const float kdamp = -2.0f * sqrtf(5.0f / 6.0f);
-    float n[3] = {(float)nd[0], (float)nd[1], (float)nd[2]};
-    float delta = (float)delta_d;
-    float vn_s = vrel[0] * n[0] + vrel[1] * n[1] + vrel[2] * n[2];
-    float vn[3], vt[3];
-    for (int i = 0; i < 3; i++) vn[i] = vn_s * n[i];
-    for (int i = 0; i < 3; i++) vt[i] = vrel[i] - vn[i];
-    float sq = sqrtf(Rbar * delta);
-    float Sn = 2.0f * estar * sq;
-    float gn = kdamp * beta * sqrtf(Sn * mbar);
-    float kn = (4.0f / 3.0f) * estar * sq * delta;
-    float Fn[3];
-    for (int i = 0; i < 3; i++) Fn[i] = kn * n[i] - gn * vn[i];
-    double up[3];
-    for (int i = 0; i < 3; i++) up[i] = u_old[i] + h * (double)vt[i];
-    double upn = up[0] * nd[0] + up[1] * nd[1] + up[2] * nd[2];
-    double ut[3];
-    for (int i = 0; i < 3; i++) ut[i] = up[i] - upn * nd[i];
-    float St = 8.0f * gstar * sq;
-    float gt = kdamp * beta * sqrtf(St * mbar);
-    float Ft[3];
-    for (int i = 0; i < 3; i++) Ft[i] = -(St * (float)ut[i]) - gt * vt[i];
-    float fn_norm = sqrtf(Fn[0] * Fn[0] + Fn[1] * Fn[1] + Fn[2] * Fn[2]);
-    float ft_norm = sqrtf(Ft[0] * Ft[0] + Ft[1] * Ft[1] + Ft[2] * Ft[2]);
-    float cap = mu * fn_norm;
-    if (ft_norm > cap) {
-        float scale = cap / ft_norm;
-        for (int i = 0; i < 3; i++) Ft[i] = Ft[i] * scale;
-        double ut_norm = sqrt(ut[0] * ut[0] + ut[1] * ut[1] + ut[2] * ut[2]);
-        if (ut_norm > 0.0) {
-            double fac = (double)(cap / St) / ut_norm;
-            for (int i = 0; i < 3; i++) u_new[i] = fac * ut[i];
-        } else {
-            for (int i = 0; i < 3; i++) u_new[i] = 0.0;
-        }
-    } else {
-        for (int i = 0; i < 3; i++) u_new[i] = ut[i];
-    }
-    for (int i = 0; i < 3; i++) F[i] = Fn[i] + Ft[i];
-}
-
-// Per-pair contribution storage: force on the pair's lower sphere with the
-// contact flag in w, that sphere's torque about its clump CoM, and the
-// partner sphere's torque (its force is minus the first); FP32 mode stores
-// floats.
-// Stores that mark their lines non-temporal: the pair contributions are
-// read once, by the next kernel, long after the L2 has turned over.
-__device__ __forceinline__ void store_nt(float4 *p, float4 v) {
-    __builtin_nontemporal_store(v.x, &p->x); __builtin_nontemporal_store(v.y, &p->y);
-    __builtin_nontemporal_store(v.z, &p->z); __builtin_nontemporal_store(v.w, &p->w);
-}
-__device__ __forceinline__ void store_nt(double4 *p, double4 v) {
-    __builtin_nontemporal_store(v.x, &p->x); __builtin_nontemporal_store(v.y, &p->y);
-    __builtin_nontemporal_store(v.z, &p->z); __builtin_nontemporal_store(v.w, &p->w);
-}
-
-template <bool FP32> struct Contrib;
-template <> struct Contrib<true> {
-    using V = float4;
-    static __device__ __forceinline__ V make(const double *a, double w) {
-        return make_float4((float)a[0], (float)a[1], (float)a[2], (float)w);
-    }
-};
-template <> struct Contrib<false> {
-    using V = double4;
-    static __device__ __forceinline__ V make(const double *a, double w) { return make_double4(a[0], a[1], a[2], w); }
-};
-
-// Torque r x f, in FP32 when the force law ran in FP32.
-template <bool FP32>
-__device__ __forceinline__ void torque(const double *r, const double *f, double *t) {
-    if (!FP32) {
-        cross3(r, f, t);
-    } else {
-        float rf[3] = {(float)r[0], (float)r[1], (float)r[2]}, ff[3] = {(float)f[0], (float)f[1], (float)f[2]}, tf[3];
-        cross3f(rf, ff, tf);
-        t[0] = tf[0]; t[1] = tf[1]; t[2] = tf[2];
-    }
-}
-
-// Evaluate pair e of the active set once, for both bodies: sphere pairs
-// have the lower sphere as body a; a boundary pair has the sphere as body b.
-// Writes the pair's history and contributions, and returns the contact
-// sides it created.
-// Ids of a pair and the clumps and template spheres of its spheres (b unused
-// for a boundary pair).
-struct PairIds { uint32_t s, t, ca, ta, cb, tb; };
-__device__ __forceinline__ PairIds pair_ids(const DevScene &S, uint32_t s, uint32_t t) {
-    PairIds q{s, t, S.owner[s], S.sts[s], 0u, 0u};
-    if (t < (uint32_t)S.ns) { q.cb = S.owner[t]; q.tb = S.sts[t]; }
-    return q;
-}
-
-template <bool FP32>
-__device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
-                                              double tnow, bool rec) {
-    using V = typename Contrib<FP32>::V;
-    V *cS = (V *)S.cS, *cTs = (V *)S.cTs, *cTt = (V *)S.cTt;
-    const double zero3[3] = {0.0, 0.0, 0.0};
-    const uint32_t s = id.s, t = id.t;
-    double *h = hist + 3 * e;
-    if (t < (uint32_t)S.ns) {
-        const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
-        const SphereKin ka = sphere_kin_of(S, id.ca, id.ta), kb = sphere_kin_of(S, id.cb, id.tb);
-        double dx = kb.p[0] - ka.p[0], dy = kb.p[1] - ka.p[1], dz = kb.p[2] - ka.p[2];
-        double d2 = dx * dx + dy * dy + dz * dz;
-        double Sr = ka.R + kb.R;
-        if (!(d2 < Sr * Sr)) {  // a false positive of the enlarged geometry: no force, no history
-            cS[e] = Contrib<FP32>::make(zero3, 0.0);
-            if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
-            if (rec) S.rec_state[e] = 0;
-            return 0;
-        }
-        double d = sqrt(d2);
-        double delta = Sr - d;
-        if (!(delta > 0.0)) {
-            cS[e] = Contrib<FP32>::make(zero3, 0.0);
-            h[0] = 0.0; h[1] = 0.0; h[2] = 0.0;
-            if (rec) { S.rec_state[e] = 1; S.rec_delta[e] = delta; S.rec_F[3 * e] = 0; S.rec_F[3 * e + 1] = 0; S.rec_F[3 * e + 2] = 0; }
-            return 0;
-        }
-        double n[3] = {dx / d, dy / d, dz / d};
-        double lever = ka.R - 0.5 * delta;
-        double p[3] = {ka.p[0] + lever * n[0], ka.p[1] + lever * n[1], ka.p[2] + lever * n[2]};
-        double ra[3] = {p[0] - ka.xc[0], p[1] - ka.xc[1], p[2] - ka.xc[2]};
-        double rb[3] = {p[0] - kb.xc[0], p[1] - kb.xc[1], p[2] - kb.xc[2]};
-        // contact kinematics in FP64 (relative velocities of similar speeds cancel)
-        double ca3[3], cb3[3];
-        cross3(ka.W, ra, ca3);
-        cross3(kb.W, rb, cb3);
-        double vrel[3] = {(kb.v[0] + cb3[0]) - (ka.v[0] + ca3[0]), (kb.v[1] + cb3[1]) - (ka.v[1] + ca3[1]),
-                          (kb.v[2] + cb3[2]) - (ka.v[2] + ca3[2])};
-        double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
-        if (!FP32) {
-            double Rbar = (ka.R * kb.R) / (ka.R + kb.R);
-            double mbar = (ka.M * kb.M) / (ka.M + kb.M);
-            double4 ma = S.mat64[a], mb = S.mat64[b];
-            law64(n, delta, vrel, Rbar, mbar, 1.0 / (ma.x + mb.x), 1.0 / (ma.y + mb.y), fmin(ma.z, mb.z),
-                  fmin(ma.w, mb.w), S.h, u_old, F, u_new);
-        } else {
-            float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
-            float Ra = (float)ka.R, Rb = (float)kb.R, Ma = (float)ka.M, Mb = (float)kb.M;
-            float4 ma = S.mat32[a], mb = S.mat32[b];
-            float Ff[3];
-            law32(n, delta, vrf, (Ra * Rb) / (Ra + Rb), (Ma * Mb) / (Ma + Mb), 1.0f / (ma.x + mb.x),
-                  1.0f / (ma.y + mb.y), fminf(ma.z, mb.z), fminf(ma.w, mb.w), S.h, u_old, Ff, u_new);
-            F[0] = Ff[0]; F[1] = Ff[1]; F[2] = Ff[2];
-        }
-        h[0] = u_new[0]; h[1] = u_new[1]; h[2] = u_new[2];
-        double fa[3] = {-F[0], -F[1], -F[2]}, ta[3], tb[3];
-        torque<FP32>(ra, fa, ta);
-        torque<FP32>(rb, F, tb);
-        store_nt(cS + e, Contrib<FP32>::make(fa, 1.0));
-        store_nt(cTs + e, Contrib<FP32>::make(ta, 0.0));
-        store_nt(cTt + e, Contrib<FP32>::make(tb, 0.0));
-        if (rec) {
-            S.rec_state[e] = 1; S.rec_delta[e] = delta;
-            for (int i = 0; i < 3; i++) {
-                S.rec_F[3 * e + i] = F[i]; S.rec_Ta[3 * e + i] = ta[i]; S.rec_Tb[3 * e + i] = tb[i];
-            }
-        }
-        return 2;
-    }
-    // boundary pair: the boundary is body a, sphere s is body b
-    const Bnd &B = S.bnd[t - (uint32_t)S.ns];
-    const SphereKin ks = sphere_kin_of(S, id.ca, id.ta);
-    double phi, n[3];
-    bool contact = bnd_distance(B, tnow, ks.p[0], ks.p[1], ks.p[2], phi, n) && phi < ks.R;
-    if (!contact) {
-        cS[e] = Contrib<FP32>::make(zero3, 0.0);
-        if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
-        if (rec) S.rec_state[e] = 0;
-        return 0;
-    }
-    double R = ks.R;
-    double delta = R - phi;
-    double lever = R - 0.5 * delta;
-    double p[3] = {ks.p[0] - lever * n[0], ks.p[1] - lever * n[1], ks.p[2] - lever * n[2]};
-    double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
-    double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
-    double rb[3] = {p[0] - ks.xc[0], p[1] - ks.xc[1], p[2] - ks.xc[2]};
-    double pw[3], cb3[3];
-    cross3(B.omg, ra, pw);
-    cross3(ks.W, rb, cb3);
-    double wv[3] = {B.vel[0] + pw[0], B.vel[1] + pw[1], B.vel[2] + pw[2]};
-    double vrel[3] = {(ks.v[0] + cb3[0]) - wv[0], (ks.v[1] + cb3[1]) - wv[1], (ks.v[2] + cb3[2]) - wv[2]};
-    double u_old[3] = {h[0], h[1], h[2]}, u_new[3], F[3];
-    if (!FP32) {
-        double4 ms = S.mat64[s];
-        law64(n, delta, vrel, R, ks.M, 1.0 / (B.e + ms.x), 1.0 / (B.g + ms.y), fmin(B.mu, ms.z), fmin(B.beta, ms.w),
-              S.h, u_old, F, u_new);
-    } else {
-        float vrf[3] = {(float)vrel[0], (float)vrel[1], (float)vrel[2]};
-        float4 ms = S.mat32[s];
-        float Ff[3];
-        law32(n, delta, vrf, (float)R, (float)ks.M, 1.0f / (B.ef + ms.x), 1.0f / (B.gf + ms.y), fminf(B.muf, ms.z),
-              fminf(B.betaf, ms.w), S.h, u_old, Ff, u_new);
-        F[0] = Ff[0]; F[1] = Ff[1]; F[2] = Ff[2];
-    }
-    h[0] = u_new[0]; h[1] = u_new[1]; h[2] = u_new[2];
-    double tb[3];
-    torque<FP32>(rb, F, tb);
-    cS[e] = Contrib<FP32>::make(F, 1.0);
-    cTs[e] = Contrib<FP32>::make(tb, 0.0);
-    if (rec) {
-        S.rec_state[e] = 1; S.rec_delta[e] = delta;
-        double fw[3] = {-F[0], -F[1], -F[2]}, tw[3];  // the boundary receives -F at the contact point
-        cross3(ra, fw, tw);
-        for (int i = 0; i < 3; i++) {
-            S.rec_F[3 * e + i] = F[i]; S.rec_R[3 * e + i] = ra[i];
-            S.rec_Ta[3 * e + i] = tw[i]; S.rec_Tb[3 * e + i] = tb[i];
-        }
-    }
-    return 1;
-}
-
-// Wave-level sum, one atomic per wavefront.
-
-// Every candidate pair of the active set, evaluated once, one lane per pair
-// (grid-stride in memory order, which follows the sphere ids and so is
-// spatially coherent).
 template <bool FP32>
 __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
-    if (aborted(S.ctl)) return;
-    const int cur = S.ctl->buf;
-    const uint32_t *pt = pick(S.pt, cur);
-    double *hist = pick(S.hist, cur);
-    const int64_t n = S.ctl->n_pairs_cur;
-    const bool rec = S.ctl->record != 0;
-    const double tnow = (double)S.ctl->step * S.h;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
-    // Software pipeline over the grid-stride loop: while pair e is evaluated,
-    // the clumps of the next pair and the ids of the one after are in flight.
-    PairIds now{};
-    uint32_t s2 = 0, t2 = 0;
-    if (e < n) now = pair_ids(S, S.ps[e], pt[e]);
-    if (e + stride < n) { s2 = S.ps[e + stride]; t2 = pt[e + stride]; }
-    uint32_t sides = 0;  // contact sides this lane created
-    for (; e < n; e += stride) {
-        PairIds nxt{};
-        if (e + stride < n) nxt = pair_ids(S, s2, t2);
-        if (e + 2 * stride < n) { s2 = S.ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
-        sides += eval_pair<FP32>(S, e, now, hist, tnow, rec);
-        now = nxt;
-    }
-    // the workgroup's count, for the interval rule (folded by k_step_end)
-    for (int off = 32; off > 0; off >>= 1) sides += __shfl_xor(sides, off, 64);
-    __shared__ uint32_t wsides[4];
-    if ((threadIdx.x & 63) == 0) wsides[threadIdx.x >> 6] = sides;
-    __syncthreads();
-    if (threadIdx.x == 0) S.part_c[blockIdx.x] = wsides[0] + wsides[1] + wsides[2] + wsides[3];
+    pairs_body<FP32, HertzMindlin>(S);
 }
 
 // Contact sides of the last evaluated step (each sphere pair in contact counts
@@ -2212,12 +1774,21 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_force_integrate(const DevScene &S, hipStream_t st) {
+hipError_t launch_force_integrate(const DevScene &S, hipStream_t st, hipFunction_t user_pairs) {
     if (S.nc == 0) return hipSuccess;
     const bool f32 = S.precision == 1;
     const unsigned pb = pair_blocks(S.cap, S.stride_cap);
-    if (f32) TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
-    else TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
+    if (user_pairs) {
+        DevScene arg = S;
+        void *args[] = {&arg};
+        hipError_t e = hipSuccess;
+        TIMED(K_FORCE, e = hipModuleLaunchKernel(user_pairs, pb, 1, 1, 256, 1, 1, 0, st, args, nullptr));
+        if (e != hipSuccess) return e;
+    } else if (f32) {
+        TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
+    } else {
+        TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
+    }
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
     if (wb) {
         if (f32) TIMED(K_REDUCE, hipLaunchKernelGGL(k_reduce_waves<true>, dim3(wb), dim3(256), 0, st, S));

@@ -1,0 +1,142 @@
+// Device helpers shared by the step kernels and the run-time compiled pair
+// kernel of a user force law: control-block and buffer selection, clump
+// rotation and sphere poses, analytic boundary distances, XCD-aware
+// workgroup numbering.
+#pragma once
+
+#include "cdem_internal.h"
+
+namespace cdem {
+
+__device__ __forceinline__ bool aborted(const Ctl *c) { return c->overflow != 0; }
+
+// Active-set buffer k of a double-buffered array.  A select keeps the pointer
+// in registers; indexing the by-value kernel argument with a runtime k would
+// copy the pointer pair to scratch memory.
+template <typename T>
+__device__ __forceinline__ T *pick(T *const (&a)[2], int k) { return k ? a[1] : a[0]; }
+
+// ---------------------------------------------------------------- rotation
+__device__ __forceinline__ void quat_mat(double w, double x, double y, double z, double *A) {
+    A[0] = 1.0 - 2.0 * (y * y + z * z);
+    A[1] = 2.0 * (x * y - w * z);
+    A[2] = 2.0 * (x * z + w * y);
+    A[3] = 2.0 * (x * y + w * z);
+    A[4] = 1.0 - 2.0 * (x * x + z * z);
+    A[5] = 2.0 * (y * z - w * x);
+    A[6] = 2.0 * (x * z - w * y);
+    A[7] = 2.0 * (y * z + w * x);
+    A[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// ---------------------------------------------------------------- pose (per sphere)
+// Kinematics of sphere s from its clump's state record: centre x_s = x_c +
+// A(q) o_s and radius, and the clump's CoM, mass, velocity and world angular
+// velocity A(q) w_body.  Every kernel that needs a sphere's pose computes it
+// this one way, so the positions of a detection, of the force kernel and of
+// a readout are the same numbers.
+struct SphereKin { double p[3], R, xc[3], M, v[3], W[3]; };
+// ... of the sphere that is template sphere ts of clump c
+__device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c, uint32_t ts) {
+    const double4 *r = S.cst + 4 * (int64_t)c;
+    const double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
+    const double o0 = S.tmpl_ofs[3 * ts], o1 = S.tmpl_ofs[3 * ts + 1], o2 = S.tmpl_ofs[3 * ts + 2];
+    SphereKin k;
+    k.R = S.tmpl_rad[ts];
+    double A[9];
+    quat_mat(k2.x, k2.y, k2.z, k2.w, A);
+    k.p[0] = k0.x + (A[0] * o0 + A[1] * o1 + A[2] * o2);
+    k.p[1] = k0.y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
+    k.p[2] = k0.z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
+    k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
+    k.M = k0.w;
+    k.v[0] = k1.x; k.v[1] = k1.y; k.v[2] = k1.z;
+    k.W[0] = A[0] * k3.x + A[1] * k3.y + A[2] * k3.z;
+    k.W[1] = A[3] * k3.x + A[4] * k3.y + A[5] * k3.z;
+    k.W[2] = A[6] * k3.x + A[7] * k3.y + A[8] * k3.z;
+    return k;
+}
+__device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
+    return sphere_kin_of(S, S.owner[s], S.sts[s]);
+}
+
+
+// ---------------------------------------------------------------- boundaries
+// Signed distance of p from boundary b at time t (positive on the domain side)
+// and the unit normal from the wall into the domain.  Returns false where the
+// boundary cannot touch p.
+__device__ __forceinline__ bool bnd_distance(const Bnd &B, double t, double px, double py, double pz, double &phi, double *n) {
+    const double *P = B.p;
+    double r0x = P[0] + t * B.vel[0], r0y = P[1] + t * B.vel[1], r0z = P[2] + t * B.vel[2];
+    double d0 = px - r0x, d1 = py - r0y, d2 = pz - r0z;
+    if (B.type == 0) {
+        phi = d0 * P[3] + d1 * P[4] + d2 * P[5];
+        n[0] = P[3]; n[1] = P[4]; n[2] = P[5];
+        return true;
+    }
+    double a0 = P[3], a1 = P[4], a2 = P[5];
+    double ta = d0 * a0 + d1 * a1 + d2 * a2;
+    double rho0 = d0 - ta * a0, rho1 = d1 - ta * a1, rho2 = d2 - ta * a2;
+    double r = sqrt(rho0 * rho0 + rho1 * rho1 + rho2 * rho2);
+    if (B.type == 1) {
+        if (!(r > 0.0)) return false;
+        phi = P[6] - r;
+        n[0] = -(rho0 / r); n[1] = -(rho1 / r); n[2] = -(rho2 / r);
+        return true;
+    }
+    double sn = P[6], cs = P[7];
+    if (B.type == 2) {
+        double H = P[8];
+        double rb = H * (sn / cs);
+        double lam = ta * cs + r * sn;
+        if (ta >= H) {
+            if (!(r > 0.0)) return false;
+            phi = r - rb;
+            n[0] = rho0 / r; n[1] = rho1 / r; n[2] = rho2 / r;
+            return true;
+        }
+        if (lam <= 0.0) {
+            double dd = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+            if (!(dd > 0.0)) return false;
+            phi = dd;
+            n[0] = d0 / dd; n[1] = d1 / dd; n[2] = d2 / dd;
+            return true;
+        }
+        if (!(r > 0.0)) return false;
+        if (lam <= H / cs) {
+            phi = r * cs - ta * sn;
+            n[0] = (rho0 / r) * cs - a0 * sn;
+            n[1] = (rho1 / r) * cs - a1 * sn;
+            n[2] = (rho2 / r) * cs - a2 * sn;
+            return true;
+        }
+        double dt = ta - H, dr = r - rb;
+        double dd = sqrt(dt * dt + dr * dr);
+        if (!(dd > 0.0)) return false;
+        phi = dd;
+        n[0] = (dt * a0 + dr * (rho0 / r)) / dd;
+        n[1] = (dt * a1 + dr * (rho1 / r)) / dd;
+        n[2] = (dt * a2 + dr * (rho2 / r)) / dd;
+        return true;
+    }
+    if (ta < P[8] || ta > P[9] || !(r > 0.0)) return false;
+    phi = ta * sn - r * cs;
+    n[0] = a0 * sn - (rho0 / r) * cs;
+    n[1] = a1 * sn - (rho1 / r) * cs;
+    n[2] = a2 * sn - (rho2 / r) * cs;
+    return true;
+}
+
+// The hardware hands workgroup i of a launch to XCD i mod 8, and each XCD has
+// its own L2.  xcd_block() renumbers the workgroups so that every XCD works on
+// one contiguous range of logical blocks: neighbouring items (spheres of one
+// bin, pairs of nearby spheres, the spheres of a clump) then share one L2
+// instead of being fetched by several.  A bijection of [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_block() {
+    const uint32_t b = blockIdx.x, n = gridDim.x;
+    const uint32_t x = b % kXcds, k = b / kXcds, per = n / kXcds, rem = n % kXcds;
+    return x * per + min(x, rem) + k;
+}
+
+}  // namespace cdem
