@@ -114,6 +114,7 @@ struct cdem_scene {
     // user force law compiled at run time (null: the built-in law)
     hipModule_t law_module = nullptr;
     hipFunction_t law_pairs = nullptr;
+    int nslots = 2;                    // active-set slots with pair storage (3 in overlap mode)
 };
 
 // FNV-1a over raw bytes: identifies the static description a checkpoint belongs to.
@@ -332,41 +333,50 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     DevScene &S = sc->S;
     if (cap > kMaxCap)
         return fail(sc, CDEM_E_CAPACITY, "the active set would exceed 2^32 - 1 entries (32-bit pair offsets)");
-    uint32_t *pt[2];
+    const int nslots = sc->nslots;
+    uint32_t *pt[3] = {nullptr, nullptr, nullptr};
     double *hs[2];
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < nslots; k++) {
         pt[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        if (!pt[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
+    }
+    for (int k = 0; k < 2; k++) {
         hs[k] = (double *)dev_alloc(sc, cap * 24);
-        if (!pt[k] || !hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
+        if (!hs[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
     }
     // per-pair and upper-segment arrays rebuilt at each detection (no content to keep)
-    dev_free(sc, S.ps); dev_free(sc, S.cS); dev_free(sc, S.cTs); dev_free(sc, S.cTt);
-    dev_free(sc, S.ut); dev_free(sc, S.us); dev_free(sc, S.um);
+    dev_free(sc, S.cS); dev_free(sc, S.cTs); dev_free(sc, S.cTt);
+    for (int k = 0; k < 3; k++) {
+        dev_free(sc, S.ps[k]); dev_free(sc, S.ut[k]); dev_free(sc, S.us[k]); dev_free(sc, S.um[k]);
+        S.ps[k] = S.ut[k] = S.us[k] = S.um[k] = nullptr;
+    }
     const size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 16 : 32;  // float4 / double4
-    S.ps = (uint32_t *)dev_alloc(sc, cap * 4);
     S.cS = dev_alloc(sc, cap * cw);
     S.cTs = dev_alloc(sc, cap * cw);
     S.cTt = dev_alloc(sc, cap * cw);
-    S.ut = (uint32_t *)dev_alloc(sc, cap * 4);
-    S.us = (uint32_t *)dev_alloc(sc, cap * 4);
-    S.um = (uint32_t *)dev_alloc(sc, cap * 4);
-    if (!S.ps || !S.cS || !S.cTs || !S.cTt || !S.ut || !S.us || !S.um)
-        return fail(sc, CDEM_E_OOM, "active-set storage");
+    if (!S.cS || !S.cTs || !S.cTt) return fail(sc, CDEM_E_OOM, "active-set storage");
+    for (int k = 0; k < nslots; k++) {
+        S.ps[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        S.ut[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        S.us[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        S.um[k] = (uint32_t *)dev_alloc(sc, cap * 4);
+        if (!S.ps[k] || !S.ut[k] || !S.us[k] || !S.um[k]) return fail(sc, CDEM_E_OOM, "active-set storage");
+    }
     if (keep) {
         // preserve the current pairs and their history (lower segments point into them)
         Ctl c;
         if (hipMemcpy(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return fail(sc, CDEM_E_HIP, "ctl read");
-        int cur = c.buf;
+        const int cur = c.buf, hb = c.hb;
         size_t n = (size_t)std::min<int64_t>(c.n_pairs_cur, S.cap);
-        if (n) {
+        if (n && S.pt[cur]) {
             if (hipMemcpyAsync(pt[cur], S.pt[cur], n * 4, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess ||
-                hipMemcpyAsync(hs[cur], S.hist[cur], n * 24, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess)
+                hipMemcpyAsync(hs[hb], S.hist[hb], n * 24, hipMemcpyDeviceToDevice, sc->stream) != hipSuccess)
                 return fail(sc, CDEM_E_HIP, "active-set copy");
         }
         if (hipStreamSynchronize(sc->stream) != hipSuccess) return fail(sc, CDEM_E_HIP, "sync");
-        for (int k = 0; k < 2; k++) { dev_free(sc, S.pt[k]); dev_free(sc, S.hist[k]); }
     }
-    for (int k = 0; k < 2; k++) { S.pt[k] = pt[k]; S.hist[k] = hs[k]; }
+    for (int k = 0; k < 3; k++) { dev_free(sc, S.pt[k]); S.pt[k] = pt[k]; }
+    for (int k = 0; k < 2; k++) { dev_free(sc, S.hist[k]); S.hist[k] = hs[k]; }
     S.cap = cap;
     if (sc->rec_cap) {  // recording arrays follow the capacity
         dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
@@ -637,7 +647,6 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.n_big = (int32_t)big.size();
     S.spos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
     S.cdet = (double4 *)dev_alloc(sc, 2 * sizeof(double4) * std::max<int64_t>(nc, 1));
-    S.smargin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cell_of = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cell_rank = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_id = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
@@ -657,15 +666,18 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.over_cap = std::max<int64_t>(4096, ns / 8);
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
     if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < 3; k++) {  // per-sphere structure of the three active-set slots
         S.lo_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
         S.lo_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.up_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.up_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        S.smargin[k] = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+        if (!S.lo_beg[k] || !S.lo_cnt[k] || !S.up_beg[k] || !S.up_cnt[k] || !S.smargin[k])
+            return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     }
-    S.up_beg = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    S.up_cnt = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    if (!S.cdet || !S.spos || !S.smargin || !S.cell_of || !S.cell_rank || !S.sorted_id || !S.sorted_owner ||
-        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl || !S.lo_beg[0] || !S.lo_beg[1] ||
-        !S.lo_cnt[0] || !S.lo_cnt[1] || !S.up_beg || !S.up_cnt)
+    S.bslot = 2;  // no detection ahead on a second stream: slots 0 and 1 alternate
+    if (!S.cdet || !S.spos || !S.cell_of || !S.cell_rank || !S.sorted_id || !S.sorted_owner ||
+        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     if (!big.empty()) {
         S.sF = (double *)dev_alloc(sc, 24 * ns);
@@ -686,21 +698,20 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     c.det_due = 1;
     c.k_cur = 1;
     if (hipMemcpyAsync(S.ctl, &c, sizeof c, hipMemcpyHostToDevice, sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "ctl"));
-    for (int k = 0; k < 2; k++) {
+    for (int k = 0; k < 3; k++) {
         if (launch_zero(S.lo_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
-            launch_zero(S.lo_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
+            launch_zero(S.lo_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
+            launch_zero(S.up_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
+            launch_zero(S.up_cnt[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
+            launch_zero(S.smargin[k], 4 * (size_t)ns, sc->stream) != hipSuccess)
             return bail(fail(sc, CDEM_E_HIP, "zero"));
     }
-    if (launch_zero(S.up_beg, 4 * (size_t)ns, sc->stream) != hipSuccess ||
-        launch_zero(S.up_cnt, 4 * (size_t)ns, sc->stream) != hipSuccess)
-        return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (launch_zero(S.part_c, 4 * (size_t)kPairBlocksMax, sc->stream) != hipSuccess ||
         launch_zero(S.part_k, 2 * 8 * (size_t)kRegionBlocksMax, sc->stream) != hipSuccess)
         return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (launch_zero(S.cacc, 4 * (size_t)nc, sc->stream) != hipSuccess ||
         launch_zero(S.sspeed, 4 * (size_t)ns, sc->stream) != hipSuccess ||
-        launch_zero(S.cdet, 2 * sizeof(double4) * nc, sc->stream) != hipSuccess ||
-        launch_zero(S.smargin, 4 * (size_t)ns, sc->stream) != hipSuccess)
+        launch_zero(S.cdet, 2 * sizeof(double4) * nc, sc->stream) != hipSuccess)
         return bail(fail(sc, CDEM_E_HIP, "zero"));
     if (hipStreamSynchronize(sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "sync"));
     *out = sc;
@@ -1022,7 +1033,7 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
         HIPCHK(hipMemcpy(st.data(), S.rec_state, ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
         HIPCHK(hipMemcpy(F.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(H.data(), S.hist[cur], 24 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(H.data(), S.hist[c.hb], 24 * ne, hipMemcpyDeviceToHost));
         if (v->Ta) HIPCHK(hipMemcpy(Ta.data(), S.rec_Ta, 24 * ne, hipMemcpyDeviceToHost));
         if (v->Tb) HIPCHK(hipMemcpy(Tb.data(), S.rec_Tb, 24 * ne, hipMemcpyDeviceToHost));
     }
@@ -1382,7 +1393,7 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     o += 8 * S.ns;
     if (E) {
         HIPCHK(hipMemcpy(o, S.pt[cur], 4 * E, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(o + 4 * E, S.hist[cur], 24 * E, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(o + 4 * E, S.hist[c.hb], 24 * E, hipMemcpyDeviceToHost));
     }
     o += 28 * E;
     if (mlp) HIPCHK(hipMemcpy(o, S.mlp, 4 * (size_t)cdem_mlp_param_count(), hipMemcpyDeviceToHost));
@@ -1430,12 +1441,13 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     }
     if (E) {
         HIPCHK(hipMemcpy(S.pt[cur], rows + 8 * S.ns, 4 * E, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(S.hist[cur], rows + 8 * S.ns + 4 * E, 24 * E, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(S.hist[c.hb], rows + 8 * S.ns + 4 * E, 24 * E, hipMemcpyHostToDevice));
     }
     // resume the saved schedule on this scene's buffers; the active set is
     // rebuilt (with the saved history carried over) before the next step
     Ctl n = hd.ctl;
     n.buf = cur;
+    n.hb = c.hb;
     n.n_pairs_cur = E;
     n.det_due = 1;
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;

@@ -72,7 +72,7 @@ struct Ctl {
     int64_t audit_last_missed;
     int64_t n_bp;            // boundary pairs written by the detection in progress
     int32_t guard_next;      // guard trips of the clumps integrated outside the wave reduction
-    int32_t pad2;
+    int32_t hb;              // which of the two history buffers holds the history of the set in use
     // interval rule of the learned envelopes: the modelled bytes per step
     int64_t contact_sides_last;  // contact sides of the last completed step (2 per sphere pair, 1 per boundary)
     double c_cal;                // measured / modelled false-positive pairs at the last detection (0: none yet)
@@ -118,7 +118,7 @@ struct DevScene {
     const float4 *mat32;
     // sphere dynamic
     double4 *spos;                   // (x, y, z, R), written by k_pose when a step needs positions
-    float *smargin;                  // margin assigned at the last detection
+    float *smargin[3];               // margin each sphere took at the detection of the set in that slot
     double4 *cdet;                   // [nc][2] clump pose at the last detection: (x, 0), q
     double *sF, *sT;                 // [ns][3] per-sphere sums (big clumps only)
     // binning
@@ -135,17 +135,22 @@ struct DevScene {
     // "lower segment" of its lower-id sphere (partners above that id,
     // ascending, boundaries last), with its tangential history; the higher
     // sphere lists the pair in its "upper segment" (partners below its id,
-    // ascending) through a link to the pair.  The lower segments come in two
-    // buffers, current chosen by ctl->buf: a detection builds the new set
-    // while carrying the history over from the current one.
-    uint32_t *lo_beg[2], *lo_cnt[2];  // [ns] each sphere's lower segment in the pair arrays
-    uint32_t *pt[2];                  // [cap] partner of the pair: sphere id, or ns + boundary
+    // ascending) through a link to the pair.  The structure comes in three
+    // slots: the set in use (ctl->buf), the one a detection on the step's
+    // stream builds (the third slot besides the one in use and bslot), and
+    // bslot, which a detection running ahead on a second stream builds while
+    // the steps go on (overlap mode; bslot = 2 and unused otherwise).  The
+    // tangential history comes in two buffers (ctl->hb holds the set in
+    // use's): a detection carries it from the set in use into the other
+    // buffer, laid out for the new set.
+    uint32_t *lo_beg[3], *lo_cnt[3];  // [ns] each sphere's lower segment in the pair arrays
+    uint32_t *pt[3];                  // [cap] partner of the pair: sphere id, or ns + boundary
     double *hist[2];                  // [cap][3]
-    uint32_t *ps;                     // [cap] the pair's lower sphere (current set)
+    uint32_t *ps[3];                  // [cap] the pair's lower sphere
     void *cS, *cTs, *cTt;             // [cap] per pair this step: force on the lower sphere (w: 1 if in contact),
                                       // torque on the lower sphere, torque on the partner sphere (float4 / double4)
-    uint32_t *up_beg, *up_cnt;        // [ns] each sphere's upper segment (current set)
-    uint32_t *ut, *us, *um;           // [cap] upper entries: partner (lower id), own sphere, linked pair
+    uint32_t *up_beg[3], *up_cnt[3];  // [ns] each sphere's upper segment
+    uint32_t *ut[3], *us[3], *um[3];  // [cap] upper entries: partner (lower id), own sphere, linked pair
     // per-workgroup partial results, reduced by the next single-workgroup kernel
     // (device-wide same-address atomics serialise; these do not)
     uint32_t *part_r;                 // [n_rblocks + 256][3] reduction: max acceleration, max speed, guard trip
@@ -193,6 +198,12 @@ struct DevScene {
     int64_t n_waves;
     // launch shape of the grid-stride kernels (tunable; results do not depend on it)
     int32_t stride_cap;              // maximum workgroups of k_pairs / k_link / k_bin_margin
+    // detection overlapped with the dynamics (a second stream builds the next
+    // active set from a snapshot of the state while the steps go on)
+    int32_t overlap;                 // on: detections are scheduled by the host (the device re-detects on a guard trip)
+    int32_t bslot;                   // the structure slot the second stream's detection writes
+    int32_t bchain;                  // this launch belongs to the second stream's detection
+    int32_t horizon;                 // steps the margins of a second-stream detection cover
     int32_t pad3;
 };
 

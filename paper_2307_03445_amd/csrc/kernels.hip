@@ -399,7 +399,7 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     float m = S.detect_mode == 2 ? S.bin_margin[region_of(g, cell)] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
-    S.smargin[s] = m;
+    slot3(S.smargin, out_slot(S))[s] = m;
 }
 
 // Fixed rule of the enlarged contact geometry: the margin covers k steps of
@@ -679,7 +679,7 @@ __device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid 
     NarrowSelf n;
     n.P = S.spos[s];
     n.own = S.owner[s];
-    n.ms = S.smargin[s];
+    n.ms = slot3(S.smargin, out_slot(S))[s];  // this detection's margin
     n.Pf = make_float4((float)(n.P.x - g.ox), (float)(n.P.y - g.oy), (float)(n.P.z - g.oz), (float)n.P.w + n.ms);
     n.exact_only = !(fabsf(n.Pf.x) < g.pre_lim && fabsf(n.Pf.y) < g.pre_lim && fabsf(n.Pf.z) < g.pre_lim);
     n.reach = (n.P.w + (double)n.ms) + g.rm_max + 1e-9;
@@ -764,35 +764,52 @@ __device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s,
     narrow_boundaries(S, g, n, emit);
 }
 
-// Write the new segments of sphere s from its ascending candidates get(k):
-// the first n_up (partners below s) to its upper segment at ub, the other
-// n_lo (partners above s, boundaries last) to its lower segment at lb as
-// pairs of the new set, each with the tangential history the pair has in the
-// current set (zero for a new pair).
+// Carry the tangential history of sphere s's new lower segment (partners
+// t_k, ascending, at lb in the pair arrays) from its lower segment in the set
+// in use: a pair present there keeps its history, a new pair starts at zero.
+// Reads history buffer hb (laid out for the set in use), writes buffer hb ^ 1
+// (laid out for the new set).
 template <class Get>
-__device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32_t ub, int n_up, uint32_t lb, int n_lo,
-                                           Get get) {
-    const int cur = S.ctl->buf, nxt = cur ^ 1;
-    for (int k = 0; k < n_up; k++) {
-        S.ut[ub + k] = get(k);
-        S.us[ub + k] = s;
-    }
-    const uint32_t ob = pick(S.lo_beg, cur)[s], oc = pick(S.lo_cnt, cur)[s];
-    const uint32_t *opt = pick(S.pt, cur) + ob;
-    const double *oh = pick(S.hist, cur) + 3 * (int64_t)ob;
-    uint32_t *npt = pick(S.pt, nxt);
-    double *nh = pick(S.hist, nxt);
+__device__ __forceinline__ void carry_history(const DevScene &S, uint32_t s, uint32_t lb, int n_lo, Get get) {
+    const int cur = S.ctl->buf, hb = S.ctl->hb;
+    const uint32_t ob = slot3(S.lo_beg, cur)[s], oc = slot3(S.lo_cnt, cur)[s];
+    const uint32_t *opt = slot3(S.pt, cur) + ob;
+    const double *oh = pick(S.hist, hb) + 3 * (int64_t)ob;
+    double *nh = pick(S.hist, hb ^ 1);
     uint32_t j = 0;
     for (int k = 0; k < n_lo; k++) {
-        const uint32_t t = get(n_up + k);
+        const uint32_t t = get(k);
         const int64_t p = (int64_t)lb + k;
-        npt[p] = t;
-        S.ps[p] = s;
         while (j < oc && opt[j] < t) j++;
         double h0 = 0.0, h1 = 0.0, h2 = 0.0;
         if (j < oc && opt[j] == t) { h0 = oh[3 * j]; h1 = oh[3 * j + 1]; h2 = oh[3 * j + 2]; }
         nh[3 * p] = h0; nh[3 * p + 1] = h1; nh[3 * p + 2] = h2;
     }
+}
+
+// Write the new segments of sphere s from its ascending candidates get(k):
+// the first n_up (partners below s) to its upper segment at ub, the other
+// n_lo (partners above s, boundaries last) to its lower segment at lb as
+// pairs of the new set, in the detection's output slot.  A detection on the
+// step's stream also carries the history over; the second stream's does not
+// (the steps go on changing the history: it is carried when the set is
+// adopted).
+template <class Get>
+__device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32_t ub, int n_up, uint32_t lb, int n_lo,
+                                           Get get) {
+    const int out = out_slot(S);
+    uint32_t *ut = slot3(S.ut, out), *us = slot3(S.us, out);
+    for (int k = 0; k < n_up; k++) {
+        ut[ub + k] = get(k);
+        us[ub + k] = s;
+    }
+    uint32_t *npt = slot3(S.pt, out), *nps = slot3(S.ps, out);
+    for (int k = 0; k < n_lo; k++) {
+        const int64_t p = (int64_t)lb + k;
+        npt[p] = get(n_up + k);
+        nps[p] = s;
+    }
+    if (!S.bchain) carry_history(S, s, lb, n_lo, [&](int k) { return get(n_up + k); });
 }
 
 // Narrow phase, one thread per sphere id: ids are spatially coherent (clumps
@@ -811,7 +828,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
     const int tid = threadIdx.x;
     const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
-    const int nxt = S.ctl->buf ^ 1;
+    const int out = out_slot(S);
     int cnt = 0, nup = 0, nbp = 0;
     const uint32_t s = (uint32_t)i;
     if (i < S.ns) {
@@ -892,10 +909,10 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     if (i >= S.ns) return;
     if (bu + totu > (unsigned long long)S.cap || bl + totl > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
     const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
-    S.up_beg[s] = ub;
-    S.up_cnt[s] = (uint32_t)nup;
-    pick(S.lo_beg, nxt)[s] = lb;
-    pick(S.lo_cnt, nxt)[s] = (uint32_t)nlo;
+    slot3(S.up_beg, out)[s] = ub;
+    slot3(S.up_cnt, out)[s] = (uint32_t)nup;
+    slot3(S.lo_beg, out)[s] = lb;
+    slot3(S.lo_cnt, out)[s] = (uint32_t)nlo;
     if (cnt > kMaxRow) {
         const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_over, 1u);
         if (k < (uint32_t)S.over_cap) S.over_list[k] = s;
@@ -910,14 +927,14 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
 __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
     const Ctl *c = S.ctl;
     if (!due(c) || c->overflow || c->row_overflow) return;
-    const int nxt = c->buf ^ 1;
+    const int out = out_slot(S);
     const int64_t n = min((int64_t)c->n_over, (int64_t)S.over_cap);
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t s = S.over_list[k];
-        const uint32_t ub = S.up_beg[s], nu = S.up_cnt[s];
-        const uint32_t lb = pick(S.lo_beg, nxt)[s], nl = pick(S.lo_cnt, nxt)[s];
-        uint32_t *urow = S.ut + ub;
-        uint32_t *lrow = pick(S.pt, nxt) + lb;
+        const uint32_t ub = slot3(S.up_beg, out)[s], nu = slot3(S.up_cnt, out)[s];
+        const uint32_t lb = slot3(S.lo_beg, out)[s], nl = slot3(S.lo_cnt, out)[s];
+        uint32_t *urow = slot3(S.ut, out) + ub;
+        uint32_t *lrow = slot3(S.pt, out) + lb;
         uint32_t mu = 0, ml = 0;
         // the predicate is the one that sized the segments: the counts cannot be exceeded
         narrow_candidates(S, s, [&](uint32_t t) {
@@ -939,18 +956,20 @@ __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
 __global__ void __launch_bounds__(256) k_link(DevScene S) {
     Ctl *ctl = S.ctl;
     if (!due(ctl) || ctl->overflow || ctl->row_overflow) return;
-    const int nxt = ctl->buf ^ 1;
-    const uint32_t *pt = pick(S.pt, nxt), *lb = pick(S.lo_beg, nxt), *lc = pick(S.lo_cnt, nxt);
+    const int out = out_slot(S);
+    const uint32_t *pt = slot3(S.pt, out), *lb = slot3(S.lo_beg, out), *lc = slot3(S.lo_cnt, out);
+    const uint32_t *us = slot3(S.us, out), *ut = slot3(S.ut, out);
+    uint32_t *um = slot3(S.um, out);
     const int64_t n = ctl->n_up;
     for (int64_t u = (int64_t)xcd_block() * blockDim.x + threadIdx.x; u < n; u += (int64_t)gridDim.x * blockDim.x) {
-        const uint32_t s = S.us[u], t = S.ut[u];
+        const uint32_t s = us[u], t = ut[u];
         const uint32_t b0 = lb[t], cnt = lc[t];
         uint32_t lo = 0, hi = cnt;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
             if (pt[b0 + mid] < s) lo = mid + 1; else hi = mid;
         }
-        if (lo < cnt && pt[b0 + lo] == s) S.um[u] = b0 + lo;
+        if (lo < cnt && pt[b0 + lo] == s) um[u] = b0 + lo;
         else ctl->asym = 1;  // segments not symmetric: the step is abandoned
     }
 }
@@ -960,8 +979,13 @@ __global__ void k_detect_end(DevScene S) {
     if (!due(c) || c->overflow) return;
     if (c->n_pairs - c->n_bp != c->n_up) c->asym = 1;  // every sphere pair has exactly one upper entry
     if (c->row_overflow || c->asym) { c->overflow = 1; return; }
+    if (S.bchain) {  // the second stream's set waits for its adoption
+        c->det_due = 0;
+        return;
+    }
     if (c->guard && !c->det_due) c->guard_trips++;
-    c->buf ^= 1;
+    c->buf = out_slot(S);
+    c->hb ^= 1;
     c->n_up_cur = c->n_up;
     c->n_pairs_cur = c->n_pairs;
     c->detections++;
@@ -982,7 +1006,7 @@ template <bool FP32>
 __global__ void __launch_bounds__(256) k_count_contacts(DevScene S, unsigned long long *part) {
     using V = typename Contrib<FP32>::V;
     const V *cS = (const V *)S.cS;
-    const uint32_t *pt = pick(S.pt, S.ctl->buf);
+    const uint32_t *pt = slot3(S.pt, S.ctl->buf);
     const int64_t n = S.ctl->n_pairs_cur;
     unsigned long long v = 0;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
@@ -1003,6 +1027,7 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
                                            double *Fs, double *Ts) {
     using V = typename Contrib<FP32>::V;
     const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
+    const uint32_t *um = slot3(S.um, S.ctl->buf);
     // Entries are taken in batches whose loads are all issued before the first
     // is used (the sums stay in ascending partner order).  Six per batch keep
     // the reduction at five waves per SIMD with no spilled register (eight
@@ -1012,7 +1037,7 @@ __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint3
     for (uint32_t k0 = 0; k0 < nu; k0 += kB) {
         int64_t e[kB];
 #pragma unroll
-        for (uint32_t j = 0; j < kB; j++) e[j] = k0 + j < nu ? (int64_t)S.um[ub + k0 + j] : -1;
+        for (uint32_t j = 0; j < kB; j++) e[j] = k0 + j < nu ? (int64_t)um[ub + k0 + j] : -1;
         V a[kB], b[kB];
 #pragma unroll
         for (uint32_t j = 0; j < kB; j++)
@@ -1139,9 +1164,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
     float m = 3.0e38f;
     if (active) {
         info = S.sinfo[s];
-        ub = S.up_beg[s]; nu = S.up_cnt[s];
-        lb = pick(S.lo_beg, cur)[s]; nl = pick(S.lo_cnt, cur)[s];
-        if (fresh) m = S.smargin[s];
+        ub = slot3(S.up_beg, cur)[s]; nu = slot3(S.up_cnt, cur)[s];
+        lb = slot3(S.lo_beg, cur)[s]; nl = slot3(S.lo_cnt, cur)[s];
+        if (fresh) m = slot3(S.smargin, cur)[s];
     }
     if (live) c0 = S.wave_c[w];
     const int cnt = (int)(info >> 8);  // the clump's sphere count
@@ -1233,7 +1258,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
         const int ldr = (int)threadIdx.x - (int)(info & 0xffu);
         const uint32_t tbl = active ? tbs[ldr] : 0xffffffffu;
         if (tbl != 0xffffffffu) {
-            if (!fresh) m = S.smargin[s];
+            if (!fresh) m = slot3(S.smargin, cur)[s];
 #pragma unroll
             for (int i = 0; i < 7; i++) { const double2 v = gs[i][ldr]; g[2 * i] = v.x; g[2 * i + 1] = v.y; }
             const uint32_t ts = tbl + (info & 0xffu);
@@ -1279,7 +1304,8 @@ __global__ void __launch_bounds__(256) k_reduce_big_spheres(DevScene S) {
     const int cur = S.ctl->buf;
     for (int64_t s = s0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < s1; s += (int64_t)gridDim.x * blockDim.x) {
         double Fs[3] = {0.0, 0.0, 0.0}, Ts[3] = {0.0, 0.0, 0.0};
-        sphere_sum<FP32>(S, S.up_beg[s], S.up_cnt[s], pick(S.lo_beg, cur)[s], pick(S.lo_cnt, cur)[s], Fs, Ts);
+        sphere_sum<FP32>(S, slot3(S.up_beg, cur)[s], slot3(S.up_cnt, cur)[s], slot3(S.lo_beg, cur)[s],
+                         slot3(S.lo_cnt, cur)[s], Fs, Ts);
         for (int i = 0; i < 3; i++) { S.sF[3 * s + i] = Fs[i]; S.sT[3 * s + i] = Ts[i]; }
     }
 }
@@ -1355,7 +1381,7 @@ __global__ void __launch_bounds__(256) k_guard_big(DevScene S) {
         if (fresh) { d = S.spos[s]; det[k] = d; }
         else d = det[k];
         const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
-        const double lim = 0.999 * (double)S.smargin[s];
+        const double lim = 0.999 * (double)slot3(S.smargin, S.ctl->buf)[s];
         if (!(dx * dx + dy * dy + dz * dz < lim * lim)) trip = 1;
     }
     if (__syncthreads_or(trip) && threadIdx.x == 0) S.ctl->guard_next = 1;
@@ -1447,8 +1473,8 @@ __global__ void __launch_bounds__(256) k_audit_brute(DevScene S, unsigned long l
     if (a >= S.ns) return;
     const int cur = S.ctl->buf;
     // every exact contact (a, b) with b above a is a pair of a's lower segment
-    uint32_t beg = pick(S.lo_beg, cur)[a], cnt = pick(S.lo_cnt, cur)[a];
-    const uint32_t *nb = pick(S.pt, cur) + beg;
+    uint32_t beg = slot3(S.lo_beg, cur)[a], cnt = slot3(S.lo_cnt, cur)[a];
+    const uint32_t *nb = slot3(S.pt, cur) + beg;
     double4 P = S.spos[a];
     uint32_t own = S.owner[a], sc = S.sscene[a];
     unsigned long long found = 0, missed = 0;
@@ -1500,9 +1526,9 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         uint32_t s = (uint32_t)i;
         double4 P = S.spos[s];
         uint32_t own = S.owner[s];
-        const uint32_t lb = pick(S.lo_beg, cur)[s], lc = pick(S.lo_cnt, cur)[s];
-        const uint32_t *lrow = pick(S.pt, cur) + lb, *urow = S.ut + S.up_beg[s];
-        const uint32_t uc = S.up_cnt[s];
+        const uint32_t lb = slot3(S.lo_beg, cur)[s], lc = slot3(S.lo_cnt, cur)[s];
+        const uint32_t *lrow = slot3(S.pt, cur) + lb, *urow = slot3(S.ut, cur) + slot3(S.up_beg, cur)[s];
+        const uint32_t uc = slot3(S.up_cnt, cur)[s];
         auto in_row = [&](uint32_t t) {  // t in s's upper (t < s) or lower segment
             const uint32_t *nb = t < s ? urow : lrow;
             const uint32_t cnt = t < s ? uc : lc;
@@ -1622,7 +1648,7 @@ __global__ void __launch_bounds__(256) k_bnd_partial(DevScene S, double *partial
     __shared__ double red[6][256];
     const uint32_t tgt = (uint32_t)S.ns + blockIdx.x;
     const int cur = S.ctl->buf;
-    const uint32_t *rb = pick(S.lo_beg, cur), *rc = pick(S.lo_cnt, cur), *nb = pick(S.pt, cur);
+    const uint32_t *rb = slot3(S.lo_beg, cur), *rc = slot3(S.lo_cnt, cur), *nb = slot3(S.pt, cur);
     const int64_t per_part = (S.ns + kBndParts - 1) / kBndParts;
     const int64_t p0 = (int64_t)blockIdx.y * per_part, p1 = min(S.ns, p0 + per_part);
     const int64_t per_lane = (per_part + 255) / 256;

@@ -311,8 +311,8 @@ template <bool FP32, class Law>
 __device__ __forceinline__ void pairs_body(const DevScene &S) {
     if (aborted(S.ctl)) return;
     const int cur = S.ctl->buf;
-    const uint32_t *pt = pick(S.pt, cur);
-    double *hist = pick(S.hist, cur);
+    const uint32_t *pt = slot3(S.pt, cur), *ps = slot3(S.ps, cur);
+    double *hist = pick(S.hist, S.ctl->hb);
     const int64_t n = S.ctl->n_pairs_cur;
     const bool rec = S.ctl->record != 0;
     const double tnow = (double)S.ctl->step * S.h;
@@ -322,13 +322,13 @@ __device__ __forceinline__ void pairs_body(const DevScene &S) {
     // the clumps of the next pair and the ids of the one after are in flight.
     PairIds now{};
     uint32_t s2 = 0, t2 = 0;
-    if (e < n) now = pair_ids(S, S.ps[e], pt[e]);
-    if (e + stride < n) { s2 = S.ps[e + stride]; t2 = pt[e + stride]; }
+    if (e < n) now = pair_ids(S, ps[e], pt[e]);
+    if (e + stride < n) { s2 = ps[e + stride]; t2 = pt[e + stride]; }
     uint32_t sides = 0;  // contact sides this lane created
     for (; e < n; e += stride) {
         PairIds nxt{};
         if (e + stride < n) nxt = pair_ids(S, s2, t2);
-        if (e + 2 * stride < n) { s2 = S.ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
+        if (e + 2 * stride < n) { s2 = ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
         sides += eval_pair<FP32, Law>(S, e, now, hist, tnow, rec);
         now = nxt;
     }
