@@ -141,7 +141,8 @@ def _steps_reporting_misses(sc, n, label):
         log(f"[{label}] audit reported missed contacts: {e}")
 
 
-def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=None, precision="fp32"):
+def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=None, precision="fp32",
+             overlap=False):
     """Time `steps` steps of one path after warmup and the autotuner.
 
     Inside the timed region only the roofline kernel is bracketed by events
@@ -161,6 +162,8 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
     # ordinary steps, each of one detection and the steps up to the next at
     # the interval bound), then steps to settle before timing
     tune = sc.autotune(detect["k_max"] if mode != "plain" else 5)
+    if overlap:  # the next active set built on a second stream while the steps go on
+        sc.set_detection(mode, **dict(detect, overlap=True))
     if graph:
         sc.set_graph(graph)
     sc.step(warmup)
@@ -356,10 +359,12 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--clumps", type=int, default=11_000_000)
-    ap.add_argument("--modes", default="plain,fixed,learned,learned_graph,batched,precision",
-                    help="paths to time: plain, fixed, learned (rover bed), learned_graph (the learned path "
-                         "replayed from captured graphs), batched (256 funnel scenes, learned, graphs), precision "
-                         "(the 4M-clump drum, learned, all-FP64 vs FP32 force arithmetic)")
+    ap.add_argument("--modes", default="plain,fixed,learned,learned_overlap,learned_graph,batched,precision",
+                    help="paths to time: plain, fixed, learned (rover bed), learned_overlap (the learned path "
+                         "with the next active set built on a second stream while the steps go on), "
+                         "learned_graph (the learned path replayed from captured graphs), batched (256 funnel "
+                         "scenes, learned, graphs), precision (the 4M-clump drum, learned, all-FP64 vs FP32 "
+                         "force arithmetic)")
     ap.add_argument("--mlp", default=None, help="npz with envelope-MLP parameters (default: the package's "
                                                 "trained weights, else train now)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -409,7 +414,7 @@ def main():
     from paper_2307_03445_amd import prep
     torch.cuda.set_device(0)
     modes = args.modes.split(",")
-    rover_modes = [m for m in modes if m in ("plain", "fixed", "learned", "learned_graph")]
+    rover_modes = [m for m in modes if m in ("plain", "fixed", "learned", "learned_overlap", "learned_graph")]
     mlp, mlp_info = None, None
     if any(m in modes for m in ("learned", "learned_graph", "batched", "precision")):
         from paper_2307_03445_amd import train
@@ -440,9 +445,10 @@ def main():
         log(f"workload: {desc.n_clumps} clumps, {desc.n_spheres} spheres, built in {time.perf_counter() - t0:.1f} s")
         log(f"envelope MLP: {mlp_info}")
         for mode in rover_modes:
-            base = "learned" if mode == "learned_graph" else mode
+            base = "learned" if mode.startswith("learned") else mode
             results[mode] = run_path(desc, base, args.steps, args.warmup, mlp=mlp,
-                                     graph=args.steps if mode == "learned_graph" else 0, label=mode)
+                                     graph=args.steps if mode == "learned_graph" else 0, label=mode,
+                                     overlap=mode == "learned_overlap")
     batched = None
     if "batched" in modes:
         t0 = time.perf_counter()

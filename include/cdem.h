@@ -125,7 +125,14 @@ typedef struct cdem_detect_params {
     double v_max_user;     /* a-priori bound on sphere speed [m/s], 0 = use measured speeds */
     double margin_cap;     /* largest margin any sphere may get [m]; sets the bin size */
     int32_t audit_period;  /* steps between brute-force audits, 0 = never */
-    int32_t reserved;
+    int32_t overlap;       /* 1: detection overlapped with the dynamics (deferred modes only).  The
+                              next active set is built on a second stream of the same device from a
+                              snapshot of the state taken every k_max steps, while the steps go on
+                              (Sec. 2.2: the active set is updated in the shadow of the dynamics),
+                              and taken into use k_max steps later; its margins cover 2 k_max
+                              steps.  A sphere that outruns them still trips the displacement
+                              guard, which re-detects on the step's stream at once.  Results are
+                              the same as with detection every step. */
 } cdem_detect_params;
 
 /* Counters of the scene (host copy of its device control block). */

@@ -47,7 +47,7 @@ class AllocatorC(C.Structure):
 
 class DetectParamsC(C.Structure):
     _fields_ = [("mode", C.c_int32), ("k_max", C.c_int32), ("safety", C.c_double), ("v_max_user", C.c_double),
-                ("margin_cap", C.c_double), ("audit_period", C.c_int32), ("reserved", C.c_int32)]
+                ("margin_cap", C.c_double), ("audit_period", C.c_int32), ("overlap", C.c_int32)]
 
 
 class CountsC(C.Structure):
@@ -241,9 +241,11 @@ class Scene:
     def sync(self):
         self._check(self._L.cdem_sync(self._h))
 
-    def set_detection(self, mode="plain", k_max=1, safety=1.5, v_max_user=0.0, margin_cap=0.0, audit_period=0):
+    def set_detection(self, mode="plain", k_max=1, safety=1.5, v_max_user=0.0, margin_cap=0.0, audit_period=0,
+                      overlap=False):
         m = {"plain": DETECT_PLAIN, "fixed": DETECT_FIXED, "learned": DETECT_LEARNED}[mode]
-        p = DetectParamsC(m, int(k_max), float(safety), float(v_max_user), float(margin_cap), int(audit_period), 0)
+        p = DetectParamsC(m, int(k_max), float(safety), float(v_max_user), float(margin_cap), int(audit_period),
+                          1 if overlap else 0)
         self._check(self._L.cdem_set_detection(self._h, C.byref(p)))
 
     def record_next_step(self, on: bool = True):

@@ -115,6 +115,24 @@ struct cdem_scene {
     hipModule_t law_module = nullptr;
     hipFunction_t law_pairs = nullptr;
     int nslots = 2;                    // active-set slots with pair storage (3 in overlap mode)
+    // detection ahead on a second stream (overlap mode)
+    struct Ahead {
+        bool on = false;
+        int32_t K = 0;                 // interval: a snapshot every K steps, adopted K steps later
+        int64_t origin = 0;            // step the intervals are counted from
+        bool inflight = false;         // a set is being built (or built and not yet adopted)
+        hipStream_t stream = nullptr;
+        hipEvent_t ev_snap = nullptr, ev_det = nullptr;
+        Ctl *ctl = nullptr;
+        double4 *cst = nullptr, *spos = nullptr, *sorted_pos = nullptr;
+        float *cacc = nullptr, *sorted_margin = nullptr, *bin_margin = nullptr;
+        float4 *sorted_f4 = nullptr;
+        uint32_t *cell_of = nullptr, *cell_rank = nullptr, *sorted_id = nullptr, *sorted_owner = nullptr;
+        uint32_t *over_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
+        uint32_t *bin_v = nullptr, *bin_a = nullptr, *reg_occ = nullptr;
+        double *part_k = nullptr;
+        int64_t n_cells_alloc = 0, n_regions_alloc = 0;
+    } ahead;
 };
 
 // FNV-1a over raw bytes: identifies the static description a checkpoint belongs to.
@@ -388,8 +406,96 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
     return CDEM_OK;
 }
 
+// ---------------------------------------------------------------- detection ahead
+// Wait for the second stream; with discard, a set in flight is dropped (it
+// is rebuilt at the next interval; results do not depend on when a detection
+// runs).  Called before anything that reallocates, regrids or rewrites the
+// state the second stream reads.
+static int ahead_drain(cdem_scene *sc, bool discard) {
+    auto &a = sc->ahead;
+    if (a.stream) HIPCHK(hipStreamSynchronize(a.stream));
+    if (discard) a.inflight = false;
+    return CDEM_OK;
+}
+
+// The second stream's buffers: a snapshot of the clump records and
+// acceleration envelopes, its own sphere positions, bins, sorted records,
+// envelope regions, overflow list and control block.
+static int ahead_alloc(cdem_scene *sc) {
+    auto &a = sc->ahead;
+    DevScene &S = sc->S;
+    const int64_t ns = std::max<int64_t>(S.ns, 1), nc = std::max<int64_t>(S.nc, 1);
+    if (!a.stream) {
+        HIPCHK(hipStreamCreateWithFlags(&a.stream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&a.ev_snap, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&a.ev_det, hipEventDisableTiming));
+        a.ctl = (Ctl *)dev_alloc(sc, sizeof(Ctl));
+        a.cst = (double4 *)dev_alloc(sc, 4 * sizeof(double4) * nc);
+        a.cacc = (float *)dev_alloc(sc, 4 * nc);
+        a.spos = (double4 *)dev_alloc(sc, sizeof(double4) * ns);
+        a.cell_of = (uint32_t *)dev_alloc(sc, 4 * ns);
+        a.cell_rank = (uint32_t *)dev_alloc(sc, 4 * ns);
+        a.sorted_id = (uint32_t *)dev_alloc(sc, 4 * ns);
+        a.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * ns);
+        a.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * ns);
+        a.sorted_margin = (float *)dev_alloc(sc, 4 * ns);
+        a.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * ns);
+        a.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
+        a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
+        if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_id || !a.sorted_owner ||
+            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.over_list || !a.part_k)
+            return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
+        Ctl z;
+        memset(&z, 0, sizeof z);
+        HIPCHK(hipMemcpyAsync(a.ctl, &z, sizeof z, hipMemcpyHostToDevice, sc->stream));
+        HIPCHK(hipStreamSynchronize(sc->stream));
+    }
+    if (S.n_cells > a.n_cells_alloc) {
+        dev_free(sc, a.cell_count); dev_free(sc, a.cell_start); dev_free(sc, a.scan_bsum);
+        const int64_t nblk = (S.n_cells + 1023) / 1024 + 1;
+        a.cell_count = (uint32_t *)dev_alloc(sc, S.n_cells * 4);
+        a.cell_start = (uint32_t *)dev_alloc(sc, (S.n_cells + 1) * 4);
+        a.scan_bsum = (uint32_t *)dev_alloc(sc, nblk * 4);
+        if (!a.cell_count || !a.cell_start || !a.scan_bsum) return fail(sc, CDEM_E_OOM, "bins of the detection ahead");
+        a.n_cells_alloc = S.n_cells;
+    }
+    if (S.n_regions > a.n_regions_alloc) {
+        dev_free(sc, a.bin_v); dev_free(sc, a.bin_a); dev_free(sc, a.reg_occ); dev_free(sc, a.bin_margin);
+        const int64_t nr = std::max<int64_t>(S.n_regions, 1);
+        a.bin_v = (uint32_t *)dev_alloc(sc, nr * 4);
+        a.bin_a = (uint32_t *)dev_alloc(sc, nr * 4);
+        a.reg_occ = (uint32_t *)dev_alloc(sc, nr * 4);
+        a.bin_margin = (float *)dev_alloc(sc, nr * 4);
+        if (!a.bin_v || !a.bin_a || !a.reg_occ || !a.bin_margin)
+            return fail(sc, CDEM_E_OOM, "regions of the detection ahead");
+        a.n_regions_alloc = S.n_regions;
+    }
+    return CDEM_OK;
+}
+
+// The second stream's view of the scene: its own snapshot, positions, bins,
+// regions and control block (whose bslot names the structure slot it writes).
+static DevScene ahead_view(const cdem_scene *sc) {
+    const auto &a = sc->ahead;
+    DevScene B = sc->S;
+    B.bchain = 1;
+    B.horizon = 2 * a.K;
+    B.ctl = a.ctl;
+    B.cst = a.cst; B.cacc = a.cacc; B.spos = a.spos;
+    B.cell_of = a.cell_of; B.cell_rank = a.cell_rank; B.cell_count = a.cell_count; B.cell_start = a.cell_start;
+    B.scan_bsum = a.scan_bsum;
+    B.sorted_id = a.sorted_id; B.sorted_owner = a.sorted_owner; B.sorted_pos = a.sorted_pos;
+    B.sorted_margin = a.sorted_margin; B.sorted_f4 = a.sorted_f4;
+    B.bin_v = a.bin_v; B.bin_a = a.bin_a; B.reg_occ = a.reg_occ; B.bin_margin = a.bin_margin;
+    B.part_k = a.part_k; B.over_list = a.over_list;
+    B.store_speed = 0; B.store_acc = 0;
+    B.plan.audit_period = 0;
+    return B;
+}
+
 static void set_bnd_margins(cdem_scene *sc) {
     int kmax = sc->det.mode == CDEM_DETECT_PLAIN ? 0 : std::max(1, sc->det.k_max);
+    if (sc->ahead.on) kmax *= 2;  // a set built ahead is used up to 2 k_max steps after its snapshot
     for (auto &b : sc->bnd) {
         double sp = std::sqrt(b.vel[0] * b.vel[0] + b.vel[1] * b.vel[1] + b.vel[2] * b.vel[2]);
         b.margin = sp * (double)kmax * sc->S.h * 1.01;
@@ -675,7 +781,6 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         if (!S.lo_beg[k] || !S.lo_cnt[k] || !S.up_beg[k] || !S.up_cnt[k] || !S.smargin[k])
             return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     }
-    S.bslot = 2;  // no detection ahead on a second stream: slots 0 and 1 alternate
     if (!S.cdet || !S.spos || !S.cell_of || !S.cell_rank || !S.sorted_id || !S.sorted_owner ||
         !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
@@ -697,6 +802,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     memset(&c, 0, sizeof c);
     c.det_due = 1;
     c.k_cur = 1;
+    c.bslot = 2;  // no detection ahead yet: slots 0 and 1 alternate
     if (hipMemcpyAsync(S.ctl, &c, sizeof c, hipMemcpyHostToDevice, sc->stream) != hipSuccess) return bail(fail(sc, CDEM_E_HIP, "ctl"));
     for (int k = 0; k < 3; k++) {
         if (launch_zero(S.lo_beg[k], 4 * (size_t)ns, sc->stream) != hipSuccess ||
@@ -726,6 +832,13 @@ extern "C" int cdem_destroy(cdem_scene *sc) {
     delete sc->timer;
     sc->timer = nullptr;
     if (sc->law_module) (void)hipModuleUnload(sc->law_module);
+    if (sc->ahead.stream) {
+        (void)hipStreamSynchronize(sc->ahead.stream);
+        (void)hipStreamDestroy(sc->ahead.stream);
+        (void)hipEventDestroy(sc->ahead.ev_snap);
+        (void)hipEventDestroy(sc->ahead.ev_det);
+        sc->ahead.stream = nullptr;
+    }
     auto owned = sc->owned;
     for (void *p : owned) dev_free(sc, p);
     (void)hipStreamSynchronize(sc->stream);  // stream-ordered frees complete before the scene is gone
@@ -747,12 +860,31 @@ static int write_ctl(cdem_scene *sc, const Ctl &c) {
 
 // Enqueue the kernels of n steps on st (timed when a timer is set and we are
 // not capturing a graph).
-static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing) {
+static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing, int64_t step0 = 0) {
     const DevScene &S = sc->S;
+    auto &a = sc->ahead;
 
     g_timer = capturing ? nullptr : sc->timer;
     for (int64_t i = 0; i < n; i++) {
-        hipError_t e = launch_pose(S, st, false);
+        hipError_t e = hipSuccess;
+        if (a.on && (step0 + i - a.origin) % a.K == 0) {
+            // adopt the set built ahead during the last interval, then take
+            // the snapshot the next one is built from
+            if (a.inflight) {
+                if (hipStreamWaitEvent(st, a.ev_det, 0) != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, "wait"); }
+                e = launch_adopt(S, ahead_view(sc), st);
+                a.inflight = false;
+            }
+            const DevScene B = ahead_view(sc);
+            if (e == hipSuccess) e = launch_snapshot(S, B, st);
+            if (e == hipSuccess) e = hipEventRecord(a.ev_snap, st);
+            if (e == hipSuccess) e = hipStreamWaitEvent(a.stream, a.ev_snap, 0);
+            if (e == hipSuccess) e = launch_detect_ahead(B, a.stream);
+            if (e == hipSuccess) e = hipEventRecord(a.ev_det, a.stream);
+            if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
+            a.inflight = true;
+        }
+        e = launch_pose(S, st, false);
         if (e == hipSuccess && sc->collecting) e = launch_collect_speed(S, st);
         if (e == hipSuccess) e = launch_detect(S, st);
         if (e == hipSuccess) e = launch_audit_binned(S, st);
@@ -762,6 +894,7 @@ static int enqueue_on(cdem_scene *sc, int64_t n, hipStream_t st, bool capturing)
         if (e != hipSuccess) { g_timer = nullptr; return fail(sc, CDEM_E_HIP, hipGetErrorString(e)); }
         if (!capturing && sc->timer && sc->timer->used > 4096) {  // bound the event pool
             HIPCHK(hipStreamSynchronize(st));
+            if (a.stream) HIPCHK(hipStreamSynchronize(a.stream));
             sc->timer->harvest();
         }
     }
@@ -792,10 +925,11 @@ static int ensure_graph(cdem_scene *sc) {
     return CDEM_OK;
 }
 
-static int enqueue_steps(cdem_scene *sc, int64_t n) {
-    // graphs carry no per-kernel events: a timed or collecting run goes eager
-    if (sc->graph_steps <= 0 || sc->timer || sc->collecting || n < sc->graph_steps)
-        return enqueue_on(sc, n, sc->stream, false);
+static int enqueue_steps(cdem_scene *sc, int64_t n, int64_t step0) {
+    // graphs carry no per-kernel events: a timed or collecting run goes eager;
+    // so does the overlap mode (the host schedules its second stream)
+    if (sc->ahead.on || sc->graph_steps <= 0 || sc->timer || sc->collecting || n < sc->graph_steps)
+        return enqueue_on(sc, n, sc->stream, false, step0);
     int rc = ensure_graph(sc);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(sc->stream));
@@ -816,15 +950,35 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
     for (int attempt = 0; attempt < 8; attempt++) {
         int64_t left = target - c.step;
         if (left <= 0) break;
-        if ((rc = enqueue_steps(sc, left)) != CDEM_OK) return rc;
+        if ((rc = enqueue_steps(sc, left, c.step)) != CDEM_OK) return rc;
         if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
-        if (sc->timer) sc->timer->harvest();
+        if (sc->timer) {
+            if ((rc = ahead_drain(sc, false)) != CDEM_OK) return rc;
+            sc->timer->harvest();
+        }
         if (c.nonfinite) return fail(sc, CDEM_E_NAN, "non-finite clump state");
+        if (c.ahead_dropped) {
+            // a set built ahead outgrew the storage: grow it (the steps ran on
+            // the set in use, which the guard kept valid)
+            if ((rc = ahead_drain(sc, true)) != CDEM_OK) return rc;
+            Ctl b;
+            HIPCHK(hipMemcpy(&b, sc->ahead.ctl, sizeof b, hipMemcpyDeviceToHost));
+            if (b.row_overflow)
+                return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 16 candidate partners (margin too large)");
+            int64_t need = (int64_t)(1.3 * (double)std::max(b.n_up, b.n_pairs)) + 1024;
+            int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
+            if (cap > kMaxCap && std::max(b.n_up, b.n_pairs) < kMaxCap) cap = kMaxCap;
+            if ((rc = alloc_active_set(sc, cap, true)) != CDEM_OK) return rc;
+            sc->regrows++;
+            c.ahead_dropped = 0;
+            if ((rc = write_ctl(sc, c)) != CDEM_OK) return rc;
+        }
         if (!c.overflow) break;
         if (c.row_overflow)
             return fail(sc, CDEM_E_CAPACITY, "too many spheres with more than 16 candidate partners (margin too large)");
         if (c.asym) return fail(sc, CDEM_E_STATE, "active-set rows are not symmetric");
         // grow the active set and resume from the step that did not complete
+        if ((rc = ahead_drain(sc, true)) != CDEM_OK) return rc;
         int64_t need = (int64_t)(1.3 * (double)std::max(c.n_up, c.n_pairs)) + 1024;
         int64_t cap = std::max<int64_t>(2 * sc->S.cap, need);
         if (cap > kMaxCap && std::max(c.n_up, c.n_pairs) < kMaxCap) cap = kMaxCap;
@@ -858,9 +1012,26 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
         return fail(sc, CDEM_E_INVALID, "deferred detection needs a positive margin cap");
     if (p->mode == CDEM_DETECT_LEARNED && !sc->S.mlp)
         return fail(sc, CDEM_E_STATE, "learned detection needs MLP parameters (cdem_set_mlp)");
-    Ctl c;
-    int rc = read_ctl(sc, c);
+    if (p->overlap != 0 && p->overlap != 1) return fail(sc, CDEM_E_INVALID, "overlap is 0 or 1");
+    if (p->overlap && p->mode == CDEM_DETECT_PLAIN)
+        return fail(sc, CDEM_E_INVALID, "overlap needs deferred detection (a margin covers the steps ahead)");
+    int rc = ahead_drain(sc, true);
     if (rc) return rc;
+    Ctl c;
+    if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
+    if (p->overlap && sc->nslots < 3) {  // the third slot's pair storage
+        sc->nslots = 3;
+        if ((rc = alloc_active_set(sc, sc->S.cap, true)) != CDEM_OK) return rc;
+    }
+    auto &a = sc->ahead;
+    a.on = p->overlap != 0;
+    a.K = std::max(1, p->k_max);
+    a.origin = c.step;
+    // the slot reserved for the second stream: never the set in use (a
+    // detection on the step's stream takes the third; with two slots of pair
+    // storage, slots 0 and 1 alternate)
+    c.bslot = sc->nslots == 3 ? (c.buf + 2) % 3 : 2;
+    sc->S.overlap = a.on ? 1 : 0;
     sc->det = *p;
     sc->S.detect_mode = p->mode;
     sc->S.plan.k_max = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
@@ -876,6 +1047,7 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
     set_bnd_margins(sc);
     HIPCHK(hipMemcpyAsync((void *)sc->S.bnd, sc->bnd.data(), sc->bnd.size() * sizeof(Bnd), hipMemcpyHostToDevice, sc->stream));
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
+    if (a.on && (rc = ahead_alloc(sc)) != CDEM_OK) return rc;
     c.det_due = 1;
     c.k_cur = p->mode == CDEM_DETECT_PLAIN ? 1 : p->k_max;
     return write_ctl(sc, c);
@@ -978,6 +1150,7 @@ extern "C" int cdem_write_state(cdem_scene *sc, const cdem_state_view *v, int wh
     int64_t nc = S.nc;
     if (stream) sc->stream = (hipStream_t)stream;
     HIPCHK(hipStreamSynchronize(sc->stream));
+    if (int rc0 = ahead_drain(sc, true)) return rc0;  // a set built from the old state is dropped
     if (where == CDEM_DEVICE) {
         HIPCHK(launch_pack_state(S, v->x, v->q, v->v, v->w, 1, sc->stream));
     } else {
@@ -1228,6 +1401,7 @@ extern "C" int cdem_collect_envelopes(cdem_scene *sc, int32_t horizon, float *fe
                                       int64_t *n) {
     if (!sc || !n || horizon < 1 || cap < 0 || (cap > 0 && (!features || !labels)))
         return fail(sc, CDEM_E_INVALID, "bad arguments");
+    if (int rc0 = ahead_drain(sc, false)) return rc0;
     DevScene &S = sc->S;
     int32_t ss = S.store_speed, sa = S.store_acc;
     S.store_speed = 1;
@@ -1299,7 +1473,9 @@ extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, 
     HIPCHK(hipEventCreate(&e1));
     for (double f : factors) {
         sc->bin_factor = f;
+        if ((rc = ahead_drain(sc, true)) != CDEM_OK) break;  // the second stream reads the grids
         if ((rc = build_grids(sc)) != CDEM_OK) break;
+        if (sc->ahead.on && (rc = ahead_alloc(sc)) != CDEM_OK) break;
         for (int32_t cap : caps) {
             sc->S.stride_cap = cap;
             Ctl c;
@@ -1321,7 +1497,9 @@ extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, 
     if (rc) return rc;
     sc->bin_factor = bf;
     sc->S.stride_cap = bc;
+    if ((rc = ahead_drain(sc, true)) != CDEM_OK) return rc;
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
+    if (sc->ahead.on && (rc = ahead_alloc(sc)) != CDEM_OK) return rc;
     Ctl c;
     if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
     c.det_due = 1;
@@ -1402,6 +1580,7 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
 
 extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     if (!sc || !buf || len < sizeof(SaveHeader)) return fail(sc, CDEM_E_INVALID, "bad arguments");
+    if (int rc0 = ahead_drain(sc, true)) return rc0;
     SaveHeader hd;
     memcpy(&hd, buf, sizeof hd);
     DevScene &S = sc->S;
@@ -1448,6 +1627,8 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     Ctl n = hd.ctl;
     n.buf = cur;
     n.hb = c.hb;
+    n.bslot = c.bslot;
+    n.ahead_dropped = 0;
     n.n_pairs_cur = E;
     n.det_due = 1;
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;

@@ -49,7 +49,7 @@ struct Ctl {
     int64_t n_up;            // upper-segment entries written by the detection in progress
     int64_t n_up_cur;        // upper-segment entries of the active set in use
     int64_t detections, guard_trips, fallbacks, audits, missed;
-    int32_t buf;             // which of the two active-set buffers is current
+    int32_t buf;             // which of the three active-set structure slots is in use
     int32_t det_due;         // a detection runs at the start of this step
     int32_t since_det;       // steps completed since the last detection
     int32_t k_cur;           // current detection interval
@@ -77,6 +77,11 @@ struct Ctl {
     int64_t contact_sides_last;  // contact sides of the last completed step (2 per sphere pair, 1 per boundary)
     double c_cal;                // measured / modelled false-positive pairs at the last detection (0: none yet)
     double dpred_last;           // modelled false-positive pairs per sphere of the set in use (0: none)
+    int32_t ahead_dropped;       // a set built ahead overflowed its storage and was not adopted
+    int32_t stale;               // (second stream) its set was outrun before its adoption: not adopted
+    int32_t bslot;               // the structure slot reserved for the second stream's set (never buf);
+                                 // in the second stream's block: the slot its detection writes
+    int32_t pad5;
 };
 
 // Detection plan parameters (fixed rule), set by cdem_set_detection.
@@ -137,9 +142,9 @@ struct DevScene {
     // sphere lists the pair in its "upper segment" (partners below its id,
     // ascending) through a link to the pair.  The structure comes in three
     // slots: the set in use (ctl->buf), the one a detection on the step's
-    // stream builds (the third slot besides the one in use and bslot), and
-    // bslot, which a detection running ahead on a second stream builds while
-    // the steps go on (overlap mode; bslot = 2 and unused otherwise).  The
+    // stream builds (the third slot besides the one in use and ctl->bslot),
+    // and ctl->bslot, which a detection running ahead on a second stream
+    // builds while the steps go on (overlap mode; unused otherwise).  The
     // tangential history comes in two buffers (ctl->hb holds the set in
     // use's): a detection carries it from the set in use into the other
     // buffer, laid out for the new set.
@@ -201,7 +206,6 @@ struct DevScene {
     // detection overlapped with the dynamics (a second stream builds the next
     // active set from a snapshot of the state while the steps go on)
     int32_t overlap;                 // on: detections are scheduled by the host (the device re-detects on a guard trip)
-    int32_t bslot;                   // the structure slot the second stream's detection writes
     int32_t bchain;                  // this launch belongs to the second stream's detection
     int32_t horizon;                 // steps the margins of a second-stream detection cover
     int32_t pad3;
@@ -246,6 +250,12 @@ extern KernelTimer *g_timer;
 // detection, an audit, training-data capture); readouts pass force = true.
 hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force);
 hipError_t launch_detect(const DevScene &S, hipStream_t st);
+// Detection ahead (overlap mode): snapshot on the step's stream (S), the
+// detection chain on the second stream (B: the second stream's view), and
+// the adoption of its set on the step's stream.
+hipError_t launch_snapshot(const DevScene &S, const DevScene &B, hipStream_t st);
+hipError_t launch_detect_ahead(const DevScene &B, hipStream_t st);
+hipError_t launch_adopt(const DevScene &S, const DevScene &B, hipStream_t st);
 // user_pairs: the pair kernel of a user force law compiled at run time (its
 // DevScene argument by value, 256 lanes per workgroup), or null for the
 // built-in law.

@@ -417,6 +417,17 @@ __global__ void k_plan(DevScene S) {
     }
     float v = fmaxf(__uint_as_float(c->vmax_bits), S.plan.v_user);
     float a = __uint_as_float(c->amax_last);
+    if (S.bchain) {
+        // a set built ahead, from a snapshot, must cover the steps until its
+        // adoption and its interval of use: the fixed horizon, capped (a
+        // sphere that outruns the cap trips the guard)
+        const double T = (double)S.horizon * S.h;
+        double m = (double)S.plan.safety * (T * (double)v) + 0.5 * (double)a * T * T;
+        m = fmax(fmin(m, (double)S.plan.margin_cap), (double)S.plan.margin_floor);
+        c->margin_cur = (float)m;
+        c->k_cur = S.plan.k_max;
+        return;
+    }
     int k = S.plan.k_max;
     double m = 0.0;
     for (; k >= 1; k--) {
@@ -567,7 +578,7 @@ __global__ void __launch_bounds__(256) k_bin_margin(DevScene S) {
 // workgroup sums of the margin model are added in a fixed order.
 __global__ void __launch_bounds__(256) k_pick_interval(DevScene S, unsigned nblk) {
     Ctl *c = S.ctl;
-    if (!due(c) || aborted(c) || S.detect_mode != 2) return;
+    if (!due(c) || aborted(c) || S.detect_mode != 2 || S.overlap) return;  // overlapped: the host's interval
     __shared__ double sv[256], sa[256];
     double v = 0.0, a = 0.0;
     for (unsigned b = threadIdx.x; b < nblk; b += blockDim.x) {
@@ -611,7 +622,7 @@ __global__ void __launch_bounds__(256) k_pick_interval(DevScene S, unsigned nblk
 __global__ void __launch_bounds__(256) k_region_margin(DevScene S) {
     const Ctl *c = S.ctl;
     if (!due(c) || aborted(c) || S.detect_mode != 2) return;
-    const double T = (double)c->k_cur * S.h;
+    const double T = (double)(S.bchain ? S.horizon : c->k_cur) * S.h;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
          r += (int64_t)gridDim.x * blockDim.x) {
         if (!S.reg_occ[r]) continue;
@@ -1463,7 +1474,7 @@ __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     c->guard_next = 0;
     c->step++;
     c->since_det++;
-    c->det_due = (S.detect_mode == 0 || c->since_det >= c->k_cur) ? 1 : 0;
+    c->det_due = (S.detect_mode == 0 || (!S.overlap && c->since_det >= c->k_cur)) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- audit
@@ -1630,6 +1641,123 @@ __global__ void __launch_bounds__(1024) k_audit_end(DevScene S) {
     }
 }
 
+// ---------------------------------------------------------------- detection ahead (overlap)
+// The next active set is built on a second stream from a snapshot of the
+// state while the steps go on (the detection of Sec. 2.2 runs in the shadow
+// of the dynamics), then adopted at the start of a later step.
+
+// Snapshot for a detection ahead: the clump records and acceleration
+// envelopes of the state at the start of this step, and the second stream's
+// control block reset for one detection at this step's time.  B is the
+// second stream's view (its records, envelopes and control block).
+__global__ void __launch_bounds__(256) k_snap(DevScene S, DevScene B) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = i; k < 4 * S.nc; k += stride) B.cst[k] = S.cst[k];
+    for (int64_t k = i; k < S.nc; k += stride) B.cacc[k] = S.cacc[k];
+    if (i == 0) {
+        Ctl *b = B.ctl;
+        const Ctl *a = S.ctl;
+        b->step = a->step;
+        b->amax_last = a->amax_last;
+        b->vmax_bits = 0;
+        b->det_due = 1; b->guard = 0;
+        b->overflow = 0; b->row_overflow = 0; b->asym = 0; b->n_over = 0;
+        b->n_up = 0; b->n_pairs = 0; b->n_bp = 0;
+        b->k_cur = S.plan.k_max;
+        b->fallbacks = 0;
+        b->collecting = 0; b->record = 0;
+        b->stale = 0;
+        // the second stream's slot: any but the one in use (the step's
+        // stream avoids it from now on)
+        b->bslot = (a->buf + 1) % 3;
+        S.ctl->bslot = b->bslot;
+    }
+}
+
+// A set built ahead is usable unless its storage overflowed or a sphere
+// outran its margin before the adoption.
+__device__ __forceinline__ bool ahead_built(const Ctl *b) {
+    return b->det_due == 0 && !b->overflow && !b->row_overflow && !b->asym;
+}
+__device__ __forceinline__ bool ahead_ok(const Ctl *b) { return ahead_built(b) && !b->stale; }
+
+// Adoption, per sphere: the set built ahead (slot bctl->bslot) takes the
+// tangential history of the pairs it shares with the set in use.
+__global__ void __launch_bounds__(256) k_adopt_rows(DevScene S, const Ctl *bctl) {
+    if (!ahead_ok(bctl) || aborted(S.ctl)) return;
+    const int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    if (i >= S.ns) return;
+    const uint32_t s = (uint32_t)i;
+    const int bs = bctl->bslot;
+    const uint32_t lb = slot3(S.lo_beg, bs)[s];
+    const int nl = (int)slot3(S.lo_cnt, bs)[s];
+    const uint32_t *npt = slot3(S.pt, bs) + lb;
+    carry_history(S, s, lb, nl, [&](int k) { return npt[k]; });
+}
+
+// Adoption, per clump: the displacement guard's reference becomes the
+// snapshot's pose and the smallest margin the clump's spheres took (big
+// clumps: the snapshot's sphere centres).  B is the second stream's view.
+__global__ void __launch_bounds__(256) k_adopt_clumps(DevScene S, DevScene B) {
+    if (!ahead_ok(B.ctl) || aborted(S.ctl)) return;
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= S.nc) return;
+    const float *m = slot3(S.smargin, B.ctl->bslot);
+    float mm = 3.0e38f;
+    for (int64_t s = S.sbeg[c]; s < S.sbeg[c + 1]; s++) mm = fminf(mm, m[s]);
+    const double4 *r = B.cst + 4 * c;
+    const double4 x = r[0], q = r[2];
+    S.cdet[2 * c] = make_double4(x.x, x.y, x.z, (double)mm);
+    S.cdet[2 * c + 1] = q;
+}
+__global__ void __launch_bounds__(256) k_adopt_big(DevScene S, DevScene B) {
+    if (!ahead_ok(B.ctl) || aborted(S.ctl)) return;
+    const int32_t c = S.big_list[blockIdx.y];
+    const int64_t s0 = S.sbeg[c], s1 = S.sbeg[c + 1];
+    double4 *det = S.bdet + S.big_sbeg[blockIdx.y];
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < s1 - s0; k += (int64_t)gridDim.x * blockDim.x)
+        det[k] = B.spos[s0 + k];
+}
+
+// Adoption, first the guard: the set built ahead is valid from this step on
+// only if no sphere has moved 0.999 of its margin since the snapshot (the
+// guard of the steps since then watched the set in use).  Otherwise it is
+// not adopted (its history would miss the contacts it lost) and the set in
+// use stays, with its own guard.  B is the second stream's view (its
+// records are the snapshot's).
+__global__ void __launch_bounds__(256) k_adopt_guard(DevScene S, DevScene B) {
+    if (!ahead_built(B.ctl) || aborted(S.ctl)) return;
+    const int64_t s = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    bool trip = false;
+    if (s < S.ns) {
+        const uint32_t c = S.owner[s], ts = S.sts[s];
+        const SphereKin now = sphere_kin_of(S, c, ts), then = sphere_kin_of(B, c, ts);
+        const double dx = now.p[0] - then.p[0], dy = now.p[1] - then.p[1], dz = now.p[2] - then.p[2];
+        const double lim = 0.999 * (double)slot3(S.smargin, B.ctl->bslot)[s];
+        trip = !(dx * dx + dy * dy + dz * dz < lim * lim);
+    }
+    if (__syncthreads_or(trip) && threadIdx.x == 0) atomicOr(&B.ctl->stale, 1);
+}
+
+// Adoption, last: the set built ahead becomes the set in use (a set whose
+// storage overflowed is dropped; the host grows the storage).
+__global__ void k_adopt_end(DevScene S, const Ctl *bctl) {
+    Ctl *c = S.ctl;
+    if (aborted(c)) return;
+    if (!ahead_ok(bctl)) {
+        if (!ahead_built(bctl)) c->ahead_dropped = 1;  // storage too small: the host grows it
+        return;
+    }
+    c->buf = bctl->bslot;
+    c->hb ^= 1;
+    c->n_up_cur = bctl->n_up;
+    c->n_pairs_cur = bctl->n_pairs;
+    c->detections++;
+    c->fallbacks += bctl->fallbacks;
+    c->since_det = 1;  // the guard's reference was set from the snapshot
+}
+
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 // grid of a grid-stride kernel over at most n items (the count lives on the device)
@@ -1756,6 +1884,28 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
     TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(const DevScene &S, const DevScene &B, hipStream_t st) {
+    if (S.nc == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_snap, dim3(stride_blocks(4 * S.nc)), dim3(256), 0, st, S, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_detect_ahead(const DevScene &B, hipStream_t st) {
+    if (B.ns == 0) return hipSuccess;
+    hipError_t e = launch_pose(B, st, false);  // bins and region features of the snapshot
+    return e == hipSuccess ? launch_detect(B, st) : e;
+}
+
+hipError_t launch_adopt(const DevScene &S, const DevScene &B, hipStream_t st) {
+    if (S.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adopt_guard, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, B);
+    hipLaunchKernelGGL(k_adopt_rows, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, (const Ctl *)B.ctl);
+    hipLaunchKernelGGL(k_adopt_clumps, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S, B);
+    if (S.n_big) hipLaunchKernelGGL(k_adopt_big, dim3(16, S.n_big), dim3(256), 0, st, S, B);
+    hipLaunchKernelGGL(k_adopt_end, dim3(1), dim3(1), 0, st, S, (const Ctl *)B.ctl);
     return hipGetLastError();
 }
 

@@ -18,11 +18,11 @@ __device__ __forceinline__ T *pick(T *const (&a)[2], int k) { return k ? a[1] : 
 // Slot k of an active-set structure array (three slots).
 template <typename T>
 __device__ __forceinline__ T *slot3(T *const (&a)[3], int k) { return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]); }
-// The slot a detection writes: the second stream's own, or for a detection
-// on the step's stream the slot that is neither in use nor the second
-// stream's (with no overlap, bslot = 2 and this alternates between 0 and 1).
+// The slot a detection writes: the second stream's own (its control block's
+// bslot), or for a detection on the step's stream the slot that is neither
+// in use nor reserved for the second stream.
 __device__ __forceinline__ int out_slot(const DevScene &S) {
-    return S.bchain ? S.bslot : 3 - S.ctl->buf - S.bslot;
+    return S.bchain ? S.ctl->bslot : 3 - S.ctl->buf - S.ctl->bslot;
 }
 
 // ---------------------------------------------------------------- rotation

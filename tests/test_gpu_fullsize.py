@@ -95,20 +95,45 @@ def test_first_step_sampled_contacts_and_forces(bed, mlp):
     assert ef.max() <= FORCE_RTOL and et.max() <= FORCE_RTOL
 
 
-def test_learned_reproduces_plain_bitwise_at_full_size(bed, mlp):
-    steps = 101  # crosses an audit at step 100 and several deferred detections
-    out = {}
-    for mode in ("plain", "learned"):
-        sc = bench.make_scene(bed, mode, mlp)
-        sc.step(steps)
-        out[mode] = (sc.state(), sc.counts())
-        sc.close()
-        print(mode, out[mode][1], flush=True)
-    (sp, cp), (sl, cl) = out["plain"], out["learned"]
+STEPS = 101  # crosses an audit at step 100 and several deferred detections
+
+
+@pytest.fixture(scope="module")
+def plain_run(bed, mlp):
+    sc = bench.make_scene(bed, "plain", mlp)
+    sc.step(STEPS)
+    out = sc.state(), sc.counts()
+    sc.close()
+    print("plain", out[1], flush=True)
+    return out
+
+
+def test_learned_reproduces_plain_bitwise_at_full_size(bed, mlp, plain_run):
+    sc = bench.make_scene(bed, "learned", mlp)
+    sc.step(STEPS)
+    sl, cl = sc.state(), sc.counts()
+    sc.close()
+    print("learned", cl, flush=True)
+    sp, cp = plain_run
     for k in ("x", "q", "v", "w"):
         assert np.array_equal(sp[k], sl[k]), k
     assert cl["missed"] == 0 and cl["audits"] >= 2
     assert cl["detections"] < cp["detections"] // 4
+
+
+def test_overlapped_detection_reproduces_plain_bitwise_at_full_size(bed, mlp, plain_run):
+    """The learned interval with the next active set built on a second
+    stream while the steps go on (margins over two intervals)."""
+    sc = bench.make_scene(bed, "learned", mlp, dict(bench.DETECT, overlap=True))
+    sc.step(STEPS)
+    so, co = sc.state(), sc.counts()
+    sc.close()
+    print("learned, overlapped", co, flush=True)
+    sp, cp = plain_run
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(sp[k], so[k]), k
+    assert co["missed"] == 0 and co["audits"] >= 2
+    assert co["detections"] <= STEPS // bench.DETECT["k_max"] + 1 + co["guard_trips"]
 
 
 def _timed(sc, steps):
