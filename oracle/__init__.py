@@ -52,6 +52,10 @@ class _Desc(C.Structure):
         ("bnd_vel", C.c_void_p), ("bnd_omega", C.c_void_p), ("bnd_scene", C.c_void_p),
         ("n_presc", C.c_int32),
         ("presc_clump", C.c_void_p), ("presc_param", C.c_void_p),
+        ("n_mesh", C.c_int32),
+        ("mesh_state", C.c_void_p), ("mesh_mat", C.c_void_p), ("mesh_scene", C.c_void_p),
+        ("n_tri", C.c_int64),
+        ("tri_mesh", C.c_void_p), ("tri_vertex", C.c_void_p),
     ]
 
 
@@ -75,6 +79,9 @@ def lib():
             "dem_oracle_read_clump_forces": (V, [P, P, P]),
             "dem_oracle_read_sphere_forces": (V, [P, P, P]),
             "dem_oracle_read_boundary_forces": (V, [P, P, P]),
+            "dem_oracle_read_mesh_forces": (V, [P, P, P]),
+            "dem_oracle_read_mesh_state": (V, [P, P]),
+            "dem_oracle_set_mesh_state": (C.c_int, [P, C.c_int32, P]),
             "dem_oracle_read_state": (V, [P, P, P, P, P]),
             "dem_oracle_read_sphere_pos": (V, [P, P]),
             "dem_oracle_n_spheres": (I64, [P]),
@@ -119,12 +126,16 @@ class Oracle:
         s.bnd_vel, s.bnd_omega, s.bnd_scene = _ptr(d.bnd_vel), _ptr(d.bnd_omega), _ptr(d.bnd_scene)
         s.n_presc = len(d.presc_clump)
         s.presc_clump, s.presc_param = _ptr(d.presc_clump), _ptr(d.presc_param)
+        s.n_mesh, s.n_tri = d.n_mesh, d.n_tri
+        s.mesh_state, s.mesh_mat, s.mesh_scene = _ptr(d.mesh_state), _ptr(d.mesh_mat), _ptr(d.mesh_scene)
+        s.tri_mesh, s.tri_vertex = _ptr(d.tri_mesh), _ptr(d.tri_vertex)
         self._h = lib().dem_oracle_create(C.byref(s))
         if not self._h:
             raise ValueError(lib().dem_oracle_last_error().decode())
         self.n_clumps = d.n_clumps
         self.n_spheres = int(lib().dem_oracle_n_spheres(self._h))
         self.n_bnd = d.n_bnd
+        self.n_mesh = d.n_mesh
         self._ncont = 0
 
     def __del__(self):
@@ -157,6 +168,23 @@ class Oracle:
         lib().dem_oracle_read_contacts(self._h, _ptr(a), _ptr(b), _ptr(dl), _ptr(F), _ptr(u))
         lib().dem_oracle_read_contact_torques(self._h, _ptr(Ta), _ptr(Tb))
         return dict(a=a, b=b, delta=dl, F=F, u=u, Ta=Ta, Tb=Tb)
+
+    def mesh_forces(self):
+        """Force the spheres exert on each mesh and its torque about the mesh's
+        reference point, from the last evaluation: ([n_mesh, 3], [n_mesh, 3])."""
+        F = np.empty((self.n_mesh, 3)); T = np.empty((self.n_mesh, 3))
+        lib().dem_oracle_read_mesh_forces(self._h, _ptr(F), _ptr(T))
+        return F, T
+
+    def mesh_state(self):
+        st = np.empty((self.n_mesh, 13))
+        lib().dem_oracle_read_mesh_state(self._h, _ptr(st))
+        return st
+
+    def set_mesh_state(self, mesh: int, state):
+        st = np.ascontiguousarray(state, np.float64).reshape(13)
+        if lib().dem_oracle_set_mesh_state(self._h, int(mesh), _ptr(st)) != 0:
+            raise ValueError("mesh index out of range")
 
     def clump_forces(self):
         F = np.empty((self.n_clumps, 3)); T = np.empty((self.n_clumps, 3))

@@ -11,7 +11,8 @@
  *   2. sphere centres x_s = x_c + A o_s (multi-sphere clump, Sec. 2.1);
  *   3. the contact set by brute force: every pair a < b of spheres of
  *      different clumps in the same scene with d^2 < (Ra+Rb)^2 (strict), and
- *      every sphere / boundary pair with signed distance phi < R;
+ *      every sphere / boundary pair with signed distance phi < R; a triangle
+ *      of a mesh is a boundary whose distance is that to its closest point;
  *   4. per contact: normal n from a to b, penetration delta, contact point at
  *      the middle of the overlap, lever arms from each clump's CoM, relative
  *      velocity split into normal and tangential parts (Eq. kinematicsContactInfo);
@@ -27,7 +28,9 @@
  *      ascending partner id (spheres, then boundaries); per clump: the sum over
  *      its spheres in ascending id, then + M g (Eq. newton_law_1/2);
  *   7. symplectic Euler: v += h F/M, x += h v; body-frame Euler equations with
- *      the gyroscopic term; q += (h/2) q (x) (0, w_body), renormalised.
+ *      the gyroscopic term; q += (h/2) q (x) (0, w_body), renormalised;
+ *   8. meshes follow their prescribed velocities: x += h v,
+ *      q += (h/2) (0, w) (x) q (world-frame w), renormalised.
  */
 #include "oracle.h"
 
@@ -62,10 +65,17 @@ struct dem_oracle {
     double *ofs;            /* [ns][3] body offsets */
     double *rad;
     double *me, *mg, *mmu, *mbeta; /* (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, beta(CoR) */
-    /* boundaries */
+    /* boundaries: nb analytic primitives, then ntri mesh triangles (nw in all) */
+    int32_t nw;
     int32_t *btype, *bscene;
     double *bparam, *bvel, *bomega;
-    double *be, *bg, *bmu, *bbeta;
+    double *be, *bg, *bmu, *bbeta;   /* [nw] */
+    /* meshes */
+    int32_t nm;
+    int64_t ntri;
+    double *mx, *mq, *mv, *mw;       /* per mesh: reference point, orientation, velocity, world angular velocity */
+    int32_t *tmesh;                  /* [ntri] */
+    double *tvb, *tv;                /* [ntri][9] vertices in the mesh frame; in the world (this step) */
     double *grav;
     /* history: contacts of the previous step, ascending key, with their u */
     int64_t nh;
@@ -168,8 +178,16 @@ dem_oracle *dem_oracle_create(const dem_oracle_desc *d) {
         o->presc[c] = i;
     }
     int32_t nb = o->nb;
-    o->btype = (int32_t *)xmalloc(nb * sizeof(int32_t));
-    o->bscene = (int32_t *)xmalloc(nb * sizeof(int32_t));
+    o->nm = d->n_mesh;
+    o->ntri = d->n_tri;
+    if (o->nm < 0 || o->ntri < 0 || (o->ntri && o->nm < 1) || (int64_t)nb + o->ntri > 0x7fffffff) {
+        set_err("bad mesh sizes");
+        dem_oracle_destroy(o);
+        return NULL;
+    }
+    int32_t nw = o->nw = nb + (int32_t)o->ntri;
+    o->btype = (int32_t *)xmalloc(nw * sizeof(int32_t));
+    o->bscene = (int32_t *)xmalloc(nw * sizeof(int32_t));
     if (nb) {
         memcpy(o->btype, d->bnd_type, nb * sizeof(int32_t));
         memcpy(o->bscene, d->bnd_scene, nb * sizeof(int32_t));
@@ -177,10 +195,10 @@ dem_oracle *dem_oracle_create(const dem_oracle_desc *d) {
     o->bparam = dup_d(d->bnd_param, (size_t)NPARAM_BND * nb);
     o->bvel = dup_d(d->bnd_vel, 3 * (size_t)nb);
     o->bomega = dup_d(d->bnd_omega, 3 * (size_t)nb);
-    o->be = (double *)xmalloc(nb * sizeof(double));
-    o->bg = (double *)xmalloc(nb * sizeof(double));
-    o->bmu = (double *)xmalloc(nb * sizeof(double));
-    o->bbeta = (double *)xmalloc(nb * sizeof(double));
+    o->be = (double *)xmalloc(nw * sizeof(double));
+    o->bg = (double *)xmalloc(nw * sizeof(double));
+    o->bmu = (double *)xmalloc(nw * sizeof(double));
+    o->bbeta = (double *)xmalloc(nw * sizeof(double));
     for (int32_t i = 0; i < nb; i++) {
         const double *m = d->bnd_mat + 4 * i;
         double E = m[0], nu = m[1];
@@ -189,6 +207,33 @@ dem_oracle *dem_oracle_create(const dem_oracle_desc *d) {
         o->bmu[i] = m[2];
         o->bbeta[i] = beta_of_cor(m[3]);
         if (o->btype[i] < 0 || o->btype[i] > 3) { set_err("unknown boundary type"); dem_oracle_destroy(o); return NULL; }
+    }
+    int32_t nm = o->nm;
+    o->mx = (double *)xmalloc(3 * (size_t)nm * sizeof(double));
+    o->mq = (double *)xmalloc(4 * (size_t)nm * sizeof(double));
+    o->mv = (double *)xmalloc(3 * (size_t)nm * sizeof(double));
+    o->mw = (double *)xmalloc(3 * (size_t)nm * sizeof(double));
+    for (int32_t m = 0; m < nm; m++) dem_oracle_set_mesh_state(o, m, d->mesh_state + 13 * m);
+    o->tmesh = (int32_t *)xmalloc(o->ntri * sizeof(int32_t));
+    o->tvb = dup_d(d->tri_vertex, 9 * (size_t)o->ntri);
+    o->tv = (double *)xmalloc(9 * (size_t)o->ntri * sizeof(double));
+    for (int64_t k = 0; k < o->ntri; k++) {
+        int32_t m = d->tri_mesh[k];
+        if (m < 0 || m >= nm || d->mesh_scene[m] < 0 || d->mesh_scene[m] >= o->nsc) {
+            set_err("triangle mesh or mesh scene out of range");
+            dem_oracle_destroy(o);
+            return NULL;
+        }
+        o->tmesh[k] = m;
+        int32_t w = nb + (int32_t)k;  /* the triangle as a boundary: its mesh's material and scene */
+        const double *mm = d->mesh_mat + 4 * m;
+        double E = mm[0], nu = mm[1];
+        o->be[w] = (1.0 - nu * nu) / E;
+        o->bg[w] = 2.0 * (2.0 - nu) * (1.0 + nu) / E;
+        o->bmu[w] = mm[2];
+        o->bbeta[w] = beta_of_cor(mm[3]);
+        o->bscene[w] = d->mesh_scene[m];
+        o->btype[w] = -1;
     }
     o->grav = dup_d(d->gravity, 3 * (size_t)o->nsc);
     o->A = (double *)xmalloc(9 * nc * sizeof(double));
@@ -208,7 +253,8 @@ void dem_oracle_destroy(dem_oracle *o) {
                     o->presc_param, o->owner, o->ofs, o->rad, o->me, o->mg, o->mmu, o->mbeta,
                     o->btype, o->bscene, o->bparam, o->bvel, o->bomega, o->be, o->bg, o->bmu,
                     o->bbeta, o->grav, o->hkey, o->hu, o->A, o->ww, o->xs, o->ckey, o->cdelta,
-                    o->cF, o->cu, o->cra, o->crb, o->sF, o->sT, o->cFc, o->cTc, o->lo_beg, o->lo_idx};
+                    o->cF, o->cu, o->cra, o->crb, o->sF, o->sT, o->cFc, o->cTc, o->lo_beg, o->lo_idx,
+                    o->mx, o->mq, o->mv, o->mw, o->tmesh, o->tvb, o->tv};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; i++) free(ptrs[i]);
     free(o);
 }
@@ -246,6 +292,74 @@ static void compute_poses(dem_oracle *o) {
                 o->xs[3 * s + i] = o->x[3 * c + i] + (A[3 * i] * of[0] + A[3 * i + 1] * of[1] + A[3 * i + 2] * of[2]);
         }
     }
+    /* triangle vertices in the world: x_mesh + A(q_mesh) v */
+    for (int64_t k = 0; k < o->ntri; k++) {
+        int32_t m = o->tmesh[k];
+        double A[9];
+        quat_to_matrix(o->mq + 4 * m, A);
+        for (int j = 0; j < 3; j++) {
+            const double *vb = o->tvb + 9 * k + 3 * j;
+            for (int i = 0; i < 3; i++)
+                o->tv[9 * k + 3 * j + i] = o->mx[3 * m + i] + (A[3 * i] * vb[0] + A[3 * i + 1] * vb[1] + A[3 * i + 2] * vb[2]);
+        }
+    }
+}
+
+/* ---------------- mesh triangles ---------------- */
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Closest point c of triangle (A, B, C) to point p, by the Voronoi regions
+ * of its vertices, edges and face (the region tests of Ericson, Real-Time
+ * Collision Detection, Sec. 5.1.5): barycentric coordinates from dot
+ * products, the first region that holds p decides. */
+static void closest_on_triangle(const double *A, const double *B, const double *C, const double *p, double *c) {
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    for (int i = 0; i < 3; i++) { ab[i] = B[i] - A[i]; ac[i] = C[i] - A[i]; ap[i] = p[i] - A[i]; }
+    double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) { for (int i = 0; i < 3; i++) c[i] = A[i]; return; }
+    for (int i = 0; i < 3; i++) bp[i] = p[i] - B[i];
+    double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) { for (int i = 0; i < 3; i++) c[i] = B[i]; return; }
+    double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        double v = d1 / (d1 - d3);
+        for (int i = 0; i < 3; i++) c[i] = A[i] + v * ab[i];
+        return;
+    }
+    for (int i = 0; i < 3; i++) cp[i] = p[i] - C[i];
+    double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+    if (d6 >= 0.0 && d5 <= d6) { for (int i = 0; i < 3; i++) c[i] = C[i]; return; }
+    double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        double w = d2 / (d2 - d6);
+        for (int i = 0; i < 3; i++) c[i] = A[i] + w * ac[i];
+        return;
+    }
+    double va = d3 * d6 - d5 * d4;
+    double e43 = d4 - d3, e56 = d5 - d6;
+    if (va <= 0.0 && e43 >= 0.0 && e56 >= 0.0) {
+        double w = e43 / (e43 + e56);
+        for (int i = 0; i < 3; i++) c[i] = B[i] + w * (C[i] - B[i]);
+        return;
+    }
+    double den = (va + vb) + vc;
+    double v = vb / den, w = vc / den;
+    for (int i = 0; i < 3; i++) c[i] = (A[i] + ab[i] * v) + ac[i] * w;
+}
+
+/* Distance of p from triangle k and the unit normal from its closest point
+ * towards p; 0 when p lies on the triangle (no normal). */
+static int triangle_distance(const dem_oracle *o, int64_t k, const double *p, double *phi, double *n) {
+    const double *V = o->tv + 9 * k;
+    double c[3], d[3];
+    closest_on_triangle(V, V + 3, V + 6, p, c);
+    for (int i = 0; i < 3; i++) d[i] = p[i] - c[i];
+    double dd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(dd > 0.0)) return 0;
+    *phi = dd;
+    for (int i = 0; i < 3; i++) n[i] = d[i] / dd;
+    return 1;
 }
 
 /* ---------------- analytic boundaries ---------------- */
@@ -255,6 +369,7 @@ static void compute_poses(dem_oracle *o) {
  * Returns 0 when the boundary cannot touch p (outside its active range or on
  * a degenerate axis point). */
 static int boundary_distance(const dem_oracle *o, int32_t b, double t, const double *p, double *phi, double *n) {
+    if (b >= o->nb) return triangle_distance(o, b - o->nb, p, phi, n);
     const double *P = o->bparam + NPARAM_BND * b;
     const double *vel = o->bvel + 3 * b;
     double r0[3], d[3];
@@ -405,7 +520,7 @@ static int64_t row_pairs(const dem_oracle *o, int64_t a, double t, const double 
             cnt++;
         }
     }
-    for (int32_t w = 0; w < o->nb; w++) {
+    for (int32_t w = 0; w < o->nw; w++) {
         if ((uint32_t)o->bscene[w] != sa) continue;
         double phi, n[3];
         if (!boundary_distance(o, w, t, xa, &phi, n)) continue;
@@ -477,14 +592,27 @@ static double pair_eval(const dem_oracle *o, int64_t a, int64_t b, double t, con
         delta = R - phi;
         double lever = R - 0.5 * delta;
         for (int i = 0; i < 3; i++) p[i] = xsph[i] - lever * n[i];
-        const double *P = o->bparam + NPARAM_BND * wi;
+        /* the wall's reference point and velocity: an analytic boundary's
+         * first parameters moved with its translation, or a mesh's reference
+         * point; velocity v + w x (p - reference) */
+        const double *vel, *om;
         double cwall[3], wv[3], pw[3];
-        for (int i = 0; i < 3; i++) cwall[i] = P[i] + t * o->bvel[3 * wi + i];
+        if (wi < o->nb) {
+            const double *P = o->bparam + NPARAM_BND * wi;
+            vel = o->bvel + 3 * wi;
+            om = o->bomega + 3 * wi;
+            for (int i = 0; i < 3; i++) cwall[i] = P[i] + t * vel[i];
+        } else {
+            int32_t m = o->tmesh[wi - o->nb];
+            vel = o->mv + 3 * m;
+            om = o->mw + 3 * m;
+            for (int i = 0; i < 3; i++) cwall[i] = o->mx[3 * m + i];
+        }
         for (int i = 0; i < 3; i++) { ra[i] = p[i] - cwall[i]; rb[i] = p[i] - o->x[3 * cs + i]; }
-        cross(o->bomega + 3 * wi, ra, pw);
+        cross(om, ra, pw);
         double wb[3];
         cross(o->ww + 3 * cs, rb, wb);
-        for (int i = 0; i < 3; i++) wv[i] = o->bvel[3 * wi + i] + pw[i];
+        for (int i = 0; i < 3; i++) wv[i] = vel[i] + pw[i];
         for (int i = 0; i < 3; i++) vrel[i] = (o->v[3 * cs + i] + wb[i]) - wv[i];
         Rbar = R;
         mbar = o->mass[cs];
@@ -647,6 +775,25 @@ static void integrate(dem_oracle *o) {
     }
 }
 
+/* Meshes follow their prescribed motion: x += h v; the orientation turns at
+ * the world-frame angular velocity w, q += (h/2) (0, w) (x) q, renormalised. */
+static void advance_meshes(dem_oracle *o) {
+    double h = o->h, hh = 0.5 * h;
+    for (int32_t m = 0; m < o->nm; m++) {
+        double *x = o->mx + 3 * m, *q = o->mq + 4 * m;
+        const double *v = o->mv + 3 * m, *w = o->mw + 3 * m;
+        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        double dq[4];
+        dq[0] = -(w[0] * q[1] + w[1] * q[2] + w[2] * q[3]);
+        dq[1] = q[0] * w[0] + (w[1] * q[3] - w[2] * q[2]);
+        dq[2] = q[0] * w[1] + (w[2] * q[1] - w[0] * q[3]);
+        dq[3] = q[0] * w[2] + (w[0] * q[2] - w[1] * q[1]);
+        for (int i = 0; i < 4; i++) q[i] = q[i] + hh * dq[i];
+        double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        for (int i = 0; i < 4; i++) q[i] = q[i] / qn;
+    }
+}
+
 void dem_oracle_step(dem_oracle *o, int64_t n) {
     for (int64_t it = 0; it < n; it++) {
         dem_oracle_eval(o);
@@ -661,6 +808,7 @@ void dem_oracle_step(dem_oracle *o, int64_t n) {
             memcpy(o->hu, o->cu, 3 * o->nh * sizeof(double));
         }
         integrate(o);
+        advance_meshes(o);
         o->step++;
     }
 }
@@ -708,10 +856,39 @@ void dem_oracle_read_boundary_forces(const dem_oracle *o, double *F, double *T) 
         int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu);
         if (b < o->ns || !(o->cdelta[k] > 0.0)) continue;
         int64_t w = b - o->ns;
+        if (w >= o->nb) continue;  /* a mesh triangle: see dem_oracle_read_mesh_forces */
         double f[3] = {-o->cF[3 * k], -o->cF[3 * k + 1], -o->cF[3 * k + 2]}, tq[3];
         cross(o->cra + 3 * k, f, tq);
         for (int i = 0; i < 3; i++) { F[3 * w + i] = F[3 * w + i] + f[i]; T[3 * w + i] = T[3 * w + i] + tq[i]; }
     }
+}
+
+void dem_oracle_read_mesh_forces(const dem_oracle *o, double *F, double *T) {
+    for (int32_t m = 0; m < 3 * o->nm; m++) { F[m] = 0.0; T[m] = 0.0; }
+    for (int64_t k = 0; k < o->ncont; k++) {
+        int64_t b = (int64_t)(o->ckey[k] & 0xffffffffu) - o->ns - o->nb;
+        if (b < 0 || !(o->cdelta[k] > 0.0)) continue;
+        int32_t m = o->tmesh[b];
+        double f[3], tq[3];
+        for (int i = 0; i < 3; i++) f[i] = -o->cF[3 * k + i];  /* the mesh receives -F at the contact point */
+        cross(o->cra + 3 * k, f, tq);
+        for (int i = 0; i < 3; i++) { F[3 * m + i] = F[3 * m + i] + f[i]; T[3 * m + i] = T[3 * m + i] + tq[i]; }
+    }
+}
+
+void dem_oracle_read_mesh_state(const dem_oracle *o, double *st) {
+    for (int32_t m = 0; m < o->nm; m++) {
+        double *r = st + 13 * m;
+        for (int i = 0; i < 3; i++) { r[i] = o->mx[3 * m + i]; r[7 + i] = o->mv[3 * m + i]; r[10 + i] = o->mw[3 * m + i]; }
+        for (int i = 0; i < 4; i++) r[3 + i] = o->mq[4 * m + i];
+    }
+}
+
+int dem_oracle_set_mesh_state(dem_oracle *o, int32_t m, const double *st) {
+    if (m < 0 || m >= o->nm) return -1;
+    for (int i = 0; i < 3; i++) { o->mx[3 * m + i] = st[i]; o->mv[3 * m + i] = st[7 + i]; o->mw[3 * m + i] = st[10 + i]; }
+    for (int i = 0; i < 4; i++) o->mq[4 * m + i] = st[3 + i];
+    return 0;
 }
 
 void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w) {
@@ -769,7 +946,7 @@ static void sphere_sample(const dem_oracle *o, int64_t s, double t, double *Fs, 
     uint32_t cs = o->owner[s], sc = o->scene[cs];
     const double *xs = o->xs + 3 * s;
     for (int i = 0; i < 3; i++) { Fs[i] = 0.0; Ts[i] = 0.0; }
-    for (int64_t p = 0; p <= ns + o->nb - 1; p++) {
+    for (int64_t p = 0; p <= ns + o->nw - 1; p++) {
         if (p == s) continue;
         int64_t a, b;
         if (p < ns) {

@@ -9,7 +9,8 @@
  *   sphere world positions from clump poses (multi-sphere clumps, Sec. 2.1);
  *   the contact set by O(N^2) brute force (every candidate pair tested,
  *   no binning, no margin);
- *   sphere-boundary contacts against analytic primitives;
+ *   sphere-boundary contacts against analytic primitives and against the
+ *   triangles of rigid meshes whose motion is prescribed;
  *   the Hertz-Mindlin law of Eq. "normal_tangential_force_model1/2" with the
  *   kinematics of Eq. "kinematicsContactInfo", the tangential history update
  *   of Eq. "updateUt" and its Coulomb clamp of Eq. "cappingOfut";
@@ -59,6 +60,15 @@ typedef struct dem_oracle_desc {
     int32_t n_presc;
     const int32_t *presc_clump;        /* [n_presc] */
     const double *presc_param;         /* [n_presc][12] v_fixed, free mask, w_body, f_extra */
+    /* triangle meshes: rigid boundaries whose motion is prescribed */
+    int32_t n_mesh;
+    const double *mesh_state;          /* [n_mesh][13] x[3] reference point, q[4] (mesh->world),
+                                          v[3], w[3] angular velocity (world frame) */
+    const double *mesh_mat;            /* [n_mesh][4] E, nu, mu, CoR */
+    const int32_t *mesh_scene;         /* [n_mesh] */
+    int64_t n_tri;
+    const int32_t *tri_mesh;           /* [n_tri] */
+    const double *tri_vertex;          /* [n_tri][3][3] vertices in the mesh frame */
 } dem_oracle_desc;
 
 /* Returns NULL on invalid input (message via dem_oracle_last_error). */
@@ -96,6 +106,15 @@ void dem_oracle_read_sphere_forces(const dem_oracle *o, double *F, double *T);
  * evaluation; [n_bnd][3] each, in the description's boundary order. */
 void dem_oracle_read_boundary_forces(const dem_oracle *o, double *F, double *T);
 void dem_oracle_read_state(const dem_oracle *o, double *x, double *q, double *v, double *w);
+/* Triangle meshes.  A contact of sphere s with triangle k has
+ * b = n_spheres + n_bnd + k.  Force the spheres exert on each mesh and its
+ * torque about the mesh's reference point, from the last evaluation,
+ * [n_mesh][3] each. */
+void dem_oracle_read_mesh_forces(const dem_oracle *o, double *F, double *T);
+/* Mesh states [n_mesh][13] (x, q, v, w as in the descriptor). */
+void dem_oracle_read_mesh_state(const dem_oracle *o, double *state);
+/* Prescribe a mesh's state (13 doubles); returns -1 for a bad index. */
+int dem_oracle_set_mesh_state(dem_oracle *o, int32_t mesh, const double *state);
 void dem_oracle_read_sphere_pos(const dem_oracle *o, double *xs);
 int64_t dem_oracle_n_spheres(const dem_oracle *o);
 

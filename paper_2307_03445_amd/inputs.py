@@ -87,6 +87,12 @@ class SceneDesc:
     bnd_scene: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     presc_clump: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     presc_param: np.ndarray = field(default_factory=lambda: np.zeros((0, PRESC_NPARAM)))
+    # triangle meshes: rigid boundaries with prescribed motion
+    mesh_state: np.ndarray = field(default_factory=lambda: np.zeros((0, 13)))  # x[3], q[4], v[3], w[3] (world)
+    mesh_mat: np.ndarray = field(default_factory=lambda: np.zeros((0, 4)))
+    mesh_scene: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    tri_mesh: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    tri_vertex: np.ndarray = field(default_factory=lambda: np.zeros((0, 3, 3)))  # mesh frame
     name: str = "scene"
 
     # ---- derived sizes -------------------------------------------------
@@ -105,6 +111,14 @@ class SceneDesc:
     @property
     def n_bnd(self) -> int:
         return int(self.bnd_type.shape[0])
+
+    @property
+    def n_mesh(self) -> int:
+        return int(np.asarray(self.mesh_scene).shape[0])
+
+    @property
+    def n_tri(self) -> int:
+        return int(np.asarray(self.tri_mesh).shape[0])
 
     def clump_sphere_counts(self) -> np.ndarray:
         tsz = np.diff(self.tmpl_sphere_begin.astype(np.int64))
@@ -143,6 +157,10 @@ class SceneDesc:
             bnd_scene=np.ascontiguousarray(self.bnd_scene, np.int32),
             presc_clump=np.ascontiguousarray(self.presc_clump, np.int32),
             presc_param=f(self.presc_param, (npr, PRESC_NPARAM)),
+            mesh_state=f(self.mesh_state, (self.n_mesh, 13)), mesh_mat=f(self.mesh_mat, (self.n_mesh, 4)),
+            mesh_scene=np.ascontiguousarray(self.mesh_scene, np.int32),
+            tri_mesh=np.ascontiguousarray(self.tri_mesh, np.int32),
+            tri_vertex=f(self.tri_vertex, (self.n_tri, 3, 3)),
         )
 
     def validate(self) -> None:
@@ -261,7 +279,7 @@ def bounding_radius(body_offsets: np.ndarray, radii: np.ndarray) -> float:
 # ---------------------------------------------------------------------------
 
 def assemble(templates, clump_template, x, q, v, w, sphere_mat, gravity, domain, h,
-             clump_scene=None, bnd=None, presc=None, name="scene") -> SceneDesc:
+             clump_scene=None, bnd=None, presc=None, meshes=None, name="scene") -> SceneDesc:
     """Build a SceneDesc from a list of (offsets, radii, mass, moments) templates."""
     sizes = [t[0].shape[0] for t in templates]
     begin = np.zeros(len(templates) + 1, np.uint32)
@@ -303,6 +321,15 @@ def assemble(templates, clump_template, x, q, v, w, sphere_mat, gravity, domain,
             P[i, 6:9] = p.get("w_body", (0, 0, 0))
             P[i, 9:12] = p.get("f_extra", (0, 0, 0))
         d.presc_param = P
+    if meshes:
+        # each: vertices [n][3][3] in the mesh frame, x, q, v, w (world angular velocity), mat, scene
+        d.mesh_state = np.array([np.r_[m.get("x", (0, 0, 0)), m.get("q", (1, 0, 0, 0)), m.get("v", (0, 0, 0)),
+                                       m.get("w", (0, 0, 0))] for m in meshes], np.float64).reshape(-1, 13)
+        d.mesh_mat = np.array([m["mat"] for m in meshes], np.float64).reshape(-1, 4)
+        d.mesh_scene = np.array([m.get("scene", 0) for m in meshes], np.int32)
+        d.tri_vertex = np.concatenate([np.asarray(m["vertices"], np.float64).reshape(-1, 3, 3) for m in meshes])
+        d.tri_mesh = np.concatenate([np.full(np.asarray(m["vertices"]).reshape(-1, 3, 3).shape[0], i, np.int32)
+                                     for i, m in enumerate(meshes)])
     return d.canonical()
 
 
