@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define CDEM_ABI_VERSION 2
+#define CDEM_ABI_VERSION 3
 
 /* ---- error codes ---- */
 #define CDEM_OK 0
@@ -103,6 +103,23 @@ typedef struct cdem_scene_desc {
     int32_t n_presc;
     const int32_t *presc_clump;        /* [n_presc] prescribed-motion clumps */
     const double *presc_param;         /* [n_presc][12] */
+    /* Triangle meshes: rigid boundaries whose motion the caller prescribes
+     * (the paper's funnel, cone and wheels are meshes, Sec. 4; a multibody
+     * solver drives them in co-simulation).  Each triangle is a boundary of
+     * its mesh's scene: a sphere touches it when its centre is closer than
+     * its radius to the triangle's closest point (two-sided, edges and
+     * vertices included); the contact normal points from that point to the
+     * centre; the mesh is flat and infinitely heavy there (Rbar = R,
+     * mbar = the clump's mass).  Every step a mesh moves with its
+     * velocities: x += h v, q += (h/2) (0, w) (x) q, renormalised. */
+    int32_t n_mesh;                    /* <= 64 */
+    const double *mesh_state;          /* [n_mesh][13] x[3] reference point, q[4] (mesh -> world, unit),
+                                          v[3], w[3] angular velocity (world frame) */
+    const double *mesh_mat;            /* [n_mesh][4] E, nu, mu, CoR */
+    const int32_t *mesh_scene;         /* [n_mesh] */
+    int64_t n_tri;                     /* n_spheres + n_bnd + n_tri < 2^31 */
+    const int32_t *tri_mesh;           /* [n_tri] */
+    const double *tri_vertex;          /* [n_tri][3][3] vertices in the mesh frame (about x) */
 } cdem_scene_desc;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  NULL
@@ -159,7 +176,8 @@ typedef struct cdem_state_view {
 } cdem_state_view;
 
 /* Contacts of the last recorded step (see cdem_record_next_step), canonical:
- * sphere pairs a < b < n_spheres, boundary contacts b = n_spheres + index.
+ * sphere pairs a < b < n_spheres, boundary contacts b = n_spheres + index,
+ * triangle contacts b = n_spheres + n_bnd + triangle index.
  * Only pairs whose exact predicate held that step (true contacts) are listed,
  * ascending by (a, b).  Host buffers of capacity 'cap' (any may be NULL);
  * *n receives the count (call with cap = 0 to size).  F is F_n + F_t of
@@ -285,6 +303,22 @@ int cdem_read_boundary_forces(cdem_scene *s, double *F, double *T);
 /* Sphere centres x_c + A(q) o_s of the current state (the clump
  * representation of Sec. 2.1), host buffer [n_spheres][3]. */
 int cdem_read_sphere_pos(cdem_scene *s, double *xs);
+
+/* ---- triangle meshes (co-simulation: the caller moves a mesh, the scene
+ * reports the force the spheres exert on it; Sec. 5.2 couples the granular
+ * side and a multibody solver this way, one exchange every few steps) ---- */
+/* Prescribe mesh `mesh`'s state (13 doubles as in cdem_scene_desc.mesh_state,
+ * host pointer; unit quaternion, finite values, else CDEM_E_INVALID).  The
+ * active set is kept: its margins are recomputed for the new velocities
+ * before the next step (a sphere the mesh outruns trips the guard). */
+int cdem_set_mesh_state(cdem_scene *s, int32_t mesh, const double *state);
+/* Current mesh states, host buffer [n_mesh][13]. */
+int cdem_read_mesh_state(cdem_scene *s, double *state);
+/* Force the spheres exert on each mesh (minus the sum of its contact forces)
+ * and its torque about the mesh's reference point at the last recorded step
+ * (see cdem_record_next_step), host buffers [n_mesh][3], summed in ascending
+ * contact order.  CDEM_E_STATE when no step was recorded. */
+int cdem_read_mesh_forces(cdem_scene *s, double *F, double *T);
 
 /* Independent exact contact sweep (no binning, no margin) over the current
  * state, compared with the active set: with the enlarged geometry of Sec.

@@ -34,6 +34,8 @@ class SceneDescC(C.Structure):
         ("n_bnd", C.c_int32), ("bnd_type", P), ("bnd_param", P), ("bnd_mat", P), ("bnd_vel", P),
         ("bnd_omega", P), ("bnd_scene", P),
         ("n_presc", C.c_int32), ("presc_clump", P), ("presc_param", P),
+        ("n_mesh", C.c_int32), ("mesh_state", P), ("mesh_mat", P), ("mesh_scene", P),
+        ("n_tri", C.c_int64), ("tri_mesh", P), ("tri_vertex", P),
     ]
 
 
@@ -103,6 +105,9 @@ SIGNATURES = {
     "cdem_mlp_backward": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P, P]),
     "cdem_mlp_backward_static": (C.c_int, [P, P, P, C.c_int64, C.c_float, P, P, P]),
     "cdem_check_force_law": (C.c_int, [C.c_char_p, C.c_char_p, C.c_size_t]),
+    "cdem_set_mesh_state": (C.c_int, [P, C.c_int32, P]),
+    "cdem_read_mesh_state": (C.c_int, [P, P]),
+    "cdem_read_mesh_forces": (C.c_int, [P, P, P]),
     "cdem_set_force_law": (C.c_int, [P, C.c_char_p, C.c_char_p, C.c_size_t]),
     "cdem_mlp_adam": (C.c_int, [P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float, P]),
     "cdem_collect_envelopes": (C.c_int, [P, C.c_int32, P, P, C.c_int64, C.POINTER(C.c_int64)]),
@@ -196,6 +201,10 @@ class Scene:
         s.bnd_type, s.bnd_param, s.bnd_mat = _ptr(d.bnd_type), _ptr(d.bnd_param), _ptr(d.bnd_mat)
         s.bnd_vel, s.bnd_omega, s.bnd_scene = _ptr(d.bnd_vel), _ptr(d.bnd_omega), _ptr(d.bnd_scene)
         s.n_presc, s.presc_clump, s.presc_param = len(d.presc_clump), _ptr(d.presc_clump), _ptr(d.presc_param)
+        s.n_mesh, s.mesh_state, s.mesh_mat = d.n_mesh, _ptr(d.mesh_state), _ptr(d.mesh_mat)
+        s.mesh_scene, s.n_tri = _ptr(d.mesh_scene), d.n_tri
+        s.tri_mesh, s.tri_vertex = _ptr(d.tri_mesh), _ptr(d.tri_vertex)
+        self.n_mesh = d.n_mesh
         self._alloc = None
         self._stream = stream
         try:
@@ -361,6 +370,22 @@ class Scene:
     def load(self, blob: bytes):
         """Restore a checkpoint written by :meth:`save` of a scene with the same description."""
         self._check(self._L.cdem_load(self._h, blob, len(blob)))
+
+    def set_mesh_state(self, mesh: int, state):
+        """Prescribe a mesh's state: x[3], q[4], v[3], w[3] (world angular velocity)."""
+        st = np.ascontiguousarray(state, np.float64).reshape(13)
+        self._check(self._L.cdem_set_mesh_state(self._h, int(mesh), _ptr(st)))
+
+    def mesh_state(self) -> np.ndarray:
+        st = np.empty((self.n_mesh, 13))
+        self._check(self._L.cdem_read_mesh_state(self._h, _ptr(st)))
+        return st
+
+    def mesh_forces(self):
+        """Force on each mesh and torque about its reference point at the recorded step."""
+        F, T = np.empty((self.n_mesh, 3)), np.empty((self.n_mesh, 3))
+        self._check(self._L.cdem_read_mesh_forces(self._h, _ptr(F), _ptr(T)))
+        return F, T
 
     def set_force_law(self, source):
         """Compile a user force law (the source of `cdem_user_law`, see

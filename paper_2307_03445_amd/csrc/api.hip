@@ -104,6 +104,12 @@ struct cdem_scene {
     std::vector<double> dom;           // [n_scenes][6]
     std::vector<int32_t> bnd_user;     // device boundary order -> user index
     std::vector<Bnd> bnd;
+    // triangle meshes: velocities, materials and margins are the host's; the
+    // device advances positions and orientations every step
+    std::vector<Mesh> mesh;
+    std::vector<double> mesh_speed;    // speed bound |v| + |w| rmax each mesh's margin was sized for
+    std::vector<int32_t> tri_user;     // device triangle order -> user index
+    std::vector<int32_t> tri_mesh;     // device triangle order -> mesh
     double rmax = 0.0;
     int64_t n_cells_alloc = 0;
     int64_t n_regions_alloc = 0;
@@ -131,6 +137,8 @@ struct cdem_scene {
         uint32_t *over_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
         uint32_t *bin_v = nullptr, *bin_a = nullptr, *reg_occ = nullptr;
         double *part_k = nullptr;
+        Mesh *mesh = nullptr;          // the meshes at the snapshot
+        double *tri_box = nullptr;
         int64_t n_cells_alloc = 0, n_regions_alloc = 0;
     } ahead;
 };
@@ -174,6 +182,16 @@ static uint64_t desc_fingerprint(const cdem_scene_desc *d, int64_t ns) {
     if (d->n_presc) {
         h = fnv1a(h, d->presc_clump, 4 * (size_t)d->n_presc);
         h = fnv1a(h, d->presc_param, 96 * (size_t)d->n_presc);
+    }
+    h = fnv1a(h, &d->n_mesh, 4);
+    if (d->n_mesh) {
+        h = fnv1a(h, d->mesh_mat, 32 * (size_t)d->n_mesh);
+        h = fnv1a(h, d->mesh_scene, 4 * (size_t)d->n_mesh);
+    }
+    h = fnv1a(h, &d->n_tri, 8);
+    if (d->n_tri) {
+        h = fnv1a(h, d->tri_mesh, 4 * (size_t)d->n_tri);
+        h = fnv1a(h, d->tri_vertex, 72 * (size_t)d->n_tri);
     }
     return h;
 }
@@ -442,8 +460,10 @@ static int ahead_alloc(cdem_scene *sc) {
         a.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * ns);
         a.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
         a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
+        a.mesh = (Mesh *)dev_alloc(sc, sizeof(Mesh) * std::max<int64_t>(S.n_mesh, 1));
+        a.tri_box = (double *)dev_alloc(sc, 48 * std::max<int64_t>(S.n_tri, 1));
         if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_id || !a.sorted_owner ||
-            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.over_list || !a.part_k)
+            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.over_list || !a.part_k || !a.mesh || !a.tri_box)
             return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
         Ctl z;
         memset(&z, 0, sizeof z);
@@ -488,18 +508,70 @@ static DevScene ahead_view(const cdem_scene *sc) {
     B.sorted_margin = a.sorted_margin; B.sorted_f4 = a.sorted_f4;
     B.bin_v = a.bin_v; B.bin_a = a.bin_a; B.reg_occ = a.reg_occ; B.bin_margin = a.bin_margin;
     B.part_k = a.part_k; B.over_list = a.over_list;
+    B.mesh = a.mesh; B.tri_box = a.tri_box;
     B.store_speed = 0; B.store_acc = 0;
     B.plan.audit_period = 0;
     return B;
 }
 
-static void set_bnd_margins(cdem_scene *sc) {
+static double norm3(const double *a) { return std::sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]); }
+
+// Speed bound of every point of a mesh: |v| + |w| rmax.
+static double mesh_speed_of(const Mesh &m) { return norm3(m.v) + norm3(m.w) * m.rmax; }
+
+// Candidate margins covering a boundary's own motion over the steps a set is
+// used: speed x steps x h, plus 1 %.
+static int margin_steps(const cdem_scene *sc) {
     int kmax = sc->det.mode == CDEM_DETECT_PLAIN ? 0 : std::max(1, sc->det.k_max);
     if (sc->ahead.on) kmax *= 2;  // a set built ahead is used up to 2 k_max steps after its snapshot
-    for (auto &b : sc->bnd) {
-        double sp = std::sqrt(b.vel[0] * b.vel[0] + b.vel[1] * b.vel[1] + b.vel[2] * b.vel[2]);
-        b.margin = sp * (double)kmax * sc->S.h * 1.01;
+    return kmax;
+}
+
+static void set_bnd_margins(cdem_scene *sc) {
+    const double kh = (double)margin_steps(sc) * sc->S.h * 1.01;
+    for (auto &b : sc->bnd) b.margin = norm3(b.vel) * kh;
+    for (size_t i = 0; i < sc->mesh.size(); i++) {
+        sc->mesh_speed[i] = mesh_speed_of(sc->mesh[i]);
+        sc->mesh[i].margin = sc->mesh_speed[i] * kh;
     }
+}
+
+// Device mesh records from the host's, keeping the positions and
+// orientations the device has advanced (the stream is drained first).
+static int push_meshes(cdem_scene *sc) {
+    const size_t n = sc->mesh.size();
+    if (!n) return CDEM_OK;
+    std::vector<Mesh> dev(n);
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    HIPCHK(hipMemcpy(dev.data(), sc->S.mesh, n * sizeof(Mesh), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < n; i++) {
+        memcpy(sc->mesh[i].x, dev[i].x, sizeof dev[i].x);
+        memcpy(sc->mesh[i].q, dev[i].q, sizeof dev[i].q);
+    }
+    HIPCHK(hipMemcpy(sc->S.mesh, sc->mesh.data(), n * sizeof(Mesh), hipMemcpyHostToDevice));
+    return CDEM_OK;
+}
+
+// Validates a mesh state (13 doubles: x, unit q, v, w).
+static bool mesh_state_ok(const double *st) {
+    if (!finite_all(st, 13)) return false;
+    const double qn = st[3] * st[3] + st[4] * st[4] + st[5] * st[5] + st[6] * st[6];
+    return std::fabs(qn - 1.0) < 1e-10;
+}
+
+static void mesh_set_state(Mesh &m, const double *st) {
+    for (int i = 0; i < 3; i++) { m.x[i] = st[i]; m.v[i] = st[7 + i]; m.w[i] = st[10 + i]; }
+    for (int i = 0; i < 4; i++) m.q[i] = st[3 + i];
+}
+
+// A contact partner as the caller numbers it: spheres as they are, analytic
+// boundaries and triangles in the description's order.
+static uint32_t user_partner(const cdem_scene *sc, uint32_t t) {
+    const uint32_t ns = (uint32_t)sc->S.ns, nb = (uint32_t)sc->S.n_bnd;
+    if (t < ns) return t;
+    const uint32_t w = t - ns;
+    if (w < nb) return ns + (uint32_t)sc->bnd_user[w];
+    return ns + nb + (uint32_t)sc->tri_user[w - nb];
 }
 
 extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc, void *stream, cdem_scene **out) {
@@ -563,6 +635,21 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         if (c < 0 || c >= nc) return invalid("prescribed clump out of range");
         presc[c] = k;
     }
+    if (d->n_mesh < 0 || d->n_mesh > kMaxMesh || d->n_tri < 0 || (d->n_tri > 0 && d->n_mesh < 1))
+        return invalid("mesh counts (at most 64 meshes)");
+    if (ns + (int64_t)d->n_bnd + d->n_tri >= ((int64_t)1 << 31) - 1) return invalid("too many spheres and triangles");
+    if (d->n_mesh && (!d->mesh_state || !d->mesh_mat || !d->mesh_scene)) return invalid("mesh arrays");
+    if (d->n_tri && (!d->tri_mesh || !d->tri_vertex)) return invalid("triangle arrays");
+    for (int k = 0; k < d->n_mesh; k++) {
+        const double *m = d->mesh_mat + 4 * k;
+        if (d->mesh_scene[k] < 0 || d->mesh_scene[k] >= d->n_scenes) return invalid("mesh scene");
+        if (!(m[0] > 0) || !(m[1] > -1 && m[1] < 0.5) || !(m[2] >= 0) || !(m[3] > 0 && m[3] <= 1))
+            return invalid("mesh material out of range");
+        if (!mesh_state_ok(d->mesh_state + 13 * k)) return invalid("mesh state (finite, unit quaternion)");
+    }
+    for (int64_t k = 0; k < d->n_tri; k++)
+        if (d->tri_mesh[k] < 0 || d->tri_mesh[k] >= d->n_mesh) return invalid("triangle mesh out of range");
+    if (!finite_all(d->tri_vertex, 9 * (size_t)d->n_tri)) return invalid("triangle vertices");
     // ---- host-side derived arrays
     sc->custom_alloc = alloc && alloc->alloc && alloc->free;
     if (sc->custom_alloc) sc->alloc = *alloc;
@@ -612,6 +699,40 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         B.mu = m[2]; B.beta = beta_of_cor(m[3]);
         B.ef = (float)B.e; B.gf = (float)B.g; B.muf = (float)B.mu; B.betaf = (float)B.beta;
     }
+    // meshes, and their triangles sorted by scene (stable)
+    sc->mesh.resize(d->n_mesh);
+    sc->mesh_speed.assign(d->n_mesh, 0.0);
+    for (int k = 0; k < d->n_mesh; k++) {
+        Mesh &M = sc->mesh[k];
+        memset(&M, 0, sizeof M);
+        mesh_set_state(M, d->mesh_state + 13 * k);
+        const double *m = d->mesh_mat + 4 * k;
+        M.e = (1.0 - m[1] * m[1]) / m[0];
+        M.g = 2.0 * (2.0 - m[1]) * (1.0 + m[1]) / m[0];
+        M.mu = m[2]; M.beta = beta_of_cor(m[3]);
+        M.ef = (float)M.e; M.gf = (float)M.g; M.muf = (float)M.mu; M.betaf = (float)M.beta;
+        M.scene = d->mesh_scene[k];
+    }
+    for (int64_t k = 0; k < d->n_tri; k++) {  // rmax: the farthest vertex from its mesh's reference point
+        Mesh &M = sc->mesh[d->tri_mesh[k]];
+        for (int j = 0; j < 3; j++) M.rmax = std::max(M.rmax, norm3(d->tri_vertex + 9 * k + 3 * j));
+    }
+    std::vector<double> tri_vb(9 * (size_t)d->n_tri);
+    {
+        std::vector<int32_t> tord(d->n_tri);
+        for (int64_t k = 0; k < d->n_tri; k++) tord[k] = (int32_t)k;
+        std::stable_sort(tord.begin(), tord.end(), [&](int32_t a, int32_t b) {
+            return d->mesh_scene[d->tri_mesh[a]] < d->mesh_scene[d->tri_mesh[b]];
+        });
+        sc->tri_user = tord;
+        sc->tri_mesh.resize(d->n_tri);
+        for (int64_t i = 0; i < d->n_tri; i++) {
+            sc->tri_mesh[i] = d->tri_mesh[tord[i]];
+            memcpy(&tri_vb[9 * i], d->tri_vertex + 9 * (size_t)tord[i], 72);
+        }
+    }
+    S.n_mesh = d->n_mesh;
+    S.n_tri = d->n_tri;
     set_bnd_margins(sc);
     sc->grids.resize(d->n_scenes);
     sc->dom.assign(d->domain, d->domain + 6 * d->n_scenes);
@@ -627,6 +748,12 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
             sc->grids[k].bnd_beg = i;
             while (i < d->n_bnd && sc->bnd[i].scene == k) i++;
             sc->grids[k].bnd_end = i;
+        }
+        int64_t j = 0;
+        for (int k = 0; k < d->n_scenes; k++) {
+            sc->grids[k].tri_beg = (int32_t)j;
+            while (j < d->n_tri && sc->mesh[sc->tri_mesh[j]].scene == k) j++;
+            sc->grids[k].tri_end = (int32_t)j;
         }
     }
     std::vector<int32_t> big;
@@ -737,6 +864,9 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     UP(mat64, mat64.data(), ns);
     UP(mat32, mat32.data(), ns);
     UP(bnd, sc->bnd.data(), sc->bnd.size());
+    UP(mesh, sc->mesh.data(), sc->mesh.size());
+    UP(tri_vb, tri_vb.data(), tri_vb.size());
+    UP(tri_mesh, sc->tri_mesh.data(), sc->tri_mesh.size());
     UP(big_list, big.data(), big.size());
     {
         std::vector<int64_t> bsb(big.size() + 1, 0);
@@ -772,6 +902,10 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.over_cap = std::max<int64_t>(4096, ns / 8);
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
     if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    if (d->n_tri) {
+        S.tri_box = (double *)dev_alloc(sc, 48 * (size_t)d->n_tri);
+        if (!S.tri_box) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    }
     for (int k = 0; k < 3; k++) {  // per-sphere structure of the three active-set slots
         S.lo_beg[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
         S.lo_cnt[k] = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
@@ -1046,6 +1180,7 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
     sc->S.guard_on = p->mode != CDEM_DETECT_PLAIN && !sc->test_no_guard ? 1 : 0;
     set_bnd_margins(sc);
     HIPCHK(hipMemcpyAsync((void *)sc->S.bnd, sc->bnd.data(), sc->bnd.size() * sizeof(Bnd), hipMemcpyHostToDevice, sc->stream));
+    if ((rc = push_meshes(sc)) != CDEM_OK) return rc;
     if ((rc = build_grids(sc)) != CDEM_OK) return rc;
     if (a.on && (rc = ahead_alloc(sc)) != CDEM_OK) return rc;
     c.det_due = 1;
@@ -1217,13 +1352,8 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
             int64_t e = (int64_t)beg[s] + k;
             uint32_t t = nb[e];
             if (!st[e]) continue;
-            uint64_t b;  // pairs are listed once, in the lower sphere's segment
-            if (t < (uint32_t)ns) {
-                b = t;
-            } else {
-                b = (uint64_t)ns + (uint64_t)sc->bnd_user[t - (uint32_t)ns];
-            }
-            rows.push_back({((uint64_t)s << 32) | b, e});
+            // pairs are listed once, in the lower sphere's segment
+            rows.push_back({((uint64_t)s << 32) | user_partner(sc, t), e});
         }
     std::sort(rows.begin(), rows.end(), [](const Row &x, const Row &y) { return x.key < y.key; });
     v->n = (int64_t)rows.size();
@@ -1298,7 +1428,7 @@ extern "C" int cdem_audit(cdem_scene *sc, cdem_audit_result *r) {
     r->missed = (int64_t)out[1];
     r->first_a = out[1] ? (uint32_t)(out[2] >> 32) : 0;
     uint32_t fb = (uint32_t)(out[2] & 0xffffffffu);
-    if (out[1] && fb >= (uint32_t)S.ns) fb = (uint32_t)S.ns + (uint32_t)sc->bnd_user[fb - (uint32_t)S.ns];
+    if (out[1]) fb = user_partner(sc, fb);
     r->first_b = out[1] ? fb : 0;
     return out[1] ? CDEM_E_MISSED_CONTACT : CDEM_OK;
 }
@@ -1509,6 +1639,108 @@ extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, 
     return CDEM_OK;
 }
 
+// ---------------------------------------------------------------- triangle meshes
+extern "C" int cdem_read_mesh_state(cdem_scene *sc, double *state) {
+    if (!sc || (!state && sc->S.n_mesh)) return fail(sc, CDEM_E_INVALID, "null argument");
+    const int32_t n = sc->S.n_mesh;
+    if (!n) return CDEM_OK;
+    std::vector<Mesh> dev(n);
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    HIPCHK(hipMemcpy(dev.data(), sc->S.mesh, n * sizeof(Mesh), hipMemcpyDeviceToHost));
+    for (int32_t m = 0; m < n; m++) {
+        double *r = state + 13 * m;
+        for (int i = 0; i < 3; i++) { r[i] = dev[m].x[i]; r[7 + i] = dev[m].v[i]; r[10 + i] = dev[m].w[i]; }
+        for (int i = 0; i < 4; i++) r[3 + i] = dev[m].q[i];
+    }
+    return CDEM_OK;
+}
+
+// A new velocity whose speed bound the mesh's margin still covers, at an
+// unchanged pose, keeps the active set (every point of the mesh moves no
+// farther per step than the margin assumed); anything else, a new pose or a
+// faster motion, resizes the margin and detects again before the next step.
+extern "C" int cdem_set_mesh_state(cdem_scene *sc, int32_t mesh, const double *state) {
+    if (!sc || !state) return fail(sc, CDEM_E_INVALID, "null argument");
+    if (mesh < 0 || mesh >= sc->S.n_mesh) return fail(sc, CDEM_E_INVALID, "mesh index out of range");
+    if (!mesh_state_ok(state)) return fail(sc, CDEM_E_INVALID, "mesh state (finite, unit quaternion)");
+    int rc;
+    HIPCHK(hipStreamSynchronize(sc->stream));
+    Mesh cur;
+    HIPCHK(hipMemcpy(&cur, sc->S.mesh + mesh, sizeof(Mesh), hipMemcpyDeviceToHost));
+    Mesh &M = sc->mesh[mesh];
+    mesh_set_state(M, state);
+    const bool same_pose = memcmp(cur.x, M.x, sizeof M.x) == 0 && memcmp(cur.q, M.q, sizeof M.q) == 0;
+    const bool covered = mesh_speed_of(M) <= sc->mesh_speed[mesh];
+    if (same_pose && covered) {  // only the velocities change; the margin is kept
+        M.margin = cur.margin;
+        HIPCHK(hipMemcpy(sc->S.mesh + mesh, &M, sizeof(Mesh), hipMemcpyHostToDevice));
+        return CDEM_OK;
+    }
+    if ((rc = ahead_drain(sc, true)) != CDEM_OK) return rc;  // a set built for the old motion is dropped
+    const double kh = (double)margin_steps(sc) * sc->S.h * 1.01;
+    sc->mesh_speed[mesh] = mesh_speed_of(M);
+    M.margin = sc->mesh_speed[mesh] * kh;
+    HIPCHK(hipMemcpy(sc->S.mesh + mesh, &M, sizeof(Mesh), hipMemcpyHostToDevice));
+    Ctl c;
+    if ((rc = read_ctl(sc, c)) != CDEM_OK) return rc;
+    c.det_due = 1;
+    return write_ctl(sc, c);
+}
+
+extern "C" int cdem_read_mesh_forces(cdem_scene *sc, double *F, double *T) {
+    if (!sc) return CDEM_E_INVALID;
+    const DevScene &S = sc->S;
+    if (!sc->rec_cap) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
+    const int32_t nm = S.n_mesh;
+    if (!nm) return CDEM_OK;
+    Ctl c;
+    int rc = read_ctl(sc, c);
+    if (rc) return rc;
+    const int cur = c.buf;
+    const int64_t ne = c.n_pairs_cur, ns = S.ns;
+    std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
+    std::vector<uint8_t> st(ne);
+    std::vector<double> dl(ne), Fr(3 * ne), Rr(3 * ne);
+    if (ns) {
+        HIPCHK(hipMemcpy(beg.data(), S.lo_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(cnt.data(), S.lo_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
+    }
+    if (ne) {
+        HIPCHK(hipMemcpy(nb.data(), S.pt[cur], 4 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(st.data(), S.rec_state, ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(Fr.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(Rr.data(), S.rec_R, 24 * ne, hipMemcpyDeviceToHost));
+    }
+    // the triangle contacts in the order the caller numbers them, then
+    // Newton's third law at each contact point: the mesh receives -F, with the
+    // lever arm from its reference point
+    const uint32_t t0 = (uint32_t)(ns + S.n_bnd);
+    struct Row { uint64_t key; int64_t e; int32_t mesh; };
+    std::vector<Row> rows;
+    for (int64_t s = 0; s < ns; s++)
+        for (uint32_t k = 0; k < cnt[s]; k++) {
+            const int64_t e = (int64_t)beg[s] + k;
+            const uint32_t t = nb[e];
+            if (t < t0 || !st[e] || !(dl[e] > 0.0)) continue;
+            rows.push_back({((uint64_t)s << 32) | user_partner(sc, t), e, sc->tri_mesh[t - t0]});
+        }
+    std::sort(rows.begin(), rows.end(), [](const Row &x, const Row &y) { return x.key < y.key; });
+    std::vector<double> f(3 * nm, 0.0), tq(3 * nm, 0.0);
+    for (const Row &r : rows) {
+        const double g[3] = {-Fr[3 * r.e], -Fr[3 * r.e + 1], -Fr[3 * r.e + 2]};
+        const double *a = &Rr[3 * r.e];
+        const double x[3] = {a[1] * g[2] - a[2] * g[1], a[2] * g[0] - a[0] * g[2], a[0] * g[1] - a[1] * g[0]};
+        for (int i = 0; i < 3; i++) {
+            f[3 * r.mesh + i] = f[3 * r.mesh + i] + g[i];
+            tq[3 * r.mesh + i] = tq[3 * r.mesh + i] + x[i];
+        }
+    }
+    if (F) memcpy(F, f.data(), 24 * (size_t)nm);
+    if (T) memcpy(T, tq.data(), 24 * (size_t)nm);
+    return CDEM_OK;
+}
+
 // ---------------------------------------------------------------- checkpoints
 namespace {
 struct SaveHeader {
@@ -1525,8 +1757,8 @@ struct SaveHeader {
 constexpr char kSaveMagic[8] = {'C', 'D', 'E', 'M', 'S', 'A', 'V', '2'};
 
 size_t save_size(const DevScene &S, int64_t entries, bool mlp) {
-    return sizeof(SaveHeader) + 13 * 8 * (size_t)S.nc + 8 * (size_t)S.ns + 4 * (size_t)entries +
-           24 * (size_t)entries + (mlp ? 4 * (size_t)cdem_mlp_param_count() : 0);
+    return sizeof(SaveHeader) + 13 * 8 * (size_t)S.nc + 13 * 8 * (size_t)S.n_mesh + 8 * (size_t)S.ns +
+           4 * (size_t)entries + 24 * (size_t)entries + (mlp ? 4 * (size_t)cdem_mlp_param_count() : 0);
 }
 }  // namespace
 
@@ -1563,6 +1795,10 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
         if ((rc = state_to_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc)) != CDEM_OK) return rc;
         o += 13 * 8 * (size_t)nc;
     }
+    if (S.n_mesh) {  // the mesh states [n_mesh][13]
+        if ((rc = cdem_read_mesh_state(sc, (double *)o)) != CDEM_OK) return rc;
+        o += 13 * 8 * (size_t)S.n_mesh;
+    }
     const int cur = c.buf;
     if (S.ns) {
         HIPCHK(hipMemcpy(o, S.lo_beg[cur], 4 * S.ns, hipMemcpyDeviceToHost));
@@ -1593,7 +1829,10 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     if (E < 0 || E >= ((int64_t)1 << 32) || len != save_size(S, E, hd.has_mlp != 0))
         return fail(sc, CDEM_E_INVALID, "checkpoint size does not match its header");
     const char *p = (const char *)buf + sizeof hd;
-    const char *rows = p + 13 * 8 * (size_t)S.nc;
+    const double *mst = (const double *)(p + 13 * 8 * (size_t)S.nc);
+    for (int32_t m = 0; m < S.n_mesh; m++)
+        if (!mesh_state_ok(mst + 13 * m)) return fail(sc, CDEM_E_INVALID, "checkpoint mesh state");
+    const char *rows = p + 13 * 8 * (size_t)(S.nc + S.n_mesh);
     const uint32_t *rb = (const uint32_t *)rows, *rn = (const uint32_t *)(rows + 4 * S.ns);
     for (int64_t s = 0; s < S.ns; s++)
         if ((uint64_t)rb[s] + rn[s] > (uint64_t)E) return fail(sc, CDEM_E_INVALID, "checkpoint rows out of range");
@@ -1604,6 +1843,11 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     }
     sc->bin_factor = hd.bin_factor > 0.0 ? hd.bin_factor : 1.0;
     S.stride_cap = hd.stride_cap > 0 && hd.stride_cap <= 16384 ? hd.stride_cap : 16384;
+    for (int32_t m = 0; m < S.n_mesh; m++) mesh_set_state(sc->mesh[m], mst + 13 * m);
+    if (S.n_mesh) {  // the saved poses and velocities (cdem_set_detection sizes the margins for them)
+        HIPCHK(hipStreamSynchronize(sc->stream));
+        HIPCHK(hipMemcpy(S.mesh, sc->mesh.data(), S.n_mesh * sizeof(Mesh), hipMemcpyHostToDevice));
+    }
     if ((rc = cdem_set_detection(sc, &hd.det)) != CDEM_OK) return rc;
     if (E > S.cap && (rc = alloc_active_set(sc, E + E / 4 + 1024, false)) != CDEM_OK) return rc;
     Ctl c;

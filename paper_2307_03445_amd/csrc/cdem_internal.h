@@ -10,6 +10,7 @@
 namespace cdem {
 
 constexpr int kMaxBnd = 4096;
+constexpr int kMaxMesh = 64;
 constexpr int kNarrowBlock = 512;  // narrow-phase workgroup: eight wavefronts share one segment allocation
 constexpr int kMaxRow = 16;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
@@ -25,13 +26,26 @@ struct Bnd {
     double margin;           // extra candidate margin covering the boundary's own motion
 };
 
+// A triangle mesh as the kernels see it: a rigid boundary with prescribed
+// motion (its state advances every step) and a material.  Its triangles are
+// boundary partners ns + n_bnd + k of the spheres.
+struct Mesh {
+    double x[3], q[4], v[3], w[3];   // reference point, orientation (mesh -> world), velocity, world angular velocity
+    double e, g, mu, beta;           // (1-nu^2)/E, 2(2-nu)(1+nu)/E, mu, damping ratio of CoR
+    float ef, gf, muf, betaf;
+    double margin;                   // extra candidate margin covering the mesh's own motion
+    double rmax;                     // largest distance of a vertex from the reference point
+    int32_t scene, pad;
+};
+
 // Per-scene uniform grid (scenes never share a bin, so no pair crosses scenes).
 struct Grid {
     double ox, oy, oz;       // lower corner
     double inv;              // 1 / bin size
     int32_t nx, ny, nz, pad;
     int64_t cell0;           // first global bin id of the scene
-    int32_t bnd_beg, bnd_end;
+    int32_t bnd_beg, bnd_end;   // the scene's analytic boundaries
+    int32_t tri_beg, tri_end;   // the scene's mesh triangles
     double gx, gy, gz;       // gravity
     float pre_eps;           // slack of the FP32 prefilter: bounds its rounding of positions relative to (ox, oy, oz)
     float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
@@ -173,6 +187,13 @@ struct DevScene {
     double *rec_Ta, *rec_Tb;         // [cap][3] torque on body a / body b about its reference point
     double *rec_cF, *rec_cT;         // [nc][3]
     const Bnd *bnd;
+    // triangle meshes
+    int32_t n_mesh, pad_m;
+    int64_t n_tri;
+    Mesh *mesh;                       // [n_mesh], state advanced by k_step_end
+    const double *tri_vb;             // [n_tri][9] vertices in the mesh frame
+    const int32_t *tri_mesh;          // [n_tri]
+    double *tri_box;                  // [n_tri][6] world bounding box at the detection in progress
     Ctl *ctl;
     // big clumps
     const int32_t *big_list;         // clump ids

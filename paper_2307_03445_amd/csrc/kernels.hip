@@ -750,7 +750,10 @@ __device__ __forceinline__ uint32_t narrow_exact_rec(const NarrowSelf &n, const 
     return d2 < Sr * Sr ? r.id : ~0u;
 }
 
-// Boundary candidates of sphere s: phi < R_s + (m_s + boundary margin).
+// Boundary candidates of sphere s: phi < R_s + (m_s + boundary margin), for
+// the analytic boundaries of its scene, then the triangles of its scene's
+// meshes (a triangle whose bounding box at this detection is farther than
+// that is skipped without the distance).
 template <class Emit>
 __device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid &g, const NarrowSelf &n, Emit emit) {
     const double tnow = (double)S.ctl->step * S.h;
@@ -758,6 +761,32 @@ __device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid 
         double phi, nv[3];
         if (!bnd_distance(S.bnd[b], tnow, n.P.x, n.P.y, n.P.z, phi, nv)) continue;
         if (phi < n.P.w + ((double)n.ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
+    }
+    const double p[3] = {n.P.x, n.P.y, n.P.z};
+    for (int64_t k = g.tri_beg; k < g.tri_end; k++) {
+        const Mesh &m = S.mesh[S.tri_mesh[k]];
+        const double lim = n.P.w + ((double)n.ms + m.margin);
+        const double *bx = S.tri_box + 6 * k;
+        if (p[0] < bx[0] - lim || p[1] < bx[1] - lim || p[2] < bx[2] - lim || p[0] > bx[3] + lim ||
+            p[1] > bx[4] + lim || p[2] > bx[5] + lim)
+            continue;
+        double phi, nv[3];
+        if (tri_distance(S, k, p, phi, nv) && phi < lim) emit((uint32_t)(S.ns + S.n_bnd + k));
+    }
+}
+
+// Bounding boxes of the triangles at the detection in progress (the meshes'
+// current poses), for the narrow phase's quick rejection.
+__global__ void __launch_bounds__(256) k_tri_boxes(DevScene S) {
+    if (!due(S.ctl) || aborted(S.ctl)) return;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_tri; k += (int64_t)gridDim.x * blockDim.x) {
+        double V[9];
+        tri_world(S, k, V);
+        double *bx = S.tri_box + 6 * k;
+        for (int i = 0; i < 3; i++) {
+            bx[i] = fmin(fmin(V[i], V[3 + i]), V[6 + i]);
+            bx[3 + i] = fmax(fmax(V[i], V[3 + i]), V[6 + i]);
+        }
     }
 }
 
@@ -1475,6 +1504,23 @@ __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
     c->step++;
     c->since_det++;
     c->det_due = (S.detect_mode == 0 || (!S.overlap && c->since_det >= c->k_cur)) ? 1 : 0;
+    // meshes follow their prescribed motion: x += h v, and the orientation
+    // turns at the world angular velocity, q += (h/2) (0, w) (x) q, renormalised
+    const double h = S.h, hh = 0.5 * S.h;
+    for (int32_t k = 0; k < S.n_mesh; k++) {
+        Mesh &m = S.mesh[k];
+        for (int i = 0; i < 3; i++) m.x[i] = m.x[i] + h * m.v[i];
+        const double *w = m.w, *q = m.q;
+        double dq[4];
+        dq[0] = -(w[0] * q[1] + w[1] * q[2] + w[2] * q[3]);
+        dq[1] = q[0] * w[0] + (w[1] * q[3] - w[2] * q[2]);
+        dq[2] = q[0] * w[1] + (w[2] * q[1] - w[0] * q[3]);
+        dq[3] = q[0] * w[2] + (w[0] * q[2] - w[1] * q[1]);
+        double nq[4];
+        for (int i = 0; i < 4; i++) nq[i] = q[i] + hh * dq[i];
+        const double qn = sqrt(nq[0] * nq[0] + nq[1] * nq[1] + nq[2] * nq[2] + nq[3] * nq[3]);
+        for (int i = 0; i < 4; i++) m.q[i] = nq[i] / qn;
+    }
 }
 
 // ---------------------------------------------------------------- audit
@@ -1512,6 +1558,11 @@ __global__ void __launch_bounds__(256) k_audit_brute(DevScene S, unsigned long l
     for (int b = g.bnd_beg; b < g.bnd_end; b++) {
         double phi, n[3];
         if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) check((uint32_t)(S.ns + b));
+    }
+    const double p[3] = {P.x, P.y, P.z};
+    for (int64_t k = g.tri_beg; k < g.tri_end; k++) {
+        double phi, n[3];
+        if (tri_distance(S, k, p, phi, n) && phi < P.w) check((uint32_t)(S.ns + S.n_bnd + k));
     }
     if (found) atomicAdd(&counts[0], found);
     if (missed) atomicAdd(&counts[1], missed);
@@ -1609,6 +1660,14 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
                 if (!in_row((uint32_t)(S.ns + b))) missed++;
             }
         }
+        const double p[3] = {P.x, P.y, P.z};
+        for (int64_t k = g.tri_beg; k < g.tri_end; k++) {
+            double phi, n[3];
+            if (tri_distance(S, k, p, phi, n) && phi < P.w) {
+                found++;
+                if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
+            }
+        }
     }
     __shared__ unsigned long long sh[2][4];
     for (int off = 32; off > 0; off >>= 1) {
@@ -1655,6 +1714,7 @@ __global__ void __launch_bounds__(256) k_snap(DevScene S, DevScene B) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t k = i; k < 4 * S.nc; k += stride) B.cst[k] = S.cst[k];
     for (int64_t k = i; k < S.nc; k += stride) B.cacc[k] = S.cacc[k];
+    for (int64_t k = i; k < S.n_mesh; k += stride) B.mesh[k] = S.mesh[k];
     if (i == 0) {
         Ctl *b = B.ctl;
         const Ctl *a = S.ctl;
@@ -1880,6 +1940,7 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     if (S.ns == 0) return hipSuccess;
     TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
     binning(S, 0, st);
+    if (S.n_tri) hipLaunchKernelGGL(k_tri_boxes, dim3(stride_blocks(S.n_tri, 1024)), dim3(256), 0, st, S);
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
     TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
     TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));

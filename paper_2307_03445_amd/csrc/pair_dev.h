@@ -179,6 +179,15 @@ struct HertzMindlin {
     }
 };
 
+// What a boundary contact needs of its boundary: combined-material terms,
+// the reference point (torques, and the lever arm of its surface velocity),
+// velocity and angular velocity.
+struct WallView {
+    double e, g, mu, beta;
+    float ef, gf, muf, betaf;
+    double ref[3], vel[3], omg[3];
+};
+
 template <bool FP32, class Law>
 __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
                                               double tnow, bool rec) {
@@ -249,11 +258,28 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         }
         return 2;
     }
-    // boundary pair: the boundary is body a, sphere s is body b
-    const Bnd &B = S.bnd[t - (uint32_t)S.ns];
+    // boundary pair: the boundary is body a, sphere s is body b; an analytic
+    // boundary, or a triangle of a mesh (its mesh's reference point, motion
+    // and material)
+    const uint32_t wi = t - (uint32_t)S.ns;
+    const bool tri = wi >= (uint32_t)S.n_bnd;
     const SphereKin ks = sphere_kin_of(S, id.ca, id.ta);
     double phi, n[3];
-    bool contact = bnd_distance(B, tnow, ks.p[0], ks.p[1], ks.p[2], phi, n) && phi < ks.R;
+    WallView B;
+    bool contact;
+    if (!tri) {
+        const Bnd &b = S.bnd[wi];
+        contact = bnd_distance(b, tnow, ks.p[0], ks.p[1], ks.p[2], phi, n) && phi < ks.R;
+        B = WallView{b.e, b.g, b.mu, b.beta, b.ef, b.gf, b.muf, b.betaf,
+                     {b.p[0] + tnow * b.vel[0], b.p[1] + tnow * b.vel[1], b.p[2] + tnow * b.vel[2]},
+                     {b.vel[0], b.vel[1], b.vel[2]}, {b.omg[0], b.omg[1], b.omg[2]}};
+    } else {
+        const int64_t k = (int64_t)(wi - (uint32_t)S.n_bnd);
+        contact = tri_distance(S, k, ks.p, phi, n) && phi < ks.R;
+        const Mesh &m = S.mesh[S.tri_mesh[k]];
+        B = WallView{m.e, m.g, m.mu, m.beta, m.ef, m.gf, m.muf, m.betaf, {m.x[0], m.x[1], m.x[2]},
+                     {m.v[0], m.v[1], m.v[2]}, {m.w[0], m.w[1], m.w[2]}};
+    }
     if (!contact) {
         cS[e] = Contrib<FP32>::make(zero3, 0.0);
         if (h[0] != 0.0 || h[1] != 0.0 || h[2] != 0.0) { h[0] = 0.0; h[1] = 0.0; h[2] = 0.0; }
@@ -264,7 +290,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     double delta = R - phi;
     double lever = R - 0.5 * delta;
     double p[3] = {ks.p[0] - lever * n[0], ks.p[1] - lever * n[1], ks.p[2] - lever * n[2]};
-    double cw[3] = {B.p[0] + tnow * B.vel[0], B.p[1] + tnow * B.vel[1], B.p[2] + tnow * B.vel[2]};
+    const double *cw = B.ref;
     double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
     double rb[3] = {p[0] - ks.xc[0], p[1] - ks.xc[1], p[2] - ks.xc[2]};
     double pw[3], cb3[3];

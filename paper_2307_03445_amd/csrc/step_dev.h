@@ -148,4 +148,75 @@ __device__ __forceinline__ uint32_t xcd_block() {
     return x * per + min(x, rem) + k;
 }
 
+// ---------------------------------------------------------------- triangle meshes
+// World vertices of triangle k: x_mesh + A(q_mesh) v for each vertex.
+__device__ __forceinline__ void tri_world(const DevScene &S, int64_t k, double *V) {
+    const Mesh &M = S.mesh[S.tri_mesh[k]];
+    double A[9];
+    quat_mat(M.q[0], M.q[1], M.q[2], M.q[3], A);
+    const double *vb = S.tri_vb + 9 * k;
+    for (int j = 0; j < 3; j++) {
+        const double b0 = vb[3 * j], b1 = vb[3 * j + 1], b2 = vb[3 * j + 2];
+        V[3 * j] = M.x[0] + (A[0] * b0 + A[1] * b1 + A[2] * b2);
+        V[3 * j + 1] = M.x[1] + (A[3] * b0 + A[4] * b1 + A[5] * b2);
+        V[3 * j + 2] = M.x[2] + (A[6] * b0 + A[7] * b1 + A[8] * b2);
+    }
+}
+
+__device__ __forceinline__ double dot3d(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+// Closest point c of triangle (A, B, C) to p: the Voronoi region of a
+// vertex, an edge or the face that holds p, found from dot products of the
+// edge vectors (the region tests of Ericson, Real-Time Collision Detection,
+// Sec. 5.1.5), in a fixed order.
+__device__ __forceinline__ void closest_on_triangle(const double *A, const double *B, const double *C, const double *p,
+                                                    double *c) {
+    double ab[3], ac[3], ap[3], bp[3], cp[3];
+    for (int i = 0; i < 3; i++) { ab[i] = B[i] - A[i]; ac[i] = C[i] - A[i]; ap[i] = p[i] - A[i]; }
+    const double d1 = dot3d(ab, ap), d2 = dot3d(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) { for (int i = 0; i < 3; i++) c[i] = A[i]; return; }
+    for (int i = 0; i < 3; i++) bp[i] = p[i] - B[i];
+    const double d3 = dot3d(ab, bp), d4 = dot3d(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) { for (int i = 0; i < 3; i++) c[i] = B[i]; return; }
+    const double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        const double v = d1 / (d1 - d3);
+        for (int i = 0; i < 3; i++) c[i] = A[i] + v * ab[i];
+        return;
+    }
+    for (int i = 0; i < 3; i++) cp[i] = p[i] - C[i];
+    const double d5 = dot3d(ab, cp), d6 = dot3d(ac, cp);
+    if (d6 >= 0.0 && d5 <= d6) { for (int i = 0; i < 3; i++) c[i] = C[i]; return; }
+    const double vb = d5 * d2 - d1 * d6;
+    if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+        const double w = d2 / (d2 - d6);
+        for (int i = 0; i < 3; i++) c[i] = A[i] + w * ac[i];
+        return;
+    }
+    const double va = d3 * d6 - d5 * d4;
+    const double e43 = d4 - d3, e56 = d5 - d6;
+    if (va <= 0.0 && e43 >= 0.0 && e56 >= 0.0) {
+        const double w = e43 / (e43 + e56);
+        for (int i = 0; i < 3; i++) c[i] = B[i] + w * (C[i] - B[i]);
+        return;
+    }
+    const double den = (va + vb) + vc;
+    const double v = vb / den, w = vc / den;
+    for (int i = 0; i < 3; i++) c[i] = (A[i] + ab[i] * v) + ac[i] * w;
+}
+
+// Distance of p from triangle k (at the mesh's current pose) and the unit
+// normal from its closest point towards p; false when p lies on it.
+__device__ __forceinline__ bool tri_distance(const DevScene &S, int64_t k, const double *p, double &phi, double *n) {
+    double V[9], c[3], d[3];
+    tri_world(S, k, V);
+    closest_on_triangle(V, V + 3, V + 6, p, c);
+    for (int i = 0; i < 3; i++) d[i] = p[i] - c[i];
+    const double dd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    if (!(dd > 0.0)) return false;
+    phi = dd;
+    for (int i = 0; i < 3; i++) n[i] = d[i] / dd;
+    return true;
+}
+
 }  // namespace cdem

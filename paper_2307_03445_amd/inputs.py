@@ -56,7 +56,7 @@ DENSITY = 2600.0
 def rng(stream: int, replica: int = 0) -> np.random.Generator:
     """Generator of seed stream ``stream`` (one per workload: 1 walled box,
     2 bed templates, 4 funnels, 5 rover bed, 6 and 7 statistics scenes, 8 cone
-    bed, 9 drum) and replica."""
+    bed, 9 drum, 11 mesh bin) and replica."""
     return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(stream, replica)))
 
 
@@ -832,6 +832,61 @@ def bed_materials(g: np.random.Generator, ns: int, cor: float = 0.5) -> np.ndarr
     mat[:, 2] = g.uniform(0.3, 0.8, ns)
     mat[:, 3] = cor
     return mat
+
+
+def grid_mesh(half: float, n: int, jitter: float, g: np.random.Generator) -> np.ndarray:
+    """A square surface of side 2*half about the origin in the plane z = 0,
+    n x n cells, each split into two triangles along alternating diagonals,
+    every vertex raised by U[-jitter, jitter] (so that spheres meet faces,
+    edges and vertices).  Returns [2 n^2][3][3] vertices."""
+    t = np.linspace(-half, half, n + 1)
+    X, Y = np.meshgrid(t, t, indexing="ij")
+    Z = g.uniform(-jitter, jitter, X.shape)
+    V = np.stack([X, Y, Z], -1)
+    tris = []
+    for i in range(n):
+        for j in range(n):
+            a, b, c, d = V[i, j], V[i + 1, j], V[i + 1, j + 1], V[i, j + 1]
+            if (i + j) % 2 == 0:
+                tris += [(a, b, c), (a, c, d)]
+            else:
+                tris += [(a, b, d), (b, c, d)]
+    return np.asarray(tris, np.float64)
+
+
+def mesh_bin(replica: int = 0, n_clumps: int = 600, n_grid: int = 24, jitter: float = 5e-6, spin: float = 20.0,
+             push: float = 0.2, res: int = 32) -> SceneDesc:
+    """Clumps on triangle meshes with prescribed motion (the paper's
+    funnels and wheels are meshes).
+
+    Three-sphere clumps (radius U[1, 2] mm, as in the walled box) deposited
+    into a 5 cm x 5 cm bin with analytic side walls, onto a turntable: a
+    triangulated floor (n_grid^2 cells, vertices jittered by +-jitter) that
+    spins at ``spin`` rad/s about the vertical axis through the bin's centre
+    and extends past the corners at any angle.  A vertical plate of two
+    triangles, at the low-x side of the pile, moves into it at ``push`` m/s;
+    a third of the clumps are pressed against the plate or the opposite
+    wall.  Materials E = 1e7 Pa, nu = 0.3, mu = 0.5, CoR = 0.5; gravity
+    -9.81 z; h = 1e-6 s."""
+    g = rng(11, replica)
+    tmpls = _box_templates(g, n_clumps, res)
+    L = 0.05
+    xp = 0.004  # the plate's plane
+    x, q = deposit(g, tmpls, np.arange(n_clumps), (xp, 0.0, L, L), 2e-5, edge=(0.3, "x"))
+    top = float(x[:, 2].max()) + 0.01
+    v = g.uniform(-0.02, 0.02, (n_clumps, 3))
+    w = np.zeros((n_clumps, 3))
+    mat = np.tile(np.array(BOX_MAT), (3 * n_clumps, 1))
+    floor = grid_mesh(0.75 * L, n_grid, jitter, g)
+    hz = 0.5 * top
+    plate = np.array([[(0.0, 0.0, -hz), (0.0, L, -hz), (0.0, L, hz)],
+                      [(0.0, 0.0, -hz), (0.0, L, hz), (0.0, 0.0, hz)]])
+    plate[:, :, 1] -= 0.5 * L
+    meshes = [dict(vertices=floor, x=(0.5 * L, 0.5 * L, 0.0), w=(0.0, 0.0, spin), mat=BOX_MAT),
+              dict(vertices=plate, x=(xp, 0.5 * L, hz), v=(push, 0.0, 0.0), mat=BOX_MAT)]
+    walls = box_walls((0, 0, 0), (L, L, top), BOX_MAT, floor=False)
+    return assemble(tmpls, np.arange(n_clumps), x, q, v, w, mat, (0, 0, -9.81), (0, 0, -0.005, L, L, top), 1e-6,
+                    bnd=walls, meshes=meshes, name=f"mesh-bin-r{replica}")
 
 
 def cone_bed(replica: int = 0, n_clumps: int = 600, side: float = 0.05, shaft: float = 12e-3,

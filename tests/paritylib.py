@@ -69,10 +69,13 @@ def hertz_scale(desc, c):
     (textbook Hertz with the pair's effective modulus), used to judge pairs whose
     net force is a near-cancellation of the spring and dashpot terms."""
     R = sphere_radii(desc)
-    ns = desc.n_spheres
+    ns, nb = desc.n_spheres, desc.n_bnd
     a, b = c["a"].astype(np.int64), c["b"].astype(np.int64)
     wall = b >= ns
-    mat_b = np.where(wall[:, None], desc.bnd_mat[np.clip(b - ns, 0, max(desc.n_bnd - 1, 0))] if desc.n_bnd else 0,
+    # a wall's material: an analytic boundary's, or a triangle's mesh's
+    wmat = np.concatenate([np.asarray(desc.bnd_mat, np.float64).reshape(-1, 4),
+                           np.asarray(desc.mesh_mat, np.float64).reshape(-1, 4)[np.asarray(desc.tri_mesh, np.int64)]])
+    mat_b = np.where(wall[:, None], wmat[np.clip(b - ns, 0, max(len(wmat) - 1, 0))] if len(wmat) else 0,
                      desc.sphere_mat[np.minimum(b, ns - 1)])
     mat_a = desc.sphere_mat[a]
     es = 1.0 / ((1 - mat_a[:, 1] ** 2) / mat_a[:, 0] + (1 - mat_b[:, 1] ** 2) / mat_b[:, 0])

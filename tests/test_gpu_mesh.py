@@ -1,0 +1,167 @@
+"""Triangle-mesh boundaries on the GPU against the oracle (rigid meshes with
+prescribed motion, the paper's funnels and wheels, Sec. 4; co-simulation
+with a multibody solver, Sec. 5.2).
+
+The workload is a bin of three-sphere clumps on a spinning, jittered
+triangulated floor with a plate of two triangles pushing into the pile
+(face, edge and vertex contacts; both translation and rotation of meshes).
+In FP64 the GPU performs the oracle's IEEE operations in the oracle's order,
+so contacts, forces, torques, mesh forces, clump states and mesh states are
+bit-identical, in plain and deferred detection alike (a complete active set
+gives the same forces whenever it was built); FP32 forces are held to the
+per-pair tolerance of the other parity tests."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2307_03445_amd import inputs as I
+from paritylib import STATE_TOL, check_pair_forces, compare_pairs, state_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mbin():
+    return I.mesh_bin()
+
+
+def _scene(desc, prec="fp64", mode="plain", overlap=False, audit=0):
+    from paper_2307_03445_amd._lib import Scene
+    sc = Scene(desc, precision=prec)
+    if mode != "plain":
+        sc.set_detection(mode, k_max=20, safety=1.5, margin_cap=1e-4, audit_period=audit, overlap=overlap)
+    return sc
+
+
+def _kinds(desc, c):
+    b = c["b"].astype(np.int64)
+    ns, nb = desc.n_spheres, desc.n_bnd
+    return dict(sphere=int((b < ns).sum()), wall=int(((b >= ns) & (b < ns + nb)).sum()),
+                tri=int((b >= ns + nb).sum()), plate=int((b >= ns + nb + desc.n_tri - 2).sum()))
+
+
+def _assert_bitwise(sc, o):
+    sg, so = sc.state(), o.state()
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(sg[k], so[k]), k
+    assert np.array_equal(sc.mesh_state(), o.mesh_state())
+
+
+def _assert_step_bitwise(sc, o, desc):
+    sc.record_next_step()
+    sc.step(1)
+    o.eval()
+    cg, co = sc.contacts(), o.contacts()
+    compare_pairs(cg, co)
+    for k in ("delta", "F", "u", "Ta", "Tb"):
+        assert np.array_equal(cg[k], co[k]), k
+    Fg, Tg = sc.mesh_forces()
+    Fo, To = o.mesh_forces()
+    assert np.array_equal(Fg, Fo) and np.array_equal(Tg, To)
+    Fg, Tg = sc.clump_forces()
+    Fo, To = o.clump_forces()
+    assert np.array_equal(Fg, Fo) and np.array_equal(Tg, To)
+    o.step(1)
+    return cg
+
+
+def test_first_step_bitwise(mbin):
+    sc, o = _scene(mbin), oracle.Oracle(mbin)
+    cg = _assert_step_bitwise(sc, o, mbin)
+    kinds = _kinds(mbin, cg)
+    print(kinds)
+    assert kinds["tri"] > 50 and kinds["plate"] > 20 and kinds["sphere"] > 200
+    _assert_bitwise(sc, o)
+
+
+@pytest.mark.parametrize("mode,overlap", [("plain", False), ("fixed", False), ("fixed", True)])
+def test_steps_bitwise(mbin, mode, overlap):
+    """300 steps: the spinning floor turns and the plate advances; clump and
+    mesh states, then a recorded step's contacts and mesh forces, are
+    bit-identical to the oracle's."""
+    sc, o = _scene(mbin, mode=mode, overlap=overlap, audit=25), oracle.Oracle(mbin)
+    sc.step(300)
+    o.step(300)
+    _assert_bitwise(sc, o)
+    cg = _assert_step_bitwise(sc, o, mbin)
+    assert _kinds(mbin, cg)["plate"] > 20
+    if mode != "plain":
+        c = sc.counts()
+        assert c["missed"] == 0 and c["audits"] > 0
+        assert c["detections"] < 100, c
+
+
+def test_fp32_forces_and_states(mbin):
+    sc, o = _scene(mbin, "fp32"), oracle.Oracle(mbin)
+    sc.record_next_step()
+    sc.step(1)
+    o.eval()
+    cg, co = sc.contacts(), o.contacts()
+    compare_pairs(cg, co)
+    print(check_pair_forces(cg, co, mbin))
+    o.step(1)
+    sc.step(99)
+    o.step(99)
+    err = state_errors(sc.state(), o.state(), mbin.tmpl_radius.min())
+    assert max(err.values()) <= STATE_TOL, err
+    # the meshes' motion is prescribed: it does not depend on the force precision
+    assert np.array_equal(sc.mesh_state(), o.mesh_state())
+
+
+@pytest.mark.parametrize("mode,overlap", [("plain", False), ("fixed", False), ("fixed", True)])
+def test_cosimulation_exchanges(mbin, mode, overlap):
+    """A multibody solver drives the plate: every 60 steps it reads the force
+    on the plate and prescribes the plate's next state, slower (the active
+    set is kept), faster, and moved to a new pose (both detect again).  The
+    oracle receives the same states at the same steps: bit-identical."""
+    sc, o = _scene(mbin, mode=mode, overlap=overlap, audit=20), oracle.Oracle(mbin)
+    plate = 1
+    forces = []
+    for k, change in enumerate(["slower", "faster", "pose", "spin"]):
+        sc.step(59)
+        o.step(59)
+        cg = _assert_step_bitwise(sc, o, mbin)
+        assert len(cg["a"])
+        F, _ = sc.mesh_forces()
+        forces.append(F[plate].copy())
+        st = sc.mesh_state()[plate].copy()
+        assert np.array_equal(st, o.mesh_state()[plate])
+        if change == "slower":
+            st[7:10] *= 0.5
+        elif change == "faster":
+            st[7:10] = (0.6, 0.0, 0.0)
+        elif change == "pose":
+            st[0] += 2e-5
+            st[3:7] = (np.cos(0.01), 0.0, 0.0, np.sin(0.01))
+        else:
+            st[10:13] = (0.0, 0.0, 1.5)
+        sc.set_mesh_state(plate, st)
+        o.set_mesh_state(plate, st)
+    sc.step(80)
+    o.step(80)
+    _assert_bitwise(sc, o)
+    _assert_step_bitwise(sc, o, mbin)
+    assert all(F[0] < 0 for F in forces)  # the pile pushes back on the plate
+    if mode != "plain":
+        assert sc.counts()["missed"] == 0
+
+
+def test_checkpoint_restores_meshes(mbin):
+    from paper_2307_03445_amd._lib import Scene
+    a = _scene(mbin, mode="fixed")
+    a.step(73)
+    blob = a.save()
+    a.step(60)
+    b = Scene(mbin)
+    b.load(blob)
+    b.step(60)
+    for k in ("x", "q", "v", "w"):
+        assert np.array_equal(a.state()[k], b.state()[k]), k
+    assert np.array_equal(a.mesh_state(), b.mesh_state())
+
+
+def test_exhaustive_audit_covers_triangles(mbin):
+    sc = _scene(mbin, mode="fixed")
+    sc.step(40)
+    r = sc.audit()
+    assert r["missed"] == 0 and r["true_contacts"] > 500, r

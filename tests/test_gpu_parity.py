@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(_lib.SIGNATURES) == names
-    assert L.cdem_abi_version() == 2
+    assert L.cdem_abi_version() == 3
 
 
 gpu = pytest.mark.gpu
