@@ -216,7 +216,8 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
 
 
 KERNEL_SOURCES = ("paper_2307_03445_amd/csrc/kernels.hip", "paper_2307_03445_amd/csrc/cdem_internal.h",
-                  "paper_2307_03445_amd/csrc/mlp_dev.h")
+                  "paper_2307_03445_amd/csrc/mlp_dev.h", "paper_2307_03445_amd/csrc/step_dev.h",
+                  "paper_2307_03445_amd/csrc/pair_dev.h")
 COUNTERS = os.path.join(ROOT, "profiles", "counters_rover_bed.json")
 
 
