@@ -56,6 +56,7 @@ class _Desc(C.Structure):
         ("mesh_state", C.c_void_p), ("mesh_mat", C.c_void_p), ("mesh_scene", C.c_void_p),
         ("n_tri", C.c_int64),
         ("tri_mesh", C.c_void_p), ("tri_vertex", C.c_void_p),
+        ("pos_exp", C.c_int32),
     ]
 
 
@@ -73,6 +74,7 @@ def lib():
             "dem_oracle_create": (P, [P]), "dem_oracle_destroy": (V, [P]),
             "dem_oracle_last_error": (C.c_char_p, []), "dem_oracle_set_threads": (V, [C.c_int]),
             "dem_oracle_step": (V, [P, I64]), "dem_oracle_step_count": (I64, [P]),
+            "dem_oracle_positions_ok": (C.c_int, [P]), "dem_oracle_read_fixed_positions": (V, [P, P]),
             "dem_oracle_eval": (I64, [P]),
             "dem_oracle_read_contacts": (V, [P, P, P, P, P, P]),
             "dem_oracle_read_contact_torques": (V, [P, P, P]),
@@ -129,6 +131,7 @@ class Oracle:
         s.n_mesh, s.n_tri = d.n_mesh, d.n_tri
         s.mesh_state, s.mesh_mat, s.mesh_scene = _ptr(d.mesh_state), _ptr(d.mesh_mat), _ptr(d.mesh_scene)
         s.tri_mesh, s.tri_vertex = _ptr(d.tri_mesh), _ptr(d.tri_vertex)
+        s.pos_exp = d.pos_exp
         self._h = lib().dem_oracle_create(C.byref(s))
         if not self._h:
             raise ValueError(lib().dem_oracle_last_error().decode())
@@ -147,6 +150,14 @@ class Oracle:
     def step(self, n: int = 1) -> None:
         lib().dem_oracle_step(self._h, int(n))
         self._ncont = -1
+        if not lib().dem_oracle_positions_ok(self._h):
+            raise OverflowError("a fixed-point position left its range")
+
+    def fixed_positions(self) -> np.ndarray:
+        """The fixed-point CoM integers [n_clumps][3] (fixed-point positions only)."""
+        k = np.empty((self.n_clumps, 3), np.int64)
+        lib().dem_oracle_read_fixed_positions(self._h, _ptr(k))
+        return k
 
     @property
     def step_count(self) -> int:

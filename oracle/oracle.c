@@ -31,6 +31,16 @@
  *      the gyroscopic term; q += (h/2) q (x) (0, w_body), renormalised;
  *   8. meshes follow their prescribed velocities: x += h v,
  *      q += (h/2) (0, w) (x) q (world-frame w), renormalised.
+ *
+ * Fixed-point positions (pos_exp = E > 0; a state representation beyond
+ * IEEE double, Sec. 3 and the data types Sec. 1 builds on): a clump's CoM is
+ * an integer k per axis, x = k 2^-E.  The vector between two spheres of
+ * different clumps is (k_b - k_a) 2^-E, exact, plus the difference of their
+ * rotated offsets A o; a lever arm from a CoM is the sphere's rotated offset
+ * plus its part of the contact normal, never a difference of world
+ * coordinates; and step 7 adds the position increment rounded to the grid,
+ * k += rint(h v 2^E).  Distances to boundaries and meshes stay in FP64 world
+ * coordinates (x = k 2^-E converted to double).
  */
 #include "oracle.h"
 
@@ -53,8 +63,14 @@ struct dem_oracle {
     int64_t step;
     int64_t nc, ns;
     int32_t nsc, nb;
-    /* clump state and static data */
+    /* clump state and static data (x: the CoM in FP64; with fixed-point
+     * positions its decoded value, the state being xq) */
     double *x, *q, *v, *w;
+    int32_t pos_exp;        /* 0, or E of the fixed-point positions x = xq 2^-E */
+    double eps;             /* 2^-E */
+    int64_t *xq;            /* [nc][3] fixed-point CoM */
+    double *xr;             /* [ns][3] rotated sphere offsets A o_s (this step) */
+    int bad_pos;            /* a fixed-point position left its range */
     double *mass, *inertia; /* per clump */
     uint32_t *scene;        /* per clump */
     int64_t *sbeg;          /* [nc+1] sphere range per clump */
@@ -135,6 +151,27 @@ dem_oracle *dem_oracle_create(const dem_oracle_desc *d) {
     }
     int64_t ns = o->ns = o->sbeg[nc];
     o->x = dup_d(d->x, 3 * nc);
+    o->pos_exp = d->pos_exp;
+    if (o->pos_exp != 0 && (o->pos_exp < 8 || o->pos_exp > 60)) {
+        set_err("position exponent must be 0 or in [8, 60]");
+        dem_oracle_destroy(o);
+        return NULL;
+    }
+    o->eps = ldexp(1.0, -o->pos_exp);
+    o->xq = (int64_t *)xmalloc(3 * (nc ? nc : 1) * sizeof(int64_t));
+    o->xr = (double *)xmalloc(3 * (ns ? ns : 1) * sizeof(double));
+    if (o->pos_exp) {
+        for (int64_t k = 0; k < 3 * nc; k++) {
+            double u = ldexp(d->x[k], o->pos_exp);  /* exact: a power-of-two scaling */
+            if (!(fabs(u) < ldexp(1.0, 60))) {
+                set_err("position outside the fixed-point range");
+                dem_oracle_destroy(o);
+                return NULL;
+            }
+            o->xq[k] = (int64_t)rint(u);
+            o->x[k] = ldexp((double)o->xq[k], -o->pos_exp);
+        }
+    }
     o->q = dup_d(d->q, 4 * nc);
     o->v = dup_d(d->v, 3 * nc);
     o->w = dup_d(d->w, 3 * nc);
@@ -254,12 +291,16 @@ void dem_oracle_destroy(dem_oracle *o) {
                     o->btype, o->bscene, o->bparam, o->bvel, o->bomega, o->be, o->bg, o->bmu,
                     o->bbeta, o->grav, o->hkey, o->hu, o->A, o->ww, o->xs, o->ckey, o->cdelta,
                     o->cF, o->cu, o->cra, o->crb, o->sF, o->sT, o->cFc, o->cTc, o->lo_beg, o->lo_idx,
-                    o->mx, o->mq, o->mv, o->mw, o->tmesh, o->tvb, o->tv};
+                    o->mx, o->mq, o->mv, o->mw, o->tmesh, o->tvb, o->tv, o->xq, o->xr};
     for (size_t i = 0; i < sizeof ptrs / sizeof ptrs[0]; i++) free(ptrs[i]);
     free(o);
 }
 
 int64_t dem_oracle_step_count(const dem_oracle *o) { return o->step; }
+int dem_oracle_positions_ok(const dem_oracle *o) { return !o->bad_pos; }
+void dem_oracle_read_fixed_positions(const dem_oracle *o, int64_t *k) {
+    for (int64_t i = 0; i < 3 * o->nc; i++) k[i] = o->pos_exp ? o->xq[i] : 0;
+}
 int64_t dem_oracle_n_spheres(const dem_oracle *o) { return o->ns; }
 
 /* ---------------- kinematics of the current state ---------------- */
@@ -288,8 +329,10 @@ static void compute_poses(dem_oracle *o) {
         for (int i = 0; i < 3; i++) o->ww[3 * c + i] = A[3 * i] * wb[0] + A[3 * i + 1] * wb[1] + A[3 * i + 2] * wb[2];
         for (int64_t s = o->sbeg[c]; s < o->sbeg[c + 1]; s++) {
             const double *of = o->ofs + 3 * s;
-            for (int i = 0; i < 3; i++)
-                o->xs[3 * s + i] = o->x[3 * c + i] + (A[3 * i] * of[0] + A[3 * i + 1] * of[1] + A[3 * i + 2] * of[2]);
+            for (int i = 0; i < 3; i++) {
+                o->xr[3 * s + i] = A[3 * i] * of[0] + A[3 * i + 1] * of[1] + A[3 * i + 2] * of[2];
+                o->xs[3 * s + i] = o->x[3 * c + i] + o->xr[3 * s + i];
+            }
         }
     }
     /* triangle vertices in the world: x_mesh + A(q_mesh) v */
@@ -497,6 +540,22 @@ static int64_t find_history(const dem_oracle *o, uint64_t key) {
     return (lo < o->nh && o->hkey[lo] == key) ? lo : -1;
 }
 
+/* Vector from sphere a to sphere b, and (fixed-point positions) the CoM
+ * difference dc = x_cb - x_ca it contains: the world difference of the two
+ * centres, or the exact integer difference of the CoMs plus the difference
+ * of the rotated offsets. */
+static void sphere_vec(const dem_oracle *o, int64_t a, int64_t b, double *dx, double *dc) {
+    if (!o->pos_exp) {
+        for (int i = 0; i < 3; i++) dx[i] = o->xs[3 * b + i] - o->xs[3 * a + i];
+        return;
+    }
+    uint32_t ca = o->owner[a], cb = o->owner[b];
+    for (int i = 0; i < 3; i++) {
+        dc[i] = (double)(o->xq[3 * cb + i] - o->xq[3 * ca + i]) * o->eps;
+        dx[i] = dc[i] + (o->xr[3 * b + i] - o->xr[3 * a + i]);
+    }
+}
+
 /* ---------------- contact set (brute force) ---------------- */
 
 /* Count (pass 0) or write (pass 1) the enlarged-geometry pairs of row a. */
@@ -510,9 +569,9 @@ static int64_t row_pairs(const dem_oracle *o, int64_t a, double t, const double 
     for (int64_t b = a + 1; b < o->ns; b++) {
         uint32_t cb = o->owner[b];
         if (cb == ca || o->scene[cb] != sa) continue;
-        const double *xb = o->xs + 3 * b;
-        double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
-        double d2 = dx * dx + dy * dy + dz * dz;
+        double v[3], dc[3];
+        sphere_vec(o, a, b, v, dc);
+        double d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         double S = o->rad[a] + o->rad[b];
         if (margin) S = S + (ma + margin[b]);
         if (d2 < S * S) {
@@ -559,17 +618,21 @@ static double pair_eval(const dem_oracle *o, int64_t a, int64_t b, double t, con
     double n[3], delta, p[3], vrel[3];
     double Rbar, mbar, estar, gstar, mu, beta;
     if (b < ns) {
-        const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
+        const double *xa = o->xs + 3 * a;
         double Ra = o->rad[a], Rb = o->rad[b];
         uint32_t ca = o->owner[a], cb = o->owner[b];
-        double dx[3];
-        for (int i = 0; i < 3; i++) dx[i] = xb[i] - xa[i];
+        double dx[3], dc[3];
+        sphere_vec(o, a, b, dx, dc);
         double d = sqrt(dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2]);
         delta = (Ra + Rb) - d;
         for (int i = 0; i < 3; i++) n[i] = dx[i] / d;
         double lever = Ra - 0.5 * delta;
-        for (int i = 0; i < 3; i++) p[i] = xa[i] + lever * n[i];
-        for (int i = 0; i < 3; i++) { ra[i] = p[i] - o->x[3 * ca + i]; rb[i] = p[i] - o->x[3 * cb + i]; }
+        if (!o->pos_exp) {
+            for (int i = 0; i < 3; i++) p[i] = xa[i] + lever * n[i];
+            for (int i = 0; i < 3; i++) { ra[i] = p[i] - o->x[3 * ca + i]; rb[i] = p[i] - o->x[3 * cb + i]; }
+        } else {  /* from the CoM of a: its offset, then along n; from b's: less dc */
+            for (int i = 0; i < 3; i++) { ra[i] = o->xr[3 * a + i] + lever * n[i]; rb[i] = ra[i] - dc[i]; }
+        }
         double wa[3], wb[3];
         cross(o->ww + 3 * ca, ra, wa);
         cross(o->ww + 3 * cb, rb, wb);
@@ -608,7 +671,10 @@ static double pair_eval(const dem_oracle *o, int64_t a, int64_t b, double t, con
             om = o->mw + 3 * m;
             for (int i = 0; i < 3; i++) cwall[i] = o->mx[3 * m + i];
         }
-        for (int i = 0; i < 3; i++) { ra[i] = p[i] - cwall[i]; rb[i] = p[i] - o->x[3 * cs + i]; }
+        for (int i = 0; i < 3; i++) {
+            ra[i] = p[i] - cwall[i];
+            rb[i] = o->pos_exp ? o->xr[3 * s + i] - lever * n[i] : p[i] - o->x[3 * cs + i];
+        }
         cross(om, ra, pw);
         double wb[3];
         cross(o->ww + 3 * cs, rb, wb);
@@ -733,6 +799,26 @@ int64_t dem_oracle_eval(dem_oracle *o) {
 
 /* ---------------- integration ---------------- */
 
+/* x += h v; with fixed-point positions the increment h v is rounded to the
+ * grid (ties to even) and added to the integer, then decoded. */
+static void advance_position(dem_oracle *o, int64_t c, double *x, const double *v) {
+    double h = o->h;
+    if (!o->pos_exp) {
+        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        return;
+    }
+    int64_t *k = o->xq + 3 * c;
+    for (int i = 0; i < 3; i++) {
+        double u = rint(ldexp(h * v[i], o->pos_exp));
+        if (!(fabs(u) < ldexp(1.0, 61)) || llabs(k[i]) >= ((int64_t)1 << 61)) {
+            o->bad_pos = 1;
+            continue;
+        }
+        k[i] = k[i] + (int64_t)u;
+        x[i] = ldexp((double)k[i], -o->pos_exp);
+    }
+}
+
 static void integrate(dem_oracle *o) {
     int64_t nc = o->nc;
     double h = o->h;
@@ -745,7 +831,7 @@ static void integrate(dem_oracle *o) {
         int32_t pi = o->presc[c];
         if (pi < 0) {
             for (int i = 0; i < 3; i++) v[i] = v[i] + h * (F[i] / M);
-            for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+            advance_position(o, c, x, v);
             /* body-frame torque and Euler's equations with the gyroscopic term */
             double tb[3];
             for (int i = 0; i < 3; i++) tb[i] = A[i] * T[0] + A[3 + i] * T[1] + A[6 + i] * T[2];
@@ -759,7 +845,7 @@ static void integrate(dem_oracle *o) {
                 if (P[3 + i] != 0.0) v[i] = v[i] + h * ((F[i] + P[9 + i]) / M);
                 else v[i] = P[i];
             }
-            for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+            advance_position(o, c, x, v);
             for (int i = 0; i < 3; i++) w[i] = P[6 + i];
         }
         /* q <- q + (h/2) q (x) (0, w), then renormalise */
@@ -953,9 +1039,9 @@ static void sphere_sample(const dem_oracle *o, int64_t s, double t, double *Fs, 
             a = s < p ? s : p;
             b = s < p ? p : s;
             /* the exact predicate of the contact set, evaluated from the lower sphere */
-            const double *xa = o->xs + 3 * a, *xb = o->xs + 3 * b;
-            double dx = xb[0] - xa[0], dy = xb[1] - xa[1], dz = xb[2] - xa[2];
-            double d2 = dx * dx + dy * dy + dz * dz;
+            double v[3], dc[3];
+            sphere_vec(o, a, b, v, dc);
+            double d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
             double S = o->rad[a] + o->rad[b];
             if (!(d2 < S * S)) continue;
             uint32_t cp = o->owner[p];

@@ -69,6 +69,11 @@ typedef struct dem_oracle_desc {
     int64_t n_tri;
     const int32_t *tri_mesh;           /* [n_tri] */
     const double *tri_vertex;          /* [n_tri][3][3] vertices in the mesh frame */
+    /* clump positions: 0 = FP64; E in [8, 60] = fixed point, x = k 2^-E with
+     * an integer k per axis (the voxel id k >> 32 and the sub-voxel offset
+     * k mod 2^32 of a voxel of side 2^(32-E)), so that the vector between
+     * two spheres is an exact integer difference plus their rotated offsets */
+    int32_t pos_exp;
 } dem_oracle_desc;
 
 /* Returns NULL on invalid input (message via dem_oracle_last_error). */
@@ -81,6 +86,10 @@ void dem_oracle_set_threads(int n);
  * tangential history and integrates. */
 void dem_oracle_step(dem_oracle *o, int64_t n);
 int64_t dem_oracle_step_count(const dem_oracle *o);
+/* 0 once a fixed-point position has left its range (|k| >= 2^61). */
+int dem_oracle_positions_ok(const dem_oracle *o);
+/* The fixed-point CoM integers [n_clumps][3] (zeros with FP64 positions). */
+void dem_oracle_read_fixed_positions(const dem_oracle *o, int64_t *k);
 
 /* Evaluate contacts and forces at the current state without advancing and
  * without committing history.  Returns the number of contacts (sphere-sphere

@@ -93,6 +93,8 @@ class SceneDesc:
     mesh_scene: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     tri_mesh: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
     tri_vertex: np.ndarray = field(default_factory=lambda: np.zeros((0, 3, 3)))  # mesh frame
+    # clump positions: 0 FP64, else fixed point with resolution 2^-pos_exp m
+    pos_exp: int = 0
     name: str = "scene"
 
     # ---- derived sizes -------------------------------------------------
@@ -161,6 +163,7 @@ class SceneDesc:
             mesh_scene=np.ascontiguousarray(self.mesh_scene, np.int32),
             tri_mesh=np.ascontiguousarray(self.tri_mesh, np.int32),
             tri_vertex=f(self.tri_vertex, (self.n_tri, 3, 3)),
+            pos_exp=int(self.pos_exp),
         )
 
     def validate(self) -> None:
