@@ -120,6 +120,18 @@ typedef struct cdem_scene_desc {
     int64_t n_tri;                     /* n_spheres + n_bnd + n_tri < 2^31 */
     const int32_t *tri_mesh;           /* [n_tri] */
     const double *tri_vertex;          /* [n_tri][3][3] vertices in the mesh frame (about x) */
+    /* Clump positions (a state representation beyond IEEE double, Sec. 3;
+     * the data types of the work Sec. 1 builds on): 0 = FP64; E in [8, 60]
+     * = fixed point, each CoM coordinate an integer k with x = k 2^-E (the
+     * high 32 bits of k a voxel id, the low 32 bits the offset inside a voxel
+     * of side 2^(32-E) m).  The vector between two spheres is then the exact
+     * difference of their integers plus their rotated offsets, so its
+     * accuracy does not depend on where the scene lies; lever arms are built
+     * from rotated offsets; x += h v adds rint(h v 2^E).  Boundary and mesh
+     * distances use world coordinates k 2^-E.  Initial CoMs and domains
+     * must lie within 2^60 grid steps of the origin; a CoM leaving 2^61 steps
+     * makes cdem_step fail with CDEM_E_NAN. */
+    int32_t pos_exp;
 } cdem_scene_desc;
 
 /* Optional device allocator (e.g. a framework's caching allocator).  NULL

@@ -36,6 +36,7 @@ class SceneDescC(C.Structure):
         ("n_presc", C.c_int32), ("presc_clump", P), ("presc_param", P),
         ("n_mesh", C.c_int32), ("mesh_state", P), ("mesh_mat", P), ("mesh_scene", P),
         ("n_tri", C.c_int64), ("tri_mesh", P), ("tri_vertex", P),
+        ("pos_exp", C.c_int32),
     ]
 
 
@@ -204,6 +205,7 @@ class Scene:
         s.n_mesh, s.mesh_state, s.mesh_mat = d.n_mesh, _ptr(d.mesh_state), _ptr(d.mesh_mat)
         s.mesh_scene, s.n_tri = _ptr(d.mesh_scene), d.n_tri
         s.tri_mesh, s.tri_vertex = _ptr(d.tri_mesh), _ptr(d.tri_vertex)
+        s.pos_exp = d.pos_exp
         self.n_mesh = d.n_mesh
         self._alloc = None
         self._stream = stream

@@ -28,7 +28,7 @@ using namespace cdem;
 
 namespace cdem {
 hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack,
-                             hipStream_t st);
+                             hipStream_t st, int raw = 0);
 }
 
 // Event pool for per-kernel timing (read after the stream is synchronised).
@@ -188,6 +188,7 @@ static uint64_t desc_fingerprint(const cdem_scene_desc *d, int64_t ns) {
         h = fnv1a(h, d->mesh_mat, 32 * (size_t)d->n_mesh);
         h = fnv1a(h, d->mesh_scene, 4 * (size_t)d->n_mesh);
     }
+    h = fnv1a(h, &d->pos_exp, 4);
     h = fnv1a(h, &d->n_tri, 8);
     if (d->n_tri) {
         h = fnv1a(h, d->tri_mesh, 4 * (size_t)d->n_tri);
@@ -613,6 +614,15 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     int64_t ns = sbeg[nc];
     if (ns >= ((int64_t)1 << 31) - kMaxBnd) return invalid("too many spheres");
     if (!finite_all(d->x, 3 * nc) || !finite_all(d->v, 3 * nc) || !finite_all(d->w, 3 * nc)) return invalid("state");
+    if (d->pos_exp != 0 && (d->pos_exp < 8 || d->pos_exp > 60)) return invalid("position exponent must be 0 or in [8, 60]");
+    if (d->pos_exp) {  // fixed-point positions: CoMs and domains within 2^60 grid steps of the origin
+        for (int64_t k = 0; k < 3 * nc; k++)
+            if (!(std::fabs(std::ldexp(d->x[k], d->pos_exp)) < std::ldexp(1.0, 60)))
+                return invalid("position outside the fixed-point range");
+        for (int64_t k = 0; k < 6 * (int64_t)d->n_scenes; k++)
+            if (!(std::fabs(std::ldexp(d->domain[k], d->pos_exp)) < std::ldexp(1.0, 60)))
+                return invalid("domain outside the fixed-point range");
+    }
     for (int64_t s = 0; s < ns; s++) {
         const double *m = d->sphere_mat + 4 * s;
         if (!(m[0] > 0) || !(m[1] > -1 && m[1] < 0.5) || !(m[2] >= 0) || !(m[3] > 0 && m[3] <= 1))
@@ -657,6 +667,9 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     DevScene &S = sc->S;
     S.nc = nc; S.ns = ns; S.n_scenes = d->n_scenes; S.n_bnd = d->n_bnd;
     S.precision = d->precision; S.detect_mode = CDEM_DETECT_PLAIN; S.h = d->h;
+    S.pos_exp = d->pos_exp;
+    S.pos_eps = std::ldexp(1.0, -d->pos_exp);
+    S.pos_inv = std::ldexp(1.0, d->pos_exp);
     sc->det.mode = CDEM_DETECT_PLAIN; sc->det.k_max = 1; sc->det.safety = 1.5; sc->det.margin_cap = 0.0;
     sc->det.audit_period = 0;
     std::vector<uint32_t> owner(ns), sscene(ns);
@@ -831,7 +844,13 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
                 const int64_t c = c0 + k;
                 const uint32_t t = d->clump_template[c];
                 const double *x = d->x + 3 * c, *q = d->q + 4 * c, *v = d->v + 3 * c, *w = d->w + 3 * c;
-                rec[4 * k + 0] = make_double4(x[0], x[1], x[2], d->tmpl_mass[t]);
+                double xe[3] = {x[0], x[1], x[2]};
+                if (d->pos_exp)  // the integer k = rint(x 2^E), stored bit for bit
+                    for (int i = 0; i < 3; i++) {
+                        const long long kq = (long long)std::rint(std::ldexp(x[i], d->pos_exp));
+                        memcpy(&xe[i], &kq, 8);
+                    }
+                rec[4 * k + 0] = make_double4(xe[0], xe[1], xe[2], d->tmpl_mass[t]);
                 rec[4 * k + 1] = make_double4(v[0], v[1], v[2], r_acc[t]);
                 rec[4 * k + 2] = make_double4(q[0], q[1], q[2], q[3]);
                 rec[4 * k + 3] = make_double4(w[0], w[1], w[2], r_ctr[t]);
@@ -1227,14 +1246,15 @@ extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
 
 // The clump state as row-major host arrays x [nc][3], q [nc][4], v [nc][3],
 // w [nc][3] (any may be null), through a device staging buffer.
-static int state_to_host(cdem_scene *sc, double *x, double *q, double *v, double *w) {
+// raw: with fixed-point positions, the integers bit for bit (checkpoints)
+static int state_to_host(cdem_scene *sc, double *x, double *q, double *v, double *w, bool raw = false) {
     const DevScene &S = sc->S;
     const int64_t nc = S.nc;
     if (nc == 0) return CDEM_OK;
     double *stage = (double *)dev_alloc(sc, 13 * 8 * (size_t)nc);
     if (!stage) return fail(sc, CDEM_E_OOM, "state staging buffer");
     double *dx = stage, *dq = stage + 3 * nc, *dv = stage + 7 * nc, *dw = stage + 10 * nc;
-    hipError_t e = launch_pack_state(S, dx, dq, dv, dw, 0, sc->stream);
+    hipError_t e = launch_pack_state(S, dx, dq, dv, dw, 0, sc->stream, raw ? 1 : 0);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     double *dst[4] = {x, q, v, w}, *src[4] = {dx, dq, dv, dw};
     const int width[4] = {3, 4, 3, 3};
@@ -1245,7 +1265,8 @@ static int state_to_host(cdem_scene *sc, double *x, double *q, double *v, double
     return CDEM_OK;
 }
 
-static int state_from_host(cdem_scene *sc, const double *x, const double *q, const double *v, const double *w) {
+static int state_from_host(cdem_scene *sc, const double *x, const double *q, const double *v, const double *w,
+                           bool raw = false) {
     const DevScene &S = sc->S;
     const int64_t nc = S.nc;
     if (nc == 0) return CDEM_OK;
@@ -1259,7 +1280,8 @@ static int state_from_host(cdem_scene *sc, const double *x, const double *q, con
     for (int a = 0; a < 4 && e == hipSuccess; a++)
         if (src[a]) e = hipMemcpy(dst[a], src[a], 8 * width[a] * (size_t)nc, hipMemcpyHostToDevice);
     if (e == hipSuccess)
-        e = launch_pack_state(S, x ? dx : nullptr, q ? dq : nullptr, v ? dv : nullptr, w ? dw : nullptr, 1, sc->stream);
+        e = launch_pack_state(S, x ? dx : nullptr, q ? dq : nullptr, v ? dv : nullptr, w ? dw : nullptr, 1, sc->stream,
+                              raw ? 1 : 0);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     dev_free(sc, stage);
     if (e != hipSuccess) return fail(sc, CDEM_E_HIP, hipGetErrorString(e));
@@ -1792,7 +1814,7 @@ extern "C" int cdem_save(cdem_scene *sc, void *buf, size_t cap, size_t *len) {
     {  // the clump state: x [nc][3], q [nc][4], v [nc][3], w [nc][3]
         double *st = (double *)o;
         const int64_t nc = S.nc;
-        if ((rc = state_to_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc)) != CDEM_OK) return rc;
+        if ((rc = state_to_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc, true)) != CDEM_OK) return rc;
         o += 13 * 8 * (size_t)nc;
     }
     if (S.n_mesh) {  // the mesh states [n_mesh][13]
@@ -1856,7 +1878,7 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     {
         const double *st = (const double *)p;
         const int64_t nc = S.nc;
-        if ((rc = state_from_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc)) != CDEM_OK) return rc;
+        if ((rc = state_from_host(sc, st, st + 3 * nc, st + 7 * nc, st + 10 * nc, true)) != CDEM_OK) return rc;
     }
     if (S.ns) {
         HIPCHK(hipMemcpy(S.lo_beg[cur], rb, 4 * S.ns, hipMemcpyHostToDevice));

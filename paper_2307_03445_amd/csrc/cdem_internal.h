@@ -187,6 +187,9 @@ struct DevScene {
     double *rec_Ta, *rec_Tb;         // [cap][3] torque on body a / body b about its reference point
     double *rec_cF, *rec_cT;         // [nc][3]
     const Bnd *bnd;
+    // fixed-point clump positions: 0, or E with x = k 2^-E (pos_eps = 2^-E)
+    int32_t pos_exp, pad_p;
+    double pos_eps, pos_inv;          // 2^-E, 2^E
     // triangle meshes
     int32_t n_mesh, pad_m;
     int64_t n_tri;

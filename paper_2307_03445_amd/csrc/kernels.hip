@@ -685,6 +685,7 @@ struct NarrowSelf {
     float ms;         // margin
     bool exact_only;  // far outside the domain the FP32 slack no longer bounds the rounding
     double reach;     // its own (R + m) plus the largest partner (R + m), plus a small slack
+    double slack;     // fixed-point positions: twice the rounding of a distance of world centres
 };
 __device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid &g, uint32_t s) {
     NarrowSelf n;
@@ -693,7 +694,15 @@ __device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid 
     n.ms = slot3(S.smargin, out_slot(S))[s];  // this detection's margin
     n.Pf = make_float4((float)(n.P.x - g.ox), (float)(n.P.y - g.oy), (float)(n.P.z - g.oz), (float)n.P.w + n.ms);
     n.exact_only = !(fabsf(n.Pf.x) < g.pre_lim && fabsf(n.Pf.y) < g.pre_lim && fabsf(n.Pf.z) < g.pre_lim);
-    n.reach = (n.P.w + (double)n.ms) + g.rm_max + 1e-9;
+    // With fixed-point positions the force kernel decides contact from exact
+    // CoM differences, the detection from world centres (a few ulps of their
+    // coordinates off): the slack covers twice that rounding, so that every
+    // contact the force kernel or an audit can see is a candidate.
+    n.slack = 0.0;
+    if (S.pos_exp)
+        n.slack = ldexp(fmax(fmax(fabs(n.P.x), fabs(n.P.y)), fabs(n.P.z)) + (n.P.w + (double)n.ms) + g.rm_max +
+                            4.0 * g.r_max, -46);
+    n.reach = (n.P.w + (double)n.ms) + g.rm_max + 1e-9 + n.slack;
     return n;
 }
 
@@ -732,7 +741,7 @@ __device__ __forceinline__ uint32_t narrow_exact(const DevScene &S, const Narrow
     const double dx = Q.x - n.P.x, dy = Q.y - n.P.y, dz = Q.z - n.P.z;
     const double d2 = dx * dx + dy * dy + dz * dz;
     double Sr = n.P.w + Q.w;
-    Sr = Sr + ((double)n.ms + (double)S.sorted_margin[j]);
+    Sr = Sr + (((double)n.ms + (double)S.sorted_margin[j]) + n.slack);
     return d2 < Sr * Sr ? S.sorted_id[j] : ~0u;
 }
 // The same test with the slot's record loaded beforehand (so that the loads
@@ -746,7 +755,7 @@ __device__ __forceinline__ uint32_t narrow_exact_rec(const NarrowSelf &n, const 
     const double dx = r.Q.x - n.P.x, dy = r.Q.y - n.P.y, dz = r.Q.z - n.P.z;
     const double d2 = dx * dx + dy * dy + dz * dz;
     double Sr = n.P.w + r.Q.w;
-    Sr = Sr + ((double)n.ms + (double)r.m);
+    Sr = Sr + (((double)n.ms + (double)r.m) + n.slack);
     return d2 < Sr * Sr ? r.id : ~0u;
 }
 
@@ -1124,10 +1133,11 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, d
     quat_mat(k2.x, k2.y, k2.z, k2.w, A);
     double v[3] = {k1.x, k1.y, k1.z}, x[3] = {k0.x, k0.y, k0.z};
     double w[3] = {k3.x, k3.y, k3.z};
+    bool pos_ok;
     if (pi < 0) {
         const double4 mi = S.tmpl_mi[S.clump_tmpl[c]];
         for (int i = 0; i < 3; i++) v[i] = v[i] + h * (F[i] / M);
-        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        pos_ok = advance_position(S, x, v);
         double I[3] = {mi.y, mi.z, mi.w};
         double tb[3];
         for (int i = 0; i < 3; i++) tb[i] = A[i] * T[0] + A[3 + i] * T[1] + A[6 + i] * T[2];
@@ -1141,7 +1151,7 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, d
             if (P[3 + i] != 0.0) v[i] = v[i] + h * ((F[i] + P[9 + i]) / M);
             else v[i] = P[i];
         }
-        for (int i = 0; i < 3; i++) x[i] = x[i] + h * v[i];
+        pos_ok = advance_position(S, x, v);
         for (int i = 0; i < 3; i++) w[i] = P[6 + i];
     }
     double acc_env = 0.0;
@@ -1173,8 +1183,9 @@ __device__ __forceinline__ float integrate_clump(const DevScene &S, int64_t c, d
         pose[10] = k2.x; pose[11] = k2.y; pose[12] = k2.z; pose[13] = k2.w;
     }
     *rctr = k3.w;
-    if (!(isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) && isfinite(v[0]) && isfinite(v[1]) &&
-          isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) && isfinite(w[2])))
+    const bool x_ok = S.pos_exp ? pos_ok : (isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]));
+    if (!(x_ok && isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]) && isfinite(w[0]) && isfinite(w[1]) &&
+          isfinite(w[2])))
         S.ctl->nonfinite = 1;
     float aenv = (float)acc_env * 1.000001f;
     if (S.store_acc) S.cacc[c] = aenv;
@@ -1266,7 +1277,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
                 // of conj(q_det) q).  Below 0.999 times the clump's smallest
                 // margin, with room for the rounding of either side, no
                 // sphere can trip and the per-sphere test is skipped.
-                const double ex = g[0] - d0.x, ey = g[1] - d0.y, ez = g[2] - d0.z;
+                const double ex = S.pos_exp ? fx_diff(S, g[0], d0.x) : g[0] - d0.x;
+                const double ey = S.pos_exp ? fx_diff(S, g[1], d0.y) : g[1] - d0.y;
+                const double ez = S.pos_exp ? fx_diff(S, g[2], d0.z) : g[2] - d0.z;
                 const double vx = d1.x * g[4] - g[3] * d1.y - (d1.z * g[6] - d1.w * g[5]);
                 const double vy = d1.x * g[5] - g[3] * d1.z - (d1.w * g[4] - d1.y * g[6]);
                 const double vz = d1.x * g[6] - g[3] * d1.w - (d1.y * g[5] - d1.z * g[4]);
@@ -1306,13 +1319,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5, 8))
             double A[9], D[9];
             quat_mat(g[3], g[4], g[5], g[6], A);
             quat_mat(g[10], g[11], g[12], g[13], D);
-            const double xs = g[0] + (A[0] * o0 + A[1] * o1 + A[2] * o2);
-            const double ys = g[1] + (A[3] * o0 + A[4] * o1 + A[5] * o2);
-            const double zs = g[2] + (A[6] * o0 + A[7] * o1 + A[8] * o2);
-            const double xd = g[7] + (D[0] * o0 + D[1] * o1 + D[2] * o2);
-            const double yd = g[8] + (D[3] * o0 + D[4] * o1 + D[5] * o2);
-            const double zd = g[9] + (D[6] * o0 + D[7] * o1 + D[8] * o2);
-            const double dx = xs - xd, dy = ys - yd, dz = zs - zd;
+            const double ax = A[0] * o0 + A[1] * o1 + A[2] * o2, ay = A[3] * o0 + A[4] * o1 + A[5] * o2,
+                         az = A[6] * o0 + A[7] * o1 + A[8] * o2;
+            const double bx = D[0] * o0 + D[1] * o1 + D[2] * o2, by = D[3] * o0 + D[4] * o1 + D[5] * o2,
+                         bz = D[6] * o0 + D[7] * o1 + D[8] * o2;
+            double dx, dy, dz;
+            if (S.pos_exp) {  // the exact CoM displacement plus that of the rotated offset
+                dx = fx_diff(S, g[0], g[7]) + (ax - bx);
+                dy = fx_diff(S, g[1], g[8]) + (ay - by);
+                dz = fx_diff(S, g[2], g[9]) + (az - bz);
+            } else {
+                dx = (g[0] + ax) - (g[7] + bx);
+                dy = (g[1] + ay) - (g[8] + by);
+                dz = (g[2] + az) - (g[9] + bz);
+            }
             const double lim = 0.999 * (double)m;
             trip = !(dx * dx + dy * dy + dz * dz < lim * lim);
         }
@@ -1406,7 +1426,9 @@ __global__ void __launch_bounds__(256) k_guard_big(DevScene S) {
     const double4 k0 = S.cst[4 * (int64_t)c], k2 = S.cst[4 * (int64_t)c + 2];
     double A[9];
     quat_mat(k2.x, k2.y, k2.z, k2.w, A);
-    const double nx[3] = {k0.x, k0.y, k0.z};
+    double nx[3] = {k0.x, k0.y, k0.z};
+    if (S.pos_exp)
+        for (int i = 0; i < 3; i++) nx[i] = fx_decode(S, fx_bits(nx[i]));
     const uint32_t tb = S.tmpl_sbeg[S.clump_tmpl[c]];
     double4 *det = S.bdet + S.big_sbeg[blockIdx.y];
     int trip = 0;
@@ -1421,8 +1443,10 @@ __global__ void __launch_bounds__(256) k_guard_big(DevScene S) {
         if (fresh) { d = S.spos[s]; det[k] = d; }
         else d = det[k];
         const double dx = xs - d.x, dy = ys - d.y, dz = zs - d.z;
-        const double lim = 0.999 * (double)slot3(S.smargin, S.ctl->buf)[s];
-        if (!(dx * dx + dy * dy + dz * dz < lim * lim)) trip = 1;
+        double lim = 0.999 * (double)slot3(S.smargin, S.ctl->buf)[s];
+        // fixed-point positions: world centres, so less the rounding of their coordinates
+        if (S.pos_exp) lim = lim - ldexp(fmax(fmax(fabs(xs), fabs(ys)), fabs(zs)) + 1.0, -48);
+        if (!(dx * dx + dy * dy + dz * dz < lim * lim) || !(lim > 0.0)) trip = 1;
     }
     if (__syncthreads_or(trip) && threadIdx.x == 0) S.ctl->guard_next = 1;
 }
@@ -1793,7 +1817,9 @@ __global__ void __launch_bounds__(256) k_adopt_guard(DevScene S, DevScene B) {
     if (s < S.ns) {
         const uint32_t c = S.owner[s], ts = S.sts[s];
         const SphereKin now = sphere_kin_of(S, c, ts), then = sphere_kin_of(B, c, ts);
-        const double dx = now.p[0] - then.p[0], dy = now.p[1] - then.p[1], dz = now.p[2] - then.p[2];
+        double d[3], dc[3];
+        sphere_vec(S, then, now, d, dc);
+        const double dx = d[0], dy = d[1], dz = d[2];
         const double lim = 0.999 * (double)slot3(S.smargin, B.ctl->bslot)[s];
         trip = !(dx * dx + dy * dy + dz * dz < lim * lim);
     }
@@ -2057,28 +2083,48 @@ hipError_t launch_audit_brute(const DevScene &S, unsigned long long *counts, uin
 // ---------------------------------------------------------------- state transfer
 // Row-major [n][3]/[n][4] device buffers <-> the clump records (null buffers
 // are skipped; the static words of a record are kept).
-__global__ void __launch_bounds__(256) k_pack_state(DevScene S, double *x, double *q, double *v, double *w, int unpack) {
+// With fixed-point positions x is decoded on the way out and rounded to the
+// grid on the way in (an x out of range leaves the position and flags the
+// state as non-finite), unless `raw` copies the integers (checkpoints).
+__global__ void __launch_bounds__(256) k_pack_state(DevScene S, double *x, double *q, double *v, double *w, int unpack,
+                                                    int raw) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= S.nc) return;
     double4 *r = S.cst + 4 * c;
     double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
+    const bool dec = S.pos_exp && !raw;
     if (!unpack) {
-        if (x) { x[3 * c] = k0.x; x[3 * c + 1] = k0.y; x[3 * c + 2] = k0.z; }
+        if (x && dec) {
+            for (int i = 0; i < 3; i++) x[3 * c + i] = fx_decode(S, fx_bits(i == 0 ? k0.x : (i == 1 ? k0.y : k0.z)));
+        } else if (x) {
+            x[3 * c] = k0.x; x[3 * c + 1] = k0.y; x[3 * c + 2] = k0.z;
+        }
         if (v) { v[3 * c] = k1.x; v[3 * c + 1] = k1.y; v[3 * c + 2] = k1.z; }
         if (q) { q[4 * c] = k2.x; q[4 * c + 1] = k2.y; q[4 * c + 2] = k2.z; q[4 * c + 3] = k2.w; }
         if (w) { w[3 * c] = k3.x; w[3 * c + 1] = k3.y; w[3 * c + 2] = k3.z; }
         return;
     }
-    if (x) { k0.x = x[3 * c]; k0.y = x[3 * c + 1]; k0.z = x[3 * c + 2]; }
+    if (x && dec) {
+        double e[3];
+        for (int i = 0; i < 3; i++) {
+            const double u = x[3 * c + i] * S.pos_inv;
+            if (!(fabs(u) < (double)kFxLimit)) { S.ctl->nonfinite = 1; return; }
+            e[i] = fx_slot((long long)rint(u));
+        }
+        k0.x = e[0]; k0.y = e[1]; k0.z = e[2];
+    } else if (x) {
+        k0.x = x[3 * c]; k0.y = x[3 * c + 1]; k0.z = x[3 * c + 2];
+    }
     if (v) { k1.x = v[3 * c]; k1.y = v[3 * c + 1]; k1.z = v[3 * c + 2]; }
     if (q) { k2.x = q[4 * c]; k2.y = q[4 * c + 1]; k2.z = q[4 * c + 2]; k2.w = q[4 * c + 3]; }
     if (w) { k3.x = w[3 * c]; k3.y = w[3 * c + 1]; k3.z = w[3 * c + 2]; }
     r[0] = k0; r[1] = k1; r[2] = k2; r[3] = k3;
 }
 
-hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack, hipStream_t st) {
+hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack, hipStream_t st,
+                             int raw) {
     if (S.nc == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_state, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S, x, q, v, w, unpack);
+    hipLaunchKernelGGL(k_pack_state, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S, x, q, v, w, unpack, raw);
     return hipGetLastError();
 }
 

@@ -199,7 +199,9 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     if (t < (uint32_t)S.ns) {
         const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
         const SphereKin ka = sphere_kin_of(S, id.ca, id.ta), kb = sphere_kin_of(S, id.cb, id.tb);
-        double dx = kb.p[0] - ka.p[0], dy = kb.p[1] - ka.p[1], dz = kb.p[2] - ka.p[2];
+        double dv[3], dc[3];
+        sphere_vec(S, ka, kb, dv, dc);
+        double dx = dv[0], dy = dv[1], dz = dv[2];
         double d2 = dx * dx + dy * dy + dz * dz;
         double Sr = ka.R + kb.R;
         if (!(d2 < Sr * Sr)) {  // a false positive of the enlarged geometry: no force, no history
@@ -218,9 +220,13 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         }
         double n[3] = {dx / d, dy / d, dz / d};
         double lever = ka.R - 0.5 * delta;
-        double p[3] = {ka.p[0] + lever * n[0], ka.p[1] + lever * n[1], ka.p[2] + lever * n[2]};
-        double ra[3] = {p[0] - ka.xc[0], p[1] - ka.xc[1], p[2] - ka.xc[2]};
-        double rb[3] = {p[0] - kb.xc[0], p[1] - kb.xc[1], p[2] - kb.xc[2]};
+        double ra[3], rb[3];  // lever arms from the two CoMs to the contact point
+        if (!S.pos_exp) {
+            double p[3] = {ka.p[0] + lever * n[0], ka.p[1] + lever * n[1], ka.p[2] + lever * n[2]};
+            for (int i = 0; i < 3; i++) { ra[i] = p[i] - ka.xc[i]; rb[i] = p[i] - kb.xc[i]; }
+        } else {  // a's rotated offset, then along n; from b's CoM, less the CoM difference
+            for (int i = 0; i < 3; i++) { ra[i] = ka.r[i] + lever * n[i]; rb[i] = ra[i] - dc[i]; }
+        }
         // contact kinematics in FP64 (relative velocities of similar speeds cancel)
         double ca3[3], cb3[3];
         cross3(ka.W, ra, ca3);
@@ -292,7 +298,8 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     double p[3] = {ks.p[0] - lever * n[0], ks.p[1] - lever * n[1], ks.p[2] - lever * n[2]};
     const double *cw = B.ref;
     double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
-    double rb[3] = {p[0] - ks.xc[0], p[1] - ks.xc[1], p[2] - ks.xc[2]};
+    double rb[3];
+    for (int i = 0; i < 3; i++) rb[i] = S.pos_exp ? ks.r[i] - lever * n[i] : p[i] - ks.xc[i];
     double pw[3], cb3[3];
     cross3(B.omg, ra, pw);
     cross3(ks.W, rb, cb3);

@@ -38,13 +38,48 @@ __device__ __forceinline__ void quat_mat(double w, double x, double y, double z,
     A[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+// ---------------------------------------------------------------- fixed-point positions
+// With fixed-point positions (S.pos_exp = E > 0) a clump record's CoM slots
+// hold 64-bit integers k, x = k 2^-E (the high 32 bits a voxel id, the low
+// 32 bits the offset in a voxel of side 2^(32-E)), stored bit for bit in the
+// double slots.
+__device__ __forceinline__ long long fx_bits(double d) { return __double_as_longlong(d); }
+__device__ __forceinline__ double fx_slot(long long k) { return __longlong_as_double(k); }
+// The world coordinate of an integer position (rounded when |k| > 2^53).
+__device__ __forceinline__ double fx_decode(const DevScene &S, long long k) { return (double)k * S.pos_eps; }
+// The exact difference of two integer positions (|ka - kb| < 2^53).
+__device__ __forceinline__ double fx_diff(const DevScene &S, double a, double b) {
+    return (double)(fx_bits(a) - fx_bits(b)) * S.pos_eps;
+}
+// Integer positions stay below 2^61 in magnitude (a quarter of the range).
+constexpr long long kFxLimit = 1LL << 61;
+// x += h v: in FP64, or with the increment rounded to the grid (ties to
+// even) and added to the integer.  Returns false when a position would leave
+// its range (the position is then kept).
+__device__ __forceinline__ bool advance_position(const DevScene &S, double *x, const double *v) {
+    if (!S.pos_exp) {
+        for (int i = 0; i < 3; i++) x[i] = x[i] + S.h * v[i];
+        return true;
+    }
+    bool ok = true;
+    for (int i = 0; i < 3; i++) {
+        const double u = rint((S.h * v[i]) * S.pos_inv);
+        const long long k = fx_bits(x[i]);
+        if (!(fabs(u) < (double)kFxLimit) || k >= kFxLimit || k <= -kFxLimit) { ok = false; continue; }
+        x[i] = fx_slot(k + (long long)u);
+    }
+    return ok;
+}
+
 // ---------------------------------------------------------------- pose (per sphere)
 // Kinematics of sphere s from its clump's state record: centre x_s = x_c +
-// A(q) o_s and radius, and the clump's CoM, mass, velocity and world angular
-// velocity A(q) w_body.  Every kernel that needs a sphere's pose computes it
-// this one way, so the positions of a detection, of the force kernel and of
-// a readout are the same numbers.
-struct SphereKin { double p[3], R, xc[3], M, v[3], W[3]; };
+// A(q) o_s and radius, the rotated offset r = A(q) o_s, and the clump's CoM,
+// mass, velocity and world angular velocity A(q) w_body (with fixed-point
+// positions: the CoM decoded to world coordinates, and its integers in cq).
+// Every kernel that needs a sphere's pose computes it this one way, so the
+// positions of a detection, of the force kernel and of a readout are the same
+// numbers.
+struct SphereKin { double p[3], R, xc[3], M, v[3], W[3], r[3], cq[3]; };
 // ... of the sphere that is template sphere ts of clump c
 __device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c, uint32_t ts) {
     const double4 *r = S.cst + 4 * (int64_t)c;
@@ -54,10 +89,18 @@ __device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c
     k.R = S.tmpl_rad[ts];
     double A[9];
     quat_mat(k2.x, k2.y, k2.z, k2.w, A);
-    k.p[0] = k0.x + (A[0] * o0 + A[1] * o1 + A[2] * o2);
-    k.p[1] = k0.y + (A[3] * o0 + A[4] * o1 + A[5] * o2);
-    k.p[2] = k0.z + (A[6] * o0 + A[7] * o1 + A[8] * o2);
-    k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
+    k.r[0] = A[0] * o0 + A[1] * o1 + A[2] * o2;
+    k.r[1] = A[3] * o0 + A[4] * o1 + A[5] * o2;
+    k.r[2] = A[6] * o0 + A[7] * o1 + A[8] * o2;
+    k.cq[0] = k0.x; k.cq[1] = k0.y; k.cq[2] = k0.z;
+    if (S.pos_exp) {
+        k.xc[0] = fx_decode(S, fx_bits(k0.x)); k.xc[1] = fx_decode(S, fx_bits(k0.y)); k.xc[2] = fx_decode(S, fx_bits(k0.z));
+    } else {
+        k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
+    }
+    k.p[0] = k.xc[0] + k.r[0];
+    k.p[1] = k.xc[1] + k.r[1];
+    k.p[2] = k.xc[2] + k.r[2];
     k.M = k0.w;
     k.v[0] = k1.x; k.v[1] = k1.y; k.v[2] = k1.z;
     k.W[0] = A[0] * k3.x + A[1] * k3.y + A[2] * k3.z;
@@ -67,6 +110,20 @@ __device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c
 }
 __device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
     return sphere_kin_of(S, S.owner[s], S.sts[s]);
+}
+// Vector d from sphere a to sphere b: the difference of their centres, or
+// with fixed-point positions the exact CoM difference dc plus the difference
+// of the rotated offsets.
+__device__ __forceinline__ void sphere_vec(const DevScene &S, const SphereKin &a, const SphereKin &b, double *d,
+                                           double *dc) {
+    if (S.pos_exp) {
+        for (int i = 0; i < 3; i++) {
+            dc[i] = fx_diff(S, b.cq[i], a.cq[i]);
+            d[i] = dc[i] + (b.r[i] - a.r[i]);
+        }
+    } else {
+        for (int i = 0; i < 3; i++) { d[i] = b.p[i] - a.p[i]; dc[i] = 0.0; }
+    }
 }
 
 
