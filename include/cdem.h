@@ -260,8 +260,12 @@ int cdem_sync(cdem_scene *s);
  * parameters. */
 int cdem_set_detection(cdem_scene *s, const cdem_detect_params *p);
 /* When on != 0, the next step stores per-contact penetration, force and
- * torques (for cdem_read_contacts, cdem_read_clump_forces and
- * cdem_read_boundary_forces); allocates the recording buffers on first use. */
+ * torques (for cdem_read_contacts, cdem_read_clump_forces,
+ * cdem_read_boundary_forces and cdem_read_mesh_forces); allocates the
+ * recording buffers on first use.  on = 1 records every contact; on = 2 only
+ * the contacts with boundaries and mesh triangles (a co-simulation exchange:
+ * the sphere pairs' records are not written, and cdem_read_contacts then
+ * lists the boundary contacts only).  CDEM_E_INVALID for other values. */
 int cdem_record_next_step(cdem_scene *s, int on);
 
 /* Batched scenes (independent scenes in one launch, each with its own bins,
@@ -320,16 +324,22 @@ int cdem_read_sphere_pos(cdem_scene *s, double *xs);
  * reports the force the spheres exert on it; Sec. 5.2 couples the granular
  * side and a multibody solver this way, one exchange every few steps) ---- */
 /* Prescribe mesh `mesh`'s state (13 doubles as in cdem_scene_desc.mesh_state,
- * host pointer; unit quaternion, finite values, else CDEM_E_INVALID).  The
- * active set is kept: its margins are recomputed for the new velocities
- * before the next step (a sphere the mesh outruns trips the guard). */
+ * host pointer; unit quaternion, finite values, else CDEM_E_INVALID).  A
+ * mesh's candidate margin covers 1.25 times its speed bound |v| + |w| r_max
+ * (r_max: its farthest vertex from the reference point) over the steps an
+ * active set is used.  New velocities that bound stays under, at an
+ * unchanged pose (x and q bit for bit as cdem_read_mesh_state returns them),
+ * keep the active set; a new pose or a faster motion resizes the margin and
+ * makes the next step detect again. */
 int cdem_set_mesh_state(cdem_scene *s, int32_t mesh, const double *state);
 /* Current mesh states, host buffer [n_mesh][13]. */
 int cdem_read_mesh_state(cdem_scene *s, double *state);
 /* Force the spheres exert on each mesh (minus the sum of its contact forces)
  * and its torque about the mesh's reference point at the last recorded step
- * (see cdem_record_next_step), host buffers [n_mesh][3], summed in ascending
- * contact order.  CDEM_E_STATE when no step was recorded. */
+ * (see cdem_record_next_step, either mode), host buffers [n_mesh][3], summed
+ * in ascending contact order (the triangle contacts are gathered on the
+ * device, then ordered and summed on the host).  CDEM_E_STATE when no step
+ * was recorded. */
 int cdem_read_mesh_forces(cdem_scene *s, double *F, double *T);
 
 /* Independent exact contact sweep (no binning, no margin) over the current

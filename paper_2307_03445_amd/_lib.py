@@ -259,8 +259,10 @@ class Scene:
                           1 if overlap else 0)
         self._check(self._L.cdem_set_detection(self._h, C.byref(p)))
 
-    def record_next_step(self, on: bool = True):
-        self._check(self._L.cdem_record_next_step(self._h, 1 if on else 0))
+    def record_next_step(self, on: bool = True, walls_only: bool = False):
+        """Record the next step's contacts (all of them, or with walls_only
+        those with boundaries and mesh triangles)."""
+        self._check(self._L.cdem_record_next_step(self._h, (2 if walls_only else 1) if on else 0))
 
     def counts(self) -> dict:
         c = CountsC()

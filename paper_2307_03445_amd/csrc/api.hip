@@ -27,6 +27,8 @@
 using namespace cdem;
 
 namespace cdem {
+hipError_t launch_mesh_contacts(const DevScene &S, unsigned long long *keys, double *FR, unsigned long long *count,
+                                int64_t cap, hipStream_t st);
 hipError_t launch_pack_state(const DevScene &S, double *x, double *q, double *v, double *w, int unpack,
                              hipStream_t st, int raw = 0);
 }
@@ -110,6 +112,8 @@ struct cdem_scene {
     std::vector<double> mesh_speed;    // speed bound |v| + |w| rmax each mesh's margin was sized for
     std::vector<int32_t> tri_user;     // device triangle order -> user index
     std::vector<int32_t> tri_mesh;     // device triangle order -> mesh
+    int64_t tri_box_len = 0;           // doubles of the triangle, chunk and scene boxes
+    int64_t mesh_cap = 0;              // triangle contacts the last mesh-force readout held
     double rmax = 0.0;
     int64_t n_cells_alloc = 0;
     int64_t n_regions_alloc = 0;
@@ -412,16 +416,37 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
         }
         if (hipStreamSynchronize(sc->stream) != hipSuccess) return fail(sc, CDEM_E_HIP, "sync");
     }
+    if (sc->rec_cap) {
+        // the recording arrays follow the capacity (a step armed to record
+        // writes them, also when it is run again after this regrow), with the
+        // recorded step's entries kept at their indices like the pairs
+        uint8_t *rs = (uint8_t *)dev_alloc(sc, cap);
+        double *rd = (double *)dev_alloc(sc, 8 * cap), *rf[4];
+        for (int k = 0; k < 4; k++) rf[k] = (double *)dev_alloc(sc, 24 * cap);
+        if (!rs || !rd || !rf[0] || !rf[1] || !rf[2] || !rf[3]) return fail(sc, CDEM_E_OOM, "recording buffers");
+        double **old[4] = {&S.rec_F, &S.rec_R, &S.rec_Ta, &S.rec_Tb};
+        if (keep) {
+            Ctl c;
+            if (hipMemcpy(&c, S.ctl, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) return fail(sc, CDEM_E_HIP, "ctl read");
+            const size_t n = (size_t)std::min<int64_t>(c.n_pairs_cur, std::min(sc->rec_cap, cap));
+            hipError_t e = hipSuccess;
+            if (n) {
+                e = hipMemcpyAsync(rs, S.rec_state, n, hipMemcpyDeviceToDevice, sc->stream);
+                if (e == hipSuccess) e = hipMemcpyAsync(rd, S.rec_delta, 8 * n, hipMemcpyDeviceToDevice, sc->stream);
+                for (int k = 0; k < 4 && e == hipSuccess; k++)
+                    e = hipMemcpyAsync(rf[k], *old[k], 24 * n, hipMemcpyDeviceToDevice, sc->stream);
+            }
+            if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+            if (e != hipSuccess) return fail(sc, CDEM_E_HIP, "recording copy");
+        }
+        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta);
+        S.rec_state = rs; S.rec_delta = rd;
+        for (int k = 0; k < 4; k++) { dev_free(sc, *old[k]); *old[k] = rf[k]; }
+        sc->rec_cap = cap;
+    }
     for (int k = 0; k < 3; k++) { dev_free(sc, S.pt[k]); S.pt[k] = pt[k]; }
     for (int k = 0; k < 2; k++) { dev_free(sc, S.hist[k]); S.hist[k] = hs[k]; }
     S.cap = cap;
-    if (sc->rec_cap) {  // recording arrays follow the capacity
-        dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
-        dev_free(sc, S.rec_Ta); dev_free(sc, S.rec_Tb);
-        S.rec_state = nullptr; S.rec_delta = nullptr; S.rec_F = nullptr; S.rec_R = nullptr;
-        S.rec_Ta = nullptr; S.rec_Tb = nullptr;
-        sc->rec_cap = 0;
-    }
     return CDEM_OK;
 }
 
@@ -462,7 +487,7 @@ static int ahead_alloc(cdem_scene *sc) {
         a.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
         a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
         a.mesh = (Mesh *)dev_alloc(sc, sizeof(Mesh) * std::max<int64_t>(S.n_mesh, 1));
-        a.tri_box = (double *)dev_alloc(sc, 48 * std::max<int64_t>(S.n_tri, 1));
+        a.tri_box = (double *)dev_alloc(sc, 8 * (size_t)std::max<int64_t>(sc->tri_box_len, 1));
         if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_id || !a.sorted_owner ||
             !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.over_list || !a.part_k || !a.mesh || !a.tri_box)
             return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
@@ -519,6 +544,9 @@ static double norm3(const double *a) { return std::sqrt(a[0] * a[0] + a[1] * a[1
 
 // Speed bound of every point of a mesh: |v| + |w| rmax.
 static double mesh_speed_of(const Mesh &m) { return norm3(m.v) + norm3(m.w) * m.rmax; }
+// A mesh's margin covers 1.25 times its speed bound, so that a
+// co-simulation's small changes of speed keep the active set.
+constexpr double kMeshSpeedHeadroom = 1.25;
 
 // Candidate margins covering a boundary's own motion over the steps a set is
 // used: speed x steps x h, plus 1 %.
@@ -532,7 +560,7 @@ static void set_bnd_margins(cdem_scene *sc) {
     const double kh = (double)margin_steps(sc) * sc->S.h * 1.01;
     for (auto &b : sc->bnd) b.margin = norm3(b.vel) * kh;
     for (size_t i = 0; i < sc->mesh.size(); i++) {
-        sc->mesh_speed[i] = mesh_speed_of(sc->mesh[i]);
+        sc->mesh_speed[i] = kMeshSpeedHeadroom * mesh_speed_of(sc->mesh[i]);
         sc->mesh[i].margin = sc->mesh_speed[i] * kh;
     }
 }
@@ -755,6 +783,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         g.gx = d->gravity[3 * k]; g.gy = d->gravity[3 * k + 1]; g.gz = d->gravity[3 * k + 2];
         g.bnd_beg = g.bnd_end = 0;
     }
+    std::vector<int32_t> chunk_tri;
     {
         int i = 0;
         for (int k = 0; k < d->n_scenes; k++) {
@@ -764,13 +793,22 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         }
         int64_t j = 0;
         for (int k = 0; k < d->n_scenes; k++) {
-            sc->grids[k].tri_beg = (int32_t)j;
+            Grid &g = sc->grids[k];
+            g.sid = k;
+            g.tri_beg = (int32_t)j;
             while (j < d->n_tri && sc->mesh[sc->tri_mesh[j]].scene == k) j++;
-            sc->grids[k].tri_end = (int32_t)j;
+            g.tri_end = (int32_t)j;
+            // chunks of at most 64 consecutive triangles of this scene
+            g.chunk_beg = (int32_t)chunk_tri.size();
+            for (int64_t t = g.tri_beg; t < g.tri_end; t += 64) chunk_tri.push_back((int32_t)t);
+            g.chunk_end = (int32_t)chunk_tri.size();
         }
+        S.n_chunk = (int64_t)chunk_tri.size();
+        chunk_tri.push_back((int32_t)d->n_tri);
     }
     std::vector<int32_t> big;
     for (int64_t c = 0; c < nc; c++) if (sbeg[c + 1] - sbeg[c] > kBigClump) big.push_back((int32_t)c);
+    sc->tri_box_len = 6 * (S.n_tri + S.n_chunk + S.n_scenes);
     // per template: the largest |o_s| + R_s (acceleration envelope) and the
     // largest |o_s| (displacement guard) of its spheres, stored as floats
     std::vector<double> r_acc(nt), r_ctr(nt);
@@ -886,6 +924,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     UP(mesh, sc->mesh.data(), sc->mesh.size());
     UP(tri_vb, tri_vb.data(), tri_vb.size());
     UP(tri_mesh, sc->tri_mesh.data(), sc->tri_mesh.size());
+    UP(chunk_tri, chunk_tri.data(), chunk_tri.size());
     UP(big_list, big.data(), big.size());
     {
         std::vector<int64_t> bsb(big.size() + 1, 0);
@@ -922,7 +961,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
     if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     if (d->n_tri) {
-        S.tri_box = (double *)dev_alloc(sc, 48 * (size_t)d->n_tri);
+        S.tri_box = (double *)dev_alloc(sc, 8 * (size_t)sc->tri_box_len);
         if (!S.tri_box) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     }
     for (int k = 0; k < 3; k++) {  // per-sphere structure of the three active-set slots
@@ -1100,6 +1139,8 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
     if (rc) return rc;
     int64_t target = c.step + n;
     int64_t missed0 = c.missed;
+    const int64_t step0 = c.step;
+    const int32_t rec0 = c.record;  // the recording asked for the first step
     for (int attempt = 0; attempt < 8; attempt++) {
         int64_t left = target - c.step;
         if (left <= 0) break;
@@ -1141,7 +1182,7 @@ extern "C" int cdem_step(cdem_scene *sc, int64_t n, void *stream) {
         c.row_overflow = 0;
         c.asym = 0;
         c.det_due = 1;
-        c.record = 0;
+        c.record = c.step == step0 ? rec0 : 0;  // a recorded step that did not complete records when run again
         if ((rc = write_ctl(sc, c)) != CDEM_OK) return rc;
     }
     if (c.step != target) return fail(sc, CDEM_E_CAPACITY, "active set could not be grown");
@@ -1209,8 +1250,10 @@ extern "C" int cdem_set_detection(cdem_scene *sc, const cdem_detect_params *p) {
 
 extern "C" int cdem_record_next_step(cdem_scene *sc, int on) {
     if (!sc) return CDEM_E_INVALID;
+    if (on < 0 || on > 2) return fail(sc, CDEM_E_INVALID, "record mode is 0, 1 or 2");
     DevScene &S = sc->S;
-    if (on && sc->rec_cap < S.cap) {
+    const bool fresh = on && sc->rec_cap < S.cap;  // new arrays: the last recorded step is gone
+    if (fresh) {
         dev_free(sc, S.rec_state); dev_free(sc, S.rec_delta); dev_free(sc, S.rec_F); dev_free(sc, S.rec_R);
         dev_free(sc, S.rec_Ta); dev_free(sc, S.rec_Tb);
         S.rec_state = (uint8_t *)dev_alloc(sc, S.cap);
@@ -1219,14 +1262,17 @@ extern "C" int cdem_record_next_step(cdem_scene *sc, int on) {
         S.rec_R = (double *)dev_alloc(sc, 24 * S.cap);
         S.rec_Ta = (double *)dev_alloc(sc, 24 * S.cap);
         S.rec_Tb = (double *)dev_alloc(sc, 24 * S.cap);
-        if (!S.rec_state || !S.rec_delta || !S.rec_F || !S.rec_R || !S.rec_Ta || !S.rec_Tb)
+        if (!S.rec_state || !S.rec_delta || !S.rec_F || !S.rec_R || !S.rec_Ta || !S.rec_Tb) {
+            sc->rec_cap = 0;  // nothing may record into them
             return fail(sc, CDEM_E_OOM, "recording buffers");
+        }
         sc->rec_cap = S.cap;
     }
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
-    c.record = on ? 1 : 0;
+    c.record = on;
+    if (fresh) c.rec_last = 0;
     return write_ctl(sc, c);
 }
 
@@ -1349,6 +1395,7 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
     Ctl c;
     int rc = read_ctl(sc, c);
     if (rc) return rc;
+    if (!c.rec_last) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
     int cur = c.buf;
     int64_t ne = c.n_pairs_cur, ns = S.ns;
     std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
@@ -1373,7 +1420,7 @@ extern "C" int cdem_read_contacts(cdem_scene *sc, cdem_contacts_view *v) {
         for (uint32_t k = 0; k < cnt[s]; k++) {
             int64_t e = (int64_t)beg[s] + k;
             uint32_t t = nb[e];
-            if (!st[e]) continue;
+            if (!st[e] || (c.rec_last == 2 && t < (uint32_t)ns)) continue;
             // pairs are listed once, in the lower sphere's segment
             rows.push_back({((uint64_t)s << 32) | user_partner(sc, t), e});
         }
@@ -1400,6 +1447,11 @@ extern "C" int cdem_read_boundary_forces(cdem_scene *sc, double *F, double *T) {
     if (!sc->rec_cap) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
     const int nb = S.n_bnd;
     if (nb == 0) return CDEM_OK;
+    {
+        Ctl c;
+        if (int rc = read_ctl(sc, c)) return rc;
+        if (!c.rec_last) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
+    }
     double *part = (double *)dev_alloc(sc, sizeof(double) * 6 * kBndParts * (size_t)nb);
     double *out = (double *)dev_alloc(sc, sizeof(double) * 6 * (size_t)nb);
     std::vector<double> h(6 * (size_t)nb);
@@ -1700,7 +1752,7 @@ extern "C" int cdem_set_mesh_state(cdem_scene *sc, int32_t mesh, const double *s
     }
     if ((rc = ahead_drain(sc, true)) != CDEM_OK) return rc;  // a set built for the old motion is dropped
     const double kh = (double)margin_steps(sc) * sc->S.h * 1.01;
-    sc->mesh_speed[mesh] = mesh_speed_of(M);
+    sc->mesh_speed[mesh] = kMeshSpeedHeadroom * mesh_speed_of(M);
     M.margin = sc->mesh_speed[mesh] * kh;
     HIPCHK(hipMemcpy(sc->S.mesh + mesh, &M, sizeof(Mesh), hipMemcpyHostToDevice));
     Ctl c;
@@ -1715,43 +1767,52 @@ extern "C" int cdem_read_mesh_forces(cdem_scene *sc, double *F, double *T) {
     if (!sc->rec_cap) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
     const int32_t nm = S.n_mesh;
     if (!nm) return CDEM_OK;
-    Ctl c;
-    int rc = read_ctl(sc, c);
-    if (rc) return rc;
-    const int cur = c.buf;
-    const int64_t ne = c.n_pairs_cur, ns = S.ns;
-    std::vector<uint32_t> beg(ns), cnt(ns), nb(ne);
-    std::vector<uint8_t> st(ne);
-    std::vector<double> dl(ne), Fr(3 * ne), Rr(3 * ne);
-    if (ns) {
-        HIPCHK(hipMemcpy(beg.data(), S.lo_beg[cur], 4 * ns, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(cnt.data(), S.lo_cnt[cur], 4 * ns, hipMemcpyDeviceToHost));
+    {
+        Ctl c;
+        if (int rc = read_ctl(sc, c)) return rc;
+        if (!c.rec_last) return fail(sc, CDEM_E_STATE, "no recorded step (call cdem_record_next_step first)");
     }
-    if (ne) {
-        HIPCHK(hipMemcpy(nb.data(), S.pt[cur], 4 * ne, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(st.data(), S.rec_state, ne, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(dl.data(), S.rec_delta, 8 * ne, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(Fr.data(), S.rec_F, 24 * ne, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(Rr.data(), S.rec_R, 24 * ne, hipMemcpyDeviceToHost));
-    }
-    // the triangle contacts in the order the caller numbers them, then
-    // Newton's third law at each contact point: the mesh receives -F, with the
-    // lever arm from its reference point
-    const uint32_t t0 = (uint32_t)(ns + S.n_bnd);
-    struct Row { uint64_t key; int64_t e; int32_t mesh; };
-    std::vector<Row> rows;
-    for (int64_t s = 0; s < ns; s++)
-        for (uint32_t k = 0; k < cnt[s]; k++) {
-            const int64_t e = (int64_t)beg[s] + k;
-            const uint32_t t = nb[e];
-            if (t < t0 || !st[e] || !(dl[e] > 0.0)) continue;
-            rows.push_back({((uint64_t)s << 32) | user_partner(sc, t), e, sc->tri_mesh[t - t0]});
+    // the triangle contacts of the recorded step, compacted on the device
+    // (a few per mesh-touching sphere), then ordered by (a, b) as the caller
+    // numbers them: Newton's third law at each contact point, the mesh
+    // receiving -F with the lever arm from its reference point
+    int64_t cap = std::max<int64_t>(sc->mesh_cap, 1024);
+    std::vector<unsigned long long> keys;
+    std::vector<double> FR;
+    unsigned long long n = 0;
+    for (int pass = 0; pass < 2; pass++) {
+        char *buf = (char *)dev_alloc(sc, 8 + 56 * (size_t)cap);
+        if (!buf) return fail(sc, CDEM_E_OOM, "mesh contact buffer");
+        unsigned long long *cnt = (unsigned long long *)buf, *k = cnt + 1;
+        double *fr = (double *)(k + cap);
+        hipError_t e = launch_zero(cnt, 8, sc->stream);
+        if (e == hipSuccess) e = launch_mesh_contacts(S, k, fr, cnt, cap, sc->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+        if (e == hipSuccess) e = hipMemcpy(&n, cnt, 8, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && (int64_t)n <= cap) {
+            keys.resize(n);
+            FR.resize(6 * n);
+            if (n) e = hipMemcpy(keys.data(), k, 8 * n, hipMemcpyDeviceToHost);
+            if (e == hipSuccess && n) e = hipMemcpy(FR.data(), fr, 48 * n, hipMemcpyDeviceToHost);
         }
+        dev_free(sc, buf);
+        if (e != hipSuccess) return fail(sc, CDEM_E_HIP, hipGetErrorString(e));
+        if ((int64_t)n <= cap) break;
+        cap = (int64_t)n + (int64_t)n / 4 + 1024;  // grown once, to what the recorded step holds
+    }
+    sc->mesh_cap = cap;
+    const uint32_t t0 = (uint32_t)(S.ns + S.n_bnd);
+    struct Row { uint64_t key; int64_t i; int32_t mesh; };
+    std::vector<Row> rows(n);
+    for (unsigned long long i = 0; i < n; i++) {
+        const uint32_t s = (uint32_t)(keys[i] >> 32), t = (uint32_t)(keys[i] & 0xffffffffu);
+        rows[i] = {((uint64_t)s << 32) | user_partner(sc, t), (int64_t)i, sc->tri_mesh[t - t0]};
+    }
     std::sort(rows.begin(), rows.end(), [](const Row &x, const Row &y) { return x.key < y.key; });
     std::vector<double> f(3 * nm, 0.0), tq(3 * nm, 0.0);
     for (const Row &r : rows) {
-        const double g[3] = {-Fr[3 * r.e], -Fr[3 * r.e + 1], -Fr[3 * r.e + 2]};
-        const double *a = &Rr[3 * r.e];
+        const double *Fr = &FR[6 * r.i], *a = &FR[6 * r.i + 3];
+        const double g[3] = {-Fr[0], -Fr[1], -Fr[2]};
         const double x[3] = {a[1] * g[2] - a[2] * g[1], a[2] * g[0] - a[0] * g[2], a[0] * g[1] - a[1] * g[0]};
         for (int i = 0; i < 3; i++) {
             f[3 * r.mesh + i] = f[3 * r.mesh + i] + g[i];
@@ -1898,6 +1959,7 @@ extern "C" int cdem_load(cdem_scene *sc, const void *buf, size_t len) {
     n.n_pairs_cur = E;
     n.det_due = 1;
     n.overflow = 0; n.row_overflow = 0; n.asym = 0; n.record = 0; n.collecting = 0; n.nonfinite = 0;
+    n.rec_last = 0;  // no step of this scene has been recorded since
     n.guard = 0;
     n.guard_next = 0;
     return write_ctl(sc, n);

@@ -42,10 +42,11 @@ struct Mesh {
 struct Grid {
     double ox, oy, oz;       // lower corner
     double inv;              // 1 / bin size
-    int32_t nx, ny, nz, pad;
+    int32_t nx, ny, nz, sid;  // bins per axis; the scene's index
     int64_t cell0;           // first global bin id of the scene
     int32_t bnd_beg, bnd_end;   // the scene's analytic boundaries
     int32_t tri_beg, tri_end;   // the scene's mesh triangles
+    int32_t chunk_beg, chunk_end;  // ... in chunks of at most 64 (chunks never span two scenes)
     double gx, gy, gz;       // gravity
     float pre_eps;           // slack of the FP32 prefilter: bounds its rounding of positions relative to (ox, oy, oz)
     float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
@@ -70,7 +71,7 @@ struct Ctl {
     int32_t overflow;        // active-set storage overflowed: later kernels of the step skip
     int32_t row_overflow;    // more spheres exceeded kMaxRow candidates than the overflow list holds
     int32_t guard;           // a clump may have moved past its margin: re-detect
-    int32_t record;          // store per-contact data this step
+    int32_t record;          // store per-contact data this step (1 every contact, 2 boundary contacts)
     int32_t nonfinite;       // a clump state became NaN/Inf
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
     int64_t pad_c0, pad_c1;
@@ -95,7 +96,7 @@ struct Ctl {
     int32_t stale;               // (second stream) its set was outrun before its adoption: not adopted
     int32_t bslot;               // the structure slot reserved for the second stream's set (never buf);
                                  // in the second stream's block: the slot its detection writes
-    int32_t pad5;
+    int32_t rec_last;            // record mode of the last recorded step (1 all contacts, 2 walls only)
 };
 
 // Detection plan parameters (fixed rule), set by cdem_set_detection.
@@ -196,7 +197,12 @@ struct DevScene {
     Mesh *mesh;                       // [n_mesh], state advanced by k_step_end
     const double *tri_vb;             // [n_tri][9] vertices in the mesh frame
     const int32_t *tri_mesh;          // [n_tri]
-    double *tri_box;                  // [n_tri][6] world bounding box at the detection in progress
+    int64_t n_chunk;
+    const int32_t *chunk_tri;         // [n_chunk + 1] first triangle of each chunk
+    // world boxes (lo[3], hi[3]) at the last detection: [n_tri] triangles,
+    // then [n_chunk] chunks and [n_scenes] scenes, those two grown by the
+    // margins of their meshes
+    double *tri_box;
     Ctl *ctl;
     // big clumps
     const int32_t *big_list;         // clump ids

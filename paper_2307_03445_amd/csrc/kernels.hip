@@ -759,6 +759,28 @@ __device__ __forceinline__ uint32_t narrow_exact_rec(const NarrowSelf &n, const 
     return d2 < Sr * Sr ? r.id : ~0u;
 }
 
+// The triangles of the sphere's scene that may lie within r of point p
+// (within r plus their mesh's margin of their box at the last detection),
+// after the scene's and each chunk's box: f(k, r + margin) for each, in
+// ascending k.
+template <class F>
+__device__ __forceinline__ void tri_near(const DevScene &S, const Grid &g, const double *p, double r, F f) {
+    if (g.chunk_beg >= g.chunk_end) return;
+    auto outside = [&](const double *b, double d) {
+        return p[0] < b[0] - d || p[1] < b[1] - d || p[2] < b[2] - d || p[0] > b[3] + d || p[1] > b[4] + d ||
+               p[2] > b[5] + d;
+    };
+    if (outside(S.tri_box + 6 * (S.n_tri + S.n_chunk + g.sid), r)) return;
+    for (int64_t c = g.chunk_beg; c < g.chunk_end; c++) {
+        if (outside(S.tri_box + 6 * (S.n_tri + c), r)) continue;
+        for (int64_t k = S.chunk_tri[c]; k < S.chunk_tri[c + 1]; k++) {
+            const double lim = r + S.mesh[S.tri_mesh[k]].margin;
+            if (outside(S.tri_box + 6 * k, lim)) continue;
+            f(k, lim);
+        }
+    }
+}
+
 // Boundary candidates of sphere s: phi < R_s + (m_s + boundary margin), for
 // the analytic boundaries of its scene, then the triangles of its scene's
 // meshes (a triangle whose bounding box at this detection is farther than
@@ -772,31 +794,67 @@ __device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid 
         if (phi < n.P.w + ((double)n.ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
     }
     const double p[3] = {n.P.x, n.P.y, n.P.z};
-    for (int64_t k = g.tri_beg; k < g.tri_end; k++) {
-        const Mesh &m = S.mesh[S.tri_mesh[k]];
-        const double lim = n.P.w + ((double)n.ms + m.margin);
-        const double *bx = S.tri_box + 6 * k;
-        if (p[0] < bx[0] - lim || p[1] < bx[1] - lim || p[2] < bx[2] - lim || p[0] > bx[3] + lim ||
-            p[1] > bx[4] + lim || p[2] > bx[5] + lim)
-            continue;
+    tri_near(S, g, p, n.P.w + (double)n.ms, [&](int64_t k, double lim) {
         double phi, nv[3];
         if (tri_distance(S, k, p, phi, nv) && phi < lim) emit((uint32_t)(S.ns + S.n_bnd + k));
-    }
+    });
 }
 
-// Bounding boxes of the triangles at the detection in progress (the meshes'
-// current poses), for the narrow phase's quick rejection.
+// World boxes of the triangles, of their chunks and of each scene's
+// triangles at the detection in progress (the meshes' current poses); the
+// chunk and scene boxes are grown by the margins of their meshes, so they
+// hold every position a triangle takes while the active set is in use.  One
+// wavefront per chunk.
 __global__ void __launch_bounds__(256) k_tri_boxes(DevScene S) {
     if (!due(S.ctl) || aborted(S.ctl)) return;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.n_tri; k += (int64_t)gridDim.x * blockDim.x) {
-        double V[9];
-        tri_world(S, k, V);
-        double *bx = S.tri_box + 6 * k;
-        for (int i = 0; i < 3; i++) {
-            bx[i] = fmin(fmin(V[i], V[3 + i]), V[6 + i]);
-            bx[3 + i] = fmax(fmax(V[i], V[3 + i]), V[6 + i]);
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; c < S.n_chunk; c += nw) {
+        const int64_t k = (int64_t)S.chunk_tri[c] + lane;
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        if (k < S.chunk_tri[c + 1]) {
+            double V[9];
+            tri_world(S, k, V);
+            double *bx = S.tri_box + 6 * k;
+            const double m = S.mesh[S.tri_mesh[k]].margin;
+            for (int i = 0; i < 3; i++) {
+                bx[i] = fmin(fmin(V[i], V[3 + i]), V[6 + i]);
+                bx[3 + i] = fmax(fmax(V[i], V[3 + i]), V[6 + i]);
+                lo[i] = bx[i] - m;
+                hi[i] = bx[3 + i] + m;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1)
+            for (int i = 0; i < 3; i++) {
+                lo[i] = fmin(lo[i], __shfl_xor(lo[i], off, 64));
+                hi[i] = fmax(hi[i], __shfl_xor(hi[i], off, 64));
+            }
+        if (lane == 0) {
+            double *cb = S.tri_box + 6 * (S.n_tri + c);
+            for (int i = 0; i < 3; i++) { cb[i] = lo[i]; cb[3 + i] = hi[i]; }
         }
     }
+}
+// ... and the scene boxes, one workgroup per scene over its chunk boxes.
+__global__ void __launch_bounds__(256) k_tri_scene_boxes(DevScene S) {
+    if (!due(S.ctl) || aborted(S.ctl)) return;
+    const Grid &g = S.grids[blockIdx.x];
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int64_t c = g.chunk_beg + threadIdx.x; c < g.chunk_end; c += blockDim.x) {
+        const double *cb = S.tri_box + 6 * (S.n_tri + c);
+        for (int i = 0; i < 3; i++) { v[i] = fmin(v[i], cb[i]); v[3 + i] = fmax(v[3 + i], cb[3 + i]); }
+    }
+    __shared__ double sh[6][256];
+    for (int i = 0; i < 6; i++) sh[i][threadIdx.x] = v[i];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int i = 0; i < 6; i++)
+                sh[i][threadIdx.x] = i < 3 ? fmin(sh[i][threadIdx.x], sh[i][threadIdx.x + w])
+                                           : fmax(sh[i][threadIdx.x], sh[i][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) S.tri_box[6 * (S.n_tri + S.n_chunk + blockIdx.x) + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 template <class Emit>
@@ -1515,8 +1573,10 @@ __global__ void __launch_bounds__(1024) k_step_end(DevScene S) {
         am = max(am, sh[0][k]); vm = max(vm, sh[1][k]); tr |= sh[2][k]; ncs += shc[k];
     }
     am = max(am, sh[0][0]); vm = max(vm, sh[1][0]); tr |= sh[2][0];
+    const int32_t rec_mode = c->record;
     c->record = 0;
     if (!ok) return;
+    if (rec_mode) c->rec_last = rec_mode;
     c->contact_sides_last = (int64_t)ncs;
     // the clumps too big for one wavefront report through the atomic slots
     c->amax_last = S.detect_mode != 0 ? max(c->amax_bits, am) : 0u;
@@ -1684,14 +1744,16 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
                 if (!in_row((uint32_t)(S.ns + b))) missed++;
             }
         }
+        // the triangles through the boxes of the last detection: grown by
+        // their meshes' margins, they hold the triangles' current positions
         const double p[3] = {P.x, P.y, P.z};
-        for (int64_t k = g.tri_beg; k < g.tri_end; k++) {
+        tri_near(S, g, p, P.w, [&](int64_t k, double) {
             double phi, n[3];
             if (tri_distance(S, k, p, phi, n) && phi < P.w) {
                 found++;
                 if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
             }
-        }
+        });
     }
     __shared__ unsigned long long sh[2][4];
     for (int off = 32; off > 0; off >>= 1) {
@@ -1795,6 +1857,14 @@ __global__ void __launch_bounds__(256) k_adopt_clumps(DevScene S, DevScene B) {
     S.cdet[2 * c] = make_double4(x.x, x.y, x.z, (double)mm);
     S.cdet[2 * c + 1] = q;
 }
+// ... and the triangle boxes of the snapshot's detection (the binned audit
+// finds the triangles through them).
+__global__ void __launch_bounds__(256) k_adopt_boxes(DevScene S, DevScene B) {
+    if (!ahead_ok(B.ctl) || aborted(S.ctl)) return;
+    const int64_t n = 6 * (S.n_tri + S.n_chunk + S.n_scenes);
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+        S.tri_box[k] = B.tri_box[k];
+}
 __global__ void __launch_bounds__(256) k_adopt_big(DevScene S, DevScene B) {
     if (!ahead_ok(B.ctl) || aborted(S.ctl)) return;
     const int32_t c = S.big_list[blockIdx.y];
@@ -1892,6 +1962,38 @@ __global__ void __launch_bounds__(256) k_bnd_partial(DevScene S, double *partial
     if (threadIdx.x < 6) partial[((int64_t)blockIdx.x * kBndParts + blockIdx.y) * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 
+// The triangle contacts of the recorded step, compacted: per sphere, the
+// triangle partners at the end of its row (partners ascend, triangles last)
+// whose contact held, appended as (sphere << 32 | partner, F, lever arm of
+// the mesh) in no particular order; *count receives their number (entries
+// past cap are counted, not written).
+__global__ void __launch_bounds__(256) k_mesh_contacts(DevScene S, unsigned long long *keys, double *FR,
+                                                       unsigned long long *count, int64_t cap) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= S.ns) return;
+    const int cur = S.ctl->buf;
+    const uint32_t beg = slot3(S.lo_beg, cur)[s], cnt = slot3(S.lo_cnt, cur)[s];
+    const uint32_t *nb = slot3(S.pt, cur);
+    const uint32_t t0 = (uint32_t)(S.ns + S.n_bnd);
+    for (uint32_t k = cnt; k-- > 0;) {
+        const int64_t e = (int64_t)beg + k;
+        const uint32_t t = nb[e];
+        if (t < t0) break;
+        if (S.rec_state[e] != 1 || !(S.rec_delta[e] > 0.0)) continue;
+        const unsigned long long i = atomicAdd(count, 1ull);
+        if ((int64_t)i >= cap) continue;
+        keys[i] = ((unsigned long long)s << 32) | t;
+        for (int j = 0; j < 3; j++) { FR[6 * i + j] = S.rec_F[3 * e + j]; FR[6 * i + 3 + j] = S.rec_R[3 * e + j]; }
+    }
+}
+
+hipError_t launch_mesh_contacts(const DevScene &S, unsigned long long *keys, double *FR, unsigned long long *count,
+                                int64_t cap, hipStream_t st) {
+    if (S.ns == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mesh_contacts, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, keys, FR, count, cap);
+    return hipGetLastError();
+}
+
 __global__ void k_bnd_final(int n_bnd, const double *partial, double *out) {
     const int b = blockIdx.x, i = threadIdx.x;
     if (b >= n_bnd || i >= 6) return;
@@ -1966,7 +2068,10 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     if (S.ns == 0) return hipSuccess;
     TIMED(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(1), 0, st, S));
     binning(S, 0, st);
-    if (S.n_tri) hipLaunchKernelGGL(k_tri_boxes, dim3(stride_blocks(S.n_tri, 1024)), dim3(256), 0, st, S);
+    if (S.n_tri) {
+        hipLaunchKernelGGL(k_tri_boxes, dim3(stride_blocks(S.n_chunk * 64, 1024)), dim3(256), 0, st, S);
+        hipLaunchKernelGGL(k_tri_scene_boxes, dim3(S.n_scenes), dim3(256), 0, st, S);
+    }
     TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
     TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
     TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
@@ -1992,6 +2097,9 @@ hipError_t launch_adopt(const DevScene &S, const DevScene &B, hipStream_t st) {
     hipLaunchKernelGGL(k_adopt_rows, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, (const Ctl *)B.ctl);
     hipLaunchKernelGGL(k_adopt_clumps, dim3(blocks_for(S.nc, 256)), dim3(256), 0, st, S, B);
     if (S.n_big) hipLaunchKernelGGL(k_adopt_big, dim3(16, S.n_big), dim3(256), 0, st, S, B);
+    if (S.n_tri)
+        hipLaunchKernelGGL(k_adopt_boxes, dim3(stride_blocks(6 * (S.n_tri + S.n_chunk + S.n_scenes), 256)), dim3(256),
+                           0, st, S, B);
     hipLaunchKernelGGL(k_adopt_end, dim3(1), dim3(1), 0, st, S, (const Ctl *)B.ctl);
     return hipGetLastError();
 }

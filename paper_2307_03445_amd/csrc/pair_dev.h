@@ -188,15 +188,17 @@ struct WallView {
     double ref[3], vel[3], omg[3];
 };
 
+// rec_mode: 0 nothing recorded, 1 every pair, 2 boundary pairs only
 template <bool FP32, class Law>
 __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
-                                              double tnow, bool rec) {
+                                              double tnow, int rec_mode) {
     using V = typename Contrib<FP32>::V;
     V *cS = (V *)S.cS, *cTs = (V *)S.cTs, *cTt = (V *)S.cTt;
     const double zero3[3] = {0.0, 0.0, 0.0};
     const uint32_t s = id.s, t = id.t;
     double *h = hist + 3 * e;
     if (t < (uint32_t)S.ns) {
+        const bool rec = rec_mode == 1;
         const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
         const SphereKin ka = sphere_kin_of(S, id.ca, id.ta), kb = sphere_kin_of(S, id.cb, id.tb);
         double dv[3], dc[3];
@@ -264,6 +266,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         }
         return 2;
     }
+    const bool rec = rec_mode != 0;
     // boundary pair: the boundary is body a, sphere s is body b; an analytic
     // boundary, or a triangle of a mesh (its mesh's reference point, motion
     // and material)
@@ -347,7 +350,7 @@ __device__ __forceinline__ void pairs_body(const DevScene &S) {
     const uint32_t *pt = slot3(S.pt, cur), *ps = slot3(S.ps, cur);
     double *hist = pick(S.hist, S.ctl->hb);
     const int64_t n = S.ctl->n_pairs_cur;
-    const bool rec = S.ctl->record != 0;
+    const int rec = S.ctl->record;
     const double tnow = (double)S.ctl->step * S.h;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t e = (int64_t)xcd_block() * blockDim.x + threadIdx.x;

@@ -1250,6 +1250,12 @@ def batch(descs) -> SceneDesc:
         bnd_type=np.concatenate([d.bnd_type for d in descs]), bnd_param=np.concatenate([d.bnd_param for d in descs]),
         bnd_mat=np.concatenate([d.bnd_mat for d in descs]), bnd_vel=np.concatenate([d.bnd_vel for d in descs]),
         bnd_omega=np.concatenate([d.bnd_omega for d in descs]), bnd_scene=np.concatenate(bs),
+        mesh_state=np.concatenate([d.mesh_state for d in descs]),
+        mesh_mat=np.concatenate([d.mesh_mat for d in descs]),
+        mesh_scene=np.concatenate([np.full(d.n_mesh, k, np.int32) for k, d in enumerate(descs)]),
+        tri_mesh=np.concatenate([d.tri_mesh.astype(np.int64) + nm for d, nm in
+                                 zip(descs, np.cumsum([0] + [d.n_mesh for d in descs]))]).astype(np.int32),
+        tri_vertex=np.concatenate([d.tri_vertex for d in descs]),
         name="batch-" + "+".join(d.name for d in descs))
     if any(d.presc_clump.size for d in descs):
         raise ValueError("batch takes scenes without prescribed clumps")

@@ -165,3 +165,73 @@ def test_exhaustive_audit_covers_triangles(mbin):
     sc.step(40)
     r = sc.audit()
     assert r["missed"] == 0 and r["true_contacts"] > 500, r
+
+
+def test_batched_mesh_scenes_each_as_alone():
+    """Three mesh bins in one batch (triangles sorted by scene, per-scene
+    triangle chunks): each scene's contacts and mesh forces are those of the
+    scene run alone, bit for bit, and of the oracle."""
+    descs = [I.mesh_bin(replica=r, n_clumps=300) for r in range(3)]
+    b = I.batch(descs)
+    sb = _scene(b, mode="fixed")
+    sb.step(60)
+    sb.record_next_step()
+    sb.step(1)
+    cb = sb.contacts()
+    Fb, Tb = sb.mesh_forces()
+    ob = oracle.Oracle(b)
+    ob.step(60)
+    ob.eval()
+    compare_pairs(cb, ob.contacts())
+    Fo, To = ob.mesh_forces()
+    assert np.array_equal(Fb, Fo) and np.array_equal(Tb, To)
+    s_off = c_off = 0
+    for k, d in enumerate(descs):
+        a = _scene(d, mode="fixed")
+        a.step(60)
+        a.record_next_step()
+        a.step(1)
+        Fa, Ta = a.mesh_forces()
+        assert np.array_equal(Fa, Fb[2 * k:2 * k + 2]) and np.array_equal(Ta, Tb[2 * k:2 * k + 2])
+        st = a.state()
+        assert np.array_equal(st["x"], sb.state()["x"][c_off:c_off + d.n_clumps])
+        s_off += d.n_spheres
+        c_off += d.n_clumps
+
+
+def test_walls_only_recording(mbin):
+    """Recording only the boundary contacts gives the same boundary contacts,
+    mesh forces and clump forces as recording every contact."""
+    a, b = _scene(mbin, mode="fixed"), _scene(mbin, mode="fixed")
+    a.step(40)
+    b.step(40)
+    a.record_next_step()
+    b.record_next_step(walls_only=True)
+    a.step(1)
+    b.step(1)
+    ca, cb = a.contacts(), b.contacts()
+    wall = ca["b"] >= mbin.n_spheres
+    assert wall.sum() > 50 and (cb["b"] >= mbin.n_spheres).all()
+    for k in ("a", "b", "delta", "F", "u", "Ta", "Tb"):
+        assert np.array_equal(ca[k][wall], cb[k]), k
+    for x, y in zip(a.mesh_forces(), b.mesh_forces()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.clump_forces(), b.clump_forces()):
+        assert np.array_equal(x, y)
+
+
+def test_recorded_step_that_regrows_storage_still_records(mbin, monkeypatch):
+    monkeypatch.setenv("CDEM_INITIAL_CAPACITY", "512")
+    small = _scene(mbin)
+    monkeypatch.delenv("CDEM_INITIAL_CAPACITY")
+    o = oracle.Oracle(mbin)
+    small.record_next_step()
+    small.step(1)
+    assert small.counts()["regrows"] >= 1
+    o.eval()
+    cg, co = small.contacts(), o.contacts()
+    compare_pairs(cg, co)
+    assert np.array_equal(cg["F"], co["F"])
+    Fg, _ = small.mesh_forces()
+    Fo, _ = o.mesh_forces()
+    assert np.array_equal(Fg, Fo)
