@@ -15,6 +15,7 @@ CPU oracle timed on the host cores.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -129,6 +130,53 @@ def make_scene(desc, mode, mlp=None, detect=None, precision="fp32"):
     return sc
 
 
+class WheelCosim:
+    """The multibody side of a co-simulation with a wheel mesh (Sec. 5.2): a
+    rigid wheel with a free vertical degree of freedom under a total load,
+    driven at fixed forward and angular velocities.  Every `every` steps it
+    records one step's boundary contacts, reads the force the spheres exert
+    on the wheel, and prescribes the wheel's vertical velocity for the next
+    interval (explicit Euler over the interval).  Works on a GPU scene or on
+    the oracle (same exchanges, same numbers)."""
+
+    def __init__(self, mesh=0, mass=10.0, load=100.0, every=10, h=1e-6):
+        self.mesh, self.mass, self.load, self.every, self.h = mesh, mass, load, every, h
+        self.since = 0
+        self.exchanges = 0
+        self.exchange_s = 0.0
+        self.last_force = None
+
+    def advance(self, sim, n, step=None):
+        step = step or (lambda k: sim.step(k))
+        gpu = hasattr(sim, "record_next_step")
+        done = 0
+        while done < n:
+            k = min(self.every - 1 - self.since, n - done)
+            if k > 0:
+                step(k)
+                done += k
+                self.since += k
+                continue
+            if gpu:
+                sim.record_next_step(walls_only=True)
+                step(1)
+                t0 = time.perf_counter()
+                F, _ = sim.mesh_forces()
+            else:
+                sim.eval()
+                F, _ = sim.mesh_forces()
+                sim.step(1)
+                t0 = time.perf_counter()
+            done += 1
+            st = sim.mesh_state()[self.mesh].copy()
+            st[9] = st[9] + (self.every * self.h) * ((F[self.mesh][2] - self.load) / self.mass)
+            sim.set_mesh_state(self.mesh, st)
+            self.exchange_s += time.perf_counter() - t0
+            self.last_force = F[self.mesh].copy()
+            self.since = 0
+            self.exchanges += 1
+
+
 def _steps_reporting_misses(sc, n, label):
     """Advance n steps; an audit that finds a missed contact still ran its
     steps: report it instead of stopping the benchmark."""
@@ -142,7 +190,7 @@ def _steps_reporting_misses(sc, n, label):
 
 
 def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=None, precision="fp32",
-             overlap=False):
+             overlap=False, cosim=None):
     """Time `steps` steps of one path after warmup and the autotuner.
 
     Inside the timed region only the roofline kernel is bracketed by events
@@ -156,8 +204,12 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
     detect = detect or DETECT
     period = detect["audit_period"] if mode != "plain" else 0
     sc = make_scene(desc, mode, mlp, detect, precision)
+    if cosim:  # every step of the warmup and of the window goes through the exchanges
+        advance = lambda n: cosim.advance(sc, n, step=lambda k: _steps_reporting_misses(sc, k, label))
+    else:
+        advance = lambda n: _steps_reporting_misses(sc, n, label)
     t0 = time.perf_counter()
-    sc.step(warmup)
+    advance(warmup)
     # bin size and launch shape from the library's autotuner (its trials are
     # ordinary steps, each of one detection and the steps up to the next at
     # the interval bound), then steps to settle before timing
@@ -166,20 +218,25 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
         sc.set_detection(mode, **dict(detect, overlap=True))
     if graph:
         sc.set_graph(graph)
-    sc.step(warmup)
+    advance(warmup)
     log(f"[{label}] warmup {2 * warmup} steps and autotuning ({tune}): {time.perf_counter() - t0:.2f} s")
     c0 = sc.counts()
     if not graph:
         sc.profile(True, only=(ROOFLINE_KERNEL,))
+    ex0 = (cosim.exchanges, cosim.exchange_s) if cosim else None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     done = 0
     while done < steps:
         n = min(period, steps - done) if period else steps - done
-        _steps_reporting_misses(sc, n, label)
+        advance(n)
         done += n
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    cos = None
+    if cosim:
+        cos = dict(every=cosim.every, exchanges=cosim.exchanges - ex0[0],
+                   exchange_ms=(cosim.exchange_s - ex0[1]) * 1e3, wheel_force=cosim.last_force.tolist())
     prof_timed = sc.profile_read() if not graph else {}
     c1 = sc.counts()
     contact_sides = sc.last_step_contacts()
@@ -212,7 +269,7 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
         log(f"    {k:22s} launches {n:6d} total {ms:9.2f} ms  avg {ms / n * 1e3:9.1f} us")
     return dict(seconds=dt, prof=prof, prof_timed=prof_timed, counts=c1, detections=dets, window=window,
                 contact_sides=contact_sides, guard_trips=window["guard_trips"], tune=tune, steps=steps,
-                audit=audit, pass_detections=c2["detections"] - c1["detections"], graph=graph)
+                audit=audit, pass_detections=c2["detections"] - c1["detections"], graph=graph, cosim=cos)
 
 
 KERNEL_SOURCES = ("paper_2307_03445_amd/csrc/kernels.hip", "paper_2307_03445_amd/csrc/cdem_internal.h",
@@ -360,12 +417,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--clumps", type=int, default=11_000_000)
-    ap.add_argument("--modes", default="plain,fixed,learned,learned_overlap,learned_graph,batched,precision",
+    ap.add_argument("--modes", default="plain,fixed,learned,learned_overlap,learned_graph,learned_fixed_point,"
+                                       "mesh_cosim,batched,precision",
                     help="paths to time: plain, fixed, learned (rover bed), learned_overlap (the learned path "
                          "with the next active set built on a second stream while the steps go on), "
-                         "learned_graph (the learned path replayed from captured graphs), batched (256 funnel "
-                         "scenes, learned, graphs), precision (the 4M-clump drum, learned, all-FP64 vs FP32 "
-                         "force arithmetic)")
+                         "learned_graph (the learned path replayed from captured graphs), learned_fixed_point "
+                         "(the learned path with fixed-point clump positions, 2^-40 m), mesh_cosim (the bed with "
+                         "the wheel as a triangle mesh, co-simulated: one exchange of wheel force and velocity "
+                         "every 10 steps), batched (256 funnel scenes, learned, graphs), precision (the "
+                         "4M-clump drum, learned, all-FP64 vs FP32 force arithmetic)")
     ap.add_argument("--mlp", default=None, help="npz with envelope-MLP parameters (default: the package's "
                                                 "trained weights, else train now)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -415,9 +475,11 @@ def main():
     from paper_2307_03445_amd import prep
     torch.cuda.set_device(0)
     modes = args.modes.split(",")
-    rover_modes = [m for m in modes if m in ("plain", "fixed", "learned", "learned_overlap", "learned_graph")]
+    rover_modes = [m for m in modes if m in ("plain", "fixed", "learned", "learned_overlap", "learned_graph",
+                                             "learned_fixed_point")]
     mlp, mlp_info = None, None
-    if any(m in modes for m in ("learned", "learned_graph", "batched", "precision")):
+    if any(m in modes for m in ("learned", "learned_graph", "learned_fixed_point", "mesh_cosim", "batched",
+                                "precision")):
         from paper_2307_03445_amd import train
         path = args.mlp or train.WEIGHTS
         if os.path.exists(path):
@@ -425,7 +487,7 @@ def main():
             mlp_info = f"loaded {os.path.relpath(path, ROOT)}"
     results, desc = {}, None
     px = pq = None
-    if rover_modes or "precision" in modes:
+    if rover_modes or "precision" in modes or "mesh_cosim" in modes:
         t0 = time.perf_counter()
         if args.patch_cache and os.path.exists(args.patch_cache):
             z = np.load(args.patch_cache)
@@ -436,7 +498,7 @@ def main():
             log(f"patch settled: {info}")
             if args.patch_cache:
                 np.savez(args.patch_cache, x=px, q=pq)
-        if mlp is None and any(m.startswith("learned") for m in rover_modes):
+        if mlp is None and (any(m.startswith("learned") for m in rover_modes) or "mesh_cosim" in modes):
             from paper_2307_03445_amd import train
             t1 = time.perf_counter()
             mlp, info = train.train(px, pq, log=log)
@@ -447,9 +509,26 @@ def main():
         log(f"envelope MLP: {mlp_info}")
         for mode in rover_modes:
             base = "learned" if mode.startswith("learned") else mode
-            results[mode] = run_path(desc, base, args.steps, args.warmup, mlp=mlp,
+            d = dataclasses.replace(desc, pos_exp=40) if mode == "learned_fixed_point" else desc
+            results[mode] = run_path(d, base, args.steps, args.warmup, mlp=mlp,
                                      graph=args.steps if mode == "learned_graph" else 0, label=mode,
                                      overlap=mode == "learned_overlap")
+    mesh_cosim = None
+    if "mesh_cosim" in modes:
+        t0 = time.perf_counter()
+        mdesc = I.rover_bed(px, pq, n_clumps=args.clumps, wheel="mesh")
+        log(f"mesh co-simulation workload: {mdesc.n_clumps} clumps, {mdesc.n_spheres} spheres, wheel of "
+            f"{mdesc.n_tri} triangles, built in {time.perf_counter() - t0:.1f} s")
+        rm = run_path(mdesc, "learned", args.steps, args.warmup, mlp=mlp, label="mesh_cosim",
+                      cosim=WheelCosim(mesh=0, mass=10.0, load=100.0, every=10, h=mdesc.h))
+        mstats = dict(spheres=mdesc.n_spheres, clumps=mdesc.n_clumps, fp32=True, bins=rm["counts"]["bins"])
+        mesh_cosim = dict(path_line(rm, mdesc.n_spheres, mstats, "learned"),
+                          workload=f"rover-scale bed of {mdesc.n_clumps} clumps, {mdesc.n_spheres} spheres, with the "
+                                   f"wheel as a mesh of {mdesc.n_tri} triangles (R = 0.254 m rim, 12 grousers) "
+                                   f"driven at slip 0.2 and co-simulated: every 10 steps one step's boundary "
+                                   f"contacts are recorded, the wheel force read and its vertical velocity "
+                                   f"prescribed (10 kg, 100 N load), learned interval",
+                          cosim=rm["cosim"], roofline=roofline(rm, mstats, "learned"))
     batched = None
     if "batched" in modes:
         t0 = time.perf_counter()
@@ -486,7 +565,7 @@ def main():
         precision["fp32_over_fp64"] = (precision["fp32"]["sphere_steps_per_s"] /
                                        precision["fp64"]["sphere_steps_per_s"])
     if not results:
-        line = {"metric": METRIC, "batched": batched, "precision": precision}
+        line = {"metric": METRIC, "batched": batched, "precision": precision, "mesh_cosim": mesh_cosim}
         print(json.dumps(line), flush=True)
         return
     main_mode = "learned" if "learned" in results else (
@@ -522,6 +601,8 @@ def main():
         line["speedup_vs_plain"] = main["sphere_steps_per_s"] / paths["plain"]["sphere_steps_per_s"]
     if batched:
         line["batched"] = batched
+    if mesh_cosim:
+        line["mesh_cosim"] = mesh_cosim
     if precision:
         line["precision"] = precision
     if not args.no_cpu:

@@ -785,7 +785,7 @@ __device__ __forceinline__ void tri_near(const DevScene &S, const Grid &g, const
 // the analytic boundaries of its scene, then the triangles of its scene's
 // meshes (a triangle whose bounding box at this detection is farther than
 // that is skipped without the distance).
-template <class Emit>
+template <bool TRI, class Emit>
 __device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid &g, const NarrowSelf &n, Emit emit) {
     const double tnow = (double)S.ctl->step * S.h;
     for (int b = g.bnd_beg; b < g.bnd_end; b++) {
@@ -793,11 +793,13 @@ __device__ __forceinline__ void narrow_boundaries(const DevScene &S, const Grid 
         if (!bnd_distance(S.bnd[b], tnow, n.P.x, n.P.y, n.P.z, phi, nv)) continue;
         if (phi < n.P.w + ((double)n.ms + S.bnd[b].margin)) emit((uint32_t)(S.ns + b));
     }
-    const double p[3] = {n.P.x, n.P.y, n.P.z};
-    tri_near(S, g, p, n.P.w + (double)n.ms, [&](int64_t k, double lim) {
-        double phi, nv[3];
-        if (tri_distance(S, k, p, phi, nv) && phi < lim) emit((uint32_t)(S.ns + S.n_bnd + k));
-    });
+    if constexpr (TRI) {
+        const double p[3] = {n.P.x, n.P.y, n.P.z};
+        tri_near(S, g, p, n.P.w + (double)n.ms, [&](int64_t k, double lim) {
+            double phi, nv[3];
+            if (tri_distance(S, k, p, phi, nv) && phi < lim) emit((uint32_t)(S.ns + S.n_bnd + k));
+        });
+    }
 }
 
 // World boxes of the triangles, of their chunks and of each scene's
@@ -857,7 +859,7 @@ __global__ void __launch_bounds__(256) k_tri_scene_boxes(DevScene S) {
     if (threadIdx.x < 6) S.tri_box[6 * (S.n_tri + S.n_chunk + blockIdx.x) + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-template <class Emit>
+template <bool TRI, class Emit>
 __device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s, Emit emit) {
     const Grid &g = S.grids[S.sscene[s]];
     const NarrowSelf n = narrow_self(S, g, s);
@@ -868,7 +870,7 @@ __device__ __forceinline__ void narrow_candidates(const DevScene &S, uint32_t s,
             if (t != ~0u) emit(t);
         }
     });
-    narrow_boundaries(S, g, n, emit);
+    narrow_boundaries<TRI>(S, g, n, emit);
 }
 
 // Carry the tangential history of sphere s's new lower segment (partners
@@ -925,6 +927,8 @@ __device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32
 // kept sorted in LDS; a sphere with more gets its segments allocated here and
 // filled by k_narrow_over.  Segments are allocated with one atomic per
 // wavefront and kind (upper entries, pairs).
+// TRI: the scene has triangles (the kernel without them keeps fewer registers).
+template <bool TRI>
 __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
     // overflow may be raised by other workgroups of this launch: one read per
     // workgroup keeps the decision uniform across its barriers
@@ -983,9 +987,9 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
                     if (t1 != ~0u) emit(t1);
                 }
             }
-            narrow_boundaries(S, g, n, emit);
+            narrow_boundaries<TRI>(S, g, n, emit);
         } else {
-            narrow_candidates(S, s, emit);  // many slots pass the prefilter: one exact pass
+            narrow_candidates<TRI>(S, s, emit);  // many slots pass the prefilter: one exact pass
         }
     }
     const int nlo = cnt - nup;
@@ -1031,6 +1035,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
 
 // Segments of the spheres with more than kMaxRow candidates: the same scan,
 // each segment kept sorted in place in the active set.
+template <bool TRI>
 __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
     const Ctl *c = S.ctl;
     if (!due(c) || c->overflow || c->row_overflow) return;
@@ -1044,7 +1049,7 @@ __global__ void __launch_bounds__(64) k_narrow_over(DevScene S) {
         uint32_t *lrow = slot3(S.pt, out) + lb;
         uint32_t mu = 0, ml = 0;
         // the predicate is the one that sized the segments: the counts cannot be exceeded
-        narrow_candidates(S, s, [&](uint32_t t) {
+        narrow_candidates<TRI>(S, s, [&](uint32_t t) {
             uint32_t *row = t < s ? urow : lrow;
             uint32_t &m = t < s ? mu : ml;
             if (m >= (t < s ? nu : nl)) return;
@@ -1101,9 +1106,11 @@ __global__ void k_detect_end(DevScene S) {
     c->guard = 0;
 }
 
-template <bool FP32>
+// Instantiated per force precision, kind of positions and presence of
+// triangles, so that each scene runs a pair kernel without the others' code.
+template <bool FP32, int FX, bool TRI>
 __global__ void __launch_bounds__(256) k_pairs(DevScene S) {
-    pairs_body<FP32, HertzMindlin>(S);
+    pairs_body<FP32, HertzMindlin, FX, TRI>(S);
 }
 
 // Contact sides of the last evaluated step (each sphere pair in contact counts
@@ -1661,6 +1668,7 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // ---------------------------------------------------------------- binned audit
 // Exact contacts of the current positions, found in freshly built bins with no
 // margin, must each be in both partners' rows of the active set.
+template <bool TRI>
 __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
     // an abandoned step (active-set overflow) is audited when it is run again
     if (!audit_due(S) || aborted(S.ctl)) return;
@@ -1746,14 +1754,16 @@ __global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
         }
         // the triangles through the boxes of the last detection: grown by
         // their meshes' margins, they hold the triangles' current positions
-        const double p[3] = {P.x, P.y, P.z};
-        tri_near(S, g, p, P.w, [&](int64_t k, double) {
-            double phi, n[3];
-            if (tri_distance(S, k, p, phi, n) && phi < P.w) {
-                found++;
-                if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
-            }
-        });
+        if constexpr (TRI) {
+            const double p[3] = {P.x, P.y, P.z};
+            tri_near(S, g, p, P.w, [&](int64_t k, double) {
+                double phi, n[3];
+                if (tri_distance(S, k, p, phi, n) && phi < P.w) {
+                    found++;
+                    if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
+                }
+            });
+        }
     }
     __shared__ unsigned long long sh[2][4];
     for (int off = 32; off > 0; off >>= 1) {
@@ -2072,8 +2082,13 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
         hipLaunchKernelGGL(k_tri_boxes, dim3(stride_blocks(S.n_chunk * 64, 1024)), dim3(256), 0, st, S);
         hipLaunchKernelGGL(k_tri_scene_boxes, dim3(S.n_scenes), dim3(256), 0, st, S);
     }
-    TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
-    TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over, dim3(256), dim3(64), 0, st, S));
+    if (S.n_tri) {
+        TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<true>, dim3(256), dim3(64), 0, st, S));
+    } else {
+        TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<false>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<false>, dim3(256), dim3(64), 0, st, S));
+    }
     TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
     return hipGetLastError();
@@ -2139,7 +2154,8 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     if (S.ns == 0 || S.plan.audit_period <= 0) return hipSuccess;
     if (g_timer) g_timer->before(K_AUDIT_ALL, st);
     binning(S, 1, st);
-    TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
+    if (S.n_tri) TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<true>, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
+    else TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<false>, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
     hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1024), 0, st, S);
     if (g_timer) g_timer->after(K_AUDIT_ALL, st);
     return hipGetLastError();
@@ -2155,10 +2171,20 @@ hipError_t launch_force_integrate(const DevScene &S, hipStream_t st, hipFunction
         hipError_t e = hipSuccess;
         TIMED(K_FORCE, e = hipModuleLaunchKernel(user_pairs, pb, 1, 1, 256, 1, 1, 0, st, args, nullptr));
         if (e != hipSuccess) return e;
-    } else if (f32) {
-        TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<true>, dim3(pb), dim3(256), 0, st, S));
     } else {
-        TIMED(K_FORCE, hipLaunchKernelGGL(k_pairs<false>, dim3(pb), dim3(256), 0, st, S));
+        const int sel = (f32 ? 4 : 0) + (S.pos_exp ? 2 : 0) + (S.n_tri ? 1 : 0);
+#define CDEM_PAIRS(A, B, C) TIMED(K_FORCE, hipLaunchKernelGGL((k_pairs<A, B, C>), dim3(pb), dim3(256), 0, st, S))
+        switch (sel) {
+            case 0: CDEM_PAIRS(false, 0, false); break;
+            case 1: CDEM_PAIRS(false, 0, true); break;
+            case 2: CDEM_PAIRS(false, 1, false); break;
+            case 3: CDEM_PAIRS(false, 1, true); break;
+            case 4: CDEM_PAIRS(true, 0, false); break;
+            case 5: CDEM_PAIRS(true, 0, true); break;
+            case 6: CDEM_PAIRS(true, 1, false); break;
+            default: CDEM_PAIRS(true, 1, true); break;
+        }
+#undef CDEM_PAIRS
     }
     unsigned wb = (unsigned)((S.n_waves + 3) / 4);
     if (wb) {

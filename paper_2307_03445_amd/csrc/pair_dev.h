@@ -188,8 +188,9 @@ struct WallView {
     double ref[3], vel[3], omg[3];
 };
 
-// rec_mode: 0 nothing recorded, 1 every pair, 2 boundary pairs only
-template <bool FP32, class Law>
+// rec_mode: 0 nothing recorded, 1 every pair, 2 boundary pairs only.  F:
+// fixed-point positions (see fixed_pos); TRI: the scene may have triangles.
+template <bool FP32, class Law, int FX, bool TRI>
 __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
                                               double tnow, int rec_mode) {
     using V = typename Contrib<FP32>::V;
@@ -200,9 +201,9 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     if (t < (uint32_t)S.ns) {
         const bool rec = rec_mode == 1;
         const uint32_t a = s, b = t;  // a < b: pairs live in the lower sphere's segment
-        const SphereKin ka = sphere_kin_of(S, id.ca, id.ta), kb = sphere_kin_of(S, id.cb, id.tb);
+        const SphereKin ka = sphere_kin_of<FX>(S, id.ca, id.ta), kb = sphere_kin_of<FX>(S, id.cb, id.tb);
         double dv[3], dc[3];
-        sphere_vec(S, ka, kb, dv, dc);
+        sphere_vec<FX>(S, ka, kb, dv, dc);
         double dx = dv[0], dy = dv[1], dz = dv[2];
         double d2 = dx * dx + dy * dy + dz * dz;
         double Sr = ka.R + kb.R;
@@ -223,7 +224,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         double n[3] = {dx / d, dy / d, dz / d};
         double lever = ka.R - 0.5 * delta;
         double ra[3], rb[3];  // lever arms from the two CoMs to the contact point
-        if (!S.pos_exp) {
+        if (!fixed_pos<FX>(S)) {
             double p[3] = {ka.p[0] + lever * n[0], ka.p[1] + lever * n[1], ka.p[2] + lever * n[2]};
             for (int i = 0; i < 3; i++) { ra[i] = p[i] - ka.xc[i]; rb[i] = p[i] - kb.xc[i]; }
         } else {  // a's rotated offset, then along n; from b's CoM, less the CoM difference
@@ -271,8 +272,8 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     // boundary, or a triangle of a mesh (its mesh's reference point, motion
     // and material)
     const uint32_t wi = t - (uint32_t)S.ns;
-    const bool tri = wi >= (uint32_t)S.n_bnd;
-    const SphereKin ks = sphere_kin_of(S, id.ca, id.ta);
+    const bool tri = TRI && wi >= (uint32_t)S.n_bnd;
+    const SphereKin ks = sphere_kin_of<FX>(S, id.ca, id.ta);
     double phi, n[3];
     WallView B;
     bool contact;
@@ -302,7 +303,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     const double *cw = B.ref;
     double ra[3] = {p[0] - cw[0], p[1] - cw[1], p[2] - cw[2]};
     double rb[3];
-    for (int i = 0; i < 3; i++) rb[i] = S.pos_exp ? ks.r[i] - lever * n[i] : p[i] - ks.xc[i];
+    for (int i = 0; i < 3; i++) rb[i] = fixed_pos<FX>(S) ? ks.r[i] - lever * n[i] : p[i] - ks.xc[i];
     double pw[3], cb3[3];
     cross3(B.omg, ra, pw);
     cross3(ks.W, rb, cb3);
@@ -343,7 +344,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
 // spatially coherent): the body of the pair kernel, for the built-in law
 // (k_pairs) and for a user law compiled at run time.  256 lanes per
 // workgroup.
-template <bool FP32, class Law>
+template <bool FP32, class Law, int FX = 2, bool TRI = true>
 __device__ __forceinline__ void pairs_body(const DevScene &S) {
     if (aborted(S.ctl)) return;
     const int cur = S.ctl->buf;
@@ -365,7 +366,7 @@ __device__ __forceinline__ void pairs_body(const DevScene &S) {
         PairIds nxt{};
         if (e + stride < n) nxt = pair_ids(S, s2, t2);
         if (e + 2 * stride < n) { s2 = ps[e + 2 * stride]; t2 = pt[e + 2 * stride]; }
-        sides += eval_pair<FP32, Law>(S, e, now, hist, tnow, rec);
+        sides += eval_pair<FP32, Law, FX, TRI>(S, e, now, hist, tnow, rec);
         now = nxt;
     }
     // the workgroup's count, for the interval rule (folded by k_step_end)

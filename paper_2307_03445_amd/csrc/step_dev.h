@@ -51,6 +51,12 @@ __device__ __forceinline__ double fx_decode(const DevScene &S, long long k) { re
 __device__ __forceinline__ double fx_diff(const DevScene &S, double a, double b) {
     return (double)(fx_bits(a) - fx_bits(b)) * S.pos_eps;
 }
+// Fixed-point positions on a code path: F = 0 never, 1 always (kernels
+// instantiated for one kind of scene, with the other path compiled out),
+// 2 as the scene says.
+template <int FX>
+__device__ __forceinline__ bool fixed_pos(const DevScene &S) { return FX == 2 ? S.pos_exp != 0 : FX == 1; }
+
 // Integer positions stay below 2^61 in magnitude (a quarter of the range).
 constexpr long long kFxLimit = 1LL << 61;
 // x += h v: in FP64, or with the increment rounded to the grid (ties to
@@ -81,6 +87,7 @@ __device__ __forceinline__ bool advance_position(const DevScene &S, double *x, c
 // numbers.
 struct SphereKin { double p[3], R, xc[3], M, v[3], W[3], r[3], cq[3]; };
 // ... of the sphere that is template sphere ts of clump c
+template <int FX = 2>
 __device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c, uint32_t ts) {
     const double4 *r = S.cst + 4 * (int64_t)c;
     const double4 k0 = r[0], k1 = r[1], k2 = r[2], k3 = r[3];
@@ -93,7 +100,7 @@ __device__ __forceinline__ SphereKin sphere_kin_of(const DevScene &S, uint32_t c
     k.r[1] = A[3] * o0 + A[4] * o1 + A[5] * o2;
     k.r[2] = A[6] * o0 + A[7] * o1 + A[8] * o2;
     k.cq[0] = k0.x; k.cq[1] = k0.y; k.cq[2] = k0.z;
-    if (S.pos_exp) {
+    if (fixed_pos<FX>(S)) {
         k.xc[0] = fx_decode(S, fx_bits(k0.x)); k.xc[1] = fx_decode(S, fx_bits(k0.y)); k.xc[2] = fx_decode(S, fx_bits(k0.z));
     } else {
         k.xc[0] = k0.x; k.xc[1] = k0.y; k.xc[2] = k0.z;
@@ -114,9 +121,10 @@ __device__ __forceinline__ SphereKin sphere_kin(const DevScene &S, uint32_t s) {
 // Vector d from sphere a to sphere b: the difference of their centres, or
 // with fixed-point positions the exact CoM difference dc plus the difference
 // of the rotated offsets.
+template <int FX = 2>
 __device__ __forceinline__ void sphere_vec(const DevScene &S, const SphereKin &a, const SphereKin &b, double *d,
                                            double *dc) {
-    if (S.pos_exp) {
+    if (fixed_pos<FX>(S)) {
         for (int i = 0; i < 3; i++) {
             dc[i] = fx_diff(S, b.cq[i], a.cq[i]);
             d[i] = dc[i] + (b.r[i] - a.r[i]);

@@ -655,6 +655,37 @@ def wheel_template(n_spheres=20000, R=0.25, width=0.2, r=4e-3, n_grouser=12, mas
     return off, np.full(off.shape[0], r), float(mass), np.array([I_other, I_axle, I_other])
 
 
+def wheel_mesh(R=0.254, width=0.2, n_theta=120, n_grouser=12, gh=8e-3, gt=8e-3):
+    """A rigid wheel as a triangle mesh in its body frame (axle along y,
+    centre at the origin): a cylindrical rim of radius R (n_theta facets),
+    two end discs, and n_grouser grousers, boxes gh tall and gt thick across
+    the full width, standing on the rim.  Returns [n][3][3] vertices."""
+    tris = []
+    th = 2 * np.pi * np.arange(n_theta + 1) / n_theta
+    y0, y1 = -width / 2, width / 2
+    for i in range(n_theta):
+        a = (R * np.cos(th[i]), R * np.sin(th[i]))
+        b = (R * np.cos(th[i + 1]), R * np.sin(th[i + 1]))
+        p00, p01 = (a[0], y0, a[1]), (a[0], y1, a[1])
+        p10, p11 = (b[0], y0, b[1]), (b[0], y1, b[1])
+        tris += [(p00, p10, p11), (p00, p11, p01)]
+        tris += [((0.0, y0, 0.0), p10, p00), ((0.0, y1, 0.0), p01, p11)]
+    for j in range(n_grouser):
+        ph = 2 * np.pi * (j + 0.5) / n_grouser
+        er, et = np.array([np.cos(ph), 0.0, np.sin(ph)]), np.array([-np.sin(ph), 0.0, np.cos(ph)])
+        ey = np.array([0.0, 1.0, 0.0])
+        c = [R * 0.99 * er + sr * gh * er + st * gt / 2 * et + sy * width / 2 * ey
+             for sr in (0, 1) for st in (-1, 1) for sy in (-1, 1)]  # corners, index 4 sr + 2 st' + sy'
+        P = lambda r, t, y: tuple(c[4 * r + 2 * t + y])
+        faces = [((0, 0, 0), (0, 1, 0), (0, 1, 1), (0, 0, 1)), ((1, 0, 0), (1, 0, 1), (1, 1, 1), (1, 1, 0)),
+                 ((0, 0, 0), (0, 0, 1), (1, 0, 1), (1, 0, 0)), ((0, 1, 0), (1, 1, 0), (1, 1, 1), (0, 1, 1)),
+                 ((0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)), ((0, 0, 1), (0, 1, 1), (1, 1, 1), (1, 0, 1))]
+        for f in faces:
+            q = [P(*v) for v in f]
+            tris += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    return np.asarray(tris, np.float64)
+
+
 def layered_lattice(g: np.random.Generator, templates, clump_template, footprint, gap=2e-4, z0=0.0):
     """Spawn positions on a lattice of size-homogeneous layers.
 
@@ -733,7 +764,7 @@ def rover_deposited_patch(replica: int = 0, n_clumps: int = 6875, side: float = 
 
 def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
             bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True,
-            wheel_x: float = 1.0) -> SceneDesc:
+            wheel_x: float = 1.0, wheel: str = "clump") -> SceneDesc:
     """Configuration 5 (the metric's workload), tiled from a settled patch.
 
     ``patch_x``/``patch_q`` are the settled clump poses of
@@ -747,7 +778,10 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
     0.2 m, 12 grousers, 10 kg) rests on the surface, driven at slip 0.2
     (omega = 0.8 rad/s, v = (1 - 0.2) omega R) with a free vertical degree of
     freedom under a total load of 100 N; it starts 50 um above the local
-    surface and sinks in under its load.
+    surface and sinks in under its load.  With ``wheel="mesh"`` the wheel is
+    the triangle mesh of :func:`wheel_mesh` instead (the rim's outer surface
+    and grouser tips where the sphere wheel has them), moving at the same
+    velocities; its vertical motion is then the caller's (co-simulation).
     """
     g = rng(5, 1000 + replica)
     tmpls = bed_templates(replica)
@@ -782,7 +816,27 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
     templates = list(tmpls)
     presc = None
     top = float(X[:, 2].max())
-    if with_wheel:
+    meshes = None
+    if with_wheel and wheel == "mesh":
+        R = 0.25
+        tv = wheel_mesh(R=R + 4e-3, gh=8e-3)
+        cx, cy = wheel_x, bed[1] / 2
+        cell = 0.004
+        nx, ny = int(np.ceil(side / cell)) + 1, int(np.ceil(side / cell)) + 1
+        ix = np.clip(np.floor(P[:, 0] / cell).astype(int), 0, nx - 1)
+        iy = np.clip(np.floor(P[:, 1] / cell).astype(int), 0, ny - 1)
+        colh = np.zeros((nx, ny))
+        np.maximum.at(colh, (ix, iy), P[:, 2] + Rr)
+        vtx = tv.reshape(-1, 3)
+        px = np.mod(cx + vtx[:, 0] - lo[0], pitch[0])
+        py = np.mod(cy + vtx[:, 1] - lo[1], pitch[1])
+        h_under = colh[np.clip((px / cell).astype(int), 0, nx - 1), np.clip((py / cell).astype(int), 0, ny - 1)]
+        zc = float((h_under + 5e-5 - vtx[:, 2]).max())
+        om = 0.8
+        vx = (1 - 0.2) * om * R
+        meshes = [dict(vertices=tv, x=(cx, cy, zc), v=(vx, 0.0, 0.0), w=(0.0, om, 0.0), mat=(5e7, 0.3, 0.8, 0.5))]
+        top = max(top, zc + R + 0.02)
+    elif with_wheel:
         wt = wheel_template(wheel_spheres)
         templates.append(wt)
         R, wr = 0.25, float(wt[1][0])
@@ -812,7 +866,7 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
         top = max(top, zc + R + 0.02)
     walls = box_walls((0, 0, 0), (bed[0], bed[1], top + 0.05), (5e7, 0.3, 0.5, 0.5))
     return assemble(templates, CT, X, Q, V, W, mat, (0, 0, -9.81), (0, 0, 0, bed[0], bed[1], top + 0.05),
-                    1e-6, bnd=walls, presc=presc, name=f"rover-r{replica}")
+                    1e-6, bnd=walls, presc=presc, meshes=meshes, name=f"rover-r{replica}")
 
 
 # ---------------------------------------------------------------------------
@@ -890,6 +944,44 @@ def mesh_bin(replica: int = 0, n_clumps: int = 600, n_grid: int = 24, jitter: fl
     walls = box_walls((0, 0, 0), (L, L, top), BOX_MAT, floor=False)
     return assemble(tmpls, np.arange(n_clumps), x, q, v, w, mat, (0, 0, -9.81), (0, 0, -0.005, L, L, top), 1e-6,
                     bnd=walls, meshes=meshes, name=f"mesh-bin-r{replica}")
+
+
+def mesh_wheel_box(replica: int = 0, n_clumps: int = 600, res: int = 32) -> SceneDesc:
+    """A small wheel mesh (R = 12 mm rim, 20 mm wide, 8 grousers 2 mm tall)
+    pressed 20 um into a deposited pile of three-sphere clumps in a walled
+    5 cm box, driven forward at 0.1 m/s while turning at 5 rad/s (its
+    vertical motion is the co-simulation's)."""
+    d = walled_box(replica=replica, n_clumps=n_clumps, dense=True, res=res)
+    tv = wheel_mesh(R=0.012, width=0.02, n_theta=48, n_grouser=8, gh=2e-3, gt=2e-3)
+    cx, cy = 0.018, 0.025
+    sb = d.sphere_begin()
+    P = np.concatenate([d.x[c] + (d.tmpl_offset[d.tmpl_sphere_begin[d.clump_template[c]]:
+                                                 d.tmpl_sphere_begin[d.clump_template[c] + 1]]
+                                  @ quat_matrix(d.q[c]).T) for c in range(d.n_clumps)])
+    R = sphere_radii_of(d)
+    assert P.shape[0] == sb[-1]
+    # the lowest centre height at which no vertex is inside a sphere, less 20 um
+    V = tv.reshape(-1, 3)
+    zc = -np.inf
+    for k in range(0, V.shape[0], 64):
+        v = V[k:k + 64]
+        dx = (cx + v[:, None, 0]) - P[None, :, 0]
+        dy = (cy + v[:, None, 1]) - P[None, :, 1]
+        h2 = R[None, :] ** 2 - dx ** 2 - dy ** 2
+        z = np.where(h2 > 0, P[None, :, 2] + np.sqrt(np.where(h2 > 0, h2, 0.0)) - v[:, None, 2], -np.inf)
+        zc = max(zc, float(z.max()))
+    mesh = dict(vertices=tv, x=(cx, cy, zc - 2e-5), v=(0.1, 0.0, 0.0), w=(0.0, 5.0, 0.0), mat=WALL_MAT)
+    return dataclasses.replace(d, mesh_state=np.r_[mesh["x"], (1, 0, 0, 0), mesh["v"], mesh["w"]][None, :],
+                               mesh_mat=np.array([WALL_MAT], np.float64), mesh_scene=np.zeros(1, np.int32),
+                               tri_mesh=np.zeros(tv.shape[0], np.int32), tri_vertex=tv,
+                               name=f"mesh-wheel-box-r{replica}")
+
+
+def sphere_radii_of(d: SceneDesc) -> np.ndarray:
+    """Radius of every sphere instance of a description."""
+    tb = np.asarray(d.tmpl_sphere_begin, np.int64)
+    ct = np.asarray(d.clump_template, np.int64)
+    return np.concatenate([d.tmpl_radius[tb[t]:tb[t + 1]] for t in ct])
 
 
 def cone_bed(replica: int = 0, n_clumps: int = 600, side: float = 0.05, shaft: float = 12e-3,

@@ -235,3 +235,22 @@ def test_recorded_step_that_regrows_storage_still_records(mbin, monkeypatch):
     Fg, _ = small.mesh_forces()
     Fo, _ = o.mesh_forces()
     assert np.array_equal(Fg, Fo)
+
+
+@pytest.mark.parametrize("mode,overlap", [("plain", False), ("fixed", False), ("fixed", True)])
+def test_wheel_cosimulation_as_the_oracle(mode, overlap):
+    """A wheel mesh driven into a pile and co-simulated (one exchange of its
+    force and vertical velocity every 10 steps, boundary contacts recorded
+    only): clump states, wheel state and wheel force after 150 steps are
+    those of the oracle taken through the same exchanges, bit for bit."""
+    import bench
+    d = I.mesh_wheel_box()
+    sc, o = _scene(d, mode=mode, overlap=overlap, audit=20), oracle.Oracle(d)
+    cg, co = bench.WheelCosim(mass=0.02, load=0.3, h=d.h), bench.WheelCosim(mass=0.02, load=0.3, h=d.h)
+    cg.advance(sc, 150)
+    co.advance(o, 150)
+    assert cg.exchanges == co.exchanges == 15
+    assert np.array_equal(cg.last_force, co.last_force) and np.abs(cg.last_force).max() > 0
+    _assert_bitwise(sc, o)
+    if mode != "plain":
+        assert sc.counts()["missed"] == 0
