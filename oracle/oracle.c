@@ -570,7 +570,12 @@ static int64_t row_pairs(const dem_oracle *o, int64_t a, double t, const double 
         uint32_t cb = o->owner[b];
         if (cb == ca || o->scene[cb] != sa) continue;
         double v[3], dc[3];
-        sphere_vec(o, a, b, v, dc);
+        if (!o->pos_exp) {  /* (sphere_vec's first case, written out in this O(N^2) loop) */
+            const double *xb = o->xs + 3 * b;
+            v[0] = xb[0] - xa[0]; v[1] = xb[1] - xa[1]; v[2] = xb[2] - xa[2];
+        } else {
+            sphere_vec(o, a, b, v, dc);
+        }
         double d2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         double S = o->rad[a] + o->rad[b];
         if (margin) S = S + (ma + margin[b]);
