@@ -13,8 +13,10 @@
 //                    prefilter over the bins in reach, exact FP64 predicate,
 //                    candidates sorted by partner id in LDS, segments
 //                    allocated per workgroup, tangential history carried
-//                    over from the current active set; k_link points each
-//                    higher sphere's entry at its pair;
+//                    over from the current active set (boundary partners:
+//                    analytic boundaries, and mesh triangles through the
+//                    boxes of k_tri_boxes / k_tri_scene_boxes); k_link
+//                    points each higher sphere's entry at its pair;
 //   k_pairs          every candidate pair once, one lane per pair: exact
 //                    predicate, kinematics of Eq. kinematicsContactInfo and
 //                    the Hertz-Mindlin law of Eqs. normal_tangential_force_model1/2,
@@ -27,9 +29,14 @@
 //                    deferred detection (clumps of more than 64 spheres
 //                    through k_reduce_big_spheres / k_integrate_big /
 //                    k_guard_big);
-//   k_step_end       folds the per-workgroup partials and schedules the next
-//                    detection and audit (k_audit_cells: exact binned check
-//                    that every contact is in the active set).
+//   k_step_end       folds the per-workgroup partials, moves the meshes and
+//                    schedules the next detection and audit (k_audit_cells:
+//                    exact binned check that every contact is in the active
+//                    set).
+// With a second stream (k_snap, k_adopt_*) the next active set is built from
+// a snapshot while the steps go on.  The pair, narrow-phase and audit kernels
+// are instantiated per force precision, kind of positions (FP64 or fixed
+// point) and presence of triangles.
 //
 // No atomic touches a floating-point result and every sum runs in a fixed
 // order, so the step is deterministic.  Compiled with -ffp-contract=off: the
