@@ -56,7 +56,7 @@ DENSITY = 2600.0
 def rng(stream: int, replica: int = 0) -> np.random.Generator:
     """Generator of seed stream ``stream`` (one per workload: 1 walled box,
     2 bed templates, 4 funnels, 5 rover bed, 6 and 7 statistics scenes, 8 cone
-    bed, 9 drum, 11 mesh bin) and replica."""
+    bed, 9 drum, 10 deposited funnels, 11 mesh bin) and replica."""
     return np.random.default_rng(np.random.SeedSequence(SEED_ROOT, spawn_key=(stream, replica)))
 
 
