@@ -655,6 +655,20 @@ def wheel_template(n_spheres=20000, R=0.25, width=0.2, r=4e-3, n_grouser=12, mas
     return off, np.full(off.shape[0], r), float(mass), np.array([I_other, I_axle, I_other])
 
 
+def surface_points(tris: np.ndarray, spacing: float) -> np.ndarray:
+    """Points covering every triangle at most `spacing` apart (a barycentric
+    grid on each), for clearance checks of a mesh against a bed."""
+    out = []
+    for t in np.asarray(tris, np.float64):
+        L = max(np.linalg.norm(t[1] - t[0]), np.linalg.norm(t[2] - t[1]), np.linalg.norm(t[0] - t[2]))
+        n = max(1, int(np.ceil(L / spacing)))
+        i, j = np.meshgrid(np.arange(n + 1), np.arange(n + 1), indexing="ij")
+        keep = i + j <= n
+        u, v = i[keep] / n, j[keep] / n
+        out.append(t[0] + u[:, None] * (t[1] - t[0]) + v[:, None] * (t[2] - t[0]))
+    return np.concatenate(out)
+
+
 def wheel_mesh(R=0.254, width=0.2, n_theta=120, n_grouser=12, gh=8e-3, gt=8e-3):
     """A rigid wheel as a triangle mesh in its body frame (axle along y,
     centre at the origin): a cylindrical rim of radius R (n_theta facets),
@@ -762,6 +776,46 @@ def rover_deposited_patch(replica: int = 0, n_clumps: int = 6875, side: float = 
     return deposit(g, tmpls, ct, (0.0, 0.0, side, side), sink_max)
 
 
+def _bed_top_spheres(X, Q, CT, tmpls, cx, cy, half_x, half_y, depth=0.015):
+    """Centres and radii of the bed spheres within `depth` of the top, under
+    the rectangle |x - cx| < half_x, |y - cy| < half_y, sorted by x."""
+    near = np.nonzero((np.abs(X[:, 0] - cx) < half_x) & (np.abs(X[:, 1] - cy) < half_y))[0]
+    near = near[X[near, 2] > X[near, 2].max() - 2 * depth]
+    Ps, Rs = [], []
+    for t in np.unique(CT[near]):
+        idx = near[CT[near] == t]
+        Ps.append((X[idx][:, None, :] + np.einsum("kij,sj->ksi", quat_matrix(Q[idx]), tmpls[t][0])).reshape(-1, 3))
+        Rs.append(np.tile(tmpls[t][1], len(idx)))
+    Ps, Rs = np.concatenate(Ps), np.concatenate(Rs)
+    keep = Ps[:, 2] + Rs > (Ps[:, 2] + Rs).max() - depth
+    Ps, Rs = Ps[keep], Rs[keep]
+    so = np.argsort(Ps[:, 0])
+    return Ps[so], Rs[so]
+
+
+def _resting_height(pts, r, cx, cy, Ps, Rs):
+    """Lowest height of a body's reference point (at cx, cy) at which none of
+    its points `pts` (offsets from the reference point, each a sphere of
+    radius r; r = 0 for surface points) overlaps a sphere (Ps, Rs, sorted by
+    x)."""
+    pts = pts[np.argsort(pts[:, 0])]
+    reach = float(Rs.max()) + r
+    zc = -np.inf
+    for k in range(0, pts.shape[0], 1024):  # points in x order against the spheres of their x strip
+        q = pts[k:k + 1024]
+        a = np.searchsorted(Ps[:, 0], cx + q[0, 0] - reach)
+        b = np.searchsorted(Ps[:, 0], cx + q[-1, 0] + reach, side="right")
+        if a >= b:
+            continue
+        P_, R_ = Ps[a:b], Rs[a:b] + r
+        dx = (cx + q[:, None, 0]) - P_[None, :, 0]
+        dy = (cy + q[:, None, 1]) - P_[None, :, 1]
+        h2 = R_[None, :] ** 2 - dx * dx - dy * dy
+        z = np.where(h2 > 0, P_[None, :, 2] + np.sqrt(np.where(h2 > 0, h2, 0.0)) - q[:, None, 2], -np.inf)
+        zc = max(zc, float(z.max()))
+    return zc
+
+
 def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clumps: int = 11_000_000,
             bed=(4.0, 1.0), side: float = 0.05, wheel_spheres: int = 20000, with_wheel: bool = True,
             wheel_x: float = 1.0, wheel: str = "clump") -> SceneDesc:
@@ -777,11 +831,12 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
     clumps start at rest.  A rigid 20,000-sphere wheel (R = 0.25 m, width
     0.2 m, 12 grousers, 10 kg) rests on the surface, driven at slip 0.2
     (omega = 0.8 rad/s, v = (1 - 0.2) omega R) with a free vertical degree of
-    freedom under a total load of 100 N; it starts 50 um above the local
-    surface and sinks in under its load.  With ``wheel="mesh"`` the wheel is
+    freedom under a total load of 100 N; it starts pressed 20 um into the
+    bed's top spheres beneath it and sinks in under its load.  With ``wheel="mesh"`` the wheel is
     the triangle mesh of :func:`wheel_mesh` instead (the rim's outer surface
     and grouser tips where the sphere wheel has them), moving at the same
-    velocities; its vertical motion is then the caller's (co-simulation).
+    velocities, pressed the same 20 um into the bed; its vertical motion is
+    then the caller's (co-simulation).
     """
     g = rng(5, 1000 + replica)
     tmpls = bed_templates(replica)
@@ -821,17 +876,13 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
         R = 0.25
         tv = wheel_mesh(R=R + 4e-3, gh=8e-3)
         cx, cy = wheel_x, bed[1] / 2
-        cell = 0.004
-        nx, ny = int(np.ceil(side / cell)) + 1, int(np.ceil(side / cell)) + 1
-        ix = np.clip(np.floor(P[:, 0] / cell).astype(int), 0, nx - 1)
-        iy = np.clip(np.floor(P[:, 1] / cell).astype(int), 0, ny - 1)
-        colh = np.zeros((nx, ny))
-        np.maximum.at(colh, (ix, iy), P[:, 2] + Rr)
-        vtx = tv.reshape(-1, 3)
-        px = np.mod(cx + vtx[:, 0] - lo[0], pitch[0])
-        py = np.mod(cy + vtx[:, 1] - lo[1], pitch[1])
-        h_under = colh[np.clip((px / cell).astype(int), 0, nx - 1), np.clip((py / cell).astype(int), 0, ny - 1)]
-        zc = float((h_under + 5e-5 - vtx[:, 2]).max())
+        # points 2 mm apart over the wheel's lowest 15 mm, against the bed's
+        # top spheres under it: the deepest point 20 um inside a sphere
+        low = tv[tv[:, :, 2].min(1) < -0.5 * R]
+        pts = surface_points(low, 2e-3)
+        pts = pts[pts[:, 2] < pts[:, 2].min() + 0.015]
+        Ps, Rs = _bed_top_spheres(X, Q, CT, tmpls, cx, cy, R + 0.03, 0.13)
+        zc = _resting_height(pts, 0.0, cx, cy, Ps, Rs) - 2e-5
         om = 0.8
         vx = (1 - 0.2) * om * R
         meshes = [dict(vertices=tv, x=(cx, cy, zc), v=(vx, 0.0, 0.0), w=(0.0, om, 0.0), mat=(5e7, 0.3, 0.8, 0.5))]
@@ -841,18 +892,12 @@ def rover_bed(patch_x: np.ndarray, patch_q: np.ndarray, replica: int = 0, n_clum
         templates.append(wt)
         R, wr = 0.25, float(wt[1][0])
         cx, cy = wheel_x, bed[1] / 2
-        # column heights of the patch surface (the bed repeats the patch)
-        cell = 0.004
-        nx, ny = int(np.ceil(side / cell)) + 1, int(np.ceil(side / cell)) + 1
-        ix = np.clip(np.floor(P[:, 0] / cell).astype(int), 0, nx - 1)
-        iy = np.clip(np.floor(P[:, 1] / cell).astype(int), 0, ny - 1)
-        colh = np.zeros((nx, ny))
-        np.maximum.at(colh, (ix, iy), P[:, 2] + Rr)
+        # its lowest spheres against the bed's top spheres under it: the
+        # deepest overlap 20 um, so that it bears on the bed from the first step
         wo = wt[0]
-        px = np.mod(cx + wo[:, 0] - lo[0], pitch[0])
-        py = np.mod(cy + wo[:, 1] - lo[1], pitch[1])
-        h_under = colh[np.clip((px / cell).astype(int), 0, nx - 1), np.clip((py / cell).astype(int), 0, ny - 1)]
-        zc = float((h_under + wr + 5e-5 - wo[:, 2]).max())  # 50 um above the surface: it settles gently
+        wlow = wo[wo[:, 2] < wo[:, 2].min() + 0.015]
+        Ps, Rs = _bed_top_spheres(X, Q, CT, tmpls, cx, cy, R + 0.03, 0.13)
+        zc = _resting_height(wlow, wr, cx, cy, Ps, Rs) - 2e-5
         X = np.vstack([X, [cx, cy, zc]])
         Q = np.vstack([Q, [1.0, 0.0, 0.0, 0.0]])
         CT = np.r_[CT, len(tmpls)]
@@ -960,8 +1005,9 @@ def mesh_wheel_box(replica: int = 0, n_clumps: int = 600, res: int = 32) -> Scen
                                   @ quat_matrix(d.q[c]).T) for c in range(d.n_clumps)])
     R = sphere_radii_of(d)
     assert P.shape[0] == sb[-1]
-    # the lowest centre height at which no vertex is inside a sphere, less 20 um
-    V = tv.reshape(-1, 3)
+    # the lowest centre height at which no point of the surface (1 mm apart)
+    # is inside a sphere, less 20 um
+    V = surface_points(tv[tv[:, :, 2].min(1) < 0], 1e-3)
     zc = -np.inf
     for k in range(0, V.shape[0], 64):
         v = V[k:k + 64]
