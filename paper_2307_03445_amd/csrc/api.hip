@@ -851,7 +851,7 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     }
     S.n_waves = (int64_t)wsched.size() / 2;
     S.n_rblocks = (S.n_waves + 3) / 4;            // workgroups of the reduction (four waves each)
-    S.n_ablocks = (ns + 255) / 256;               // workgroups of the audit
+    S.n_ablocks = std::min<int64_t>((ns + 255) / 256, kStepGrid);  // workgroups of the audit
     S.part_r = (uint32_t *)dev_alloc(sc, 12 * (S.n_rblocks + 256));  // + the folded partials
     S.part_a = (unsigned long long *)dev_alloc(sc, 16 * std::max<int64_t>(S.n_ablocks, 1));
     S.part_c = (uint32_t *)dev_alloc(sc, 4 * (size_t)kPairBlocksMax);

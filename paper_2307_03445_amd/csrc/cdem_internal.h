@@ -13,6 +13,12 @@ constexpr int kMaxBnd = 4096;
 constexpr int kMaxMesh = 64;
 constexpr int kNarrowBlock = 512;  // narrow-phase workgroup: eight wavefronts share one segment allocation
 constexpr int kMaxRow = 16;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
+// Workgroup cap of the per-sphere binning and audit kernels, which loop over
+// logical blocks of 256 spheres: most steps launch them with nothing to do,
+// and a capped grid returns in a few microseconds where one workgroup per
+// block took ~30-50.  (The narrow phase keeps one workgroup per block: looped
+// over a capped grid, its detections took half as long again.)
+constexpr int kStepGrid = 8192;
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
 constexpr int kRegionBins = 2;     // edge of an envelope region of the learned margins, in bins
 

@@ -213,55 +213,63 @@ __global__ void __launch_bounds__(256) k_pose(DevScene S, int force) {
     if (!force && (aborted(ctl) || !(det || aud || ctl->collecting))) return;
     const bool bin = !force && (det || aud);
     const bool feat = bin && det && S.detect_mode == 2;
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool speeds = S.store_speed || ctl->collecting || S.detect_mode != 0;
-    float speed = 0.0f, acc = 0.0f;
-    int64_t r = -1;
-    if (s < S.ns) {
-        const uint32_t c = S.owner[s], ts = S.sts[s];
-        const SphereKin k = sphere_kin_of(S, c, ts);
-        S.spos[s] = make_double4(k.p[0], k.p[1], k.p[2], k.R);
-        if (speeds) {
-            const double r0 = k.p[0] - k.xc[0], r1 = k.p[1] - k.xc[1], r2 = k.p[2] - k.xc[2];
-            const double u0 = k.v[0] + (k.W[1] * r2 - k.W[2] * r1), u1 = k.v[1] + (k.W[2] * r0 - k.W[0] * r2),
-                         u2 = k.v[2] + (k.W[0] * r1 - k.W[1] * r0);
-            speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
-            if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
+    float smax = 0.0f;  // this lane's largest sphere speed
+    // logical blocks of 256 spheres, at most kStepGrid workgroups (a launch on
+    // a step that neither detects nor audits returns at once)
+    const int64_t nvb = (S.ns + 255) / 256;
+    for (int64_t vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
+        const int64_t s = vb * 256 + threadIdx.x;
+        float speed = 0.0f, acc = 0.0f;
+        int64_t r = -1;
+        if (s < S.ns) {
+            const uint32_t c = S.owner[s], ts = S.sts[s];
+            const SphereKin k = sphere_kin_of(S, c, ts);
+            S.spos[s] = make_double4(k.p[0], k.p[1], k.p[2], k.R);
+            if (speeds) {
+                const double r0 = k.p[0] - k.xc[0], r1 = k.p[1] - k.xc[1], r2 = k.p[2] - k.xc[2];
+                const double u0 = k.v[0] + (k.W[1] * r2 - k.W[2] * r1), u1 = k.v[1] + (k.W[2] * r0 - k.W[0] * r2),
+                             u2 = k.v[2] + (k.W[0] * r1 - k.W[1] * r0);
+                speed = (float)sqrt(u0 * u0 + u1 * u1 + u2 * u2) * 1.000001f;
+                if (S.store_speed || ctl->collecting) S.sspeed[s] = speed;
+            }
+            if (bin) {
+                const Grid &g = S.grids[S.sscene[s]];
+                int ix, iy, iz;
+                cell_coords(g, k.p[0], k.p[1], k.p[2], ix, iy, iz);
+                const uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
+                S.cell_of[s] = cell;
+                S.cell_rank[s] = atomicAdd(&S.cell_count[cell], 1u);
+                if (feat) { r = region_of(g, cell); acc = S.cacc[c]; }
+            }
         }
-        if (bin) {
-            const Grid &g = S.grids[S.sscene[s]];
-            int ix, iy, iz;
-            cell_coords(g, k.p[0], k.p[1], k.p[2], ix, iy, iz);
-            const uint32_t cell = (uint32_t)(g.cell0 + ((int64_t)iz * g.ny + iy) * g.nx + ix);
-            S.cell_of[s] = cell;
-            S.cell_rank[s] = atomicAdd(&S.cell_count[cell], 1u);
-            if (feat) { r = region_of(g, cell); acc = S.cacc[c]; }
+        if (feat) {
+            float v = speed, a = acc;
+            const int rl = (int)r, rh = (int)(r >> 32);
+            const int pl = __shfl_up(rl, 1, 64), ph = __shfl_up(rh, 1, 64);
+            const bool head = lane == 0 || pl != rl || ph != rh;
+            const unsigned long long heads = __ballot(head);
+            for (int off = 1; off < 64; off <<= 1) {  // run maxima, from the lanes further down the run
+                const int ol = __shfl_down(rl, off, 64), oh = __shfl_down(rh, off, 64);
+                const float ov = __shfl_down(v, off, 64), oa = __shfl_down(a, off, 64);
+                if (lane + off < 64 && ol == rl && oh == rh) { v = fmaxf(v, ov); a = fmaxf(a, oa); }
+            }
+            if (head && r >= 0) {
+                const unsigned long long later = lane < 63 ? heads >> (lane + 1) : 0ull;
+                const int next = later ? lane + 1 + __builtin_ctzll(later) : 64;
+                if (v > 0.f) atomicMax(&S.bin_v[r], __float_as_uint(v));
+                if (a > 0.f) atomicMax(&S.bin_a[r], __float_as_uint(a));
+                atomicAdd(&S.reg_occ[r], (uint32_t)(next - lane));
+            }
         }
-    }
-    if (feat) {
-        float v = speed, a = acc;
-        const int rl = (int)r, rh = (int)(r >> 32);
-        const int pl = __shfl_up(rl, 1, 64), ph = __shfl_up(rh, 1, 64);
-        const bool head = lane == 0 || pl != rl || ph != rh;
-        const unsigned long long heads = __ballot(head);
-        for (int off = 1; off < 64; off <<= 1) {  // run maxima, from the lanes further down the run
-            const int ol = __shfl_down(rl, off, 64), oh = __shfl_down(rh, off, 64);
-            const float ov = __shfl_down(v, off, 64), oa = __shfl_down(a, off, 64);
-            if (lane + off < 64 && ol == rl && oh == rh) { v = fmaxf(v, ov); a = fmaxf(a, oa); }
-        }
-        if (head && r >= 0) {
-            const unsigned long long later = lane < 63 ? heads >> (lane + 1) : 0ull;
-            const int next = later ? lane + 1 + __builtin_ctzll(later) : 64;
-            if (v > 0.f) atomicMax(&S.bin_v[r], __float_as_uint(v));
-            if (a > 0.f) atomicMax(&S.bin_a[r], __float_as_uint(a));
-            atomicAdd(&S.reg_occ[r], (uint32_t)(next - lane));
-        }
+        smax = fmaxf(smax, speed);
     }
     if (S.detect_mode == 0) return;
     // the global speed maximum (the fixed rule, and the learned rule's
     // fallback): one filtered atomic per workgroup
     __shared__ float wmax[4];
+    float speed = smax;
     for (int off = 32; off > 0; off >>= 1) speed = fmaxf(speed, __shfl_xor(speed, off, 64));
     if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = speed;
     __syncthreads();
@@ -388,10 +396,7 @@ __global__ void __launch_bounds__(kScanBlock) k_scan_final(DevScene S, const uin
 // Scatter spheres into their bins.  For a detection, every sphere also takes
 // this detection's margin (fixed rule: one value; learned: per sphere), from
 // which the integration sets its clump's displacement guard.
-__global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *margin_src, int which) {
-    if (!chain_active(S, which)) return;
-    int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= S.ns) return;
+__device__ __forceinline__ void scatter_sphere(const DevScene &S, const float *margin_src, int which, int64_t s) {
     uint32_t cell = S.cell_of[s];
     uint32_t slot = S.cell_start[cell] + S.cell_rank[s];  // its rank within the bin, from the count
     double4 p = S.spos[s];
@@ -407,6 +412,12 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
     S.sorted_margin[slot] = m;
     slot3(S.smargin, out_slot(S))[s] = m;
+}
+
+__global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *margin_src, int which) {
+    if (!chain_active(S, which)) return;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S.ns; s += (int64_t)gridDim.x * blockDim.x)
+        scatter_sphere(S, margin_src, which, s);
 }
 
 // Fixed rule of the enlarged contact geometry: the margin covers k steps of
@@ -1676,100 +1687,107 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // Exact contacts of the current positions, found in freshly built bins with no
 // margin, must each be in both partners' rows of the active set.
 template <bool TRI>
-__global__ void __launch_bounds__(256) k_audit_cells(DevScene S) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_audit_cells(DevScene S) {
     // an abandoned step (active-set overflow) is audited when it is run again
     if (!audit_due(S) || aborted(S.ctl)) return;
-    __shared__ uint32_t alst[kMaxRow * 256];
-    int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+    __shared__ uint32_t alst[kMaxRow * 256];  // each lane reads back only its own column
     unsigned long long found = 0, missed = 0;
-    if (i < S.ns) {
-        const int cur = S.ctl->buf;
-        uint32_t s = (uint32_t)i;
-        double4 P = S.spos[s];
-        uint32_t own = S.owner[s];
-        const uint32_t lb = slot3(S.lo_beg, cur)[s], lc = slot3(S.lo_cnt, cur)[s];
-        const uint32_t *lrow = slot3(S.pt, cur) + lb, *urow = slot3(S.ut, cur) + slot3(S.up_beg, cur)[s];
-        const uint32_t uc = slot3(S.up_cnt, cur)[s];
-        auto in_row = [&](uint32_t t) {  // t in s's upper (t < s) or lower segment
-            const uint32_t *nb = t < s ? urow : lrow;
-            const uint32_t cnt = t < s ? uc : lc;
-            uint32_t lo = 0, hi = cnt;
-            while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
-            return lo < cnt && nb[lo] == t;
-        };
-        const Grid &g = S.grids[S.sscene[s]];
-        const double reach = P.w + g.r_max + 1e-9;
-        // the FP32 prefilter of the narrow phase, without margins
-        const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
-        const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
-        auto prefilter = [&](uint32_t j) {
-            const float4 Qf = S.sorted_f4[j];
-            const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
-            return exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
-        };
-        auto exact = [&](uint32_t j) {
-            if (S.sorted_owner[j] == own) return;
-            double4 Q = S.sorted_pos[j];
-            double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-            double d2 = dx * dx + dy * dy + dz * dz;
-            double Sr = P.w + Q.w;
-            if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
-        };
-        // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
-        int npre = 0;
-        if (!exact_only)
-            scan_reach32(S, g, Pf.x, Pf.y, Pf.z, (float)reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
-                slot_batches(S.sorted_f4, jb, je, [&](float4 Qf) {
-                    const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
-                    return fx * fx + fy * fy + fz * fz < fr * fr;
-                }, [&](uint32_t j) {
-                    if (npre < kMaxRow) alst[npre * 256 + threadIdx.x] = j;
-                    npre++;
+    // logical blocks of 256 spheres over at most kStepGrid workgroups; one
+    // partial per workgroup
+    const int64_t nvb = (S.ns + 255) / 256;
+    for (int64_t vb = xcd_block(); vb < nvb; vb += gridDim.x) {
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));  // nothing derived from the lane is held across iterations
+        const int64_t i = vb * 256 + tid;
+        if (i < S.ns) {
+            const int cur = S.ctl->buf;
+            uint32_t s = (uint32_t)i;
+            double4 P = S.spos[s];
+            uint32_t own = S.owner[s];
+            const uint32_t lb = slot3(S.lo_beg, cur)[s], lc = slot3(S.lo_cnt, cur)[s];
+            const uint32_t *lrow = slot3(S.pt, cur) + lb, *urow = slot3(S.ut, cur) + slot3(S.up_beg, cur)[s];
+            const uint32_t uc = slot3(S.up_cnt, cur)[s];
+            auto in_row = [&](uint32_t t) {  // t in s's upper (t < s) or lower segment
+                const uint32_t *nb = t < s ? urow : lrow;
+                const uint32_t cnt = t < s ? uc : lc;
+                uint32_t lo = 0, hi = cnt;
+                while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
+                return lo < cnt && nb[lo] == t;
+            };
+            const Grid &g = S.grids[S.sscene[s]];
+            const double reach = P.w + g.r_max + 1e-9;
+            // the FP32 prefilter of the narrow phase, without margins
+            const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
+            const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+            auto prefilter = [&](uint32_t j) {
+                const float4 Qf = S.sorted_f4[j];
+                const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+                return exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
+            };
+            auto exact = [&](uint32_t j) {
+                if (S.sorted_owner[j] == own) return;
+                double4 Q = S.sorted_pos[j];
+                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                double d2 = dx * dx + dy * dy + dz * dz;
+                double Sr = P.w + Q.w;
+                if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
+            };
+            // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
+            int npre = 0;
+            if (!exact_only)
+                scan_reach32(S, g, Pf.x, Pf.y, Pf.z, (float)reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
+                    slot_batches(S.sorted_f4, jb, je, [&](float4 Qf) {
+                        const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+                        return fx * fx + fy * fy + fz * fz < fr * fr;
+                    }, [&](uint32_t j) {
+                        if (npre < kMaxRow) alst[npre * 256 + tid] = j;
+                        npre++;
+                    });
                 });
-            });
-        if (!exact_only && npre <= kMaxRow) {
-            // two listed slots at a time, their records loaded together
-            for (int k = 0; k < npre; k += 2) {
-                const bool two = k + 1 < npre;
-                const uint32_t j0 = alst[k * 256 + threadIdx.x], j1 = two ? alst[(k + 1) * 256 + threadIdx.x] : j0;
-                const uint32_t o0 = S.sorted_owner[j0], o1 = S.sorted_owner[j1];
-                const double4 Q0 = S.sorted_pos[j0], Q1 = S.sorted_pos[j1];
-                const uint32_t i0 = S.sorted_id[j0], i1 = S.sorted_id[j1];
-                for (int u = 0; u < (two ? 2 : 1); u++) {
-                    const uint32_t o = u ? o1 : o0, id = u ? i1 : i0;
-                    const double4 Q = u ? Q1 : Q0;
-                    if (o == own) continue;
-                    const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                    const double d2 = dx * dx + dy * dy + dz * dz;
-                    const double Sr = P.w + Q.w;
-                    if (d2 < Sr * Sr) { found++; if (!in_row(id)) missed++; }
+            if (!exact_only && npre <= kMaxRow) {
+                // two listed slots at a time, their records loaded together
+                for (int k = 0; k < npre; k += 2) {
+                    const bool two = k + 1 < npre;
+                    const uint32_t j0 = alst[k * 256 + tid], j1 = two ? alst[(k + 1) * 256 + tid] : j0;
+                    const uint32_t o0 = S.sorted_owner[j0], o1 = S.sorted_owner[j1];
+                    const double4 Q0 = S.sorted_pos[j0], Q1 = S.sorted_pos[j1];
+                    const uint32_t i0 = S.sorted_id[j0], i1 = S.sorted_id[j1];
+                    for (int u = 0; u < (two ? 2 : 1); u++) {
+                        const uint32_t o = u ? o1 : o0, id = u ? i1 : i0;
+                        const double4 Q = u ? Q1 : Q0;
+                        if (o == own) continue;
+                        const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                        const double d2 = dx * dx + dy * dy + dz * dz;
+                        const double Sr = P.w + Q.w;
+                        if (d2 < Sr * Sr) { found++; if (!in_row(id)) missed++; }
+                    }
                 }
+            } else {
+                scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
+                    for (uint32_t j = jb; j < je; j++)
+                        if (prefilter(j)) exact(j);
+                });
             }
-        } else {
-            scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
-                for (uint32_t j = jb; j < je; j++)
-                    if (prefilter(j)) exact(j);
-            });
-        }
-        double tnow = (double)S.ctl->step * S.h;
-        for (int b = g.bnd_beg; b < g.bnd_end; b++) {
-            double phi, n[3];
-            if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) {
-                found++;
-                if (!in_row((uint32_t)(S.ns + b))) missed++;
-            }
-        }
-        // the triangles through the boxes of the last detection: grown by
-        // their meshes' margins, they hold the triangles' current positions
-        if constexpr (TRI) {
-            const double p[3] = {P.x, P.y, P.z};
-            tri_near(S, g, p, P.w, [&](int64_t k, double) {
+            double tnow = (double)S.ctl->step * S.h;
+            for (int b = g.bnd_beg; b < g.bnd_end; b++) {
                 double phi, n[3];
-                if (tri_distance(S, k, p, phi, n) && phi < P.w) {
+                if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) {
                     found++;
-                    if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
+                    if (!in_row((uint32_t)(S.ns + b))) missed++;
                 }
-            });
+            }
+            // the triangles through the boxes of the last detection: grown by
+            // their meshes' margins, they hold the triangles' current positions
+            if constexpr (TRI) {
+                const double p[3] = {P.x, P.y, P.z};
+                tri_near(S, g, p, P.w, [&](int64_t k, double) {
+                    double phi, n[3];
+                    if (tri_distance(S, k, p, phi, n) && phi < P.w) {
+                        found++;
+                        if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
+                    }
+                });
+            }
         }
     }
     __shared__ unsigned long long sh[2][4];
@@ -1933,6 +1951,9 @@ __global__ void k_adopt_end(DevScene S, const Ctl *bctl) {
 
 // ---------------------------------------------------------------- launchers
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline unsigned capped_blocks(int64_t n, int b, int cap) {
+    return (unsigned)std::min<int64_t>((n + b - 1) / b, cap);
+}
 // grid of a grid-stride kernel over at most n items (the count lives on the device)
 static inline unsigned stride_blocks(int64_t n, int32_t cap = 16384) {
     return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, cap > 0 ? cap : 16384));
@@ -2048,7 +2069,7 @@ hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force) {
         unsigned zb = (unsigned)std::min<int64_t>(blocks_for(S.n_cells, 256), 16384);
         TIMED(K_BINS_BEGIN, hipLaunchKernelGGL(k_bins_begin, dim3(zb), dim3(256), 0, st, S));
     }
-    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S, force ? 1 : 0));
+    TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(capped_blocks(S.ns, 256, kStepGrid)), dim3(256), 0, st, S, force ? 1 : 0));
     return hipGetLastError();
 }
 
@@ -2077,7 +2098,7 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
     TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBsumBlock), 0, st, S, bsum, nblk, which));
     TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S,
                                            (const uint32_t *)bsum, which));
-    TIMED(K_CELL_SCATTER, hipLaunchKernelGGL(k_cell_scatter, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S,
+    TIMED(K_CELL_SCATTER, hipLaunchKernelGGL(k_cell_scatter, dim3(capped_blocks(S.ns, 256, kStepGrid)), dim3(256), 0, st, S,
                                              (const float *)nullptr, which));
 }
 
@@ -2161,8 +2182,8 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     if (S.ns == 0 || S.plan.audit_period <= 0) return hipSuccess;
     if (g_timer) g_timer->before(K_AUDIT_ALL, st);
     binning(S, 1, st);
-    if (S.n_tri) TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<true>, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
-    else TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<false>, dim3(blocks_for(S.ns, 256)), dim3(256), 0, st, S));
+    if (S.n_tri) TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<true>, dim3(S.n_ablocks), dim3(256), 0, st, S));
+    else TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<false>, dim3(S.n_ablocks), dim3(256), 0, st, S));
     hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1024), 0, st, S);
     if (g_timer) g_timer->after(K_AUDIT_ALL, st);
     return hipGetLastError();
