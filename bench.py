@@ -45,11 +45,12 @@ def layout_bytes(kernel: str, st: dict) -> float:
     every array it reads or writes touched once (gathers of neighbour data
     counted as cache hits).  P pairs of the active set, U of them sphere
     pairs (each also listed in the higher sphere's upper segment), C contact
-    pairs, v one contribution vector (force or torque with a fourth word:
-    float4 or double4)."""
+    pairs, v one force contribution (with a fourth word, the contact flag:
+    float4 or double4), t one torque contribution (three floats or doubles)."""
     ns, nc, cells = st["spheres"], st["clumps"], st["bins"]
     P, U, C = st["pairs"], st["upper"], st["contact_sides"] / 2.0
     v = 16 if st["fp32"] else 32
+    t = 12 if st["fp32"] else 24
     mat = 16 if st["fp32"] else 32
     guard, learned = st["guard"], st.get("learned", False)
     det_frac = st.get("detect_fraction", 1.0)  # share of the launches on a step with a detection
@@ -72,7 +73,7 @@ def layout_bytes(kernel: str, st: dict) -> float:
         # sphere; per sphere pair the partner's torque; per contact the history
         # write; compulsory per-sphere and per-clump gathers (owner, template
         # sphere, material; the clump record)
-        return P * (8 + 24 + 2 * v) + U * v + C * 24 + ns * (8 + mat) + nc * 128
+        return P * (8 + 24 + v + t) + U * t + C * 24 + ns * (8 + mat) + nc * 128
     if kernel == "k_reduce_waves":
         # per upper entry: link, the pair's force and the partner's torque; per
         # pair: force and torque of the lower sphere; per sphere: clump position
@@ -80,7 +81,7 @@ def layout_bytes(kernel: str, st: dict) -> float:
         # later steps test a per-clump bound first); per clump: record read and
         # write, template, scene, prescribed-motion index (+ its pose at the last
         # detection for the guard, + acceleration envelope when learned)
-        return (U * (4 + 2 * v) + P * 2 * v + ns * (20 + (4 * det_frac if guard else 0)) +
+        return (U * (4 + v + t) + P * (v + t) + ns * (20 + (4 * det_frac if guard else 0)) +
                 nc * (268 + (64 if guard else 0) + (4 if learned else 0)))
     if kernel in ("k_scan_reduce", "k_scan_final"):
         return cells * (4 if kernel == "k_scan_reduce" else 8)

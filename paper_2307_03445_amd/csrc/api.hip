@@ -391,10 +391,11 @@ static int alloc_active_set(cdem_scene *sc, int64_t cap, bool keep) {
         dev_free(sc, S.ps[k]); dev_free(sc, S.ut[k]); dev_free(sc, S.us[k]); dev_free(sc, S.um[k]);
         S.ps[k] = S.ut[k] = S.us[k] = S.um[k] = nullptr;
     }
-    const size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 16 : 32;  // float4 / double4
+    const size_t cw = S.precision == CDEM_PREC_FP32_FORCE ? 16 : 32;  // force: float4 / double4
+    const size_t tw = S.precision == CDEM_PREC_FP32_FORCE ? 12 : 24;  // torques: three floats / doubles
     S.cS = dev_alloc(sc, cap * cw);
-    S.cTs = dev_alloc(sc, cap * cw);
-    S.cTt = dev_alloc(sc, cap * cw);
+    S.cTs = dev_alloc(sc, cap * tw);
+    S.cTt = dev_alloc(sc, cap * tw);
     if (!S.cS || !S.cTs || !S.cTt) return fail(sc, CDEM_E_OOM, "active-set storage");
     for (int k = 0; k < nslots; k++) {
         S.ps[k] = (uint32_t *)dev_alloc(sc, cap * 4);

@@ -173,8 +173,9 @@ struct DevScene {
     uint32_t *pt[3];                  // [cap] partner of the pair: sphere id, or ns + boundary
     double *hist[2];                  // [cap][3]
     uint32_t *ps[3];                  // [cap] the pair's lower sphere
-    void *cS, *cTs, *cTt;             // [cap] per pair this step: force on the lower sphere (w: 1 if in contact),
-                                      // torque on the lower sphere, torque on the partner sphere (float4 / double4)
+    void *cS, *cTs, *cTt;             // [cap] per pair this step: force on the lower sphere (float4 / double4,
+                                      // w: 1 if in contact), torque on the lower sphere and on the partner sphere
+                                      // (three floats / doubles, packed)
     uint32_t *up_beg[3], *up_cnt[3];  // [ns] each sphere's upper segment
     uint32_t *ut[3], *us[3], *um[3];  // [cap] upper entries: partner (lower id), own sphere, linked pair
     // per-workgroup partial results, reduced by the next single-workgroup kernel

@@ -1158,19 +1158,23 @@ template <bool FP32>
 __device__ __forceinline__ void sphere_sum(const DevScene &S, uint32_t ub, uint32_t nu, uint32_t lb, uint32_t nl,
                                            double *Fs, double *Ts) {
     using V = typename Contrib<FP32>::V;
-    const V *cS = (const V *)S.cS, *cTs = (const V *)S.cTs, *cTt = (const V *)S.cTt;
+    using T = typename Contrib<FP32>::T;
+    const V *cS = (const V *)S.cS;
+    const T *cTs = (const T *)S.cTs, *cTt = (const T *)S.cTt;
     const uint32_t *um = slot3(S.um, S.ctl->buf);
     // Entries are taken in batches whose loads are all issued before the first
     // is used (the sums stay in ascending partner order).  Six per batch keep
     // the reduction at five waves per SIMD with no spilled register (eight
     // spill; holding the first lower batch through the upper one spills too).
     constexpr uint32_t kB = 6;
-    V la[kB], lt[kB];
+    V la[kB];
+    T lt[kB];
     for (uint32_t k0 = 0; k0 < nu; k0 += kB) {
         int64_t e[kB];
 #pragma unroll
         for (uint32_t j = 0; j < kB; j++) e[j] = k0 + j < nu ? (int64_t)um[ub + k0 + j] : -1;
-        V a[kB], b[kB];
+        V a[kB];
+        T b[kB];
 #pragma unroll
         for (uint32_t j = 0; j < kB; j++)
             if (e[j] >= 0) { a[j] = cS[e[j]]; b[j] = cTt[e[j]]; }

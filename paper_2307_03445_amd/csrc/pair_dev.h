@@ -128,16 +128,29 @@ __device__ __forceinline__ void store_nt(double4 *p, double4 v) {
     __builtin_nontemporal_store(v.z, &p->z); __builtin_nontemporal_store(v.w, &p->w);
 }
 
+// A torque contribution: three components, packed (12 or 24 bytes a pair).
+template <class T> struct Vec3 { T x, y, z; };
+template <class T> __device__ __forceinline__ void store_nt(Vec3<T> *p, Vec3<T> v) {
+    __builtin_nontemporal_store(v.x, &p->x); __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z);
+}
+
 template <bool FP32> struct Contrib;
+// Force contributions carry a fourth word (1 when the pair is in contact);
+// torque contributions are three words.
 template <> struct Contrib<true> {
     using V = float4;
+    using T = Vec3<float>;
     static __device__ __forceinline__ V make(const double *a, double w) {
         return make_float4((float)a[0], (float)a[1], (float)a[2], (float)w);
     }
+    static __device__ __forceinline__ T make3(const double *a) { return T{(float)a[0], (float)a[1], (float)a[2]}; }
 };
 template <> struct Contrib<false> {
     using V = double4;
+    using T = Vec3<double>;
     static __device__ __forceinline__ V make(const double *a, double w) { return make_double4(a[0], a[1], a[2], w); }
+    static __device__ __forceinline__ T make3(const double *a) { return T{a[0], a[1], a[2]}; }
 };
 
 // Torque r x f, in FP32 when the force law ran in FP32.
@@ -194,7 +207,9 @@ template <bool FP32, class Law, int FX, bool TRI>
 __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, const PairIds &id, double *hist,
                                               double tnow, int rec_mode) {
     using V = typename Contrib<FP32>::V;
-    V *cS = (V *)S.cS, *cTs = (V *)S.cTs, *cTt = (V *)S.cTt;
+    using T = typename Contrib<FP32>::T;
+    V *cS = (V *)S.cS;
+    T *cTs = (T *)S.cTs, *cTt = (T *)S.cTt;
     const double zero3[3] = {0.0, 0.0, 0.0};
     const uint32_t s = id.s, t = id.t;
     double *h = hist + 3 * e;
@@ -257,8 +272,8 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
         torque<FP32>(ra, fa, ta);
         torque<FP32>(rb, F, tb);
         store_nt(cS + e, Contrib<FP32>::make(fa, 1.0));
-        store_nt(cTs + e, Contrib<FP32>::make(ta, 0.0));
-        store_nt(cTt + e, Contrib<FP32>::make(tb, 0.0));
+        store_nt(cTs + e, Contrib<FP32>::make3(ta));
+        store_nt(cTt + e, Contrib<FP32>::make3(tb));
         if (rec) {
             S.rec_state[e] = 1; S.rec_delta[e] = delta;
             for (int i = 0; i < 3; i++) {
@@ -326,7 +341,7 @@ __device__ __forceinline__ uint32_t eval_pair(const DevScene &S, int64_t e, cons
     double tb[3];
     torque<FP32>(rb, F, tb);
     cS[e] = Contrib<FP32>::make(F, 1.0);
-    cTs[e] = Contrib<FP32>::make(tb, 0.0);
+    cTs[e] = Contrib<FP32>::make3(tb);
     if (rec) {
         S.rec_state[e] = 1; S.rec_delta[e] = delta;
         double fw[3] = {-F[0], -F[1], -F[2]}, tw[3];  // the boundary receives -F at the contact point

@@ -20,21 +20,21 @@ def _stats(**kw):
 
 def test_reduction_bytes_follow_the_per_unit_model():
     st = _stats()
-    v = 16
-    want = (1800 * (4 + 2 * v) + 2000 * 2 * v + 1000 * (20 + 4 * 0.05) + 300 * (268 + 64 + 4))
+    v, t = 16, 12  # force with its contact word, torque packed
+    want = (1800 * (4 + v + t) + 2000 * (v + t) + 1000 * (20 + 4 * 0.05) + 300 * (268 + 64 + 4))
     assert bench.layout_bytes("k_reduce_waves", st) == want
     # plain path: no guard words, no envelope, no margins
     st = _stats(guard=False, learned=False, detect_fraction=1.0)
-    assert bench.layout_bytes("k_reduce_waves", st) == 1800 * 36 + 2000 * 32 + 1000 * 20 + 300 * 268
-    # FP64 contributions double the contribution vector
+    assert bench.layout_bytes("k_reduce_waves", st) == 1800 * 32 + 2000 * 28 + 1000 * 20 + 300 * 268
+    # FP64 contributions double both vectors
     st = _stats(fp32=False)
     assert bench.layout_bytes("k_reduce_waves", st) - bench.layout_bytes("k_reduce_waves", _stats()) \
-        == 1800 * 2 * 16 + 2000 * 2 * 16
+        == 1800 * (16 + 12) + 2000 * (16 + 12)
 
 
 def test_pair_bytes_follow_the_per_unit_model():
     st = _stats()
-    want = 2000 * (8 + 24 + 32) + 1800 * 16 + 1500 * 24 + 1000 * (8 + 16) + 300 * 128
+    want = 2000 * (8 + 24 + 16 + 12) + 1800 * 12 + 1500 * 24 + 1000 * (8 + 16) + 300 * 128
     assert bench.layout_bytes("k_pairs", st) == want
 
 
