@@ -157,6 +157,12 @@ struct DevScene {
     double4 *sorted_pos;
     float *sorted_margin;
     float4 *sorted_f4;               // FP32 prefilter record: position - grid origin, radius + margin
+    uint32_t *stage;                 // [kMaxRow][ns] each sphere's candidates from the narrow phase's first pass
+    uint2 *stage_n;                  // [ns] their count; how many lie below the sphere (low 16 bits) and are
+                                     // boundaries (high 16); beyond kMaxRow candidates: count, how many below,
+                                     // and the boundaries in the sphere's first entry
+    unsigned long long *narrow_part; // [ceil(ns / kNarrowBlock)][3] per narrow-phase workgroup: its upper entries,
+                                     // pairs and boundary pairs, then (scanned) their bases
     // Active set, pair-major.  Each candidate pair is stored once, in the
     // "lower segment" of its lower-id sphere (partners above that id,
     // ascending, boundaries last), with its tangential history; the higher
@@ -276,7 +282,7 @@ struct KernelTimer {
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
                 K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_GUARD_BIG, K_BINS_BEGIN,
-                K_AUDIT_ALL, K_PICK_INTERVAL, K_COUNT };
+                K_AUDIT_ALL, K_PICK_INTERVAL, K_NARROW_ROWS, K_NARROW_BASE, K_CARRY, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 

@@ -9,11 +9,13 @@
 //                    the learned envelopes' region features;
 //   detection        (when due: every step, or every k steps with the
 //                    enlarged contact geometry of Sec. 2.2) scan of the bin
-//                    counts, scatter into bin order, k_narrow: FP32
-//                    prefilter over the bins in reach, exact FP64 predicate,
-//                    candidates sorted by partner id in LDS, segments
-//                    allocated per workgroup, tangential history carried
-//                    over from the current active set (boundary partners:
+//                    counts, scatter into bin order, k_narrow (one thread
+//                    per slot, in bin order): FP32 prefilter over the bins
+//                    in reach, exact FP64 predicate, candidates sorted by
+//                    partner id in LDS and staged per sphere; k_narrow_rows
+//                    (one thread per sphere id): segments allocated per
+//                    workgroup, tangential history carried over from the
+//                    current active set (boundary partners:
 //                    analytic boundaries, and mesh triangles through the
 //                    boxes of k_tri_boxes / k_tri_scene_boxes); k_link
 //                    points each higher sphere's entry at its pair;
@@ -132,6 +134,11 @@ __device__ __forceinline__ int clamp_cell32(float v, int n) {
     v = fminf(fmaxf(v, 0.0f), (float)(n - 1));
     return (int)v;
 }
+
+// The rows are visited one behind the loads: the bin range of the next row
+// in reach is requested before the current row's records are visited, so
+// that each row waits for one load (its records) instead of two (its bin
+// range, then its records).
 template <typename F>
 __device__ __forceinline__ void scan_reach32(const DevScene &S, const Grid &g, float px, float py, float pz,
                                              float reach, F &&f) {
@@ -139,21 +146,31 @@ __device__ __forceinline__ void scan_reach32(const DevScene &S, const Grid &g, f
     const int z0 = clamp_cell32((pz - reach) * inv, g.nz), z1 = clamp_cell32((pz + reach) * inv, g.nz);
     const int y0 = clamp_cell32((py - reach) * inv, g.ny), y1 = clamp_cell32((py + reach) * inv, g.ny);
     const float r2 = reach * reach;
-    for (int zz = z0; zz <= z1; zz++) {
-        const float gz = slab_gap32(pz, b, zz, g.nz);
-        const float rz = r2 - gz * gz;
-        if (rz < 0.0f) continue;
-        for (int yy = y0; yy <= y1; yy++) {
+    int zz = z0, yy = y0 - 1;
+    // the next row in reach after (zz, yy), with its bin range; false when none is left
+    auto advance = [&](uint32_t &jb, uint32_t &je) {
+        for (;;) {
+            if (++yy > y1) { yy = y0; if (++zz > z1) return false; }
+            const float gz = slab_gap32(pz, b, zz, g.nz);
+            const float rz = r2 - gz * gz;
+            if (rz < 0.0f) { yy = y1; continue; }  // the whole slab is out of reach
             const float gy = slab_gap32(py, b, yy, g.ny);
             const float ry = rz - gy * gy;
             if (ry < 0.0f) continue;
             const float rx = sqrtf(ry);
             const int x0 = clamp_cell32((px - rx) * inv, g.nx), x1 = clamp_cell32((px + rx) * inv, g.nx);
             const int64_t rowc = g.cell0 + ((int64_t)zz * g.ny + yy) * g.nx;
-            const uint32_t jb = S.cell_start[rowc + x0];
-            const uint32_t je = S.cell_start[rowc + x1 + 1];  // the next bin's start
-            f(jb, je);
+            jb = S.cell_start[rowc + x0];
+            je = S.cell_start[rowc + x1 + 1];  // the next bin's start
+            return true;
         }
+    };
+    uint32_t jb, je, nb = 0, ne = 0;
+    bool more = advance(jb, je);
+    while (more) {
+        more = advance(nb, ne);
+        f(jb, je);
+        jb = nb; je = ne;
     }
 }
 
@@ -917,10 +934,8 @@ __device__ __forceinline__ void carry_history(const DevScene &S, uint32_t s, uin
 // Write the new segments of sphere s from its ascending candidates get(k):
 // the first n_up (partners below s) to its upper segment at ub, the other
 // n_lo (partners above s, boundaries last) to its lower segment at lb as
-// pairs of the new set, in the detection's output slot.  A detection on the
-// step's stream also carries the history over; the second stream's does not
-// (the steps go on changing the history: it is carried when the set is
-// adopted).
+// pairs of the new set, in the detection's output slot.  (k_carry then
+// carries the tangential history over.)
 template <class Get>
 __device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32_t ub, int n_up, uint32_t lb, int n_lo,
                                            Get get) {
@@ -936,107 +951,199 @@ __device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32
         npt[p] = get(n_up + k);
         nps[p] = s;
     }
-    if (!S.bchain) carry_history(S, s, lb, n_lo, [&](int k) { return get(n_up + k); });
 }
 
-// Narrow phase, one thread per sphere id: ids are spatially coherent (clumps
-// are laid out in Morton order), so a wavefront's neighbour scans share cache
-// lines and the pairs come out in that order.  Up to kMaxRow candidates are
-// kept sorted in LDS; a sphere with more gets its segments allocated here and
-// filled by k_narrow_over.  Segments are allocated with one atomic per
-// wavefront and kind (upper entries, pairs).
+// Narrow phase, first pass: one thread per sphere id (ids are spatially
+// coherent: clumps are laid out in Morton order, so a wavefront's neighbour
+// scans share cache lines).  Each sphere's candidates, up to kMaxRow kept
+// sorted in LDS while they are found, are staged with its counts, entry k of
+// every sphere together (a wavefront writes, and the second pass reads, each
+// entry as one contiguous run); a sphere with more candidates stages only its
+// counts (its segments are filled by k_narrow_over).  Each workgroup also
+// sums its spheres' upper entries, pairs and boundary pairs, which
+// k_narrow_base turns into the bases of their segments.
 // TRI: the scene has triangles (the kernel without them keeps fewer registers).
 template <bool TRI>
-__global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
-    // overflow may be raised by other workgroups of this launch: one read per
-    // workgroup keeps the decision uniform across its barriers
-    __shared__ int skip;
-    if (threadIdx.x == 0) skip = !due(S.ctl) || aborted(S.ctl);
-    __syncthreads();
-    if (skip) return;
-    __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
+__device__ __forceinline__ void narrow_sphere(const DevScene &S, uint32_t s, uint32_t *lst, int &cnt, int &nup,
+                                              int &nbp) {
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)xcd_block() * kNarrowBlock + tid;
-    const int out = out_slot(S);
-    int cnt = 0, nup = 0, nbp = 0;
-    const uint32_t s = (uint32_t)i;
-    if (i < S.ns) {
-        auto emit = [&](uint32_t t) {
-            if (cnt < kMaxRow) {
-                int k = cnt;
-                while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
-                    lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
-                    k--;
-                }
-                lst[k * kNarrowBlock + tid] = t;
+    auto emit = [&](uint32_t t) {
+        if (cnt < kMaxRow) {
+            int k = cnt;
+            while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
+                lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
+                k--;
             }
-            cnt++;
-            nup += t < s;
-            nbp += t >= (uint32_t)S.ns;
-        };
-        const Grid &g = S.grids[S.sscene[s]];
-        const NarrowSelf n = narrow_self(S, g, s);
-        // First the cheap FP32 test over every slot in reach, keeping the slots
-        // that pass in the LDS list; then the exact test over that short list.
-        // Split this way, a wavefront runs the exact test and the sorted insert
-        // as often as its busiest lane has prefilter hits, not as often as it
-        // has slots in reach.
-        int npre = 0;
-        if (!n.exact_only)
-            scan_reach32(S, g, n.Pf.x, n.Pf.y, n.Pf.z, (float)n.reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
-                slot_batches(S.sorted_f4, jb, je, [&](float4 q) { return narrow_prefilter_rec(g, n, q); },
-                             [&](uint32_t j) {
-                                 if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = j;
-                                 npre++;
-                             });
-            });
-        if (!n.exact_only && npre <= kMaxRow) {
-            // two listed slots at a time, both read before either is inserted:
-            // an insert writes at most at the position of the later slot read
-            for (int k = 0; k < npre; k += 2) {
-                const bool two = k + 1 < npre;
-                const uint32_t j0 = lst[k * kNarrowBlock + tid];
-                const uint32_t j1 = two ? lst[(k + 1) * kNarrowBlock + tid] : j0;
-                const SlotRec r0 = load_slot(S, j0), r1 = load_slot(S, j1);
-                const uint32_t t0 = narrow_exact_rec(n, r0);
-                if (t0 != ~0u) emit(t0);
-                if (two) {
-                    const uint32_t t1 = narrow_exact_rec(n, r1);
-                    if (t1 != ~0u) emit(t1);
-                }
-            }
-            narrow_boundaries<TRI>(S, g, n, emit);
-        } else {
-            narrow_candidates<TRI>(S, s, emit);  // many slots pass the prefilter: one exact pass
+            lst[k * kNarrowBlock + tid] = t;
         }
+        cnt++;
+        nup += t < s;
+        nbp += t >= (uint32_t)S.ns;
+    };
+    const Grid &g = S.grids[S.sscene[s]];
+    const NarrowSelf n = narrow_self(S, g, s);
+    // First the cheap FP32 test over every slot in reach, keeping the slots
+    // that pass in the LDS list; then the exact test over that short list.
+    // Split this way, a wavefront runs the exact test and the sorted insert
+    // as often as its busiest lane has prefilter hits, not as often as it
+    // has slots in reach.
+    int npre = 0;
+    if (!n.exact_only)
+        scan_reach32(S, g, n.Pf.x, n.Pf.y, n.Pf.z, (float)n.reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
+            slot_batches(S.sorted_f4, jb, je, [&](float4 q) { return narrow_prefilter_rec(g, n, q); },
+                         [&](uint32_t q) {
+                             if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = q;
+                             npre++;
+                         });
+        });
+    if (!n.exact_only && npre <= kMaxRow) {
+        // two listed slots at a time, both read before either is inserted:
+        // an insert writes at most at the position of the later slot read
+        for (int k = 0; k < npre; k += 2) {
+            const bool two = k + 1 < npre;
+            const uint32_t j0 = lst[k * kNarrowBlock + tid];
+            const uint32_t j1 = two ? lst[(k + 1) * kNarrowBlock + tid] : j0;
+            const SlotRec r0 = load_slot(S, j0), r1 = load_slot(S, j1);
+            const uint32_t t0 = narrow_exact_rec(n, r0);
+            if (t0 != ~0u) emit(t0);
+            if (two) {
+                const uint32_t t1 = narrow_exact_rec(n, r1);
+                if (t1 != ~0u) emit(t1);
+            }
+        }
+        narrow_boundaries<TRI>(S, g, n, emit);
+    } else {
+        narrow_candidates<TRI>(S, s, emit);  // many slots pass the prefilter: one exact pass
     }
+    // staging: the counts (below it and boundaries packed for a listed
+    // sphere), then entry k at stage[k ns + s]
+    if (cnt > kMaxRow) {
+        S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup);
+        S.stage[s] = (uint32_t)nbp;
+        return;
+    }
+    S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup | ((uint32_t)nbp << 16));
+    for (int k = 0; k < cnt; k++) S.stage[(int64_t)k * S.ns + s] = lst[k * kNarrowBlock + tid];
+}
+
+template <bool TRI>
+__global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
+    // nothing in this launch raises the abort flags: the test is uniform
+    if (!due(S.ctl) || aborted(S.ctl)) return;
+    __shared__ uint32_t lst[kMaxRow * kNarrowBlock];
+    const int64_t blk = xcd_block(), i = blk * kNarrowBlock + threadIdx.x;
+    int cnt = 0, nup = 0, nbp = 0;
+    if (i < S.ns) narrow_sphere<TRI>(S, (uint32_t)i, lst, cnt, nup, nbp);
+    unsigned long long v[3] = {(unsigned long long)nup, (unsigned long long)(cnt - nup), (unsigned long long)nbp};
+    __shared__ unsigned long long sh[3][kNarrowBlock / 64];
+    for (int q = 0; q < 3; q++) {
+        for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+        if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long t = 0;
+        for (int k = 0; k < kNarrowBlock / 64; k++) t += sh[threadIdx.x][k];
+        S.narrow_part[3 * blk + threadIdx.x] = t;
+    }
+}
+
+// Narrow phase, second pass: the segments of the new set, in sphere id
+// order (pairs follow their lower sphere's id, so that the pair kernel and
+// the reduction stream them), placed by a scan of the workgroup sums of the
+// first pass rather than by atomics (tens of thousands of workgroups adding
+// to one counter serialise): k_narrow_base turns the sums into bases (and the
+// totals, which also size a regrow), k_narrow_rows writes the segments of
+// the same workgroups of kNarrowBlock spheres, k_carry the history.
+__device__ __forceinline__ void staged_counts(const DevScene &S, int64_t i, int &cnt, int &nup, int &nbp) {
+    cnt = 0; nup = 0; nbp = 0;
+    if (i >= S.ns) return;
+    const uint2 c = S.stage_n[i];
+    cnt = (int)c.x;
+    if (cnt <= kMaxRow) { nup = (int)(c.y & 0xffffu); nbp = (int)(c.y >> 16); }
+    else { nup = (int)c.y; nbp = (int)S.stage[i]; }
+}
+
+// Exclusive scan of the workgroup sums in place: one workgroup, each lane
+// taking kBaseItems consecutive workgroups per pass (their loads issued
+// together); the totals go to the control block, and a set beyond the
+// storage's capacity aborts the step (it is regrown).
+constexpr int kBaseBlock = 1024, kBaseItems = 4;
+__global__ void __launch_bounds__(kBaseBlock) k_narrow_base(DevScene S, int64_t nblk) {
+    Ctl *c = S.ctl;
+    if (!due(c) || aborted(c)) return;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned long long *P = S.narrow_part;
+    __shared__ unsigned long long wt[3][kBaseBlock / 64];
+    unsigned long long carry[3] = {0, 0, 0};
+    for (int64_t b0 = 0; b0 < nblk; b0 += (int64_t)kBaseBlock * kBaseItems) {
+        const int64_t i0 = b0 + (int64_t)threadIdx.x * kBaseItems;
+        unsigned long long loc[kBaseItems][3], v[3] = {0, 0, 0};
+#pragma unroll
+        for (int k = 0; k < kBaseItems; k++)
+#pragma unroll
+            for (int q = 0; q < 3; q++) {
+                loc[k][q] = i0 + k < nblk ? P[3 * (i0 + k) + q] : 0ull;
+                v[q] += loc[k][q];
+            }
+        unsigned long long x[3];
+#pragma unroll
+        for (int q = 0; q < 3; q++) {  // inclusive wave scans
+            x[q] = v[q];
+            for (int off = 1; off < 64; off <<= 1) {
+                const unsigned long long y = __shfl_up(x[q], off, 64);
+                if (lane >= off) x[q] += y;
+            }
+            if (lane == 63) wt[q][wid] = x[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            unsigned long long below = 0, tot = 0;
+            for (int k = 0; k < kBaseBlock / 64; k++) {
+                const unsigned long long t = wt[q][k];
+                if (k < wid) below += t;
+                tot += t;
+            }
+            unsigned long long ex = carry[q] + below + (x[q] - v[q]);
+#pragma unroll
+            for (int k = 0; k < kBaseItems; k++) {
+                if (i0 + k < nblk) P[3 * (i0 + k) + q] = ex;
+                ex += loc[k][q];
+            }
+            carry[q] += tot;
+        }
+        __syncthreads();  // wt is rewritten by the next pass
+    }
+    if (threadIdx.x == 0) {
+        c->n_up = (int64_t)carry[0];
+        c->n_pairs = (int64_t)carry[1];
+        c->n_bp = (int64_t)carry[2];
+        if (carry[0] > (unsigned long long)S.cap || carry[1] > (unsigned long long)S.cap) c->overflow = 1;
+    }
+}
+
+__global__ void __launch_bounds__(kNarrowBlock) k_narrow_rows(DevScene S) {
+    if (!due(S.ctl) || aborted(S.ctl)) return;  // uniform: set before this launch or not at all
+    const int tid = threadIdx.x;
+    const int64_t blk = xcd_block(), i = blk * kNarrowBlock + tid;
+    const int out = out_slot(S);
+    const uint32_t s = (uint32_t)i;
+    int cnt, nup, nbp;
+    staged_counts(S, i, cnt, nup, nbp);
     const int nlo = cnt - nup;
-    // segment allocation: scans within each wavefront, then one atomic per
-    // workgroup and counter (same-address atomics serialise device-wide)
-    __shared__ uint32_t wtot[3][kNarrowBlock / 64];
-    __shared__ unsigned long long wbase[2][kNarrowBlock / 64];
-    uint32_t totu, totl, totbp;
+    // offsets within the workgroup: scans within each wavefront, then the
+    // wavefronts' totals through LDS
+    __shared__ uint32_t wtot[2][kNarrowBlock / 64];
+    uint32_t totu, totl;
     const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
     const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
-    (void)wave_excl_scan((uint32_t)nbp, totbp);
     const int wid = tid >> 6;
-    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; wtot[2][wid] = totbp; }
+    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; }
     __syncthreads();
-    if (tid == 0) {
-        unsigned long long su = 0, sl = 0, sbp = 0;
-        for (int k = 0; k < kNarrowBlock / 64; k++) { su += wtot[0][k]; sl += wtot[1][k]; sbp += wtot[2][k]; }
-        unsigned long long bu0 = su ? atomicAdd((unsigned long long *)&S.ctl->n_up, su) : 0ull;
-        unsigned long long bl0 = sl ? atomicAdd((unsigned long long *)&S.ctl->n_pairs, sl) : 0ull;
-        if (sbp) atomicAdd((unsigned long long *)&S.ctl->n_bp, sbp);  // rare: workgroups next to a boundary
-        for (int k = 0; k < kNarrowBlock / 64; k++) {
-            wbase[0][k] = bu0; bu0 += wtot[0][k];
-            wbase[1][k] = bl0; bl0 += wtot[1][k];
-        }
-    }
-    __syncthreads();
-    const unsigned long long bu = wbase[0][wid], bl = wbase[1][wid];
+    unsigned long long bu = S.narrow_part[3 * blk], bl = S.narrow_part[3 * blk + 1];
+    for (int k = 0; k < wid; k++) { bu += wtot[0][k]; bl += wtot[1][k]; }
     if (i >= S.ns) return;
-    if (bu + totu > (unsigned long long)S.cap || bl + totl > (unsigned long long)S.cap) { S.ctl->overflow = 1; return; }
     const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
     slot3(S.up_beg, out)[s] = ub;
     slot3(S.up_cnt, out)[s] = (uint32_t)nup;
@@ -1048,7 +1155,7 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         else S.ctl->row_overflow = 1;
         return;
     }
-    write_rows(S, s, ub, nup, lb, nlo, [&](int k) { return lst[k * kNarrowBlock + tid]; });
+    write_rows(S, s, ub, nup, lb, nlo, [&](int k) { return S.stage[(int64_t)k * S.ns + i]; });
 }
 
 // Segments of the spheres with more than kMaxRow candidates: the same scan,
@@ -1101,6 +1208,40 @@ __global__ void __launch_bounds__(256) k_link(DevScene S) {
         }
         if (lo < cnt && pt[b0 + lo] == s) um[u] = b0 + lo;
         else ctl->asym = 1;  // segments not symmetric: the step is abandoned
+    }
+}
+
+// Tangential history of the new set, one lane per new pair (s, t): a pair
+// present in s's lower segment of the set in use keeps its history (binary
+// search), a new pair starts at zero.  Reads history buffer hb (laid out for
+// the set in use), writes buffer hb ^ 1 (laid out for the new set).  Only a
+// detection on the step's stream carries: the second stream's set takes the
+// history when it is adopted (the steps go on changing it meanwhile).
+__global__ void __launch_bounds__(256) k_carry(DevScene S) {
+    Ctl *ctl = S.ctl;
+    if (!due(ctl) || ctl->overflow || ctl->row_overflow) return;
+    const int out = out_slot(S), cur = ctl->buf, hb = ctl->hb;
+    const uint32_t *nps = slot3(S.ps, out), *npt = slot3(S.pt, out);
+    const uint32_t *olb = slot3(S.lo_beg, cur), *olc = slot3(S.lo_cnt, cur), *opt = slot3(S.pt, cur);
+    const double *oh = pick(S.hist, hb);
+    double *nh = pick(S.hist, hb ^ 1);
+    const int64_t n = min(ctl->n_pairs, S.cap);
+    for (int64_t p = (int64_t)xcd_block() * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t s = nps[p], t = npt[p];
+        double h0 = 0.0, h1 = 0.0, h2 = 0.0;
+        if (s < (uint32_t)S.ns) {
+            const uint32_t b0 = olb[s], cnt = olc[s];
+            uint32_t lo = 0, hi = cnt;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (opt[b0 + mid] < t) lo = mid + 1; else hi = mid;
+            }
+            if (lo < cnt && opt[b0 + lo] == t) {
+                const double *h = oh + 3 * ((int64_t)b0 + lo);
+                h0 = h[0]; h1 = h[1]; h2 = h[2];
+            }
+        }
+        nh[3 * p] = h0; nh[3 * p + 1] = h1; nh[3 * p + 2] = h2;
     }
 }
 
@@ -2050,7 +2191,8 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_integrate_big", "k_step_end", "k_plan", "k_audit_cells",
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
                                            "k_narrow_over", "k_region_margin", "k_guard_big", "k_bins_begin",
-                                           "audit_total", "k_pick_interval"};
+                                           "audit_total", "k_pick_interval", "k_narrow_rows", "k_narrow_base",
+                                           "k_carry"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -2075,6 +2217,13 @@ hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force) {
     }
     TIMED(K_POSE, hipLaunchKernelGGL(k_pose, dim3(capped_blocks(S.ns, 256, kStepGrid)), dim3(256), 0, st, S, force ? 1 : 0));
     return hipGetLastError();
+}
+
+// The second pass of the narrow phase: counts, bases, segments.
+static void narrow_rows(const DevScene &S, hipStream_t st) {
+    const unsigned nb = blocks_for(S.ns, kNarrowBlock);
+    TIMED(K_NARROW_BASE, hipLaunchKernelGGL(k_narrow_base, dim3(1), dim3(kBaseBlock), 0, st, S, (int64_t)nb));
+    TIMED(K_NARROW_ROWS, hipLaunchKernelGGL(k_narrow_rows, dim3(nb), dim3(kNarrowBlock), 0, st, S));
 }
 
 // Bin every sphere of the current positions.  In a step (which = 0: the
@@ -2116,12 +2265,16 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     }
     if (S.n_tri) {
         TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        narrow_rows(S, st);
         TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<true>, dim3(256), dim3(64), 0, st, S));
     } else {
         TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<false>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        narrow_rows(S, st);
         TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<false>, dim3(256), dim3(64), 0, st, S));
     }
     TIMED(K_LINK, hipLaunchKernelGGL(k_link, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
+    if (!S.bchain)
+        TIMED(K_CARRY, hipLaunchKernelGGL(k_carry, dim3(stride_blocks(S.cap, S.stride_cap)), dim3(256), 0, st, S));
     TIMED(K_DETECT_END, hipLaunchKernelGGL(k_detect_end, dim3(1), dim3(1), 0, st, S));
     return hipGetLastError();
 }
