@@ -63,9 +63,17 @@ def layout_bytes(kernel: str, st: dict) -> float:
     if kernel == "k_cell_scatter":
         return ns * 132
     if kernel == "k_narrow":
-        # positions, margins, bin starts; new pairs (partner, own id, history),
-        # upper entries (partner, own id), the current pairs merged for history
-        return ns * 88 + cells * 8 + 32 * P + 8 * U + 28 * P
+        # first pass: positions, margins, bin starts; the staged counts and
+        # candidates (both sides of every pair)
+        return ns * 88 + cells * 8 + ns * 8 + 4 * (P + U)
+    if kernel == "k_narrow_rows":
+        # staged counts and candidates read; segment bounds; new pairs and
+        # upper entries (partner, own id)
+        return ns * 8 + 4 * (P + U) + ns * 16 + 8 * P + 8 * U
+    if kernel == "k_carry":
+        # new pairs' ids, the current set's bounds and partners, history read
+        # and written
+        return 8 * P + ns * 8 + 28 * P + 24 * P
     if kernel == "k_link":
         return U * 28
     if kernel == "k_pairs":
@@ -105,8 +113,8 @@ def survey_step_bytes(p: float, p_m: float, k: float, deferred: bool) -> float:
 def survey_kernel_bytes(kernel: str, st: dict) -> float:
     """The same terms per launch of the kernel that carries them: k_reduce_waves
     a8 + a9 (+ the guard's 24 B per sphere when detection is deferred), k_pairs
-    a7, k_narrow a3 + a5 (per detection).  0 for a kernel the terms do not
-    name."""
+    a7, k_narrow a3 and k_carry a5 (per detection).  0 for a kernel the terms
+    do not name."""
     ns = st["spheres"]
     p = st["contact_sides"] / 2.0 / ns
     p_m = st["pairs"] / ns
@@ -115,7 +123,9 @@ def survey_kernel_bytes(kernel: str, st: dict) -> float:
     if kernel == "k_pairs":
         return ns * (60 + 92 * p + 8 * (p_m - p))
     if kernel == "k_narrow":
-        return ns * ((64 + 8 * p_m) + 64 * p_m)
+        return ns * (64 + 8 * p_m)
+    if kernel == "k_carry":
+        return ns * 64 * p_m
     return 0.0
 
 

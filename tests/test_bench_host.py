@@ -59,7 +59,8 @@ def test_survey_terms():
     p, pm = 1.5, 2.0
     assert abs(bench.survey_kernel_bytes("k_reduce_waves", st) - 1000 * (16 + 56 * p + 84 + 24)) < 1e-6
     assert abs(bench.survey_kernel_bytes("k_pairs", st) - 1000 * (60 + 92 * p + 8 * (pm - p))) < 1e-6
-    assert abs(bench.survey_kernel_bytes("k_narrow", st) - 1000 * (64 + 8 * pm + 64 * pm)) < 1e-6
+    assert abs(bench.survey_kernel_bytes("k_narrow", st) - 1000 * (64 + 8 * pm)) < 1e-6
+    assert abs(bench.survey_kernel_bytes("k_carry", st) - 1000 * 64 * pm) < 1e-6
 
 
 def test_audit_cost_is_amortised_over_its_period():
