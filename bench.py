@@ -321,13 +321,15 @@ def path_stats(res, desc_stats, mode):
                 detect_fraction=min(1.0, res["detections"] / max(1, res["steps"])))
 
 
-def roofline(res, desc_stats, mode):
+def roofline(res, desc_stats, mode, counters=True):
     """Roofline entry of the dominant kernel: `achieved` from the per-unit
     bytes of the hot-path scope table's measurement section (per sphere,
     with the measured contacts and candidates per sphere) times the spheres
     a launch processes, divided by the kernel's mean launch duration (HIP
     events inside the timed region when it is the kernel timed there);
-    `achieved_layout` the same with this library's own record layout."""
+    `achieved_layout` the same with this library's own record layout.
+    `traffic` only for the workload the committed counters were taken on
+    (`counters`; null for the other workloads)."""
     prof = res["prof"]
     k, (n, ms) = max(prof.items(), key=lambda kv: kv[1][1] if kv[0] != "audit_total" else -1)
     timed = k in res["prof_timed"]
@@ -347,7 +349,7 @@ def roofline(res, desc_stats, mode):
     gbs = b / avg_s / 1e9 if b else None
     gbl = bl / avg_s / 1e9 if bl else None
     return dict(bound="hbm", kernel=k, achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=(gbs / HBM_PEAK_GBS) if gbs else None, traffic=measured_traffic(k),
+                frac=(gbs / HBM_PEAK_GBS) if gbs else None, traffic=measured_traffic(k) if counters else None,
                 bytes_per_launch=b, avg_launch_us=avg_s * 1e6, timed_region=timed,
                 achieved_layout=gbl, frac_layout=(gbl / HBM_PEAK_GBS) if gbl else None,
                 bytes_per_launch_layout=bl)
@@ -539,7 +541,7 @@ def main():
                                    f"driven at slip 0.2 and co-simulated: every 10 steps one step's boundary "
                                    f"contacts are recorded, the wheel force read and its vertical velocity "
                                    f"prescribed (10 kg, 100 N load), learned interval",
-                          cosim=rm["cosim"], roofline=roofline(rm, mstats, "learned"))
+                          cosim=rm["cosim"], roofline=roofline(rm, mstats, "learned", counters=False))
     batched = None
     if "batched" in modes:
         t0 = time.perf_counter()
@@ -557,7 +559,7 @@ def main():
                                 f"{bdesc.n_clumps} clumps, {bdesc.n_spheres} spheres, {args.funnel_settle_s} s "
                                 f"into the discharge, learned interval, one captured graph of {args.steps} steps "
                                 f"per replay",
-                       roofline=roofline(rb, bstats, "learned"))
+                       roofline=roofline(rb, bstats, "learned", counters=False))
     precision = None
     if "precision" in modes:
         t0 = time.perf_counter()
@@ -572,7 +574,7 @@ def main():
             pstats = dict(spheres=ddesc.n_spheres, clumps=ddesc.n_clumps, fp32=(prec == "fp32"),
                           bins=rp["counts"]["bins"])
             precision[prec] = dict(path_line(rp, ddesc.n_spheres, pstats, "learned"),
-                                   roofline=roofline(rp, pstats, "learned"))
+                                   roofline=roofline(rp, pstats, "learned", counters=False))
         precision["fp32_over_fp64"] = (precision["fp32"]["sphere_steps_per_s"] /
                                        precision["fp64"]["sphere_steps_per_s"])
     if not results:
