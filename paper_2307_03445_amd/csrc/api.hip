@@ -140,6 +140,7 @@ struct cdem_scene {
         uint32_t *stage = nullptr;
         uint2 *stage_n = nullptr;
         unsigned long long *narrow_part = nullptr;
+        uint32_t *narrow_woff = nullptr;
         uint32_t *cell_of = nullptr, *cell_rank = nullptr, *sorted_id = nullptr, *sorted_owner = nullptr;
         uint32_t *over_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
         uint32_t *bin_v = nullptr, *bin_a = nullptr, *reg_occ = nullptr;
@@ -491,13 +492,15 @@ static int ahead_alloc(cdem_scene *sc) {
         a.stage = (uint32_t *)dev_alloc(sc, 4 * (size_t)kMaxRow * ns);
         a.stage_n = (uint2 *)dev_alloc(sc, sizeof(uint2) * ns);
         a.narrow_part = (unsigned long long *)dev_alloc(sc, 24 * (size_t)((ns + kNarrowBlock - 1) / kNarrowBlock));
+        a.narrow_woff =
+            (uint32_t *)dev_alloc(sc, 8 * (kNarrowBlock / 64) * (size_t)((ns + kNarrowBlock - 1) / kNarrowBlock));
         a.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
         a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
         a.mesh = (Mesh *)dev_alloc(sc, sizeof(Mesh) * std::max<int64_t>(S.n_mesh, 1));
         a.tri_box = (double *)dev_alloc(sc, 8 * (size_t)std::max<int64_t>(sc->tri_box_len, 1));
         if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_id || !a.sorted_owner ||
-            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.stage || !a.stage_n || !a.narrow_part || !a.over_list || !a.part_k ||
-            !a.mesh || !a.tri_box)
+            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.stage || !a.stage_n || !a.narrow_part ||
+            !a.narrow_woff || !a.over_list || !a.part_k || !a.mesh || !a.tri_box)
             return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
         Ctl z;
         memset(&z, 0, sizeof z);
@@ -540,7 +543,7 @@ static DevScene ahead_view(const cdem_scene *sc) {
     B.scan_bsum = a.scan_bsum;
     B.sorted_id = a.sorted_id; B.sorted_owner = a.sorted_owner; B.sorted_pos = a.sorted_pos;
     B.sorted_margin = a.sorted_margin; B.sorted_f4 = a.sorted_f4;
-    B.stage = a.stage; B.stage_n = a.stage_n; B.narrow_part = a.narrow_part;
+    B.stage = a.stage; B.stage_n = a.stage_n; B.narrow_part = a.narrow_part; B.narrow_woff = a.narrow_woff;
     B.bin_v = a.bin_v; B.bin_a = a.bin_a; B.reg_occ = a.reg_occ; B.bin_margin = a.bin_margin;
     B.part_k = a.part_k; B.over_list = a.over_list;
     B.mesh = a.mesh; B.tri_box = a.tri_box;
@@ -959,9 +962,10 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * std::max<int64_t>(ns, 1));
     S.stage = (uint32_t *)dev_alloc(sc, 4 * (size_t)kMaxRow * std::max<int64_t>(ns, 1));
     S.stage_n = (uint2 *)dev_alloc(sc, sizeof(uint2) * std::max<int64_t>(ns, 1));
-    S.narrow_part = (unsigned long long *)dev_alloc(sc, 24 * (size_t)((std::max<int64_t>(ns, 1) + kNarrowBlock - 1) /
-                                                                      kNarrowBlock));
-    if (!S.sorted_f4 || !S.stage || !S.stage_n || !S.narrow_part)
+    const size_t nnb = (size_t)((std::max<int64_t>(ns, 1) + kNarrowBlock - 1) / kNarrowBlock);
+    S.narrow_part = (unsigned long long *)dev_alloc(sc, 24 * nnb);
+    S.narrow_woff = (uint32_t *)dev_alloc(sc, 8 * (kNarrowBlock / 64) * nnb);
+    if (!S.sorted_f4 || !S.stage || !S.stage_n || !S.narrow_part || !S.narrow_woff)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     S.rec_cF = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));
     S.rec_cT = (double *)dev_alloc(sc, 24 * std::max<int64_t>(nc, 1));

@@ -13,11 +13,12 @@ constexpr int kMaxBnd = 4096;
 constexpr int kMaxMesh = 64;
 constexpr int kNarrowBlock = 512;  // narrow-phase workgroup: eight wavefronts share one segment allocation
 constexpr int kMaxRow = 16;        // candidates the narrow phase sorts in LDS per sphere (more: k_narrow_over)
-// Workgroup cap of the per-sphere binning and audit kernels, which loop over
-// logical blocks of 256 spheres: most steps launch them with nothing to do,
-// and a capped grid returns in a few microseconds where one workgroup per
-// block took ~30-50.  (The narrow phase keeps one workgroup per block: looped
-// over a capped grid, its detections took half as long again.)
+// Workgroup cap of the binning, bin-scan, segment-writing and audit kernels,
+// which loop over logical blocks: most steps launch them with nothing to do, and a
+// capped grid returns in a few microseconds where one workgroup per block
+// took ~30-50.  (The narrow phase's first pass keeps one workgroup per block:
+// looped, it needs more registers, and its detections took half as long
+// again.)
 constexpr int kStepGrid = 8192;
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
 constexpr int kRegionBins = 2;     // edge of an envelope region of the learned margins, in bins
@@ -163,6 +164,8 @@ struct DevScene {
                                      // and the boundaries in the sphere's first entry
     unsigned long long *narrow_part; // [ceil(ns / kNarrowBlock)][3] per narrow-phase workgroup: its upper entries,
                                      // pairs and boundary pairs, then (scanned) their bases
+    uint32_t *narrow_woff;           // [ceil(ns / kNarrowBlock)][kNarrowBlock / 64][2] each wavefront's upper
+                                     // entries and pairs below it in its workgroup
     // Active set, pair-major.  Each candidate pair is stored once, in the
     // "lower segment" of its lower-id sphere (partners above that id,
     // ascending, boundaries last), with its tangential history; the higher

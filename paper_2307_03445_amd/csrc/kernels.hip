@@ -342,15 +342,20 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *sh, ui
     return incl - v;
 }
 
+// Both passes take the tiles of kScanTile bins on at most kStepGrid
+// workgroups (a step that bins nothing returns at once).
 __global__ void __launch_bounds__(kScanBlock) k_scan_reduce(DevScene S, uint32_t *bsum, int which) {
     if (!chain_active(S, which)) return;
     __shared__ uint32_t sh[kScanBlock];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t v = 0;
-    for (int k = 0; k < kScanItems; k++) if (base + k < S.n_cells) v += S.cell_count[base + k];
-    uint32_t tot;
-    block_excl_scan(v, sh, tot);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+    const int64_t ntile = (S.n_cells + kScanTile - 1) / kScanTile;
+    for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {  // block_excl_scan ends on a barrier
+        const int64_t base = b * kScanTile + threadIdx.x * kScanItems;
+        uint32_t v = 0;
+        for (int k = 0; k < kScanItems; k++) if (base + k < S.n_cells) v += S.cell_count[base + k];
+        uint32_t tot;
+        block_excl_scan(v, sh, tot);
+        if (threadIdx.x == 0) bsum[b] = tot;
+    }
 }
 
 // Exclusive scan of the block sums in place: one workgroup of 1024 lanes,
@@ -394,19 +399,22 @@ __global__ void __launch_bounds__(kBsumBlock) k_scan_bsum(DevScene S, uint32_t *
 __global__ void __launch_bounds__(kScanBlock) k_scan_final(DevScene S, const uint32_t *bsum, int which) {
     if (!chain_active(S, which)) return;
     __shared__ uint32_t sh[kScanBlock];
-    int64_t base = (int64_t)blockIdx.x * kScanTile + threadIdx.x * kScanItems;
-    uint32_t loc[kScanItems];
-    uint32_t v = 0;
-    for (int k = 0; k < kScanItems; k++) {
-        loc[k] = base + k < S.n_cells ? S.cell_count[base + k] : 0u;
-        v += loc[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_excl_scan(v, sh, tot) + bsum[blockIdx.x];
-    for (int k = 0; k < kScanItems; k++) {
-        if (base + k < S.n_cells) S.cell_start[base + k] = ex;
-        ex += loc[k];
-        if (base + k == S.n_cells - 1) S.cell_start[S.n_cells] = ex;  // the end of the last bin
+    const int64_t ntile = (S.n_cells + kScanTile - 1) / kScanTile;
+    for (int64_t b = blockIdx.x; b < ntile; b += gridDim.x) {  // block_excl_scan ends on a barrier
+        const int64_t base = b * kScanTile + threadIdx.x * kScanItems;
+        uint32_t loc[kScanItems];
+        uint32_t v = 0;
+        for (int k = 0; k < kScanItems; k++) {
+            loc[k] = base + k < S.n_cells ? S.cell_count[base + k] : 0u;
+            v += loc[k];
+        }
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, sh, tot) + bsum[b];
+        for (int k = 0; k < kScanItems; k++) {
+            if (base + k < S.n_cells) S.cell_start[base + k] = ex;
+            ex += loc[k];
+            if (base + k == S.n_cells - 1) S.cell_start[S.n_cells] = ex;  // the end of the last bin
+        }
     }
 }
 
@@ -1041,10 +1049,17 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         if ((threadIdx.x & 63) == 0) sh[q][threadIdx.x >> 6] = v[q];
     }
     __syncthreads();
+    constexpr int kWaves = kNarrowBlock / 64;
     if (threadIdx.x < 3) {
         unsigned long long t = 0;
-        for (int k = 0; k < kNarrowBlock / 64; k++) t += sh[threadIdx.x][k];
+        for (int k = 0; k < kWaves; k++) t += sh[threadIdx.x][k];
         S.narrow_part[3 * blk + threadIdx.x] = t;
+    } else if (threadIdx.x >= 64 && threadIdx.x < 64 + 2 * kWaves) {
+        // each wavefront's upper entries and pairs below it in the workgroup
+        const int w = (threadIdx.x - 64) >> 1, q = (threadIdx.x - 64) & 1;
+        unsigned long long t = 0;
+        for (int k = 0; k < w; k++) t += sh[q][k];
+        S.narrow_woff[(blk * kWaves + w) * 2 + q] = (uint32_t)t;
     }
 }
 
@@ -1053,8 +1068,9 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
 // the reduction stream them), placed by a scan of the workgroup sums of the
 // first pass rather than by atomics (tens of thousands of workgroups adding
 // to one counter serialise): k_narrow_base turns the sums into bases (and the
-// totals, which also size a regrow), k_narrow_rows writes the segments of
-// the same workgroups of kNarrowBlock spheres, k_carry the history.
+// totals, which also size a regrow), k_narrow_rows writes the segments (with
+// each wavefront's offset in its workgroup, also from the first pass),
+// k_carry the history.
 __device__ __forceinline__ void staged_counts(const DevScene &S, int64_t i, int &cnt, int &nup, int &nbp) {
     cnt = 0; nup = 0; nbp = 0;
     if (i >= S.ns) return;
@@ -1123,39 +1139,41 @@ __global__ void __launch_bounds__(kBaseBlock) k_narrow_base(DevScene S, int64_t 
     }
 }
 
+// The segments, one wavefront per 64 spheres of a first-pass workgroup (its
+// base: the workgroup's scanned sums plus the wavefront's offset within the
+// workgroup, both from the first pass), over at most kStepGrid workgroups: a
+// step without a detection returns at once.  No barriers: each wavefront
+// works alone.
 __global__ void __launch_bounds__(kNarrowBlock) k_narrow_rows(DevScene S) {
     if (!due(S.ctl) || aborted(S.ctl)) return;  // uniform: set before this launch or not at all
-    const int tid = threadIdx.x;
-    const int64_t blk = xcd_block(), i = blk * kNarrowBlock + tid;
-    const int out = out_slot(S);
-    const uint32_t s = (uint32_t)i;
-    int cnt, nup, nbp;
-    staged_counts(S, i, cnt, nup, nbp);
-    const int nlo = cnt - nup;
-    // offsets within the workgroup: scans within each wavefront, then the
-    // wavefronts' totals through LDS
-    __shared__ uint32_t wtot[2][kNarrowBlock / 64];
-    uint32_t totu, totl;
-    const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
-    const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
-    const int wid = tid >> 6;
-    if ((tid & 63) == 0) { wtot[0][wid] = totu; wtot[1][wid] = totl; }
-    __syncthreads();
-    unsigned long long bu = S.narrow_part[3 * blk], bl = S.narrow_part[3 * blk + 1];
-    for (int k = 0; k < wid; k++) { bu += wtot[0][k]; bl += wtot[1][k]; }
-    if (i >= S.ns) return;
-    const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
-    slot3(S.up_beg, out)[s] = ub;
-    slot3(S.up_cnt, out)[s] = (uint32_t)nup;
-    slot3(S.lo_beg, out)[s] = lb;
-    slot3(S.lo_cnt, out)[s] = (uint32_t)nlo;
-    if (cnt > kMaxRow) {
-        const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_over, 1u);
-        if (k < (uint32_t)S.over_cap) S.over_list[k] = s;
-        else S.ctl->row_overflow = 1;
-        return;
+    constexpr int kWaves = kNarrowBlock / 64;
+    const int lane = threadIdx.x & 63, out = out_slot(S);
+    const int64_t nw = (S.ns + 63) / 64;  // wavefronts of spheres
+    for (int64_t gw = (int64_t)xcd_block() * kWaves + (threadIdx.x >> 6); gw < nw; gw += (int64_t)gridDim.x * kWaves) {
+        const int64_t blk = gw / kWaves, i = gw * 64 + lane;
+        int cnt, nup, nbp;
+        staged_counts(S, i, cnt, nup, nbp);
+        const int nlo = cnt - nup;
+        uint32_t totu, totl;
+        const uint32_t offu = wave_excl_scan((uint32_t)nup, totu);
+        const uint32_t offl = wave_excl_scan((uint32_t)nlo, totl);
+        const uint32_t *wo = S.narrow_woff + gw * 2;
+        const unsigned long long bu = S.narrow_part[3 * blk] + wo[0], bl = S.narrow_part[3 * blk + 1] + wo[1];
+        if (i >= S.ns) continue;
+        const uint32_t s = (uint32_t)i;
+        const uint32_t ub = (uint32_t)(bu + offu), lb = (uint32_t)(bl + offl);
+        slot3(S.up_beg, out)[s] = ub;
+        slot3(S.up_cnt, out)[s] = (uint32_t)nup;
+        slot3(S.lo_beg, out)[s] = lb;
+        slot3(S.lo_cnt, out)[s] = (uint32_t)nlo;
+        if (cnt > kMaxRow) {
+            const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_over, 1u);
+            if (k < (uint32_t)S.over_cap) S.over_list[k] = s;
+            else S.ctl->row_overflow = 1;
+            continue;
+        }
+        write_rows(S, s, ub, nup, lb, nlo, [&](int k) { return S.stage[(int64_t)k * S.ns + i]; });
     }
-    write_rows(S, s, ub, nup, lb, nlo, [&](int k) { return S.stage[(int64_t)k * S.ns + i]; });
 }
 
 // Segments of the spheres with more than kMaxRow candidates: the same scan,
@@ -2223,7 +2241,8 @@ hipError_t launch_pose(const DevScene &S, hipStream_t st, bool force) {
 static void narrow_rows(const DevScene &S, hipStream_t st) {
     const unsigned nb = blocks_for(S.ns, kNarrowBlock);
     TIMED(K_NARROW_BASE, hipLaunchKernelGGL(k_narrow_base, dim3(1), dim3(kBaseBlock), 0, st, S, (int64_t)nb));
-    TIMED(K_NARROW_ROWS, hipLaunchKernelGGL(k_narrow_rows, dim3(nb), dim3(kNarrowBlock), 0, st, S));
+    TIMED(K_NARROW_ROWS, hipLaunchKernelGGL(k_narrow_rows, dim3(std::min<unsigned>(nb, kStepGrid)), dim3(kNarrowBlock), 0,
+                                            st, S));
 }
 
 // Bin every sphere of the current positions.  In a step (which = 0: the
@@ -2247,9 +2266,10 @@ static void binning(const DevScene &S, int which, hipStream_t st) {
     }
     int64_t nblk = (S.n_cells + kScanTile - 1) / kScanTile;
     uint32_t *bsum = S.scan_bsum;
-    TIMED(K_SCAN_REDUCE, hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S, bsum, which));
+    const unsigned sb = (unsigned)std::min<int64_t>(nblk, kStepGrid);
+    TIMED(K_SCAN_REDUCE, hipLaunchKernelGGL(k_scan_reduce, dim3(sb), dim3(kScanBlock), 0, st, S, bsum, which));
     TIMED(K_SCAN_BSUM, hipLaunchKernelGGL(k_scan_bsum, dim3(1), dim3(kBsumBlock), 0, st, S, bsum, nblk, which));
-    TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nblk), dim3(kScanBlock), 0, st, S,
+    TIMED(K_SCAN_FINAL, hipLaunchKernelGGL(k_scan_final, dim3(sb), dim3(kScanBlock), 0, st, S,
                                            (const uint32_t *)bsum, which));
     TIMED(K_CELL_SCATTER, hipLaunchKernelGGL(k_cell_scatter, dim3(capped_blocks(S.ns, 256, kStepGrid)), dim3(256), 0, st, S,
                                              (const float *)nullptr, which));
