@@ -58,7 +58,7 @@ struct Grid {
     float pre_eps;           // slack of the FP32 prefilter: bounds its rounding of positions relative to (ox, oy, oz)
     float pre_lim;           // beyond this distance from the origin a sphere skips the prefilter
     double b;                // bin size
-    double rm_max;           // largest radius + largest margin of any sphere (the partner side of a reach)
+    double rm_max;           // largest radius + the margin cap (bounds the partner side of any reach)
     double r_max;            // largest radius (the partner side of the audit's reach)
     int32_t rnx, rny, rnz, rpad;  // envelope regions: blocks of kRegionBins^3 bins
     int64_t reg0;            // first global region id of the scene
@@ -81,7 +81,9 @@ struct Ctl {
     int32_t record;          // store per-contact data this step (1 every contact, 2 boundary contacts)
     int32_t nonfinite;       // a clump state became NaN/Inf
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
-    int64_t pad_c0, pad_c1;
+    uint32_t m_max_bits;     // largest margin any sphere takes at the detection in progress (float bits, >= 0)
+    int32_t pad_c0;
+    int64_t pad_c1;
     int64_t n_pairs;         // pairs of the detection in progress
     int64_t n_pairs_cur;     // pairs of the active set in use
     int32_t asym;            // an entry had no mirror (never expected): the step is abandoned

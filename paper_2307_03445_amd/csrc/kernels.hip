@@ -452,6 +452,7 @@ __global__ void __launch_bounds__(256) k_cell_scatter(DevScene S, const float *m
 __global__ void k_plan(DevScene S) {
     Ctl *c = S.ctl;
     if (!due(c) || aborted(c)) return;
+    c->m_max_bits = 0u;  // raised below (fixed rule) or by k_region_margin (learned)
     if (S.detect_mode == 0) { c->margin_cur = 0.0f; c->k_cur = 1; return; }
     if (S.detect_mode == 2) {  // per-region margins; k_bin_margin may shorten the interval
         c->k_cur = S.plan.k_max;
@@ -468,6 +469,7 @@ __global__ void k_plan(DevScene S) {
         double m = (double)S.plan.safety * (T * (double)v) + 0.5 * (double)a * T * T;
         m = fmax(fmin(m, (double)S.plan.margin_cap), (double)S.plan.margin_floor);
         c->margin_cur = (float)m;
+        c->m_max_bits = __float_as_uint(c->margin_cur);
         c->k_cur = S.plan.k_max;
         return;
     }
@@ -482,6 +484,7 @@ __global__ void k_plan(DevScene S) {
     m = fmax(m, (double)S.plan.margin_floor);
     if (S.plan.test_zero_margin) { m = 0.0; k = S.plan.k_max; }
     c->margin_cur = (float)m;
+    c->m_max_bits = __float_as_uint(c->margin_cur);
     c->k_cur = k;
 }
 
@@ -662,18 +665,24 @@ __global__ void __launch_bounds__(256) k_pick_interval(DevScene S, unsigned nblk
 
 // Margin of every occupied region for the interval chosen above (clamped to
 // [floor, cap]: a region that still needs more relies on the guard).
+// The largest of them bounds the partner side of the narrow phase's reach.
 __global__ void __launch_bounds__(256) k_region_margin(DevScene S) {
-    const Ctl *c = S.ctl;
+    Ctl *c = S.ctl;
     if (!due(c) || aborted(c) || S.detect_mode != 2) return;
     const double T = (double)(S.bchain ? S.horizon : c->k_cur) * S.h;
+    float mmax = 0.0f;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < S.n_regions;
          r += (int64_t)gridDim.x * blockDim.x) {
         if (!S.reg_occ[r]) continue;
         const double ve = (double)__uint_as_float(S.bin_v[r]), ae = (double)__uint_as_float(S.bin_a[r]);
         double m = (double)S.plan.safety * (T * ve) + 0.5 * ae * T * T;
         m = fmin(fmax(m, (double)S.plan.margin_floor), (double)S.plan.margin_cap);
-        S.bin_margin[r] = S.plan.test_zero_margin ? 0.0f : (float)m;
+        const float mf = S.plan.test_zero_margin ? 0.0f : (float)m;
+        S.bin_margin[r] = mf;
+        mmax = fmaxf(mmax, mf);
     }
+    for (int off = 32; off > 0; off >>= 1) mmax = fmaxf(mmax, __shfl_xor(mmax, off, 64));
+    if ((threadIdx.x & 63) == 0 && mmax > 0.0f) raise_max(&c->m_max_bits, mmax);  // filtered: few atomics land
 }
 
 // Training-data capture: remember each sphere's region and each region's
@@ -745,7 +754,9 @@ __device__ __forceinline__ NarrowSelf narrow_self(const DevScene &S, const Grid 
     if (S.pos_exp)
         n.slack = ldexp(fmax(fmax(fabs(n.P.x), fabs(n.P.y)), fabs(n.P.z)) + (n.P.w + (double)n.ms) + g.rm_max +
                             4.0 * g.r_max, -46);
-    n.reach = (n.P.w + (double)n.ms) + g.rm_max + 1e-9 + n.slack;
+    // the partner side: the largest radius and the largest margin any sphere
+    // takes at this detection
+    n.reach = (n.P.w + (double)n.ms) + (g.r_max + (double)__uint_as_float(S.ctl->m_max_bits)) + 1e-9 + n.slack;
     return n;
 }
 
