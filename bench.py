@@ -290,11 +290,18 @@ COUNTERS = os.path.join(ROOT, "profiles", "counters_rover_bed.json")
 
 
 def kernel_source_hash() -> str:
+    """Fingerprint of the kernel sources with comments and layout removed
+    (a change of wording leaves the compiled kernels, and so the counters
+    taken on them, as they were)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 

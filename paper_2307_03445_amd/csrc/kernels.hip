@@ -10,15 +10,16 @@
 //   detection        (when due: every step, or every k steps with the
 //                    enlarged contact geometry of Sec. 2.2) scan of the bin
 //                    counts, scatter into bin order, k_narrow (one thread
-//                    per slot, in bin order): FP32 prefilter over the bins
-//                    in reach, exact FP64 predicate, candidates sorted by
-//                    partner id in LDS and staged per sphere; k_narrow_rows
-//                    (one thread per sphere id): segments allocated per
-//                    workgroup, tangential history carried over from the
-//                    current active set (boundary partners:
-//                    analytic boundaries, and mesh triangles through the
-//                    boxes of k_tri_boxes / k_tri_scene_boxes); k_link
-//                    points each higher sphere's entry at its pair;
+//                    per sphere): FP32 prefilter over the bins in reach,
+//                    exact FP64 predicate (boundary partners: analytic
+//                    boundaries, and mesh triangles through the boxes of
+//                    k_tri_boxes / k_tri_scene_boxes), candidates sorted by
+//                    partner id in LDS and staged per sphere;
+//                    k_narrow_base scans the workgroups' counts into
+//                    segment bases (no atomics), k_narrow_rows writes the
+//                    segments, k_link points each higher sphere's entry at
+//                    its pair, k_carry carries the tangential history over
+//                    from the current active set;
 //   k_pairs          every candidate pair once, one lane per pair: exact
 //                    predicate, kinematics of Eq. kinematicsContactInfo and
 //                    the Hertz-Mindlin law of Eqs. normal_tangential_force_model1/2,
