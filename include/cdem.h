@@ -278,7 +278,7 @@ int cdem_record_next_step(cdem_scene *s, int on);
 int cdem_set_graph(cdem_scene *s, int32_t steps_per_graph);
 
 /* Autotuner: time `steps` steps for each candidate bin-size factor (bins of
- * 1, 1.25, 1.5 or 1.75 times the minimum R_max + margin cap) and launch shape of
+ * 0.75, 1, 1.25, 1.5 or 1.75 times R_max + margin cap) and launch shape of
  * the grid-stride kernels, and keep the fastest.  The tuning steps are
  * ordinary steps of the simulation (results do not depend on the choice).
  * *bin_factor and *stride_cap (may be NULL) receive the choice. */

@@ -287,9 +287,9 @@ static bool finite_all(const double *p, size_t n) {
 // allocate the bin arrays when they grow.
 static int build_grids(cdem_scene *sc) {
     DevScene &S = sc->S;
-    // bins of R_max + margin cap: a sphere's candidates lie within its reach
-    // (R + m) + (R_max + m_cap), at most two bins away, and the scan visits
-    // only the bins that reach touches
+    // bins of about R_max + margin cap: a sphere's candidates lie within its
+    // reach (R + m) + (R_max + m), and the scan visits only the bins that
+    // reach touches (smaller bins fit it more tightly, at more rows)
     double b = (sc->rmax + std::max(0.0, sc->det.margin_cap)) * sc->bin_factor;
     if (!(b > 0.0)) b = 1.0;  // no spheres: any positive bin size will do
     int64_t cell0 = 0, reg0 = 0;
@@ -1683,7 +1683,7 @@ extern "C" int cdem_set_graph(cdem_scene *sc, int32_t steps_per_graph) {
 
 extern "C" int cdem_autotune(cdem_scene *sc, int32_t steps, double *bin_factor, int32_t *stride_cap) {
     if (!sc || steps < 1) return fail(sc, CDEM_E_INVALID, "bad arguments");
-    const double factors[] = {1.0, 1.25, 1.5, 1.75};
+    const double factors[] = {0.75, 1.0, 1.25, 1.5, 1.75};
     const int32_t caps[] = {2048, 4096, 8192, 16384};
     double best = 1e300, bf = sc->bin_factor;
     int32_t bc = sc->S.stride_cap;

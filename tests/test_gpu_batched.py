@@ -54,8 +54,8 @@ def test_graph_replay_and_autotune_do_not_change_results(batch):
     ref, g = _scene(batch), _scene(batch)
     ref.step(120)
     g.set_graph(20)
-    choice = g.autotune(5)          # 81 tuning steps: ordinary steps of the run
-    assert choice["bin_factor"] in (1.0, 1.25, 1.5, 1.75)
+    choice = g.autotune(5)          # 101 tuning steps: ordinary steps of the run
+    assert choice["bin_factor"] in (0.75, 1.0, 1.25, 1.5, 1.75)
     assert choice["stride_cap"] in (2048, 4096, 8192, 16384)
     done = g.counts()["steps"]
     g.step(120 - done)
