@@ -323,34 +323,44 @@ def test_clumps_at_the_wavefront_size_boundary(prec):
         assert np.array_equal(sf[k], sg[k]), k
 
 
-def _crowded_scene(n_small=70, n_big=3):
+def _crowded_scene(n_small=70, n_big=3, walls=False):
     """Large spheres each touched by more partners than the narrow phase sorts
-    in LDS (its overflow path), on a Fibonacci lattice of small spheres."""
-    big, small = I.sphere_template(5e-3), I.sphere_template(8e-4)
+    in LDS (its overflow path), on a Fibonacci lattice of small spheres.  With
+    `walls`, a floor the large spheres press 1 um into and a side wall the
+    first one presses, the small spheres that would lie outside them left out:
+    spheres past the LDS rows that also have boundary partners."""
+    R, r = 5e-3, 8e-4
+    big, small = I.sphere_template(R), I.sphere_template(r)
     k = np.arange(n_small) + 0.5
     phi = np.arccos(1 - 2 * k / n_small)
     th = np.pi * (1 + 5 ** 0.5) * k
     dirs = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], 1)
+    centres = [np.array([0.02 + 0.02 * j, 0.03, 0.03]) for j in range(n_big)]
+    lo = (centres[0][0] - R + 1e-6, 0.0, centres[0][2] - R + 1e-6)
     X, CT = [], []
-    for j in range(n_big):
-        c = np.array([0.02 + 0.02 * j, 0.03, 0.03])
+    for c in centres:
         X.append(c)
         CT.append(0)
-        X.extend(c + (5e-3 + 8e-4 - 5e-6) * dirs)
-        CT.extend([1] * n_small)
+        p = c + (R + r - 5e-6) * dirs
+        if walls:
+            p = p[(p[:, 0] - r > lo[0]) & (p[:, 2] - r > lo[2])]
+        X.extend(p)
+        CT.extend([1] * len(p))
     X = np.array(X)
     nc = len(X)
     g = np.random.default_rng(7)
     v = g.uniform(-0.01, 0.01, (nc, 3))
     mat = np.tile(np.array(I.BOX_MAT), (nc, 1))
+    bnd = I.box_walls(lo, (0.08, 0.06, 0.06), I.BOX_MAT) if walls else None
     return I.assemble([big, small], CT, X, np.tile([1.0, 0, 0, 0], (nc, 1)), v, np.zeros((nc, 3)), mat,
-                      (0, 0, 0), (0, 0, 0, 0.08, 0.06, 0.06), 1e-6)
+                      (0, 0, 0), (0, 0, 0, 0.08, 0.06, 0.06), 1e-6, bnd=bnd)
 
 
 @gpu
+@pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("mode", ["plain", "fixed"])
-def test_spheres_with_more_candidates_than_lds_rows(mode):
-    d = _crowded_scene()
+def test_spheres_with_more_candidates_than_lds_rows(mode, walls):
+    d = _crowded_scene(walls=walls)
     sc, o = _scene(d, "fp64"), oracle.Oracle(d)
     if mode == "fixed":
         sc.set_detection("fixed", k_max=10, safety=1.5, margin_cap=2e-4, audit_period=5)
@@ -358,8 +368,13 @@ def test_spheres_with_more_candidates_than_lds_rows(mode):
     sc.step(1)
     o.eval()
     cg, co = sc.contacts(), o.contacts()
-    per = np.bincount(np.r_[co["a"], co["b"]].astype(int), minlength=d.n_spheres)
-    assert per.max() > 64
+    per = np.bincount(np.r_[co["a"], co["b"]].astype(int), minlength=d.n_spheres + 8)
+    assert per[:d.n_spheres].max() > (32 if walls else 64)
+    if walls:  # an over-full sphere with boundary partners: the floor, and for the first the side wall
+        over = np.nonzero(per[:d.n_spheres] > 16)[0]
+        on_wall = co["a"][co["b"] >= d.n_spheres]
+        assert np.isin(over, on_wall).sum() >= 3
+        assert (on_wall == 0).sum() == 2
     compare_pairs(cg, co)
     assert np.array_equal(cg["F"], co["F"]) and np.array_equal(cg["u"], co["u"])
     sc.step(20)
