@@ -135,13 +135,14 @@ struct cdem_scene {
         hipEvent_t ev_snap = nullptr, ev_det = nullptr;
         Ctl *ctl = nullptr;
         double4 *cst = nullptr, *spos = nullptr, *sorted_pos = nullptr;
-        float *cacc = nullptr, *sorted_margin = nullptr, *bin_margin = nullptr;
+        float *cacc = nullptr, *bin_margin = nullptr;
+        uint4 *sorted_meta = nullptr;
         float4 *sorted_f4 = nullptr;
         uint32_t *stage = nullptr;
         uint2 *stage_n = nullptr;
         unsigned long long *narrow_part = nullptr;
         uint32_t *narrow_woff = nullptr;
-        uint32_t *cell_of = nullptr, *cell_rank = nullptr, *sorted_id = nullptr, *sorted_owner = nullptr;
+        uint32_t *cell_of = nullptr, *cell_rank = nullptr;
         uint32_t *over_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
         uint32_t *bin_v = nullptr, *bin_a = nullptr, *reg_occ = nullptr;
         double *part_k = nullptr;
@@ -484,10 +485,8 @@ static int ahead_alloc(cdem_scene *sc) {
         a.spos = (double4 *)dev_alloc(sc, sizeof(double4) * ns);
         a.cell_of = (uint32_t *)dev_alloc(sc, 4 * ns);
         a.cell_rank = (uint32_t *)dev_alloc(sc, 4 * ns);
-        a.sorted_id = (uint32_t *)dev_alloc(sc, 4 * ns);
-        a.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * ns);
+        a.sorted_meta = (uint4 *)dev_alloc(sc, sizeof(uint4) * ns);
         a.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * ns);
-        a.sorted_margin = (float *)dev_alloc(sc, 4 * ns);
         a.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * ns);
         a.stage = (uint32_t *)dev_alloc(sc, 4 * (size_t)kMaxRow * ns);
         a.stage_n = (uint2 *)dev_alloc(sc, sizeof(uint2) * ns);
@@ -498,8 +497,8 @@ static int ahead_alloc(cdem_scene *sc) {
         a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
         a.mesh = (Mesh *)dev_alloc(sc, sizeof(Mesh) * std::max<int64_t>(S.n_mesh, 1));
         a.tri_box = (double *)dev_alloc(sc, 8 * (size_t)std::max<int64_t>(sc->tri_box_len, 1));
-        if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_id || !a.sorted_owner ||
-            !a.sorted_pos || !a.sorted_margin || !a.sorted_f4 || !a.stage || !a.stage_n || !a.narrow_part ||
+        if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_meta ||
+            !a.sorted_pos || !a.sorted_f4 || !a.stage || !a.stage_n || !a.narrow_part ||
             !a.narrow_woff || !a.over_list || !a.part_k || !a.mesh || !a.tri_box)
             return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
         Ctl z;
@@ -541,8 +540,7 @@ static DevScene ahead_view(const cdem_scene *sc) {
     B.cst = a.cst; B.cacc = a.cacc; B.spos = a.spos;
     B.cell_of = a.cell_of; B.cell_rank = a.cell_rank; B.cell_count = a.cell_count; B.cell_start = a.cell_start;
     B.scan_bsum = a.scan_bsum;
-    B.sorted_id = a.sorted_id; B.sorted_owner = a.sorted_owner; B.sorted_pos = a.sorted_pos;
-    B.sorted_margin = a.sorted_margin; B.sorted_f4 = a.sorted_f4;
+    B.sorted_meta = a.sorted_meta; B.sorted_pos = a.sorted_pos; B.sorted_f4 = a.sorted_f4;
     B.stage = a.stage; B.stage_n = a.stage_n; B.narrow_part = a.narrow_part; B.narrow_woff = a.narrow_woff;
     B.bin_v = a.bin_v; B.bin_a = a.bin_a; B.reg_occ = a.reg_occ; B.bin_margin = a.bin_margin;
     B.part_k = a.part_k; B.over_list = a.over_list;
@@ -955,10 +953,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     S.cdet = (double4 *)dev_alloc(sc, 2 * sizeof(double4) * std::max<int64_t>(nc, 1));
     S.cell_of = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.cell_rank = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    S.sorted_id = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
-    S.sorted_owner = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
+    S.sorted_meta = (uint4 *)dev_alloc(sc, sizeof(uint4) * std::max<int64_t>(ns, 1));
     S.sorted_pos = (double4 *)dev_alloc(sc, sizeof(double4) * std::max<int64_t>(ns, 1));
-    S.sorted_margin = (float *)dev_alloc(sc, 4 * std::max<int64_t>(ns, 1));
     S.sorted_f4 = (float4 *)dev_alloc(sc, sizeof(float4) * std::max<int64_t>(ns, 1));
     S.stage = (uint32_t *)dev_alloc(sc, 4 * (size_t)kMaxRow * std::max<int64_t>(ns, 1));
     S.stage_n = (uint2 *)dev_alloc(sc, sizeof(uint2) * std::max<int64_t>(ns, 1));
@@ -991,8 +987,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
         if (!S.lo_beg[k] || !S.lo_cnt[k] || !S.up_beg[k] || !S.up_cnt[k] || !S.smargin[k])
             return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     }
-    if (!S.cdet || !S.spos || !S.cell_of || !S.cell_rank || !S.sorted_id || !S.sorted_owner ||
-        !S.sorted_pos || !S.sorted_margin || !S.rec_cF || !S.rec_cT || !S.ctl)
+    if (!S.cdet || !S.spos || !S.cell_of || !S.cell_rank || !S.sorted_meta || !S.sorted_pos || !S.rec_cF ||
+        !S.rec_cT || !S.ctl)
         return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     if (!big.empty()) {
         S.sF = (double *)dev_alloc(sc, 24 * ns);

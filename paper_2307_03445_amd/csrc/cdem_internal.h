@@ -156,9 +156,9 @@ struct DevScene {
     uint32_t *cell_start;            // [n_cells + 1] exclusive scan of the counts, then the total
     uint32_t *scan_bsum;             // block sums of the bin-count scan
     uint32_t *cell_rank;             // [ns] each sphere's rank within its bin, taken when counting
-    uint32_t *sorted_id, *sorted_owner;
+    uint4 *sorted_meta;              // per slot of the bins: sphere id, clump, margin (float bits; 0 in the
+                                     // audit's binning), 0
     double4 *sorted_pos;
-    float *sorted_margin;
     float4 *sorted_f4;               // FP32 prefilter record: position - grid origin, radius + margin
     uint32_t *stage;                 // [kMaxRow][ns] each sphere's candidates from the narrow phase's first pass
     uint2 *stage_n;                  // [ns] their count; how many lie below the sphere (low 16 bits) and are

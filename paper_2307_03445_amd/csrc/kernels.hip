@@ -426,17 +426,17 @@ __device__ __forceinline__ void scatter_sphere(const DevScene &S, const float *m
     uint32_t cell = S.cell_of[s];
     uint32_t slot = S.cell_start[cell] + S.cell_rank[s];  // its rank within the bin, from the count
     double4 p = S.spos[s];
-    S.sorted_id[slot] = (uint32_t)s;
-    S.sorted_owner[slot] = S.owner[s];
+    const uint32_t own = S.owner[s];
     S.sorted_pos[slot] = p;
     const Grid &g = S.grids[S.sscene[s]];
     if (which) {  // the audit's binning: prefilter records without margin
+        S.sorted_meta[slot] = make_uint4((uint32_t)s, own, 0u, 0u);
         S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w);
         return;
     }
     float m = S.detect_mode == 2 ? S.bin_margin[region_of(g, cell)] : (margin_src ? margin_src[s] : S.ctl->margin_cur);
+    S.sorted_meta[slot] = make_uint4((uint32_t)s, own, __float_as_uint(m), 0u);
     S.sorted_f4[slot] = make_float4((float)(p.x - g.ox), (float)(p.y - g.oy), (float)(p.z - g.oz), (float)p.w + m);
-    S.sorted_margin[slot] = m;
     slot3(S.smargin, out_slot(S))[s] = m;
 }
 
@@ -791,19 +791,21 @@ __device__ __forceinline__ void slot_batches(const float4 *rec, uint32_t jb, uin
 // The exact predicate of the enlarged geometry for slot j (another clump,
 // d^2 < ((R_s + R_t) + (m_s + m_t))^2); returns the partner's id or ~0u.
 __device__ __forceinline__ uint32_t narrow_exact(const DevScene &S, const NarrowSelf &n, uint32_t j) {
-    if (S.sorted_owner[j] == n.own) return ~0u;
+    const uint4 md = S.sorted_meta[j];
+    if (md.y == n.own) return ~0u;
     const double4 Q = S.sorted_pos[j];
     const double dx = Q.x - n.P.x, dy = Q.y - n.P.y, dz = Q.z - n.P.z;
     const double d2 = dx * dx + dy * dy + dz * dz;
     double Sr = n.P.w + Q.w;
-    Sr = Sr + (((double)n.ms + (double)S.sorted_margin[j]) + n.slack);
-    return d2 < Sr * Sr ? S.sorted_id[j] : ~0u;
+    Sr = Sr + (((double)n.ms + (double)__uint_as_float(md.z)) + n.slack);
+    return d2 < Sr * Sr ? md.x : ~0u;
 }
 // The same test with the slot's record loaded beforehand (so that the loads
 // of several slots are in flight together).
 struct SlotRec { double4 Q; uint32_t own, id; float m; };
 __device__ __forceinline__ SlotRec load_slot(const DevScene &S, uint32_t j) {
-    return SlotRec{S.sorted_pos[j], S.sorted_owner[j], S.sorted_id[j], S.sorted_margin[j]};
+    const uint4 md = S.sorted_meta[j];
+    return SlotRec{S.sorted_pos[j], md.y, md.x, __uint_as_float(md.z)};
 }
 __device__ __forceinline__ uint32_t narrow_exact_rec(const NarrowSelf &n, const SlotRec &r) {
     if (r.own == n.own) return ~0u;
@@ -1900,12 +1902,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                 return exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
             };
             auto exact = [&](uint32_t j) {
-                if (S.sorted_owner[j] == own) return;
+                const uint4 md = S.sorted_meta[j];
+                if (md.y == own) return;
                 double4 Q = S.sorted_pos[j];
                 double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
                 double d2 = dx * dx + dy * dy + dz * dz;
                 double Sr = P.w + Q.w;
-                if (d2 < Sr * Sr) { found++; if (!in_row(S.sorted_id[j])) missed++; }
+                if (d2 < Sr * Sr) { found++; if (!in_row(md.x)) missed++; }
             };
             // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
             int npre = 0;
@@ -1924,9 +1927,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                 for (int k = 0; k < npre; k += 2) {
                     const bool two = k + 1 < npre;
                     const uint32_t j0 = alst[k * 256 + tid], j1 = two ? alst[(k + 1) * 256 + tid] : j0;
-                    const uint32_t o0 = S.sorted_owner[j0], o1 = S.sorted_owner[j1];
+                    const uint4 m0 = S.sorted_meta[j0], m1 = S.sorted_meta[j1];
                     const double4 Q0 = S.sorted_pos[j0], Q1 = S.sorted_pos[j1];
-                    const uint32_t i0 = S.sorted_id[j0], i1 = S.sorted_id[j1];
+                    const uint32_t o0 = m0.y, o1 = m1.y, i0 = m0.x, i1 = m1.x;
                     for (int u = 0; u < (two ? 2 : 1); u++) {
                         const uint32_t o = u ? o1 : o0, id = u ? i1 : i0;
                         const double4 Q = u ? Q1 : Q0;
