@@ -347,7 +347,8 @@ def roofline(res, desc_stats, mode, counters=True):
     launches = n
     if k == "k_pose":  # works on the steps that detect or audit
         launches = max(1, res["pass_detections"] + (res["audit"] or {}).get("audits", 0))
-    if k in ("k_narrow", "k_narrow_base", "k_narrow_rows", "k_link", "k_carry", "k_cell_count", "k_cell_scatter",
+    if k in ("k_narrow", "k_narrow_fb", "k_narrow_base", "k_narrow_rows", "k_link", "k_carry", "k_cell_count",
+             "k_cell_scatter",
              "k_detect_begin", "k_scan_reduce", "k_scan_final"):
         launches = max(1, res["detections"] if timed else res["pass_detections"])
     avg_s = ms / 1e3 / launches

@@ -143,7 +143,7 @@ struct cdem_scene {
         unsigned long long *narrow_part = nullptr;
         uint32_t *narrow_woff = nullptr;
         uint32_t *cell_of = nullptr, *cell_rank = nullptr;
-        uint32_t *over_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
+        uint32_t *over_list = nullptr, *fb_list = nullptr, *cell_count = nullptr, *cell_start = nullptr, *scan_bsum = nullptr;
         uint32_t *bin_v = nullptr, *bin_a = nullptr, *reg_occ = nullptr;
         double *part_k = nullptr;
         Mesh *mesh = nullptr;          // the meshes at the snapshot
@@ -494,12 +494,13 @@ static int ahead_alloc(cdem_scene *sc) {
         a.narrow_woff =
             (uint32_t *)dev_alloc(sc, 8 * (kNarrowBlock / 64) * (size_t)((ns + kNarrowBlock - 1) / kNarrowBlock));
         a.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
+        a.fb_list = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(S.ns, 1));
         a.part_k = (double *)dev_alloc(sc, 2 * 8 * (size_t)kRegionBlocksMax);
         a.mesh = (Mesh *)dev_alloc(sc, sizeof(Mesh) * std::max<int64_t>(S.n_mesh, 1));
         a.tri_box = (double *)dev_alloc(sc, 8 * (size_t)std::max<int64_t>(sc->tri_box_len, 1));
         if (!a.ctl || !a.cst || !a.cacc || !a.spos || !a.cell_of || !a.cell_rank || !a.sorted_meta ||
             !a.sorted_pos || !a.sorted_f4 || !a.stage || !a.stage_n || !a.narrow_part ||
-            !a.narrow_woff || !a.over_list || !a.part_k || !a.mesh || !a.tri_box)
+            !a.narrow_woff || !a.over_list || !a.fb_list || !a.part_k || !a.mesh || !a.tri_box)
             return fail(sc, CDEM_E_OOM, "buffers of the detection ahead");
         Ctl z;
         memset(&z, 0, sizeof z);
@@ -543,7 +544,7 @@ static DevScene ahead_view(const cdem_scene *sc) {
     B.sorted_meta = a.sorted_meta; B.sorted_pos = a.sorted_pos; B.sorted_f4 = a.sorted_f4;
     B.stage = a.stage; B.stage_n = a.stage_n; B.narrow_part = a.narrow_part; B.narrow_woff = a.narrow_woff;
     B.bin_v = a.bin_v; B.bin_a = a.bin_a; B.reg_occ = a.reg_occ; B.bin_margin = a.bin_margin;
-    B.part_k = a.part_k; B.over_list = a.over_list;
+    B.part_k = a.part_k; B.over_list = a.over_list; B.fb_list = a.fb_list;
     B.mesh = a.mesh; B.tri_box = a.tri_box;
     B.store_speed = 0; B.store_acc = 0;
     B.plan.audit_period = 0;
@@ -973,7 +974,8 @@ extern "C" int cdem_create(const cdem_scene_desc *d, const cdem_allocator *alloc
     // many small ones); a list of ns/8 (at least 4096) of them per detection
     S.over_cap = std::max<int64_t>(4096, ns / 8);
     S.over_list = (uint32_t *)dev_alloc(sc, 4 * S.over_cap);
-    if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
+    S.fb_list = (uint32_t *)dev_alloc(sc, 4 * std::max<int64_t>(S.ns, 1));
+    if (!S.sspeed || !S.cacc || !S.cell_t || !S.over_list || !S.fb_list) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));
     if (d->n_tri) {
         S.tri_box = (double *)dev_alloc(sc, 8 * (size_t)sc->tri_box_len);
         if (!S.tri_box) return bail(fail(sc, CDEM_E_OOM, "device allocation failed"));

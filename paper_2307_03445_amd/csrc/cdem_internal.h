@@ -20,6 +20,10 @@ constexpr int kMaxRow = 16;        // candidates the narrow phase sorts in LDS p
 // looped, it needs more registers, and its detections took half as long
 // again.)
 constexpr int kStepGrid = 8192;
+// Workgroups (of one wavefront) of the narrow phase's exact pass over the
+// spheres its first pass leaves: few spheres, so a small grid whose launch
+// on a step without detection costs next to nothing.
+constexpr int kFbGrid = 512;
 constexpr int kBigClump = 64;      // clumps with more spheres reduce through a workgroup
 constexpr int kRegionBins = 2;     // edge of an envelope region of the learned margins, in bins
 
@@ -82,7 +86,7 @@ struct Ctl {
     int32_t nonfinite;       // a clump state became NaN/Inf
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
     uint32_t m_max_bits;     // largest margin any sphere takes at the detection in progress (float bits, >= 0)
-    int32_t pad_c0;
+    int32_t n_fb;            // spheres of this detection whose candidates k_narrow_fb finds
     int64_t pad_c1;
     int64_t n_pairs;         // pairs of the detection in progress
     int64_t n_pairs_cur;     // pairs of the active set in use
@@ -198,6 +202,7 @@ struct DevScene {
     double *part_k;                   // [2][region-kernel workgroups] sums of the interval rule's margin model
     int64_t n_ablocks;
     uint32_t *over_list;             // [over_cap] spheres whose rows k_narrow_over fills
+    uint32_t *fb_list;               // [ns] spheres whose candidates k_narrow_fb finds (FP64 scan)
     int64_t over_cap;
     // recording
     uint8_t *rec_state;              // per pair of the recorded step
@@ -287,7 +292,7 @@ struct KernelTimer {
 enum KernelId { K_POSE, K_DETECT_BEGIN, K_CELL_COUNT, K_SCAN_REDUCE, K_SCAN_BSUM, K_SCAN_FINAL, K_CELL_SCATTER,
                 K_NARROW, K_DETECT_END, K_FORCE, K_FORCE_BIG, K_INTEGRATE_BIG, K_STEP_END, K_PLAN, K_AUDIT,
                 K_LINK, K_REDUCE, K_BIN_FEATURES, K_BIN_MARGIN, K_NARROW_OVER, K_REGION_MARGIN, K_GUARD_BIG, K_BINS_BEGIN,
-                K_AUDIT_ALL, K_PICK_INTERVAL, K_NARROW_ROWS, K_NARROW_BASE, K_CARRY, K_COUNT };
+                K_AUDIT_ALL, K_PICK_INTERVAL, K_NARROW_ROWS, K_NARROW_BASE, K_CARRY, K_NARROW_FB, K_COUNT };
 extern const char *const kKernelNames[K_COUNT];
 extern KernelTimer *g_timer;
 

@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
     if (i == 0 && det) {
         S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_bp = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
-        S.ctl->n_over = 0;
+        S.ctl->n_over = 0; S.ctl->n_fb = 0;
     }
     if (i == 0 && aud) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
 }
@@ -306,7 +306,7 @@ __global__ void __launch_bounds__(256) k_detect_begin(DevScene S, int which) {
         for (int64_t k = i; k < S.n_regions; k += stride) { S.bin_v[k] = 0; S.bin_a[k] = 0; S.reg_occ[k] = 0; }
     if (i == 0 && !which) {
         S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_bp = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
-        S.ctl->n_over = 0;
+        S.ctl->n_over = 0; S.ctl->n_fb = 0;
     }
     if (i == 0 && which == 1) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
 }
@@ -985,40 +985,85 @@ __device__ __forceinline__ void write_rows(const DevScene &S, uint32_t s, uint32
 // sums its spheres' upper entries, pairs and boundary pairs, which
 // k_narrow_base turns into the bases of their segments.
 // TRI: the scene has triangles (the kernel without them keeps fewer registers).
+// Candidate t of sphere s: inserted in order into the lane's LDS column
+// (entry k at col[k stride], at most kMaxRow kept); all candidates, those
+// below s and the boundary ones are counted.
+__device__ __forceinline__ void emit_sorted(uint32_t *col, int stride, uint32_t t, uint32_t s, int64_t ns, int &cnt,
+                                            int &nup, int &nbp) {
+    if (cnt < kMaxRow) {
+        int k = cnt;
+        while (k > 0 && col[(k - 1) * stride] > t) {
+            col[k * stride] = col[(k - 1) * stride];
+            k--;
+        }
+        col[k * stride] = t;
+    }
+    cnt++;
+    nup += t < s;
+    nbp += t >= (uint32_t)ns;
+}
+
+// Staging of sphere s: its counts (below it and boundaries packed for a
+// listed sphere), then entry k at stage[k ns + s]; a sphere with more than
+// kMaxRow candidates stages its counts only.
+template <class Get>
+__device__ __forceinline__ void stage_sphere(const DevScene &S, uint32_t s, int cnt, int nup, int nbp, Get get) {
+    if (cnt > kMaxRow) {
+        S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup);
+        S.stage[s] = (uint32_t)nbp;
+        return;
+    }
+    S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup | ((uint32_t)nbp << 16));
+    for (int k = 0; k < cnt; k++) S.stage[(int64_t)k * S.ns + s] = get(k);
+}
+
 template <bool TRI>
 __device__ __forceinline__ void narrow_sphere(const DevScene &S, uint32_t s, uint32_t *lst, int &cnt, int &nup,
                                               int &nbp) {
     const int tid = threadIdx.x;
-    auto emit = [&](uint32_t t) {
-        if (cnt < kMaxRow) {
-            int k = cnt;
-            while (k > 0 && lst[(k - 1) * kNarrowBlock + tid] > t) {
-                lst[k * kNarrowBlock + tid] = lst[(k - 1) * kNarrowBlock + tid];
-                k--;
-            }
-            lst[k * kNarrowBlock + tid] = t;
-        }
-        cnt++;
-        nup += t < s;
-        nbp += t >= (uint32_t)S.ns;
-    };
+    auto emit = [&](uint32_t t) { emit_sorted(lst + tid, kNarrowBlock, t, s, S.ns, cnt, nup, nbp); };
     const Grid &g = S.grids[S.sscene[s]];
-    const NarrowSelf n = narrow_self(S, g, s);
     // First the cheap FP32 test over every slot in reach, keeping the slots
     // that pass in the LDS list; then the exact test over that short list.
     // Split this way, a wavefront runs the exact test and the sorted insert
     // as often as its busiest lane has prefilter hits, not as often as it
-    // has slots in reach.
+    // has slots in reach. The scan holds only the FP32 view of the sphere;
+    // its FP64 record is read again for the exact tests.
+    float4 Pf;
+    float reach32;
+    bool exact_only;
+    {
+        const NarrowSelf n0 = narrow_self(S, g, s);
+        Pf = n0.Pf;
+        reach32 = (float)n0.reach + 2.0f * g.pre_eps;
+        exact_only = n0.exact_only;
+    }
     int npre = 0;
-    if (!n.exact_only)
-        scan_reach32(S, g, n.Pf.x, n.Pf.y, n.Pf.z, (float)n.reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
-            slot_batches(S.sorted_f4, jb, je, [&](float4 q) { return narrow_prefilter_rec(g, n, q); },
+    if (!exact_only)
+        scan_reach32(S, g, Pf.x, Pf.y, Pf.z, reach32, [&](uint32_t jb, uint32_t je) {
+            slot_batches(S.sorted_f4, jb, je, [&](float4 q) {
+                             const float fx = q.x - Pf.x, fy = q.y - Pf.y, fz = q.z - Pf.z;
+                             const float fr = (Pf.w + q.w) + g.pre_eps;
+                             return fx * fx + fy * fy + fz * fz < fr * fr;
+                         },
                          [&](uint32_t q) {
                              if (npre < kMaxRow) lst[npre * kNarrowBlock + tid] = q;
                              npre++;
                          });
         });
-    if (!n.exact_only && npre <= kMaxRow) {
+    uint32_t s2 = s;
+    asm volatile("" : "+v"(s2));  // a fresh read, not the values loaded before the scan
+    const NarrowSelf n = narrow_self(S, g, s2);
+    if (n.exact_only || npre > kMaxRow) {
+        // many slots pass the prefilter (or the sphere is far outside its
+        // grid): k_narrow_fb finds its candidates with one exact pass and
+        // adds its counts to the workgroup's sums; kept out of this kernel,
+        // that pass's registers do not limit the wavefronts in flight here
+        const uint32_t k = atomicAdd((uint32_t *)&S.ctl->n_fb, 1u);
+        S.fb_list[k] = s;
+        return;
+    }
+    {
         // two listed slots at a time, both read before either is inserted:
         // an insert writes at most at the position of the later slot read
         for (int k = 0; k < npre; k += 2) {
@@ -1034,18 +1079,8 @@ __device__ __forceinline__ void narrow_sphere(const DevScene &S, uint32_t s, uin
             }
         }
         narrow_boundaries<TRI>(S, g, n, emit);
-    } else {
-        narrow_candidates<TRI>(S, s, emit);  // many slots pass the prefilter: one exact pass
     }
-    // staging: the counts (below it and boundaries packed for a listed
-    // sphere), then entry k at stage[k ns + s]
-    if (cnt > kMaxRow) {
-        S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup);
-        S.stage[s] = (uint32_t)nbp;
-        return;
-    }
-    S.stage_n[s] = make_uint2((uint32_t)cnt, (uint32_t)nup | ((uint32_t)nbp << 16));
-    for (int k = 0; k < cnt; k++) S.stage[(int64_t)k * S.ns + s] = lst[k * kNarrowBlock + tid];
+    stage_sphere(S, s, cnt, nup, nbp, [&](int k) { return lst[k * kNarrowBlock + tid]; });
 }
 
 template <bool TRI>
@@ -1074,6 +1109,35 @@ __global__ void __launch_bounds__(kNarrowBlock) k_narrow(DevScene S) {
         unsigned long long t = 0;
         for (int k = 0; k < w; k++) t += sh[q][k];
         S.narrow_woff[(blk * kWaves + w) * 2 + q] = (uint32_t)t;
+    }
+}
+
+// Candidates of the spheres the first pass left (more than kMaxRow slots
+// through its prefilter, or far outside their grid): one exact FP64 pass over
+// the slots in reach, staged as the first pass stages, the counts added to
+// the sums of the sphere's workgroup and to the offsets of the wavefronts
+// after its own there (integer adds, so their order does not matter).
+template <bool TRI>
+__global__ void __launch_bounds__(64) k_narrow_fb(DevScene S) {
+    if (!due(S.ctl) || aborted(S.ctl)) return;
+    __shared__ uint32_t lst[kMaxRow * 64];
+    constexpr int kWaves = kNarrowBlock / 64;
+    const int tid = threadIdx.x;
+    const int64_t n = S.ctl->n_fb;
+    for (int64_t k = (int64_t)blockIdx.x * 64 + tid; k < n; k += (int64_t)gridDim.x * 64) {
+        const uint32_t s = S.fb_list[k];
+        int cnt = 0, nup = 0, nbp = 0;
+        narrow_candidates<TRI>(S, s, [&](uint32_t t) { emit_sorted(lst + tid, 64, t, s, S.ns, cnt, nup, nbp); });
+        stage_sphere(S, s, cnt, nup, nbp, [&](int q) { return lst[q * 64 + tid]; });
+        const int64_t blk = s / kNarrowBlock;
+        const int w = (int)(s % kNarrowBlock) / 64;
+        atomicAdd(&S.narrow_part[3 * blk], (unsigned long long)nup);
+        atomicAdd(&S.narrow_part[3 * blk + 1], (unsigned long long)(cnt - nup));
+        atomicAdd(&S.narrow_part[3 * blk + 2], (unsigned long long)nbp);
+        for (int v = w + 1; v < kWaves; v++) {
+            atomicAdd(&S.narrow_woff[(blk * kWaves + v) * 2], (uint32_t)nup);
+            atomicAdd(&S.narrow_woff[(blk * kWaves + v) * 2 + 1], (uint32_t)(cnt - nup));
+        }
     }
 }
 
@@ -2021,7 +2085,7 @@ __global__ void __launch_bounds__(256) k_snap(DevScene S, DevScene B) {
         b->amax_last = a->amax_last;
         b->vmax_bits = 0;
         b->det_due = 1; b->guard = 0;
-        b->overflow = 0; b->row_overflow = 0; b->asym = 0; b->n_over = 0;
+        b->overflow = 0; b->row_overflow = 0; b->asym = 0; b->n_over = 0; b->n_fb = 0;
         b->n_up = 0; b->n_pairs = 0; b->n_bp = 0;
         b->k_cur = S.plan.k_max;
         b->fallbacks = 0;
@@ -2225,7 +2289,7 @@ const char *const kKernelNames[K_COUNT] = {"k_pose", "k_detect_begin", "k_cell_c
                                            "k_link", "k_reduce_waves", "k_bin_features", "k_bin_margin",
                                            "k_narrow_over", "k_region_margin", "k_guard_big", "k_bins_begin",
                                            "audit_total", "k_pick_interval", "k_narrow_rows", "k_narrow_base",
-                                           "k_carry"};
+                                           "k_carry", "k_narrow_fb"};
 KernelTimer *g_timer = nullptr;
 
 #define TIMED(id, launch)                           \
@@ -2300,10 +2364,12 @@ hipError_t launch_detect(const DevScene &S, hipStream_t st) {
     }
     if (S.n_tri) {
         TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<true>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        TIMED(K_NARROW_FB, hipLaunchKernelGGL(k_narrow_fb<true>, dim3(kFbGrid), dim3(64), 0, st, S));
         narrow_rows(S, st);
         TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<true>, dim3(256), dim3(64), 0, st, S));
     } else {
         TIMED(K_NARROW, hipLaunchKernelGGL(k_narrow<false>, dim3(blocks_for(S.ns, kNarrowBlock)), dim3(kNarrowBlock), 0, st, S));
+        TIMED(K_NARROW_FB, hipLaunchKernelGGL(k_narrow_fb<false>, dim3(kFbGrid), dim3(64), 0, st, S));
         narrow_rows(S, st);
         TIMED(K_NARROW_OVER, hipLaunchKernelGGL(k_narrow_over<false>, dim3(256), dim3(64), 0, st, S));
     }
