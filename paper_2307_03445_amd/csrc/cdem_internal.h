@@ -87,7 +87,7 @@ struct Ctl {
     int32_t n_over;          // spheres of this detection with more than kMaxRow candidates
     uint32_t m_max_bits;     // largest margin any sphere takes at the detection in progress (float bits, >= 0)
     int32_t n_fb;            // spheres of this detection whose candidates k_narrow_fb finds
-    int64_t pad_c1;
+    int64_t n_afb;           // spheres of the audit in progress whose sphere partners k_audit_fb checks
     int64_t n_pairs;         // pairs of the detection in progress
     int64_t n_pairs_cur;     // pairs of the active set in use
     int32_t asym;            // an entry had no mirror (never expected): the step is abandoned

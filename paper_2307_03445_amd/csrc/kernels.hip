@@ -213,7 +213,7 @@ __global__ void __launch_bounds__(256) k_bins_begin(DevScene S) {
         S.ctl->n_up = 0; S.ctl->n_pairs = 0; S.ctl->n_bp = 0; S.ctl->row_overflow = 0; S.ctl->asym = 0;
         S.ctl->n_over = 0; S.ctl->n_fb = 0;
     }
-    if (i == 0 && aud) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; }
+    if (i == 0 && aud) { S.ctl->audit_true = 0; S.ctl->audit_last_missed = 0; S.ctl->n_afb = 0; }
 }
 
 // Poses of the current state, one lane per sphere, and the speed of each
@@ -1927,6 +1927,37 @@ __global__ void k_zero(uint8_t *p, size_t n) {
 // ---------------------------------------------------------------- binned audit
 // Exact contacts of the current positions, found in freshly built bins with no
 // margin, must each be in both partners' rows of the active set.
+
+// Sphere s's rows of the active set in use: has(t) tells whether partner t
+// is in its upper (t < s) or lower segment (binary search).
+struct AuditRows {
+    const uint32_t *lrow, *urow;
+    uint32_t lc, uc, s;
+    __device__ __forceinline__ AuditRows(const DevScene &S, uint32_t s_) : s(s_) {
+        const int cur = S.ctl->buf;
+        lrow = slot3(S.pt, cur) + slot3(S.lo_beg, cur)[s];
+        lc = slot3(S.lo_cnt, cur)[s];
+        urow = slot3(S.ut, cur) + slot3(S.up_beg, cur)[s];
+        uc = slot3(S.up_cnt, cur)[s];
+    }
+    __device__ __forceinline__ bool has(uint32_t t) const {
+        const uint32_t *nb = t < s ? urow : lrow;
+        const uint32_t cnt = t < s ? uc : lc;
+        uint32_t lo = 0, hi = cnt;
+        while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
+        return lo < cnt && nb[lo] == t;
+    }
+};
+
+// The partner side of the audit's reach: the largest radius (no margins).
+__device__ __forceinline__ double audit_reach(const Grid &g, const double4 &P) { return P.w + g.r_max + 1e-9; }
+
+// One lane per sphere: the FP32 prefilter over the bins in reach into an LDS
+// list, then the exact test over it, then the boundaries and triangles.  A
+// sphere with more than kMaxRow prefilter hits (or far outside its grid)
+// leaves its sphere partners to k_audit_fb, so that the rare long exact pass
+// does not set this kernel's registers; the scan holds only the sphere's
+// FP32 view, its FP64 record and rows are read afterwards.
 template <bool TRI>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k_audit_cells(DevScene S) {
     // an abandoned step (active-set overflow) is audited when it is run again
@@ -1941,43 +1972,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
         asm volatile("" : "+v"(tid));  // nothing derived from the lane is held across iterations
         const int64_t i = vb * 256 + tid;
         if (i < S.ns) {
-            const int cur = S.ctl->buf;
-            uint32_t s = (uint32_t)i;
-            double4 P = S.spos[s];
-            uint32_t own = S.owner[s];
-            const uint32_t lb = slot3(S.lo_beg, cur)[s], lc = slot3(S.lo_cnt, cur)[s];
-            const uint32_t *lrow = slot3(S.pt, cur) + lb, *urow = slot3(S.ut, cur) + slot3(S.up_beg, cur)[s];
-            const uint32_t uc = slot3(S.up_cnt, cur)[s];
-            auto in_row = [&](uint32_t t) {  // t in s's upper (t < s) or lower segment
-                const uint32_t *nb = t < s ? urow : lrow;
-                const uint32_t cnt = t < s ? uc : lc;
-                uint32_t lo = 0, hi = cnt;
-                while (lo < hi) { uint32_t m = (lo + hi) >> 1; if (nb[m] < t) lo = m + 1; else hi = m; }
-                return lo < cnt && nb[lo] == t;
-            };
+            const uint32_t s = (uint32_t)i;
             const Grid &g = S.grids[S.sscene[s]];
-            const double reach = P.w + g.r_max + 1e-9;
             // the FP32 prefilter of the narrow phase, without margins
-            const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
-            const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
-            auto prefilter = [&](uint32_t j) {
-                const float4 Qf = S.sorted_f4[j];
-                const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
-                return exact_only || fx * fx + fy * fy + fz * fz < fr * fr;
-            };
-            auto exact = [&](uint32_t j) {
-                const uint4 md = S.sorted_meta[j];
-                if (md.y == own) return;
-                double4 Q = S.sorted_pos[j];
-                double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
-                double d2 = dx * dx + dy * dy + dz * dz;
-                double Sr = P.w + Q.w;
-                if (d2 < Sr * Sr) { found++; if (!in_row(md.x)) missed++; }
-            };
-            // as in the narrow phase: prefilter hits to an LDS list, then the exact test over it
+            float4 Pf;
+            float reach32;
+            bool exact_only;
+            {
+                const double4 P0 = S.spos[s];
+                Pf = make_float4((float)(P0.x - g.ox), (float)(P0.y - g.oy), (float)(P0.z - g.oz), (float)P0.w);
+                exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+                reach32 = (float)audit_reach(g, P0) + 2.0f * g.pre_eps;
+            }
             int npre = 0;
             if (!exact_only)
-                scan_reach32(S, g, Pf.x, Pf.y, Pf.z, (float)reach + 2.0f * g.pre_eps, [&](uint32_t jb, uint32_t je) {
+                scan_reach32(S, g, Pf.x, Pf.y, Pf.z, reach32, [&](uint32_t jb, uint32_t je) {
                     slot_batches(S.sorted_f4, jb, je, [&](float4 Qf) {
                         const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
                         return fx * fx + fy * fy + fz * fz < fr * fr;
@@ -1986,7 +1995,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                         npre++;
                     });
                 });
-            if (!exact_only && npre <= kMaxRow) {
+            uint32_t s2 = s;
+            asm volatile("" : "+v"(s2));  // fresh reads, not the values loaded before the scan
+            const double4 P = S.spos[s2];
+            const uint32_t own = S.owner[s2];
+            const AuditRows rows(S, s2);
+            if (exact_only || npre > kMaxRow) {
+                const unsigned long long k = atomicAdd((unsigned long long *)&S.ctl->n_afb, 1ull);
+                S.fb_list[k] = s;
+            } else {
                 // two listed slots at a time, their records loaded together
                 for (int k = 0; k < npre; k += 2) {
                     const bool two = k + 1 < npre;
@@ -2001,21 +2018,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                         const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
                         const double d2 = dx * dx + dy * dy + dz * dz;
                         const double Sr = P.w + Q.w;
-                        if (d2 < Sr * Sr) { found++; if (!in_row(id)) missed++; }
+                        if (d2 < Sr * Sr) { found++; if (!rows.has(id)) missed++; }
                     }
                 }
-            } else {
-                scan_reach(S, g, P.x, P.y, P.z, reach, [&](uint32_t jb, uint32_t je) {
-                    for (uint32_t j = jb; j < je; j++)
-                        if (prefilter(j)) exact(j);
-                });
             }
             double tnow = (double)S.ctl->step * S.h;
             for (int b = g.bnd_beg; b < g.bnd_end; b++) {
                 double phi, n[3];
                 if (bnd_distance(S.bnd[b], tnow, P.x, P.y, P.z, phi, n) && phi < P.w) {
                     found++;
-                    if (!in_row((uint32_t)(S.ns + b))) missed++;
+                    if (!rows.has((uint32_t)(S.ns + b))) missed++;
                 }
             }
             // the triangles through the boxes of the last detection: grown by
@@ -2026,7 +2038,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                     double phi, n[3];
                     if (tri_distance(S, k, p, phi, n) && phi < P.w) {
                         found++;
-                        if (!in_row((uint32_t)(S.ns + S.n_bnd + k))) missed++;
+                        if (!rows.has((uint32_t)(S.ns + S.n_bnd + k))) missed++;
                     }
                 });
             }
@@ -2042,6 +2054,47 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
     if (threadIdx.x == 0) {
         S.part_a[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
         S.part_a[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+    }
+}
+
+// The sphere partners of the spheres k_audit_cells left: every slot in reach
+// through the prefilter (all of them far outside the grid), then the exact
+// test; the counts are added to the first workgroup's partial.
+template <bool TRI>
+__global__ void __launch_bounds__(64) k_audit_fb(DevScene S) {
+    if (!audit_due(S) || aborted(S.ctl)) return;
+    unsigned long long found = 0, missed = 0;
+    const int64_t n = S.ctl->n_afb;
+    for (int64_t k = (int64_t)blockIdx.x * 64 + threadIdx.x; k < n; k += (int64_t)gridDim.x * 64) {
+        const uint32_t s = S.fb_list[k];
+        const double4 P = S.spos[s];
+        const uint32_t own = S.owner[s];
+        const AuditRows rows(S, s);
+        const Grid &g = S.grids[S.sscene[s]];
+        const float4 Pf = make_float4((float)(P.x - g.ox), (float)(P.y - g.oy), (float)(P.z - g.oz), (float)P.w);
+        const bool exact_only = !(fabsf(Pf.x) < g.pre_lim && fabsf(Pf.y) < g.pre_lim && fabsf(Pf.z) < g.pre_lim);
+        scan_reach(S, g, P.x, P.y, P.z, audit_reach(g, P), [&](uint32_t jb, uint32_t je) {
+            for (uint32_t j = jb; j < je; j++) {
+                const float4 Qf = S.sorted_f4[j];
+                const float fx = Qf.x - Pf.x, fy = Qf.y - Pf.y, fz = Qf.z - Pf.z, fr = (Pf.w + Qf.w) + g.pre_eps;
+                if (!(exact_only || fx * fx + fy * fy + fz * fz < fr * fr)) continue;
+                const uint4 md = S.sorted_meta[j];
+                if (md.y == own) continue;
+                const double4 Q = S.sorted_pos[j];
+                const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
+                const double d2 = dx * dx + dy * dy + dz * dz;
+                const double Sr = P.w + Q.w;
+                if (d2 < Sr * Sr) { found++; if (!rows.has(md.x)) missed++; }
+            }
+        });
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        found += __shfl_xor(found, off, 64);
+        missed += __shfl_xor(missed, off, 64);
+    }
+    if (threadIdx.x == 0 && (found | missed)) {
+        atomicAdd(&S.part_a[0], found);
+        atomicAdd(&S.part_a[1], missed);
     }
 }
 
@@ -2442,6 +2495,8 @@ hipError_t launch_audit_binned(const DevScene &S, hipStream_t st) {
     binning(S, 1, st);
     if (S.n_tri) TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<true>, dim3(S.n_ablocks), dim3(256), 0, st, S));
     else TIMED(K_AUDIT, hipLaunchKernelGGL(k_audit_cells<false>, dim3(S.n_ablocks), dim3(256), 0, st, S));
+    if (S.n_tri) hipLaunchKernelGGL(k_audit_fb<true>, dim3(kFbGrid), dim3(64), 0, st, S);
+    else hipLaunchKernelGGL(k_audit_fb<false>, dim3(kFbGrid), dim3(64), 0, st, S);
     hipLaunchKernelGGL(k_audit_end, dim3(1), dim3(1024), 0, st, S);
     if (g_timer) g_timer->after(K_AUDIT_ALL, st);
     return hipGetLastError();
