@@ -14,7 +14,9 @@
 //                    exact FP64 predicate (boundary partners: analytic
 //                    boundaries, and mesh triangles through the boxes of
 //                    k_tri_boxes / k_tri_scene_boxes), candidates sorted by
-//                    partner id in LDS and staged per sphere;
+//                    partner id in LDS and staged per sphere (k_narrow_fb
+//                    takes the rare sphere with more than 16 prefilter
+//                    hits through one exact FP64 pass);
 //                    k_narrow_base scans the workgroups' counts into
 //                    segment bases (no atomics), k_narrow_rows writes the
 //                    segments, k_link points each higher sphere's entry at
