@@ -265,7 +265,7 @@ def run_path(desc, mode, steps, warmup, mlp=None, graph=0, label=None, detect=No
         a1 = sc.counts()
         n_a, ms_a = pa.get("audit_total", (0, 0.0))
         audit = dict(steps=period, audits=a1["audits"] - a0["audits"], missed=a1["missed"] - a0["missed"],
-                     true_contacts_seen=None, chain_ms=ms_a, chain_launches=n_a)
+                     true_contacts_seen=a1["audit_contacts"], chain_ms=ms_a, chain_launches=n_a)
     # every kernel, over one audit period more (or 20 steps of the plain path)
     sc.profile(True)
     _steps_reporting_misses(sc, period or min(20, steps), label)

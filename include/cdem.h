@@ -179,6 +179,8 @@ typedef struct cdem_counts {
     int64_t pairs;        /* distinct candidate pairs of the active set (sphere pairs + boundary pairs) */
     int32_t k_current;    /* current detection interval */
     int32_t reserved;
+    int64_t audit_contacts; /* exact contacts the last binned audit found (sphere pairs once, boundary and
+                               triangle contacts), the count cdem_audit reports for the same positions */
 } cdem_counts;
 
 /* Clump state view: each pointer may be NULL (skipped).  where = CDEM_HOST or

@@ -57,7 +57,7 @@ class CountsC(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("clumps", "spheres", "bins", "candidates", "steps", "detections",
                                           "guard_trips", "fallbacks", "audits", "missed", "capacity", "regrows",
                                           "pairs")] + \
-               [("k_current", C.c_int32), ("reserved", C.c_int32)]
+               [("k_current", C.c_int32), ("reserved", C.c_int32), ("audit_contacts", C.c_int64)]
 
 
 class StateViewC(C.Structure):

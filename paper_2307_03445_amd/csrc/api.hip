@@ -1303,6 +1303,7 @@ extern "C" int cdem_get_counts(cdem_scene *sc, cdem_counts *out) {
     out->guard_trips = c.guard_trips; out->fallbacks = c.fallbacks; out->audits = c.audits;
     out->missed = c.missed; out->capacity = sc->S.cap; out->regrows = sc->regrows; out->k_current = c.k_cur;
     out->pairs = c.n_pairs_cur;
+    out->audit_contacts = c.audit_true;
     return CDEM_OK;
 }
 

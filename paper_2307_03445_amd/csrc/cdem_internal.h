@@ -96,7 +96,7 @@ struct Ctl {
     uint32_t amax_bits;      // max sphere acceleration estimate of the step in progress
     uint32_t amax_last;      // ... of the last completed step
     float margin_cur;        // margin of every sphere at the last detection (fixed rule)
-    int64_t audit_true;      // true contacts seen by the last audit
+    int64_t audit_true;      // exact contacts seen by the last binned audit (sphere pairs once)
     int64_t audit_last_missed;
     int64_t n_bp;            // boundary pairs written by the detection in progress
     int32_t guard_next;      // guard trips of the clumps integrated outside the wave reduction

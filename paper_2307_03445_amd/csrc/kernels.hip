@@ -1955,7 +1955,9 @@ struct AuditRows {
 __device__ __forceinline__ double audit_reach(const Grid &g, const double4 &P) { return P.w + g.r_max + 1e-9; }
 
 // One lane per sphere: the FP32 prefilter over the bins in reach into an LDS
-// list, then the exact test over it, then the boundaries and triangles.  A
+// list, then the exact test over it, then the boundaries and triangles (each
+// contact counted once: a sphere pair by its lower sphere; a miss by either
+// side whose row lacks it).  A
 // sphere with more than kMaxRow prefilter hits (or far outside its grid)
 // leaves its sphere partners to k_audit_fb, so that the rare long exact pass
 // does not set this kernel's registers; the scan holds only the sphere's
@@ -2020,7 +2022,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) k
                         const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
                         const double d2 = dx * dx + dy * dy + dz * dz;
                         const double Sr = P.w + Q.w;
-                        if (d2 < Sr * Sr) { found++; if (!rows.has(id)) missed++; }
+                        if (d2 < Sr * Sr) { found += id > s; if (!rows.has(id)) missed++; }
                     }
                 }
             }
@@ -2086,7 +2088,7 @@ __global__ void __launch_bounds__(64) k_audit_fb(DevScene S) {
                 const double dx = Q.x - P.x, dy = Q.y - P.y, dz = Q.z - P.z;
                 const double d2 = dx * dx + dy * dy + dz * dz;
                 const double Sr = P.w + Q.w;
-                if (d2 < Sr * Sr) { found++; if (!rows.has(md.x)) missed++; }
+                if (d2 < Sr * Sr) { found += md.x > s; if (!rows.has(md.x)) missed++; }
             }
         });
     }

@@ -385,6 +385,30 @@ def test_spheres_with_more_candidates_than_lds_rows(mode, walls):
 
 
 @gpu
+@pytest.mark.parametrize("walls", [False, True])
+def test_binned_audit_counts_every_contact(walls):
+    """The binned audit's exact contacts (each sphere pair once, and the
+    boundary contacts) against the exhaustive audit and the oracle's contact
+    set at the same positions, on the scene whose large spheres pass more than
+    16 slots through the audit's prefilter (its exact FP64 pass)."""
+    d = _crowded_scene(walls=walls)
+    sc, o = _scene(d, "fp64"), oracle.Oracle(d)
+    sc.set_detection("fixed", k_max=10, safety=1.5, margin_cap=2e-4, audit_period=5)
+    sc.step(5)  # a detection and an audit at step 0, then deferred steps
+    o.step(5)
+    full = sc.audit()
+    o.eval()
+    co = o.contacts()
+    n_oracle = len(co["a"])
+    sc.step(1)  # step 5 audits the positions after five steps, in bins of its own
+    c = sc.counts()
+    assert c["audits"] == 2 and c["missed"] == 0 and full["missed"] == 0
+    assert c["audit_contacts"] == full["true_contacts"] == n_oracle, (c["audit_contacts"], full, n_oracle)
+    per = np.bincount(np.r_[co["a"], co["b"]].astype(int), minlength=d.n_spheres + 8)
+    assert per[:d.n_spheres].max() > 16
+
+
+@gpu
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_boundary_forces(dense, prec):
     sc, o = _scene(dense, prec), oracle.Oracle(dense)
